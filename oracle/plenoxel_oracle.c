@@ -1,0 +1,703 @@
+/*
+ * plenoxel_oracle.c -- plain FP64 CPU oracle for the Plenoxels hot path
+ * (Fridovich-Keil, Yu et al., "Plenoxels: Radiance Fields without Neural
+ * Networks", arXiv 2112.05131).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * definition that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the HIP library,
+ * and it includes nothing from it.
+ *
+ * Precision contract.  Every *discrete* decision (ray hit/miss, number of
+ * samples, the lower-corner cell of each sample, the touched set, prune and
+ * upsample occupancy) follows one fixed IEEE-FP32 recipe so that an FP32 GPU
+ * path can reproduce it bit for bit.  Everything continuous (interpolation,
+ * SH colour, compositing, gradients, TV, RMSProp) is FP64.  The file must be
+ * compiled with -ffp-contract=off so that the FP32 recipe is not fused.
+ *
+ * What is computed, with the passage of the paper each part follows:
+ *   - data structure: dense index grid of int32, -1 = NULL, pointing into a
+ *     table of (sigma, 27 SH coefficients); NULL reads as all-zero
+ *     (Sec. 3.2; supplement B.1 "Implementation Details");
+ *   - trilinear interpolation of sigma and SH at each sample (Sec. 3.3);
+ *   - degree-2 real SH colour per channel, clipped with a ReLU (Sec. 3.2;
+ *     supplement B.1, ReLU instead of a sigmoid);
+ *   - Max quadrature, Eq. (1), composited over a background colour
+ *     (Sec. 3.1; white background of the synthetic scenes, Sec. 4.1);
+ *   - the exact gradient of Eq. (1) for a given dL/dC (chain rule written
+ *     out; the paper's "gradient kernels", supplement B.1);
+ *   - TV regulariser with the 256/D normalisation and the SH edge rule
+ *     (Sec. 3.5, loss below Eq. (2); supplement B.1);
+ *   - RMSProp (Sec. 3.5);
+ *   - density-threshold pruning with dilation, and trilinear resampling to
+ *     a new resolution (Sec. 3.4).
+ * Readings where the paper is silent (sample placement, SH constants and
+ * signs, sigma ReLU, TV epsilon, RMSProp beta/eps, background rule) are the
+ * ones listed in the design notes; each is restated where it is used.
+ *
+ * Parity pins live in tests/test_oracle_*.py; every function below is pinned
+ * by at least one closed form, invariant, library routine or brute force.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NSH 27 /* 3 colour channels x 9 degree-2 SH coefficients */
+
+/* ------------------------------------------------------------------------ */
+/* Grid coordinate frame.  Voxel values live at voxel centres: voxel i of an
+ * axis of N voxels spanning [lo, hi] sits at world lo + (i + 0.5) (hi-lo)/N,
+ * i.e. at grid coordinate i, where g = p * scale + offset with
+ * scale = N/(hi-lo) and offset = -lo*scale - 0.5.  The step along a unit ray
+ * is step_voxels voxel lengths of the finest axis.  FP64 maths, rounded to
+ * FP32 once. */
+void orc_grid_geometry(const int32_t reso[3], const double lo[3],
+                       const double hi[3], double step_voxels,
+                       float scale_out[3], float offset_out[3],
+                       float *step_out)
+{
+    double max_scale = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double s = (double)reso[a] / (hi[a] - lo[a]);
+        scale_out[a] = (float)s;
+        offset_out[a] = (float)(-lo[a] * s - 0.5);
+        if (s > max_scale) max_scale = s;
+    }
+    *step_out = (float)(step_voxels / max_scale);
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP32 ray/sample recipe (discrete decisions). */
+
+typedef struct {
+    float og[3], dg[3];
+    float t_near, t_far;
+} ray_geom;
+
+/* Slab test of the ray against the lattice hull [0, N-1]^3 in grid
+ * coordinates.  Returns 1 on a hit (t_near < t_far), 0 on a miss. */
+static int ray_setup(const int32_t reso[3], const float scale[3],
+                     const float offset[3], const float o[3], const float d[3],
+                     ray_geom *r)
+{
+    float t_near = 0.0f;
+    float t_far = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        float og = o[a] * scale[a];
+        og = og + offset[a];
+        float dg = d[a] * scale[a];
+        float top = (float)(reso[a] - 1);
+        r->og[a] = og;
+        r->dg[a] = dg;
+        if (dg == 0.0f) {
+            if (og < 0.0f || og > top) return 0;
+            continue;
+        }
+        float t0 = (-og) / dg;
+        float t1 = (top - og) / dg;
+        float tlo = t0 < t1 ? t0 : t1;
+        float thi = t0 < t1 ? t1 : t0;
+        if (tlo > t_near) t_near = tlo;
+        if (thi < t_far) t_far = thi;
+    }
+    r->t_near = t_near;
+    r->t_far = t_far;
+    return t_near < t_far;
+}
+
+/* Parameter of sample k: computed directly from k, never by accumulation. */
+static float sample_t(const ray_geom *r, float step, int k)
+{
+    float kk = (float)k * step;
+    return r->t_near + kk;
+}
+
+/* Lower-corner cell and in-cell fraction of the sample at parameter t. */
+static void sample_cell(const int32_t reso[3], const ray_geom *r, float t,
+                        int cell[3], double frac[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        float p = t * r->dg[a];
+        float g = r->og[a] + p;
+        int i0 = (int)floorf(g);
+        if (i0 < 0) i0 = 0;
+        if (i0 > reso[a] - 2) i0 = reso[a] - 2;
+        float f = g - (float)i0;
+        if (f < 0.0f) f = 0.0f;
+        if (f > 1.0f) f = 1.0f;
+        cell[a] = i0;
+        frac[a] = (double)f;
+    }
+}
+
+/* Length of the interval that sample k stands for: the step, except the last
+ * interval, which stops at the exit point t_far (left-endpoint samples,
+ * "constant values between samples", Sec. 3.1). */
+static float sample_delta(const ray_geom *r, float step, float t)
+{
+    float rest = r->t_far - t;
+    return rest < step ? rest : step;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Degree-2 real spherical harmonics (Sec. 3.2: 9 coefficients per channel).
+ * Orthonormal real basis in the order (l,m) = (0,0),(1,-1),(1,0),(1,1),
+ * (2,-2),(2,-1),(2,0),(2,1),(2,2), built from the complex harmonics with the
+ * Condon-Shortley phase as sqrt(2) Im Y_l^|m| (m<0), Y_l^0, sqrt(2) Re Y_l^m
+ * (m>0), evaluated at the ray direction d = (x, y, z). */
+void orc_sh_basis(const double d[3], double y[9])
+{
+    const double pi = 3.14159265358979323846;
+    const double x = d[0], yy = d[1], z = d[2];
+    const double c00 = 0.5 / sqrt(pi);
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2 = sqrt(15.0 / (4.0 * pi));
+    const double c20 = sqrt(5.0 / (16.0 * pi));
+    const double c22 = sqrt(15.0 / (16.0 * pi));
+    y[0] = c00;
+    y[1] = -c1 * yy;
+    y[2] = c1 * z;
+    y[3] = -c1 * x;
+    y[4] = c2 * x * yy;
+    y[5] = -c2 * yy * z;
+    y[6] = c20 * (3.0 * z * z - 1.0);
+    y[7] = -c2 * x * z;
+    y[8] = c22 * (x * x - yy * yy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trilinear interpolation of sigma and the 27 SH coefficients from the 8
+ * voxels around a sample (Sec. 3.3).  NULL voxels read as zero (supplement
+ * B.1).  Also returns the 8 corner table ids (-1 = NULL) and weights. */
+
+static int64_t lin_id(const int32_t reso[3], int i, int j, int k)
+{
+    return ((int64_t)i * reso[1] + j) * (int64_t)reso[2] + k;
+}
+
+static void interpolate(const int32_t reso[3], const int32_t *index,
+                        const double *density, const double *sh,
+                        const int cell[3], const double f[3],
+                        double *sigma, double k[ORC_NSH], int64_t ids[8],
+                        double w[8])
+{
+    *sigma = 0.0;
+    for (int q = 0; q < ORC_NSH; ++q) k[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+        double wc = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) *
+                    (dz ? f[2] : 1.0 - f[2]);
+        int64_t id = index[lin_id(reso, cell[0] + dx, cell[1] + dy,
+                                  cell[2] + dz)];
+        ids[c] = id;
+        w[c] = wc;
+        if (id < 0) continue;
+        *sigma += wc * density[id];
+        for (int q = 0; q < ORC_NSH; ++q) k[q] += wc * sh[id * ORC_NSH + q];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-sample record of one ray (forward quantities the gradient needs). */
+typedef struct {
+    double sigma_pre;      /* interpolated sigma before the ReLU */
+    double rgb_pre[3];     /* SH colour before the ReLU */
+    double sigma, rgb[3];  /* after the ReLUs */
+    double delta;          /* interval length */
+    double T;              /* transmittance before the sample */
+    double T_next;         /* transmittance after the sample */
+    double weight;         /* T * (1 - exp(-sigma delta)) */
+    int64_t ids[8];
+    double w[8];
+} sample_rec;
+
+/* Walks one ray and fills recs (if non-NULL, capacity cap).  Returns the
+ * number of samples n; *rgb and *tau get the composited colour (with the
+ * background) and the optical depth sum(sigma delta). */
+static int march_ray(const int32_t reso[3], const float scale[3],
+                     const float offset[3], float step, const int32_t *index,
+                     const double *density, const double *sh, const float o[3],
+                     const float d[3], const double bg[3], sample_rec *recs,
+                     int cap, double rgb[3], double *tau, double *t_final)
+{
+    ray_geom r;
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    *tau = 0.0;
+    *t_final = 1.0;
+    if (!ray_setup(reso, scale, offset, o, d, &r)) {
+        for (int c = 0; c < 3; ++c) rgb[c] = bg[c];
+        return 0;
+    }
+    double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+    double ylm[9];
+    orc_sh_basis(dd, ylm);
+
+    double T = 1.0;
+    int n = 0;
+    for (int k = 0;; ++k) {
+        float t = sample_t(&r, step, k);
+        if (!(t < r.t_far)) break;
+        int cell[3];
+        double f[3];
+        sample_cell(reso, &r, t, cell, f);
+        double delta = (double)sample_delta(&r, step, t);
+
+        double sig, kc[ORC_NSH];
+        int64_t ids[8];
+        double w[8];
+        interpolate(reso, index, density, sh, cell, f, &sig, kc, ids, w);
+
+        double sigma = sig > 0.0 ? sig : 0.0;
+        double col_pre[3], col[3];
+        for (int ch = 0; ch < 3; ++ch) {
+            double s = 0.0;
+            for (int l = 0; l < 9; ++l) s += kc[ch * 9 + l] * ylm[l];
+            col_pre[ch] = s;
+            col[ch] = s > 0.0 ? s : 0.0;
+        }
+        double alpha = -expm1(-sigma * delta);
+        double weight = T * alpha;
+        double T_next = T * exp(-sigma * delta);
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] += weight * col[ch];
+        *tau += sigma * delta;
+
+        if (recs && n < cap) {
+            sample_rec *s = &recs[n];
+            s->sigma_pre = sig;
+            s->sigma = sigma;
+            for (int ch = 0; ch < 3; ++ch) {
+                s->rgb_pre[ch] = col_pre[ch];
+                s->rgb[ch] = col[ch];
+            }
+            s->delta = delta;
+            s->T = T;
+            s->T_next = T_next;
+            s->weight = weight;
+            memcpy(s->ids, ids, sizeof(ids));
+            memcpy(s->w, w, sizeof(w));
+        }
+        T = T_next;
+        ++n;
+    }
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] += T * bg[ch];
+    *t_final = T;
+    return n;
+}
+
+/* Number of samples of a ray (FP32 recipe only). */
+static int count_samples(const int32_t reso[3], const float scale[3],
+                         const float offset[3], float step, const float o[3],
+                         const float d[3])
+{
+    ray_geom r;
+    if (!ray_setup(reso, scale, offset, o, d, &r)) return 0;
+    int n = 0;
+    while (sample_t(&r, step, n) < r.t_far) ++n;
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward rendering of n_rays rays: rgb_out[3R], tau_out[R] (optical depth),
+ * tfinal_out[R] (transmittance left after the last sample), nsamp_out[R]
+ * (number of samples).  Any output may be NULL. */
+void orc_render_fwd(const int32_t reso[3], const float scale[3],
+                    const float offset[3], float step, const int32_t *index,
+                    const double *density, const double *sh,
+                    const float *rays_o, const float *rays_d, int64_t n_rays,
+                    const double bg[3], double *rgb_out, double *tau_out,
+                    double *tfinal_out, int32_t *nsamp_out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double rgb[3], tau, tf;
+        int n = march_ray(reso, scale, offset, step, index, density, sh,
+                          rays_o + 3 * r, rays_d + 3 * r, bg, NULL, 0, rgb,
+                          &tau, &tf);
+        if (rgb_out)
+            for (int c = 0; c < 3; ++c) rgb_out[3 * r + c] = rgb[c];
+        if (tau_out) tau_out[r] = tau;
+        if (tfinal_out) tfinal_out[r] = tf;
+        if (nsamp_out) nsamp_out[r] = n;
+    }
+}
+
+/* Per-sample trace of one ray, for tests: writes up to cap samples of
+ * t, delta, sigma_pre, rgb_pre (3 per sample) and lower-corner cell (3 per
+ * sample).  Returns the number of samples of the ray. */
+int orc_trace_ray(const int32_t reso[3], const float scale[3],
+                  const float offset[3], float step, const int32_t *index,
+                  const double *density, const double *sh, const float o[3],
+                  const float d[3], int cap, double *t_out, double *delta_out,
+                  double *sigma_pre_out, double *rgb_pre_out, int32_t *cell_out)
+{
+    ray_geom r;
+    if (!ray_setup(reso, scale, offset, o, d, &r)) return 0;
+    double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+    double ylm[9];
+    orc_sh_basis(dd, ylm);
+    int n = 0;
+    for (int k = 0;; ++k) {
+        float t = sample_t(&r, step, k);
+        if (!(t < r.t_far)) break;
+        if (n < cap) {
+            int cell[3];
+            double f[3], sig, kc[ORC_NSH], w[8];
+            int64_t ids[8];
+            sample_cell(reso, &r, t, cell, f);
+            interpolate(reso, index, density, sh, cell, f, &sig, kc, ids, w);
+            t_out[n] = (double)t;
+            delta_out[n] = (double)sample_delta(&r, step, t);
+            sigma_pre_out[n] = sig;
+            for (int ch = 0; ch < 3; ++ch) {
+                double s = 0.0;
+                for (int l = 0; l < 9; ++l) s += kc[ch * 9 + l] * ylm[l];
+                rgb_pre_out[3 * n + ch] = s;
+            }
+            for (int a = 0; a < 3; ++a) cell_out[3 * n + a] = cell[a];
+        }
+        ++n;
+    }
+    return n;
+}
+
+/* Ray setup only, for tests: t_near/t_far of the FP32 recipe and the sample
+ * count.  Returns 1 on hit. */
+int orc_ray_extent(const int32_t reso[3], const float scale[3],
+                   const float offset[3], float step, const float o[3],
+                   const float d[3], float *t_near, float *t_far,
+                   int32_t *n_samples)
+{
+    ray_geom r;
+    int hit = ray_setup(reso, scale, offset, o, d, &r);
+    *t_near = hit ? r.t_near : 0.0f;
+    *t_far = hit ? r.t_far : 0.0f;
+    *n_samples = count_samples(reso, scale, offset, step, o, d);
+    return hit;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of the rendered colour for a given dL/dC (grad_rgb[3R]).
+ *
+ * With C = sum_k w_k c_k + T_n bg, w_k = T_k (1 - exp(-sigma_k delta_k)),
+ * T_{k+1} = T_k exp(-sigma_k delta_k) and R_k = sum_{j>k} w_j c_j + T_n bg
+ * (everything the ray collects after sample k):
+ *   dC/dsigma_k = delta_k (T_{k+1} c_k - R_k),
+ *   dC/dc_k     = w_k.
+ * Through the ReLUs (derivative 0 at 0), the SH basis and the trilinear
+ * weights this gives the gradient of every corner value.  Gradients are
+ * ADDED into grad_density[M] and grad_sh[M*27]; touched[M] is set to 1 for
+ * every non-NULL corner of every sample of every ray (the active set). */
+void orc_render_bwd(const int32_t reso[3], const float scale[3],
+                    const float offset[3], float step, const int32_t *index,
+                    const double *density, const double *sh,
+                    const float *rays_o, const float *rays_d, int64_t n_rays,
+                    const double bg[3], const double *grad_rgb,
+                    double *grad_density, double *grad_sh, uint8_t *touched)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
+        int n = count_samples(reso, scale, offset, step, o, d);
+        if (n == 0) continue;
+        sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
+        double rgb[3], tau, T_n;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, bg,
+                  recs, n, rgb, &tau, &T_n);
+        double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+        double ylm[9];
+        orc_sh_basis(dd, ylm);
+        const double *g = grad_rgb + 3 * r;
+
+        /* R = what the ray collects after the current sample, built from the
+         * back so that it is a plain sum. */
+        double R[3] = {T_n * bg[0], T_n * bg[1], T_n * bg[2]};
+        for (int k = n - 1; k >= 0; --k) {
+            const sample_rec *s = &recs[k];
+            double gc = 0.0, gR = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                gc += g[ch] * s->rgb[ch];
+                gR += g[ch] * R[ch];
+            }
+            double dsig = s->sigma_pre > 0.0
+                              ? s->delta * (s->T_next * gc - gR)
+                              : 0.0;
+            double dk[ORC_NSH];
+            for (int ch = 0; ch < 3; ++ch) {
+                double dcol = s->rgb_pre[ch] > 0.0 ? s->weight * g[ch] : 0.0;
+                for (int l = 0; l < 9; ++l) dk[ch * 9 + l] = dcol * ylm[l];
+            }
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = s->ids[c];
+                if (id < 0) continue;
+                double wc = s->w[c];
+#pragma omp atomic
+                grad_density[id] += wc * dsig;
+                for (int q = 0; q < ORC_NSH; ++q) {
+#pragma omp atomic
+                    grad_sh[id * ORC_NSH + q] += wc * dk[q];
+                }
+                touched[id] = 1;
+            }
+            for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
+        }
+        free(recs);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total variation over the cells start, start+1, ..., start+count-1 (mod the
+ * number of cells) in storage order (supplement B.1: contiguous segments of
+ * the pointer grid).  For cell v and channel d:
+ *   Delta_a = (D_a/256) (V_d(v + e_a) - V_d(v)),
+ *   term    = sqrt(Delta_x^2 + Delta_y^2 + Delta_z^2 + eps).
+ * sigma: NULL or out-of-range neighbours read 0.  SH: a NULL current cell has
+ * no SH terms, and a NULL or out-of-range neighbour counts as equal to the
+ * current cell (Delta = 0).  Loss = lambda_sigma/|V| sum term_sigma +
+ * lambda_sh/|V| sum term_sh with |V| = count.  Gradients are ADDED; every
+ * non-NULL voxel among v and its three forward neighbours is marked touched.
+ * Returns the loss. */
+double orc_tv(const int32_t reso[3], const int32_t *index,
+              const double *density, const double *sh, int64_t start,
+              int64_t count, double lambda_sigma, double lambda_sh, double eps,
+              double *grad_density, double *grad_sh, uint8_t *touched)
+{
+    const int64_t ncell = (int64_t)reso[0] * reso[1] * reso[2];
+    double s_axis[3];
+    for (int a = 0; a < 3; ++a) s_axis[a] = (double)reso[a] / 256.0;
+    const double inv_v = 1.0 / (double)count;
+    double sum_sigma = 0.0, sum_sh = 0.0;
+
+    for (int64_t c = 0; c < count; ++c) {
+        int64_t v = ((start + c) % ncell + ncell) % ncell;
+        int i = (int)(v / ((int64_t)reso[1] * reso[2]));
+        int j = (int)((v / reso[2]) % reso[1]);
+        int k = (int)(v % reso[2]);
+        int64_t id = index[v];
+        int64_t nid[3];
+        int in_range[3] = {i + 1 < reso[0], j + 1 < reso[1], k + 1 < reso[2]};
+        nid[0] = in_range[0] ? index[lin_id(reso, i + 1, j, k)] : -1;
+        nid[1] = in_range[1] ? index[lin_id(reso, i, j + 1, k)] : -1;
+        nid[2] = in_range[2] ? index[lin_id(reso, i, j, k + 1)] : -1;
+
+        /* density channel */
+        {
+            double x0 = id >= 0 ? density[id] : 0.0;
+            double dlt[3], ss = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double xa = nid[a] >= 0 ? density[nid[a]] : 0.0;
+                dlt[a] = s_axis[a] * (xa - x0);
+                ss += dlt[a] * dlt[a];
+            }
+            double term = sqrt(ss + eps);
+            sum_sigma += term;
+            double scale = lambda_sigma * inv_v / term;
+            if (id >= 0) {
+                double gsum = 0.0;
+                for (int a = 0; a < 3; ++a) gsum += s_axis[a] * dlt[a];
+                grad_density[id] -= scale * gsum;
+                touched[id] = 1;
+            }
+            for (int a = 0; a < 3; ++a) {
+                if (nid[a] < 0) continue;
+                grad_density[nid[a]] += scale * s_axis[a] * dlt[a];
+                touched[nid[a]] = 1;
+            }
+        }
+        /* SH channels */
+        if (id >= 0) {
+            for (int q = 0; q < ORC_NSH; ++q) {
+                double x0 = sh[id * ORC_NSH + q];
+                double dlt[3], ss = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    dlt[a] = nid[a] >= 0
+                                 ? s_axis[a] * (sh[nid[a] * ORC_NSH + q] - x0)
+                                 : 0.0;
+                    ss += dlt[a] * dlt[a];
+                }
+                double term = sqrt(ss + eps);
+                sum_sh += term;
+                double scale = lambda_sh * inv_v / term;
+                double gsum = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    if (nid[a] < 0) continue;
+                    gsum += s_axis[a] * dlt[a];
+                    grad_sh[nid[a] * ORC_NSH + q] += scale * s_axis[a] * dlt[a];
+                }
+                grad_sh[id * ORC_NSH + q] -= scale * gsum;
+            }
+        }
+    }
+    return lambda_sigma * inv_v * sum_sigma + lambda_sh * inv_v * sum_sh;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RMSProp (Sec. 3.5) on the active voxels only: for each of the 28 values of
+ * an active voxel, v <- beta v + (1-beta) g^2, p <- p - lr g / (sqrt(v) + eps),
+ * then the gradient is cleared.  lr_sigma for density, lr_sh for SH.
+ * Inactive voxels (parameters, state and gradient) are left as they are. */
+void orc_rmsprop(int64_t n_vox, const uint8_t *active, double *density,
+                 double *sh, double *v_density, double *v_sh,
+                 double *grad_density, double *grad_sh, double lr_sigma,
+                 double lr_sh, double beta, double eps)
+{
+    for (int64_t m = 0; m < n_vox; ++m) {
+        if (!active[m]) continue;
+        {
+            double g = grad_density[m];
+            v_density[m] = beta * v_density[m] + (1.0 - beta) * g * g;
+            density[m] -= lr_sigma * g / (sqrt(v_density[m]) + eps);
+            grad_density[m] = 0.0;
+        }
+        for (int q = 0; q < ORC_NSH; ++q) {
+            int64_t p = m * ORC_NSH + q;
+            double g = grad_sh[p];
+            v_sh[p] = beta * v_sh[p] + (1.0 - beta) * g * g;
+            sh[p] -= lr_sh * g / (sqrt(v_sh[p]) + eps);
+            grad_sh[p] = 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid creation: table ids in increasing storage order of the occupied
+ * cells.  Returns the number of occupied cells. */
+int64_t orc_grid_create(const int32_t reso[3], const uint8_t *mask,
+                        int32_t *index_out)
+{
+    const int64_t ncell = (int64_t)reso[0] * reso[1] * reso[2];
+    int64_t m = 0;
+    for (int64_t v = 0; v < ncell; ++v) index_out[v] = mask[v] ? (int32_t)m++ : -1;
+    return m;
+}
+
+/* Density-threshold pruning with dilation (Sec. 3.4; supplement B.1 for the
+ * sigma threshold).  A voxel counts as occupied when it is non-NULL and its
+ * stored density is >= thresh.  A non-NULL voxel is kept when it or any of
+ * its 26 neighbours is occupied.  keep_out[ncell] gets 1 for kept voxels.
+ * Returns the number kept; *n_pruned gets the number of non-NULL voxels
+ * removed. */
+int64_t orc_prune_mask(const int32_t reso[3], const int32_t *index,
+                       const double *density, double thresh, uint8_t *keep_out,
+                       int64_t *n_pruned)
+{
+    int64_t kept = 0, pruned = 0;
+    for (int i = 0; i < reso[0]; ++i)
+        for (int j = 0; j < reso[1]; ++j)
+            for (int k = 0; k < reso[2]; ++k) {
+                int64_t v = lin_id(reso, i, j, k);
+                keep_out[v] = 0;
+                if (index[v] < 0) continue;
+                int any = 0;
+                for (int a = -1; a <= 1 && !any; ++a)
+                    for (int b = -1; b <= 1 && !any; ++b)
+                        for (int c = -1; c <= 1 && !any; ++c) {
+                            int ii = i + a, jj = j + b, kk = k + c;
+                            if (ii < 0 || jj < 0 || kk < 0 || ii >= reso[0] ||
+                                jj >= reso[1] || kk >= reso[2])
+                                continue;
+                            int32_t id = index[lin_id(reso, ii, jj, kk)];
+                            if (id >= 0 && density[id] >= thresh) any = 1;
+                        }
+                if (any) {
+                    keep_out[v] = 1;
+                    ++kept;
+                } else {
+                    ++pruned;
+                }
+            }
+    *n_pruned = pruned;
+    return kept;
+}
+
+/* Resampling to a new resolution (Sec. 3.4: trilinear initialisation after
+ * subdivision, arbitrary ratios allowed).  New voxel j along an axis is
+ * occupied when its parent cell p = floor((2j+1) N_old / (2 N_new)) is
+ * occupied.  Its values are the trilinear interpolation of the old field
+ * (NULL = 0) at old grid coordinate ((j + 0.5) N_old / N_new) - 0.5, clamped
+ * to [0, N_old - 1].  Writes index_new (new table in storage order) and the
+ * new density/SH (sized by the caller from orc_upsample_count).  Returns the
+ * new voxel count. */
+int64_t orc_upsample_count(const int32_t reso[3], const int32_t *index,
+                           const int32_t new_reso[3])
+{
+    int64_t m = 0;
+    for (int i = 0; i < new_reso[0]; ++i) {
+        int pi = (int)(((int64_t)(2 * i + 1) * reso[0]) / (2 * (int64_t)new_reso[0]));
+        for (int j = 0; j < new_reso[1]; ++j) {
+            int pj = (int)(((int64_t)(2 * j + 1) * reso[1]) / (2 * (int64_t)new_reso[1]));
+            for (int k = 0; k < new_reso[2]; ++k) {
+                int pk = (int)(((int64_t)(2 * k + 1) * reso[2]) / (2 * (int64_t)new_reso[2]));
+                if (index[lin_id(reso, pi, pj, pk)] >= 0) ++m;
+            }
+        }
+    }
+    return m;
+}
+
+static void upsample_coord(int j, int n_old, int n_new, int *i0, double *f)
+{
+    double g = ((double)j + 0.5) * (double)n_old / (double)n_new - 0.5;
+    if (g < 0.0) g = 0.0;
+    if (g > (double)(n_old - 1)) g = (double)(n_old - 1);
+    int c = (int)floor(g);
+    if (c > n_old - 2) c = n_old - 2;
+    if (c < 0) c = 0;
+    *i0 = c;
+    *f = g - (double)c;
+}
+
+int64_t orc_upsample(const int32_t reso[3], const int32_t *index,
+                     const double *density, const double *sh,
+                     const int32_t new_reso[3], int32_t *index_new,
+                     double *density_new, double *sh_new)
+{
+    int64_t m = 0;
+    for (int i = 0; i < new_reso[0]; ++i) {
+        int pi = (int)(((int64_t)(2 * i + 1) * reso[0]) / (2 * (int64_t)new_reso[0]));
+        for (int j = 0; j < new_reso[1]; ++j) {
+            int pj = (int)(((int64_t)(2 * j + 1) * reso[1]) / (2 * (int64_t)new_reso[1]));
+            for (int k = 0; k < new_reso[2]; ++k) {
+                int pk = (int)(((int64_t)(2 * k + 1) * reso[2]) / (2 * (int64_t)new_reso[2]));
+                int64_t v = lin_id(new_reso, i, j, k);
+                if (index[lin_id(reso, pi, pj, pk)] < 0) {
+                    index_new[v] = -1;
+                    continue;
+                }
+                index_new[v] = (int32_t)m;
+                int cell[3];
+                double f[3];
+                upsample_coord(i, reso[0], new_reso[0], &cell[0], &f[0]);
+                upsample_coord(j, reso[1], new_reso[1], &cell[1], &f[1]);
+                upsample_coord(k, reso[2], new_reso[2], &cell[2], &f[2]);
+                double sig, kc[ORC_NSH], w[8];
+                int64_t ids[8];
+                interpolate(reso, index, density, sh, cell, f, &sig, kc, ids, w);
+                density_new[m] = sig;
+                for (int q = 0; q < ORC_NSH; ++q) sh_new[m * ORC_NSH + q] = kc[q];
+                ++m;
+            }
+        }
+    }
+    return m;
+}
+
+/* Learning-rate schedules (supplement B.1).  Log-linear decay from lr0 at
+ * step 0 to lr1 at step max_steps; with delay_steps > 0 it is scaled by
+ * mult + (1 - mult) sin(pi/2 min(1, step/delay_steps)) (the delayed form of
+ * the JAXNeRF / Mip-NeRF schedule). */
+double orc_lr_schedule(double step, double lr0, double lr1, double max_steps,
+                       double delay_steps, double delay_mult)
+{
+    const double pi = 3.14159265358979323846;
+    double frac = step / max_steps;
+    if (frac > 1.0) frac = 1.0;
+    double lr = exp((1.0 - frac) * log(lr0) + frac * log(lr1));
+    if (delay_steps > 0.0) {
+        double u = step / delay_steps;
+        if (u > 1.0) u = 1.0;
+        lr *= delay_mult + (1.0 - delay_mult) * sin(0.5 * pi * u);
+    }
+    return lr;
+}
