@@ -1,0 +1,243 @@
+"""Throughput benchmark of the Plenoxels training step on one MI355X.
+
+Workload (the differentiation/scale configuration): a 512^3 sparse grid at 5%
+occupancy (6.71M voxels, FP32 records) built from 32 seeded Gaussian density
+blobs, 100 cameras on the radius-2 sphere at 800x800, and 1M-ray batches drawn
+uniformly from all their pixels; targets are renders of the ground-truth grid.
+The trained grid has the same occupancy with perturbed values.  One step =
+fused render + MSE + backward over the batch, TV on a random contiguous 1%
+segment of the cells, and sparse RMSProp on the active voxels.
+
+Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
+(render_train, algorithmic bytes from the library's work counters over its
+HIP-event duration) and the FP64 oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2112_05131_amd import binding as B  # noqa: E402
+from paper_2112_05131_amd.grid import Grid  # noqa: E402
+from paper_2112_05131_amd.train import TrainConfig, Trainer  # noqa: E402
+
+METRIC = "fwd+bwd Mrays/s & HBM GB/s vs plain FP32; p50/p99 view-render latency"
+HBM_PEAK_GBS = 8000.0
+RESO = (512, 512, 512)
+OCC = 0.05
+N_BLOBS = 32
+SEED = 2
+BATCH = 1 << 20
+N_CAMS, W, H = 100, 800, 800
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(sh_dtype, n_batches):
+    t0 = time.time()
+    gt = synth.blob_scene(RESO, N_BLOBS, OCC, SEED, device="cuda")
+    gt_grid = Grid.from_mask(gt.mask, RESO, gt.density, gt.sh)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(SEED + 1000)
+    dens = gt.density * (0.5 + torch.rand(gt.n_vox, device="cuda", generator=gen))
+    sh = gt.sh + 0.05 * torch.randn(gt.n_vox, 27, device="cuda", generator=gen)
+    grid = Grid.from_mask(gt.mask, RESO, dens, sh, sh_dtype=sh_dtype)
+    poses = synth.sphere_poses(N_CAMS, seed=SEED)
+    batches = []
+    for b in range(n_batches):
+        o, d, _ = synth.sampled_camera_rays(poses, W, H, BATCH, seed=SEED + 10 * b, device="cuda")
+        tgt = torch.empty(BATCH, 3, device="cuda")
+        B.plx_render_fwd(gt_grid.desc(), o, d, tgt)
+        batches.append((o, d, tgt))
+    torch.cuda.synchronize()
+    log(f"workload built in {time.time() - t0:.1f}s: M={grid.n_vox}, batches={n_batches}")
+    return gt, grid, batches, (dens, sh)
+
+
+def time_steps(trainer, batches, warmup, steps):
+    g = trainer.grid
+    c = trainer.cfg
+    for i in range(warmup):
+        o, d, t = batches[i % len(batches)]
+        trainer.step(o, d, t)
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(steps):
+        o, d, t = batches[(warmup + i) % len(batches)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        lr_s, lr_h = trainer.learning_rates()
+        e[0].record()
+        B.plx_render_train(g.desc(), o, d, t, 1.0 / o.shape[0], trainer.grad, trainer.touched,
+                           trainer.loss_sum, None, c.background)
+        e[1].record()
+        s0, cnt = trainer.tv_segment()
+        B.plx_tv_grad(g.desc(), s0, cnt, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps, trainer.grad,
+                      trainer.touched, trainer.tv_loss_sum)
+        e[2].record()
+        B.plx_rmsprop_step(g.desc(), g.master, trainer.vstate, trainer.grad, trainer.touched, lr_s,
+                           lr_h, c.beta, c.eps)
+        e[3].record()
+        trainer.step_id += 1
+        evs.append(e)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                     for e in evs]).mean(axis=0)
+    return ms, wall, k_ms
+
+
+def work_counters(grid, batch):
+    o, d, _ = batch
+    cm = torch.zeros(B.plx_occ_words(grid.reso), dtype=torch.int32, device="cuda")
+    vm = torch.zeros((grid.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    return B.plx_render_stats(grid.desc(), o, d, cm, vm)
+
+
+def active_count(trainer, batch):
+    """Active-set size of one step (untimed; the state is restored)."""
+    g, c = trainer.grid, trainer.cfg
+    o, d, t = batch
+    grad0 = trainer.grad.clone()
+    touched0 = trainer.touched.clone()
+    B.plx_render_train(g.desc(), o, d, t, 1.0 / o.shape[0], trainer.grad, trainer.touched,
+                       trainer.loss_sum, None, c.background)
+    s0, cnt = trainer.tv_segment()
+    B.plx_tv_grad(g.desc(), s0, cnt, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps, trainer.grad,
+                  trainer.touched, trainer.tv_loss_sum)
+    a = B.plx_touched_count(trainer.touched, g.n_vox)
+    trainer.grad.copy_(grad0)
+    trainer.touched.copy_(touched0)
+    return a, cnt
+
+
+def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: fwd + MSE +
+    bwd over S rays of the batch, TV on S/R of the step's segment and RMSProp
+    on the sample's active voxels, timed on the host."""
+    from oracle import oracle as O
+    dens, sh = grid_vals
+    og = O.make_grid(np.array(RESO, np.int32), gt.mask.cpu().numpy(), dens.cpu().double().numpy(),
+                     sh.cpu().double().numpy())
+    o, d, t = (x.cpu().numpy() for x in batch)
+    ncell = RESO[0] * RESO[1] * RESO[2]
+
+    def run(s):
+        t0 = time.perf_counter()
+        rgb = O.render_fwd(og, o[:s], d[:s])[0]
+        g_rgb, _ = O.mse_grad(rgb, t[:s])
+        gd, gs, act = O.render_bwd(og, o[:s], d[:s], g_rgb)
+        cnt = max(1, int(math.ceil(0.01 * ncell * s / BATCH)))
+        _, td, ts, a2 = O.tv(og, 12345, cnt, 1e-5, 1e-3)
+        act = act | a2
+        m = og.n_vox
+        O.rmsprop(act, og.density, og.sh, np.zeros(m), np.zeros((m, 27)), gd + td, gs + ts,
+                  1.0, 0.01)
+        return time.perf_counter() - t0
+
+    probe = 2000
+    tp = run(probe)
+    s = int(min(BATCH, max(probe, probe * budget_s / max(tp, 1e-6))))
+    ts_ = run(s)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(s / ts_ / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "sample": f"{s} rays of one 1M-ray batch (fwd+MSE+bwd), TV on {s}/{BATCH} of the 1% "
+                      f"segment, RMSProp on the sample's active voxels; {ts_:.1f} s FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the library has no multi-GPU path).", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    sh_dtype = B.DTYPES[args.dtype]
+    n_batches = min(args.warmup + args.steps, 8)
+    gt, grid, batches, vals = build_workload(sh_dtype, n_batches)
+    trainer = Trainer(grid, TrainConfig(), seed=SEED)
+
+    counts = work_counters(grid, batches[0])
+    n_act, tv_cells = active_count(trainer, batches[0])
+    log(f"counters: samples={counts[0]} occupied_samples={counts[1]} U_idx={counts[2]} "
+        f"U_occ={counts[3]} active={n_act}")
+
+    ms, wall, k_ms = time_steps(trainer, batches, args.warmup, args.steps)
+    mrays = BATCH / (ms * 1e-3) / 1e6
+    log(f"step {ms:.3f} ms (wall {wall / args.steps * 1e3:.3f} ms/step); kernels ms: "
+        f"render_train {k_ms[0]:.3f} tv {k_ms[1]:.3f} rmsprop {k_ms[2]:.3f}")
+
+    P = 112 if sh_dtype == B.PLX_F32 else 58
+    alg_render = 4 * counts[2] + (P + 224) * counts[3] + 36 * BATCH
+    achieved = alg_render / (k_ms[0] * 1e-3) / 1e9
+    alg_rms = n_act * (672 if sh_dtype == B.PLX_F32 else 726)
+    alg_tv = 4 * 4 * tv_cells
+    step_gbs = (alg_render + alg_rms + alg_tv) / (ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(mrays, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": "512^3 sparse grid, 5% occupancy (6.71M voxels), SH deg 2, "
+                        "1M-ray batches from 100 cameras at 800x800; step = fused "
+                        "render+MSE+backward, TV on a 1% contiguous segment, sparse RMSProp",
+            "sh_storage": args.dtype,
+            "batch_rays": BATCH,
+            "grid": list(RESO),
+            "n_vox": grid.n_vox,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "render_train",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "kernels_ms": {"render_train": round(float(k_ms[0]), 4), "tv_grad": round(float(k_ms[1]), 4),
+                       "rmsprop_step": round(float(k_ms[2]), 4)},
+        "step_hbm_gbs_algorithmic": round(step_gbs, 1),
+        "work": {"samples": counts[0], "occupied_samples": counts[1], "index_entries": counts[2],
+                 "voxels_read": counts[3], "active_voxels": n_act, "tv_cells": tv_cells},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(gt, vals, batches[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

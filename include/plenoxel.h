@@ -1,0 +1,270 @@
+/*
+ * plenoxel.h -- C ABI of the MI355X (gfx950) Plenoxels hot-path library.
+ *
+ * Plenoxels (arXiv 2112.05131) represents a radiance field as a dense index
+ * grid whose cells are NULL or point into a table of occupied voxels, each
+ * holding a density sigma and 27 degree-2 SH coefficients (Sec. 3.2 and
+ * supplement B.1).  This library implements, in hand-written HIP kernels:
+ * grid creation, density-threshold pruning with dilation and trilinear
+ * resampling (Sec. 3.4), differentiable volume rendering with trilinear
+ * interpolation and Max quadrature (Sec. 3.1, Eq. (1); Sec. 3.3) and its
+ * exact backward pass, the TV regulariser (Sec. 3.5 and supplement B.1) and
+ * RMSProp with sparse (active-voxel) updates (Sec. 3.5 and Sec. 3.8).
+ *
+ * General rules
+ *  - Every pointer marked "device" is device memory owned by the caller.  The
+ *    library never keeps a pointer after a call returns.  Pointers marked
+ *    "host" are ordinary host memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All calls only
+ *    enqueue work on `stream` and return, except those documented as
+ *    synchronising (they return host integers and wait for `stream`).
+ *  - Every call returns PLX_OK or an error code and never throws.  Arguments
+ *    are validated before any launch (PLX_EINVAL); a HIP error at launch or a
+ *    synchronising call is reported as PLX_EDEVICE.  plx_last_error() returns
+ *    the message of the last failure on the calling thread.
+ *  - Some calls (marked "temporary device memory") take stream-ordered
+ *    scratch with hipMallocAsync and release it with hipFreeAsync on the
+ *    same stream.
+ *  - Index grids are int32, z fastest: cell (i,j,k) has storage id
+ *    (i*Ny + j)*Nz + k; -1 marks NULL.  Table ids of occupied voxels follow
+ *    increasing storage id.
+ *
+ * Voxel record layout (one record per occupied voxel, table order)
+ *  Logical slots 0..31: slots 0..26 are the SH coefficients, channel-major
+ *  (R0..R8, G0..G8, B0..B8; basis order (l,m) = (0,0),(1,-1),(1,0),(1,1),
+ *  (2,-2),(2,-1),(2,0),(2,1),(2,2)), slot 28 is the density sigma, slots 27
+ *  and 29..31 are unused and kept at zero.
+ *   PLX_F32  : 32 x float32 = 128 bytes (slot s at byte 4s).
+ *   PLX_BF16 / PLX_F16 : 64 bytes; SH slot s (s < 27) is a 16-bit value at
+ *              byte 2s, sigma is a float32 at byte 56, the rest is unused.
+ *  Gradient, RMSProp state and FP32 master records always use the 128-byte
+ *  PLX_F32 layout.
+ */
+#ifndef PLENOXEL_H
+#define PLENOXEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *plx_stream; /* hipStream_t */
+
+enum {
+    PLX_OK = 0,
+    PLX_EINVAL = 1,      /* bad argument; nothing was launched */
+    PLX_EDEVICE = 2,     /* HIP reported an error */
+    PLX_EUNSUPPORTED = 3 /* valid request this build does not implement */
+};
+
+enum { PLX_F32 = 0, PLX_BF16 = 1, PLX_F16 = 2 };
+
+#define PLX_REC_SLOTS 32
+#define PLX_SLOT_SIGMA 28
+#define PLX_NSH 27
+
+/* A grid as the kernels see it.  Geometry: a world point p has grid
+ * coordinate g = p*scale + offset per axis (voxel centres at integers
+ * 0..N-1); `step` is the sample spacing along a unit ray (world units).
+ * `occ` is the cell occupancy bitmap built by plx_grid_build_occupancy
+ * (required by the render calls, ignored elsewhere). */
+typedef struct plx_grid {
+    int32_t reso[3];
+    float scale[3];
+    float offset[3];
+    float step;
+    int32_t sh_dtype;      /* PLX_F32 / PLX_BF16 / PLX_F16 */
+    int64_t n_vox;         /* number of occupied voxels M */
+    const int32_t *index;  /* device [Nx*Ny*Nz] */
+    void *data;            /* device [M] records */
+    const uint32_t *occ;   /* device [plx_occ_words(reso)] */
+} plx_grid;
+
+/* Options of the render calls. */
+typedef struct plx_render_opts {
+    float background[3]; /* colour added with the transmittance left after the
+                            last sample (white background of the synthetic
+                            scenes, Sec. 4.1) */
+} plx_render_opts;
+
+/* ---------------------------------------------------------------- misc */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *plx_last_error(void);
+
+/* Library version string. */
+const char *plx_version(void);
+
+/* Number of device bytes of one voxel record of dtype (128 or 64), or 0. */
+int64_t plx_record_bytes(int32_t sh_dtype);
+
+/* Number of uint32 words of the cell occupancy bitmap of a grid. */
+int64_t plx_occ_words(const int32_t reso[3]);
+
+/* Grid frame of the axis-aligned box [lo, hi] (host, FP64 rounded once to
+ * FP32): scale = N/(hi-lo), offset = -lo*scale - 0.5, step = step_voxels /
+ * max(scale).  Voxel centres sit at grid coordinates 0..N-1. */
+int plx_grid_geometry(const int32_t reso[3], const double lo[3], const double hi[3],
+                      double step_voxels, float scale_out[3], float offset_out[3],
+                      float *step_out);
+
+/* Learning-rate schedule (host).  Log-linear decay from lr0 at step 0 to
+ * lr1 at max_steps, times mult + (1-mult) sin(pi/2 min(1, step/delay)) when
+ * delay_steps > 0: the delayed exponential of supplement B.1 (sigma) and the
+ * pure exponential (SH, delay_steps = 0). */
+double plx_lr_schedule(double step, double lr0, double lr1, double max_steps,
+                       double delay_steps, double delay_mult);
+
+/* ---------------------------------------------------------------- grid */
+
+/* Number of non-zero bytes of mask[n] (device).  Synchronising;
+ * temporary device memory. */
+int plx_mask_count(const uint8_t *mask, int64_t n, int64_t *count_out, plx_stream stream);
+
+/* Index grid from an occupancy mask (Sec. 3.2, supplement B.1): index_out[v]
+ * = number of set mask bytes before v, or -1 where mask[v] == 0.  mask and
+ * index_out are device arrays of Nx*Ny*Nz entries.  Temporary device
+ * memory. */
+int plx_grid_create(const uint8_t *mask, const int32_t reso[3], int32_t *index_out,
+                    plx_stream stream);
+
+/* Writes n records of sh_dtype into out (device): density[n] and sh[n][27]
+ * (device float32) when given, else the constant sigma0 and DC coefficient
+ * dc (all three channels; higher orders 0).  Unused slots are zeroed and 16-bit
+ * SH are rounded to nearest even. */
+int plx_records_pack(int32_t sh_dtype, int64_t n, const float *density, const float *sh,
+                     float sigma0, float dc, void *out, plx_stream stream);
+
+/* Reads n records of sh_dtype back to density[n] and sh[n][27] (device
+ * float32; either may be NULL). */
+int plx_records_unpack(int32_t sh_dtype, int64_t n, const void *records, float *density,
+                       float *sh, plx_stream stream);
+
+/* Converts n records from src_dtype to dst_dtype (device to device; 16-bit
+ * results rounded to nearest even).  src and dst must not overlap. */
+int plx_records_convert(int32_t src_dtype, const void *src, int32_t dst_dtype, void *dst,
+                        int64_t n, plx_stream stream);
+
+/* Cell occupancy bitmap: bit v of occ_out is set when cell v (lower corner
+ * (i,j,k), i < Nx-1, j < Ny-1, k < Nz-1) has at least one non-NULL corner
+ * voxel.  A sample in a cell without that bit reads only zeros and adds
+ * nothing to colour, transmittance or gradient, so the render kernels skip
+ * it exactly.  occ_out: device [plx_occ_words(reso)]. */
+int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream stream);
+
+/* Density-threshold pruning with dilation (Sec. 3.4; supplement B.1): a
+ * voxel is occupied when non-NULL with stored density >= sigma_thresh; a
+ * non-NULL voxel is kept when it or one of its 26 neighbours is occupied.
+ * keep_out (device u8 [Nx*Ny*Nz]) gets 1 for kept voxels.  Returns the
+ * numbers kept and removed (exact integers).  Synchronising; temporary
+ * device memory. */
+int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,
+                         int64_t *n_kept, int64_t *n_pruned, plx_stream stream);
+
+/* Compacts a pruned grid: out->index and out->data (sized n_kept from
+ * plx_grid_prune_count, same reso and dtype as grid) get the kept voxels in
+ * the original order.  Temporary device memory. */
+int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out,
+                         plx_stream stream);
+
+/* Number of voxels of the grid resampled to new_reso: new voxel j (per
+ * axis) is occupied when its parent cell floor((2j+1) N_old / (2 N_new)) is
+ * occupied.  Synchronising; temporary device memory. */
+int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int64_t *n_out,
+                            plx_stream stream);
+
+/* Resamples to out->reso (Sec. 3.4: trilinear initialisation after
+ * subdivision; any ratio): occupancy as in plx_grid_upsample_count, values
+ * by trilinear interpolation of the old field (NULL = 0) at old grid
+ * coordinate ((j + 0.5) N_old / N_new) - 0.5 clamped to [0, N_old - 1]
+ * (computed in FP64).  out->data has out->sh_dtype records.  Temporary
+ * device memory. */
+int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stream);
+
+/* ---------------------------------------------------------------- render */
+
+/* Forward rendering (Sec. 3.1-3.3).  Each ray (unit direction) is marched
+ * through the lattice hull [0,N-1]^3 at t_k = t_near + k*step while
+ * t_k < t_far; sample k stands for the interval min(step, t_far - t_k).
+ * sigma and the 27 SH coefficients are trilinear in the 8 surrounding
+ * voxels (NULL = 0); sigma and each colour channel are clipped at 0; colour
+ * is composited with Eq. (1) and the background is added with the remaining
+ * transmittance.  Outputs (device float32): rgb_out[n_rays][3] and tau_out[n_rays]
+ * = sum sigma_k delta_k (the optical depth, so T_final = exp(-tau)).  tau_out
+ * may be NULL. */
+int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                   const float *rays_d, int64_t n_rays, float *rgb_out, float *tau_out,
+                   plx_stream stream);
+
+/* Backward pass of plx_render_fwd for a given dL/dC (grad_rgb[n_rays][3]).
+ * Each ray is replayed from its last sample to its first; transmittance is
+ * recomputed from the forward optical depth tau_fwd[n_rays] (no per-sample
+ * state).  Gradients of sigma and the SH coefficients are ADDED (FP32
+ * atomics) into grad (device [M] FP32 records); touched (device uint32
+ * bitmap of M bits) gets the bit of every non-NULL corner voxel of every
+ * sample. */
+int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                   const float *rays_d, int64_t n_rays, const float *grad_rgb,
+                   const float *tau_fwd, float *grad, uint32_t *touched, plx_stream stream);
+
+/* One fused training pass over a ray batch: forward, the MSE reconstruction
+ * loss of Sec. 3.5 with its gradient dL/dC = 2 loss_scale (C - target), and
+ * the backward pass into grad/touched as in plx_render_bwd.  loss_scale is
+ * 1/(number of rays of the batch) for the paper's mean; loss_sum (device
+ * double, ADDED) accumulates loss_scale * sum ||C - target||^2.  rgb_out may
+ * be NULL. */
+int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                     const float *rays_d, const float *target, int64_t n_rays,
+                     float loss_scale, float *rgb_out, float *grad, uint32_t *touched,
+                     double *loss_sum, plx_stream stream);
+
+/* Work counters of a ray batch, for bandwidth accounting (not timed work):
+ * counts[0] = samples (all), counts[1] = samples in occupied cells,
+ * counts[2] = distinct index entries read (corners of occupied cells),
+ * counts[3] = distinct non-NULL voxels read.  cell_mark is device scratch of
+ * plx_occ_words(reso) words and vox_mark of ceil(M/32) words; both are
+ * cleared by the call.  Synchronising. */
+int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,
+                     int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark,
+                     int64_t counts[4], plx_stream stream);
+
+/* ---------------------------------------------------------------- TV */
+
+/* Total variation over cell_count cells starting at storage id cell_start
+ * (wrapping modulo the number of cells; contiguous segments in storage
+ * order, supplement B.1).  For cell v and channel d, Delta_a = (D_a/256)
+ * (V_d(v+e_a) - V_d(v)) and term = sqrt(sum_a Delta_a^2 + eps); for sigma a
+ * NULL or out-of-range neighbour reads 0, for SH a NULL current cell has no
+ * terms and a NULL or out-of-range neighbour counts as equal to the current
+ * cell.  Adds lambda_sigma/count * d(sum term_sigma) + lambda_sh/count *
+ * d(sum term_sh) into grad (device [M] FP32 records), sets touched bits of
+ * every non-NULL voxel among v and its three forward neighbours, and ADDS the
+ * loss to loss_sum (device double; may be NULL). */
+int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
+                float lambda_sigma, float lambda_sh, float eps, float *grad,
+                uint32_t *touched, double *loss_sum, plx_stream stream);
+
+/* ---------------------------------------------------------------- optimiser */
+
+/* Number of set bits among the first n_vox bits of touched (the active set
+ * of a step).  Synchronising; temporary device memory. */
+int plx_touched_count(const uint32_t *touched, int64_t n_vox, int64_t *count_out,
+                      plx_stream stream);
+
+/* RMSProp (Sec. 3.5) on the active voxels (touched bits): for each of the 28
+ * values, v <- beta v + (1-beta) g^2 and p <- p - lr g / (sqrt(v) + eps),
+ * lr = lr_sigma for sigma and lr_sh for SH; then g <- 0 and the touched
+ * bits are cleared.  Inactive voxels are not read or written.  vstate and
+ * grad are FP32 records.  For 16-bit grids `master` holds the FP32 records
+ * that are updated and grid->data receives their rounding; for PLX_F32 grids
+ * master must be NULL and grid->data is updated in place. */
+int plx_rmsprop_step(const plx_grid *grid, float *master, float *vstate, float *grad,
+                     uint32_t *touched, float lr_sigma, float lr_sh, float beta, float eps,
+                     plx_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLENOXEL_H */

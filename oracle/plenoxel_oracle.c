@@ -104,6 +104,8 @@ static int ray_setup(const int32_t reso[3], const float scale[3],
     }
     r->t_near = t_near;
     r->t_far = t_far;
+    /* a zero direction has no exit point: no samples */
+    if (!(t_far < INFINITY)) return 0;
     return t_near < t_far;
 }
 

@@ -1,0 +1,311 @@
+"""ctypes binding of libplenoxel_hip.so (include/plenoxel.h).
+
+Argument marshalling only: every function here checks tensor devices, dtypes,
+shapes and contiguity, passes raw device pointers and the current HIP stream,
+and raises ``PlxError`` with the library's message on a non-zero return.
+All compute runs in the library's kernels.  The library is loaded from
+``_build/`` next to this file; if it is missing, importing the functions
+fails loudly (build it with ``python paper_2112_05131_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "_build", "libplenoxel_hip.so")
+HEADER = os.path.join(ROOT, "include", "plenoxel.h")
+
+PLX_OK, PLX_EINVAL, PLX_EDEVICE, PLX_EUNSUPPORTED = 0, 1, 2, 3
+PLX_F32, PLX_BF16, PLX_F16 = 0, 1, 2
+REC_SLOTS = 32
+SLOT_SIGMA = 28
+NSH = 27
+DTYPES = {"f32": PLX_F32, "bf16": PLX_BF16, "f16": PLX_F16}
+
+
+class PlxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[plx error {code}] {msg}")
+        self.code = code
+
+
+class PlxGrid(ctypes.Structure):
+    _fields_ = [
+        ("reso", ctypes.c_int32 * 3),
+        ("scale", ctypes.c_float * 3),
+        ("offset", ctypes.c_float * 3),
+        ("step", ctypes.c_float),
+        ("sh_dtype", ctypes.c_int32),
+        ("n_vox", ctypes.c_int64),
+        ("index", ctypes.c_void_p),
+        ("data", ctypes.c_void_p),
+        ("occ", ctypes.c_void_p),
+    ]
+
+
+class PlxRenderOpts(ctypes.Structure):
+    _fields_ = [("background", ctypes.c_float * 3)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_F = ctypes.c_float
+_I32 = ctypes.c_int32
+_GP = ctypes.POINTER(PlxGrid)
+_OP = ctypes.POINTER(PlxRenderOpts)
+
+_SIGS = {
+    "plx_last_error": ([], ctypes.c_char_p),
+    "plx_version": ([], ctypes.c_char_p),
+    "plx_record_bytes": ([_I32], _I64),
+    "plx_occ_words": ([_P], _I64),
+    "plx_grid_geometry": ([_P, _P, _P, ctypes.c_double, _P, _P, _P], ctypes.c_int),
+    "plx_lr_schedule": ([ctypes.c_double] * 6, ctypes.c_double),
+    "plx_mask_count": ([_P, _I64, _P, _P], ctypes.c_int),
+    "plx_grid_create": ([_P, _P, _P, _P], ctypes.c_int),
+    "plx_records_pack": ([_I32, _I64, _P, _P, _F, _F, _P, _P], ctypes.c_int),
+    "plx_records_unpack": ([_I32, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "plx_records_convert": ([_I32, _P, _I32, _P, _I64, _P], ctypes.c_int),
+    "plx_grid_build_occupancy": ([_GP, _P, _P], ctypes.c_int),
+    "plx_grid_prune_count": ([_GP, _F, _P, _P, _P, _P], ctypes.c_int),
+    "plx_grid_prune_apply": ([_GP, _P, _GP, _P], ctypes.c_int),
+    "plx_grid_upsample_count": ([_GP, _P, _P, _P], ctypes.c_int),
+    "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
+    "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "plx_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
+    "plx_touched_count": ([_P, _I64, _P, _P], ctypes.c_int),
+    "plx_rmsprop_step": ([_GP, _P, _P, _P, _P, _F, _F, _F, _F, _P], ctypes.c_int),
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/plenoxel.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(plx_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library not built: {LIB_PATH} is missing "
+                "(run python paper_2112_05131_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != PLX_OK:
+        msg = lib().plx_last_error().decode(errors="replace")
+        raise PlxError(rc, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None, name: str, dtype=None, numel=None, device_ok=True):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _i3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+# --------------------------------------------------------------------- misc
+
+def plx_version() -> str:
+    return lib().plx_version().decode()
+
+
+def plx_record_bytes(sh_dtype: int) -> int:
+    return int(lib().plx_record_bytes(sh_dtype))
+
+
+def plx_occ_words(reso) -> int:
+    return int(lib().plx_occ_words(ctypes.cast(_i3(reso), _P)))
+
+
+def plx_grid_geometry(reso, lo=(-0.5,) * 3, hi=(0.5,) * 3, step_voxels=0.5):
+    sc = (ctypes.c_float * 3)()
+    of = (ctypes.c_float * 3)()
+    st = ctypes.c_float()
+    lo_ = (ctypes.c_double * 3)(*lo)
+    hi_ = (ctypes.c_double * 3)(*hi)
+    _check(lib().plx_grid_geometry(ctypes.cast(_i3(reso), _P), ctypes.cast(lo_, _P),
+                                   ctypes.cast(hi_, _P), float(step_voxels), ctypes.cast(sc, _P),
+                                   ctypes.cast(of, _P), ctypes.byref(st)))
+    return tuple(sc), tuple(of), st.value
+
+
+def plx_lr_schedule(step, lr0, lr1, max_steps, delay_steps=0.0, delay_mult=1.0) -> float:
+    return float(lib().plx_lr_schedule(float(step), float(lr0), float(lr1), float(max_steps),
+                                       float(delay_steps), float(delay_mult)))
+
+
+# --------------------------------------------------------------------- grid
+
+def plx_mask_count(mask: torch.Tensor) -> int:
+    out = ctypes.c_int64()
+    _check(lib().plx_mask_count(_dptr(mask, "mask", torch.uint8), mask.numel(), ctypes.byref(out),
+                                _stream()))
+    return int(out.value)
+
+
+def plx_grid_create(mask: torch.Tensor, reso, index_out: torch.Tensor):
+    n = int(reso[0]) * int(reso[1]) * int(reso[2])
+    _check(lib().plx_grid_create(_dptr(mask, "mask", torch.uint8, n), ctypes.cast(_i3(reso), _P),
+                                 _dptr(index_out, "index_out", torch.int32, n), _stream()))
+
+
+def plx_records_pack(sh_dtype, n, density, sh, sigma0, dc, out):
+    _check(lib().plx_records_pack(sh_dtype, int(n), _dptr(density, "density", torch.float32),
+                                  _dptr(sh, "sh", torch.float32), float(sigma0), float(dc),
+                                  _dptr(out, "out"), _stream()))
+
+
+def plx_records_unpack(sh_dtype, n, records, density=None, sh=None):
+    _check(lib().plx_records_unpack(sh_dtype, int(n), _dptr(records, "records"),
+                                    _dptr(density, "density", torch.float32),
+                                    _dptr(sh, "sh", torch.float32), _stream()))
+
+
+def plx_records_convert(src_dtype, src, dst_dtype, dst, n):
+    _check(lib().plx_records_convert(src_dtype, _dptr(src, "src"), dst_dtype, _dptr(dst, "dst"),
+                                     int(n), _stream()))
+
+
+def plx_grid_build_occupancy(g: PlxGrid, occ_out: torch.Tensor):
+    _check(lib().plx_grid_build_occupancy(ctypes.byref(g), _dptr(occ_out, "occ_out", torch.int32),
+                                          _stream()))
+
+
+def plx_grid_prune_count(g: PlxGrid, sigma_thresh, keep_out: torch.Tensor):
+    kept, pruned = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().plx_grid_prune_count(ctypes.byref(g), float(sigma_thresh),
+                                      _dptr(keep_out, "keep_out", torch.uint8), ctypes.byref(kept),
+                                      ctypes.byref(pruned), _stream()))
+    return int(kept.value), int(pruned.value)
+
+
+def plx_grid_prune_apply(g: PlxGrid, keep: torch.Tensor, out: PlxGrid):
+    _check(lib().plx_grid_prune_apply(ctypes.byref(g), _dptr(keep, "keep", torch.uint8),
+                                      ctypes.byref(out), _stream()))
+
+
+def plx_grid_upsample_count(g: PlxGrid, new_reso) -> int:
+    n = ctypes.c_int64()
+    _check(lib().plx_grid_upsample_count(ctypes.byref(g), ctypes.cast(_i3(new_reso), _P),
+                                         ctypes.byref(n), _stream()))
+    return int(n.value)
+
+
+def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid):
+    _check(lib().plx_grid_upsample_apply(ctypes.byref(g), ctypes.byref(out), _stream()))
+
+
+# --------------------------------------------------------------------- render
+
+def _opts(bg):
+    return PlxRenderOpts((ctypes.c_float * 3)(*[float(x) for x in bg]))
+
+
+def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    o = _opts(bg)
+    _check(lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(o),
+                                _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                _dptr(tau_out, "tau_out", torch.float32, n), _stream()))
+
+
+def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
+                   bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    o = _opts(bg)
+    _check(lib().plx_render_bwd(ctypes.byref(g), ctypes.byref(o),
+                                _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                _dptr(grad_rgb, "grad_rgb", torch.float32, 3 * n),
+                                _dptr(tau_fwd, "tau_fwd", torch.float32, n),
+                                _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                _dptr(touched, "touched", torch.int32), _stream()))
+
+
+def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
+                     rgb_out=None, bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    o = _opts(bg)
+    _check(lib().plx_render_train(ctypes.byref(g), ctypes.byref(o),
+                                  _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                  _dptr(rays_d, "rays_d", torch.float32, 3 * n),
+                                  _dptr(target, "target", torch.float32, 3 * n), n,
+                                  float(loss_scale), _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                  _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                  _dptr(touched, "touched", torch.int32),
+                                  _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark):
+    n = rays_o.shape[0]
+    counts = (ctypes.c_int64 * 4)()
+    _check(lib().plx_render_stats(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                  _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                  _dptr(cell_mark, "cell_mark", torch.int32),
+                                  _dptr(vox_mark, "vox_mark", torch.int32),
+                                  ctypes.cast(counts, _P), _stream()))
+    return tuple(int(c) for c in counts)
+
+
+# --------------------------------------------------------------------- TV / optimiser
+
+def plx_tv_grad(g: PlxGrid, cell_start, cell_count, lambda_sigma, lambda_sh, eps, grad, touched,
+                loss_sum=None):
+    _check(lib().plx_tv_grad(ctypes.byref(g), int(cell_start), int(cell_count), float(lambda_sigma),
+                             float(lambda_sh), float(eps),
+                             _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                             _dptr(touched, "touched", torch.int32),
+                             _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_touched_count(touched, n_vox) -> int:
+    out = ctypes.c_int64()
+    _check(lib().plx_touched_count(_dptr(touched, "touched", torch.int32), int(n_vox),
+                                   ctypes.byref(out), _stream()))
+    return int(out.value)
+
+
+def plx_rmsprop_step(g: PlxGrid, master, vstate, grad, touched, lr_sigma, lr_sh, beta=0.95,
+                     eps=1e-8):
+    _check(lib().plx_rmsprop_step(ctypes.byref(g), _dptr(master, "master", torch.float32),
+                                  _dptr(vstate, "vstate", torch.float32, REC_SLOTS * g.n_vox),
+                                  _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                  _dptr(touched, "touched", torch.int32), float(lr_sigma),
+                                  float(lr_sh), float(beta), float(eps), _stream()))

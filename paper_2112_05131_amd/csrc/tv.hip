@@ -1,0 +1,133 @@
+// tv.hip -- total-variation regulariser over a contiguous segment of cells
+// (Sec. 3.5, the loss below Eq. (2); supplement B.1: stochastic TV on
+// random contiguous segments of the pointer grid, differences normalised by
+// D/256, and the SH rule that empty cells and edges count as equal to the
+// current cell) for gfx950.
+//
+// One thread per cell of the segment.  The density term reads the cell and
+// its three forward neighbours (NULL or out of range = 0); SH terms exist
+// only for a non-NULL cell, and a NULL or out-of-range neighbour gives a zero
+// difference.  Gradients go to the cell and its neighbours with float
+// atomics (neighbouring cells share voxels); the loss is reduced per block
+// and added once in FP64.
+#include "plx_internal.hpp"
+
+namespace plx {
+namespace {
+
+template <int DT>
+__global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64_t count,
+                                                 int64_t ncell, float lam_sig_v, float lam_sh_v,
+                                                 float eps, float s0, float s1, float s2,
+                                                 float *grad, uint32_t *touched, double *loss_sum) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double local = 0.0;
+    if (c < count) {
+        int64_t v = start + c;
+        v = v < ncell ? v : v % ncell;
+        const int k = (int)(v % g.nz);
+        const int64_t r = v / g.nz;
+        const int j = (int)(r % g.ny);
+        const int i = (int)(r / g.ny);
+        const int64_t sy = g.nz, sx = (int64_t)g.ny * g.nz;
+        const int id = g.index[v];
+        const int nid[3] = {i + 1 < g.nx ? g.index[v + sx] : -1, j + 1 < g.ny ? g.index[v + sy] : -1,
+                            k + 1 < g.nz ? g.index[v + 1] : -1};
+        const float sa[3] = {s0, s1, s2};
+
+        // density channel: NULL or out-of-range reads 0
+        {
+            const float x0 = id >= 0 ? rec_sigma<DT>(g.data, id) : 0.0f;
+            float dl[3], ss = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float xa = nid[a] >= 0 ? rec_sigma<DT>(g.data, nid[a]) : 0.0f;
+                dl[a] = sa[a] * (xa - x0);
+                ss += dl[a] * dl[a];
+            }
+            const float term = sqrtf(ss + eps);
+            local += (double)lam_sig_v * (double)term;
+            const float coef = lam_sig_v / term;
+            if (id >= 0) {
+                const float gsum = sa[0] * dl[0] + sa[1] * dl[1] + sa[2] * dl[2];
+                const float gv = -coef * gsum;
+                if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)id * PLX_REC_SLOTS + PLX_SLOT_SIGMA, gv);
+                atomicOr(touched + (id >> 5), 1u << (id & 31));
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (nid[a] < 0) continue;
+                const float gv = coef * sa[a] * dl[a];
+                if (gv != 0.0f)
+                    unsafeAtomicAdd(grad + (int64_t)nid[a] * PLX_REC_SLOTS + PLX_SLOT_SIGMA, gv);
+                atomicOr(touched + (nid[a] >> 5), 1u << (nid[a] & 31));
+            }
+        }
+        // SH channels of a non-NULL cell
+        if (id >= 0) {
+            double sum_sh = 0.0;
+            for (int q = 0; q < PLX_NSH; ++q) {
+                const float x0 = rec_slot<DT>(g.data, id, q);
+                float dl[3], ss = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    dl[a] = nid[a] >= 0 ? sa[a] * (rec_slot<DT>(g.data, nid[a], q) - x0) : 0.0f;
+                    ss += dl[a] * dl[a];
+                }
+                const float term = sqrtf(ss + eps);
+                sum_sh += (double)term;
+                const float coef = lam_sh_v / term;
+                float gsum = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (nid[a] < 0) continue;
+                    const float gv = coef * sa[a] * dl[a];
+                    gsum += sa[a] * dl[a];
+                    if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)nid[a] * PLX_REC_SLOTS + q, gv);
+                }
+                const float gv = -coef * gsum;
+                if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)id * PLX_REC_SLOTS + q, gv);
+            }
+            local += (double)lam_sh_v * sum_sh;
+        }
+    }
+    // block reduction of the loss, one FP64 atomic per block
+    __shared__ double part[4];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) local += __shfl_xor(local, m);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss_sum) {
+        const double t = part[0] + part[1] + part[2] + part[3];
+        if (t != 0.0) unsafeAtomicAdd(loss_sum, t);
+    }
+}
+
+}  // namespace
+}  // namespace plx
+
+using namespace plx;
+
+extern "C" int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
+                           float lambda_sigma, float lambda_sh, float eps, float *grad,
+                           uint32_t *touched, double *loss_sum, plx_stream stream) {
+    const char *fn = "plx_tv_grad";
+    int rc = validate_grid(grid, false, fn);
+    if (rc) return rc;
+    if (cell_count < 0) return fail(PLX_EINVAL, "%s: cell_count < 0", fn);
+    if (cell_count == 0) return PLX_OK;
+    if (!grad || !touched) return fail(PLX_EINVAL, "%s: grad/touched is NULL", fn);
+    if (!(eps >= 0.0f)) return fail(PLX_EINVAL, "%s: eps must be >= 0", fn);
+    const int64_t ncell = n_cells(grid->reso);
+    const int64_t start = ((cell_start % ncell) + ncell) % ncell;
+    const float inv = (float)(1.0 / (double)cell_count);
+    hipStream_t s = as_stream(stream);
+    const unsigned nb = (unsigned)((cell_count + 255) / 256);
+    GridDev g = to_dev(grid);
+    const float s0 = grid->reso[0] / 256.0f, s1 = grid->reso[1] / 256.0f, s2 = grid->reso[2] / 256.0f;
+    PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                    tv_kernel<DT><<<nb, 256, 0, s>>>(g, start, cell_count, ncell, lambda_sigma * inv,
+                                                     lambda_sh * inv, eps, s0, s1, s2, grad, touched,
+                                                     loss_sum));
+    return check_launch(fn);
+}

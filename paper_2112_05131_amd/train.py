@@ -1,0 +1,86 @@
+"""Training driver: one optimisation step = fused render/MSE/backward over a
+ray batch, TV on a random contiguous segment of cells, and sparse RMSProp
+(Sec. 3.5; hyper-parameters of supplement B.1/B.2).  Host code only chooses
+scalars (learning rates, the TV segment) and enqueues library calls."""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .grid import Grid
+
+
+@dataclass
+class TrainConfig:
+    # learning-rate schedules (supplement B.1)
+    lr_sigma0: float = 30.0
+    lr_sigma1: float = 0.05
+    lr_sh0: float = 1e-2
+    lr_sh1: float = 5e-6
+    lr_max_steps: int = 250000
+    lr_sigma_delay_steps: int = 15000
+    lr_sigma_delay_mult: float = 0.01
+    # RMSProp
+    beta: float = 0.95
+    eps: float = 1e-8
+    # TV (synthetic-scene weights, supplement B.2); applied on tv_fraction of
+    # the cells per step
+    lambda_tv_sigma: float = 1e-5
+    lambda_tv_sh: float = 1e-3
+    tv_fraction: float = 0.01
+    tv_eps: float = 1e-9
+    background: tuple = (1.0, 1.0, 1.0)
+
+
+class Trainer:
+    """Holds the optimiser state of one grid and runs training steps."""
+
+    def __init__(self, grid: Grid, cfg: TrainConfig | None = None, seed: int = 0):
+        self.cfg = cfg or TrainConfig()
+        self.rng = np.random.default_rng(seed)
+        self.step_id = 0
+        self.set_grid(grid)
+
+    def set_grid(self, grid: Grid):
+        """Attach a (new) grid; the optimiser state starts from zero."""
+        self.grid = grid
+        dev = grid.device
+        m = grid.n_vox
+        self.grad = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=dev)
+        self.vstate = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=dev)
+        self.touched = torch.zeros((m + 31) // 32, dtype=torch.int32, device=dev)
+        self.loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.tv_loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def learning_rates(self, step=None):
+        c = self.cfg
+        t = self.step_id if step is None else step
+        lr_s = B.plx_lr_schedule(t, c.lr_sigma0, c.lr_sigma1, c.lr_max_steps,
+                                 c.lr_sigma_delay_steps, c.lr_sigma_delay_mult)
+        lr_h = B.plx_lr_schedule(t, c.lr_sh0, c.lr_sh1, c.lr_max_steps)
+        return lr_s, lr_h
+
+    def tv_segment(self):
+        n = self.grid.n_cells
+        count = max(1, int(math.ceil(self.cfg.tv_fraction * n)))
+        start = int(self.rng.integers(0, n))
+        return start, count
+
+    def step(self, rays_o, rays_d, target, tv: bool = True, rgb_out=None):
+        """One optimisation step on a ray batch (all device tensors)."""
+        c, g = self.cfg, self.grid
+        lr_s, lr_h = self.learning_rates()
+        n = rays_o.shape[0]
+        B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
+                           self.touched, self.loss_sum, rgb_out, c.background)
+        if tv and (c.lambda_tv_sigma > 0 or c.lambda_tv_sh > 0):
+            start, count = self.tv_segment()
+            B.plx_tv_grad(g.desc(), start, count, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps,
+                          self.grad, self.touched, self.tv_loss_sum)
+        B.plx_rmsprop_step(g.desc(), g.master, self.vstate, self.grad, self.touched, lr_s, lr_h,
+                           c.beta, c.eps)
+        self.step_id += 1

@@ -188,6 +188,29 @@ def all_camera_rays(poses: torch.Tensor, width: int, height: int, fov_deg=45.0, 
     return torch.cat(os_), torch.cat(ds_)
 
 
+def sampled_camera_rays(poses: torch.Tensor, width: int, height: int, n: int, seed: int,
+                        fov_deg: float = 45.0, device="cpu"):
+    """n rays drawn uniformly (with replacement) from all pixels of all
+    cameras, as a training batch is.  Returns (rays_o, rays_d, pixel_ids)
+    where pixel_ids index the row-major concatenation of the images."""
+    g = _gen(seed)
+    npix = width * height
+    ids = torch.randint(0, poses.shape[0] * npix, (n,), generator=g, dtype=torch.int64)
+    ids = ids.to(device)
+    cam = ids // npix
+    pix = ids % npix
+    j = (pix // width).double()
+    i = (pix % width).double()
+    f = 0.5 * width / np.tan(0.5 * np.deg2rad(fov_deg))
+    dcam = torch.stack([(i + 0.5 - 0.5 * width) / f, -(j + 0.5 - 0.5 * height) / f,
+                        -torch.ones_like(i)], dim=-1)
+    P = poses.to(device=device, dtype=torch.float64)[cam]  # [n,3,4]
+    d = torch.einsum("nij,nj->ni", P[:, :, :3], dcam)
+    d = d / d.norm(dim=1, keepdim=True)
+    o = P[:, :, 3]
+    return o.float().contiguous(), d.float().contiguous(), ids
+
+
 def random_rays(n: int, seed: int, radius: float = 2.0, target_half: float = 0.45):
     """n rays from the radius-`radius` sphere towards uniform points of the box
     [-target_half, target_half]^3 (float32, unit directions)."""

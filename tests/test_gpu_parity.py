@@ -1,0 +1,444 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (FP32 path): RGB within 1e-5 absolute per channel; gradients per
+element within 1e-4 * (|ref| + 1e-3 * max|ref| of the group {sigma, SH});
+counts (samples, touched/active voxels, kept/pruned voxels, grid ids)
+bit-exact.  Inputs always come from the seeded generators in synth/, and
+expected values from the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from paper_2112_05131_amd import binding as B
+from paper_2112_05131_amd.autograd import render
+from paper_2112_05131_amd.grid import Grid
+from tests.gpu_util import (RGB_ATOL, assert_grads_close, assert_touched_equal, bits_to_bool,
+                            gpu_render, make_pair, say, split_records)
+
+pytestmark = pytest.mark.gpu
+
+C1_RESO = (32, 32, 32)
+SQRT_PI = math.sqrt(math.pi)  # DC coefficient of a grey (0.5) colour
+
+
+def special_rays():
+    """Axis-aligned, lattice-plane, inside-start, missing, diagonal and
+    zero-direction rays."""
+    o = [(-2.0, 0.0, 0.0), (0.0, -2.0, 0.1), (0.05, 0.1, -2.0), (0.0, 0.0, 0.0),
+         (-2.0, 0.9, 0.0), (-2.0, -2.0, -2.0), (0.1, 0.2, 0.3), (-2.0, 0.015625, 0.046875),
+         (0.49, 0.49, 0.49)]
+    d = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), (0.6, 0.0, 0.8), (1.0, 0.0, 0.0),
+         (1 / math.sqrt(3),) * 3, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (-1 / math.sqrt(3),) * 3]
+    return torch.tensor(o, dtype=torch.float32), torch.tensor(d, dtype=torch.float32)
+
+
+def c1_inputs():
+    gt = synth.blob_scene(C1_RESO, n_blobs=4, occupancy=1.0, seed=0)
+    poses = synth.sphere_poses(4, seed=0)
+    o, d = synth.all_camera_rays(poses, 64, 64)
+    return gt, o, d
+
+
+# ------------------------------------------------------------------ grid ops
+
+@pytest.mark.parametrize("reso,occ,seed", [((32, 32, 32), 1.0, 0), ((37, 29, 41), 0.3, 1),
+                                           ((64, 64, 64), 0.1, 2), ((5, 3, 2), 0.5, 3)])
+def test_create_and_occupancy_bitexact(reso, occ, seed):
+    say("create/occupancy", reso, occ)
+    sv = synth.dense_random(reso, seed=seed, occupancy=occ)
+    og, gg = make_pair(sv)
+    assert gg.n_vox == og.n_vox == sv.n_vox
+    assert np.array_equal(gg.index.cpu().numpy(), og.index)
+    # occupancy bit of a cell = any non-NULL corner (brute force from the oracle index)
+    nx, ny, nz = reso
+    idx = og.index.reshape(reso) >= 0
+    occ_ref = np.zeros(reso, bool)
+    c = idx[:-1, :-1, :-1] | idx[1:, :-1, :-1] | idx[:-1, 1:, :-1] | idx[:-1, :-1, 1:] | \
+        idx[1:, 1:, :-1] | idx[1:, :-1, 1:] | idx[:-1, 1:, 1:] | idx[1:, 1:, 1:]
+    occ_ref[:-1, :-1, :-1] = c
+    got = bits_to_bool(gg.occ, nx * ny * nz)
+    assert np.array_equal(got, occ_ref.reshape(-1))
+    # records hold exactly the generator values
+    d, s = gg.unpack()
+    assert torch.equal(d.cpu(), sv.density.cpu()) and torch.equal(s.cpu(), sv.sh.cpu())
+
+
+def test_prune_and_upsample_c2_shapes():
+    # 64^3 grid with blob densities (peak 50), prune sigma < 5, then 64^3 -> 256^3
+    say("prune/upsample 64^3 -> 256^3")
+    sv = synth.blob_scene((64, 64, 64), n_blobs=32, occupancy=1.0, seed=1)
+    og, gg = make_pair(sv)
+    keep_ref, kept_ref, pruned_ref = O.prune_mask(og, 5.0)
+    g2, kept, pruned = gg.prune(5.0)
+    assert (kept, pruned) == (kept_ref, pruned_ref)
+    og2, _, _ = O.prune(og, 5.0)
+    assert np.array_equal(g2.index.cpu().numpy(), og2.index)
+    d2, s2 = g2.unpack()
+    assert np.array_equal(d2.cpu().double().numpy(), og2.density)
+    assert np.array_equal(s2.cpu().double().numpy(), og2.sh)
+    g3 = g2.upsample((256, 256, 256))
+    og3 = O.upsample(og2, (256, 256, 256))
+    assert g3.n_vox == og3.n_vox == kept * 64
+    assert np.array_equal(g3.index.cpu().numpy(), og3.index)
+    d3, s3 = g3.unpack()
+    np.testing.assert_allclose(d3.cpu().double().numpy(), og3.density, rtol=2e-7, atol=1e-30)
+    np.testing.assert_allclose(s3.cpu().double().numpy(), og3.sh, rtol=2e-7, atol=1e-6 * 2e-7)
+
+
+@pytest.mark.parametrize("seed,new", [(4, (9, 8, 10)), (5, (6, 5, 7)), (6, (13, 11, 15))])
+def test_upsample_any_ratio(seed, new):
+    say("upsample any ratio", new)
+    sv = synth.dense_random((6, 5, 7), seed=seed, occupancy=0.4)
+    og, gg = make_pair(sv)
+    g2 = gg.upsample(new)
+    og2 = O.upsample(og, new)
+    assert np.array_equal(g2.index.cpu().numpy(), og2.index)
+    d, s = g2.unpack()
+    np.testing.assert_allclose(d.cpu().double().numpy(), og2.density, rtol=2e-7)
+    np.testing.assert_allclose(s.cpu().double().numpy(), og2.sh, rtol=2e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_prune_random_sparse_bitexact(seed):
+    say("prune random", seed)
+    sv = synth.dense_random((23, 31, 17), seed=seed, occupancy=0.6, sigma_lo=0.0, sigma_hi=10.0)
+    og, gg = make_pair(sv)
+    for thr in (2.0, 8.5, 9.9, 11.0):
+        keep = torch.empty(gg.n_cells, dtype=torch.uint8, device="cuda")
+        kept, pruned = B.plx_grid_prune_count(gg.desc(), thr, keep)
+        keep_ref, kr, pr = O.prune_mask(og, thr)
+        assert (kept, pruned) == (kr, pr)
+        assert np.array_equal(keep.cpu().numpy(), keep_ref)
+
+
+# ------------------------------------------------------------------ forward
+
+def test_forward_c1_gt_grid():
+    say("fwd c1")
+    gt, o, d = c1_inputs()
+    og, gg = make_pair(gt)
+    rgb, tau = gpu_render(gg, o, d)
+    rgb_ref, tau_ref, _, ns = O.render_fwd(og, o.numpy(), d.numpy())
+    assert np.abs(rgb - rgb_ref).max() <= RGB_ATOL
+    assert np.all(np.abs(tau - tau_ref) <= 1e-5 * np.maximum(1.0, tau_ref))
+    # sample count and work counters
+    cm = torch.zeros(B.plx_occ_words(C1_RESO), dtype=torch.int32, device="cuda")
+    vm = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    counts = B.plx_render_stats(gg.desc(), o.cuda(), d.cuda(), cm, vm)
+    assert counts[0] == int(ns.sum())
+
+
+@pytest.mark.parametrize("reso,occ,seed,nrays", [((37, 29, 41), 0.3, 11, 3001),
+                                                 ((16, 16, 16), 0.05, 12, 777),
+                                                 ((8, 8, 8), 1.0, 13, 1)])
+def test_forward_random_sparse_and_special_rays(reso, occ, seed, nrays):
+    say("fwd random", reso, occ)
+    lo, hi = (-0.3, -0.7, -0.2), (0.5, 0.4, 0.9)
+    sv = synth.dense_random(reso, seed=seed, occupancy=occ)
+    og, gg = make_pair(sv, lo=lo, hi=hi)
+    o, d = synth.random_rays(nrays, seed=seed + 100)
+    so, sd = special_rays()
+    o, d = torch.cat([o, so]), torch.cat([d, sd])
+    bg = (0.3, 0.6, 0.9)
+    rgb, tau = gpu_render(gg, o, d, bg)
+    rgb_ref, tau_ref, _, _ = O.render_fwd(og, o.numpy(), d.numpy(), bg)
+    assert np.abs(rgb - rgb_ref).max() <= RGB_ATOL
+    assert np.all(np.abs(tau - tau_ref) <= 1e-5 * np.maximum(1.0, tau_ref))
+
+
+def test_forward_empty_inputs():
+    say("fwd empty")
+    reso = (7, 6, 5)
+    mask = torch.zeros(7 * 6 * 5, dtype=torch.uint8, device="cuda")
+    g = Grid.from_mask(mask, reso)
+    assert g.n_vox == 0
+    o, d = synth.random_rays(100, seed=3)
+    rgb, tau = gpu_render(g, o, d, (0.25, 0.5, 0.75))
+    assert np.array_equal(rgb, np.tile([0.25, 0.5, 0.75], (100, 1))) and np.all(tau == 0)
+    # zero rays: nothing is written
+    out = torch.full((1, 3), 7.0, device="cuda")
+    B.plx_render_fwd(g.desc(), o[:0].cuda(), d[:0].cuda(), out[:0])
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+
+
+# ------------------------------------------------------------------ backward
+
+@pytest.mark.parametrize("case", ["c1", "sparse"])
+def test_backward_matches_oracle(case):
+    say("bwd", case)
+    if case == "c1":
+        gt, o, d = c1_inputs()
+        sv, bg = gt, (1.0, 1.0, 1.0)
+        og, gg = make_pair(sv)
+    else:
+        sv = synth.dense_random((29, 23, 31), seed=21, occupancy=0.35, ho_scale=0.3)
+        og, gg = make_pair(sv)
+        o, d = synth.random_rays(4001, seed=22)
+        bg = (0.1, 0.8, 0.4)
+    n = o.shape[0]
+    G = torch.from_numpy(np.random.default_rng(23).normal(size=(n, 3))).float()
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    B.plx_render_fwd(gg.desc(), o.cuda(), d.cuda(), rgb, tau, bg)
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    B.plx_render_bwd(gg.desc(), o.cuda(), d.cuda(), G.cuda(), tau, grad, touched, bg)
+    torch.cuda.synchronize()
+    gd, gs, t_ref = O.render_bwd(og, o.numpy(), d.numpy(), G.double().numpy(), bg)
+    assert_touched_equal(touched, t_ref, "bwd " + case)
+    assert_grads_close(grad, gd, gs, "bwd " + case)
+    # unused record slots are never written
+    assert torch.all(grad[:, 27] == 0) and torch.all(grad[:, 29:] == 0)
+
+
+def test_autograd_function_matches_oracle():
+    say("autograd")
+    sv = synth.dense_random((12, 12, 12), seed=31, occupancy=0.7, ho_scale=0.2)
+    og, gg = make_pair(sv)
+    o, d = synth.random_rays(1500, seed=32)
+    params = gg.param_records().requires_grad_(True)
+    rgb = render(gg, o.cuda(), d.cuda())
+    G = torch.from_numpy(np.random.default_rng(33).normal(size=(1500, 3))).float().cuda()
+    (rgb * G).sum().backward()
+    gd, gs, _ = O.render_bwd(og, o.numpy(), d.numpy(), G.double().cpu().numpy())
+    assert_grads_close(params.grad, gd, gs, "autograd")
+    rgb_ref = O.render_fwd(og, o.numpy(), d.numpy())[0]
+    assert np.abs(rgb.detach().cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL
+
+
+# ------------------------------------------------------------------ TV
+
+@pytest.mark.parametrize("reso,occ,start,count", [((11, 9, 13), 0.5, 1200, 500),
+                                                  ((11, 9, 13), 0.5, 0, 11 * 9 * 13),
+                                                  ((32, 32, 32), 1.0, 100, 9000)])
+def test_tv_matches_oracle(reso, occ, start, count):
+    say("tv", reso, start, count)
+    sv = synth.dense_random(reso, seed=41, occupancy=occ)
+    og, gg = make_pair(sv)
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lam_s, lam_h, eps = 1.0, 0.7, 1e-9
+    B.plx_tv_grad(gg.desc(), start, count, lam_s, lam_h, eps, grad, touched, loss)
+    torch.cuda.synchronize()
+    l_ref, gd, gs, t_ref = O.tv(og, start, count, lam_s, lam_h, eps)
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+    assert_touched_equal(touched, t_ref, "tv")
+    assert_grads_close(grad, gd, gs, "tv")
+
+
+# ------------------------------------------------------------------ RMSProp
+
+@pytest.mark.parametrize("sh_dtype", [B.PLX_F32, B.PLX_BF16])
+def test_rmsprop_matches_oracle(sh_dtype):
+    say("rmsprop", sh_dtype)
+    sv = synth.dense_random((10, 10, 10), seed=51, occupancy=0.8)
+    og, gg = make_pair(sv, sh_dtype=sh_dtype)
+    m = gg.n_vox
+    rng = np.random.default_rng(52)
+    act = (rng.random(m) < 0.4).astype(np.uint8)
+    dens = sv.density.double().numpy().copy()
+    sh = sv.sh.double().numpy().copy()
+    vd, vs = np.zeros(m), np.zeros((m, 27))
+    vstate = torch.zeros(m, 32, device="cuda")
+    lr_s, lr_h, beta, eps = 3.0, 0.01, 0.95, 1e-8
+    for it in range(2):
+        gdn = rng.normal(size=m) * 10.0 ** rng.uniform(-6, 0, m)
+        gsh = rng.normal(size=(m, 27))
+        grad = torch.zeros(m, 32)
+        grad[:, 28] = torch.from_numpy(gdn).float()
+        grad[:, :27] = torch.from_numpy(gsh).float()
+        grad = grad.cuda()
+        # the oracle sees the same FP32 gradient values
+        gdn = grad[:, 28].double().cpu().numpy().copy()
+        gsh = grad[:, :27].double().cpu().numpy().copy()
+        words = np.packbits(act, bitorder="little")
+        words = np.concatenate([words, np.zeros((-len(words)) % 4, np.uint8)]).view(np.int32)
+        touched = torch.from_numpy(words.copy()).cuda()
+        B.plx_rmsprop_step(gg.desc(), gg.master, vstate, grad, touched, lr_s, lr_h, beta, eps)
+        torch.cuda.synchronize()
+        O.rmsprop(act, dens, sh, vd, vs, gdn, gsh, lr_s, lr_h, beta, eps)
+        assert torch.all(touched == 0)
+        on = act.astype(bool)
+        assert torch.all(grad[torch.from_numpy(on).cuda()] == 0)
+        # inactive gradients untouched
+        assert np.array_equal(grad[torch.from_numpy(~on).cuda()][:, 28].double().cpu().numpy(), gdn[~on])
+    p = gg.param_records()
+    pd, ps = split_records(p)
+    np.testing.assert_allclose(pd, dens, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(ps, sh, rtol=2e-6, atol=1e-6)
+    vdg, vsg = split_records(vstate)
+    np.testing.assert_allclose(vdg, vd, rtol=2e-6, atol=1e-30)
+    np.testing.assert_allclose(vsg, vs, rtol=2e-6, atol=1e-30)
+    if sh_dtype != B.PLX_F32:
+        d16, s16 = gg.unpack()
+        assert torch.equal(s16.cpu(), p[:, :27].detach().cpu().to(torch.bfloat16).float())
+        assert torch.equal(d16.cpu(), p[:, 28].detach().cpu())
+
+
+# ------------------------------------------------------------------ full step
+
+def test_train_step_c1_matches_oracle():
+    """c1: dense 32^3 from uniform init, 4 cameras 64x64; fused render + MSE
+    + backward, TV (lambda 1e-5, all cells), one RMSProp step."""
+    say("train step c1")
+    gt, o, d = c1_inputs()
+    og_gt, _ = make_pair(gt)
+    target = O.render_fwd(og_gt, o.numpy(), d.numpy())[0].astype(np.float32)
+    init = synth.uniform_values(C1_RESO, gt.mask, 0.1, SQRT_PI)
+    og, gg = make_pair(init)
+    n = o.shape[0]
+    m = gg.n_vox
+    grad = torch.zeros(m, 32, device="cuda")
+    touched = torch.zeros((m + 31) // 32, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tvl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rgb = torch.empty(n, 3, device="cuda")
+    tgt = torch.from_numpy(target).cuda()
+    lam, eps_tv = 1e-5, 1e-9
+    B.plx_render_train(gg.desc(), o.cuda(), d.cuda(), tgt, 1.0 / n, grad, touched, loss, rgb)
+    B.plx_tv_grad(gg.desc(), 0, 32 ** 3, lam, lam, eps_tv, grad, touched, tvl)
+    torch.cuda.synchronize()
+    # oracle
+    rgb_ref = O.render_fwd(og, o.numpy(), d.numpy())[0]
+    g_rgb, loss_ref = O.mse_grad(rgb_ref, target)
+    gd, gs, t1 = O.render_bwd(og, o.numpy(), d.numpy(), g_rgb)
+    tvl_ref, td, ts, t2 = O.tv(og, 0, 32 ** 3, lam, lam, eps_tv)
+    gd, gs, act = gd + td, gs + ts, (t1 | t2)
+    assert np.abs(rgb.cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL
+    assert abs(loss.item() - loss_ref) <= 1e-5 * loss_ref
+    assert abs(tvl.item() - tvl_ref) <= 1e-5 * tvl_ref
+    assert_touched_equal(touched, act, "train c1")
+    assert_grads_close(grad, gd, gs, "train c1")
+    # one RMSProp step; the update of each value may differ by what the
+    # stated gradient tolerance allows through g / (sqrt((1-beta) g^2) + eps)
+    beta, eps = 0.95, 1e-8
+    lr_s, lr_h = B.plx_lr_schedule(0, 30, 0.05, 250000, 15000, 0.01), B.plx_lr_schedule(0, 0.01, 5e-6, 250000)
+    vstate = torch.zeros(m, 32, device="cuda")
+    B.plx_rmsprop_step(gg.desc(), None, vstate, grad, touched, lr_s, lr_h, beta, eps)
+    torch.cuda.synchronize()
+    dens, sh = og.density.copy(), og.sh.copy()
+    O.rmsprop(act, dens, sh, np.zeros(m), np.zeros((m, 27)), gd.copy(), gs.copy(), lr_s, lr_h,
+              beta, eps)
+    pd, ps = split_records(gg.data)
+    for name, got, ref, p0, g, lr in (("sigma", pd, dens, og.density, gd, lr_s),
+                                      ("sh", ps, sh, og.sh, gs, lr_h)):
+        gtol = 1e-4 * (np.abs(g) + 1e-3 * np.abs(g).max())
+        sens = lr * eps / (math.sqrt(1 - beta) * np.abs(g) + eps) ** 2
+        tol = sens * gtol + 4e-7 * np.abs(p0) + 1e-6 * lr
+        assert np.all(np.abs(got - ref) <= tol), name
+    assert torch.all(grad == 0) and torch.all(touched == 0)
+
+
+def test_fused_train_equals_fwd_mse_bwd():
+    say("fused vs separate")
+    sv = synth.dense_random((24, 24, 24), seed=61, occupancy=0.4, ho_scale=0.2)
+    _, gg = make_pair(sv)
+    o, d = synth.random_rays(5000, seed=62)
+    o, d = o.cuda(), d.cuda()
+    tgt = synth.targets_uniform(5000, seed=63).cuda()
+    m, n = gg.n_vox, 5000
+    g1 = torch.zeros(m, 32, device="cuda")
+    t1 = torch.zeros((m + 31) // 32, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rgb1 = torch.empty(n, 3, device="cuda")
+    B.plx_render_train(gg.desc(), o, d, tgt, 1.0 / n, g1, t1, loss, rgb1)
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    B.plx_render_fwd(gg.desc(), o, d, rgb, tau)
+    grgb = (2.0 / n) * (rgb - tgt)
+    g2 = torch.zeros(m, 32, device="cuda")
+    t2 = torch.zeros_like(t1)
+    B.plx_render_bwd(gg.desc(), o, d, grgb.contiguous(), tau, g2, t2)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb1, rgb)
+    assert torch.equal(t1, t2)
+    assert abs(loss.item() - ((rgb.double() - tgt.double()) ** 2).sum().item() / n) <= 1e-6 * loss.item()
+    ref = g2.double().cpu().numpy()
+    assert_grads_close(g1, ref[:, 28], ref[:, :27], "fused")
+
+
+# ------------------------------------------------------------------ 16-bit SH
+
+@pytest.mark.parametrize("sh_dtype", [B.PLX_BF16, B.PLX_F16])
+def test_16bit_forward_and_backward(sh_dtype):
+    say("16-bit", sh_dtype)
+    gt, o, d = c1_inputs()
+    og16, g16 = make_pair(gt, sh_dtype=sh_dtype)   # oracle sees the rounded coefficients
+    og32, _ = make_pair(gt)
+    rgb, tau = gpu_render(g16, o, d)
+    rgb16_ref = O.render_fwd(og16, o.numpy(), d.numpy())[0]
+    rgb32_ref = O.render_fwd(og32, o.numpy(), d.numpy())[0]
+    assert np.abs(rgb - rgb16_ref).max() <= RGB_ATOL          # kernel parity
+    err = np.abs(rgb - rgb32_ref).max()                        # storage precision
+    say("  max |rgb - fp32 oracle| =", err)
+    assert err <= (2e-3 if sh_dtype == B.PLX_F16 else 4e-3)
+    n = o.shape[0]
+    G = torch.from_numpy(np.random.default_rng(71).normal(size=(n, 3))).float()
+    grad = torch.zeros(g16.n_vox, 32, device="cuda")
+    touched = torch.zeros((g16.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    B.plx_render_bwd(g16.desc(), o.cuda(), d.cuda(), G.cuda(), torch.from_numpy(tau).float().cuda(),
+                     grad, touched)
+    torch.cuda.synchronize()
+    gd, gs, t_ref = O.render_bwd(og16, o.numpy(), d.numpy(), G.double().numpy())
+    assert_touched_equal(touched, t_ref, "16-bit bwd")
+    assert_grads_close(grad, gd, gs, "16-bit bwd")
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+@pytest.fixture(scope="module")
+def c3_scene():
+    """512^3 at 5% occupancy (about 6.7M voxels), 100 cameras at 800x800,
+    a 1M-ray batch (seed 2)."""
+    say("building c3 scene")
+    sv = synth.blob_scene((512, 512, 512), n_blobs=32, occupancy=0.05, seed=2, device="cuda")
+    poses = synth.sphere_poses(100, seed=2)
+    o, d, _ = synth.sampled_camera_rays(poses, 800, 800, 1 << 20, seed=2, device="cuda")
+    gg = Grid.from_mask(sv.mask, sv.reso, sv.density, sv.sh)
+    og = O.make_grid(np.array(sv.reso, np.int32), sv.mask.cpu().numpy(),
+                     sv.density.cpu().double().numpy(), sv.sh.cpu().double().numpy())
+    return sv, gg, og, o, d
+
+
+def test_full_size_forward_sampled(c3_scene):
+    sv, gg, og, o, d = c3_scene
+    say("c3 fwd, M =", gg.n_vox)
+    assert gg.n_vox == round(0.05 * 512 ** 3)
+    n = o.shape[0]
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    B.plx_render_fwd(gg.desc(), o, d, rgb, tau)
+    torch.cuda.synchronize()
+    sel = np.random.default_rng(81).choice(n, 1500, replace=False)
+    so, sd = o[sel].cpu().numpy(), d[sel].cpu().numpy()
+    rgb_ref, tau_ref, _, _ = O.render_fwd(og, so, sd)
+    assert np.abs(rgb[sel].cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL
+    assert np.all(np.abs(tau[sel].cpu().double().numpy() - tau_ref) <= 1e-5 * np.maximum(1, tau_ref))
+
+
+def test_full_size_backward_subset(c3_scene):
+    sv, gg, og, o, d = c3_scene
+    say("c3 bwd subset")
+    sel = torch.from_numpy(np.random.default_rng(82).choice(o.shape[0], 800, replace=False)).cuda()
+    so, sd = o[sel].contiguous(), d[sel].contiguous()
+    n = so.shape[0]
+    G = torch.from_numpy(np.random.default_rng(83).normal(size=(n, 3))).float().cuda()
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    B.plx_render_fwd(gg.desc(), so, sd, rgb, tau)
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    B.plx_render_bwd(gg.desc(), so, sd, G, tau, grad, touched)
+    torch.cuda.synchronize()
+    gd, gs, t_ref = O.render_bwd(og, so.cpu().numpy(), sd.cpu().numpy(), G.double().cpu().numpy())
+    assert_touched_equal(touched, t_ref, "c3 bwd")
+    on = torch.from_numpy(t_ref.astype(bool)).cuda()
+    sub = grad[on]
+    assert_grads_close(sub, gd[t_ref.astype(bool)], gs[t_ref.astype(bool)], "c3 bwd")
+    assert torch.all(grad[~on] == 0)

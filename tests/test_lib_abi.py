@@ -1,0 +1,142 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+the header declares, validates arguments before launching anything, and its
+host-only helpers agree with the oracle and the paper's values.  No GPU
+compute is called here."""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2112_05131_amd import binding as B
+from oracle import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_library_exports_every_header_function():
+    names = B.header_functions()
+    assert len(names) >= 20
+    L = B.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert sorted(B._SIGS) == names
+
+
+def test_version_and_record_sizes():
+    assert "gfx950" in B.plx_version()
+    assert B.plx_record_bytes(B.PLX_F32) == 128
+    assert B.plx_record_bytes(B.PLX_BF16) == 64
+    assert B.plx_record_bytes(B.PLX_F16) == 64
+    assert B.plx_record_bytes(7) == 0
+    assert B.plx_occ_words((32, 32, 32)) == 32 ** 3 // 32
+    assert B.plx_occ_words((3, 5, 7)) == (105 + 31) // 32
+
+
+@pytest.mark.parametrize("reso,lo,hi,step", [
+    ((32, 32, 32), (-0.5,) * 3, (0.5,) * 3, 0.5),
+    ((512, 512, 512), (-0.5,) * 3, (0.5,) * 3, 0.5),
+    ((37, 29, 41), (-0.3, -0.7, -0.2), (0.5, 0.4, 0.9), 0.5),
+    ((16, 16, 16), (0.1, -0.05, 0.2), (0.13125, -0.01875, 0.23125), 0.5),
+])
+def test_grid_geometry_matches_oracle_bitwise(reso, lo, hi, step):
+    sc, of, st = B.plx_grid_geometry(reso, lo, hi, step)
+    osc, oof, ost = O.grid_geometry(np.array(reso, np.int32), lo, hi, step)
+    assert np.array_equal(np.array(sc, np.float32), osc)
+    assert np.array_equal(np.array(of, np.float32), oof)
+    assert np.float32(st) == ost
+
+
+def test_lr_schedule_matches_paper_and_oracle():
+    hp = json.load(open(os.path.join(HERE, "golden", "paper_hyperparams.json")))
+    s, h = hp["lr_sigma"], hp["lr_sh"]
+    for t in (0, 1, 500, 15000, 38400, 125000, 250000, 300000):
+        a = B.plx_lr_schedule(t, s["lr0"], s["lr1"], s["max_steps"], s["delay_steps"], 0.01)
+        b = O.lr_schedule(t, s["lr0"], s["lr1"], s["max_steps"], s["delay_steps"], 0.01)
+        assert abs(a - b) <= 1e-12 * abs(b)
+        a = B.plx_lr_schedule(t, h["lr0"], h["lr1"], h["max_steps"])
+        b = O.lr_schedule(t, h["lr0"], h["lr1"], h["max_steps"])
+        assert abs(a - b) <= 1e-12 * abs(b)
+    assert abs(B.plx_lr_schedule(250000, s["lr0"], s["lr1"], s["max_steps"], s["delay_steps"], 0.01)
+               - s["lr1"]) < 1e-15
+
+
+def _grid_desc(**kw):
+    g = B.PlxGrid()
+    g.reso[:] = kw.get("reso", (8, 8, 8))
+    g.scale[:] = (8.0, 8.0, 8.0)
+    g.offset[:] = (3.5, 3.5, 3.5)
+    g.step = kw.get("step", 0.0625)
+    g.sh_dtype = kw.get("sh_dtype", 0)
+    g.n_vox = kw.get("n_vox", 10)
+    g.index = kw.get("index", 0x10000)
+    g.data = kw.get("data", 0x20000)
+    g.occ = kw.get("occ", 0x30000)
+    return g
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("reso", (1, 8, 8), "reso[0]"),
+    ("sh_dtype", 9, "sh_dtype"),
+    ("n_vox", -1, "n_vox"),
+    ("index", None, "index"),
+    ("data", None, "data"),
+    ("occ", None, "occupancy"),
+    ("step", 0.0, "step"),
+    ("data", 0x20040, "aligned"),
+])
+def test_render_rejects_bad_grid_before_launch(field, value, needle):
+    g = _grid_desc(**{field: value})
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    rc = B.lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(0x40000),
+                                ctypes.c_void_p(0x50000), 4, ctypes.c_void_p(0x60000), None, None)
+    assert rc == B.PLX_EINVAL
+    assert needle in B.lib().plx_last_error().decode()
+
+
+def test_other_entry_points_reject_bad_arguments():
+    L = B.lib()
+    g = _grid_desc()
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    # negative ray count, NULL outputs, NULL options
+    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, -1, None, None,
+                            None) == B.PLX_EINVAL
+    assert L.plx_render_fwd(ctypes.byref(g), None, None, None, 0, None, None, None) == B.PLX_EINVAL
+    assert L.plx_render_bwd(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(0x40000),
+                            ctypes.c_void_p(0x50000), 3, None, None, None, None,
+                            None) == B.PLX_EINVAL
+    assert L.plx_tv_grad(ctypes.byref(g), 0, -5, 1.0, 1.0, 1e-9, None, None, None,
+                         None) == B.PLX_EINVAL
+    assert L.plx_rmsprop_step(ctypes.byref(g), ctypes.c_void_p(0x70000), ctypes.c_void_p(0x80000),
+                              ctypes.c_void_p(0x90000), ctypes.c_void_p(0xa0000), 0.1, 0.1, 0.95,
+                              1e-8, None) == B.PLX_EINVAL  # master given for an FP32 grid
+    assert "master" in L.plx_last_error().decode()
+    g16 = _grid_desc(sh_dtype=B.PLX_BF16)
+    assert L.plx_rmsprop_step(ctypes.byref(g16), None, ctypes.c_void_p(0x80000),
+                              ctypes.c_void_p(0x90000), ctypes.c_void_p(0xa0000), 0.1, 0.1, 0.95,
+                              1e-8, None) == B.PLX_EINVAL
+    assert L.plx_rmsprop_step(ctypes.byref(g), None, ctypes.c_void_p(0x80000),
+                              ctypes.c_void_p(0x90000), ctypes.c_void_p(0xa0000), 0.1, 0.1, 1.5,
+                              1e-8, None) == B.PLX_EINVAL
+    reso = (ctypes.c_int32 * 3)(1, 4, 4)
+    assert L.plx_grid_create(ctypes.c_void_p(0x1000), ctypes.cast(reso, ctypes.c_void_p),
+                             ctypes.c_void_p(0x2000), None) == B.PLX_EINVAL
+    assert L.plx_mask_count(None, 5, None, None) == B.PLX_EINVAL
+    assert L.plx_records_pack(B.PLX_F32, -2, None, None, 0.0, 0.0, None, None) == B.PLX_EINVAL
+
+
+def test_empty_work_is_a_no_op_without_device():
+    # zero rays / zero cells / empty grids return PLX_OK without touching HIP
+    L = B.lib()
+    g = _grid_desc()
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, 0, None, None,
+                            None) == B.PLX_OK
+    assert L.plx_tv_grad(ctypes.byref(g), 0, 0, 1.0, 1.0, 1e-9, None, None, None, None) == B.PLX_OK
+    out = ctypes.c_int64(-1)
+    assert L.plx_mask_count(None, 0, ctypes.byref(out), None) == B.PLX_OK and out.value == 0
+    g0 = _grid_desc(n_vox=0, data=None)
+    assert L.plx_rmsprop_step(ctypes.byref(g0), None, None, None, None, 0.1, 0.1, 0.95, 1e-8,
+                              None) == B.PLX_OK
