@@ -73,6 +73,9 @@ def lib():
         L.orc_render_bwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
                                      _P, _P, _P, _P]
         L.orc_render_bwd.restype = None
+        L.orc_render_bwd_mass.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
+                                          _P, _P, _P]
+        L.orc_render_bwd_mass.restype = None
         L.orc_tv.argtypes = [_P, _P, _P, _P, i64, i64, f64, f64, f64, _P, _P, _P]
         L.orc_tv.restype = f64
         L.orc_rmsprop.argtypes = [i64, _P, _P, _P, _P, _P, _P, _P, f64, f64, f64, f64]
@@ -179,6 +182,19 @@ def render_bwd(g: Grid, rays_o, rays_d, grad_rgb, bg=(1.0, 1.0, 1.0)):
                          _ptr(_c(bg, np.float64)), _ptr(gr), _ptr(gd), _ptr(gs),
                          _ptr(touched))
     return gd, gs, touched
+
+
+def render_bwd_mass(g: Grid, rays_o, rays_d, gabs_rgb, bg=(1.0, 1.0, 1.0)):
+    """Per-element sums of the absolute gradient terms for |dL/dC| =
+    gabs_rgb (see orc_render_bwd_mass): (mass_density[M], mass_sh[M,27])."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    ga = np.abs(_c(gabs_rgb, np.float64).reshape(-1, 3))
+    md = np.zeros(g.n_vox, np.float64)
+    ms = np.zeros((g.n_vox, 27), np.float64)
+    lib().orc_render_bwd_mass(*_grid_args(g), _ptr(o), _ptr(d), o.shape[0],
+                              _ptr(_c(bg, np.float64)), _ptr(ga), _ptr(md), _ptr(ms))
+    return md, ms
 
 
 def mse_grad(rgb, target):

@@ -448,6 +448,65 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
     }
 }
 
+/* Conditioning of the gradient sums, for tolerances: the same walk as
+ * orc_render_bwd, but every term is ADDED in absolute value, with |dL/dC|
+ * given in gabs_rgb[3R] (non-negative).  For sigma the term
+ * delta (T_{k+1} g.c - g.R) contributes delta (T_{k+1} |g|.c + |g|.R), the
+ * size of the two parts whose difference it is; for SH, |w_k g_ch Y_l|.
+ * A float32 evaluation of the gradient can differ from the exact one by a
+ * small multiple of the float32 unit roundoff times these sums. */
+void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
+                         const float offset[3], float step,
+                         const int32_t *index, const double *density,
+                         const double *sh, const float *rays_o,
+                         const float *rays_d, int64_t n_rays,
+                         const double bg[3], const double *gabs_rgb,
+                         double *mass_density, double *mass_sh)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
+        int n = count_samples(reso, scale, offset, step, o, d);
+        if (n == 0) continue;
+        sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
+        double rgb[3], tau, T_n;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, bg,
+                  recs, n, rgb, &tau, &T_n);
+        double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+        double ylm[9];
+        orc_sh_basis(dd, ylm);
+        const double *g = gabs_rgb + 3 * r;
+        double R[3] = {T_n * fabs(bg[0]), T_n * fabs(bg[1]), T_n * fabs(bg[2])};
+        for (int k = n - 1; k >= 0; --k) {
+            const sample_rec *s = &recs[k];
+            double gc = 0.0, gR = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                gc += g[ch] * s->rgb[ch];
+                gR += g[ch] * R[ch];
+            }
+            double msig = s->sigma_pre > 0.0 ? s->delta * (s->T_next * gc + gR) : 0.0;
+            double mk[ORC_NSH];
+            for (int ch = 0; ch < 3; ++ch) {
+                double dcol = s->rgb_pre[ch] > 0.0 ? s->weight * g[ch] : 0.0;
+                for (int l = 0; l < 9; ++l) mk[ch * 9 + l] = dcol * fabs(ylm[l]);
+            }
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = s->ids[c];
+                if (id < 0) continue;
+                double wc = s->w[c];
+#pragma omp atomic
+                mass_density[id] += wc * msig;
+                for (int q = 0; q < ORC_NSH; ++q) {
+#pragma omp atomic
+                    mass_sh[id * ORC_NSH + q] += wc * mk[q];
+                }
+            }
+            for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
+        }
+        free(recs);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Total variation over the cells start, start+1, ..., start+count-1 (mod the
  * number of cells) in storage order (supplement B.1: contiguous segments of

@@ -565,3 +565,27 @@ def test_upsample_non_integer_ratio_counts_brute_force():
                 pc = int(math.floor((c + 0.5) * 7 / new[2]))
                 cnt += idx[pa, pb, pc] >= 0
     assert gu.n_vox == cnt
+
+
+def test_gradient_mass_bounds_gradient_and_is_tight_without_cancellation():
+    sv = synth.dense_random((7, 6, 8), seed=35, occupancy=0.6, ho_scale=0.2)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(60, seed=36)
+    o, d = o.numpy(), d.numpy()
+    G = np.random.default_rng(37).normal(size=(60, 3))
+    gd, gs, touched = O.render_bwd(g, o, d, G)
+    md, ms = O.render_bwd_mass(g, o, d, np.abs(G))
+    assert np.all(md >= np.abs(gd) * (1 - 1e-12)) and np.all(ms >= np.abs(gs) * (1 - 1e-12))
+    assert np.all(md[touched == 0] == 0) and np.all(ms[touched == 0] == 0)
+    # a direction where every basis value is >= 0 and dL/dC >= 0: the SH
+    # terms cannot cancel, so the mass equals the gradient
+    dirn = np.array([-0.6, -0.3, 0.74])
+    dirn = (dirn / np.linalg.norm(dirn)).astype(np.float32)
+    assert np.all(O.sh_basis(dirn.astype(np.float64)) >= 0)
+    oo = (-1.5 * dirn[None, :] + np.random.default_rng(38).uniform(-0.2, 0.2, (20, 3))).astype(np.float32)
+    dd = np.tile(dirn, (20, 1))
+    Gp = np.abs(np.random.default_rng(39).normal(size=(20, 3)))
+    _, gs2, _ = O.render_bwd(g, oo, dd, Gp)
+    _, ms2 = O.render_bwd_mass(g, oo, dd, Gp)
+    assert np.abs(ms2).max() > 0
+    np.testing.assert_allclose(ms2, gs2, rtol=1e-12, atol=1e-300)
