@@ -67,8 +67,8 @@ enum { PLX_F32 = 0, PLX_BF16 = 1, PLX_F16 = 2 };
 /* A grid as the kernels see it.  Geometry: a world point p has grid
  * coordinate g = p*scale + offset per axis (voxel centres at integers
  * 0..N-1); `step` is the sample spacing along a unit ray (world units).
- * `occ` is the cell occupancy bitmap built by plx_grid_build_occupancy
- * (required by the render calls, ignored elsewhere). */
+ * `occ` is the occupancy structure built by plx_grid_build_occupancy
+ * (plx_occ_bytes bytes; required by the render calls, ignored elsewhere). */
 typedef struct plx_grid {
     int32_t reso[3];
     float scale[3];
@@ -99,8 +99,20 @@ const char *plx_version(void);
 /* Number of device bytes of one voxel record of dtype (128 or 64), or 0. */
 int64_t plx_record_bytes(int32_t sh_dtype);
 
-/* Number of uint32 words of the cell occupancy bitmap of a grid. */
+/* Number of uint32 words of a cell bitmap of a grid (one bit per cell). */
 int64_t plx_occ_words(const int32_t reso[3]);
+
+/* Bytes of the occupancy structure of a grid: the cell bitmap
+ * (plx_occ_words words at offset 0) followed, at byte offset
+ * plx_occ_brick_offset, by one byte per brick of 8x8x8 cells (cells are
+ * indexed by their lower corner, 0..N-2 per axis; Ba = ceil((Na-1)/8) bricks
+ * per axis, brick (a,b,c) at (a*By + b)*Bz + c): the Chebyshev distance, in
+ * bricks, to the nearest brick holding an occupied cell (0 for such a brick),
+ * capped at PLX_BRICK_DIST_CAP. */
+int64_t plx_occ_bytes(const int32_t reso[3]);
+int64_t plx_occ_brick_offset(const int32_t reso[3]);
+#define PLX_BRICK 8
+#define PLX_BRICK_DIST_CAP 16
 
 /* Grid frame of the axis-aligned box [lo, hi] (host, FP64 rounded once to
  * FP32): scale = N/(hi-lo), offset = -lo*scale - 0.5, step = step_voxels /
@@ -146,11 +158,14 @@ int plx_records_unpack(int32_t sh_dtype, int64_t n, const void *records, float *
 int plx_records_convert(int32_t src_dtype, const void *src, int32_t dst_dtype, void *dst,
                         int64_t n, plx_stream stream);
 
-/* Cell occupancy bitmap: bit v of occ_out is set when cell v (lower corner
- * (i,j,k), i < Nx-1, j < Ny-1, k < Nz-1) has at least one non-NULL corner
- * voxel.  A sample in a cell without that bit reads only zeros and adds
- * nothing to colour, transmittance or gradient, so the render kernels skip
- * it exactly.  occ_out: device [plx_occ_words(reso)]. */
+/* Occupancy structure (layout at plx_occ_bytes): bit v of the cell bitmap is
+ * set when cell v (lower corner (i,j,k), i < Nx-1, j < Ny-1, k < Nz-1) has
+ * at least one non-NULL corner voxel, and each brick gets its distance to the
+ * nearest brick with a set bit.  A sample in a cell without that bit reads
+ * only zeros and adds nothing to colour, transmittance or gradient, so the
+ * render kernels skip such samples, and whole boxes of empty bricks, exactly.
+ * occ_out: device, plx_occ_bytes(reso) bytes.  Temporary device memory is not
+ * used. */
 int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream stream);
 
 /* Density-threshold pruning with dilation (Sec. 3.4; supplement B.1): a

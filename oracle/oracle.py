@@ -68,13 +68,15 @@ def lib():
         L.orc_trace_ray.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i32, _P,
                                     _P, _P, _P, _P]
         L.orc_trace_ray.restype = i32
+        L.orc_camera_rays.argtypes = [_P, f64, ctypes.c_int32, ctypes.c_int32, _P, _P]
+        L.orc_camera_rays.restype = None
         L.orc_ray_extent.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P]
         L.orc_ray_extent.restype = i32
         L.orc_render_bwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
                                      _P, _P, _P, _P]
         L.orc_render_bwd.restype = None
         L.orc_render_bwd_mass.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
-                                          _P, _P, _P]
+                                          _P, f64, _P, _P]
         L.orc_render_bwd_mass.restype = None
         L.orc_tv.argtypes = [_P, _P, _P, _P, i64, i64, f64, f64, f64, _P, _P, _P]
         L.orc_tv.restype = f64
@@ -184,16 +186,18 @@ def render_bwd(g: Grid, rays_o, rays_d, grad_rgb, bg=(1.0, 1.0, 1.0)):
     return gd, gs, touched
 
 
-def render_bwd_mass(g: Grid, rays_o, rays_d, gabs_rgb, bg=(1.0, 1.0, 1.0)):
+def render_bwd_mass(g: Grid, rays_o, rays_d, gabs_rgb, bg=(1.0, 1.0, 1.0), gate_rel=0.0):
     """Per-element sums of the absolute gradient terms for |dL/dC| =
-    gabs_rgb (see orc_render_bwd_mass): (mass_density[M], mass_sh[M,27])."""
+    gabs_rgb (see orc_render_bwd_mass): (mass_density[M], mass_sh[M,27]).
+    Terms behind a ReLU gate within gate_rel of its kink count as open."""
     o = _c(rays_o, np.float32).reshape(-1, 3)
     d = _c(rays_d, np.float32).reshape(-1, 3)
     ga = np.abs(_c(gabs_rgb, np.float64).reshape(-1, 3))
     md = np.zeros(g.n_vox, np.float64)
     ms = np.zeros((g.n_vox, 27), np.float64)
     lib().orc_render_bwd_mass(*_grid_args(g), _ptr(o), _ptr(d), o.shape[0],
-                              _ptr(_c(bg, np.float64)), _ptr(ga), _ptr(md), _ptr(ms))
+                              _ptr(_c(bg, np.float64)), _ptr(ga), float(gate_rel), _ptr(md),
+                              _ptr(ms))
     return md, ms
 
 
@@ -223,6 +227,16 @@ def trace_ray(g: Grid, o, d, cap=None):
                             _ptr(sp), _ptr(rp), _ptr(cell))
     assert n <= cap, "trace capacity too small"
     return dict(t=t[:n], delta=delta[:n], sigma_pre=sp[:n], rgb_pre=rp[:n], cell=cell[:n])
+
+
+def camera_rays(c2w, focal, width, height):
+    """Pixel-centred pinhole rays of one view (orc_camera_rays):
+    (rays_o, rays_d) float32 [H*W, 3]."""
+    m = _c(c2w, np.float64).reshape(12)
+    o = np.empty((width * height, 3), np.float32)
+    d = np.empty((width * height, 3), np.float32)
+    lib().orc_camera_rays(_ptr(m), float(focal), int(width), int(height), _ptr(o), _ptr(d))
+    return o, d
 
 
 def ray_extent(g: Grid, o, d):

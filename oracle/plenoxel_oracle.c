@@ -364,6 +364,34 @@ int orc_trace_ray(const int32_t reso[3], const float scale[3],
     return n;
 }
 
+/* Rays of a novel-view request: a pixel-centred pinhole camera of W x H
+ * pixels, focal length f (pixels, principal point at the image centre) and
+ * camera-to-world matrix c2w (3x4 row-major: columns are the camera x, y, z
+ * axes and the centre; the camera looks along -z, image y points up).
+ * Pixel (px, py), row-major, gets
+ *   d_cam = ((px + 0.5 - W/2)/f, -((py + 0.5 - H/2)/f), -1),
+ *   d = R d_cam / |R d_cam|  (FP64, sums left to right, rounded to FP32),
+ *   o = the camera centre (rounded to FP32). */
+void orc_camera_rays(const double c2w[12], double focal, int32_t width,
+                     int32_t height, float *rays_o, float *rays_d)
+{
+    for (int32_t py = 0; py < height; ++py)
+        for (int32_t px = 0; px < width; ++px) {
+            double x = ((double)px + 0.5 - 0.5 * (double)width) / focal;
+            double y = -(((double)py + 0.5 - 0.5 * (double)height) / focal);
+            double z = -1.0;
+            double dv[3];
+            for (int a = 0; a < 3; ++a)
+                dv[a] = c2w[4 * a + 0] * x + c2w[4 * a + 1] * y + c2w[4 * a + 2] * z;
+            double nrm = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            int64_t r = (int64_t)py * width + px;
+            for (int a = 0; a < 3; ++a) {
+                rays_d[3 * r + a] = (float)(dv[a] / nrm);
+                rays_o[3 * r + a] = (float)c2w[4 * a + 3];
+            }
+        }
+}
+
 /* Ray setup only, for tests: t_near/t_far of the FP32 recipe and the sample
  * count.  Returns 1 on hit. */
 int orc_ray_extent(const int32_t reso[3], const float scale[3],
@@ -454,14 +482,20 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
  * delta (T_{k+1} g.c - g.R) contributes delta (T_{k+1} |g|.c + |g|.R), the
  * size of the two parts whose difference it is; for SH, |w_k g_ch Y_l|.
  * A float32 evaluation of the gradient can differ from the exact one by a
- * small multiple of the float32 unit roundoff times these sums. */
+ * small multiple of the float32 unit roundoff times these sums.
+ *
+ * A ReLU gate (sigma_pre > 0, colour_pre > 0) is a discrete decision taken
+ * from a rounded value: when |pre| <= gate_rel times the sum of the absolute
+ * terms that form it, float32 may decide it either way, and both gradients
+ * are correct.  Such terms enter the mass whether or not the gate is open
+ * here, so the tolerance admits either decision. */
 void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
                          const float offset[3], float step,
                          const int32_t *index, const double *density,
                          const double *sh, const float *rays_o,
                          const float *rays_d, int64_t n_rays,
                          const double bg[3], const double *gabs_rgb,
-                         double *mass_density, double *mass_sh)
+                         double gate_rel, double *mass_density, double *mass_sh)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < n_rays; ++r) {
@@ -479,15 +513,27 @@ void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
         double R[3] = {T_n * fabs(bg[0]), T_n * fabs(bg[1]), T_n * fabs(bg[2])};
         for (int k = n - 1; k >= 0; --k) {
             const sample_rec *s = &recs[k];
+            /* absolute sums behind sigma_pre and the three colours */
+            double abs_sig = 0.0, abs_col[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = s->ids[c];
+                if (id < 0) continue;
+                abs_sig += s->w[c] * fabs(density[id]);
+                for (int ch = 0; ch < 3; ++ch)
+                    for (int l = 0; l < 9; ++l)
+                        abs_col[ch] += s->w[c] * fabs(sh[id * ORC_NSH + ch * 9 + l] * ylm[l]);
+            }
             double gc = 0.0, gR = 0.0;
             for (int ch = 0; ch < 3; ++ch) {
-                gc += g[ch] * s->rgb[ch];
+                gc += g[ch] * fabs(s->rgb_pre[ch]);
                 gR += g[ch] * R[ch];
             }
-            double msig = s->sigma_pre > 0.0 ? s->delta * (s->T_next * gc + gR) : 0.0;
+            int sig_on = s->sigma_pre > 0.0 || fabs(s->sigma_pre) <= gate_rel * abs_sig;
+            double msig = sig_on ? s->delta * (s->T_next * gc + gR) : 0.0;
             double mk[ORC_NSH];
             for (int ch = 0; ch < 3; ++ch) {
-                double dcol = s->rgb_pre[ch] > 0.0 ? s->weight * g[ch] : 0.0;
+                int on = s->rgb_pre[ch] > 0.0 || fabs(s->rgb_pre[ch]) <= gate_rel * abs_col[ch];
+                double dcol = on ? s->weight * g[ch] : 0.0;
                 for (int l = 0; l < 9; ++l) mk[ch * 9 + l] = dcol * fabs(ylm[l]);
             }
             for (int c = 0; c < 8; ++c) {

@@ -65,6 +65,8 @@ _SIGS = {
     "plx_version": ([], ctypes.c_char_p),
     "plx_record_bytes": ([_I32], _I64),
     "plx_occ_words": ([_P], _I64),
+    "plx_occ_bytes": ([_P], _I64),
+    "plx_occ_brick_offset": ([_P], _I64),
     "plx_grid_geometry": ([_P, _P, _P, ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "plx_lr_schedule": ([ctypes.c_double] * 6, ctypes.c_double),
     "plx_mask_count": ([_P, _I64, _P, _P], ctypes.c_int),
@@ -150,6 +152,14 @@ def plx_record_bytes(sh_dtype: int) -> int:
 
 def plx_occ_words(reso) -> int:
     return int(lib().plx_occ_words(ctypes.cast(_i3(reso), _P)))
+
+
+def plx_occ_bytes(reso) -> int:
+    return int(lib().plx_occ_bytes(ctypes.cast(_i3(reso), _P)))
+
+
+def plx_occ_brick_offset(reso) -> int:
+    return int(lib().plx_occ_brick_offset(ctypes.cast(_i3(reso), _P)))
 
 
 def plx_grid_geometry(reso, lo=(-0.5,) * 3, hi=(0.5,) * 3, step_voxels=0.5):

@@ -98,7 +98,17 @@ int64_t plx_record_bytes(int32_t sh_dtype) {
 
 int64_t plx_occ_words(const int32_t reso[3]) {
     if (!reso) return 0;
-    return (n_cells(reso) + 31) / 32;
+    return occ_words(reso);
+}
+
+int64_t plx_occ_brick_offset(const int32_t reso[3]) {
+    if (!reso || reso[0] < 2 || reso[1] < 2 || reso[2] < 2) return 0;
+    return occ_brick_offset(reso);
+}
+
+int64_t plx_occ_bytes(const int32_t reso[3]) {
+    if (!reso || reso[0] < 2 || reso[1] < 2 || reso[2] < 2) return 0;
+    return (occ_brick_offset(reso) + n_bricks(reso) + 255) / 256 * 256;
 }
 
 int plx_grid_geometry(const int32_t reso[3], const double lo[3], const double hi[3],

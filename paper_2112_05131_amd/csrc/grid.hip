@@ -259,6 +259,61 @@ __global__ void occupancy_kernel(GridDev g, int64_t ncell, int64_t nwords, uint3
     if (lane == 32 && w + 1 < nwords) occ[w + 1] = (uint32_t)(b >> 32);
 }
 
+// Brick seed: 0 when any cell of the brick has its occupancy bit, else far.
+__global__ void brick_seed_kernel(GridDev g, uint8_t *bd) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = (int64_t)g.bx * g.by * g.bz;
+    if (b >= nb) return;
+    const int bk = (int)(b % g.bz);
+    const int bj = (int)((b / g.bz) % g.by);
+    const int bi = (int)(b / ((int64_t)g.bz * g.by));
+    const int i1 = min((bi + 1) * PLX_BRICK, g.nx - 1), j1 = min((bj + 1) * PLX_BRICK, g.ny - 1),
+              k0 = bk * PLX_BRICK, k1 = min((bk + 1) * PLX_BRICK, g.nz - 1);
+    bool any = false;
+    for (int i = bi * PLX_BRICK; i < i1 && !any; ++i)
+        for (int j = bj * PLX_BRICK; j < j1 && !any; ++j) {
+            const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
+            for (int k = k0; k < k1; ++k) {
+                const int64_t v = row + k;
+                if ((g.occ[v >> 5] >> (v & 31)) & 1u) {
+                    any = true;
+                    break;
+                }
+            }
+        }
+    bd[b] = any ? 0 : 255;
+}
+
+// One relaxation pass of the Chebyshev distance over bricks, in place:
+// d <- min(d, 1 + min over the 26 neighbours).  Every value stays an upper
+// bound of the true distance; `last` clamps to the cap, which turns the
+// values of unconverged (far) bricks into lower bounds.
+__global__ void brick_dist_pass_kernel(GridDev g, uint8_t *bd, int last) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = (int64_t)g.bx * g.by * g.bz;
+    if (b >= nb) return;
+    const int bk = (int)(b % g.bz);
+    const int bj = (int)((b / g.bz) % g.by);
+    const int bi = (int)(b / ((int64_t)g.bz * g.by));
+    int d = bd[b];
+    for (int a = -1; a <= 1; ++a) {
+        const int ii = bi + a;
+        if (ii < 0 || ii >= g.bx) continue;
+        for (int c = -1; c <= 1; ++c) {
+            const int jj = bj + c;
+            if (jj < 0 || jj >= g.by) continue;
+            for (int e = -1; e <= 1; ++e) {
+                const int kk = bk + e;
+                if (kk < 0 || kk >= g.bz) continue;
+                const int nd = bd[((int64_t)ii * g.by + jj) * g.bz + kk] + 1;
+                d = nd < d ? nd : d;
+            }
+        }
+    }
+    if (last) d = d < PLX_BRICK_DIST_CAP ? d : PLX_BRICK_DIST_CAP;
+    bd[b] = (uint8_t)d;
+}
+
 template <int DT>
 __global__ void prune_occ_kernel(GridDev g, int64_t ncell, float thresh, uint8_t *occ8) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,8 +535,20 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
     int64_t nwords = plx_occ_words(grid->reso);
     // whole waves, so every word is written by the wave that owns it
     int64_t nthreads = (ncell + 63) / 64 * 64;
-    occupancy_kernel<<<blocks_for(nthreads, 256), 256, 0, s>>>(to_dev(grid), ncell, nwords, occ_out);
-    return check_launch("plx_grid_build_occupancy");
+    plx_grid gd = *grid;
+    gd.occ = occ_out;
+    GridDev g = to_dev(&gd);
+    occupancy_kernel<<<blocks_for(nthreads, 256), 256, 0, s>>>(g, ncell, nwords, occ_out);
+    if ((rc = check_launch("plx_grid_build_occupancy"))) return rc;
+    uint8_t *bd = reinterpret_cast<uint8_t *>(occ_out) + occ_brick_offset(grid->reso);
+    const int64_t nb = n_bricks(grid->reso);
+    brick_seed_kernel<<<blocks_for(nb, 256), 256, 0, s>>>(g, bd);
+    if ((rc = check_launch("plx_grid_build_occupancy"))) return rc;
+    for (int p = 0; p < PLX_BRICK_DIST_CAP; ++p) {
+        brick_dist_pass_kernel<<<blocks_for(nb, 256), 256, 0, s>>>(g, bd, p == PLX_BRICK_DIST_CAP - 1);
+        if ((rc = check_launch("plx_grid_build_occupancy"))) return rc;
+    }
+    return PLX_OK;
 }
 
 int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,

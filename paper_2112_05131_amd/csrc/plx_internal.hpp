@@ -31,14 +31,24 @@ int validate_grid(const plx_grid *g, bool need_occ, const char *fn);
 
 inline int64_t n_cells(const int32_t r[3]) { return (int64_t)r[0] * r[1] * r[2]; }
 
+// Bricks of PLX_BRICK^3 cells over the cell lattice 0..N-2 per axis.
+inline int bricks_along(int n) { return (n - 1 + PLX_BRICK - 1) / PLX_BRICK; }
+inline int64_t occ_words(const int32_t r[3]) { return (n_cells(r) + 31) / 32; }
+inline int64_t occ_brick_offset(const int32_t r[3]) { return (occ_words(r) * 4 + 255) / 256 * 256; }
+inline int64_t n_bricks(const int32_t r[3]) {
+    return (int64_t)bricks_along(r[0]) * bricks_along(r[1]) * bricks_along(r[2]);
+}
+
 // -------------------------------------------------------- kernel-side grid
 struct GridDev {
     int nx, ny, nz;
+    int bx, by, bz;  // bricks per axis
     float scale[3], offset[3];
     float step;
     const int32_t *index;
     const void *data;
-    const uint32_t *occ;
+    const uint32_t *occ;     // cell bitmap
+    const uint8_t *bdist;    // brick distances
     int64_t n_vox;
 };
 
@@ -47,6 +57,9 @@ inline GridDev to_dev(const plx_grid *g) {
     d.nx = g->reso[0];
     d.ny = g->reso[1];
     d.nz = g->reso[2];
+    d.bx = bricks_along(d.nx);
+    d.by = bricks_along(d.ny);
+    d.bz = bricks_along(d.nz);
     for (int a = 0; a < 3; ++a) {
         d.scale[a] = g->scale[a];
         d.offset[a] = g->offset[a];
@@ -55,6 +68,8 @@ inline GridDev to_dev(const plx_grid *g) {
     d.index = g->index;
     d.data = g->data;
     d.occ = g->occ;
+    d.bdist = g->occ ? reinterpret_cast<const uint8_t *>(g->occ) + occ_brick_offset(g->reso)
+                     : nullptr;
     d.n_vox = g->n_vox;
     return d;
 }
@@ -196,13 +211,21 @@ constexpr int kRec16Bytes = 64;
 
 template <int DT> struct Rec;
 
+// Record access in two steps so that a caller can issue all its loads before
+// converting any of them: raw() loads lane L's chunk (slots 4L..4L+3),
+// cvt() turns it into four floats without branches.
 template <> struct Rec<PLX_F32> {
     static constexpr int bytes = kRecF32Bytes;
-    // slots 4L..4L+3 of a record
-    __device__ static inline float4 load4(const void *data, int64_t id, int L) {
+    using Raw = float4;
+    __device__ static inline Raw raw(const void *data, int64_t id, int L) {
         const float4 *p = reinterpret_cast<const float4 *>(
             static_cast<const char *>(data) + id * (int64_t)kRecF32Bytes);
         return p[L];
+    }
+    __device__ static inline Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static inline float4 cvt(Raw r, int) { return r; }
+    __device__ static inline float4 load4(const void *data, int64_t id, int L) {
+        return raw(data, id, L);
     }
 };
 
@@ -213,25 +236,28 @@ __device__ inline float f16_to_f32(uint32_t h) {
 
 template <int DT> struct Rec16 {
     static constexpr int bytes = kRec16Bytes;
-    __device__ static inline float cvt(uint32_t h) {
+    using Raw = uint2;
+    __device__ static inline float h2f(uint32_t h) {
         return DT == PLX_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
     }
-    // slots 4L..4L+3 (lane 7 returns sigma in .x)
-    __device__ static inline float4 load4(const void *data, int64_t id, int L) {
+    __device__ static inline Raw raw(const void *data, int64_t id, int L) {
         const uint2 *p = reinterpret_cast<const uint2 *>(
             static_cast<const char *>(data) + id * (int64_t)kRec16Bytes);
-        uint2 w = p[L];
+        return p[L];
+    }
+    __device__ static inline Raw zero() { return make_uint2(0u, 0u); }
+    // slots 4L..4L+3; lane 7's chunk holds sigma (FP32) in its first word
+    __device__ static inline float4 cvt(Raw w, int L) {
+        const bool sig = L == 7;
         float4 v;
-        if (L == 7) {
-            v.x = __uint_as_float(w.x);
-            v.y = v.z = v.w = 0.0f;
-        } else {
-            v.x = cvt(w.x & 0xffffu);
-            v.y = cvt(w.x >> 16);
-            v.z = cvt(w.y & 0xffffu);
-            v.w = cvt(w.y >> 16);
-        }
+        v.x = sig ? __uint_as_float(w.x) : h2f(w.x & 0xffffu);
+        v.y = sig ? 0.0f : h2f(w.x >> 16);
+        v.z = sig ? 0.0f : h2f(w.y & 0xffffu);
+        v.w = sig ? 0.0f : h2f(w.y >> 16);
         return v;
+    }
+    __device__ static inline float4 load4(const void *data, int64_t id, int L) {
+        return cvt(raw(data, id, L), L);
     }
 };
 template <> struct Rec<PLX_BF16> : Rec16<PLX_BF16> {};

@@ -1,38 +1,53 @@
 // render.hip -- differentiable volume rendering over the sparse voxel grid
 // (Sec. 3.1-3.3, Eq. (1); supplement B.1) for gfx950.
 //
-// Work mapping.  One ray per group of 8 lanes (8 rays per wave64, 32 per
-// 256-thread block).  Lane L of a group owns record slots 4L..4L+3, so the 8
-// lanes together read a voxel record with one 16-byte load each (one 128-byte
-// line for FP32 records, half a line for 16-bit ones).  Lane 7 holds sigma
-// (slot 28).  Ray-level scalars (geometry, transmittance, colour) are kept
-// redundantly by the 8 lanes; SH colour is a 3-channel sum over the group
-// (xor shuffles), sigma is a shuffle from lane 7.
+// Work mapping.  One ray per 32 lanes (two rays per wave64, eight per
+// 256-thread block), lane L owning record slot L: slots 0..26 are the SH
+// coefficients, lane 28 holds sigma.  A corner record is read with one 4-byte
+// load per lane (one 128-byte line for FP32 records), and a corner's gradient
+// is added with one atomic instruction whose lanes cover one contiguous line,
+// the access pattern for which the L2 float atomics of CDNA4 are fastest.
+// Ray-level scalars are kept redundantly by the 32 lanes; SH colour is three
+// xor-shuffle sums over the ray's lanes and sigma a shuffle from lane 28.
 //
-// Exact empty-space skipping.  A sample whose lower-corner cell has no
-// non-NULL corner reads only zeros: it changes neither colour nor
-// transmittance and has no gradient.  Candidate samples are tested 32 at a
-// time against the cell occupancy bitmap (4 per lane, one ballot each), and
-// only the occupied ones are processed, in order.  The 8 corner ids and the
-// lane's 8 corner values stay in registers while consecutive samples remain
-// in the same cell.
+// Exact empty-space skipping, two levels.  A sample whose lower-corner cell
+// has no non-NULL corner reads only zeros: it changes neither colour nor
+// transmittance and has no gradient.
+//  - Brick level: every 8^3-cell brick stores its Chebyshev distance D (in
+//    bricks) to the nearest brick with an occupied cell.  From a sample in a
+//    brick with D > 0, every cell of the box of bricks within D-1 of it is
+//    empty, so the ray jumps to the box's exit point along its own direction
+//    (less a margin of 5% of a step, far above FP32 rounding of t and g).
+//  - Cell level: near occupied bricks, 32 candidate samples are tested at a
+//    time against the cell bitmap (one per lane, one ballot) and only the
+//    occupied ones are processed, in order.
+// The 8 corner ids and the lane's 8 corner values stay in registers while
+// consecutive samples stay in one cell; a move to a face-adjacent cell keeps
+// the 4 shared corners and loads only the other 4.
+//
+// Transmittance is exp(-tau) of the FP64 optical depth in both passes.
 //
 // Backward.  The ray is replayed from its last sample to its first.  With
 // tau_after the optical depth after sample k (starting from the forward
 // total), T_{k+1} = exp(-tau_after), T_k = exp(-(tau_after - sigma delta))
 // and the rest of the ray R_k = sum_{j>k} w_j c_j + T_n bg is a running sum;
 // dC/dsigma_k = delta (T_{k+1} c_k - R_k), dC/dc_k = w_k.  Corner gradients
-// are accumulated in registers while the ray stays in one cell and added to
-// the FP32 gradient records with hardware float atomics when it leaves.
+// are accumulated in registers for as long as a voxel stays a corner of the
+// current cell and are added to the FP32 gradient records with hardware float
+// atomics when it stops being one.  The fused training kernel keeps the list
+// of non-empty 32-sample chunks found by its forward pass in LDS and replays
+// exactly those in reverse.
 #include "plx_internal.hpp"
 
 namespace plx {
 namespace {
 
-constexpr int kLPR = 8;                         // lanes per ray
+constexpr int kLPR = 32;                        // lanes per ray
 constexpr int kThreads = 256;                   // 4 waves
-constexpr int kRaysPerBlock = kThreads / kLPR;  // 32
-constexpr int kChunk = 32;                      // candidate samples per round
+constexpr int kRaysPerBlock = kThreads / kLPR;  // 8
+constexpr int kChunk = 32;                      // candidate samples per round (one per lane)
+constexpr int kMaxChunks = 48;                  // chunk list entries per ray (fused kernel)
+constexpr float kSkipMargin = 0.05f;            // in steps
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
 
@@ -54,26 +69,134 @@ struct RenderArgs {
     int nb8;
 };
 
-// Per-lane corner cache of the current cell.
+// Slot L of a record as one 32-bit load plus a branch-free conversion.
+template <int DT> struct Slot;
+template <> struct Slot<PLX_F32> {
+    __device__ static inline uint32_t raw(const void *data, int64_t id, int L) {
+        return reinterpret_cast<const uint32_t *>(static_cast<const char *>(data) +
+                                                  id * (int64_t)kRecF32Bytes)[L];
+    }
+    __device__ static inline float cvt(uint32_t r, int) { return __uint_as_float(r); }
+};
+template <int DT> struct Slot16 {
+    // lanes 0..27 read the 32-bit word holding their 16-bit slot, lane 28
+    // the FP32 sigma at byte 56, lanes 29..31 read nothing
+    __device__ static inline uint32_t raw(const void *data, int64_t id, int L) {
+        if (L > PLX_SLOT_SIGMA) return 0u;
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(static_cast<const char *>(data) +
+                                                               id * (int64_t)kRec16Bytes);
+        return p[L == PLX_SLOT_SIGMA ? 14 : (L >> 1)];
+    }
+    __device__ static inline float cvt(uint32_t r, int L) {
+        const uint32_t h = (L & 1) ? (r >> 16) : (r & 0xffffu);
+        const float v = DT == PLX_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
+        return L == PLX_SLOT_SIGMA ? __uint_as_float(r) : (L < PLX_NSH ? v : 0.0f);
+    }
+};
+template <> struct Slot<PLX_BF16> : Slot16<PLX_BF16> {};
+template <> struct Slot<PLX_F16> : Slot16<PLX_F16> {};
+
+// Per-lane cache of the current cell: corner ids (all lanes), the id of
+// corner L (lanes 0..7), and this lane's slot of the eight corner records.
 struct CornerCache {
-    int64_t cell;  // storage id of the lower corner, -1 = none
-    int myc;       // table id of corner L (this lane's corner)
+    int cell[3];  // lower corner; cell[0] < 0 = empty cache
+    int myc;
     int ids[8];
-    float4 val[8];
+    float val[8];
 };
 
+__device__ inline int64_t corner_offset(const GridDev &g, int c) {
+    return ((c >> 2) & 1) * ((int64_t)g.ny * g.nz) + ((c >> 1) & 1) * (int64_t)g.nz + (c & 1);
+}
+
+// Loads the corners of `mask` (bit c = corner c) for the cell cc.cell.
+// Returns the id of corner L when L is in the mask (-1 otherwise).
 template <int DT>
-__device__ inline void load_cell(const GridDev &g, int64_t lin, int L, CornerCache &cc) {
-    const int64_t sy = g.nz, sx = (int64_t)g.ny * g.nz;
-    const int64_t off = ((L >> 2) & 1) * sx + ((L >> 1) & 1) * sy + (L & 1);
-    cc.cell = lin;
-    cc.myc = g.index[lin + off];
+__device__ __forceinline__ int load_corners(const GridDev &g, CornerCache &cc, int L, unsigned mask) {
+    const int64_t lin = cell_id(g, cc.cell);
+    const int mine = (L < 8 && ((mask >> L) & 1u)) ? g.index[lin + corner_offset(g, L)] : -1;
+    uint32_t raw[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) cc.ids[c] = __shfl(cc.myc, c, kLPR);
+    for (int c = 0; c < 8; ++c) {
+        if ((mask >> c) & 1u) {
+            cc.ids[c] = __shfl(mine, c, kLPR);
+            raw[c] = cc.ids[c] >= 0 ? Slot<DT>::raw(g.data, cc.ids[c], L) : 0u;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        cc.val[c] = cc.ids[c] >= 0 ? Rec<DT>::load4(g.data, cc.ids[c], L)
-                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        if ((mask >> c) & 1u) cc.val[c] = cc.ids[c] >= 0 ? Slot<DT>::cvt(raw[c], L) : 0.0f;
+    return mine;
+}
+
+// Adds the accumulators of the corners in `mask` to the gradient records
+// (one atomic instruction per corner line) and marks those corners touched;
+// clears their accumulators.
+__device__ __forceinline__ void flush(float *grad, uint32_t *touched, const CornerCache &cc,
+                                      float acc[8], int L, unsigned mask) {
+    const bool slot_used = L < PLX_NSH || L == PLX_SLOT_SIGMA;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!((mask >> c) & 1u)) continue;
+        if (cc.ids[c] >= 0 && slot_used && acc[c] != 0.0f)
+            unsafeAtomicAdd(grad + (int64_t)cc.ids[c] * PLX_REC_SLOTS + L, acc[c]);
+        acc[c] = 0.0f;
+    }
+    if (L < 8 && ((mask >> L) & 1u) && cc.myc >= 0)
+        atomicOr(touched + (cc.myc >> 5), 1u << (cc.myc & 31));
+}
+
+// Moves the cache along one axis (BIT 4 = x, 2 = y, 1 = z) by +1 (PLUS) or
+// -1: the four shared corners change position, the other four are flushed
+// (backward) and reloaded.
+template <int DT, bool BWD, int BIT, bool PLUS>
+__device__ __forceinline__ void shift_cell(const GridDev &g, CornerCache &cc, float acc[8],
+                                           float *grad, uint32_t *touched, int L) {
+    // positions that receive a shared corner (and whose old corner leaves)
+    unsigned keep = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (((c & BIT) != 0) == !PLUS) keep |= 1u << c;
+    if (BWD) flush(grad, touched, cc, acc, L, keep);
+    // corner L's new voxel was corner L^BIT, held by lane L^BIT
+    const int shifted = __shfl(cc.myc, (L ^ BIT) & 7, kLPR);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if ((keep >> c) & 1u) {
+            cc.ids[c] = cc.ids[c ^ BIT];
+            cc.val[c] = cc.val[c ^ BIT];
+            if (BWD) {
+                acc[c] = acc[c ^ BIT];
+                acc[c ^ BIT] = 0.0f;
+            }
+        }
+    }
+    constexpr int a = BIT == 4 ? 0 : (BIT == 2 ? 1 : 2);
+    cc.cell[a] += PLUS ? 1 : -1;
+    const int mine = load_corners<DT>(g, cc, L, 0xffu & ~keep);
+    cc.myc = (L < 8 && ((keep >> L) & 1u)) ? shifted : mine;
+}
+
+// Makes `cell` the cached cell.
+template <int DT, bool BWD>
+__device__ __forceinline__ void move_to(const GridDev &g, CornerCache &cc, const int cell[3],
+                                        float acc[8], float *grad, uint32_t *touched, int L) {
+    const int dx = cell[0] - cc.cell[0], dy = cell[1] - cc.cell[1], dz = cell[2] - cc.cell[2];
+    if (dx == 0 && dy == 0 && dz == 0) return;
+    if (cc.cell[0] >= 0 && abs(dx) + abs(dy) + abs(dz) == 1) {
+        if (dx == 1) shift_cell<DT, BWD, 4, true>(g, cc, acc, grad, touched, L);
+        else if (dx == -1) shift_cell<DT, BWD, 4, false>(g, cc, acc, grad, touched, L);
+        else if (dy == 1) shift_cell<DT, BWD, 2, true>(g, cc, acc, grad, touched, L);
+        else if (dy == -1) shift_cell<DT, BWD, 2, false>(g, cc, acc, grad, touched, L);
+        else if (dz == 1) shift_cell<DT, BWD, 1, true>(g, cc, acc, grad, touched, L);
+        else shift_cell<DT, BWD, 1, false>(g, cc, acc, grad, touched, L);
+        return;
+    }
+    if (BWD && cc.cell[0] >= 0) flush(grad, touched, cc, acc, L, 0xffu);
+    cc.cell[0] = cell[0];
+    cc.cell[1] = cell[1];
+    cc.cell[2] = cell[2];
+    cc.myc = load_corners<DT>(g, cc, L, 0xffu);
 }
 
 __device__ inline void corner_weights(const float f[3], float w[8]) {
@@ -84,26 +207,19 @@ __device__ inline void corner_weights(const float f[3], float w[8]) {
     for (int c = 0; c < 8; ++c) w[c] = ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1];
 }
 
-// Interpolated slots of this lane, the (pre-ReLU) sigma of the group and the
-// (pre-ReLU) colour of the group.
+// Interpolated (pre-ReLU) sigma and colour of the ray's current sample.
 struct Interp {
     float sigma_pre;
     float col_pre[3];
 };
 
-__device__ inline Interp interpolate(const CornerCache &cc, const float w[8], const float yr[4],
-                                     const float yg[4], const float yb[4]) {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+__device__ __forceinline__ Interp interpolate(const CornerCache &cc, const float w[8], float y,
+                                              int ch) {
+    float v = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        v.x += w[c] * cc.val[c].x;
-        v.y += w[c] * cc.val[c].y;
-        v.z += w[c] * cc.val[c].z;
-        v.w += w[c] * cc.val[c].w;
-    }
-    float pr = v.x * yr[0] + v.y * yr[1] + v.z * yr[2] + v.w * yr[3];
-    float pg = v.x * yg[0] + v.y * yg[1] + v.z * yg[2] + v.w * yg[3];
-    float pb = v.x * yb[0] + v.y * yb[1] + v.z * yb[2] + v.w * yb[3];
+    for (int c = 0; c < 8; ++c) v += w[c] * cc.val[c];
+    const float p = v * y;
+    float pr = ch == 0 ? p : 0.0f, pg = ch == 1 ? p : 0.0f, pb = ch == 2 ? p : 0.0f;
 #pragma unroll
     for (int m = 1; m < kLPR; m <<= 1) {
         pr += __shfl_xor(pr, m, kLPR);
@@ -111,58 +227,126 @@ __device__ inline Interp interpolate(const CornerCache &cc, const float w[8], co
         pb += __shfl_xor(pb, m, kLPR);
     }
     Interp r;
-    r.sigma_pre = __shfl(v.x, 7, kLPR);
+    r.sigma_pre = __shfl(v, PLX_SLOT_SIGMA, kLPR);
     r.col_pre[0] = pr;
     r.col_pre[1] = pg;
     r.col_pre[2] = pb;
     return r;
 }
 
-// Occupancy of the 32 candidate samples k0..k0+31 of the group's ray
-// (bit i = sample k0+i lies in an occupied cell).  Group-uniform result.
+// Occupancy of the 32 candidate samples k0..k0+31 of the ray (bit i = sample
+// k0+i exists and lies in an occupied cell).  Uniform over the ray's lanes.
 __device__ inline uint32_t chunk_mask(const GridDev &g, const RayGeom &r, int n, int k0, int L) {
-    uint32_t m = 0;
-    const int shift = threadIdx.x & 56;
-#pragma unroll
-    for (int j = 0; j < kChunk / kLPR; ++j) {
-        const int k = k0 + j * kLPR + L;
-        bool ne = false;
-        if (k < n) {
-            Sample s = sample_at(g, r, k);
-            ne = cell_occupied(g, cell_id(g, s.cell));
-        }
-        unsigned long long b = __ballot(ne);
-        m |= ((uint32_t)(b >> shift) & 0xffu) << (kLPR * j);
+    const int k = k0 + L;
+    bool ne = false;
+    if (k >= 0 && k < n) {
+        Sample s = sample_at(g, r, k);
+        ne = cell_occupied(g, cell_id(g, s.cell));
     }
-    return m;
+    const unsigned long long b = __ballot(ne);
+    return (uint32_t)(b >> (threadIdx.x & 32));
 }
 
-// Adds the register accumulators of the cached cell into the gradient
-// records and marks its non-NULL corners as touched.
-__device__ inline void flush(float *grad, uint32_t *touched, const CornerCache &cc, float4 acc[8],
-                             int L) {
+// Brick-level skip.  Returns the distance D of the brick of sample k (0 when
+// it has an occupied cell); for D > 0 also the number of further samples m
+// (in the direction of travel) that certainly stay in the empty box of bricks
+// within D-1 of it.
+template <bool FORWARD>
+__device__ __forceinline__ int brick_skip(const GridDev &g, const RayGeom &r, int k, const Sample &s,
+                                          int *m) {
+    const int b[3] = {s.cell[0] / PLX_BRICK, s.cell[1] / PLX_BRICK, s.cell[2] / PLX_BRICK};
+    const int D = g.bdist[((int64_t)b[0] * g.by + b[1]) * g.bz + b[2]];
+    if (D == 0) return 0;
+    const int nb[3] = {g.bx, g.by, g.bz};
+    const float t = r.t_near + (float)k * g.step;
+    float t_edge = FORWARD ? __builtin_inff() : -__builtin_inff();
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (cc.ids[c] >= 0) {
-            float *p = grad + (int64_t)cc.ids[c] * PLX_REC_SLOTS + 4 * L;
-            const float a4[4] = {acc[c].x, acc[c].y, acc[c].z, acc[c].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int s = 4 * L + e;
-                if ((s < PLX_NSH || s == PLX_SLOT_SIGMA) && a4[e] != 0.0f) unsafeAtomicAdd(p + e, a4[e]);
+    for (int a = 0; a < 3; ++a) {
+        const float dg = r.dg[a];
+        if (dg == 0.0f) continue;
+        // box faces on the grid boundary are never crossed by a sample
+        const bool up = (dg > 0.0f) == FORWARD;
+        const int bf = up ? b[a] + (D - 1) : b[a] - (D - 1);
+        if (up ? bf >= nb[a] - 1 : bf <= 0) continue;
+        const float face = (float)((up ? bf + 1 : bf) * PLX_BRICK);
+        const float tf = (face - r.og[a]) / dg;
+        t_edge = FORWARD ? fminf(t_edge, tf) : fmaxf(t_edge, tf);
+    }
+    const float span = FORWARD ? (t_edge - t) : (t - t_edge);
+    float q = span / g.step - kSkipMargin;
+    q = q < (float)kMaxSamples ? q : (float)kMaxSamples;
+    *m = q > 0.0f ? (int)q : 0;
+    return D;
+}
+
+// ------------------------------------------------------------------ forward march
+
+struct ChunkEntry {
+    int k0;
+    uint32_t mask;
+};
+
+// Front-to-back march of one ray (Eq. (1)): returns the colour before the
+// background is added in C, and the optical depth in tau.  With RECORD, the
+// non-empty chunks are appended to `list` (capacity kMaxChunks; *overflow is
+// set when it runs out).
+template <int DT, bool RECORD>
+__device__ __forceinline__ void march_forward(const GridDev &g, const RayGeom &r, int n, int L,
+                                              float y, int ch, CornerCache &cc, float acc[8],
+                                              float C[3], double &tau, ChunkEntry *list,
+                                              int &n_list, bool &overflow) {
+    C[0] = C[1] = C[2] = 0.0f;
+    tau = 0.0;
+    int k = 0;
+    while (k < n) {
+        const Sample s0 = sample_at(g, r, k);
+        int m;
+        if (brick_skip<true>(g, r, k, s0, &m)) {
+            k += m + 1;
+            continue;
+        }
+        uint32_t mask = chunk_mask(g, r, n, k, L);
+        if (RECORD && mask) {
+            if (n_list < kMaxChunks) {
+                list[n_list].k0 = k;  // every lane of the ray writes the same entry
+                list[n_list].mask = mask;
+                ++n_list;
+            } else {
+                overflow = true;
             }
         }
-        acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+        while (mask) {
+            const int bit = __ffs(mask) - 1;
+            mask &= mask - 1;
+            const Sample s = sample_at(g, r, k + bit);
+            move_to<DT, false>(g, cc, s.cell, acc, nullptr, nullptr, L);
+            float w[8];
+            corner_weights(s.f, w);
+            const Interp ip = interpolate(cc, w, y, ch);
+            const float sigma = fmaxf(ip.sigma_pre, 0.0f);
+            const float sd = sigma * s.delta;
+            const float wk = expf(-(float)tau) * (-expm1f(-sd));
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) C[c3] += wk * fmaxf(ip.col_pre[c3], 0.0f);
+            tau += (double)sd;
+        }
+        k += kChunk;
     }
-    if (cc.myc >= 0) atomicOr(touched + (cc.myc >> 5), 1u << (cc.myc & 31));
 }
+
+// ------------------------------------------------------------------ kernel
 
 template <int DT, int MODE>
 __global__ __launch_bounds__(kThreads) void render_kernel(GridDev g, RenderArgs a) {
+    constexpr bool FWD = MODE == MODE_FWD || MODE == MODE_TRAIN;
+    constexpr bool BWD = MODE == MODE_BWD || MODE == MODE_TRAIN;
+    __shared__ ChunkEntry chunks[MODE == MODE_TRAIN ? kRaysPerBlock * kMaxChunks : 1];
+
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
     const int L = threadIdx.x & (kLPR - 1);
-    const int64_t ray = (int64_t)blk * kRaysPerBlock + (threadIdx.x / kLPR);
+    const int gid = threadIdx.x / kLPR;  // ray slot in the block
+    const int64_t ray = (int64_t)blk * kRaysPerBlock + gid;
     const bool live = ray < a.n_rays;
 
     float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
@@ -176,65 +360,48 @@ __global__ __launch_bounds__(kThreads) void render_kernel(GridDev g, RenderArgs 
     RayGeom r;
     const int n = live ? ray_setup(g, o, d, r) : 0;
 
-    // SH basis of this lane's four slots, split by colour channel
-    float yr[4], yg[4], yb[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int s = 4 * L + e;
-        const float y = s < PLX_NSH ? sh_basis_at(s % 9, d[0], d[1], d[2]) : 0.0f;
-        const int ch = s / 9;
-        yr[e] = ch == 0 ? y : 0.0f;
-        yg[e] = ch == 1 ? y : 0.0f;
-        yb[e] = (ch == 2 && s < PLX_NSH) ? y : 0.0f;
-    }
+    // SH basis value and colour channel of this lane's slot
+    const int ch = L < PLX_NSH ? L / 9 : 3;
+    const float y = L < PLX_NSH ? sh_basis_at(L % 9, d[0], d[1], d[2]) : 0.0f;
 
     CornerCache cc;
-    cc.cell = -1;
+    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
     cc.myc = -1;
+    float acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
 
-    float C[3] = {0.f, 0.f, 0.f};
-    float tau = 0.0f;
+    // optical depth in FP64: transmittance is exp(-tau) in both passes, so
+    // its error stays at one float rounding of tau instead of growing with the
+    // number of samples
+    double tau = 0.0;
     double loss = 0.0;
     float gr[3] = {0.f, 0.f, 0.f};
+    int n_list = 0;
+    bool overflow = false;
+    ChunkEntry *my_chunks = chunks + (MODE == MODE_TRAIN ? gid * kMaxChunks : 0);
 
     // ------------------------------------------------------------ forward
-    if (MODE == MODE_FWD || MODE == MODE_TRAIN) {
-        float T = 1.0f;
-        for (int k0 = 0; k0 < n; k0 += kChunk) {
-            uint32_t m = chunk_mask(g, r, n, k0, L);
-            while (m) {
-                const int bit = __ffs(m) - 1;
-                m &= m - 1;
-                const Sample s = sample_at(g, r, k0 + bit);
-                const int64_t lin = cell_id(g, s.cell);
-                if (lin != cc.cell) load_cell<DT>(g, lin, L, cc);
-                float w[8];
-                corner_weights(s.f, w);
-                const Interp ip = interpolate(cc, w, yr, yg, yb);
-                const float sigma = fmaxf(ip.sigma_pre, 0.0f);
-                const float sd = sigma * s.delta;
-                const float wk = T * (-expm1f(-sd));
+    if (FWD) {
+        float C[3];
+        march_forward<DT, MODE == MODE_TRAIN>(g, r, n, L, y, ch, cc, acc, C, tau, my_chunks, n_list,
+                                              overflow);
+        const float T_final = expf(-(float)tau);
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) C[ch] += wk * fmaxf(ip.col_pre[ch], 0.0f);
-                T *= expf(-sd);
-                tau += sd;
-            }
-        }
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) C[ch] += T * a.bg[ch];
+        for (int c3 = 0; c3 < 3; ++c3) C[c3] += T_final * a.bg[c3];
         if (live && L == 0) {
             if (MODE == MODE_FWD || a.rgb_out) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) a.rgb_out[3 * ray + ch] = C[ch];
+                for (int c3 = 0; c3 < 3; ++c3) a.rgb_out[3 * ray + c3] = C[c3];
             }
-            if (MODE == MODE_FWD && a.tau_out) a.tau_out[ray] = tau;
+            if (MODE == MODE_FWD && a.tau_out) a.tau_out[ray] = (float)tau;
         }
         if (MODE == MODE_TRAIN && live) {
             float l2 = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const float diff = C[ch] - a.target[3 * ray + ch];
-                gr[ch] = 2.0f * a.loss_scale * diff;
+            for (int c3 = 0; c3 < 3; ++c3) {
+                const float diff = C[c3] - a.target[3 * ray + c3];
+                gr[c3] = 2.0f * a.loss_scale * diff;
                 l2 += diff * diff;
             }
             if (L == 0) loss = (double)a.loss_scale * (double)l2;
@@ -242,68 +409,69 @@ __global__ __launch_bounds__(kThreads) void render_kernel(GridDev g, RenderArgs 
     }
 
     // ------------------------------------------------------------ backward
-    if (MODE == MODE_BWD || MODE == MODE_TRAIN) {
+    if (BWD) {
         if (MODE == MODE_BWD && live) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gr[ch] = a.grad_rgb[3 * ray + ch];
-            tau = a.tau_in[ray];
+            for (int c3 = 0; c3 < 3; ++c3) gr[c3] = a.grad_rgb[3 * ray + c3];
+            tau = (double)a.tau_in[ray];
         }
-        float4 acc[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-        bool dirty = false;
-        float tau_after = tau;
-        float T_after = expf(-tau_after);
+        double tau_after = tau;
+        float T_after = expf(-(float)tau_after);
         float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]);
-        const int last0 = n > 0 ? ((n - 1) / kChunk) * kChunk : -1;
-        for (int k0 = last0; k0 >= 0; k0 -= kChunk) {
-            uint32_t m = chunk_mask(g, r, n, k0, L);
-            while (m) {
-                const int bit = 31 - __clz(m);
-                m &= ~(1u << bit);
-                const Sample s = sample_at(g, r, k0 + bit);
-                const int64_t lin = cell_id(g, s.cell);
-                if (lin != cc.cell) {
-                    if (dirty) flush(a.grad, a.touched, cc, acc, L);
-                    load_cell<DT>(g, lin, L, cc);
+        const float gch = ch == 0 ? gr[0] : (ch == 1 ? gr[1] : (ch == 2 ? gr[2] : 0.0f));
+        // the cache may hold the forward pass's last cell: its corners have
+        // nothing accumulated yet, which is what the backward expects
+        const bool use_list = MODE == MODE_TRAIN && !overflow;
+        int li = n_list - 1;  // list cursor (fused kernel)
+        int k = n - 1;        // sample cursor (replay by traversal)
+        while (use_list ? li >= 0 : k >= 0) {
+            int k0;
+            uint32_t mask;
+            if (use_list) {
+                k0 = my_chunks[li].k0;
+                mask = my_chunks[li].mask;
+                --li;
+            } else {
+                const Sample s0 = sample_at(g, r, k);
+                int m;
+                if (brick_skip<false>(g, r, k, s0, &m)) {
+                    k -= m + 1;
+                    continue;
                 }
-                dirty = true;
+                k0 = k - (kChunk - 1);
+                mask = chunk_mask(g, r, n, k0, L);
+                k -= kChunk;
+            }
+            while (mask) {
+                const int bit = 31 - __clz(mask);
+                mask &= ~(1u << bit);
+                const Sample s = sample_at(g, r, k0 + bit);
+                move_to<DT, true>(g, cc, s.cell, acc, a.grad, a.touched, L);
                 float w[8];
                 corner_weights(s.f, w);
-                const Interp ip = interpolate(cc, w, yr, yg, yb);
+                const Interp ip = interpolate(cc, w, y, ch);
                 const float sigma = fmaxf(ip.sigma_pre, 0.0f);
                 const float sd = sigma * s.delta;
-                const float tau_before = fmaxf(tau_after - sd, 0.0f);
-                const float T_before = expf(-tau_before);
+                const double tau_before = fmax(tau_after - (double)sd, 0.0);
+                const float T_before = expf(-(float)tau_before);
                 const float wk = T_before * (-expm1f(-sd));
-                float col[3], gc = 0.0f;
+                float gc = 0.0f;
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    col[ch] = fmaxf(ip.col_pre[ch], 0.0f);
-                    gc += gr[ch] * col[ch];
-                }
+                for (int c3 = 0; c3 < 3; ++c3) gc += gr[c3] * fmaxf(ip.col_pre[c3], 0.0f);
                 const float dsig = ip.sigma_pre > 0.0f ? s.delta * (T_after * gc - gR) : 0.0f;
-                const float dR = ip.col_pre[0] > 0.0f ? wk * gr[0] : 0.0f;
-                const float dG = ip.col_pre[1] > 0.0f ? wk * gr[1] : 0.0f;
-                const float dB = ip.col_pre[2] > 0.0f ? wk * gr[2] : 0.0f;
+                const float pre_ch = ch == 0 ? ip.col_pre[0]
+                                             : (ch == 1 ? ip.col_pre[1] : ip.col_pre[2]);
                 gR += wk * gc;
                 tau_after = tau_before;
                 T_after = T_before;
-                // this lane's four slot gradients (slot 28 = sigma on lane 7)
-                float dk[4];
+                // this lane's slot gradient (slot 28 = sigma)
+                const float dk = L == PLX_SLOT_SIGMA ? dsig
+                                                     : (ch < 3 && pre_ch > 0.0f ? wk * gch * y : 0.0f);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) dk[e] = yr[e] * dR + yg[e] * dG + yb[e] * dB;
-                if (L == 7) dk[0] = dsig;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    acc[c].x += w[c] * dk[0];
-                    acc[c].y += w[c] * dk[1];
-                    acc[c].z += w[c] * dk[2];
-                    acc[c].w += w[c] * dk[3];
-                }
+                for (int c = 0; c < 8; ++c) acc[c] += w[c] * dk;
             }
         }
-        if (dirty) flush(a.grad, a.touched, cc, acc, L);
+        if (cc.cell[0] >= 0) flush(a.grad, a.touched, cc, acc, L, 0xffu);
     }
 
     if (MODE == MODE_TRAIN) {
@@ -312,6 +480,106 @@ __global__ __launch_bounds__(kThreads) void render_kernel(GridDev g, RenderArgs 
         for (int m = 32; m >= 1; m >>= 1) loss += __shfl_xor(loss, m);
         if ((threadIdx.x & 63) == 0 && loss != 0.0) unsafeAtomicAdd(a.loss_sum, loss);
     }
+}
+
+// ------------------------------------------------------------------ novel views
+
+// Pixel-centred pinhole ray of pixel (px, py) of a view, in FP64 with a fixed
+// operation order (no contraction), rounded to FP32 once.
+__device__ inline void camera_ray(const plx_view &v, int px, int py, float o[3], float d[3]) {
+#pragma clang fp contract(off)
+    const double x = ((double)px + 0.5 - 0.5 * (double)v.width) / v.focal;
+    const double yv = -(((double)py + 0.5 - 0.5 * (double)v.height) / v.focal);
+    const double z = -1.0;
+    double dv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dv[a] = v.c2w[4 * a + 0] * x + v.c2w[4 * a + 1] * yv + v.c2w[4 * a + 2] * z;
+    const double nrm = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d[a] = (float)(dv[a] / nrm);
+        o[a] = (float)v.c2w[4 * a + 3];
+    }
+}
+
+constexpr int kTileW = 4, kTileH = 2;  // pixels per tile = rays per block
+
+struct ViewsArgs {
+    const GridDev *scenes;
+    const plx_view *views;
+    const int64_t *tile_start;  // [n_views + 1]
+    unsigned long long *counter;
+    int n_views;
+    int64_t n_tiles;
+    float bg[3];
+    float *rgb_out;
+};
+
+// Persistent tile queue over all pixels of all views of the launch: each block
+// takes the next 4x2-pixel tile, finds its view, generates the rays of its
+// pixels and runs the same forward march as plx_render_fwd.  A pixel's colour
+// depends only on its own ray and scene, never on the rest of the batch.
+template <int DT>
+__global__ __launch_bounds__(kThreads) void views_kernel(ViewsArgs a) {
+    __shared__ long long tile_sh;
+    const int L = threadIdx.x & (kLPR - 1);
+    const int gid = threadIdx.x / kLPR;
+    const int ch = L < PLX_NSH ? L / 9 : 3;
+    while (true) {
+        if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(a.counter, 1ull);
+        __syncthreads();
+        const int64_t tile = tile_sh;
+        __syncthreads();
+        if (tile >= a.n_tiles) break;
+        int lo = 0, hi = a.n_views - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.tile_start[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const plx_view &v = a.views[lo];
+        const int64_t tl = tile - a.tile_start[lo];
+        const int tpr = (v.width + kTileW - 1) / kTileW;
+        const int px = (int)(tl % tpr) * kTileW + (gid % kTileW);
+        const int py = (int)(tl / tpr) * kTileH + (gid / kTileW);
+        const bool live = px < v.width && py < v.height;
+        const GridDev g = a.scenes[v.scene];
+        float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+        if (live) camera_ray(v, px, py, o, d);
+        RayGeom r;
+        const int n = live ? ray_setup(g, o, d, r) : 0;
+        const float y = L < PLX_NSH ? sh_basis_at(L % 9, d[0], d[1], d[2]) : 0.0f;
+        CornerCache cc;
+        cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+        cc.myc = -1;
+        float acc[8];
+        float C[3];
+        double tau;
+        int n_list = 0;
+        bool overflow = false;
+        march_forward<DT, false>(g, r, n, L, y, ch, cc, acc, C, tau, nullptr, n_list, overflow);
+        if (live && L == 0) {
+            const float T_final = expf(-(float)tau);
+            float *out = a.rgb_out + 3 * (v.out_offset + (int64_t)py * v.width + px);
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) out[c3] = C[c3] + T_final * a.bg[c3];
+        }
+    }
+}
+
+struct ViewsLayout {
+    int64_t counter, tile_start, scenes, views, bytes;
+};
+
+ViewsLayout views_layout(int32_t n_scenes, int32_t n_views) {
+    auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
+    ViewsLayout l;
+    l.counter = 0;
+    l.tile_start = 256;
+    l.scenes = l.tile_start + up((int64_t)(n_views + 1) * (int64_t)sizeof(int64_t));
+    l.views = l.scenes + up((int64_t)n_scenes * (int64_t)sizeof(GridDev));
+    l.bytes = l.views + up((int64_t)n_views * (int64_t)sizeof(plx_view));
+    return l;
 }
 
 // Work counters (one thread per ray; diagnostic, not a hot path).
@@ -329,7 +597,6 @@ __global__ void stats_kernel(GridDev g, const float *rays_o, const float *rays_d
         const int n = ray_setup(g, o, d, r);
         n_all = n;
         int64_t last = -1;
-        const int64_t sy = g.nz, sx = (int64_t)g.ny * g.nz;
         for (int k = 0; k < n; ++k) {
             const Sample s = sample_at(g, r, k);
             const int64_t lin = cell_id(g, s.cell);
@@ -338,7 +605,7 @@ __global__ void stats_kernel(GridDev g, const float *rays_o, const float *rays_d
             if (lin == last) continue;
             last = lin;
             for (int c = 0; c < 8; ++c) {
-                const int64_t v = lin + ((c >> 2) & 1) * sx + ((c >> 1) & 1) * sy + (c & 1);
+                const int64_t v = lin + corner_offset(g, c);
                 atomicOr(cell_mark + (v >> 5), 1u << (v & 31));
                 const int id = g.index[v];
                 if (id >= 0) atomicOr(vox_mark + (id >> 5), 1u << (id & 31));
@@ -357,7 +624,7 @@ __global__ void stats_kernel(GridDev g, const float *rays_o, const float *rays_d
 
 int validate_rays(const float *o, const float *d, int64_t n, const char *fn) {
     if (n < 0) return fail(PLX_EINVAL, "%s: n_rays < 0", fn);
-    if (n > ((int64_t)1 << 36)) return fail(PLX_EINVAL, "%s: n_rays too large", fn);
+    if (n > ((int64_t)1 << 34)) return fail(PLX_EINVAL, "%s: n_rays too large", fn);
     if (n > 0 && (!o || !d)) return fail(PLX_EINVAL, "%s: rays are NULL", fn);
     return PLX_OK;
 }
@@ -442,6 +709,67 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     a.loss_sum = loss_sum;
     a.loss_scale = loss_scale;
     return launch_render<MODE_TRAIN>(grid, a, as_stream(stream), fn);
+}
+
+int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views) {
+    if (n_scenes < 1 || n_views < 0) return 0;
+    return views_layout(n_scenes, n_views).bytes;
+}
+
+int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *views,
+                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
+                     int64_t workspace_bytes, plx_stream stream) {
+    const char *fn = "plx_render_views";
+    if (!scenes || n_scenes < 1) return fail(PLX_EINVAL, "%s: need at least one scene", fn);
+    if (n_views < 0) return fail(PLX_EINVAL, "%s: n_views < 0", fn);
+    if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
+    if (n_views == 0) return PLX_OK;
+    if (!views || !rgb_out || !workspace) return fail(PLX_EINVAL, "%s: NULL views/rgb_out/workspace", fn);
+    const ViewsLayout lay = views_layout(n_scenes, n_views);
+    if (workspace_bytes < lay.bytes)
+        return fail(PLX_EINVAL, "%s: workspace of %lld bytes, need %lld", fn, (long long)workspace_bytes,
+                    (long long)lay.bytes);
+    const int32_t dt = scenes[0].sh_dtype;
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        int rc = validate_grid(&scenes[s], true, fn);
+        if (rc) return rc;
+        if (scenes[s].sh_dtype != dt) return fail(PLX_EINVAL, "%s: scenes must share one sh_dtype", fn);
+    }
+    // host image of the workspace: counter, tile offsets, scene and view tables
+    std::vector<unsigned char> img((size_t)lay.bytes, 0);
+    int64_t *tile_start = reinterpret_cast<int64_t *>(img.data() + lay.tile_start);
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n_views; ++i) {
+        const plx_view &v = views[i];
+        if (v.scene < 0 || v.scene >= n_scenes) return fail(PLX_EINVAL, "%s: view %d: bad scene", fn, i);
+        if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
+            return fail(PLX_EINVAL, "%s: view %d: bad size %dx%d", fn, i, v.width, v.height);
+        if (!(v.focal > 0.0) || v.out_offset < 0)
+            return fail(PLX_EINVAL, "%s: view %d: bad focal or out_offset", fn, i);
+        tile_start[i] = tiles;
+        tiles += (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + kTileH - 1) / kTileH);
+    }
+    tile_start[n_views] = tiles;
+    GridDev *sc = reinterpret_cast<GridDev *>(img.data() + lay.scenes);
+    for (int32_t s = 0; s < n_scenes; ++s) sc[s] = to_dev(&scenes[s]);
+    memcpy(img.data() + lay.views, views, sizeof(plx_view) * (size_t)n_views);
+    hipStream_t s = as_stream(stream);
+    PLX_CHECK_HIP(hipMemcpyAsync(workspace, img.data(), (size_t)lay.bytes, hipMemcpyHostToDevice, s), fn);
+    // the host image is released on return: wait for the copy
+    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
+    char *ws = static_cast<char *>(workspace);
+    ViewsArgs va;
+    va.counter = reinterpret_cast<unsigned long long *>(ws + lay.counter);
+    va.tile_start = reinterpret_cast<const int64_t *>(ws + lay.tile_start);
+    va.scenes = reinterpret_cast<const GridDev *>(ws + lay.scenes);
+    va.views = reinterpret_cast<const plx_view *>(ws + lay.views);
+    va.n_views = n_views;
+    va.n_tiles = tiles;
+    va.rgb_out = rgb_out;
+    for (int i = 0; i < 3; ++i) va.bg[i] = opts->background[i];
+    const int64_t nblk = tiles < 4096 ? tiles : 4096;  // persistent: about 16 blocks per CU
+    PLX_DISPATCH_DT(dt, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
+    return check_launch(fn);
 }
 
 int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,

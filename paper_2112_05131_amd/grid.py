@@ -22,7 +22,8 @@ class Grid:
     index  int32  [Nx*Ny*Nz]   -1 = NULL, else table id (storage order)
     data   records [M, 32]     float32 (PLX_F32) or int16 (16-bit SH)
     master float32 [M, 32]     FP32 records behind 16-bit data (else None)
-    occ    int32  [words]      cell occupancy bitmap (rebuilt on change)
+    occ    int32  [bytes/4]    occupancy structure: cell bitmap + brick
+                               distances (rebuilt on change)
     """
 
     def __init__(self, reso, index, data, sh_dtype=B.PLX_F32, master=None,
@@ -34,7 +35,7 @@ class Grid:
         self.data = data
         self.sh_dtype = int(sh_dtype)
         self.master = master
-        self.occ = torch.zeros(B.plx_occ_words(self.reso), dtype=torch.int32, device=index.device)
+        self.occ = torch.zeros(B.plx_occ_bytes(self.reso) // 4, dtype=torch.int32, device=index.device)
         if build_occ:
             self.rebuild_occupancy()
 

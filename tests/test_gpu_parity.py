@@ -460,3 +460,72 @@ def test_full_size_backward_subset(c3_scene):
     md, ms = grad_mass(og, so.cpu().numpy(), sd.cpu().numpy(), G.double().cpu().numpy())
     assert_grads_close(sub, gd[tb], gs[tb], "c3 bwd", (md[tb], ms[tb]))
     assert torch.all(grad[~on] == 0)
+
+
+# ------------------------------------------------------------------ empty-space skipping
+
+def _islands(reso, seed, n_islands=5, radius=3):
+    """A few small cubes of occupied voxels in an otherwise empty grid."""
+    rng = np.random.default_rng(seed)
+    mask = np.zeros(reso, np.uint8)
+    for _ in range(n_islands):
+        c = [int(rng.integers(radius, r - radius)) for r in reso]
+        mask[c[0] - radius:c[0] + radius, c[1] - radius:c[1] + radius, c[2] - radius:c[2] + radius] = 1
+    m = int(mask.sum())
+    g = torch.Generator().manual_seed(seed)
+    dens = (0.5 + 40 * torch.rand(m, generator=g, dtype=torch.float64)).float()
+    sh = ((torch.rand(m, 27, generator=g, dtype=torch.float64) * 2 - 1) * 0.1).float()
+    sh[:, 0] += 2.0
+    sh[:, 9] += 2.0
+    sh[:, 18] += 2.0
+    return synth.SceneValues(tuple(reso), torch.from_numpy(mask.reshape(-1)), dens, sh, m)
+
+
+def test_brick_distances_match_chessboard_transform():
+    import scipy.ndimage as ndi
+    say("brick distances")
+    for reso, seed in (((128, 128, 128), 91), ((61, 45, 77), 92)):
+        sv = _islands(reso, seed)
+        og, gg = make_pair(sv)
+        nx, ny, nz = reso
+        idx = og.index.reshape(reso) >= 0
+        cell = idx[:-1, :-1, :-1] | idx[1:, :-1, :-1] | idx[:-1, 1:, :-1] | idx[:-1, :-1, 1:] | \
+            idx[1:, 1:, :-1] | idx[1:, :-1, 1:] | idx[:-1, 1:, 1:] | idx[1:, 1:, 1:]
+        nb = [-(-(r - 1) // 8) for r in reso]
+        pad = np.zeros([b * 8 for b in nb], bool)
+        pad[:nx - 1, :ny - 1, :nz - 1] = cell
+        bocc = pad.reshape(nb[0], 8, nb[1], 8, nb[2], 8).any(axis=(1, 3, 5))
+        ref = np.minimum(ndi.distance_transform_cdt(~bocc, metric="chessboard"), 16)
+        raw = gg.occ.cpu().numpy().view(np.uint8)
+        off = B.plx_occ_brick_offset(reso)
+        got = raw[off:off + bocc.size].reshape(bocc.shape)
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("seed", [93, 94])
+def test_skipping_islands_forward_backward(seed):
+    say("islands", seed)
+    sv = _islands((128, 128, 128), seed, n_islands=6, radius=2)
+    og, gg = make_pair(sv)
+    o, d = synth.random_rays(3000, seed=seed + 1, target_half=0.4)
+    rgb, tau = gpu_render(gg, o, d)
+    rgb_ref, tau_ref, _, _ = O.render_fwd(og, o.numpy(), d.numpy())
+    assert np.abs(rgb - rgb_ref).max() <= RGB_ATOL
+    G = torch.from_numpy(np.random.default_rng(seed + 2).normal(size=(3000, 3))).float()
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    B.plx_render_bwd(gg.desc(), o.cuda(), d.cuda(), G.cuda(), torch.from_numpy(tau).float().cuda(),
+                     grad, touched)
+    torch.cuda.synchronize()
+    gd, gs, t_ref = O.render_bwd(og, o.numpy(), d.numpy(), G.double().numpy())
+    assert t_ref.sum() > 0
+    assert_touched_equal(touched, t_ref, "islands bwd")
+    assert_grads_close(grad, gd, gs, "islands bwd", grad_mass(og, o.numpy(), d.numpy(), G.double().numpy()))
+    # fused training on the same rays: same touched set
+    t2 = torch.zeros_like(touched)
+    g2 = torch.zeros_like(grad)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    B.plx_render_train(gg.desc(), o.cuda(), d.cuda(), torch.zeros(3000, 3, device="cuda"), 1.0 / 3000,
+                       g2, t2, loss)
+    torch.cuda.synchronize()
+    assert_touched_equal(t2, t_ref, "islands train")

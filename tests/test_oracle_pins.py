@@ -589,3 +589,41 @@ def test_gradient_mass_bounds_gradient_and_is_tight_without_cancellation():
     _, ms2 = O.render_bwd_mass(g, oo, dd, Gp)
     assert np.abs(ms2).max() > 0
     np.testing.assert_allclose(ms2, gs2, rtol=1e-12, atol=1e-300)
+
+
+def test_camera_rays_match_pinhole_geometry():
+    # against the independent generator (torch matmul, FP64) and geometry:
+    # unit directions, the centre pixel looks at the camera's -z axis, the
+    # corner pixels span the stated field of view
+    poses = synth.sphere_poses(3, seed=44)
+    for p in poses:
+        W, H, fov = 37, 23, 45.0
+        f = 0.5 * W / math.tan(0.5 * math.radians(fov))
+        c2w = p.numpy().reshape(12)
+        o, d = O.camera_rays(c2w, f, W, H)
+        so, sd = synth.camera_rays(p, W, H, fov)
+        np.testing.assert_array_equal(o, so.numpy())
+        np.testing.assert_allclose(d, sd.numpy(), atol=1.2e-7, rtol=0)
+        np.testing.assert_allclose(np.linalg.norm(d.astype(np.float64), axis=1), 1.0, atol=2e-7)
+        fwd = -p.numpy()[:, 2]
+        ang = np.degrees(np.arccos(np.clip(d.astype(np.float64) @ fwd, -1, 1)))
+        half_diag = np.degrees(np.arctan(math.hypot(W - 1, H - 1) / 2 / f))
+        assert abs(ang.max() - half_diag) < 1e-3
+
+
+def test_gradient_mass_gate_band_adds_only_near_kink_terms():
+    # with negative colours present, widening the gate band can only add
+    # mass, and a zero band gives the plain mass
+    sv = synth.dense_random((6, 6, 6), seed=40, ho_scale=0.6)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(40, seed=41)
+    o, d = o.numpy(), d.numpy()
+    G = np.abs(np.random.default_rng(42).normal(size=(40, 3)))
+    p_d, p_s = O.render_bwd_mass(g, o, d, G)
+    a_d, a_s = O.render_bwd_mass(g, o, d, G, gate_rel=0.5)
+    z_d, z_s = O.render_bwd_mass(g, o, d, G, gate_rel=0.0)
+    # (OpenMP accumulation order may differ between calls)
+    np.testing.assert_allclose(p_s, z_s, rtol=1e-12)
+    np.testing.assert_allclose(p_d, z_d, rtol=1e-12)
+    assert np.all(a_s >= p_s * (1 - 1e-12)) and np.all(a_d >= p_d * (1 - 1e-12))
+    assert (a_s > p_s * (1 + 1e-9)).any()
