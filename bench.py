@@ -152,7 +152,8 @@ def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
                   1.0, 0.01)
         return time.perf_counter() - t0
 
-    probe = 2000
+    run(500)  # first touch of the grid arrays
+    probe = 4000
     tp = run(probe)
     s = int(min(BATCH, max(probe, probe * budget_s / max(tp, 1e-6))))
     ts_ = run(s)
@@ -162,6 +163,48 @@ def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
                       f"segment, RMSProp on the sample's active voxels; {ts_:.1f} s FP64"}
 
 
+def serving_leg(n_sat=160, n_load=240):
+    """8 resident scenes (4 at 256^3, 4 at 512^3, 5-10% occupancy, FP16 SH),
+    requests at 200x200 .. 1920x1080 with random poses on the view sphere:
+    saturation throughput (all requests at once), then Poisson arrivals at 50,
+    80 and 95% of it.  Returns the serving summary."""
+    from paper_2112_05131_amd.serve import Server, random_requests, run_load
+    t0 = time.time()
+    scenes = []
+    for i, seed in enumerate(range(3, 11)):
+        reso = (256,) * 3 if i < 4 else (512,) * 3
+        occ = 0.05 + 0.05 * (i % 4) / 3.0
+        sv = synth.blob_scene(reso, N_BLOBS, occ, seed, device="cuda")
+        scenes.append(Grid.from_mask(sv.mask, reso, sv.density, sv.sh, sh_dtype=B.PLX_F16))
+        del sv
+    torch.cuda.synchronize()
+    resident = sum(s.index.numel() * 4 + s.data.numel() * s.data.element_size() +
+                   s.occ.numel() * 4 for s in scenes)
+    log(f"serving scenes built in {time.time() - t0:.1f}s, resident {resident / 1e9:.2f} GB")
+    srv = Server(scenes, hbm_budget=1 << 30, n_streams=4, max_batch=32, keep_outputs=False)
+    run_load(srv, random_requests(16, 8, seed=99), None)  # warm-up
+    reqs = random_requests(n_sat, 8, seed=100)
+    lat, wall = run_load(srv, reqs, None)
+    pix = sum(r.n_pixels for r in reqs)
+    sat_rps = n_sat / wall
+    out = {"scenes": "4x256^3 + 4x512^3, 5-10% occupancy, FP16 SH",
+           "resident_gb": round(resident / 1e9, 3),
+           "saturation_mrays_s": round(pix / wall / 1e6, 2),
+           "saturation_requests_s": round(sat_rps, 1), "loads": []}
+    for frac in (0.5, 0.8, 0.95):
+        reqs = random_requests(n_load, 8, seed=101 + int(frac * 100))
+        lat, wall = run_load(srv, reqs, sat_rps * frac, seed=7)
+        pix = sum(r.n_pixels for r in reqs)
+        out["loads"].append({"load": frac, "offered_requests_s": round(sat_rps * frac, 1),
+                             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                             "mrays_s": round(pix / wall / 1e6, 2), "requests": n_load})
+        log(f"serving load {frac}: p50 {out['loads'][-1]['p50_ms']} ms p99 {out['loads'][-1]['p99_ms']} ms")
+    del srv, scenes
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +212,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the BF16/FP16-SH steps")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -234,6 +279,26 @@ def main():
         "work": {"samples": counts[0], "occupied_samples": counts[1], "index_entries": counts[2],
                  "voxels_read": counts[3], "active_voxels": n_act, "tv_cells": tv_cells},
     }
+    if not args.no_compare:
+        # the same step with SH stored in FP32, BF16 and FP16 (FP32 optimiser
+        # state and accumulation in all three)
+        prec = {args.dtype: {"ms_per_step": round(ms, 4), "mrays_s": round(mrays, 3),
+                             "render_train_ms": round(float(k_ms[0]), 4)}}
+        for name in ("f32", "bf16", "f16"):
+            if name in prec:
+                continue
+            g2 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=B.DTYPES[name])
+            tr2 = Trainer(g2, TrainConfig(), seed=SEED)
+            ms2, _, k2 = time_steps(tr2, batches, 2, max(5, args.steps // 2))
+            prec[name] = {"ms_per_step": round(ms2, 4), "mrays_s": round(BATCH / ms2 / 1e3, 3),
+                          "render_train_ms": round(float(k2[0]), 4)}
+            log(f"{name}: step {ms2:.3f} ms, render_train {k2[0]:.3f} ms")
+            del g2, tr2
+        for name in prec:
+            prec[name]["speedup_vs_f32"] = round(prec["f32"]["ms_per_step"] / prec[name]["ms_per_step"], 4)
+        out["precision"] = prec
+    if not args.no_serving:
+        out["serving"] = serving_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(gt, vals, batches[0])
     print(json.dumps(out), flush=True)

@@ -234,6 +234,41 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
                      float loss_scale, float *rgb_out, float *grad, uint32_t *touched,
                      double *loss_sum, plx_stream stream);
 
+/* One novel-view request (serving).  Rays are pixel-centred pinhole rays:
+ * pixel (px, py) of a width x height image gets, in FP64 with sums left to
+ * right and then rounded to FP32, d_cam = ((px + 0.5 - width/2)/focal,
+ * -((py + 0.5 - height/2)/focal), -1), d = R d_cam / |R d_cam| and o = the
+ * camera centre, where c2w = [R | centre] is row-major 3x4 (columns: the
+ * camera x, y, z axes and its centre; the camera looks along -z, image y
+ * points up). */
+typedef struct plx_view {
+    double c2w[12];
+    double focal;       /* pixels; principal point at the image centre */
+    int32_t width;
+    int32_t height;
+    int32_t scene;      /* index into the scene table */
+    int32_t reserved;   /* set to 0 */
+    int64_t out_offset; /* index (in pixels) of this view's first pixel in rgb_out */
+} plx_view;
+
+/* Bytes of device workspace plx_render_views needs for these table sizes. */
+int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views);
+
+/* Renders a batch of novel views of resident scenes in one launch (the
+ * forward model of plx_render_fwd, Sec. 3.1-3.3, with rays generated on the
+ * device; interactive rendering is claimed in Sec. 1).  The views may mix
+ * scenes and resolutions.  All pixels of all views form one queue of 4x2-pixel
+ * tiles drained by a persistent grid, so the colour of a pixel depends only on
+ * its ray and scene, never on the rest of the batch.  scenes (host array of
+ * n_scenes descriptors, one sh_dtype, occupancy built) and views (host array)
+ * are copied into `workspace` (device, plx_render_views_workspace bytes); the
+ * call waits for that copy on `stream` (work queued before it on `stream`
+ * completes first) and then enqueues the render.  rgb_out: device float32,
+ * 3 floats per pixel at 3*(out_offset + py*width + px). */
+int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *views,
+                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
+                     int64_t workspace_bytes, plx_stream stream);
+
 /* Work counters of a ray batch, for bandwidth accounting (not timed work):
  * counts[0] = samples (all), counts[1] = samples in occupied cells,
  * counts[2] = distinct index entries read (corners of occupied cells),

@@ -52,6 +52,18 @@ class PlxRenderOpts(ctypes.Structure):
     _fields_ = [("background", ctypes.c_float * 3)]
 
 
+class PlxView(ctypes.Structure):
+    _fields_ = [
+        ("c2w", ctypes.c_double * 12),
+        ("focal", ctypes.c_double),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("scene", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("out_offset", ctypes.c_int64),
+    ]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -83,6 +95,8 @@ _SIGS = {
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_views_workspace": ([_I32, _I32], _I64),
+    "plx_render_views": ([_GP, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
     "plx_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_touched_count": ([_P, _I64, _P, _P], ctypes.c_int),
     "plx_rmsprop_step": ([_GP, _P, _P, _P, _P, _F, _F, _F, _F, _P], ctypes.c_int),
@@ -281,6 +295,25 @@ def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touch
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
                                   _dptr(touched, "touched", torch.int32),
                                   _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_render_views_workspace(n_scenes: int, n_views: int) -> int:
+    return int(lib().plx_render_views_workspace(int(n_scenes), int(n_views)))
+
+
+def plx_render_views(scenes, views, rgb_out, workspace, bg=(1.0, 1.0, 1.0), stream=None):
+    """scenes: list of PlxGrid; views: list of PlxView; rgb_out: device
+    float32 tensor; workspace: device uint8 tensor of at least
+    plx_render_views_workspace bytes.  stream: a torch.cuda.Stream (default:
+    the current stream)."""
+    sc = (PlxGrid * len(scenes))(*scenes)
+    vw = (PlxView * max(len(views), 1))(*views)
+    o = _opts(bg)
+    s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    _check(lib().plx_render_views(ctypes.cast(sc, _GP), len(scenes), ctypes.cast(vw, _P), len(views),
+                                  ctypes.byref(o), _dptr(rgb_out, "rgb_out", torch.float32),
+                                  _dptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                                  s))
 
 
 def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark):

@@ -185,24 +185,29 @@ __device__ inline bool cell_occupied(const GridDev &g, int64_t lin) {
 
 // ----------------------------------------------------------- SH basis
 // Real orthonormal degree-2 SH (Condon-Shortley phase) at direction d, order
-// (0,0),(1,-1),(1,0),(1,1),(2,-2),(2,-1),(2,0),(2,1),(2,2).
-__device__ inline float sh_basis_at(int l, float x, float y, float z) {
-    const float k0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
-    const float k1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
-    const float k2 = 1.09254843059207907f;   // sqrt(15 / (4 pi))
-    const float k20 = 0.31539156525252005f;  // sqrt(5 / (16 pi))
-    const float k22 = 0.54627421529603959f;  // sqrt(15 / (16 pi))
+// (0,0),(1,-1),(1,0),(1,1),(2,-2),(2,-1),(2,0),(2,1),(2,2).  Evaluated once
+// per ray in FP64 and rounded once: 3z^2 - 1 and x^2 - y^2 cancel near their
+// zeros, where an FP32 evaluation would lose most of its digits.
+__device__ inline float sh_basis_at(int l, float xf, float yf, float zf) {
+    const double x = xf, y = yf, z = zf;
+    const double k0 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
+    const double k1 = 0.48860251190291992;   // sqrt(3 / (4 pi))
+    const double k2 = 1.09254843059207907;   // sqrt(15 / (4 pi))
+    const double k20 = 0.31539156525252005;  // sqrt(5 / (16 pi))
+    const double k22 = 0.54627421529603959;  // sqrt(15 / (16 pi))
+    double v;
     switch (l) {
-    case 0: return k0;
-    case 1: return -k1 * y;
-    case 2: return k1 * z;
-    case 3: return -k1 * x;
-    case 4: return k2 * x * y;
-    case 5: return -k2 * y * z;
-    case 6: return k20 * (3.0f * z * z - 1.0f);
-    case 7: return -k2 * x * z;
-    default: return k22 * (x * x - y * y);
+    case 0: v = k0; break;
+    case 1: v = -k1 * y; break;
+    case 2: v = k1 * z; break;
+    case 3: v = -k1 * x; break;
+    case 4: v = k2 * x * y; break;
+    case 5: v = -k2 * y * z; break;
+    case 6: v = k20 * (3.0 * z * z - 1.0); break;
+    case 7: v = -k2 * x * z; break;
+    default: v = k22 * (x * x - y * y); break;
     }
+    return (float)v;
 }
 
 // ----------------------------------------------------------- records

@@ -37,6 +37,10 @@
 // atomics when it stops being one.  The fused training kernel keeps the list
 // of non-empty 32-sample chunks found by its forward pass in LDS and replays
 // exactly those in reverse.
+#include <string.h>
+
+#include <vector>
+
 #include "plx_internal.hpp"
 
 namespace plx {
