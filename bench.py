@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(sh_dtype, n_batches):
+def build_workload(sh_dtype, n_batches, coherent=True):
     t0 = time.time()
     gt = synth.blob_scene(RESO, N_BLOBS, OCC, SEED, device="cuda")
     gt_grid = Grid.from_mask(gt.mask, RESO, gt.density, gt.sh)
@@ -57,7 +57,8 @@ def build_workload(sh_dtype, n_batches):
     poses = synth.sphere_poses(N_CAMS, seed=SEED)
     batches = []
     for b in range(n_batches):
-        o, d, _ = synth.sampled_camera_rays(poses, W, H, BATCH, seed=SEED + 10 * b, device="cuda")
+        o, d, _ = synth.sampled_camera_rays(poses, W, H, BATCH, seed=SEED + 10 * b, device="cuda",
+                                            coherent=coherent)
         tgt = torch.empty(BATCH, 3, device="cuda")
         B.plx_render_fwd(gt_grid.desc(), o, d, tgt)
         batches.append((o, d, tgt))
@@ -153,10 +154,11 @@ def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
         return time.perf_counter() - t0
 
     run(500)  # first touch of the grid arrays
-    probe = 4000
-    tp = run(probe)
-    s = int(min(BATCH, max(probe, probe * budget_s / max(tp, 1e-6))))
+    s = 4000
     ts_ = run(s)
+    while ts_ < 0.5 * budget_s and s < BATCH:
+        s = int(min(BATCH, s * min(8.0, budget_s / max(ts_, 1e-6))))
+        ts_ = run(s)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(s / ts_ / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{s} rays of one 1M-ray batch (fwd+MSE+bwd), TV on {s}/{BATCH} of the 1% "
@@ -214,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the BF16/FP16-SH steps")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--ray-order", default="coherent", choices=["coherent", "random"],
+                    help="order of the rays inside each batch (the same rays either way)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -222,7 +226,7 @@ def main():
     torch.cuda.set_device(0)
     sh_dtype = B.DTYPES[args.dtype]
     n_batches = min(args.warmup + args.steps, 8)
-    gt, grid, batches, vals = build_workload(sh_dtype, n_batches)
+    gt, grid, batches, vals = build_workload(sh_dtype, n_batches, args.ray_order == "coherent")
     trainer = Trainer(grid, TrainConfig(), seed=SEED)
 
     counts = work_counters(grid, batches[0])
@@ -261,6 +265,7 @@ def main():
                         "render+MSE+backward, TV on a 1% contiguous segment, sparse RMSProp",
             "sh_storage": args.dtype,
             "batch_rays": BATCH,
+            "ray_order": args.ray_order,
             "grid": list(RESO),
             "n_vox": grid.n_vox,
         },
@@ -297,6 +302,21 @@ def main():
         for name in prec:
             prec[name]["speedup_vs_f32"] = round(prec["f32"]["ms_per_step"] / prec[name]["ms_per_step"], 4)
         out["precision"] = prec
+        if args.ray_order == "coherent":
+            # the same rays, shuffled inside each batch
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(SEED + 77)
+            shuffled = []
+            for o, d, t in batches:
+                p = torch.randperm(BATCH, device="cuda", generator=gen)
+                shuffled.append((o[p].contiguous(), d[p].contiguous(), t[p].contiguous()))
+            g3 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=sh_dtype)
+            tr3 = Trainer(g3, TrainConfig(), seed=SEED)
+            ms3, _, k3 = time_steps(tr3, shuffled, 2, max(5, args.steps // 2))
+            out["random_order"] = {"ms_per_step": round(ms3, 4), "mrays_s": round(BATCH / ms3 / 1e3, 3),
+                                   "render_train_ms": round(float(k3[0]), 4)}
+            log(f"random ray order: step {ms3:.3f} ms, render_train {k3[0]:.3f} ms")
+            del g3, tr3, shuffled
     if not args.no_serving:
         out["serving"] = serving_leg()
     if not args.no_cpu_baseline:

@@ -216,12 +216,13 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
  * Each ray is replayed from its last sample to its first; transmittance is
  * recomputed from the forward optical depth tau_fwd[n_rays] (no per-sample
  * state).  Gradients of sigma and the SH coefficients are ADDED (FP32
- * atomics) into grad (device [M] FP32 records); touched (device uint32
- * bitmap of M bits) gets the bit of every non-NULL corner voxel of every
- * sample. */
+ * atomics) into grad (device [M] FP32 records); touched (device uint8[M],
+ * one byte per voxel) is set to 1 for every non-NULL corner voxel of every
+ * sample in an occupied cell (plain byte stores: set bytes are never
+ * cleared here). */
 int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
                    const float *rays_d, int64_t n_rays, const float *grad_rgb,
-                   const float *tau_fwd, float *grad, uint32_t *touched, plx_stream stream);
+                   const float *tau_fwd, float *grad, uint8_t *touched, plx_stream stream);
 
 /* One fused training pass over a ray batch: forward, the MSE reconstruction
  * loss of Sec. 3.5 with its gradient dL/dC = 2 loss_scale (C - target), and
@@ -231,7 +232,7 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
  * be NULL. */
 int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
                      const float *rays_d, const float *target, int64_t n_rays,
-                     float loss_scale, float *rgb_out, float *grad, uint32_t *touched,
+                     float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
                      double *loss_sum, plx_stream stream);
 
 /* One novel-view request (serving).  Rays are pixel-centred pinhole rays:
@@ -288,29 +289,29 @@ int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *ray
  * NULL or out-of-range neighbour reads 0, for SH a NULL current cell has no
  * terms and a NULL or out-of-range neighbour counts as equal to the current
  * cell.  Adds lambda_sigma/count * d(sum term_sigma) + lambda_sh/count *
- * d(sum term_sh) into grad (device [M] FP32 records), sets touched bits of
- * every non-NULL voxel among v and its three forward neighbours, and ADDS the
+ * d(sum term_sh) into grad (device [M] FP32 records), sets the touched byte
+ * of every non-NULL voxel among v and its three forward neighbours, and ADDS the
  * loss to loss_sum (device double; may be NULL). */
 int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
                 float lambda_sigma, float lambda_sh, float eps, float *grad,
-                uint32_t *touched, double *loss_sum, plx_stream stream);
+                uint8_t *touched, double *loss_sum, plx_stream stream);
 
 /* ---------------------------------------------------------------- optimiser */
 
-/* Number of set bits among the first n_vox bits of touched (the active set
- * of a step).  Synchronising; temporary device memory. */
-int plx_touched_count(const uint32_t *touched, int64_t n_vox, int64_t *count_out,
+/* Number of nonzero bytes among touched[0..n_vox) (the active set of a
+ * step).  Synchronising; temporary device memory. */
+int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
                       plx_stream stream);
 
-/* RMSProp (Sec. 3.5) on the active voxels (touched bits): for each of the 28
- * values, v <- beta v + (1-beta) g^2 and p <- p - lr g / (sqrt(v) + eps),
- * lr = lr_sigma for sigma and lr_sh for SH; then g <- 0 and the touched
- * bits are cleared.  Inactive voxels are not read or written.  vstate and
+/* RMSProp (Sec. 3.5) on the active voxels (nonzero touched bytes): for each
+ * of the 28 values, v <- beta v + (1-beta) g^2 and p <- p - lr g / (sqrt(v) +
+ * eps), lr = lr_sigma for sigma and lr_sh for SH; then g <- 0 and the touched
+ * bytes are cleared.  Inactive voxels are not read or written.  vstate and
  * grad are FP32 records.  For 16-bit grids `master` holds the FP32 records
  * that are updated and grid->data receives their rounding; for PLX_F32 grids
  * master must be NULL and grid->data is updated in place. */
 int plx_rmsprop_step(const plx_grid *grid, float *master, float *vstate, float *grad,
-                     uint32_t *touched, float lr_sigma, float lr_sh, float beta, float eps,
+                     uint8_t *touched, float lr_sigma, float lr_sh, float beta, float eps,
                      plx_stream stream);
 
 #ifdef __cplusplus

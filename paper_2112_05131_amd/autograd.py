@@ -32,7 +32,7 @@ class RenderFn(torch.autograd.Function):
         rays_o, rays_d, tau = ctx.saved_tensors
         g = ctx.grid
         grad = torch.zeros(g.n_vox, B.REC_SLOTS, dtype=torch.float32, device=rays_o.device)
-        touched = torch.zeros((g.n_vox + 31) // 32, dtype=torch.int32, device=rays_o.device)
+        touched = torch.zeros(g.n_vox, dtype=torch.uint8, device=rays_o.device)
         B.plx_render_bwd(g.desc(), rays_o, rays_d, grad_rgb.contiguous().float(), tau, grad,
                          touched, ctx.bg)
         return grad, None, None, None, None

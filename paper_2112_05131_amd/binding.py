@@ -280,7 +280,7 @@ def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
                                 _dptr(grad_rgb, "grad_rgb", torch.float32, 3 * n),
                                 _dptr(tau_fwd, "tau_fwd", torch.float32, n),
                                 _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
-                                _dptr(touched, "touched", torch.int32), _stream()))
+                                _dptr(touched, "touched", torch.uint8), _stream()))
 
 
 def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
@@ -293,7 +293,7 @@ def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touch
                                   _dptr(target, "target", torch.float32, 3 * n), n,
                                   float(loss_scale), _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
-                                  _dptr(touched, "touched", torch.int32),
+                                  _dptr(touched, "touched", torch.uint8),
                                   _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
 
 
@@ -334,13 +334,13 @@ def plx_tv_grad(g: PlxGrid, cell_start, cell_count, lambda_sigma, lambda_sh, eps
     _check(lib().plx_tv_grad(ctypes.byref(g), int(cell_start), int(cell_count), float(lambda_sigma),
                              float(lambda_sh), float(eps),
                              _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
-                             _dptr(touched, "touched", torch.int32),
+                             _dptr(touched, "touched", torch.uint8),
                              _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
 
 
 def plx_touched_count(touched, n_vox) -> int:
     out = ctypes.c_int64()
-    _check(lib().plx_touched_count(_dptr(touched, "touched", torch.int32), int(n_vox),
+    _check(lib().plx_touched_count(_dptr(touched, "touched", torch.uint8), int(n_vox),
                                    ctypes.byref(out), _stream()))
     return int(out.value)
 
@@ -350,5 +350,5 @@ def plx_rmsprop_step(g: PlxGrid, master, vstate, grad, touched, lr_sigma, lr_sh,
     _check(lib().plx_rmsprop_step(ctypes.byref(g), _dptr(master, "master", torch.float32),
                                   _dptr(vstate, "vstate", torch.float32, REC_SLOTS * g.n_vox),
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
-                                  _dptr(touched, "touched", torch.int32), float(lr_sigma),
+                                  _dptr(touched, "touched", torch.uint8), float(lr_sigma),
                                   float(lr_sh), float(beta), float(eps), _stream()))

@@ -169,6 +169,17 @@ __global__ void count_nonzero_kernel(const uint8_t *m, int64_t n, unsigned long 
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
 }
 
+__global__ void nonzero_bytes_kernel(const uint8_t *b, int64_t n, unsigned long long *out) {
+    // 4 bytes per thread
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    int c = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (i + e < n && b[i + e]) ++c;
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
 __global__ void popcount_kernel(const uint32_t *w, int64_t nw, int64_t nbits,
                                 unsigned long long *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -636,7 +647,7 @@ int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stre
     return check_launch("plx_grid_upsample_apply");
 }
 
-int plx_touched_count(const uint32_t *touched, int64_t n_vox, int64_t *count_out,
+int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
                       plx_stream stream) {
     if (!count_out) return fail(PLX_EINVAL, "plx_touched_count: count_out is NULL");
     if (n_vox < 0) return fail(PLX_EINVAL, "plx_touched_count: n_vox < 0");
@@ -646,15 +657,35 @@ int plx_touched_count(const uint32_t *touched, int64_t n_vox, int64_t *count_out
     }
     if (!touched) return fail(PLX_EINVAL, "plx_touched_count: touched is NULL");
     hipStream_t s = as_stream(stream);
-    int64_t nw = (n_vox + 31) / 32;
     TempBuf tmp;
     int rc = tmp.alloc(sizeof(unsigned long long), s);
     if (rc) return rc;
     auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
     PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_touched_count");
-    popcount_kernel<<<blocks_for(nw, 256), 256, 0, s>>>(touched, nw, n_vox, cnt);
+    nonzero_bytes_kernel<<<blocks_for((n_vox + 3) / 4, 256), 256, 0, s>>>(touched, n_vox, cnt);
     if ((rc = check_launch("plx_touched_count"))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, "plx_touched_count");
 }
 
 }  // extern "C"
+
+namespace plx {
+
+int count_set_bits(const uint32_t *words, int64_t n_bits, int64_t *count_out, hipStream_t s,
+                   const char *fn) {
+    if (n_bits <= 0) {
+        *count_out = 0;
+        return PLX_OK;
+    }
+    const int64_t nw = (n_bits + 31) / 32;
+    TempBuf tmp;
+    int rc = tmp.alloc(sizeof(unsigned long long), s);
+    if (rc) return rc;
+    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
+    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), fn);
+    popcount_kernel<<<blocks_for(nw, 256), 256, 0, s>>>(words, nw, n_bits, cnt);
+    if ((rc = check_launch(fn))) return rc;
+    return sync_read_u64(cnt, 1, count_out, s, fn);
+}
+
+}  // namespace plx

@@ -2,10 +2,10 @@
 // Sec. 3.8: the gradient is very sparse, so only voxels that received a
 // gradient term are updated) for gfx950.
 //
-// One 256-thread block per word of the touched bitmap, i.e. per 32 voxels;
-// 8 lanes per voxel, 4 FP32 slots per lane (16-byte accesses, one 128-byte
-// line per voxel and array).  A block whose word is zero reads 4 bytes and
-// exits, so the cost of a step follows the active set, not the grid.
+// 8 lanes per voxel (32 voxels per 256-thread block), 4 FP32 slots per lane
+// (16-byte accesses, one 128-byte line per voxel and array).  An inactive
+// voxel costs one byte read of the touched map, so the cost of a step follows
+// the active set, not the grid.
 #include "plx_internal.hpp"
 
 namespace plx {
@@ -13,17 +13,15 @@ namespace {
 
 template <int DT>
 __global__ __launch_bounds__(256) void rmsprop_kernel(void *data, float *master, float *vstate,
-                                                      float *grad, uint32_t *touched,
+                                                      float *grad, uint8_t *touched,
                                                       int64_t n_vox, float lr_sigma, float lr_sh,
                                                       float beta, float eps) {
-    const int64_t wid = blockIdx.x;
-    const uint32_t word = touched[wid];
-    __syncthreads();  // every lane has read the word before it is cleared
-    if (threadIdx.x == 0 && word) touched[wid] = 0u;
-    if (!word) return;
-    const int vi = threadIdx.x >> 3, L = threadIdx.x & 7;
-    const int64_t m = wid * 32 + vi;
-    if (!((word >> vi) & 1u) || m >= n_vox) return;
+    const int L = threadIdx.x & 7;
+    const int64_t m = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+    if (m >= n_vox) return;
+    // the 8 lanes of a voxel (one wave) read its byte before lane 0 clears it
+    if (!touched[m]) return;
+    if (L == 0) touched[m] = 0;
 
     float *P = DT == PLX_F32 ? static_cast<float *>(data) : master;
     float4 *pp = reinterpret_cast<float4 *>(P + m * PLX_REC_SLOTS) + L;
@@ -65,7 +63,7 @@ __global__ __launch_bounds__(256) void rmsprop_kernel(void *data, float *master,
 using namespace plx;
 
 extern "C" int plx_rmsprop_step(const plx_grid *grid, float *master, float *vstate, float *grad,
-                                uint32_t *touched, float lr_sigma, float lr_sh, float beta,
+                                uint8_t *touched, float lr_sigma, float lr_sh, float beta,
                                 float eps, plx_stream stream) {
     const char *fn = "plx_rmsprop_step";
     int rc = validate_grid(grid, false, fn);

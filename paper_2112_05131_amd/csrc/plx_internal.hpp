@@ -26,6 +26,11 @@ int check_launch(const char *what);
 
 inline hipStream_t as_stream(plx_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Number of set bits among the first n_bits bits of a device bitmap
+// (synchronising).
+int count_set_bits(const uint32_t *words, int64_t n_bits, int64_t *count_out, hipStream_t s,
+                   const char *fn);
+
 // Validates a grid descriptor for kernels; need_occ for the render calls.
 int validate_grid(const plx_grid *g, bool need_occ, const char *fn);
 

@@ -19,7 +19,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64_t count,
                                                  int64_t ncell, float lam_sig_v, float lam_sh_v,
                                                  float eps, float s0, float s1, float s2,
-                                                 float *grad, uint32_t *touched, double *loss_sum) {
+                                                 float *grad, uint8_t *touched, double *loss_sum) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double local = 0.0;
     if (c < count) {
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
                 const float gsum = sa[0] * dl[0] + sa[1] * dl[1] + sa[2] * dl[2];
                 const float gv = -coef * gsum;
                 if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)id * PLX_REC_SLOTS + PLX_SLOT_SIGMA, gv);
-                atomicOr(touched + (id >> 5), 1u << (id & 31));
+                touched[id] = 1;
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
                 const float gv = coef * sa[a] * dl[a];
                 if (gv != 0.0f)
                     unsafeAtomicAdd(grad + (int64_t)nid[a] * PLX_REC_SLOTS + PLX_SLOT_SIGMA, gv);
-                atomicOr(touched + (nid[a] >> 5), 1u << (nid[a] & 31));
+                touched[nid[a]] = 1;
             }
         }
         // SH channels of a non-NULL cell
@@ -110,7 +110,7 @@ using namespace plx;
 
 extern "C" int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
                            float lambda_sigma, float lambda_sh, float eps, float *grad,
-                           uint32_t *touched, double *loss_sum, plx_stream stream) {
+                           uint8_t *touched, double *loss_sum, plx_stream stream) {
     const char *fn = "plx_tv_grad";
     int rc = validate_grid(grid, false, fn);
     if (rc) return rc;

@@ -36,6 +36,45 @@ class TrainConfig:
     background: tuple = (1.0, 1.0, 1.0)
 
 
+class RaySampler:
+    """Training batches over a fixed set of rays (all pixels of the training
+    cameras) and their target colours.  Each epoch visits every ray once, in
+    a seeded random order: batches are consecutive slices of a fresh
+    permutation (supplement B.1: 5000-ray batches).  With coherent=True the
+    rays of each batch are listed in increasing storage order; the batch holds
+    the same rays, but neighbouring rays then run on neighbouring wavefronts
+    (store the rays camera by camera, pixels in a spatially coherent order).
+    The rays stay resident on the device; a batch is a gather."""
+
+    def __init__(self, rays_o: torch.Tensor, rays_d: torch.Tensor, target: torch.Tensor,
+                 batch: int, seed: int = 0, coherent: bool = True):
+        if not (rays_o.shape == rays_d.shape == target.shape and rays_o.shape[-1] == 3):
+            raise ValueError("rays_o, rays_d and target must all be [N, 3]")
+        if batch < 1:
+            raise ValueError("batch must be positive")
+        self.o, self.d, self.t = rays_o, rays_d, target
+        self.n = rays_o.shape[0]
+        self.batch = int(batch)
+        self.coherent = coherent
+        self.gen = torch.Generator(device=rays_o.device)
+        self.gen.manual_seed(int(seed))
+        self.epoch = -1
+        self._perm = None
+        self._pos = self.n
+
+    def next_batch(self):
+        if self._pos + self.batch > self.n:
+            # a new epoch; a short tail of the previous permutation is dropped
+            self._perm = torch.randperm(self.n, device=self.o.device, generator=self.gen)
+            self._pos = 0
+            self.epoch += 1
+        ids = self._perm[self._pos:self._pos + self.batch]
+        self._pos += self.batch
+        if self.coherent:
+            ids = torch.sort(ids).values
+        return self.o[ids], self.d[ids], self.t[ids]
+
+
 class Trainer:
     """Holds the optimiser state of one grid and runs training steps."""
 
@@ -52,7 +91,7 @@ class Trainer:
         m = grid.n_vox
         self.grad = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=dev)
         self.vstate = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=dev)
-        self.touched = torch.zeros((m + 31) // 32, dtype=torch.int32, device=dev)
+        self.touched = torch.zeros(m, dtype=torch.uint8, device=dev)
         self.loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
         self.tv_loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
 

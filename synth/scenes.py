@@ -188,15 +188,34 @@ def all_camera_rays(poses: torch.Tensor, width: int, height: int, fov_deg=45.0, 
     return torch.cat(os_), torch.cat(ds_)
 
 
+def _morton2(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """Interleaves the bits of two non-negative int64 tensors (< 2^16)."""
+    def spread(v):
+        v = v & 0xFFFF
+        v = (v | (v << 8)) & 0x00FF00FF
+        v = (v | (v << 4)) & 0x0F0F0F0F
+        v = (v | (v << 2)) & 0x33333333
+        v = (v | (v << 1)) & 0x55555555
+        return v
+    return spread(x) | (spread(y) << 1)
+
+
 def sampled_camera_rays(poses: torch.Tensor, width: int, height: int, n: int, seed: int,
-                        fov_deg: float = 45.0, device="cpu"):
+                        fov_deg: float = 45.0, device="cpu", coherent: bool = False):
     """n rays drawn uniformly (with replacement) from all pixels of all
-    cameras, as a training batch is.  Returns (rays_o, rays_d, pixel_ids)
-    where pixel_ids index the row-major concatenation of the images."""
+    cameras, as a training batch is.  With coherent=True the same rays are
+    returned ordered by camera and by Morton order of the pixel (a data-loader
+    choice that changes no ray, only the order they are listed in).  Returns
+    (rays_o, rays_d, pixel_ids) where pixel_ids index the row-major
+    concatenation of the images."""
     g = _gen(seed)
     npix = width * height
     ids = torch.randint(0, poses.shape[0] * npix, (n,), generator=g, dtype=torch.int64)
     ids = ids.to(device)
+    if coherent:
+        cam_, pix_ = ids // npix, ids % npix
+        key = cam_ * (1 << 32) + _morton2(pix_ % width, pix_ // width)
+        ids = ids[torch.argsort(key)]
     cam = ids // npix
     pix = ids % npix
     j = (pix // width).double()

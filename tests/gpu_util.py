@@ -114,12 +114,13 @@ def assert_grads_close(gpu_rec, ref_d, ref_s, what="", mass=None):
     return stats
 
 
-def assert_touched_equal(gpu_words, ref_touched, what=""):
+def assert_touched_equal(gpu_bytes, ref_touched, what=""):
+    """The touched map (one byte per voxel) equals the oracle's active set."""
     n = ref_touched.shape[0]
-    got = bits_to_bool(gpu_words, n)
+    b = gpu_bytes.cpu().numpy()
+    assert b.shape[0] == n, f"{what}: touched map has {b.shape[0]} bytes for {n} voxels"
+    assert np.isin(b, (0, 1)).all(), f"{what}: touched bytes other than 0/1"
+    got = b.astype(bool)
     ref = ref_touched.astype(bool)
     assert got.sum() == ref.sum(), f"{what}: touched count {got.sum()} vs {ref.sum()}"
     assert np.array_equal(got, ref), f"{what}: touched sets differ"
-    # no bits beyond n
-    w = gpu_words.cpu().numpy().astype(np.int32).view(np.uint8)
-    assert not np.unpackbits(w, bitorder="little")[n:].any()

@@ -188,7 +188,7 @@ def test_backward_matches_oracle(case):
     tau = torch.empty(n, device="cuda")
     B.plx_render_fwd(gg.desc(), o.cuda(), d.cuda(), rgb, tau, bg)
     grad = torch.zeros(gg.n_vox, 32, device="cuda")
-    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
     B.plx_render_bwd(gg.desc(), o.cuda(), d.cuda(), G.cuda(), tau, grad, touched, bg)
     torch.cuda.synchronize()
     gd, gs, t_ref = O.render_bwd(og, o.numpy(), d.numpy(), G.double().numpy(), bg)
@@ -224,7 +224,7 @@ def test_tv_matches_oracle(reso, occ, start, count):
     sv = synth.dense_random(reso, seed=41, occupancy=occ)
     og, gg = make_pair(sv)
     grad = torch.zeros(gg.n_vox, 32, device="cuda")
-    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     lam_s, lam_h, eps = 1.0, 0.7, 1e-9
     B.plx_tv_grad(gg.desc(), start, count, lam_s, lam_h, eps, grad, touched, loss)
@@ -260,9 +260,7 @@ def test_rmsprop_matches_oracle(sh_dtype):
         # the oracle sees the same FP32 gradient values
         gdn = grad[:, 28].double().cpu().numpy().copy()
         gsh = grad[:, :27].double().cpu().numpy().copy()
-        words = np.packbits(act, bitorder="little")
-        words = np.concatenate([words, np.zeros((-len(words)) % 4, np.uint8)]).view(np.int32)
-        touched = torch.from_numpy(words.copy()).cuda()
+        touched = torch.from_numpy(act.astype(np.uint8)).cuda()
         B.plx_rmsprop_step(gg.desc(), gg.master, vstate, grad, touched, lr_s, lr_h, beta, eps)
         torch.cuda.synchronize()
         O.rmsprop(act, dens, sh, vd, vs, gdn, gsh, lr_s, lr_h, beta, eps)
@@ -301,7 +299,7 @@ def test_train_step_c1_matches_oracle():
     n = o.shape[0]
     m = gg.n_vox
     grad = torch.zeros(m, 32, device="cuda")
-    touched = torch.zeros((m + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(m, dtype=torch.uint8, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     tvl = torch.zeros(1, dtype=torch.float64, device="cuda")
     rgb = torch.empty(n, 3, device="cuda")
@@ -351,7 +349,7 @@ def test_fused_train_equals_fwd_mse_bwd():
     tgt = synth.targets_uniform(5000, seed=63).cuda()
     m, n = gg.n_vox, 5000
     g1 = torch.zeros(m, 32, device="cuda")
-    t1 = torch.zeros((m + 31) // 32, dtype=torch.int32, device="cuda")
+    t1 = torch.zeros(m, dtype=torch.uint8, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     rgb1 = torch.empty(n, 3, device="cuda")
     B.plx_render_train(gg.desc(), o, d, tgt, 1.0 / n, g1, t1, loss, rgb1)
@@ -397,7 +395,7 @@ def test_16bit_forward_and_backward(sh_dtype):
     n = o.shape[0]
     G = torch.from_numpy(np.random.default_rng(71).normal(size=(n, 3))).float()
     grad = torch.zeros(g16.n_vox, 32, device="cuda")
-    touched = torch.zeros((g16.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(g16.n_vox, dtype=torch.uint8, device="cuda")
     B.plx_render_bwd(g16.desc(), o.cuda(), d.cuda(), G.cuda(), torch.from_numpy(tau).float().cuda(),
                      grad, touched)
     torch.cuda.synchronize()
@@ -449,7 +447,7 @@ def test_full_size_backward_subset(c3_scene):
     tau = torch.empty(n, device="cuda")
     B.plx_render_fwd(gg.desc(), so, sd, rgb, tau)
     grad = torch.zeros(gg.n_vox, 32, device="cuda")
-    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
     B.plx_render_bwd(gg.desc(), so, sd, G, tau, grad, touched)
     torch.cuda.synchronize()
     gd, gs, t_ref = O.render_bwd(og, so.cpu().numpy(), sd.cpu().numpy(), G.double().cpu().numpy())
@@ -513,7 +511,7 @@ def test_skipping_islands_forward_backward(seed):
     assert np.abs(rgb - rgb_ref).max() <= RGB_ATOL
     G = torch.from_numpy(np.random.default_rng(seed + 2).normal(size=(3000, 3))).float()
     grad = torch.zeros(gg.n_vox, 32, device="cuda")
-    touched = torch.zeros((gg.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
     B.plx_render_bwd(gg.desc(), o.cuda(), d.cuda(), G.cuda(), torch.from_numpy(tau).float().cuda(),
                      grad, touched)
     torch.cuda.synchronize()
