@@ -165,6 +165,48 @@ def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
                       f"segment, RMSProp on the sample's active voxels; {ts_:.1f} s FP64"}
 
 
+def state_leg(grid, batch, steps, cap=640):
+    """Separate forward + backward of one batch, with the backward recomputing
+    every sample (plx_render_fwd/bwd) or replaying the samples stored by the
+    forward pass (plx_render_fwd_state/bwd_state, at most `cap` per ray)."""
+    o, d, t = batch
+    n = o.shape[0]
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    g_rgb = torch.empty(n, 3, device="cuda")
+    grad = torch.zeros(grid.n_vox, B.REC_SLOTS, device="cuda")
+    touched = torch.zeros(grid.n_vox, dtype=torch.uint8, device="cuda")
+    state = torch.empty(B.plx_render_state_bytes(n, cap), dtype=torch.uint8, device="cuda")
+    reps = max(3, steps // 4)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    desc = grid.desc()
+    fwd = timed(lambda: B.plx_render_fwd(desc, o, d, rgb, tau))
+    torch.sub(rgb, t, out=g_rgb).mul_(2.0 / n)
+    bwd = timed(lambda: B.plx_render_bwd(desc, o, d, g_rgb, tau, grad, touched))
+    fwd_s = timed(lambda: B.plx_render_fwd_state(desc, o, d, rgb, tau, state, cap))
+    bwd_s = timed(lambda: B.plx_render_bwd_state(desc, o, d, g_rgb, tau, state, cap, grad, touched))
+    counts = state[:4 * n].view(torch.int32)
+    over = int((counts > cap).sum())
+    del state, grad
+    torch.cuda.empty_cache()
+    log(f"recompute fwd {fwd:.3f} bwd {bwd:.3f} ms; stored state fwd {fwd_s:.3f} bwd {bwd_s:.3f} ms")
+    return {"recompute": {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4)},
+            "stored": {"fwd_ms": round(fwd_s, 4), "bwd_ms": round(bwd_s, 4), "cap": cap,
+                       "state_gb": round(B.plx_render_state_bytes(n, cap) / 1e9, 3),
+                       "rays_over_cap": over}}
+
+
 def serving_leg(n_sat=160, n_load=240):
     """8 resident scenes (4 at 256^3, 4 at 512^3, 5-10% occupancy, FP16 SH),
     requests at 200x200 .. 1920x1080 with random poses on the view sphere:
@@ -317,6 +359,8 @@ def main():
                                    "render_train_ms": round(float(k3[0]), 4)}
             log(f"random ray order: step {ms3:.3f} ms, render_train {k3[0]:.3f} ms")
             del g3, tr3, shuffled
+    if not args.no_compare:
+        out["backward_state"] = state_leg(grid, batches[0], args.steps)
     if not args.no_serving:
         out["serving"] = serving_leg()
     if not args.no_cpu_baseline:

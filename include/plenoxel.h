@@ -235,6 +235,31 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
                      float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
                      double *loss_sum, plx_stream stream);
 
+/* Backward without recomputing the samples (the stored-state variant of the
+ * backward pass of Sec. 3.1-3.3).  plx_render_fwd_state is plx_render_fwd
+ * that also records, for each ray, its occupied samples in order: the sample
+ * index and the pre-activation density and SH-projected colour (the colour
+ * coefficients dotted with the ray's SH basis, per channel), at most `cap`
+ * per ray, plus the ray's total count.  plx_render_bwd_state is
+ * plx_render_bwd that replays those samples (it still reads the corner index
+ * entries for the scatter, but no voxel records); a ray with more than `cap`
+ * occupied samples is replayed by recomputation.  Results equal
+ * plx_render_bwd's up to FP32 rounding order.
+ *
+ * `state` is caller-owned device memory of plx_render_state_bytes(n_rays,
+ * cap) bytes, 256-byte aligned, written by the forward call and read by the
+ * backward call with the same rays, grid and cap.  Layout: int32
+ * count[n_rays]; int32 index[n_rays][cap]; float4 values[n_rays][cap] (each
+ * part starts on a 256-byte boundary).  0 <= cap <= 2^20. */
+int64_t plx_render_state_bytes(int64_t n_rays, int32_t cap);
+int plx_render_fwd_state(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                         const float *rays_d, int64_t n_rays, float *rgb_out, float *tau_out,
+                         void *state, int64_t state_bytes, int32_t cap, plx_stream stream);
+int plx_render_bwd_state(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                         const float *rays_d, int64_t n_rays, const float *grad_rgb,
+                         const float *tau_fwd, const void *state, int64_t state_bytes, int32_t cap,
+                         float *grad, uint8_t *touched, plx_stream stream);
+
 /* One novel-view request (serving).  Rays are pixel-centred pinhole rays:
  * pixel (px, py) of a width x height image gets, in FP64 with sums left to
  * right and then rounded to FP32, d_cam = ((px + 0.5 - width/2)/focal,
@@ -258,7 +283,7 @@ int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views);
 /* Renders a batch of novel views of resident scenes in one launch (the
  * forward model of plx_render_fwd, Sec. 3.1-3.3, with rays generated on the
  * device; interactive rendering is claimed in Sec. 1).  The views may mix
- * scenes and resolutions.  All pixels of all views form one queue of 4x2-pixel
+ * scenes and resolutions.  All pixels of all views form one queue of 16x16-pixel
  * tiles drained by a persistent grid, so the colour of a pixel depends only on
  * its ray and scene, never on the rest of the batch.  scenes (host array of
  * n_scenes descriptors, one sh_dtype, occupancy built) and views (host array)

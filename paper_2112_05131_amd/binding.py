@@ -94,6 +94,10 @@ _SIGS = {
     "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_state_bytes": ([_I64, _I32], _I64),
+    "plx_render_fwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P], ctypes.c_int),
+    "plx_render_bwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P],
+                             ctypes.c_int),
     "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_views_workspace": ([_I32, _I32], _I64),
     "plx_render_views": ([_GP, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
@@ -295,6 +299,45 @@ def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touch
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
                                   _dptr(touched, "touched", torch.uint8),
                                   _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_render_state_bytes(n_rays: int, cap: int) -> int:
+    return int(lib().plx_render_state_bytes(int(n_rays), int(cap)))
+
+
+def _state_ptr(state, n, cap):
+    need = plx_render_state_bytes(n, cap)
+    if not (isinstance(state, torch.Tensor) and state.is_cuda and state.dtype == torch.uint8
+            and state.is_contiguous() and state.numel() >= need):
+        raise ValueError(f"state must be a contiguous CUDA uint8 tensor of >= {need} bytes")
+    return ctypes.c_void_p(state.data_ptr()), state.numel()
+
+
+def plx_render_fwd_state(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out, state, cap,
+                         bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    o = _opts(bg)
+    sp, sb = _state_ptr(state, n, cap)
+    _check(lib().plx_render_fwd_state(ctypes.byref(g), ctypes.byref(o),
+                                      _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                      _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                      _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                      _dptr(tau_out, "tau_out", torch.float32, n), sp, sb, int(cap),
+                                      _stream()))
+
+
+def plx_render_bwd_state(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, state, cap, grad, touched,
+                         bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    o = _opts(bg)
+    sp, sb = _state_ptr(state, n, cap)
+    _check(lib().plx_render_bwd_state(ctypes.byref(g), ctypes.byref(o),
+                                      _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                      _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                      _dptr(grad_rgb, "grad_rgb", torch.float32, 3 * n),
+                                      _dptr(tau_fwd, "tau_fwd", torch.float32, n), sp, sb, int(cap),
+                                      _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                      _dptr(touched, "touched", torch.uint8), _stream()))
 
 
 def plx_render_views_workspace(n_scenes: int, n_views: int) -> int:

@@ -1,23 +1,18 @@
 // render.hip -- differentiable volume rendering over the sparse voxel grid
 // (Sec. 3.1-3.3, Eq. (1); supplement B.1) for gfx950.
 //
-// Work mapping: one ray per wave64 (four per 256-thread block).  The lanes
-// form four rows of 16: row r < 3 holds the nine SH coefficients of colour
-// channel r (lanes 16r .. 16r+8), row 3 holds the density (lane 48).  Every
-// ray-level quantity is uniform over the wave, so corner ids, cells and
-// sample masks live in scalar registers and all branches are uniform.
+// Work mapping: one ray per lane, 256 rays per block.  A heavily sampled
+// ray is a long chain of dependent memory accesses (occupancy bits, index
+// entries, voxel records), so the kernels keep as many rays in flight as the
+// register file allows rather than spreading one ray over a wave.
 //
 // SH factorisation.  The SH basis depends only on the ray direction, so the
-// pre-activation colour of a sample is sum_c w_c (sum_l y_l k_{c,l}): the
-// coefficients of a corner are projected on the ray's basis once, when the
-// corner is loaded (one 4-byte load per lane and a 16-lane DPP reduction
-// within each row), and each sample then interpolates four numbers per
-// corner: row r of the wave interpolates channel r (r < 3) or density (r = 3).
-// In the backward pass the gradient of a coefficient is y_l times the
-// gradient of its channel's projected value, so the lanes accumulate one
-// number per corner and multiply by y_l when the corner is flushed; the flush
-// is one float atomic instruction per corner whose lanes cover one 128-byte
-// record line.
+// pre-activation colour of a sample is sum_c w_c (sum_l y_l k_{c,l}): when a
+// corner voxel is loaded its coefficients are projected on the ray's basis
+// once, and each sample interpolates four numbers per corner (density and
+// the three projected channels).  In the backward pass the gradient of a
+// coefficient is y_l times the gradient of its channel's projected value,
+// so a lane accumulates four numbers per corner.
 //
 // Exact empty-space skipping, two levels.  A sample whose lower-corner cell
 // has no non-NULL corner reads only zeros: it changes neither colour nor
@@ -27,10 +22,9 @@
 //    brick with D > 0, every cell of the box of bricks within D-1 of it is
 //    empty, so the ray jumps to the box's exit point along its own direction
 //    (less a margin of 5% of a step, far above FP32 rounding of t and g).
-//  - Cell level: near occupied bricks, 64 candidate samples are placed at a
-//    time (one per lane) and tested against the cell bitmap; one ballot gives
-//    the occupied ones, which are processed in order, each reading its cell
-//    and interpolation weights from the lane that placed it.
+//  - Cell level: near occupied bricks a lane tests 16 candidate samples at a
+//    time against the cell bitmap (16 independent loads) and processes only
+//    the occupied ones.
 // The corner ids and projected values of the current cell stay in registers
 // while consecutive samples stay in one cell; a move to a face-adjacent cell
 // keeps the 4 shared corners and loads only the other 4.
@@ -43,9 +37,14 @@
 // and the rest of the ray R_k = sum_{j>k} w_j c_j + T_n bg is a running sum;
 // dC/dsigma_k = delta (T_{k+1} c_k - R_k), dC/dc_k = w_k.  Corner gradients
 // are accumulated in registers for as long as a voxel stays a corner of the
-// current cell.  The fused training kernel keeps the list of non-empty
-// 64-sample chunks found by its forward pass in LDS and replays exactly those
-// in reverse.
+// current cell.  When it stops being one, the lane appends (voxel, four
+// accumulated values, lane) to a queue in LDS; after every step of the
+// replay the wave drains the queue two voxels at a time, 32 lanes per voxel,
+// so that each voxel's 28 gradient values go out as one float atomic
+// instruction covering its 128-byte gradient record (the access pattern for
+// which the L2 float atomics are fastest).  The fused training kernel replays
+// only the span between the first and last occupied sample of its forward
+// pass.
 #include <string.h>
 
 #include <vector>
@@ -56,12 +55,11 @@ namespace plx {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kThreads = 256;                    // 4 waves
-constexpr int kRaysPerBlock = kThreads / kWave;  // 4
-constexpr int kChunk = 64;                       // candidate samples per round (one per lane)
-constexpr int kMaxChunks = 40;                   // chunk list entries per ray (fused kernel)
-constexpr float kSkipMargin = 0.05f;             // in steps
-constexpr int kSigmaLane = 48;                   // row 3, first lane
+constexpr int kThreads = 256;          // rays per block
+constexpr int kWavesPerBlock = kThreads / kWave;
+constexpr int kChunk = 16;             // candidate samples tested per round
+constexpr int kQCap = 8 * kWave;       // queue entries per wave (8 corners per lane per step)
+constexpr float kSkipMargin = 0.05f;   // in steps
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
 
@@ -76,6 +74,10 @@ struct RenderArgs {
     float *grad;            // BWD, TRAIN
     uint8_t *touched;       // BWD, TRAIN
     double *loss_sum;       // TRAIN
+    int *st_count;          // per-ray sample state (optional): occupied samples of each ray
+    int *st_kidx;           // [n_rays][st_cap] their sample indices
+    float4 *st_vals;        // [n_rays][st_cap] pre-activation density and projected colour
+    int st_cap;
     int64_t n_rays;
     float bg[3];
     float loss_scale;
@@ -83,225 +85,244 @@ struct RenderArgs {
     int nb8;
 };
 
-// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ int64_t uni64(int64_t v) {
-    const uint64_t u = (uint64_t)v;
-    const uint32_t lo = (uint32_t)uni((int)(uint32_t)u), hi = (uint32_t)uni((int)(uint32_t)(u >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ int lane_i(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
-__device__ __forceinline__ float lane_f(float v, int i) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-}
+// ------------------------------------------------------------ voxel records
 
-template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-// Sum over the 16 lanes of each row, left in every lane of the row.  Each
-// step adds a partner's value (lane^1, lane^2, the mirrored quad, the
-// mirrored half-row); the pairing is symmetric and addition commutes, so
-// every lane of a row ends with the same bits.
-__device__ __forceinline__ float row_sum(float v) {
-    v += dpp_f<0xB1>(v);   // quad_perm(1,0,3,2)
-    v += dpp_f<0x4E>(v);   // quad_perm(2,3,0,1)
-    v += dpp_f<0x141>(v);  // row_half_mirror
-    v += dpp_f<0x140>(v);  // row_mirror
-    return v;
-}
-
-// Role of a lane: its row, the record slot it reads and writes (-1: none) and
-// the SH basis value of that slot's coefficient at the ray direction (1 for
-// the density slot).
-struct Lane {
-    int L;
-    int row;
-    int slot;
-    float y;
+// Density and the three colour channels projected on the ray's SH basis y.
+struct Q4 {
+    float s, r, g, b;
 };
 
-__device__ inline Lane lane_role(const float d[3]) {
-    Lane l;
-    l.L = threadIdx.x & (kWave - 1);
-    l.row = l.L >> 4;
-    const int j = l.L & 15;
-    if (l.row < 3 && j < 9) {
-        l.slot = 9 * l.row + j;
-        l.y = sh_basis_at(j, d[0], d[1], d[2]);
-    } else if (l.L == kSigmaLane) {
-        l.slot = PLX_SLOT_SIGMA;
-        l.y = 1.0f;
-    } else {
-        l.slot = -1;
-        l.y = 0.0f;
+__device__ __forceinline__ Q4 q4_zero() { return Q4{0.0f, 0.0f, 0.0f, 0.0f}; }
+
+template <int DT> struct Project;
+template <> struct Project<PLX_F32> {
+    // slots 0..27 as seven 16-byte loads, sigma (slot 28) as one 4-byte load
+    __device__ static inline Q4 run(const void *data, int id, const float y[9]) {
+        const float *rec = static_cast<const float *>(data) + (int64_t)id * PLX_REC_SLOTS;
+        const float4 *p = reinterpret_cast<const float4 *>(rec);
+        float v[28];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            const float4 t = p[i];
+            v[4 * i] = t.x;
+            v[4 * i + 1] = t.y;
+            v[4 * i + 2] = t.z;
+            v[4 * i + 3] = t.w;
+        }
+        Q4 q;
+        q.s = rec[PLX_SLOT_SIGMA];
+        q.r = 0.0f;
+        q.g = 0.0f;
+        q.b = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            q.r += y[l] * v[l];
+            q.g += y[l] * v[9 + l];
+            q.b += y[l] * v[18 + l];
+        }
+        return q;
     }
-    return l;
+};
+template <int DT> struct Project16 {
+    // the 64-byte record as four 16-byte loads: 16-bit slot s in word s/2,
+    // the FP32 density in word 14
+    __device__ static inline float h2f(uint32_t h) {
+        return DT == PLX_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
+    }
+    __device__ static inline float slot(const uint32_t w[16], int s) {
+        return h2f((s & 1) ? (w[s >> 1] >> 16) : (w[s >> 1] & 0xffffu));
+    }
+    __device__ static inline Q4 run(const void *data, int id, const float y[9]) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(static_cast<const char *>(data) +
+                                                         (int64_t)id * kRec16Bytes);
+        uint32_t w[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint4 t = p[i];
+            w[4 * i] = t.x;
+            w[4 * i + 1] = t.y;
+            w[4 * i + 2] = t.z;
+            w[4 * i + 3] = t.w;
+        }
+        Q4 q;
+        q.s = __uint_as_float(w[14]);
+        q.r = 0.0f;
+        q.g = 0.0f;
+        q.b = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            q.r += y[l] * slot(w, l);
+            q.g += y[l] * slot(w, 9 + l);
+            q.b += y[l] * slot(w, 18 + l);
+        }
+        return q;
+    }
+};
+template <> struct Project<PLX_BF16> : Project16<PLX_BF16> {};
+template <> struct Project<PLX_F16> : Project16<PLX_F16> {};
+
+// ------------------------------------------------------------ flush queue
+
+// Per-wave queue of flushed corners in LDS (structure of arrays).
+struct Queue {
+    int *count;     // entries in use
+    int *id;        // [kQCap] voxel id
+    uint8_t *src;   // [kQCap] lane that flushed it (selects the SH basis)
+    float *v;       // [4][kQCap] accumulated density, R, G, B gradients
+    float *y;       // [64][9] SH basis of each lane's ray
+};
+
+// Appends one entry per active lane (lanes outside the caller's branch do not
+// append).  Offsets come from one leader lane; only this wave uses the queue,
+// and its LDS accesses are ordered.
+__device__ __forceinline__ void push(const Queue &qu, int id, const Q4 &a) {
+    const uint64_t act = __ballot(1);
+    const int leader = __builtin_ctzll(act);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    int base = 0;
+    if (lane_id() == leader) {
+        base = *qu.count;
+        *qu.count = base + __popcll(act);
+    }
+    base = __builtin_amdgcn_readlane(base, leader);
+    const int e = base + rank;
+    qu.id[e] = id;
+    qu.src[e] = (uint8_t)lane_id();
+    qu.v[e] = a.s;
+    qu.v[kQCap + e] = a.r;
+    qu.v[2 * kQCap + e] = a.g;
+    qu.v[3 * kQCap + e] = a.b;
 }
 
-// Slot s (0..26 or PLX_SLOT_SIGMA) of a record as one 32-bit load plus a
-// branch-free conversion.
-template <int DT> struct Slot;
-template <> struct Slot<PLX_F32> {
-    __device__ static inline uint32_t raw(const void *data, int64_t id, int s) {
-        return reinterpret_cast<const uint32_t *>(static_cast<const char *>(data) +
-                                                  id * (int64_t)kRecF32Bytes)[s];
+// Sends every queued voxel's gradient to its FP32 record: lanes 0..31 take
+// one entry and lanes 32..63 the next, lane L & 31 = record slot (0..26 SH,
+// 28 density, 29 marks the voxel touched).  Called by the whole wave.
+__device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *touched) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int E = __builtin_amdgcn_readfirstlane(*qu.count);
+    if (E == 0) return;
+    const int L = lane_id();
+    const int s = L & 31;
+    const int ch = s < PLX_NSH ? 1 + s / 9 : 0;  // v row: 0 density, 1..3 colour
+    const int l = s < PLX_NSH ? s % 9 : 0;
+    const bool writes = s < PLX_NSH || s == PLX_SLOT_SIGMA;
+    // four pairs of entries per round, so that their LDS reads overlap
+    for (int e0 = 0; e0 < E; e0 += 8) {
+        int id[4], src[4];
+        float a[4], yv[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 2 * u + (L >> 5);
+            ok[u] = e < E;
+            id[u] = ok[u] ? qu.id[e] : 0;
+            src[u] = ok[u] ? (int)qu.src[e] : 0;
+            a[u] = ok[u] ? qu.v[ch * kQCap + e] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yv[u] = s < PLX_NSH ? qu.y[src[u] * 9 + l] : 1.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!ok[u]) continue;
+            const float val = yv[u] * a[u];
+            if (writes && val != 0.0f)
+                unsafeAtomicAdd(grad + (int64_t)id[u] * PLX_REC_SLOTS + s, val);
+            if (s == PLX_SLOT_SIGMA + 1) touched[id[u]] = 1;
+        }
     }
-    __device__ static inline float cvt(uint32_t r, int) { return __uint_as_float(r); }
-};
-template <int DT> struct Slot16 {
-    // the 32-bit word holding 16-bit slot s, or the FP32 density at byte 56
-    __device__ static inline uint32_t raw(const void *data, int64_t id, int s) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(static_cast<const char *>(data) +
-                                                               id * (int64_t)kRec16Bytes);
-        return p[s == PLX_SLOT_SIGMA ? 14 : (s >> 1)];
-    }
-    __device__ static inline float cvt(uint32_t r, int s) {
-        const uint32_t h = (s & 1) ? (r >> 16) : (r & 0xffffu);
-        const float v = DT == PLX_BF16 ? bf16_to_f32(h) : f16_to_f32(h);
-        return s == PLX_SLOT_SIGMA ? __uint_as_float(r) : v;
-    }
-};
-template <> struct Slot<PLX_BF16> : Slot16<PLX_BF16> {};
-template <> struct Slot<PLX_F16> : Slot16<PLX_F16> {};
-
-// Uniform copy of a grid descriptor read from memory.
-__device__ inline GridDev uniform_grid(const GridDev &s) {
-    GridDev g;
-    g.nx = uni(s.nx);
-    g.ny = uni(s.ny);
-    g.nz = uni(s.nz);
-    g.bx = uni(s.bx);
-    g.by = uni(s.by);
-    g.bz = uni(s.bz);
-    for (int a = 0; a < 3; ++a) {
-        g.scale[a] = uni(s.scale[a]);
-        g.offset[a] = uni(s.offset[a]);
-    }
-    g.step = uni(s.step);
-    auto up = [](const void *p) {
-        return reinterpret_cast<const void *>(uni64((int64_t)reinterpret_cast<uint64_t>(p)));
-    };
-    g.index = static_cast<const int32_t *>(up(s.index));
-    g.data = up(s.data);
-    g.occ = static_cast<const uint32_t *>(up(s.occ));
-    g.bdist = static_cast<const uint8_t *>(up(s.bdist));
-    g.n_vox = uni64(s.n_vox);
-    return g;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (L == 0) *qu.count = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------ corner cache
 
-// The current cell: corner ids (uniform) and, per lane, its row's projected
-// value of each corner (channel r: sum_l y_l k_{c,9r+l}; row 3: density).
+// The lane's current cell: corner ids and projected values.
 struct CornerCache {
     int cell[3];  // lower corner; cell[0] < 0 = empty cache
     int ids[8];
-    float q[8];
+    Q4 q[8];
 };
 
 __device__ inline int64_t corner_offset(const GridDev &g, int c) {
     return ((c >> 2) & 1) * ((int64_t)g.ny * g.nz) + ((c >> 1) & 1) * (int64_t)g.nz + (c & 1);
 }
 
-// Loads the corners of `mask` (bit c = corner c) of the cell cc.cell.
-template <int DT>
-__device__ __forceinline__ void load_corners(const GridDev &g, CornerCache &cc, const Lane &ln,
-                                             unsigned mask) {
-    const int64_t lin = cell_id(g, cc.cell);
-    int mine = -1;
-    if (ln.L < 8 && ((mask >> ln.L) & 1u)) mine = g.index[lin + corner_offset(g, ln.L)];
-    uint32_t raw[8];
+template <class T> __device__ __forceinline__ void swap2(T &a, T &b) {
+    const T t = a;
+    a = b;
+    b = t;
+}
+
+// Exchanges the corners at positions c and c ^ BIT (the two faces of the cell
+// across axis BIT).  After a move by +-1 along that axis, the shared corners
+// then sit at their new positions; the other four positions are reloaded.
+template <int BIT, bool BWD>
+__device__ __forceinline__ void swap_faces(CornerCache &cc, Q4 acc[8]) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        if ((mask >> c) & 1u) {
-            cc.ids[c] = lane_i(mine, c);
-            raw[c] = 0u;
-            if (cc.ids[c] >= 0 && ln.slot >= 0) raw[c] = Slot<DT>::raw(g.data, cc.ids[c], ln.slot);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if ((mask >> c) & 1u) {
-            const float v = (cc.ids[c] >= 0 && ln.slot >= 0) ? Slot<DT>::cvt(raw[c], ln.slot) : 0.0f;
-            cc.q[c] = row_sum(ln.y * v);
-        }
+        if (c & BIT) continue;
+        swap2(cc.ids[c], cc.ids[c | BIT]);
+        swap2(cc.q[c], cc.q[c | BIT]);
+        if (BWD) swap2(acc[c], acc[c | BIT]);
     }
 }
 
-// Adds the accumulated gradients of the corners in `mask` to the FP32
-// gradient records (one atomic instruction per corner line), marks those
-// corners touched, and clears their accumulators.
-__device__ __forceinline__ void flush(float *grad, uint8_t *touched, const CornerCache &cc,
-                                      float acc[8], const Lane &ln, unsigned mask) {
-    int tid = -1;  // lane 56 + c marks corner c
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (!((mask >> c) & 1u)) continue;
-        if (cc.ids[c] >= 0) {
-            const float gv = ln.row < 3 ? ln.y * acc[c] : acc[c];
-            if (ln.slot >= 0 && gv != 0.0f)
-                unsafeAtomicAdd(grad + (int64_t)cc.ids[c] * PLX_REC_SLOTS + ln.slot, gv);
-            tid = ln.L == 56 + c ? cc.ids[c] : tid;
-        }
-        acc[c] = 0.0f;
-    }
-    if (tid >= 0) touched[tid] = 1;
-}
-
-// Moves the cache along one axis (BIT 4 = x, 2 = y, 1 = z) by +1 (PLUS) or
-// -1: the four shared corners change position, the other four are flushed
-// (backward) and reloaded.
-template <int DT, bool BWD, int BIT, bool PLUS>
-__device__ __forceinline__ void shift_cell(const GridDev &g, CornerCache &cc, float acc[8],
-                                           float *grad, uint8_t *touched, const Lane &ln) {
-    // positions that receive a shared corner (their old corner leaves)
-    unsigned keep = 0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        if (((c & BIT) != 0) == !PLUS) keep |= 1u << c;
-    if (BWD) flush(grad, touched, cc, acc, ln, keep);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if ((keep >> c) & 1u) {
-            cc.ids[c] = cc.ids[c ^ BIT];
-            cc.q[c] = cc.q[c ^ BIT];
-            if (BWD) {
-                acc[c] = acc[c ^ BIT];
-                acc[c ^ BIT] = 0.0f;
-            }
-        }
-    }
-    constexpr int a = BIT == 4 ? 0 : (BIT == 2 ? 1 : 2);
-    cc.cell[a] += PLUS ? 1 : -1;
-    load_corners<DT>(g, cc, ln, 0xffu & ~keep);
-}
-
-// Makes `cell` the cached cell.
+// Makes `cell` the lane's cached cell.  On a move to a face-adjacent cell the
+// four shared corners change position (positions `keep` receive the corner
+// at position ^ bit) and only the other four are loaded; on any other move
+// all eight are.  Corners that stop being corners are flushed first
+// (backward).  Without `project` only the corner ids are loaded (the replay
+// of stored samples needs them for the scatter, not the values).
 template <int DT, bool BWD>
 __device__ __forceinline__ void move_to(const GridDev &g, CornerCache &cc, const int cell[3],
-                                        float acc[8], float *grad, uint8_t *touched,
-                                        const Lane &ln) {
+                                        Q4 acc[8], const Queue &qu, const float y[9],
+                                        bool project = true) {
     const int dx = cell[0] - cc.cell[0], dy = cell[1] - cc.cell[1], dz = cell[2] - cc.cell[2];
     if (dx == 0 && dy == 0 && dz == 0) return;
-    if (cc.cell[0] >= 0 && abs(dx) + abs(dy) + abs(dz) == 1) {
-        if (dx == 1) shift_cell<DT, BWD, 4, true>(g, cc, acc, grad, touched, ln);
-        else if (dx == -1) shift_cell<DT, BWD, 4, false>(g, cc, acc, grad, touched, ln);
-        else if (dy == 1) shift_cell<DT, BWD, 2, true>(g, cc, acc, grad, touched, ln);
-        else if (dy == -1) shift_cell<DT, BWD, 2, false>(g, cc, acc, grad, touched, ln);
-        else if (dz == 1) shift_cell<DT, BWD, 1, true>(g, cc, acc, grad, touched, ln);
-        else shift_cell<DT, BWD, 1, false>(g, cc, acc, grad, touched, ln);
-        return;
+    const bool had = cc.cell[0] >= 0;
+    const bool adj = had && abs(dx) + abs(dy) + abs(dz) == 1;
+    const int bit = dx != 0 ? 4 : (dy != 0 ? 2 : 1);
+    const bool plus = dx + dy + dz > 0;
+    unsigned keep = 0;
+    if (adj) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (((c & bit) != 0) != plus) keep |= 1u << c;
     }
-    if (BWD && cc.cell[0] >= 0) flush(grad, touched, cc, acc, ln, 0xffu);
+    if (BWD && had) {
+        // corners leaving: those at `keep` positions (shift) or all (jump)
+        const unsigned leave = adj ? keep : 0xffu;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (((leave >> c) & 1u) && cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
+    }
+    if (adj) {
+        if (bit == 4) swap_faces<4, BWD>(cc, acc);
+        else if (bit == 2) swap_faces<2, BWD>(cc, acc);
+        else swap_faces<1, BWD>(cc, acc);
+    }
     cc.cell[0] = cell[0];
     cc.cell[1] = cell[1];
     cc.cell[2] = cell[2];
-    load_corners<DT>(g, cc, ln, 0xffu);
+    const int64_t lin = cell_id(g, cc.cell);
+    int nid[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) nid[c] = ((keep >> c) & 1u) ? cc.ids[c] : g.index[lin + corner_offset(g, c)];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!((keep >> c) & 1u)) {
+            cc.ids[c] = nid[c];
+            cc.q[c] = (project && nid[c] >= 0) ? Project<DT>::run(g.data, nid[c], y) : q4_zero();
+            if (BWD) acc[c] = q4_zero();
+        }
+    }
 }
 
 __device__ inline void corner_weights(const float f[3], float w[8]) {
@@ -312,44 +333,34 @@ __device__ inline void corner_weights(const float f[3], float w[8]) {
     for (int c = 0; c < 8; ++c) w[c] = ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1];
 }
 
-// ------------------------------------------------------------ samples
-
-// Places the 64 candidate samples k0..k0+63 (sample k0+L in lane L).  With
-// TEST, returns the uniform mask of those that exist and lie in an occupied
-// cell.
-template <bool TEST>
-__device__ __forceinline__ uint64_t place_chunk(const GridDev &g, const RayGeom &r, int n, int k0,
-                                                int L, Sample &s) {
-    const int k = k0 + L;
-    bool ne = false;
-    s.cell[0] = s.cell[1] = s.cell[2] = 0;
-    s.f[0] = s.f[1] = s.f[2] = 0.0f;
-    s.delta = 0.0f;
-    if (k >= 0 && k < n) {
-        s = sample_at(g, r, k);
-        if (TEST) ne = cell_occupied(g, cell_id(g, s.cell));
+// Interpolated (pre-activation) density and projected colour at weights w.
+__device__ __forceinline__ Q4 interpolate(const CornerCache &cc, const float w[8]) {
+    Q4 v = q4_zero();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        v.s += w[c] * cc.q[c].s;
+        v.r += w[c] * cc.q[c].r;
+        v.g += w[c] * cc.q[c].g;
+        v.b += w[c] * cc.q[c].b;
     }
-    return TEST ? __ballot(ne) : 0ull;
+    return v;
 }
 
-// The sample placed in lane i, as uniform values.
-struct USample {
-    int cell[3];
-    float w[8];
-    float delta;
-};
+// ------------------------------------------------------------ sample cursor
 
-__device__ __forceinline__ USample take_sample(const Sample &s, int i) {
-    USample u;
-    float f[3];
+// Occupancy of samples k0 .. k0+15 (bit i: sample k0+i exists and its cell
+// is occupied); the 16 bitmap loads are independent.
+__device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &r, int n, int k0) {
+    uint32_t m = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        u.cell[a] = lane_i(s.cell[a], i);
-        f[a] = lane_f(s.f[a], i);
+    for (int i = 0; i < kChunk; ++i) {
+        const int k = k0 + i;
+        if (k >= 0 && k < n) {
+            const Sample s = sample_at(g, r, k);
+            if (cell_occupied(g, cell_id(g, s.cell))) m |= 1u << i;
+        }
     }
-    u.delta = lane_f(s.delta, i);
-    corner_weights(f, u.w);
-    return u;
+    return m;
 }
 
 // Brick-level skip.  Returns the distance D of the brick of sample k (0 when
@@ -360,7 +371,7 @@ template <bool FORWARD>
 __device__ __forceinline__ int brick_skip(const GridDev &g, const RayGeom &r, int k, int *m) {
     const Sample s = sample_at(g, r, k);
     const int b[3] = {s.cell[0] / PLX_BRICK, s.cell[1] / PLX_BRICK, s.cell[2] / PLX_BRICK};
-    const int D = uni((int)g.bdist[((int64_t)b[0] * g.by + b[1]) * g.bz + b[2]]);
+    const int D = g.bdist[((int64_t)b[0] * g.by + b[1]) * g.bz + b[2]];
     if (D == 0) return 0;
     const int nb[3] = {g.bx, g.by, g.bz};
     const float t = r.t_near + (float)k * g.step;
@@ -380,226 +391,309 @@ __device__ __forceinline__ int brick_skip(const GridDev &g, const RayGeom &r, in
     const float span = FORWARD ? (t_edge - t) : (t - t_edge);
     float q = span / g.step - kSkipMargin;
     q = q < (float)kMaxSamples ? q : (float)kMaxSamples;
-    *m = uni(q > 0.0f ? (int)q : 0);
+    *m = q > 0.0f ? (int)q : 0;
     return D;
 }
 
-// Uniform ray: origin and direction of ray `ray` in every lane.
-__device__ __forceinline__ void load_ray(const float *o_in, const float *d_in, int64_t ray,
-                                         float o[3], float d[3]) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        o[i] = uni(o_in[3 * ray + i]);
-        d[i] = uni(d_in[3 * ray + i]);
+// Position in the ray's list of occupied samples.
+struct Cursor {
+    int k;          // next sample to examine
+    int k0;         // first sample of the current chunk
+    uint32_t mask;  // occupied samples of the chunk not yet returned
+};
+
+// Next occupied sample in increasing order, or -1 after the last one.
+__device__ __forceinline__ int next_forward(const GridDev &g, const RayGeom &r, int n, Cursor &c) {
+    while (c.mask == 0u) {
+        if (c.k >= n) return -1;
+        int m;
+        if (brick_skip<true>(g, r, c.k, &m)) {
+            c.k += m + 1;
+            continue;
+        }
+        c.k0 = c.k;
+        c.mask = chunk_bits(g, r, n, c.k);
+        c.k += kChunk;
     }
+    const int b = __builtin_ctz(c.mask);
+    c.mask &= c.mask - 1u;
+    return c.k0 + b;
+}
+
+// Next occupied sample in decreasing order, not below k_lo; -1 when done.
+__device__ __forceinline__ int next_backward(const GridDev &g, const RayGeom &r, int n, int k_lo,
+                                             Cursor &c) {
+    while (c.mask == 0u) {
+        if (c.k < k_lo) return -1;
+        int m;
+        if (brick_skip<false>(g, r, c.k, &m)) {
+            c.k -= m + 1;
+            continue;
+        }
+        c.k0 = c.k - (kChunk - 1);
+        c.mask = chunk_bits(g, r, n, c.k0);
+        if (c.k0 < k_lo) c.mask &= ~0u << (k_lo - c.k0);
+        c.k -= kChunk;
+    }
+    const int b = 31 - __builtin_clz(c.mask);
+    c.mask &= ~(1u << b);
+    return c.k0 + b;
 }
 
 // ------------------------------------------------------------ forward march
 
-struct ChunkList {
-    int *k0;
-    unsigned long long *mask;
-};
-
-// Front-to-back march of one ray (Eq. (1)).  Returns in C the colour of the
-// lane's row before the background is added (rows 0..2), and the optical
-// depth in tau.  With RECORD, the non-empty chunks are appended to `list`
-// (capacity kMaxChunks; *overflow is set when it runs out).
-template <int DT, bool RECORD>
+// Front-to-back march of one ray (Eq. (1)).  Returns the colour before the
+// background is added in C and the optical depth in tau; with the span
+// pointers, the first and last occupied sample (k_first > k_last if none).
+// With STORE, the first `cap` occupied samples (index and pre-activation
+// values) go to kidx/vals and their total count to *count.
+template <int DT, bool STORE = false>
 __device__ __forceinline__ void march_forward(const GridDev &g, const RayGeom &r, int n,
-                                              const Lane &ln, CornerCache &cc, float &C,
-                                              double &tau, ChunkList list, int &n_list,
-                                              bool &overflow) {
-    C = 0.0f;
+                                              const float y[9], CornerCache &cc, float C[3],
+                                              double &tau, int *k_first, int *k_last,
+                                              int *count = nullptr, int *kidx = nullptr,
+                                              float4 *vals = nullptr, int cap = 0) {
+    C[0] = C[1] = C[2] = 0.0f;
     tau = 0.0;
-    int k = 0;
-    while (k < n) {
-        int m;
-        if (brick_skip<true>(g, r, k, &m)) {
-            k += m + 1;
-            continue;
-        }
-        Sample s;
-        uint64_t mask = place_chunk<true>(g, r, n, k, ln.L, s);
-        if (RECORD && mask) {
-            if (n_list < kMaxChunks) {
-                if (ln.L == 0) {
-                    list.k0[n_list] = k;
-                    list.mask[n_list] = mask;
-                }
-                ++n_list;
-            } else {
-                overflow = true;
+    Cursor cur{0, 0, 0u};
+    Q4 none[8];
+    Queue noq{};
+    int first = n, last = -1, stored = 0;
+    while (true) {
+        const int k = next_forward(g, r, n, cur);
+        if (k < 0) break;
+        if (first == n) first = k;
+        last = k;
+        const Sample s = sample_at(g, r, k);
+        move_to<DT, false>(g, cc, s.cell, none, noq, y);
+        float w[8];
+        corner_weights(s.f, w);
+        const Q4 v = interpolate(cc, w);
+        if (STORE) {
+            if (stored < cap) {
+                kidx[stored] = k;
+                vals[stored] = make_float4(v.s, v.r, v.g, v.b);
             }
+            ++stored;
         }
-        while (mask) {
-            const int i = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const USample u = take_sample(s, i);
-            move_to<DT, false>(g, cc, u.cell, nullptr, nullptr, nullptr, ln);
-            float v = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) v += u.w[c] * cc.q[c];
-            const float sigma = fmaxf(lane_f(v, kSigmaLane), 0.0f);
-            const float sd = sigma * u.delta;
-            const float wk = expf(-(float)tau) * (-expm1f(-sd));
-            C += wk * fmaxf(v, 0.0f);
-            tau += (double)sd;
-        }
-        k += kChunk;
+        const float sd = fmaxf(v.s, 0.0f) * s.delta;
+        const float wk = expf(-(float)tau) * (-expm1f(-sd));
+        C[0] += wk * fmaxf(v.r, 0.0f);
+        C[1] += wk * fmaxf(v.g, 0.0f);
+        C[2] += wk * fmaxf(v.b, 0.0f);
+        tau += (double)sd;
     }
+    if (k_first) *k_first = first;
+    if (k_last) *k_last = last;
+    if (STORE) *count = stored;
 }
 
-// ------------------------------------------------------------------ kernel
+__device__ inline void sh_basis_all(const float d[3], float y[9]) {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) y[l] = sh_basis_at(l, d[0], d[1], d[2]);
+}
 
-template <int DT, int MODE>
-__global__ __launch_bounds__(kThreads) void render_kernel(GridDev g, RenderArgs a) {
-    constexpr bool FWD = MODE == MODE_FWD || MODE == MODE_TRAIN;
-    constexpr bool BWD = MODE == MODE_BWD || MODE == MODE_TRAIN;
-    constexpr int kList = MODE == MODE_TRAIN ? kRaysPerBlock * kMaxChunks : 1;
-    __shared__ int list_k0[kList];
-    __shared__ unsigned long long list_mask[kList];
+// ------------------------------------------------------------------ kernels
+
+template <int DT, bool STORE>
+__global__ __launch_bounds__(kThreads) void render_fwd_kernel(GridDev g, RenderArgs a) {
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    float o[3], d[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = a.rays_o[3 * ray + i];
+        d[i] = a.rays_d[3 * ray + i];
+    }
+    RayGeom r;
+    const int n = ray_setup(g, o, d, r);
+    float y[9];
+    sh_basis_all(d, y);
+    CornerCache cc;
+    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+    float C[3];
+    double tau;
+    if (STORE) {
+        const int64_t base = ray * a.st_cap;
+        march_forward<DT, true>(g, r, n, y, cc, C, tau, nullptr, nullptr, a.st_count + ray,
+                                a.st_kidx + base, a.st_vals + base, a.st_cap);
+    } else {
+        march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
+    }
+    const float T_final = expf(-(float)tau);
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) a.rgb_out[3 * ray + c3] = C[c3] + T_final * a.bg[c3];
+    if (a.tau_out) a.tau_out[ray] = (float)tau;
+}
+
+// Backward (MODE_BWD) and fused training (MODE_TRAIN).  Every lane of a
+// block stays until its wave is done (the queue drains need all 64 lanes).
+// With STATE (MODE_BWD), a ray whose occupied samples were all stored by the
+// forward pass replays them from the state (index loads only, no record
+// gathers or interpolation); a ray with more than st_cap samples replays by
+// traversal and recomputation.
+template <int DT, int MODE, bool STATE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+void render_bwd_kernel(GridDev g, RenderArgs a) {
+    __shared__ int q_count[kWavesPerBlock];
+    __shared__ int q_id[kWavesPerBlock * kQCap];
+    __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
+    __shared__ float q_v[kWavesPerBlock * 4 * kQCap];
+    __shared__ float q_y[kWavesPerBlock * kWave * 9];
     __shared__ double blk_loss;
     __shared__ unsigned blk_done;
 
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
-    if (MODE == MODE_TRAIN) {
-        if (threadIdx.x == 0) {
-            blk_loss = 0.0;
-            blk_done = 0u;
-        }
-        __syncthreads();
+    const int wid = threadIdx.x / kWave;
+    const int L = lane_id();
+    if (threadIdx.x == 0) {
+        blk_loss = 0.0;
+        blk_done = 0u;
     }
-    const int wid = uni((int)(threadIdx.x / kWave));
-    const int64_t ray = (int64_t)blk * kRaysPerBlock + wid;
-    if (ray >= a.n_rays) return;  // the whole wave
+    if (L == 0) q_count[wid] = 0;
+    __syncthreads();
+    Queue qu;
+    qu.count = q_count + wid;
+    qu.id = q_id + wid * kQCap;
+    qu.src = q_src + wid * kQCap;
+    qu.v = q_v + wid * 4 * kQCap;
+    qu.y = q_y + wid * kWave * 9;
 
-    float o[3], d[3];
-    load_ray(a.rays_o, a.rays_d, ray, o, d);
+    const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
+    const bool live = ray < a.n_rays;
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            o[i] = a.rays_o[3 * ray + i];
+            d[i] = a.rays_d[3 * ray + i];
+        }
+    }
     RayGeom r;
-    const int n = ray_setup(g, o, d, r);
-    const Lane ln = lane_role(d);
+    const int n = live ? ray_setup(g, o, d, r) : 0;
+    // the lane's SH basis lives in the queue's table (read when a corner is
+    // projected and when the wave drains the queue)
+    float *y = qu.y + L * 9;
+    sh_basis_all(d, y);
 
     CornerCache cc;
     cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
-    float acc[8];
+    Q4 acc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+    for (int c = 0; c < 8; ++c) acc[c] = q4_zero();
 
-    // optical depth in FP64: transmittance is exp(-tau) in both passes, so
-    // its error stays at one float rounding of tau instead of growing with the
-    // number of samples
     double tau = 0.0;
     float gr[3] = {0.f, 0.f, 0.f};
-    int n_list = 0;
-    bool overflow = false;
-    ChunkList list;
-    list.k0 = list_k0 + (MODE == MODE_TRAIN ? wid * kMaxChunks : 0);
-    list.mask = list_mask + (MODE == MODE_TRAIN ? wid * kMaxChunks : 0);
-
-    // ------------------------------------------------------------ forward
-    if (FWD) {
-        float Crow;
-        march_forward<DT, MODE == MODE_TRAIN>(g, r, n, ln, cc, Crow, tau, list, n_list, overflow);
-        const float T_final = expf(-(float)tau);
+    int k_hi = n - 1, k_lo = 0;
+    if (MODE == MODE_TRAIN) {
         float C[3];
-#pragma unroll
-        for (int c3 = 0; c3 < 3; ++c3) C[c3] = lane_f(Crow, 16 * c3) + T_final * a.bg[c3];
-        if (ln.L == 0) {
-            if (MODE == MODE_FWD || a.rgb_out) {
-#pragma unroll
-                for (int c3 = 0; c3 < 3; ++c3) a.rgb_out[3 * ray + c3] = C[c3];
-            }
-            if (MODE == MODE_FWD && a.tau_out) a.tau_out[ray] = (float)tau;
-        }
-        if (MODE == MODE_TRAIN) {
-            float l2 = 0.0f;
+        int k_first, k_last;
+        march_forward<DT>(g, r, n, y, cc, C, tau, &k_first, &k_last);
+        k_lo = k_first;
+        k_hi = k_last;
+        const float T_final = expf(-(float)tau);
+        double l2 = 0.0;
+        if (live) {
 #pragma unroll
             for (int c3 = 0; c3 < 3; ++c3) {
-                const float diff = C[c3] - uni(a.target[3 * ray + c3]);
+                const float Cc = C[c3] + T_final * a.bg[c3];
+                if (a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
+                const float diff = Cc - a.target[3 * ray + c3];
                 gr[c3] = 2.0f * a.loss_scale * diff;
-                l2 += diff * diff;
-            }
-            // block sum in LDS; the block's last live wave adds it to the total
-            if (ln.L == 0) {
-                atomicAdd(&blk_loss, (double)a.loss_scale * (double)l2);
-                __threadfence_block();
-                const int64_t left = a.n_rays - (int64_t)blk * kRaysPerBlock;
-                const unsigned live = left < kRaysPerBlock ? (unsigned)left : (unsigned)kRaysPerBlock;
-                if (atomicAdd(&blk_done, 1u) == live - 1u) {
-                    __threadfence_block();
-                    unsafeAtomicAdd(a.loss_sum, atomicAdd(&blk_loss, 0.0));
-                }
+                l2 += (double)(diff * diff);
             }
         }
+        // block sum of the loss: wave sums in LDS, the last wave adds it to the total
+        double wl = (double)a.loss_scale * l2;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) wl += __shfl_xor(wl, m);
+        if (L == 0) {
+            atomicAdd(&blk_loss, wl);
+            __threadfence_block();
+            if (atomicAdd(&blk_done, 1u) == (unsigned)kWavesPerBlock - 1u) {
+                __threadfence_block();
+                const double tot = atomicAdd(&blk_loss, 0.0);
+                if (tot != 0.0) unsafeAtomicAdd(a.loss_sum, tot);
+            }
+        }
+    } else if (live) {
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) gr[c3] = a.grad_rgb[3 * ray + c3];
+        tau = (double)a.tau_in[ray];
     }
 
-    // ------------------------------------------------------------ backward
-    if (BWD) {
-        if (MODE == MODE_BWD) {
-#pragma unroll
-            for (int c3 = 0; c3 < 3; ++c3) gr[c3] = uni(a.grad_rgb[3 * ray + c3]);
-            tau = (double)uni(a.tau_in[ray]);
-        }
-        __builtin_amdgcn_wave_barrier();
-        double tau_after = tau;
-        float T_after = expf(-(float)tau_after);
-        float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]);
-        // this row's colour gradient (0 on the density row)
-        const float grow = ln.row == 0 ? gr[0] : (ln.row == 1 ? gr[1] : (ln.row == 2 ? gr[2] : 0.0f));
-        // the cache may hold the forward pass's last cell: its corners have
-        // nothing accumulated yet, which is what the backward expects
-        const bool use_list = MODE == MODE_TRAIN && !overflow;
-        int li = n_list - 1;  // list cursor (fused kernel)
-        int k = n - 1;        // sample cursor (replay by traversal)
-        while (use_list ? li >= 0 : k >= 0) {
-            int k0;
-            uint64_t mask;
-            Sample s;
-            if (use_list) {
-                k0 = uni(list.k0[li]);
-                const unsigned long long mk = list.mask[li];
-                mask = ((uint64_t)(uint32_t)uni((int)(uint32_t)(mk >> 32)) << 32) |
-                       (uint64_t)(uint32_t)uni((int)(uint32_t)mk);
-                --li;
-                place_chunk<false>(g, r, n, k0, ln.L, s);
-            } else {
-                int m;
-                if (brick_skip<false>(g, r, k, &m)) {
-                    k -= m + 1;
-                    continue;
+    double tau_after = tau;
+    float T_after = expf(-(float)tau_after);
+    float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]);
+    // the cache may hold the forward pass's last cell: its corners have
+    // nothing accumulated yet, which is what the backward expects
+    Cursor cur{k_hi, 0, 0u};
+    bool active = live && n > 0 && k_lo <= k_hi;
+    // stored samples of this ray (STATE): replayed from index j down to 0
+    bool stored = false;
+    int j = -1;
+    int64_t st_base = 0;
+    if (STATE && live) {
+        const int cnt = a.st_count[ray];
+        stored = cnt <= a.st_cap;
+        j = cnt - 1;
+        st_base = ray * a.st_cap;
+        if (stored && cnt == 0) active = false;
+    }
+    while (__any(active)) {
+        if (active) {
+            int k;
+            Q4 vs = q4_zero();
+            if (STATE && stored) {
+                k = -1;
+                if (j >= 0) {
+                    k = a.st_kidx[st_base + j];
+                    const float4 t = a.st_vals[st_base + j];
+                    vs = Q4{t.x, t.y, t.z, t.w};
+                    --j;
                 }
-                k0 = k - (kChunk - 1);
-                mask = place_chunk<true>(g, r, n, k0, ln.L, s);
-                k -= kChunk;
+            } else {
+                k = next_backward(g, r, n, k_lo, cur);
             }
-            while (mask) {
-                const int i = 63 - __builtin_clzll(mask);
-                mask &= ~(1ull << i);
-                const USample u = take_sample(s, i);
-                move_to<DT, true>(g, cc, u.cell, acc, a.grad, a.touched, ln);
-                float v = 0.0f;
+            if (k < 0) {
+                if (cc.cell[0] >= 0) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) v += u.w[c] * cc.q[c];
-                const float sigma_pre = lane_f(v, kSigmaLane);
-                const float sd = fmaxf(sigma_pre, 0.0f) * u.delta;
+                    for (int c = 0; c < 8; ++c)
+                        if (cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
+                }
+                active = false;
+            } else {
+                const Sample s = sample_at(g, r, k);
+                move_to<DT, true>(g, cc, s.cell, acc, qu, y, !(STATE && stored));
+                float w[8];
+                corner_weights(s.f, w);
+                const Q4 v = (STATE && stored) ? vs : interpolate(cc, w);
+                const float sd = fmaxf(v.s, 0.0f) * s.delta;
                 const double tau_before = fmax(tau_after - (double)sd, 0.0);
                 const float T_before = expf(-(float)tau_before);
                 const float wk = T_before * (-expm1f(-sd));
-                // d(colour . grad_rgb) / d(sigma) needs all three channels
-                const float t = grow * fmaxf(v, 0.0f);
-                const float gc = (lane_f(t, 0) + lane_f(t, 16)) + lane_f(t, 32);
-                const float dsig = sigma_pre > 0.0f ? u.delta * (T_after * gc - gR) : 0.0f;
-                const float g_row = ln.row < 3 ? (v > 0.0f ? wk * grow : 0.0f) : dsig;
+                const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) +
+                                 gr[2] * fmaxf(v.b, 0.0f);
+                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) : 0.0f;
+                const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
+                const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
+                const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] += u.w[c] * g_row;
+                for (int c = 0; c < 8; ++c) {
+                    acc[c].s += w[c] * dsig;
+                    acc[c].r += w[c] * g_r;
+                    acc[c].g += w[c] * g_g;
+                    acc[c].b += w[c] * g_b;
+                }
                 gR += wk * gc;
                 tau_after = tau_before;
                 T_after = T_before;
             }
         }
-        if (cc.cell[0] >= 0) flush(a.grad, a.touched, cc, acc, ln, 0xffu);
+        drain(qu, a.grad, a.touched);
     }
 }
 
@@ -623,7 +717,7 @@ __device__ inline void camera_ray(const plx_view &v, int px, int py, float o[3],
     }
 }
 
-constexpr int kTileW = 2, kTileH = 2;  // pixels per tile = rays per block
+constexpr int kTileW = 16, kTileH = 16;  // pixels per tile = rays per block
 
 struct ViewsArgs {
     const GridDev *scenes;
@@ -637,61 +731,47 @@ struct ViewsArgs {
 };
 
 // Persistent tile queue over all pixels of all views of the launch: each block
-// takes the next 2x2-pixel tile, finds its view, generates the rays of its
-// pixels (one per wave) and runs the same forward march as plx_render_fwd.  A
+// takes the next 16x16-pixel tile, finds its view, generates the rays of its
+// pixels (one per lane) and runs the same forward march as plx_render_fwd.  A
 // pixel's colour depends only on its own ray and scene, never on the rest of
 // the batch.
 template <int DT>
 __global__ __launch_bounds__(kThreads) void views_kernel(ViewsArgs a) {
     __shared__ long long tile_sh;
-    const int wid = uni((int)(threadIdx.x / kWave));
     while (true) {
         if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(a.counter, 1ull);
         __syncthreads();
-        const int64_t tile = uni64(tile_sh);
+        const int64_t tile = tile_sh;
         __syncthreads();
         if (tile >= a.n_tiles) break;
         int lo = 0, hi = a.n_views - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (uni64(a.tile_start[mid]) <= tile) lo = mid;
+            if (a.tile_start[mid] <= tile) lo = mid;
             else hi = mid - 1;
         }
         const plx_view &v = a.views[lo];
-        const int width = uni(v.width), height = uni(v.height);
-        const int64_t tl = tile - uni64(a.tile_start[lo]);
-        const int tpr = (width + kTileW - 1) / kTileW;
-        const int px = (int)(tl % tpr) * kTileW + (wid % kTileW);
-        const int py = (int)(tl / tpr) * kTileH + (wid / kTileW);
-        if (px < width && py < height) {
-            const GridDev g = uniform_grid(a.scenes[uni(v.scene)]);
+        const int64_t tl = tile - a.tile_start[lo];
+        const int tpr = (v.width + kTileW - 1) / kTileW;
+        const int px = (int)(tl % tpr) * kTileW + (int)(threadIdx.x % kTileW);
+        const int py = (int)(tl / tpr) * kTileH + (int)(threadIdx.x / kTileW);
+        if (px < v.width && py < v.height) {
+            const GridDev g = a.scenes[v.scene];
             float o[3], d[3];
             camera_ray(v, px, py, o, d);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                o[i] = uni(o[i]);
-                d[i] = uni(d[i]);
-            }
             RayGeom r;
             const int n = ray_setup(g, o, d, r);
-            const Lane ln = lane_role(d);
+            float y[9];
+            sh_basis_all(d, y);
             CornerCache cc;
             cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
-            float Crow;
-            double tau;
-            int n_list = 0;
-            bool overflow = false;
-            ChunkList none = {nullptr, nullptr};
-            march_forward<DT, false>(g, r, n, ln, cc, Crow, tau, none, n_list, overflow);
-            const float T_final = expf(-(float)tau);
             float C[3];
+            double tau;
+            march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
+            const float T_final = expf(-(float)tau);
+            float *out = a.rgb_out + 3 * (v.out_offset + (int64_t)py * v.width + px);
 #pragma unroll
-            for (int c3 = 0; c3 < 3; ++c3) C[c3] = lane_f(Crow, 16 * c3) + T_final * a.bg[c3];
-            if (ln.L == 0) {
-                float *out = a.rgb_out + 3 * (uni64(v.out_offset) + (int64_t)py * width + px);
-#pragma unroll
-                for (int c3 = 0; c3 < 3; ++c3) out[c3] = C[c3];
-            }
+            for (int c3 = 0; c3 < 3; ++c3) out[c3] = C[c3] + T_final * a.bg[c3];
         }
     }
 }
@@ -758,16 +838,53 @@ int validate_rays(const float *o, const float *d, int64_t n, const char *fn) {
     return PLX_OK;
 }
 
-template <int MODE>
+template <int MODE, bool STATE = false>
 int launch_render(const plx_grid *grid, RenderArgs &a, hipStream_t s, const char *fn) {
-    const int64_t nb = (a.n_rays + kRaysPerBlock - 1) / kRaysPerBlock;
+    const int64_t nb = (a.n_rays + kThreads - 1) / kThreads;
     if (nb > 0x7ffffff0) return fail(PLX_EINVAL, "%s: too many rays", fn);
     a.n_blocks = (int)nb;
     a.nb8 = round_up8(nb);
     GridDev g = to_dev(grid);
-    PLX_DISPATCH_DT(grid->sh_dtype, DT,
-                    render_kernel<DT, MODE><<<a.nb8, kThreads, 0, s>>>(g, a));
+    if (MODE == MODE_FWD) {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                        render_fwd_kernel<DT, STATE><<<a.nb8, kThreads, 0, s>>>(g, a));
+    } else {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                        render_bwd_kernel<DT, MODE, STATE && MODE == MODE_BWD><<<a.nb8, kThreads, 0, s>>>(g, a));
+    }
     return check_launch(fn);
+}
+
+// Layout of the per-sample state buffer: per-ray counts, then sample indices,
+// then float4 values, each part 256-byte aligned.
+struct StateLayout {
+    int64_t kidx, vals, bytes;
+};
+
+StateLayout state_layout(int64_t n_rays, int32_t cap) {
+    auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
+    StateLayout l;
+    l.kidx = up(n_rays * 4);
+    l.vals = l.kidx + up(n_rays * (int64_t)cap * 4);
+    l.bytes = l.vals + n_rays * (int64_t)cap * 16;
+    return l;
+}
+
+int attach_state(RenderArgs &a, void *state, int64_t state_bytes, int32_t cap, const char *fn) {
+    if (!state) return fail(PLX_EINVAL, "%s: state is NULL", fn);
+    if (cap < 0 || cap > (1 << 20)) return fail(PLX_EINVAL, "%s: cap %d out of range", fn, (int)cap);
+    if (reinterpret_cast<uintptr_t>(state) % 256)
+        return fail(PLX_EINVAL, "%s: state must be 256-byte aligned", fn);
+    const StateLayout l = state_layout(a.n_rays, cap);
+    if (state_bytes < l.bytes)
+        return fail(PLX_EINVAL, "%s: state of %lld bytes, need %lld", fn, (long long)state_bytes,
+                    (long long)l.bytes);
+    char *base = static_cast<char *>(state);
+    a.st_count = reinterpret_cast<int *>(base);
+    a.st_kidx = reinterpret_cast<int *>(base + l.kidx);
+    a.st_vals = reinterpret_cast<float4 *>(base + l.vals);
+    a.st_cap = cap;
+    return PLX_OK;
 }
 
 RenderArgs base_args(const plx_render_opts *opts, const float *o, const float *d, int64_t n) {
@@ -840,6 +957,47 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     return launch_render<MODE_TRAIN>(grid, a, as_stream(stream), fn);
 }
 
+int64_t plx_render_state_bytes(int64_t n_rays, int32_t cap) {
+    if (n_rays < 0 || cap < 0 || cap > (1 << 20)) return 0;
+    return state_layout(n_rays, cap).bytes;
+}
+
+int plx_render_fwd_state(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                         const float *rays_d, int64_t n_rays, float *rgb_out, float *tau_out,
+                         void *state, int64_t state_bytes, int32_t cap, plx_stream stream) {
+    const char *fn = "plx_render_fwd_state";
+    int rc = validate_grid(grid, true, fn);
+    if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
+    if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
+    if (n_rays == 0) return PLX_OK;
+    if (!rgb_out) return fail(PLX_EINVAL, "%s: rgb_out is NULL", fn);
+    RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    if ((rc = attach_state(a, state, state_bytes, cap, fn))) return rc;
+    a.rgb_out = rgb_out;
+    a.tau_out = tau_out;
+    return launch_render<MODE_FWD, true>(grid, a, as_stream(stream), fn);
+}
+
+int plx_render_bwd_state(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                         const float *rays_d, int64_t n_rays, const float *grad_rgb,
+                         const float *tau_fwd, const void *state, int64_t state_bytes, int32_t cap,
+                         float *grad, uint8_t *touched, plx_stream stream) {
+    const char *fn = "plx_render_bwd_state";
+    int rc = validate_grid(grid, true, fn);
+    if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
+    if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
+    if (n_rays == 0) return PLX_OK;
+    if (!grad_rgb || !tau_fwd || !grad || !touched)
+        return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
+    RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    if ((rc = attach_state(a, const_cast<void *>(state), state_bytes, cap, fn))) return rc;
+    a.grad_rgb = grad_rgb;
+    a.tau_in = tau_fwd;
+    a.grad = grad;
+    a.touched = touched;
+    return launch_render<MODE_BWD, true>(grid, a, as_stream(stream), fn);
+}
+
 int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views) {
     if (n_scenes < 1 || n_views < 0) return 0;
     return views_layout(n_scenes, n_views).bytes;
@@ -896,7 +1054,7 @@ int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *v
     va.n_tiles = tiles;
     va.rgb_out = rgb_out;
     for (int i = 0; i < 3; ++i) va.bg[i] = opts->background[i];
-    const int64_t nblk = tiles < 4096 ? tiles : 4096;  // persistent: about 16 blocks per CU
+    const int64_t nblk = tiles < 2048 ? tiles : 2048;  // persistent: 8 blocks per CU
     PLX_DISPATCH_DT(dt, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
     return check_launch(fn);
 }

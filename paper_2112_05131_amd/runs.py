@@ -1,0 +1,198 @@
+"""Multi-step training runs on the seeded synthetic scenes.
+
+coarse_to_fine: the coarse-to-fine schedule of Sec. 3.6 / supplement B.1 at
+  the 256^3 sparse-scene size: a dense 64^3 grid with the uniform init is
+  trained on 5000-ray batches drawn from all pixels of 100 cameras, pruned at
+  density 5 (with dilation), upsampled to 256^3 and trained further.  Reports
+  the time per step of each stage, the prune/upsample times and voxel counts,
+  and the held-out PSNR after each stage.
+
+precision_drift: the same training (same init, same batch sequence) with the
+  SH coefficients stored as FP32, BF16 and FP16 (FP32 density, master
+  records, optimiser state and accumulation in all three) on the 512^3 / 5%
+  scene with 1M-ray batches; reports, after the given number of steps, the
+  held-out PSNR of each grid against the ground truth and the per-pixel
+  difference of the 16-bit runs from the FP32 run.
+
+Host code only chooses the schedule; every step is the library's fused
+render/MSE/backward, TV and sparse RMSProp.
+
+    python -m paper_2112_05131_amd.runs coarse_to_fine
+    python -m paper_2112_05131_amd.runs drift --steps 2000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+import synth
+
+from . import binding as B
+from .grid import Grid
+from .train import RaySampler, TrainConfig, Trainer
+
+
+def render_rays(grid: Grid, o: torch.Tensor, d: torch.Tensor, bg=(1.0, 1.0, 1.0),
+                chunk: int = 1 << 22) -> torch.Tensor:
+    out = torch.empty(o.shape[0], 3, dtype=torch.float32, device=o.device)
+    for s in range(0, o.shape[0], chunk):
+        B.plx_render_fwd(grid.desc(), o[s:s + chunk], d[s:s + chunk], out[s:s + chunk], None, bg)
+    return out
+
+
+def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
+    mse = torch.mean((a.double() - b.double()) ** 2).item()
+    return float("inf") if mse == 0 else -10.0 * math.log10(mse)
+
+
+def _camera_set(n_cams: int, width: int, height: int, seed: int, device):
+    """All rays of n_cams cameras, each camera's pixels in Morton order (so
+    that a sorted batch is spatially coherent)."""
+    poses = synth.sphere_poses(n_cams, seed=seed)
+    o, d = synth.all_camera_rays(poses, width, height, device=device)
+    npix = width * height
+    pix = torch.arange(npix, device=device)
+    order = torch.argsort(synth.scenes.morton2(pix % width, pix // width))
+    idx = (torch.arange(n_cams, device=device)[:, None] * npix + order[None, :]).reshape(-1)
+    return o[idx].contiguous(), d[idx].contiguous()
+
+
+def _timed_steps(trainer: Trainer, sampler: RaySampler, steps: int) -> float:
+    """Runs `steps` training steps; returns the mean ms per step (device
+    events around the steps, batch gathers included)."""
+    if steps <= 0:
+        return 0.0
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        trainer.step(*sampler.next_batch())
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def coarse_to_fine(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 5000,
+                   gt_reso=(256, 256, 256), occupancy: float = 0.10, n_blobs: int = 32,
+                   coarse=(64, 64, 64), prune_sigma: float = 5.0, n_cams: int = 100,
+                   width: int = 800, height: int = 800, seed: int = 1, log=print) -> dict:
+    dev = torch.device("cuda")
+    t0 = time.time()
+    gt = synth.blob_scene(gt_reso, n_blobs, occupancy, seed, device=dev)
+    gt_grid = Grid.from_mask(gt.mask, gt_reso, gt.density, gt.sh)
+    del gt
+    o, d = _camera_set(n_cams, width, height, seed, dev)
+    tgt = render_rays(gt_grid, o, d)
+    ho, hd = _camera_set(2, 200, 200, seed + 500, dev)  # held-out views
+    htgt = render_rays(gt_grid, ho, hd)
+    del gt_grid
+    torch.cuda.synchronize()
+    log(f"c2 data: {o.shape[0]} training rays, {ho.shape[0]} held-out, {time.time() - t0:.1f}s")
+
+    n = coarse[0] * coarse[1] * coarse[2]
+    mask = torch.ones(n, dtype=torch.uint8, device=dev)
+    grid = Grid.from_mask(mask, coarse, sigma0=0.1, dc=math.sqrt(math.pi))
+    trainer = Trainer(grid, TrainConfig(), seed=seed)
+    sampler = RaySampler(o, d, tgt, batch, seed=seed)
+    _timed_steps(trainer, sampler, 5)  # warm-up
+    ms_coarse = _timed_steps(trainer, sampler, steps_coarse)
+    p_coarse = psnr(render_rays(trainer.grid, ho, hd), htgt)
+    log(f"c2 coarse {coarse}: M={grid.n_vox}, {ms_coarse:.3f} ms/step, held-out PSNR {p_coarse:.2f}")
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pruned_grid, kept, pruned = trainer.grid.prune(prune_sigma)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fine = pruned_grid.upsample(gt_reso)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    trainer.set_grid(fine)
+    del grid, pruned_grid
+    p_up = psnr(render_rays(fine, ho, hd), htgt)
+    ms_fine = _timed_steps(trainer, sampler, steps_fine)
+    p_fine = psnr(render_rays(trainer.grid, ho, hd), htgt)
+    log(f"c2 fine {tuple(gt_reso)}: M={fine.n_vox}, {ms_fine:.3f} ms/step, PSNR after upsample "
+        f"{p_up:.2f}, after training {p_fine:.2f}")
+    return {
+        "scene": f"{gt_reso[0]}^3 blobs at {occupancy:.0%} occupancy, {n_cams} cameras {width}x{height}",
+        "batch_rays": batch,
+        "coarse": {"reso": list(coarse), "n_vox": n, "steps": steps_coarse,
+                   "ms_per_step": round(ms_coarse, 4), "psnr_heldout": round(p_coarse, 3)},
+        "prune": {"sigma_thresh": prune_sigma, "kept": kept, "pruned": pruned,
+                  "ms": round((t2 - t1) * 1e3, 3)},
+        "upsample": {"reso": list(gt_reso), "n_vox": fine.n_vox, "ms": round((t3 - t2) * 1e3, 3),
+                     "psnr_heldout": round(p_up, 3)},
+        "fine": {"steps": steps_fine, "ms_per_step": round(ms_fine, 4),
+                 "psnr_heldout": round(p_fine, 3)},
+    }
+
+
+def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512),
+                    occupancy: float = 0.05, n_blobs: int = 32, n_cams: int = 100,
+                    width: int = 800, height: int = 800, seed: int = 2, log=print) -> dict:
+    dev = torch.device("cuda")
+    gt = synth.blob_scene(reso, n_blobs, occupancy, seed, device=dev)
+    gt_grid = Grid.from_mask(gt.mask, reso, gt.density, gt.sh)
+    o, d = _camera_set(n_cams, width, height, seed, dev)
+    tgt = render_rays(gt_grid, o, d)
+    ho, hd = _camera_set(10, 200, 200, seed + 500, dev)  # 10 held-out poses
+    htgt = render_rays(gt_grid, ho, hd)
+    del gt_grid
+    # the trained grids start from the ground-truth occupancy with perturbed values
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 1000)
+    dens = gt.density * (0.5 + torch.rand(gt.n_vox, device=dev, generator=gen))
+    sh = gt.sh + 0.05 * torch.randn(gt.n_vox, 27, device=dev, generator=gen)
+    out = {"scene": f"{reso[0]}^3 blobs at {occupancy:.0%} occupancy", "steps": steps,
+           "batch_rays": batch, "heldout": "10 poses at 200x200", "runs": {}}
+    renders = {}
+    for name in ("f32", "bf16", "f16"):
+        grid = Grid.from_mask(gt.mask, reso, dens, sh, sh_dtype=B.DTYPES[name])
+        trainer = Trainer(grid, TrainConfig(), seed=seed)
+        sampler = RaySampler(o, d, tgt, batch, seed=seed)
+        p0 = psnr(render_rays(grid, ho, hd), htgt)
+        t0 = time.perf_counter()
+        ms = _timed_steps(trainer, sampler, steps)
+        wall = time.perf_counter() - t0
+        img = render_rays(grid, ho, hd)
+        renders[name] = img
+        loss = trainer.loss_sum.item() / max(steps, 1)
+        out["runs"][name] = {"psnr_heldout_init": round(p0, 3), "psnr_heldout": round(psnr(img, htgt), 3),
+                             "ms_per_step": round(ms, 4), "mean_train_loss": loss,
+                             "wall_s": round(wall, 1)}
+        log(f"drift {name}: PSNR {p0:.2f} -> {out['runs'][name]['psnr_heldout']:.2f}, "
+            f"{ms:.3f} ms/step")
+        del grid, trainer, sampler
+        torch.cuda.empty_cache()
+    for name in ("bf16", "f16"):
+        diff = (renders[name] - renders["f32"]).abs()
+        out["runs"][name]["vs_f32"] = {"psnr": round(psnr(renders[name], renders["f32"]), 3),
+                                       "max_abs": float(diff.max()), "mean_abs": float(diff.mean()),
+                                       "p99_abs": float(torch.quantile(diff.flatten()[::7], 0.99))}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("run", choices=["coarse_to_fine", "drift"])
+    ap.add_argument("--steps", type=int, default=None)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.run == "coarse_to_fine":
+        s = args.steps or 300
+        res = coarse_to_fine(steps_coarse=s, steps_fine=s, log=log)
+    else:
+        res = precision_drift(steps=args.steps or 2000, log=log)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

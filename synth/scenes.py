@@ -188,7 +188,7 @@ def all_camera_rays(poses: torch.Tensor, width: int, height: int, fov_deg=45.0, 
     return torch.cat(os_), torch.cat(ds_)
 
 
-def _morton2(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+def morton2(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     """Interleaves the bits of two non-negative int64 tensors (< 2^16)."""
     def spread(v):
         v = v & 0xFFFF
@@ -214,7 +214,7 @@ def sampled_camera_rays(poses: torch.Tensor, width: int, height: int, n: int, se
     ids = ids.to(device)
     if coherent:
         cam_, pix_ = ids // npix, ids % npix
-        key = cam_ * (1 << 32) + _morton2(pix_ % width, pix_ // width)
+        key = cam_ * (1 << 32) + morton2(pix_ % width, pix_ // width)
         ids = ids[torch.argsort(key)]
     cam = ids // npix
     pix = ids % npix

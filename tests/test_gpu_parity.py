@@ -198,6 +198,52 @@ def test_backward_matches_oracle(case):
     assert torch.all(grad[:, 27] == 0) and torch.all(grad[:, 29:] == 0)
 
 
+@pytest.mark.parametrize("cap", [4096, 5, 0])
+def test_backward_from_stored_state_matches_oracle(cap):
+    """Stored-state backward: every ray's samples stored (cap 4096), most rays
+    over the cap (5: they fall back to recomputation), none stored (0)."""
+    say("bwd state", cap)
+    sv = synth.dense_random((29, 23, 31), seed=21, occupancy=0.35, ho_scale=0.3)
+    og, gg = make_pair(sv)
+    o, d = synth.random_rays(4001, seed=22)
+    bg = (0.1, 0.8, 0.4)
+    n = o.shape[0]
+    G = torch.from_numpy(np.random.default_rng(23).normal(size=(n, 3))).float()
+    rgb = torch.empty(n, 3, device="cuda")
+    tau = torch.empty(n, device="cuda")
+    state = torch.empty(B.plx_render_state_bytes(n, cap), dtype=torch.uint8, device="cuda")
+    B.plx_render_fwd_state(gg.desc(), o.cuda(), d.cuda(), rgb, tau, state, cap, bg)
+    # the forward outputs equal plx_render_fwd's bit for bit
+    rgb2, tau2 = gpu_render(gg, o, d, bg)
+    assert np.array_equal(rgb.cpu().numpy(), rgb2) and np.array_equal(tau.cpu().numpy(), tau2)
+    # stored counts are the oracle's occupied-sample counts
+    counts = state[:4 * n].view(torch.int32).cpu().numpy()
+    idx = og.index.reshape(tuple(og.reso)) >= 0
+
+    def n_occupied(i):
+        # samples whose lower-corner cell has a non-NULL corner
+        c = O.trace_ray(og, o[i].numpy(), d[i].numpy())["cell"]
+        occ = np.zeros(c.shape[0], bool)
+        for dx in (0, 1):
+            for dy in (0, 1):
+                for dz in (0, 1):
+                    occ |= idx[c[:, 0] + dx, c[:, 1] + dy, c[:, 2] + dz]
+        return int(occ.sum())
+
+    ref_counts = np.array([n_occupied(i) for i in range(0, n, 40)])
+    assert np.array_equal(counts[::40], ref_counts)
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
+    B.plx_render_bwd_state(gg.desc(), o.cuda(), d.cuda(), G.cuda(), tau, state, cap, grad, touched, bg)
+    torch.cuda.synchronize()
+    if cap == 5:
+        assert (counts > cap).sum() > n // 4 and (counts <= cap).sum() > n // 4
+    gd, gs, t_ref = O.render_bwd(og, o.numpy(), d.numpy(), G.double().numpy(), bg)
+    assert_touched_equal(touched, t_ref, f"bwd state {cap}")
+    assert_grads_close(grad, gd, gs, f"bwd state {cap}",
+                       grad_mass(og, o.numpy(), d.numpy(), G.double().numpy(), bg))
+
+
 def test_autograd_function_matches_oracle():
     say("autograd")
     sv = synth.dense_random((12, 12, 12), seed=31, occupancy=0.7, ho_scale=0.2)

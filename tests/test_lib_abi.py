@@ -140,3 +140,33 @@ def test_empty_work_is_a_no_op_without_device():
     g0 = _grid_desc(n_vox=0, data=None)
     assert L.plx_rmsprop_step(ctypes.byref(g0), None, None, None, None, 0.1, 0.1, 0.95, 1e-8,
                               None) == B.PLX_OK
+
+
+def test_state_buffer_layout_and_validation():
+    L = B.lib()
+    # layout: counts, indices, float4 values, each 256-byte aligned
+    n, cap = 1000, 7
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert B.plx_render_state_bytes(n, cap) == up(4 * n) + up(4 * n * cap) + 16 * n * cap
+    assert B.plx_render_state_bytes(n, 0) == up(4 * n)
+    assert B.plx_render_state_bytes(-1, 4) == 0 and B.plx_render_state_bytes(4, -1) == 0
+    g = _grid_desc()
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    o, d, rgb = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000), ctypes.c_void_p(0x60000)
+    need = B.plx_render_state_bytes(4, 3)
+    # too small, misaligned, NULL, cap out of range: rejected before any launch
+    for state, nbytes, cap, needle in [(0x100000, need - 1, 3, "need"),
+                                       (0x100010, need, 3, "aligned"),
+                                       (None, need, 3, "NULL"),
+                                       (0x100000, need, -1, "cap")]:
+        rc = L.plx_render_fwd_state(ctypes.byref(g), ctypes.byref(opts), o, d, 4, rgb, None,
+                                    ctypes.c_void_p(state) if state else None, nbytes, cap, None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+        rc = L.plx_render_bwd_state(ctypes.byref(g), ctypes.byref(opts), o, d, 4,
+                                    ctypes.c_void_p(0x70000), ctypes.c_void_p(0x80000),
+                                    ctypes.c_void_p(state) if state else None, nbytes, cap,
+                                    ctypes.c_void_p(0x90000), ctypes.c_void_p(0xa0000), None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+    # zero rays: no-op
+    assert L.plx_render_fwd_state(ctypes.byref(g), ctypes.byref(opts), None, None, 0, None, None,
+                                  None, 0, 3, None) == B.PLX_OK
