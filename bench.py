@@ -3,15 +3,18 @@
 Workload (the differentiation/scale configuration): a 512^3 sparse grid at 5%
 occupancy (6.71M voxels, FP32 records) built from 32 seeded Gaussian density
 blobs, 100 cameras on the radius-2 sphere at 800x800, and 1M-ray batches drawn
-uniformly from all their pixels; targets are renders of the ground-truth grid.
-The trained grid has the same occupancy with perturbed values.  One step =
-fused render + MSE + backward over the batch, TV on a random contiguous 1%
-segment of the cells, and sparse RMSProp on the active voxels.
+uniformly from all their pixels (listed in camera / Morton-pixel order; the
+same rays shuffled are timed too); targets are renders of the ground-truth
+grid.  The trained grid has the same occupancy with perturbed values.  One
+step = fused render + MSE + backward over the batch, TV on a random
+contiguous 1% segment of the cells, and sparse RMSProp on the active voxels.
 
 Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
 (render_train, algorithmic bytes from the library's work counters over its
-HIP-event duration) and the FP64 oracle timed on a bounded sample of the same
-workload on the host cores.
+HIP-event duration), the same step with BF16/FP16 SH storage and with
+shuffled rays, separate forward/backward with and without stored per-sample
+state, the serving latency leg, and the FP64 oracle timed on a bounded sample
+of the same workload on the host cores.
 """
 import argparse
 import json
@@ -107,7 +110,7 @@ def time_steps(trainer, batches, warmup, steps):
 
 def work_counters(grid, batch):
     o, d, _ = batch
-    cm = torch.zeros(B.plx_occ_words(grid.reso), dtype=torch.int32, device="cuda")
+    cm = torch.zeros((grid.n_cells + 31) // 32, dtype=torch.int32, device="cuda")
     vm = torch.zeros((grid.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
     return B.plx_render_stats(grid.desc(), o, d, cm, vm)
 

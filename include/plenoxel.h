@@ -78,7 +78,7 @@ typedef struct plx_grid {
     int64_t n_vox;         /* number of occupied voxels M */
     const int32_t *index;  /* device [Nx*Ny*Nz] */
     void *data;            /* device [M] records */
-    const uint32_t *occ;   /* device [plx_occ_words(reso)] */
+    const uint32_t *occ;   /* device, plx_occ_bytes(reso) bytes */
 } plx_grid;
 
 /* Options of the render calls. */
@@ -99,16 +99,20 @@ const char *plx_version(void);
 /* Number of device bytes of one voxel record of dtype (128 or 64), or 0. */
 int64_t plx_record_bytes(int32_t sh_dtype);
 
-/* Number of uint32 words of a cell bitmap of a grid (one bit per cell). */
+/* Number of uint32 words of the cell bitmap of a grid: 16 words (512 bits)
+ * per brick of 8x8x8 cells.  Cells are indexed by their lower corner,
+ * 0..N-2 per axis; there are Ba = ceil((Na-1)/8) bricks per axis, brick
+ * (a,b,c) has number (a*By + b)*Bz + c, and cell (i,j,k) is bit
+ * (i%8)*64 + (j%8)*8 + k%8 of the 512 bits of brick (i/8, j/8, k/8) (bit n of
+ * a brick is bit n%32 of its word n/32).  Bits of cells outside the lattice
+ * are 0. */
 int64_t plx_occ_words(const int32_t reso[3]);
 
 /* Bytes of the occupancy structure of a grid: the cell bitmap
  * (plx_occ_words words at offset 0) followed, at byte offset
- * plx_occ_brick_offset, by one byte per brick of 8x8x8 cells (cells are
- * indexed by their lower corner, 0..N-2 per axis; Ba = ceil((Na-1)/8) bricks
- * per axis, brick (a,b,c) at (a*By + b)*Bz + c): the Chebyshev distance, in
- * bricks, to the nearest brick holding an occupied cell (0 for such a brick),
- * capped at PLX_BRICK_DIST_CAP. */
+ * plx_occ_brick_offset, by one byte per brick (brick order as above): the
+ * Chebyshev distance, in bricks, to the nearest brick holding an occupied
+ * cell (0 for such a brick), capped at PLX_BRICK_DIST_CAP. */
 int64_t plx_occ_bytes(const int32_t reso[3]);
 int64_t plx_occ_brick_offset(const int32_t reso[3]);
 #define PLX_BRICK 8
@@ -158,10 +162,11 @@ int plx_records_unpack(int32_t sh_dtype, int64_t n, const void *records, float *
 int plx_records_convert(int32_t src_dtype, const void *src, int32_t dst_dtype, void *dst,
                         int64_t n, plx_stream stream);
 
-/* Occupancy structure (layout at plx_occ_bytes): bit v of the cell bitmap is
- * set when cell v (lower corner (i,j,k), i < Nx-1, j < Ny-1, k < Nz-1) has
- * at least one non-NULL corner voxel, and each brick gets its distance to the
- * nearest brick with a set bit.  A sample in a cell without that bit reads
+/* Occupancy structure (layout at plx_occ_words / plx_occ_bytes): the bit of
+ * cell (i,j,k) (lower corner, i < Nx-1, j < Ny-1, k < Nz-1) is set when the
+ * cell has at least one non-NULL corner voxel, and each brick gets its
+ * distance to the nearest brick with a set bit.  The bitmap is brick-major so
+ * that the cells a ray crosses inside one brick share one 64-byte line.  A sample in a cell without that bit reads
  * only zeros and adds nothing to colour, transmittance or gradient, so the
  * render kernels skip such samples, and whole boxes of empty bricks, exactly.
  * occ_out: device, plx_occ_bytes(reso) bytes.  Temporary device memory is not
@@ -299,8 +304,8 @@ int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *v
  * counts[0] = samples (all), counts[1] = samples in occupied cells,
  * counts[2] = distinct index entries read (corners of occupied cells),
  * counts[3] = distinct non-NULL voxels read.  cell_mark is device scratch of
- * plx_occ_words(reso) words and vox_mark of ceil(M/32) words; both are
- * cleared by the call.  Synchronising. */
+ * ceil(Nx*Ny*Nz/32) words and vox_mark of ceil(M/32) words; both are cleared
+ * by the call.  Synchronising. */
 int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,
                      int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark,
                      int64_t counts[4], plx_stream stream);

@@ -245,29 +245,34 @@ __global__ void unpack_kernel(int64_t n, const void *rec, float *density, float 
     }
 }
 
-// Cell occupancy bits; one thread per cell, words assembled by ballot.
-__global__ void occupancy_kernel(GridDev g, int64_t ncell, int64_t nwords, uint32_t *occ) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Cell occupancy bits in brick-major order: thread t is bit t of the bitmap,
+// i.e. brick t/512, cell (t%512)/64, (t/8)%8, t%8 inside it; 32-bit words are
+// assembled by ballot.  Cells outside the lattice (partial bricks) get 0.
+__global__ void occupancy_kernel(GridDev g, int64_t nbits, uint32_t *occ) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bit = false;
-    if (v < ncell) {
-        int k = (int)(v % g.nz);
-        int64_t r = v / g.nz;
-        int j = (int)(r % g.ny);
-        int i = (int)(r / g.ny);
+    if (t < nbits) {
+        const int64_t b = t >> 9;
+        const int l = (int)(t & 511);
+        const int bk = (int)(b % g.bz);
+        const int bj = (int)((b / g.bz) % g.by);
+        const int bi = (int)(b / ((int64_t)g.bz * g.by));
+        const int i = bi * PLX_BRICK + (l >> 6), j = bj * PLX_BRICK + ((l >> 3) & 7),
+                  k = bk * PLX_BRICK + (l & 7);
         if (i < g.nx - 1 && j < g.ny - 1 && k < g.nz - 1) {
             const int64_t sy = g.nz, sx = (int64_t)g.ny * g.nz;
-            const int32_t *p = g.index + v;
+            const int32_t *p = g.index + ((int64_t)i * g.ny + j) * g.nz + k;
             // NULL entries are negative, table ids are not: the cell is empty
             // exactly when the AND of all eight entries is negative
             bit = (p[0] & p[1] & p[sy] & p[sy + 1] & p[sx] & p[sx + 1] & p[sx + sy] &
                    p[sx + sy + 1]) >= 0;
         }
     }
-    unsigned long long b = __ballot(bit);
+    const unsigned long long m = __ballot(bit);
     const int lane = threadIdx.x & 63;
-    int64_t w = (v - lane) >> 5;  // first word of this wave
-    if (lane == 0 && w < nwords) occ[w] = (uint32_t)(b & 0xffffffffull);
-    if (lane == 32 && w + 1 < nwords) occ[w + 1] = (uint32_t)(b >> 32);
+    const int64_t w = (t - lane) >> 5;  // first word of this wave
+    if (lane == 0 && (t - lane) < nbits) occ[w] = (uint32_t)(m & 0xffffffffull);
+    if (lane == 32 && (t - lane) + 32 < nbits) occ[w + 1] = (uint32_t)(m >> 32);
 }
 
 // Brick seed: 0 when any cell of the brick has its occupancy bit, else far.
@@ -275,23 +280,8 @@ __global__ void brick_seed_kernel(GridDev g, uint8_t *bd) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nb = (int64_t)g.bx * g.by * g.bz;
     if (b >= nb) return;
-    const int bk = (int)(b % g.bz);
-    const int bj = (int)((b / g.bz) % g.by);
-    const int bi = (int)(b / ((int64_t)g.bz * g.by));
-    const int i1 = min((bi + 1) * PLX_BRICK, g.nx - 1), j1 = min((bj + 1) * PLX_BRICK, g.ny - 1),
-              k0 = bk * PLX_BRICK, k1 = min((bk + 1) * PLX_BRICK, g.nz - 1);
-    bool any = false;
-    for (int i = bi * PLX_BRICK; i < i1 && !any; ++i)
-        for (int j = bj * PLX_BRICK; j < j1 && !any; ++j) {
-            const int64_t row = ((int64_t)i * g.ny + j) * g.nz;
-            for (int k = k0; k < k1; ++k) {
-                const int64_t v = row + k;
-                if ((g.occ[v >> 5] >> (v & 31)) & 1u) {
-                    any = true;
-                    break;
-                }
-            }
-        }
+    uint32_t any = 0u;
+    for (int w = 0; w < 16; ++w) any |= g.occ[b * 16 + w];
     bd[b] = any ? 0 : 255;
 }
 
@@ -542,14 +532,13 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
     if (rc) return rc;
     if (!occ_out) return fail(PLX_EINVAL, "plx_grid_build_occupancy: occ_out is NULL");
     hipStream_t s = as_stream(stream);
-    int64_t ncell = n_cells(grid->reso);
-    int64_t nwords = plx_occ_words(grid->reso);
-    // whole waves, so every word is written by the wave that owns it
-    int64_t nthreads = (ncell + 63) / 64 * 64;
+    // bits are whole bricks of 512, so whole waves: every word is written by
+    // the wave that owns it
+    const int64_t nbits = occ_words(grid->reso) * 32;
     plx_grid gd = *grid;
     gd.occ = occ_out;
     GridDev g = to_dev(&gd);
-    occupancy_kernel<<<blocks_for(nthreads, 256), 256, 0, s>>>(g, ncell, nwords, occ_out);
+    occupancy_kernel<<<blocks_for(nbits, 256), 256, 0, s>>>(g, nbits, occ_out);
     if ((rc = check_launch("plx_grid_build_occupancy"))) return rc;
     uint8_t *bd = reinterpret_cast<uint8_t *>(occ_out) + occ_brick_offset(grid->reso);
     const int64_t nb = n_bricks(grid->reso);

@@ -38,11 +38,12 @@ inline int64_t n_cells(const int32_t r[3]) { return (int64_t)r[0] * r[1] * r[2];
 
 // Bricks of PLX_BRICK^3 cells over the cell lattice 0..N-2 per axis.
 inline int bricks_along(int n) { return (n - 1 + PLX_BRICK - 1) / PLX_BRICK; }
-inline int64_t occ_words(const int32_t r[3]) { return (n_cells(r) + 31) / 32; }
-inline int64_t occ_brick_offset(const int32_t r[3]) { return (occ_words(r) * 4 + 255) / 256 * 256; }
 inline int64_t n_bricks(const int32_t r[3]) {
     return (int64_t)bricks_along(r[0]) * bricks_along(r[1]) * bricks_along(r[2]);
 }
+// Cell bitmap: 512 bits (16 words) per brick, bricks in storage order.
+inline int64_t occ_words(const int32_t r[3]) { return n_bricks(r) * (PLX_BRICK * PLX_BRICK * PLX_BRICK / 32); }
+inline int64_t occ_brick_offset(const int32_t r[3]) { return (occ_words(r) * 4 + 255) / 256 * 256; }
 
 // -------------------------------------------------------- kernel-side grid
 struct GridDev {
@@ -184,8 +185,13 @@ __device__ inline int64_t cell_id(const GridDev &g, const int c[3]) {
     return ((int64_t)c[0] * g.ny + c[1]) * (int64_t)g.nz + c[2];
 }
 
-__device__ inline bool cell_occupied(const GridDev &g, int64_t lin) {
-    return (g.occ[lin >> 5] >> (lin & 31)) & 1u;
+// Occupancy bit of the cell with lower corner c: brick (c/8) holds 512 bits,
+// cell (i,j,k) of a brick at bit (i%8)*64 + (j%8)*8 + k%8, so the cells a ray
+// crosses inside one brick share one 64-byte line.
+__device__ inline bool cell_occupied(const GridDev &g, const int c[3]) {
+    const int64_t b = ((int64_t)(c[0] >> 3) * g.by + (c[1] >> 3)) * g.bz + (c[2] >> 3);
+    const int bit = ((c[0] & 7) << 6) | ((c[1] & 7) << 3) | (c[2] & 7);
+    return (g.occ[b * 16 + (bit >> 5)] >> (bit & 31)) & 1u;
 }
 
 // ----------------------------------------------------------- SH basis

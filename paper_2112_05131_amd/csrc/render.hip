@@ -357,10 +357,46 @@ __device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &
         const int k = k0 + i;
         if (k >= 0 && k < n) {
             const Sample s = sample_at(g, r, k);
-            if (cell_occupied(g, cell_id(g, s.cell))) m |= 1u << i;
+            if (cell_occupied(g, s.cell)) m |= 1u << i;
         }
     }
     return m;
+}
+
+// Brick-level skip.  Returns the distance D of the brick of sample k (0 when
+// it has an occupied cell); for D > 0 also the number of further samples m
+// (in the direction of travel) that certainly stay in the empty box of bricks
+// within D-1 of it.
+// Number of further samples after sample k (in the direction of travel)
+// that certainly stay inside the box of bricks within R of brick b, where
+// sample k lies (at t = t_near + k*step): the box's exit parameter along the
+// ray, less a margin of 5% of a step.
+template <bool FORWARD>
+__device__ __forceinline__ int samples_in_box(const GridDev &g, const RayGeom &r, int k,
+                                              const int b[3], int R) {
+    const int nb[3] = {g.bx, g.by, g.bz};
+    const float t = r.t_near + (float)k * g.step;
+    float t_edge = FORWARD ? __builtin_inff() : -__builtin_inff();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float dg = r.dg[a];
+        if (dg == 0.0f) continue;
+        // box faces on the grid boundary are never crossed by a sample
+        const bool up = (dg > 0.0f) == FORWARD;
+        const int bf = up ? b[a] + R : b[a] - R;
+        if (up ? bf >= nb[a] - 1 : bf <= 0) continue;
+        const float face = (float)((up ? bf + 1 : bf) * PLX_BRICK);
+        const float tf = (face - r.og[a]) / dg;
+        t_edge = FORWARD ? fminf(t_edge, tf) : fmaxf(t_edge, tf);
+    }
+    const float span = FORWARD ? (t_edge - t) : (t - t_edge);
+    float q = span / g.step - kSkipMargin;
+    q = q < (float)kMaxSamples ? q : (float)kMaxSamples;
+    return q > 0.0f ? (int)q : 0;
+}
+
+__device__ __forceinline__ int64_t brick_id(const GridDev &g, const int b[3]) {
+    return ((int64_t)b[0] * g.by + b[1]) * g.bz + b[2];
 }
 
 // Brick-level skip.  Returns the distance D of the brick of sample k (0 when
@@ -371,27 +407,9 @@ template <bool FORWARD>
 __device__ __forceinline__ int brick_skip(const GridDev &g, const RayGeom &r, int k, int *m) {
     const Sample s = sample_at(g, r, k);
     const int b[3] = {s.cell[0] / PLX_BRICK, s.cell[1] / PLX_BRICK, s.cell[2] / PLX_BRICK};
-    const int D = g.bdist[((int64_t)b[0] * g.by + b[1]) * g.bz + b[2]];
+    const int D = g.bdist[brick_id(g, b)];
     if (D == 0) return 0;
-    const int nb[3] = {g.bx, g.by, g.bz};
-    const float t = r.t_near + (float)k * g.step;
-    float t_edge = FORWARD ? __builtin_inff() : -__builtin_inff();
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float dg = r.dg[a];
-        if (dg == 0.0f) continue;
-        // box faces on the grid boundary are never crossed by a sample
-        const bool up = (dg > 0.0f) == FORWARD;
-        const int bf = up ? b[a] + (D - 1) : b[a] - (D - 1);
-        if (up ? bf >= nb[a] - 1 : bf <= 0) continue;
-        const float face = (float)((up ? bf + 1 : bf) * PLX_BRICK);
-        const float tf = (face - r.og[a]) / dg;
-        t_edge = FORWARD ? fminf(t_edge, tf) : fmaxf(t_edge, tf);
-    }
-    const float span = FORWARD ? (t_edge - t) : (t - t_edge);
-    float q = span / g.step - kSkipMargin;
-    q = q < (float)kMaxSamples ? q : (float)kMaxSamples;
-    *m = q > 0.0f ? (int)q : 0;
+    *m = samples_in_box<FORWARD>(g, r, k, b, D - 1);
     return D;
 }
 
@@ -697,6 +715,422 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     }
 }
 
+// ------------------------------------------------------------ brick-binned training
+//
+// plx_render_train runs the batch in brick order.  Rays sampled from many
+// cameras share few voxels with their neighbours in the batch, so a ray-order
+// pass fetches every voxel record (and read-modify-writes every gradient
+// line) about as often as rays cross it.  Here each ray is cut into segments,
+// one per 8^3-cell brick with occupied cells that its samples pass through
+// (a ray crosses a brick at most once: cell indices are monotone along it);
+// the segments are sorted by brick, and the forward and backward passes run
+// one lane per segment in that order, so the lanes of a wave read and update
+// the same few hundred voxels.  Per ray, the segment results compose exactly
+// as the samples do: the colour is sum_s T_in(s) C_s + T_n bg with
+// T_in(s) = exp(-sum_{s'<s} tau_s'), and the backward replay of a segment
+// starts from the optical depth after it and the radiance the ray collects
+// after it (g . R), so every sample sees the same T_k, w_k and R_k.
+
+constexpr int kScanT = 256, kScanI = 16, kScanTile = kScanT * kScanI;
+
+// Exclusive block-wide scan of one int64 per thread; *total gets the sum.
+__device__ int64_t block_scan_excl(int64_t v, int64_t *total) {
+    __shared__ int64_t wsum[kScanT / kWave];
+    const int L = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (L >= o) x += y;
+    }
+    if (L == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanT / kWave; ++i) {
+        if (i < w) before += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kScanT) void count_sum_kernel(const unsigned *c, int64_t n,
+                                                           int64_t *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i)
+        if (base + i < n) s += c[base + i];
+    int64_t tot;
+    block_scan_excl(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanT) void block_offsets_kernel(const int64_t *bsum, int64_t nb,
+                                                               int64_t *boff) {
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanT) {
+        const int64_t b = b0 + threadIdx.x;
+        int64_t tot;
+        const int64_t ex = block_scan_excl(b < nb ? bsum[b] : 0, &tot);
+        if (b < nb) boff[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) boff[nb] = carry;
+}
+
+// out[i] = sum of c[0..i), out[n] = total.
+__global__ __launch_bounds__(kScanT) void count_scan_kernel(const unsigned *c, int64_t n,
+                                                            const int64_t *boff, int64_t *out) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+    unsigned v[kScanI];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i) {
+        v[i] = base + i < n ? c[base + i] : 0u;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t r = boff[blockIdx.x] + block_scan_excl(s, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanI; ++i) {
+        if (base + i < n) out[base + i] = r;
+        r += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = boff[gridDim.x];
+}
+
+__global__ void zero_u32_kernel(unsigned *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+struct BinArgs {
+    const float *rays_o;
+    const float *rays_d;
+    const float *target;
+    float *rgb_out;
+    double *loss_sum;
+    float *grad;
+    uint8_t *touched;
+    int64_t n_rays;
+    int64_t n_seg;
+    float bg[3];
+    float loss_scale;
+    int n_blocks;  // blocks of the launch at hand (rays or segments)
+    int nb8;
+    unsigned *nseg;      // [n_rays] segments of each ray
+    int64_t *seg_off;    // [n_rays + 1] first ray-major slot of each ray
+    unsigned *bcount;    // [n_bricks] segments in each brick
+    unsigned *bcursor;   // [n_bricks] placement cursors
+    int64_t *boff;       // [n_bricks + 1] first brick-major position of each brick
+    int4 *bseg;          // [n_seg] brick-major: ray, first sample, last sample, ray-major slot
+    double *tau_seg;     // [n_seg] ray-major: optical depth of the segment
+    float4 *c_seg;       // [n_seg] ray-major: colour the segment adds (before T_in)
+    double *tau_in;      // [n_seg] ray-major: optical depth before the segment
+    float *gr_after;     // [n_seg] ray-major: g . (radiance collected after the segment)
+    float4 *g_ray;       // [n_rays] dL/dC of each ray
+};
+
+__device__ __forceinline__ void load_ray_lane(const BinArgs &a, int64_t ray, float o[3], float d[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = a.rays_o[3 * ray + i];
+        d[i] = a.rays_d[3 * ray + i];
+    }
+}
+
+// Calls f(brick, first sample, last sample) for every brick with an occupied
+// cell that the ray's samples enter, in ray order; boxes of empty bricks are
+// skipped with the distance field, and inside a brick only the samples near
+// its exit face are placed.
+template <class F>
+__device__ __forceinline__ void walk_bricks(const GridDev &g, const RayGeom &r, int n, F &&f) {
+    int k = 0;
+    while (k < n) {
+        const Sample s = sample_at(g, r, k);
+        const int b[3] = {s.cell[0] / PLX_BRICK, s.cell[1] / PLX_BRICK, s.cell[2] / PLX_BRICK};
+        const int64_t bid = brick_id(g, b);
+        const int D = g.bdist[bid];
+        const int m = samples_in_box<true>(g, r, k, b, D > 0 ? D - 1 : 0);
+        if (D > 0) {
+            k += m + 1;
+            continue;
+        }
+        int ke = m < n - 1 - k ? k + m : n - 1;
+        while (ke + 1 < n) {
+            const Sample s2 = sample_at(g, r, ke + 1);
+            if (s2.cell[0] / PLX_BRICK != b[0] || s2.cell[1] / PLX_BRICK != b[1] ||
+                s2.cell[2] / PLX_BRICK != b[2])
+                break;
+            ++ke;
+        }
+        f(bid, k, ke);
+        k = ke + 1;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void seg_count_kernel(GridDev g, BinArgs a) {
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    float o[3], d[3];
+    load_ray_lane(a, ray, o, d);
+    RayGeom r;
+    const int n = ray_setup(g, o, d, r);
+    unsigned cnt = 0;
+    walk_bricks(g, r, n, [&](int64_t bid, int, int) {
+        ++cnt;
+        atomicAdd(a.bcount + bid, 1u);
+    });
+    a.nseg[ray] = cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a) {
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    float o[3], d[3];
+    load_ray_lane(a, ray, o, d);
+    RayGeom r;
+    const int n = ray_setup(g, o, d, r);
+    int64_t slot = a.seg_off[ray];
+    walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
+        const int64_t pos = a.boff[bid] + atomicAdd(a.bcursor + bid, 1u);
+        a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
+        ++slot;
+    });
+}
+
+// Occupied samples of [k_lo, k_hi] in increasing / decreasing order.
+struct SpanCursor {
+    int k;          // next sample to examine
+    int k0;         // first sample of the current chunk
+    uint32_t mask;  // occupied samples of the chunk not yet returned
+};
+
+__device__ __forceinline__ int span_next_up(const GridDev &g, const RayGeom &r, int n, int k_hi,
+                                            SpanCursor &c) {
+    while (c.mask == 0u) {
+        if (c.k > k_hi) return -1;
+        c.k0 = c.k;
+        c.mask = chunk_bits(g, r, n, c.k);
+        if (k_hi - c.k < kChunk - 1) c.mask &= (2u << (k_hi - c.k)) - 1u;
+        c.k += kChunk;
+    }
+    const int b = __builtin_ctz(c.mask);
+    c.mask &= c.mask - 1u;
+    return c.k0 + b;
+}
+
+__device__ __forceinline__ int span_next_down(const GridDev &g, const RayGeom &r, int n, int k_lo,
+                                              SpanCursor &c) {
+    while (c.mask == 0u) {
+        if (c.k < k_lo) return -1;
+        c.k0 = c.k - (kChunk - 1);
+        c.mask = chunk_bits(g, r, n, c.k0);
+        if (c.k0 < k_lo) c.mask &= ~0u << (k_lo - c.k0);
+        c.k -= kChunk;
+    }
+    const int b = 31 - __builtin_clz(c.mask);
+    c.mask &= ~(1u << b);
+    return c.k0 + b;
+}
+
+// Forward over one segment (transmittance relative to its start).
+template <int DT>
+__global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a) {
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    if (i >= a.n_seg) return;
+    const int4 sg = a.bseg[i];
+    float o[3], d[3];
+    load_ray_lane(a, sg.x, o, d);
+    RayGeom r;
+    const int n = ray_setup(g, o, d, r);
+    float y[9];
+    sh_basis_all(d, y);
+    CornerCache cc;
+    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+    Q4 none[8];
+    Queue noq{};
+    SpanCursor cur{sg.y, 0, 0u};
+    double tau = 0.0;
+    float C[3] = {0.0f, 0.0f, 0.0f};
+    while (true) {
+        const int k = span_next_up(g, r, n, sg.z, cur);
+        if (k < 0) break;
+        const Sample s = sample_at(g, r, k);
+        move_to<DT, false>(g, cc, s.cell, none, noq, y);
+        float w[8];
+        corner_weights(s.f, w);
+        const Q4 v = interpolate(cc, w);
+        const float sd = fmaxf(v.s, 0.0f) * s.delta;
+        const float wk = expf(-(float)tau) * (-expm1f(-sd));
+        C[0] += wk * fmaxf(v.r, 0.0f);
+        C[1] += wk * fmaxf(v.g, 0.0f);
+        C[2] += wk * fmaxf(v.b, 0.0f);
+        tau += (double)sd;
+    }
+    a.tau_seg[sg.w] = tau;
+    a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
+}
+
+// Per ray: composes its segments, the loss and dL/dC = 2 loss_scale (C - target),
+// and for every segment the optical depth before it and g . R after it.
+__global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
+    __shared__ double blk_loss[kWavesPerBlock];
+    const int64_t ray = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    double l2 = 0.0;
+    if (ray < a.n_rays) {
+        const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
+        double tau = 0.0;
+        float C[3] = {0.0f, 0.0f, 0.0f};
+        for (int64_t s = s0; s < s1; ++s) {
+            a.tau_in[s] = tau;
+            const float T = expf(-(float)tau);
+            const float4 c = a.c_seg[s];
+            C[0] += T * c.x;
+            C[1] += T * c.y;
+            C[2] += T * c.z;
+            tau += a.tau_seg[s];
+        }
+        const float T_final = expf(-(float)tau);
+        float gr[3], R[3];
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) {
+            const float Cc = C[c3] + T_final * a.bg[c3];
+            if (a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
+            const float diff = Cc - a.target[3 * ray + c3];
+            gr[c3] = 2.0f * a.loss_scale * diff;
+            l2 += (double)(diff * diff);
+            R[c3] = T_final * a.bg[c3];
+        }
+        a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], 0.0f);
+        for (int64_t s = s1 - 1; s >= s0; --s) {
+            a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
+            const float T = expf(-(float)a.tau_in[s]);
+            const float4 c = a.c_seg[s];
+            R[0] += T * c.x;
+            R[1] += T * c.y;
+            R[2] += T * c.z;
+        }
+    }
+    double wl = (double)a.loss_scale * l2;
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) wl += __shfl_xor(wl, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) blk_loss[threadIdx.x / kWave] = wl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) t += blk_loss[w];
+        if (t != 0.0) unsafeAtomicAdd(a.loss_sum, t);
+    }
+}
+
+// Backward replay of one segment, from its last occupied sample to its first.
+template <int DT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+void seg_bwd_kernel(GridDev g, BinArgs a) {
+    __shared__ int q_count[kWavesPerBlock];
+    __shared__ int q_id[kWavesPerBlock * kQCap];
+    __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
+    __shared__ float q_v[kWavesPerBlock * 4 * kQCap];
+    __shared__ float q_y[kWavesPerBlock * kWave * 9];
+
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int wid = threadIdx.x / kWave;
+    const int L = lane_id();
+    if (L == 0) q_count[wid] = 0;
+    __syncthreads();
+    Queue qu;
+    qu.count = q_count + wid;
+    qu.id = q_id + wid * kQCap;
+    qu.src = q_src + wid * kQCap;
+    qu.v = q_v + wid * 4 * kQCap;
+    qu.y = q_y + wid * kWave * 9;
+
+    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    const bool live = i < a.n_seg;
+    int4 sg = make_int4(0, 0, -1, 0);
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+    if (live) {
+        sg = a.bseg[i];
+        load_ray_lane(a, sg.x, o, d);
+    }
+    RayGeom r;
+    const int n = live ? ray_setup(g, o, d, r) : 0;
+    float *y = qu.y + L * 9;
+    sh_basis_all(d, y);
+
+    CornerCache cc;
+    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+    Q4 acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = q4_zero();
+
+    float gr[3] = {0.f, 0.f, 0.f};
+    double tau_after = 0.0;
+    float gR = 0.0f;
+    if (live) {
+        const float4 gg = a.g_ray[sg.x];
+        gr[0] = gg.x;
+        gr[1] = gg.y;
+        gr[2] = gg.z;
+        tau_after = a.tau_in[sg.w] + a.tau_seg[sg.w];
+        gR = a.gr_after[sg.w];
+    }
+    float T_after = expf(-(float)tau_after);
+    SpanCursor cur{sg.z, 0, 0u};
+    bool active = live && n > 0;
+    while (__any(active)) {
+        if (active) {
+            const int k = span_next_down(g, r, n, sg.y, cur);
+            if (k < 0) {
+                if (cc.cell[0] >= 0) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
+                }
+                active = false;
+            } else {
+                const Sample s = sample_at(g, r, k);
+                move_to<DT, true>(g, cc, s.cell, acc, qu, y);
+                float w[8];
+                corner_weights(s.f, w);
+                const Q4 v = interpolate(cc, w);
+                const float sd = fmaxf(v.s, 0.0f) * s.delta;
+                const double tau_before = fmax(tau_after - (double)sd, 0.0);
+                const float T_before = expf(-(float)tau_before);
+                const float wk = T_before * (-expm1f(-sd));
+                const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) +
+                                 gr[2] * fmaxf(v.b, 0.0f);
+                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) : 0.0f;
+                const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
+                const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
+                const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    acc[c].s += w[c] * dsig;
+                    acc[c].r += w[c] * g_r;
+                    acc[c].g += w[c] * g_g;
+                    acc[c].b += w[c] * g_b;
+                }
+                gR += wk * gc;
+                tau_after = tau_before;
+                T_after = T_before;
+            }
+        }
+        drain(qu, a.grad, a.touched);
+    }
+}
+
 // ------------------------------------------------------------------ novel views
 
 // Pixel-centred pinhole ray of pixel (px, py) of a view, in FP64 with a fixed
@@ -809,7 +1243,7 @@ __global__ void stats_kernel(GridDev g, const float *rays_o, const float *rays_d
         for (int k = 0; k < n; ++k) {
             const Sample s = sample_at(g, r, k);
             const int64_t lin = cell_id(g, s.cell);
-            if (!cell_occupied(g, lin)) continue;
+            if (!cell_occupied(g, s.cell)) continue;
             ++n_occ;
             if (lin == last) continue;
             last = lin;
@@ -887,6 +1321,110 @@ int attach_state(RenderArgs &a, void *state, int64_t state_bytes, int32_t cap, c
     return PLX_OK;
 }
 
+// Exclusive scan of n counts into out[0..n] (out[n] = total).  tmp: 2*nb+1
+// int64 where nb = ceil(n / kScanTile).
+int scan_counts(const unsigned *c, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s,
+                const char *fn) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1 || nb > 0x7fffffff) return fail(PLX_EINVAL, "%s: bad scan size", fn);
+    int64_t *bsum = tmp, *boff = tmp + nb;
+    count_sum_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, bsum);
+    int rc = check_launch(fn);
+    if (rc) return rc;
+    block_offsets_kernel<<<1, kScanT, 0, s>>>(bsum, nb, boff);
+    if ((rc = check_launch(fn))) return rc;
+    count_scan_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, boff, out);
+    return check_launch(fn);
+}
+
+inline int64_t scan_tmp_words(int64_t n) { return 2 * ((n + kScanTile - 1) / kScanTile) + 1; }
+inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+// The brick-binned fused training pass (see the comment above BinArgs).
+int render_train_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
+    const int64_t n_rays = a.n_rays;
+    if (n_rays > 0x7fffffffLL - kThreads) return fail(PLX_EINVAL, "%s: too many rays", fn);
+    GridDev g = to_dev(grid);
+    const int64_t nbk = n_bricks(grid->reso);
+    // per-ray and per-brick temporaries
+    int64_t off = 0;
+    const int64_t o_nseg = off; off += align256(n_rays * 4);
+    const int64_t o_segoff = off; off += align256((n_rays + 1) * 8);
+    const int64_t o_gray = off; off += align256(n_rays * 16);
+    const int64_t o_bcount = off; off += align256(nbk * 4);
+    const int64_t o_bcursor = off; off += align256(nbk * 4);
+    const int64_t o_boff = off; off += align256((nbk + 1) * 8);
+    const int64_t o_scan = off; off += align256((scan_tmp_words(n_rays) + scan_tmp_words(nbk)) * 8);
+    TempBuf t1;
+    int rc = t1.alloc((size_t)off, s);
+    if (rc) return rc;
+    char *base = static_cast<char *>(t1.ptr);
+    a.nseg = reinterpret_cast<unsigned *>(base + o_nseg);
+    a.seg_off = reinterpret_cast<int64_t *>(base + o_segoff);
+    a.g_ray = reinterpret_cast<float4 *>(base + o_gray);
+    a.bcount = reinterpret_cast<unsigned *>(base + o_bcount);
+    a.bcursor = reinterpret_cast<unsigned *>(base + o_bcursor);
+    a.boff = reinterpret_cast<int64_t *>(base + o_boff);
+    int64_t *scan_tmp = reinterpret_cast<int64_t *>(base + o_scan);
+
+    const unsigned zb = (unsigned)((nbk + 255) / 256);
+    zero_u32_kernel<<<zb, 256, 0, s>>>(a.bcount, nbk);
+    if ((rc = check_launch(fn))) return rc;
+    zero_u32_kernel<<<zb, 256, 0, s>>>(a.bcursor, nbk);
+    if ((rc = check_launch(fn))) return rc;
+
+    const int64_t nbr = (n_rays + kThreads - 1) / kThreads;
+    a.n_blocks = (int)nbr;
+    a.nb8 = round_up8(nbr);
+    seg_count_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
+    if ((rc = check_launch(fn))) return rc;
+    if ((rc = scan_counts(a.nseg, n_rays, a.seg_off, scan_tmp, s, fn))) return rc;
+    if ((rc = scan_counts(a.bcount, nbk, a.boff, scan_tmp + scan_tmp_words(n_rays), s, fn)))
+        return rc;
+    int64_t n_seg = 0;
+    PLX_CHECK_HIP(hipMemcpyAsync(&n_seg, a.seg_off + n_rays, sizeof(n_seg), hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
+    if (n_seg < 0 || n_seg > 0x7fffffffLL - kThreads)
+        return fail(PLX_EINVAL, "%s: %lld ray segments, more than this pass handles", fn,
+                    (long long)n_seg);
+    a.n_seg = n_seg;
+
+    // per-segment temporaries
+    TempBuf t2;
+    int64_t o2 = 0;
+    const int64_t o_bseg = o2; o2 += align256(n_seg * 16);
+    const int64_t o_tseg = o2; o2 += align256(n_seg * 8);
+    const int64_t o_cseg = o2; o2 += align256(n_seg * 16);
+    const int64_t o_tin = o2; o2 += align256(n_seg * 8);
+    const int64_t o_gra = o2; o2 += align256(n_seg * 4);
+    if (n_seg > 0) {
+        if ((rc = t2.alloc((size_t)o2, s))) return rc;
+        char *b2 = static_cast<char *>(t2.ptr);
+        a.bseg = reinterpret_cast<int4 *>(b2 + o_bseg);
+        a.tau_seg = reinterpret_cast<double *>(b2 + o_tseg);
+        a.c_seg = reinterpret_cast<float4 *>(b2 + o_cseg);
+        a.tau_in = reinterpret_cast<double *>(b2 + o_tin);
+        a.gr_after = reinterpret_cast<float *>(b2 + o_gra);
+        seg_emit_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
+        if ((rc = check_launch(fn))) return rc;
+    }
+    const int64_t nbs = (n_seg + kThreads - 1) / kThreads;
+    BinArgs as = a;
+    as.n_blocks = (int)nbs;
+    as.nb8 = round_up8(nbs);
+    if (n_seg > 0) {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
+        if ((rc = check_launch(fn))) return rc;
+    }
+    seg_combine_kernel<<<(unsigned)nbr, kThreads, 0, s>>>(a);
+    if ((rc = check_launch(fn))) return rc;
+    if (n_seg > 0) {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
+        if ((rc = check_launch(fn))) return rc;
+    }
+    return PLX_OK;
+}
+
 RenderArgs base_args(const plx_render_opts *opts, const float *o, const float *d, int64_t n) {
     RenderArgs a = {};
     a.rays_o = o;
@@ -947,14 +1485,18 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     if (n_rays == 0) return PLX_OK;
     if (!target || !grad || !touched || !loss_sum)
         return fail(PLX_EINVAL, "%s: NULL target/grad/touched/loss_sum", fn);
-    RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    BinArgs a = {};
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
     a.target = target;
     a.rgb_out = rgb_out;
+    a.loss_sum = loss_sum;
     a.grad = grad;
     a.touched = touched;
-    a.loss_sum = loss_sum;
+    a.n_rays = n_rays;
+    for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
     a.loss_scale = loss_scale;
-    return launch_render<MODE_TRAIN>(grid, a, as_stream(stream), fn);
+    return render_train_binned(grid, a, as_stream(stream), fn);
 }
 
 int64_t plx_render_state_bytes(int64_t n_rays, int32_t cap) {
@@ -1067,7 +1609,7 @@ int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *ray
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (!cell_mark || !vox_mark || !counts) return fail(PLX_EINVAL, "%s: NULL argument", fn);
     hipStream_t s = as_stream(stream);
-    const int64_t cw = plx_occ_words(grid->reso), vw = (grid->n_vox + 31) / 32;
+    const int64_t cw = (n_cells(grid->reso) + 31) / 32, vw = (grid->n_vox + 31) / 32;
     PLX_CHECK_HIP(hipMemsetAsync(cell_mark, 0, cw * 4, s), fn);
     if (vw) PLX_CHECK_HIP(hipMemsetAsync(vox_mark, 0, vw * 4, s), fn);
     TempBuf tmp;

@@ -57,6 +57,19 @@ def bits_to_bool(words: torch.Tensor, n: int) -> np.ndarray:
     return np.unpackbits(w, bitorder="little")[:n].astype(bool)
 
 
+def occupancy_cells(occ_words: torch.Tensor, reso) -> np.ndarray:
+    """The cell bitmap of an occupancy structure as a bool array [Nx, Ny, Nz]
+    over lower corners (brick-major layout: 512 bits per 8^3 brick, cell
+    (i,j,k) at bit (i%8)*64 + (j%8)*8 + k%8 of brick (i/8, j/8, k/8))."""
+    nx, ny, nz = reso
+    bx, by, bz = [-(-(r - 1) // 8) for r in reso]
+    bits = bits_to_bool(occ_words, bx * by * bz * 512).reshape(bx, by, bz, 8, 8, 8)
+    full = bits.transpose(0, 3, 1, 4, 2, 5).reshape(bx * 8, by * 8, bz * 8)
+    out = np.zeros(reso, bool)
+    out[:nx - 1, :ny - 1, :nz - 1] = full[:nx - 1, :ny - 1, :nz - 1]
+    return out
+
+
 def gpu_render(gg, o, d, bg=(1.0, 1.0, 1.0)):
     n = o.shape[0]
     rgb = torch.empty(n, 3, dtype=torch.float32, device="cuda")

@@ -31,8 +31,10 @@ def test_version_and_record_sizes():
     assert B.plx_record_bytes(B.PLX_BF16) == 64
     assert B.plx_record_bytes(B.PLX_F16) == 64
     assert B.plx_record_bytes(7) == 0
-    assert B.plx_occ_words((32, 32, 32)) == 32 ** 3 // 32
-    assert B.plx_occ_words((3, 5, 7)) == (105 + 31) // 32
+    # 16 words (512 bits) per brick of 8^3 cells over the cells 0..N-2
+    assert B.plx_occ_words((32, 32, 32)) == 4 ** 3 * 16
+    assert B.plx_occ_words((3, 5, 7)) == 16
+    assert B.plx_occ_words((10, 17, 9)) == 2 * 2 * 1 * 16
 
 
 @pytest.mark.parametrize("reso,lo,hi,step", [
