@@ -218,13 +218,17 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
                    plx_stream stream);
 
 /* Backward pass of plx_render_fwd for a given dL/dC (grad_rgb[n_rays][3]).
- * Each ray is replayed from its last sample to its first; transmittance is
- * recomputed from the forward optical depth tau_fwd[n_rays] (no per-sample
- * state).  Gradients of sigma and the SH coefficients are ADDED (FP32
- * atomics) into grad (device [M] FP32 records); touched (device uint8[M],
- * one byte per voxel) is set to 1 for every non-NULL corner voxel of every
- * sample in an occupied cell (plain byte stores: set bytes are never
- * cleared here). */
+ * Each ray is replayed from its last sample to its first with the
+ * transmittance recomputed from optical depths (no per-sample state is kept
+ * between the calls; tau_fwd[n_rays], the forward's optical depth, is part of
+ * the forward/backward contract but this call recomputes it).  Gradients of
+ * sigma and the SH coefficients are ADDED (FP32 atomics) into grad (device
+ * [M] FP32 records); touched (device uint8[M], one byte per voxel) is set to 1
+ * for every non-NULL corner voxel of every sample in an occupied cell (plain
+ * byte stores: set bytes are never cleared here).  plx_render_fwd,
+ * plx_render_bwd and plx_render_train process the rays in brick order
+ * (temporary device memory; synchronising once, to size the per-brick ray
+ * segments). */
 int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
                    const float *rays_d, int64_t n_rays, const float *grad_rgb,
                    const float *tau_fwd, float *grad, uint8_t *touched, plx_stream stream);

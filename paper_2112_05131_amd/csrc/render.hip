@@ -87,6 +87,42 @@ struct RenderArgs {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Wave-uniform copies (readfirstlane) of values the compiler cannot prove
+// uniform, so that they live in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)uni((int)(uint32_t)u), hi = (uint32_t)uni((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T> __device__ __forceinline__ T *uni_ptr(T *p) {
+    return reinterpret_cast<T *>(uni64((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+__device__ inline GridDev uniform_grid(const GridDev &s) {
+    GridDev g;
+    g.nx = uni(s.nx);
+    g.ny = uni(s.ny);
+    g.nz = uni(s.nz);
+    g.bx = uni(s.bx);
+    g.by = uni(s.by);
+    g.bz = uni(s.bz);
+    for (int a = 0; a < 3; ++a) {
+        g.scale[a] = uni(s.scale[a]);
+        g.offset[a] = uni(s.offset[a]);
+    }
+    g.step = uni(s.step);
+    g.index = uni_ptr(s.index);
+    g.data = uni_ptr(s.data);
+    g.occ = uni_ptr(s.occ);
+    g.bdist = uni_ptr(s.bdist);
+    g.n_vox = uni64(s.n_vox);
+    return g;
+}
+
 // ------------------------------------------------------------ voxel records
 
 // Density and the three colour channels projected on the ray's SH basis y.
@@ -717,7 +753,8 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 
 // ------------------------------------------------------------ brick-binned training
 //
-// plx_render_train runs the batch in brick order.  Rays sampled from many
+// plx_render_fwd, plx_render_bwd and plx_render_train run the batch in brick
+// order.  Rays sampled from many
 // cameras share few voxels with their neighbours in the batch, so a ray-order
 // pass fetches every voxel record (and read-modify-writes every gradient
 // line) about as often as rays cross it.  Here each ray is cut into segments,
@@ -810,7 +847,9 @@ __global__ void zero_u32_kernel(unsigned *p, int64_t n) {
 struct BinArgs {
     const float *rays_o;
     const float *rays_d;
-    const float *target;
+    const float *target;    // TRAIN
+    const float *grad_rgb;  // BWD
+    float *tau_out;         // FWD (optional)
     float *rgb_out;
     double *loss_sum;
     float *grad;
@@ -981,8 +1020,11 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
     a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
 }
 
-// Per ray: composes its segments, the loss and dL/dC = 2 loss_scale (C - target),
-// and for every segment the optical depth before it and g . R after it.
+// Per ray: composes its segments into the colour (and optical depth).  FWD
+// writes them out; TRAIN also forms the loss and dL/dC = 2 loss_scale (C -
+// target), BWD takes dL/dC as given; both then record, for every segment,
+// the optical depth before it and g . R after it.
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
     __shared__ double blk_loss[kWavesPerBlock];
     const int64_t ray = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -992,7 +1034,7 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
         double tau = 0.0;
         float C[3] = {0.0f, 0.0f, 0.0f};
         for (int64_t s = s0; s < s1; ++s) {
-            a.tau_in[s] = tau;
+            if (MODE != MODE_FWD) a.tau_in[s] = tau;
             const float T = expf(-(float)tau);
             const float4 c = a.c_seg[s];
             C[0] += T * c.x;
@@ -1005,31 +1047,41 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
 #pragma unroll
         for (int c3 = 0; c3 < 3; ++c3) {
             const float Cc = C[c3] + T_final * a.bg[c3];
-            if (a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
-            const float diff = Cc - a.target[3 * ray + c3];
-            gr[c3] = 2.0f * a.loss_scale * diff;
-            l2 += (double)(diff * diff);
+            if (MODE != MODE_BWD && a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
+            if (MODE == MODE_TRAIN) {
+                const float diff = Cc - a.target[3 * ray + c3];
+                gr[c3] = 2.0f * a.loss_scale * diff;
+                l2 += (double)(diff * diff);
+            } else if (MODE == MODE_BWD) {
+                gr[c3] = a.grad_rgb[3 * ray + c3];
+            }
             R[c3] = T_final * a.bg[c3];
         }
-        a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], 0.0f);
-        for (int64_t s = s1 - 1; s >= s0; --s) {
-            a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
-            const float T = expf(-(float)a.tau_in[s]);
-            const float4 c = a.c_seg[s];
-            R[0] += T * c.x;
-            R[1] += T * c.y;
-            R[2] += T * c.z;
+        if (MODE == MODE_FWD) {
+            if (a.tau_out) a.tau_out[ray] = (float)tau;
+        } else {
+            a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], 0.0f);
+            for (int64_t s = s1 - 1; s >= s0; --s) {
+                a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
+                const float T = expf(-(float)a.tau_in[s]);
+                const float4 c = a.c_seg[s];
+                R[0] += T * c.x;
+                R[1] += T * c.y;
+                R[2] += T * c.z;
+            }
         }
     }
-    double wl = (double)a.loss_scale * l2;
+    if (MODE == MODE_TRAIN) {
+        double wl = (double)a.loss_scale * l2;
 #pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) wl += __shfl_xor(wl, m);
-    if ((threadIdx.x & (kWave - 1)) == 0) blk_loss[threadIdx.x / kWave] = wl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kWavesPerBlock; ++w) t += blk_loss[w];
-        if (t != 0.0) unsafeAtomicAdd(a.loss_sum, t);
+        for (int m = kWave / 2; m >= 1; m >>= 1) wl += __shfl_xor(wl, m);
+        if ((threadIdx.x & (kWave - 1)) == 0) blk_loss[threadIdx.x / kWave] = wl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kWavesPerBlock; ++w) t += blk_loss[w];
+            if (t != 0.0) unsafeAtomicAdd(a.loss_sum, t);
+        }
     }
 }
 
@@ -1170,12 +1222,13 @@ struct ViewsArgs {
 // pixel's colour depends only on its own ray and scene, never on the rest of
 // the batch.
 template <int DT>
-__global__ __launch_bounds__(kThreads) void views_kernel(ViewsArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+void views_kernel(ViewsArgs a) {
     __shared__ long long tile_sh;
     while (true) {
         if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(a.counter, 1ull);
         __syncthreads();
-        const int64_t tile = tile_sh;
+        const int64_t tile = uni64(tile_sh);
         __syncthreads();
         if (tile >= a.n_tiles) break;
         int lo = 0, hi = a.n_views - 1;
@@ -1185,12 +1238,13 @@ __global__ __launch_bounds__(kThreads) void views_kernel(ViewsArgs a) {
             else hi = mid - 1;
         }
         const plx_view &v = a.views[lo];
-        const int64_t tl = tile - a.tile_start[lo];
-        const int tpr = (v.width + kTileW - 1) / kTileW;
+        const int width = uni(v.width), height = uni(v.height);
+        const int64_t tl = tile - uni64(a.tile_start[lo]);
+        const int tpr = (width + kTileW - 1) / kTileW;
         const int px = (int)(tl % tpr) * kTileW + (int)(threadIdx.x % kTileW);
         const int py = (int)(tl / tpr) * kTileH + (int)(threadIdx.x / kTileW);
-        if (px < v.width && py < v.height) {
-            const GridDev g = a.scenes[v.scene];
+        if (px < width && py < height) {
+            const GridDev g = uniform_grid(a.scenes[uni(v.scene)]);
             float o[3], d[3];
             camera_ray(v, px, py, o, d);
             RayGeom r;
@@ -1203,7 +1257,7 @@ __global__ __launch_bounds__(kThreads) void views_kernel(ViewsArgs a) {
             double tau;
             march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
             const float T_final = expf(-(float)tau);
-            float *out = a.rgb_out + 3 * (v.out_offset + (int64_t)py * v.width + px);
+            float *out = a.rgb_out + 3 * (uni64(v.out_offset) + (int64_t)py * width + px);
 #pragma unroll
             for (int c3 = 0; c3 < 3; ++c3) out[c3] = C[c3] + T_final * a.bg[c3];
         }
@@ -1340,8 +1394,10 @@ int scan_counts(const unsigned *c, int64_t n, int64_t *out, int64_t *tmp, hipStr
 inline int64_t scan_tmp_words(int64_t n) { return 2 * ((n + kScanTile - 1) / kScanTile) + 1; }
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
-// The brick-binned fused training pass (see the comment above BinArgs).
-int render_train_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
+// The brick-binned passes (see the comment above BinArgs): MODE_FWD renders,
+// MODE_BWD and MODE_TRAIN also run the backward replay.
+template <int MODE>
+int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
     const int64_t n_rays = a.n_rays;
     if (n_rays > 0x7fffffffLL - kThreads) return fail(PLX_EINVAL, "%s: too many rays", fn);
     GridDev g = to_dev(grid);
@@ -1416,9 +1472,9 @@ int render_train_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const ch
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
     }
-    seg_combine_kernel<<<(unsigned)nbr, kThreads, 0, s>>>(a);
+    seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
     if ((rc = check_launch(fn))) return rc;
-    if (n_seg > 0) {
+    if (MODE != MODE_FWD && n_seg > 0) {
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
     }
@@ -1450,10 +1506,14 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_rays == 0) return PLX_OK;
     if (!rgb_out) return fail(PLX_EINVAL, "%s: rgb_out is NULL", fn);
-    RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    BinArgs a = {};
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
     a.rgb_out = rgb_out;
     a.tau_out = tau_out;
-    return launch_render<MODE_FWD>(grid, a, as_stream(stream), fn);
+    a.n_rays = n_rays;
+    for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    return render_binned<MODE_FWD>(grid, a, as_stream(stream), fn);
 }
 
 int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
@@ -1466,12 +1526,15 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (n_rays == 0) return PLX_OK;
     if (!grad_rgb || !tau_fwd || !grad || !touched)
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
-    RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    BinArgs a = {};
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
     a.grad_rgb = grad_rgb;
-    a.tau_in = tau_fwd;
     a.grad = grad;
     a.touched = touched;
-    return launch_render<MODE_BWD>(grid, a, as_stream(stream), fn);
+    a.n_rays = n_rays;
+    for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    return render_binned<MODE_BWD>(grid, a, as_stream(stream), fn);
 }
 
 int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
@@ -1496,7 +1559,7 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     a.n_rays = n_rays;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
     a.loss_scale = loss_scale;
-    return render_train_binned(grid, a, as_stream(stream), fn);
+    return render_binned<MODE_TRAIN>(grid, a, as_stream(stream), fn);
 }
 
 int64_t plx_render_state_bytes(int64_t n_rays, int32_t cap) {
