@@ -42,6 +42,12 @@ N_BLOBS = 32
 SEED = 2
 BATCH = 1 << 20
 N_CAMS, W, H = 100, 800, 800
+# HBM bytes moved by one plx_render_train call of this workload (FP32
+# records), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
+# `bench.py --counters`, each scaled by its reading for a 1 GiB device copy
+# (FETCH x2, WRITE x1): 9.998 GB fetched + 8.711 GB written.  Re-measure
+# whenever the render kernels change.
+RENDER_TRAIN_TRAFFIC_GB_F32 = 18.71
 
 
 def log(*a):
@@ -252,6 +258,25 @@ def serving_leg(n_sat=160, n_load=240):
     return out
 
 
+def counter_run(sh_dtype, coherent):
+    """Dispatch sequence for rocprofv3 --pmc passes: a warm-up step, one
+    training step (render_train's kernels, tv_kernel, rmsprop_kernel), then a
+    1 GiB device-to-device copy (1 GiB read + 1 GiB written) whose counter
+    readings give the scale of FETCH_SIZE / WRITE_SIZE."""
+    gt, grid, batches, vals = build_workload(sh_dtype, 1, coherent)
+    trainer = Trainer(grid, TrainConfig(), seed=SEED)
+    o, d, t = batches[0]
+    for _ in range(2):
+        trainer.step(o, d, t)
+        torch.cuda.synchronize()
+    src = torch.ones(1 << 28, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("counter run done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +288,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
     ap.add_argument("--ray-order", default="coherent", choices=["coherent", "random"],
                     help="order of the rays inside each batch (the same rays either way)")
+    ap.add_argument("--counters", action="store_true",
+                    help="for counter runs under rocprofv3: one warm-up and one timed-shape "
+                         "training step on one batch, then a 1 GiB device copy that calibrates "
+                         "the byte counters; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -270,6 +299,9 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     sh_dtype = B.DTYPES[args.dtype]
+    if args.counters:
+        counter_run(sh_dtype, args.ray_order == "coherent")
+        return
     n_batches = min(args.warmup + args.steps, 8)
     gt, grid, batches, vals = build_workload(sh_dtype, n_batches, args.ray_order == "coherent")
     trainer = Trainer(grid, TrainConfig(), seed=SEED)
@@ -316,12 +348,15 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "render_train",
+            "kernel": "render_train (one plx_render_train call: seg_count, count scans, seg_emit, "
+                      "seg_fwd, seg_combine, seg_bwd)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": RENDER_TRAIN_TRAFFIC_GB_F32 if sh_dtype == B.PLX_F32 else None,
+            "traffic_unit": "GB per call (measured)",
+            "algorithmic_gb": round(alg_render / 1e9, 3),
         },
         "kernels_ms": {"render_train": round(float(k_ms[0]), 4), "tv_grad": round(float(k_ms[1]), 4),
                        "rmsprop_step": round(float(k_ms[2]), 4)},

@@ -59,6 +59,7 @@ constexpr int kThreads = 256;          // rays per block
 constexpr int kWavesPerBlock = kThreads / kWave;
 constexpr int kChunk = 16;             // candidate samples tested per round
 constexpr int kQCap = 8 * kWave;       // queue entries per wave (8 corners per lane per step)
+constexpr int kQRow = kQCap + 8;       // LDS row stride of the queue values (rows on distinct banks)
 constexpr float kSkipMargin = 0.05f;   // in steps
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
@@ -201,36 +202,69 @@ template <> struct Project<PLX_F16> : Project16<PLX_F16> {};
 
 // ------------------------------------------------------------ flush queue
 
+// The lane's current cell: corner ids and projected values.
+struct CornerCache {
+    int cell[3];  // lower corner; cell[0] < 0 = empty cache
+    int ids[8];
+    Q4 q[8];
+};
+
+
 // Per-wave queue of flushed corners in LDS (structure of arrays).
 struct Queue {
     int *count;     // entries in use
     int *id;        // [kQCap] voxel id
     uint8_t *src;   // [kQCap] lane that flushed it (selects the SH basis)
-    float *v;       // [4][kQCap] accumulated density, R, G, B gradients
+    float *v;       // [4][kQRow] accumulated density, R, G, B gradients
     float *y;       // [64][9] SH basis of each lane's ray
 };
 
-// Appends one entry per active lane (lanes outside the caller's branch do not
-// append).  Offsets come from one leader lane; only this wave uses the queue,
-// and its LDS accesses are ordered.
-__device__ __forceinline__ void push(const Queue &qu, int id, const Q4 &a) {
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Appends, for every active lane, its corners in `mask` (bit c = corner c)
+// that are not NULL, with their accumulators.  One offset reservation per
+// call: a lane's entries start at the sum of the counts of the active lanes
+// below it (from the bit planes of the counts); only this wave uses the
+// queue, and its LDS accesses are ordered.
+__device__ __forceinline__ void push_corners(const Queue &qu, const CornerCache &cc,
+                                             const Q4 acc[8], unsigned mask) {
+    unsigned m = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (((mask >> c) & 1u) && cc.ids[c] >= 0) m |= 1u << c;
+    const int cnt = __popc(m);
+    int before = 0, total = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint64_t plane = __ballot((cnt >> b) & 1);
+        before += lanes_below(plane) << b;
+        total += __popcll(plane) << b;
+    }
+    if (total == 0) return;
     const uint64_t act = __ballot(1);
     const int leader = __builtin_ctzll(act);
-    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
     int base = 0;
     if (lane_id() == leader) {
         base = *qu.count;
-        *qu.count = base + __popcll(act);
+        *qu.count = base + total;
     }
     base = __builtin_amdgcn_readlane(base, leader);
-    const int e = base + rank;
-    qu.id[e] = id;
-    qu.src[e] = (uint8_t)lane_id();
-    qu.v[e] = a.s;
-    qu.v[kQCap + e] = a.r;
-    qu.v[2 * kQCap + e] = a.g;
-    qu.v[3 * kQCap + e] = a.b;
+    int e = base + before;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if ((m >> c) & 1u) {
+            qu.id[e] = cc.ids[c];
+            qu.src[e] = (uint8_t)lane_id();
+            qu.v[e] = acc[c].s;
+            qu.v[kQRow + e] = acc[c].r;
+            qu.v[2 * kQRow + e] = acc[c].g;
+            qu.v[3 * kQRow + e] = acc[c].b;
+            ++e;
+        }
+    }
 }
 
 // Sends every queued voxel's gradient to its FP32 record: lanes 0..31 take
@@ -246,23 +280,24 @@ __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *tou
     const int ch = s < PLX_NSH ? 1 + s / 9 : 0;  // v row: 0 density, 1..3 colour
     const int l = s < PLX_NSH ? s % 9 : 0;
     const bool writes = s < PLX_NSH || s == PLX_SLOT_SIGMA;
-    // four pairs of entries per round, so that their LDS reads overlap
-    for (int e0 = 0; e0 < E; e0 += 8) {
-        int id[4], src[4];
-        float a[4], yv[4];
-        bool ok[4];
+    // eight pairs of entries per round, so that their LDS reads overlap
+    constexpr int U = 8;
+    for (int e0 = 0; e0 < E; e0 += 2 * U) {
+        int id[U], src[U];
+        float a[U], yv[U];
+        bool ok[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int e = e0 + 2 * u + (L >> 5);
             ok[u] = e < E;
             id[u] = ok[u] ? qu.id[e] : 0;
             src[u] = ok[u] ? (int)qu.src[e] : 0;
-            a[u] = ok[u] ? qu.v[ch * kQCap + e] : 0.0f;
+            a[u] = ok[u] ? qu.v[ch * kQRow + e] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) yv[u] = s < PLX_NSH ? qu.y[src[u] * 9 + l] : 1.0f;
+        for (int u = 0; u < U; ++u) yv[u] = s < PLX_NSH ? qu.y[src[u] * 9 + l] : 1.0f;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
             const float val = yv[u] * a[u];
             if (writes && val != 0.0f)
@@ -279,12 +314,6 @@ __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *tou
 
 // ------------------------------------------------------------ corner cache
 
-// The lane's current cell: corner ids and projected values.
-struct CornerCache {
-    int cell[3];  // lower corner; cell[0] < 0 = empty cache
-    int ids[8];
-    Q4 q[8];
-};
 
 __device__ inline int64_t corner_offset(const GridDev &g, int c) {
     return ((c >> 2) & 1) * ((int64_t)g.ny * g.nz) + ((c >> 1) & 1) * (int64_t)g.nz + (c & 1);
@@ -334,10 +363,7 @@ __device__ __forceinline__ void move_to(const GridDev &g, CornerCache &cc, const
     }
     if (BWD && had) {
         // corners leaving: those at `keep` positions (shift) or all (jump)
-        const unsigned leave = adj ? keep : 0xffu;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (((leave >> c) & 1u) && cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
+        push_corners(qu, cc, acc, adj ? keep : 0xffu);
     }
     if (adj) {
         if (bit == 4) swap_faces<4, BWD>(cc, acc);
@@ -594,7 +620,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     __shared__ int q_count[kWavesPerBlock];
     __shared__ int q_id[kWavesPerBlock * kQCap];
     __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
-    __shared__ float q_v[kWavesPerBlock * 4 * kQCap];
+    __shared__ float q_v[kWavesPerBlock * 4 * kQRow];
     __shared__ float q_y[kWavesPerBlock * kWave * 9];
     __shared__ double blk_loss;
     __shared__ unsigned blk_done;
@@ -613,7 +639,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     qu.count = q_count + wid;
     qu.id = q_id + wid * kQCap;
     qu.src = q_src + wid * kQCap;
-    qu.v = q_v + wid * 4 * kQCap;
+    qu.v = q_v + wid * 4 * kQRow;
     qu.y = q_y + wid * kWave * 9;
 
     const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
@@ -713,11 +739,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
                 k = next_backward(g, r, n, k_lo, cur);
             }
             if (k < 0) {
-                if (cc.cell[0] >= 0) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
-                }
+                if (cc.cell[0] >= 0) push_corners(qu, cc, acc, 0xffu);
                 active = false;
             } else {
                 const Sample s = sample_at(g, r, k);
@@ -1092,7 +1114,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
     __shared__ int q_count[kWavesPerBlock];
     __shared__ int q_id[kWavesPerBlock * kQCap];
     __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
-    __shared__ float q_v[kWavesPerBlock * 4 * kQCap];
+    __shared__ float q_v[kWavesPerBlock * 4 * kQRow];
     __shared__ float q_y[kWavesPerBlock * kWave * 9];
 
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
@@ -1105,7 +1127,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
     qu.count = q_count + wid;
     qu.id = q_id + wid * kQCap;
     qu.src = q_src + wid * kQCap;
-    qu.v = q_v + wid * 4 * kQCap;
+    qu.v = q_v + wid * 4 * kQRow;
     qu.y = q_y + wid * kWave * 9;
 
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
@@ -1145,11 +1167,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
         if (active) {
             const int k = span_next_down(g, r, n, sg.y, cur);
             if (k < 0) {
-                if (cc.cell[0] >= 0) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (cc.ids[c] >= 0) push(qu, cc.ids[c], acc[c]);
-                }
+                if (cc.cell[0] >= 0) push_corners(qu, cc, acc, 0xffu);
                 active = false;
             } else {
                 const Sample s = sample_at(g, r, k);
@@ -1333,7 +1351,7 @@ int launch_render(const plx_grid *grid, RenderArgs &a, hipStream_t s, const char
     a.n_blocks = (int)nb;
     a.nb8 = round_up8(nb);
     GridDev g = to_dev(grid);
-    if (MODE == MODE_FWD) {
+    if constexpr (MODE == MODE_FWD) {
         PLX_DISPATCH_DT(grid->sh_dtype, DT,
                         render_fwd_kernel<DT, STATE><<<a.nb8, kThreads, 0, s>>>(g, a));
     } else {

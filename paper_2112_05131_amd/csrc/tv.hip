@@ -4,12 +4,15 @@
 // D/256, and the SH rule that empty cells and edges count as equal to the
 // current cell) for gfx950.
 //
-// One thread per cell of the segment.  The density term reads the cell and
-// its three forward neighbours (NULL or out of range = 0); SH terms exist
-// only for a non-NULL cell, and a NULL or out-of-range neighbour gives a zero
-// difference.  Gradients go to the cell and its neighbours with float
-// atomics (neighbouring cells share voxels); the loss is reduced per block
-// and added once in FP64.
+// Density term: one thread per cell of the segment, reading the cell and
+// its three forward neighbours (NULL or out of range = 0).  SH terms exist
+// only for a non-NULL cell (a NULL or out-of-range neighbour gives a zero
+// difference): the block collects its non-NULL cells in LDS and then handles
+// each with 32 lanes, lane q = coefficient q, so the four records are read and
+// the four gradient records updated with one line-wide access each.
+// Gradients go to the cell and its neighbours with float atomics
+// (neighbouring cells share voxels); the loss is reduced per block and added
+// once in FP64.
 #include "plx_internal.hpp"
 
 namespace plx {
@@ -20,7 +23,13 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
                                                  int64_t ncell, float lam_sig_v, float lam_sh_v,
                                                  float eps, float s0, float s1, float s2,
                                                  float *grad, uint8_t *touched, double *loss_sum) {
+    __shared__ int4 cells[256];  // non-NULL cells of the block: id and forward neighbours
+    __shared__ int n_cells_sh;
+    __shared__ double part[4];
+    if (threadIdx.x == 0) n_cells_sh = 0;
+    __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float sa[3] = {s0, s1, s2};
     double local = 0.0;
     if (c < count) {
         int64_t v = start + c;
@@ -33,7 +42,6 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
         const int id = g.index[v];
         const int nid[3] = {i + 1 < g.nx ? g.index[v + sx] : -1, j + 1 < g.ny ? g.index[v + sy] : -1,
                             k + 1 < g.nz ? g.index[v + 1] : -1};
-        const float sa[3] = {s0, s1, s2};
 
         // density channel: NULL or out-of-range reads 0
         {
@@ -63,36 +71,42 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
                 touched[nid[a]] = 1;
             }
         }
-        // SH channels of a non-NULL cell
-        if (id >= 0) {
-            double sum_sh = 0.0;
-            for (int q = 0; q < PLX_NSH; ++q) {
-                const float x0 = rec_slot<DT>(g.data, id, q);
-                float dl[3], ss = 0.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dl[a] = nid[a] >= 0 ? sa[a] * (rec_slot<DT>(g.data, nid[a], q) - x0) : 0.0f;
-                    ss += dl[a] * dl[a];
-                }
-                const float term = sqrtf(ss + eps);
-                sum_sh += (double)term;
-                const float coef = lam_sh_v / term;
-                float gsum = 0.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (nid[a] < 0) continue;
-                    const float gv = coef * sa[a] * dl[a];
-                    gsum += sa[a] * dl[a];
-                    if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)nid[a] * PLX_REC_SLOTS + q, gv);
-                }
-                const float gv = -coef * gsum;
-                if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)id * PLX_REC_SLOTS + q, gv);
-            }
-            local += (double)lam_sh_v * sum_sh;
-        }
+        if (id >= 0) cells[atomicAdd(&n_cells_sh, 1)] = make_int4(id, nid[0], nid[1], nid[2]);
     }
+    __syncthreads();
+
+    // SH channels of the non-NULL cells: 8 groups of 32 lanes, lane q = slot q
+    const int q = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int nc = n_cells_sh;
+    for (int e = grp; e < nc; e += 8) {
+        const int4 cl = cells[e];
+        const int nb[3] = {cl.y, cl.z, cl.w};
+        float term = 0.0f;
+        if (q < PLX_NSH) {
+            const float x0 = rec_slot<DT>(g.data, cl.x, q);
+            float dl[3], ss = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dl[a] = nb[a] >= 0 ? sa[a] * (rec_slot<DT>(g.data, nb[a], q) - x0) : 0.0f;
+                ss += dl[a] * dl[a];
+            }
+            term = sqrtf(ss + eps);
+            const float coef = lam_sh_v / term;
+            float gsum = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (nb[a] < 0) continue;
+                const float gv = coef * sa[a] * dl[a];
+                gsum += sa[a] * dl[a];
+                if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)nb[a] * PLX_REC_SLOTS + q, gv);
+            }
+            const float gv = -coef * gsum;
+            if (gv != 0.0f) unsafeAtomicAdd(grad + (int64_t)cl.x * PLX_REC_SLOTS + q, gv);
+        }
+        local += (double)lam_sh_v * (double)term;
+    }
+
     // block reduction of the loss, one FP64 atomic per block
-    __shared__ double part[4];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) local += __shfl_xor(local, m);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = local;

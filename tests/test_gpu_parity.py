@@ -217,9 +217,13 @@ def test_backward_from_stored_state_matches_oracle(cap):
     tau = torch.empty(n, device="cuda")
     state = torch.empty(B.plx_render_state_bytes(n, cap), dtype=torch.uint8, device="cuda")
     B.plx_render_fwd_state(gg.desc(), o.cuda(), d.cuda(), rgb, tau, state, cap, bg)
-    # the forward outputs equal plx_render_fwd's bit for bit
+    # the forward outputs match the oracle (and plx_render_fwd, which composes
+    # per-brick segments and so rounds in another order)
+    rgb_ref, tau_ref = O.render_fwd(og, o.numpy(), d.numpy(), bg)[:2]
+    assert np.abs(rgb.cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL
+    assert np.allclose(tau.cpu().double().numpy(), tau_ref, rtol=1e-5, atol=1e-6)
     rgb2, tau2 = gpu_render(gg, o, d, bg)
-    assert np.array_equal(rgb.cpu().numpy(), rgb2) and np.array_equal(tau.cpu().numpy(), tau2)
+    assert np.abs(rgb.cpu().numpy() - rgb2).max() <= RGB_ATOL
     # stored counts are the oracle's occupied-sample counts
     counts = state[:4 * n].view(torch.int32).cpu().numpy()
     idx = og.index.reshape(tuple(og.reso)) >= 0

@@ -76,3 +76,18 @@ def test_coherent_batches_hold_the_same_rays():
     p1 = torch.argsort(i1, stable=True)
     p2 = torch.argsort(i2, stable=True)
     assert torch.equal(d1[p1], d2[p2]) and torch.equal(o1[p1], o2[p2])
+
+
+def test_psnr_and_camera_set_order():
+    from paper_2112_05131_amd.runs import _camera_set, psnr
+    a = torch.zeros(10, 3)
+    b = torch.full((10, 3), 0.1)
+    assert abs(psnr(a, b) - 20.0) < 1e-6  # 0.1 rounded to float32
+    assert psnr(a, a) == float("inf")
+    # every pixel of every camera once, each camera's pixels in Morton order
+    o, d = _camera_set(2, 8, 4, seed=1, device="cpu")
+    o1, d1 = synth.all_camera_rays(synth.sphere_poses(2, seed=1), 8, 4)
+    assert o.shape == o1.shape == (64, 3)
+    pix = torch.arange(32)
+    order = torch.argsort(synth.morton2(pix % 8, pix // 8))
+    assert torch.equal(d[:32], d1[order]) and torch.equal(d[32:], d1[32 + order])
