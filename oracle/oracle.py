@@ -84,6 +84,8 @@ def lib():
         L.orc_rmsprop.restype = None
         L.orc_grid_create.argtypes = [_P, _P, _P]
         L.orc_grid_create.restype = i64
+        L.orc_max_weight.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P]
+        L.orc_max_weight.restype = None
         L.orc_prune_mask.argtypes = [_P, _P, _P, f64, _P, _P]
         L.orc_prune_mask.restype = i64
         L.orc_upsample_count.argtypes = [_P, _P, _P]
@@ -273,17 +275,35 @@ def rmsprop(active, density, sh, v_density, v_sh, grad_density, grad_sh,
                       float(lr_sh), float(beta), float(eps))
 
 
-def prune_mask(g: Grid, thresh):
+def max_weight(g: Grid, rays_o, rays_d, wmax=None):
+    """Per-voxel maximum sample weight over the rays (float64[M]); raises
+    `wmax` in place when given (accumulation over batches)."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    if wmax is None:
+        wmax = np.zeros(g.n_vox, np.float64)
+    assert wmax.dtype == np.float64 and wmax.flags["C_CONTIGUOUS"] and wmax.shape == (g.n_vox,)
+    lib().orc_max_weight(_ptr(g.reso), _ptr(g.scale), _ptr(g.offset), float(g.step), _ptr(g.index),
+                         _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d), o.shape[0], _ptr(wmax))
+    return wmax
+
+
+def prune_mask(g: Grid, thresh, values=None):
+    """Keep mask of pruning with dilation: a voxel is occupied when
+    values[id] >= thresh (values = the stored density unless given, e.g. the
+    maximum sample weight for pruning by weight)."""
+    vals = g.density if values is None else _c(values, np.float64)
+    assert vals.shape == (g.n_vox,)
     keep = np.empty(g.index.shape[0], np.uint8)
     npr = ctypes.c_int64()
-    kept = lib().orc_prune_mask(_ptr(g.reso), _ptr(g.index), _ptr(g.density), float(thresh),
+    kept = lib().orc_prune_mask(_ptr(g.reso), _ptr(g.index), _ptr(vals), float(thresh),
                                 _ptr(keep), ctypes.byref(npr))
     return keep, int(kept), int(npr.value)
 
 
-def prune(g: Grid, thresh) -> tuple[Grid, int, int]:
+def prune(g: Grid, thresh, values=None) -> tuple[Grid, int, int]:
     """Prunes and compacts (table order preserved)."""
-    keep, kept, npruned = prune_mask(g, thresh)
+    keep, kept, npruned = prune_mask(g, thresh, values)
     old_ids = g.index[keep.astype(bool)]
     index, m = grid_create(g.reso, keep)
     assert m == kept

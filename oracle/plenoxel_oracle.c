@@ -30,7 +30,8 @@
  *   - TV regulariser with the 256/D normalisation and the SH edge rule
  *     (Sec. 3.5, loss below Eq. (2); supplement B.1);
  *   - RMSProp (Sec. 3.5);
- *   - density-threshold pruning with dilation, and trilinear resampling to
+ *   - density-threshold pruning with dilation, the per-voxel maximum sample
+ *     weight that pruning by weight thresholds, and trilinear resampling to
  *     a new resolution (Sec. 3.4).
  * Readings where the paper is silent (sample placement, SH constants and
  * signs, sigma ReLU, TV epsilon, RMSProp beta/eps, background rule) are the
@@ -679,14 +680,47 @@ int64_t orc_grid_create(const int32_t reso[3], const uint8_t *mask,
     return m;
 }
 
-/* Density-threshold pruning with dilation (Sec. 3.4; supplement B.1 for the
- * sigma threshold).  A voxel counts as occupied when it is non-NULL and its
- * stored density is >= thresh.  A non-NULL voxel is kept when it or any of
- * its 26 neighbours is occupied.  keep_out[ncell] gets 1 for kept voxels.
- * Returns the number kept; *n_pruned gets the number of non-NULL voxels
- * removed. */
+/* Largest sample weight seen by each voxel, the statistic of pruning by
+ * weight (Sec. 3.4, the method taken from PlenOctrees; supplement B.1 for
+ * the thresholds).  The weight of sample k is its compositing weight in
+ * Eq. (1), w_k = T_k (1 - exp(-sigma_k delta_k)).  A voxel's statistic is
+ * the largest w_k over the samples whose trilinear interpolation reads it,
+ * i.e. the samples whose cell has it as one of its 8 corners.  wmax[M] is
+ * raised in place (wmax[id] = max(wmax[id], w_k)), so calls over batches of
+ * rays give the maximum over all of them. */
+void orc_max_weight(const int32_t reso[3], const float scale[3],
+                    const float offset[3], float step, const int32_t *index,
+                    const double *density, const double *sh,
+                    const float *rays_o, const float *rays_d, int64_t n_rays,
+                    double *wmax)
+{
+    const double no_bg[3] = {0.0, 0.0, 0.0};
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
+        int n = count_samples(reso, scale, offset, step, o, d);
+        if (n == 0) continue;
+        sample_rec *recs = (sample_rec *)malloc((size_t)n * sizeof(sample_rec));
+        double rgb[3], tau, tf;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, no_bg,
+                  recs, n, rgb, &tau, &tf);
+        for (int k = 0; k < n; ++k)
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = recs[k].ids[c];
+                if (id >= 0 && recs[k].weight > wmax[id]) wmax[id] = recs[k].weight;
+            }
+        free(recs);
+    }
+}
+
+/* Threshold pruning with dilation (Sec. 3.4; supplement B.1 for the
+ * thresholds).  value[M] is the per-voxel statistic: the stored density for
+ * pruning by density, the maximum sample weight (orc_max_weight) for pruning
+ * by weight.  A voxel counts as occupied when it is non-NULL and its value is
+ * >= thresh.  A non-NULL voxel is kept when it or any of its 26 neighbours
+ * is occupied.  keep_out[ncell] gets 1 for kept voxels.  Returns the number
+ * kept; *n_pruned gets the number of non-NULL voxels removed. */
 int64_t orc_prune_mask(const int32_t reso[3], const int32_t *index,
-                       const double *density, double thresh, uint8_t *keep_out,
+                       const double *value, double thresh, uint8_t *keep_out,
                        int64_t *n_pruned)
 {
     int64_t kept = 0, pruned = 0;
@@ -705,7 +739,7 @@ int64_t orc_prune_mask(const int32_t reso[3], const int32_t *index,
                                 jj >= reso[1] || kk >= reso[2])
                                 continue;
                             int32_t id = index[lin_id(reso, ii, jj, kk)];
-                            if (id >= 0 && density[id] >= thresh) any = 1;
+                            if (id >= 0 && value[id] >= thresh) any = 1;
                         }
                 if (any) {
                     keep_out[v] = 1;

@@ -512,6 +512,109 @@ def test_prune_single_dense_voxel_survives_as_block():
     assert kept == 27 + 8 and npr == n ** 3 - 35
 
 
+# ----------------------------------------------------------------------------
+# Pruning by weight (Sec. 3.4): per-voxel maximum of the compositing weight
+
+
+def _axis_ray(n, gy, gz):
+    """+x ray whose grid coordinates across the axis are (gy, gz)."""
+    return [[-2.0, (gy + 0.5) / n - 0.5, (gz + 0.5) / n - 0.5]], [[1.0, 0.0, 0.0]]
+
+
+def test_max_weight_constant_density_axis_ray_closed_form():
+    # Constant density: sample k sits at grid x = k/2 in cell floor(k/2) and
+    # every interval is h = 1/(2n) world units, so w_k = exp(-s k h)(1 - exp(-s h)),
+    # decreasing in k.  Voxel x is a corner of cells x-1 and x, whose first
+    # sample is k = 2 max(x-1, 0); only the 4 voxel lines around the ray see it.
+    n, sig = 16, 3.7
+    g = dense_grid((n, n, n), np.full(n ** 3, sig), np.zeros((n ** 3, 27)))
+    o, d = _axis_ray(n, 5.3, 9.6)
+    w = O.max_weight(g, o, d)
+    h = 0.5 / n
+    expect = np.zeros((n, n, n))
+    for x in range(n):
+        k = 2 * max(x - 1, 0)
+        expect[x, 5:7, 9:11] = math.exp(-sig * k * h) * (1.0 - math.exp(-sig * h))
+    got = np.zeros(n ** 3)
+    got[g.index >= 0] = w[g.index[g.index >= 0]]
+    np.testing.assert_allclose(got.reshape(n, n, n), expect, rtol=1e-12, atol=0)
+
+
+def test_max_weight_peaks_at_a_surface():
+    # Density 0 for voxels x < s and S from x = s on: along the axis ray the
+    # interpolated density is 0 up to grid x = s-1, rises linearly to S over
+    # cell s-1 and stays S.  The weights rise, peak just inside the surface and
+    # fall, so the maximum is not the first sample's weight (a "first" or "sum"
+    # reduction fails here), and voxels before the surface see only zero.  (n a
+    # power of two keeps the FP32 sample positions at exactly k/2.)
+    n, s, S = 16, 6, 40.0
+    i, j, k = lattice_coords((n, n, n))
+    g = dense_grid((n, n, n), np.where(i >= s, S, 0.0), np.zeros((n ** 3, 27)))
+    o, d = _axis_ray(n, 3.25, 7.5)
+    w = O.max_weight(g, o, d)
+    h = 0.5 / n
+    xs = 0.5 * np.arange(2 * (n - 1))
+    sig = np.clip(xs - (s - 1), 0.0, 1.0) * S
+    tau_before = np.concatenate([[0.0], np.cumsum(sig * h)[:-1]])
+    wk = np.exp(-tau_before) * (1.0 - np.exp(-sig * h))
+    cell = np.floor(xs).astype(int)
+    expect = np.zeros((n, n, n))
+    for x in range(n):
+        near = (cell == x) | (cell == x - 1)
+        expect[x, 3:5, 7:9] = wk[near].max() if near.any() else 0.0
+    got = np.zeros(n ** 3)
+    got[g.index >= 0] = w[g.index[g.index >= 0]]
+    np.testing.assert_allclose(got.reshape(n, n, n), expect, rtol=1e-12, atol=1e-300)
+    peak = int(np.argmax(expect[:, 3, 7]))
+    assert expect[peak, 3, 7] > expect[peak + 2, 3, 7] > 0 and expect[s - 2, 3, 7] == 0.0
+
+
+def test_max_weight_is_a_maximum_over_rays_and_bounded_by_opacity():
+    sv = synth.dense_random((9, 8, 10), seed=41, occupancy=0.5, sigma_lo=0.0, sigma_hi=40.0)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(120, seed=42)
+    o, d = o.numpy(), d.numpy()
+    w_all = O.max_weight(g, o, d)
+    w_a = O.max_weight(g, o[:50], d[:50])
+    w_b = O.max_weight(g, o[50:], d[50:])
+    # accumulation over batches is the element-wise maximum, not a sum
+    np.testing.assert_array_equal(w_all, np.maximum(w_a, w_b))
+    acc = O.max_weight(g, o[:50], d[:50])
+    O.max_weight(g, o[50:], d[50:], acc)
+    np.testing.assert_array_equal(acc, w_all)
+    # w_k <= sum_k w_k = 1 - T_final of its ray; a voxel is seen only by
+    # samples that read it, so the set with a non-zero maximum lies inside the
+    # touched set of the gradient pass
+    _, _, tf, _ = O.render_fwd(g, o, d)
+    assert w_all.max() <= (1.0 - tf).max() + 1e-15
+    _, _, touched = O.render_bwd(g, o, d, np.ones((120, 3)))
+    assert np.all(touched[w_all > 0] == 1) and (w_all > 0).sum() > 20
+    # one ray at a time: the largest voxel value is that ray's largest weight
+    for r in range(10):
+        wr = O.max_weight(g, o[r:r + 1], d[r:r + 1])
+        tr = O.trace_ray(g, o[r], d[r])
+        sig = np.maximum(tr["sigma_pre"], 0.0)
+        tau = np.concatenate([[0.0], np.cumsum(sig * tr["delta"])[:-1]])
+        wk = np.exp(-tau) * -np.expm1(-sig * tr["delta"])
+        assert abs(wr.max() - (wk.max() if len(wk) else 0.0)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [33, 34])
+def test_prune_by_weight_matches_brute_force(seed):
+    reso = (7, 6, 6)
+    sv = synth.dense_random(reso, seed=seed, occupancy=0.6)
+    g = oracle_grid(sv)
+    vals = np.random.default_rng(seed).uniform(0.0, 1.0, g.n_vox)
+    thresh = 0.9
+    keep, kept, npr = O.prune_mask(g, thresh, vals)
+    bk = _brute_keep(reso, g.index, vals, thresh)
+    assert np.array_equal(keep.astype(bool), bk)
+    assert kept == bk.sum() and kept + npr == g.n_vox
+    g2, k2, p2 = O.prune(g, thresh, vals)
+    assert (k2, p2) == (kept, npr)
+    np.testing.assert_array_equal(g2.density, g.density[g.index[bk]])
+
+
 def test_upsample_affine_exact_and_counts():
     n, n2 = 6, 12
     i, j, k = lattice_coords((n, n, n))
