@@ -182,6 +182,17 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
 int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,
                          int64_t *n_kept, int64_t *n_pruned, plx_stream stream);
 
+/* Weight-threshold pruning with dilation (Sec. 3.4, pruning by weight as in
+ * PlenOctrees; thresholds in supplement B.1): as plx_grid_prune_count, with a
+ * voxel occupied when non-NULL with wmax[id] >= w_thresh.  wmax: device
+ * float32 [n_vox], the per-voxel maximum sample weight of
+ * plx_render_max_weight over the training rays.  keep_out, the counts and the
+ * errors are those of plx_grid_prune_count; compact with
+ * plx_grid_prune_apply.  Synchronising; temporary device memory. */
+int plx_grid_prune_weight_count(const plx_grid *grid, const float *wmax, float w_thresh,
+                                uint8_t *keep_out, int64_t *n_kept, int64_t *n_pruned,
+                                plx_stream stream);
+
 /* Compacts a pruned grid: out->index and out->data (sized n_kept from
  * plx_grid_prune_count, same reso and dtype as grid) get the kept voxels in
  * the original order.  Temporary device memory. */
@@ -243,6 +254,21 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
                      const float *rays_d, const float *target, int64_t n_rays,
                      float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
                      double *loss_sum, plx_stream stream);
+
+/* Per-voxel maximum sample weight, the statistic of pruning by weight
+ * (Sec. 3.4, the method of PlenOctrees).  Sample k of a ray has the weight
+ * w_k = T_k (1 - exp(-sigma_k delta_k)) that Eq. (1) gives its colour, with
+ * the samples, densities and transmittance of plx_render_fwd (FP32 weights,
+ * FP64 optical depth).  Each non-NULL corner voxel of the sample's cell (the
+ * 8 voxels its interpolation reads) is raised to at least w_k:
+ * wmax[id] = max(wmax[id], w_k).  wmax: device float32 [n_vox], caller-owned
+ * and caller-initialised (zeros before the first batch); calls over batches
+ * of rays accumulate the maximum over all of them, in any order.  Samples in
+ * cells without a non-NULL corner have no voxel to raise and are skipped.
+ * Brick order as plx_render_fwd (temporary device memory; synchronising
+ * once). */
+int plx_render_max_weight(const plx_grid *grid, const float *rays_o, const float *rays_d,
+                          int64_t n_rays, float *wmax, plx_stream stream);
 
 /* Backward without recomputing the samples (the stored-state variant of the
  * backward pass of Sec. 3.1-3.3).  plx_render_fwd_state is plx_render_fwd

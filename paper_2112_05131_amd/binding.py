@@ -88,12 +88,14 @@ _SIGS = {
     "plx_records_convert": ([_I32, _P, _I32, _P, _I64, _P], ctypes.c_int),
     "plx_grid_build_occupancy": ([_GP, _P, _P], ctypes.c_int),
     "plx_grid_prune_count": ([_GP, _F, _P, _P, _P, _P], ctypes.c_int),
+    "plx_grid_prune_weight_count": ([_GP, _P, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_grid_prune_apply": ([_GP, _P, _GP, _P], ctypes.c_int),
     "plx_grid_upsample_count": ([_GP, _P, _P, _P], ctypes.c_int),
     "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
     "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_max_weight": ([_GP, _P, _P, _I64, _P, _P], ctypes.c_int),
     "plx_render_state_bytes": ([_I64, _I32], _I64),
     "plx_render_fwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P], ctypes.c_int),
     "plx_render_bwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P],
@@ -242,6 +244,15 @@ def plx_grid_prune_count(g: PlxGrid, sigma_thresh, keep_out: torch.Tensor):
     return int(kept.value), int(pruned.value)
 
 
+def plx_grid_prune_weight_count(g: PlxGrid, wmax: torch.Tensor, w_thresh, keep_out: torch.Tensor):
+    kept, pruned = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().plx_grid_prune_weight_count(ctypes.byref(g), _dptr(wmax, "wmax", torch.float32, g.n_vox),
+                                             float(w_thresh),
+                                             _dptr(keep_out, "keep_out", torch.uint8),
+                                             ctypes.byref(kept), ctypes.byref(pruned), _stream()))
+    return int(kept.value), int(pruned.value)
+
+
 def plx_grid_prune_apply(g: PlxGrid, keep: torch.Tensor, out: PlxGrid):
     _check(lib().plx_grid_prune_apply(ctypes.byref(g), _dptr(keep, "keep", torch.uint8),
                                       ctypes.byref(out), _stream()))
@@ -311,6 +322,14 @@ def _state_ptr(state, n, cap):
             and state.is_contiguous() and state.numel() >= need):
         raise ValueError(f"state must be a contiguous CUDA uint8 tensor of >= {need} bytes")
     return ctypes.c_void_p(state.data_ptr()), state.numel()
+
+
+def plx_render_max_weight(g: PlxGrid, rays_o, rays_d, wmax):
+    n = rays_o.shape[0]
+    _check(lib().plx_render_max_weight(ctypes.byref(g),
+                                       _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                       _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                       _dptr(wmax, "wmax", torch.float32, g.n_vox), _stream()))
 
 
 def plx_render_fwd_state(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out, state, cap,

@@ -323,6 +323,14 @@ __global__ void prune_occ_kernel(GridDev g, int64_t ncell, float thresh, uint8_t
     occ8[v] = (id >= 0 && rec_sigma<DT>(g.data, id) >= thresh) ? 1 : 0;
 }
 
+__global__ void prune_occ_value_kernel(GridDev g, int64_t ncell, const float *value, float thresh,
+                                      uint8_t *occ8) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= ncell) return;
+    int32_t id = g.index[v];
+    occ8[v] = (id >= 0 && value[id] >= thresh) ? 1 : 0;
+}
+
 __global__ void prune_keep_kernel(GridDev g, int64_t ncell, const uint8_t *occ8, uint8_t *keep,
                                   unsigned long long *counts) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,6 +464,40 @@ int sync_read_u64(const unsigned long long *dev, int n, int64_t *host, hipStream
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+
+// Shared by both prune counts: occupied = non-NULL with density (value ==
+// NULL) or value[id] at least thresh; kept = non-NULL with an occupied voxel
+// in its 3x3x3 neighbourhood.
+int prune_count(const plx_grid *grid, const float *value, float thresh, uint8_t *keep_out,
+                int64_t *n_kept, int64_t *n_pruned, plx_stream stream, const char *fn) {
+    int rc = validate_grid(grid, false, fn);
+    if (rc) return rc;
+    if (!keep_out || !n_kept || !n_pruned) return fail(PLX_EINVAL, "%s: NULL argument", fn);
+    hipStream_t s = as_stream(stream);
+    int64_t ncell = n_cells(grid->reso);
+    TempBuf tmp;
+    if ((rc = tmp.alloc(ncell + 64, s))) return rc;
+    auto *counts = static_cast<unsigned long long *>(tmp.ptr);
+    uint8_t *occ8 = static_cast<uint8_t *>(tmp.ptr) + 64;
+    PLX_CHECK_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), fn);
+    GridDev g = to_dev(grid);
+    unsigned nb = blocks_for(ncell, 256);
+    if (value) {
+        prune_occ_value_kernel<<<nb, 256, 0, s>>>(g, ncell, value, thresh, occ8);
+    } else {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                        prune_occ_kernel<DT><<<nb, 256, 0, s>>>(g, ncell, thresh, occ8));
+    }
+    if ((rc = check_launch(fn))) return rc;
+    prune_keep_kernel<<<nb, 256, 0, s>>>(g, ncell, occ8, keep_out, counts);
+    if ((rc = check_launch(fn))) return rc;
+    int64_t h[2];
+    if ((rc = sync_read_u64(counts, 2, h, s, fn))) return rc;
+    *n_kept = h[0];
+    *n_pruned = h[1] - h[0];
+    return PLX_OK;
+}
+
 }  // namespace
 }  // namespace plx
 
@@ -553,29 +595,16 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
 
 int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,
                          int64_t *n_kept, int64_t *n_pruned, plx_stream stream) {
-    int rc = validate_grid(grid, false, "plx_grid_prune_count");
-    if (rc) return rc;
-    if (!keep_out || !n_kept || !n_pruned)
-        return fail(PLX_EINVAL, "plx_grid_prune_count: NULL argument");
-    hipStream_t s = as_stream(stream);
-    int64_t ncell = n_cells(grid->reso);
-    TempBuf tmp;
-    if ((rc = tmp.alloc(ncell + 64, s))) return rc;
-    auto *counts = static_cast<unsigned long long *>(tmp.ptr);
-    uint8_t *occ8 = static_cast<uint8_t *>(tmp.ptr) + 64;
-    PLX_CHECK_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), "plx_grid_prune_count");
-    GridDev g = to_dev(grid);
-    unsigned nb = blocks_for(ncell, 256);
-    PLX_DISPATCH_DT(grid->sh_dtype, DT,
-                    prune_occ_kernel<DT><<<nb, 256, 0, s>>>(g, ncell, sigma_thresh, occ8));
-    if ((rc = check_launch("plx_grid_prune_count"))) return rc;
-    prune_keep_kernel<<<nb, 256, 0, s>>>(g, ncell, occ8, keep_out, counts);
-    if ((rc = check_launch("plx_grid_prune_count"))) return rc;
-    int64_t h[2];
-    if ((rc = sync_read_u64(counts, 2, h, s, "plx_grid_prune_count"))) return rc;
-    *n_kept = h[0];
-    *n_pruned = h[1] - h[0];
-    return PLX_OK;
+    return plx::prune_count(grid, nullptr, sigma_thresh, keep_out, n_kept, n_pruned, stream,
+                            "plx_grid_prune_count");
+}
+
+int plx_grid_prune_weight_count(const plx_grid *grid, const float *wmax, float w_thresh,
+                                uint8_t *keep_out, int64_t *n_kept, int64_t *n_pruned,
+                                plx_stream stream) {
+    if (!wmax) return plx::fail(PLX_EINVAL, "plx_grid_prune_weight_count: wmax is NULL");
+    return plx::prune_count(grid, wmax, w_thresh, keep_out, n_kept, n_pruned, stream,
+                            "plx_grid_prune_weight_count");
 }
 
 int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out,

@@ -62,7 +62,7 @@ constexpr int kQCap = 8 * kWave;       // queue entries per wave (8 corners per 
 constexpr int kQRow = kQCap + 8;       // LDS row stride of the queue values (rows on distinct banks)
 constexpr float kSkipMargin = 0.05f;   // in steps
 
-enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2, MODE_MAXW = 3 };
 
 struct RenderArgs {
     const float *rays_o;
@@ -893,6 +893,7 @@ struct BinArgs {
     double *tau_in;      // [n_seg] ray-major: optical depth before the segment
     float *gr_after;     // [n_seg] ray-major: g . (radiance collected after the segment)
     float4 *g_ray;       // [n_rays] dL/dC of each ray
+    float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
 
 __device__ __forceinline__ void load_ray_lane(const BinArgs &a, int64_t ray, float o[3], float d[3]) {
@@ -1051,6 +1052,16 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
     __shared__ double blk_loss[kWavesPerBlock];
     const int64_t ray = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     double l2 = 0.0;
+    if constexpr (MODE == MODE_MAXW) {
+        if (ray < a.n_rays) {
+            double tau = 0.0;
+            for (int64_t s = a.seg_off[ray]; s < a.seg_off[ray + 1]; ++s) {
+                a.tau_in[s] = tau;
+                tau += a.tau_seg[s];
+            }
+        }
+        return;
+    }
     if (ray < a.n_rays) {
         const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
         double tau = 0.0;
@@ -1199,6 +1210,120 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
         }
         drain(qu, a.grad, a.touched);
     }
+}
+
+// ------------------------------------------------------------ maximum sample weight
+
+// Density-only corner cache of the weight pass.  Slot p holds the corner
+// whose lattice coordinates have the parities of p's bits (x: bit 2, y: bit 1,
+// z: bit 0), so a corner keeps its slot for as long as it stays a corner of
+// the current cell and a move never exchanges registers: the slots whose
+// corner left are flushed and reloaded.
+struct SigmaCache {
+    int cell[3];
+    int ids[8];
+    float s[8];
+    float wm[8];  // largest sample weight the corner has seen while cached
+};
+
+// Cell offset (corner number, x: bit 2) of the corner in slot p of `cell`.
+__device__ __forceinline__ int slot_corner(int p, const int cell[3]) {
+    return p ^ (((cell[0] & 1) << 2) | ((cell[1] & 1) << 1) | (cell[2] & 1));
+}
+
+// Raises wmax of the cached corners in `mask` (non-negative floats order as
+// their bit patterns, so an unsigned maximum is the float maximum).
+__device__ __forceinline__ void flush_max(const SigmaCache &sc, unsigned mask, float *wmax) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        if (((mask >> p) & 1u) && sc.ids[p] >= 0 && sc.wm[p] > 0.0f)
+            atomicMax(reinterpret_cast<unsigned *>(wmax) + sc.ids[p], __float_as_uint(sc.wm[p]));
+}
+
+// Makes `cell` the cached cell; leaving corners are flushed when MAXW.
+template <int DT, bool MAXW>
+__device__ __forceinline__ void sigma_move_to(const GridDev &g, SigmaCache &sc, const int cell[3],
+                                              float *wmax) {
+    if (cell[0] == sc.cell[0] && cell[1] == sc.cell[1] && cell[2] == sc.cell[2]) return;
+    const bool had = sc.cell[0] >= 0;
+    unsigned stay = 0;
+    if (had) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int c = slot_corner(p, cell);
+            const unsigned ox = (unsigned)(cell[0] + ((c >> 2) & 1) - sc.cell[0]);
+            const unsigned oy = (unsigned)(cell[1] + ((c >> 1) & 1) - sc.cell[1]);
+            const unsigned oz = (unsigned)(cell[2] + (c & 1) - sc.cell[2]);
+            if (ox <= 1u && oy <= 1u && oz <= 1u) stay |= 1u << p;
+        }
+        if (MAXW) flush_max(sc, ~stay & 0xffu, wmax);
+    }
+    sc.cell[0] = cell[0];
+    sc.cell[1] = cell[1];
+    sc.cell[2] = cell[2];
+    const int64_t lin = cell_id(g, sc.cell);
+    int nid[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        nid[p] = ((stay >> p) & 1u) ? sc.ids[p] : g.index[lin + corner_offset(g, slot_corner(p, cell))];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        if (!((stay >> p) & 1u)) {
+            sc.ids[p] = nid[p];
+            sc.s[p] = nid[p] >= 0 ? rec_sigma<DT>(g.data, nid[p]) : 0.0f;
+            sc.wm[p] = 0.0f;
+        }
+    }
+}
+
+// The weight pass runs in brick order in two phases over the same segments.
+// Phase 0 gives each segment's optical depth (density only; no colour is
+// needed), the combine step turns those into the depth before each segment,
+// and phase 1 replays the segment from there: sample k's weight is
+// T_k (1 - exp(-sigma_k delta_k)) with T_k from the ray's running optical
+// depth, exactly as the forward pass composites, and every non-NULL corner of
+// the sample's cell keeps the largest weight it sees; a corner's maximum goes
+// to wmax (one atomic maximum) when it leaves the cache.
+template <int DT, int PHASE>
+__global__ __launch_bounds__(kThreads) void seg_weight_kernel(GridDev g, BinArgs a) {
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    if (i >= a.n_seg) return;
+    const int4 sg = a.bseg[i];
+    float o[3], d[3];
+    load_ray_lane(a, sg.x, o, d);
+    RayGeom r;
+    const int n = ray_setup(g, o, d, r);
+    SigmaCache sc;
+    sc.cell[0] = sc.cell[1] = sc.cell[2] = -1;
+    SpanCursor cur{sg.y, 0, 0u};
+    double tau = PHASE == 0 ? 0.0 : a.tau_in[sg.w];
+    while (true) {
+        const int k = span_next_up(g, r, n, sg.z, cur);
+        if (k < 0) break;
+        const Sample smp = sample_at(g, r, k);
+        sigma_move_to<DT, PHASE == 1>(g, sc, smp.cell, a.wmax);
+        // trilinear weights in slot order
+        float sp = 0.0f;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int c = slot_corner(p, smp.cell);
+            const float ax = (c >> 2) & 1 ? smp.f[0] : 1.0f - smp.f[0];
+            const float ay = (c >> 1) & 1 ? smp.f[1] : 1.0f - smp.f[1];
+            const float az = c & 1 ? smp.f[2] : 1.0f - smp.f[2];
+            sp += ax * ay * az * sc.s[p];
+        }
+        const float sd = fmaxf(sp, 0.0f) * smp.delta;
+        if (PHASE == 1) {
+            const float wk = expf(-(float)tau) * (-expm1f(-sd));
+#pragma unroll
+            for (int p = 0; p < 8; ++p) sc.wm[p] = fmaxf(sc.wm[p], wk);
+        }
+        tau += (double)sd;
+    }
+    if (PHASE == 0) a.tau_seg[sg.w] = tau;
+    else if (sc.cell[0] >= 0) flush_max(sc, 0xffu, a.wmax);
 }
 
 // ------------------------------------------------------------------ novel views
@@ -1486,6 +1611,15 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     BinArgs as = a;
     as.n_blocks = (int)nbs;
     as.nb8 = round_up8(nbs);
+    if constexpr (MODE == MODE_MAXW) {
+        if (n_seg == 0) return PLX_OK;
+        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_weight_kernel<DT, 0><<<as.nb8, kThreads, 0, s>>>(g, as));
+        if ((rc = check_launch(fn))) return rc;
+        seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
+        if ((rc = check_launch(fn))) return rc;
+        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_weight_kernel<DT, 1><<<as.nb8, kThreads, 0, s>>>(g, as));
+        return check_launch(fn);
+    }
     if (n_seg > 0) {
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
@@ -1553,6 +1687,21 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     a.n_rays = n_rays;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
     return render_binned<MODE_BWD>(grid, a, as_stream(stream), fn);
+}
+
+int plx_render_max_weight(const plx_grid *grid, const float *rays_o, const float *rays_d,
+                          int64_t n_rays, float *wmax, plx_stream stream) {
+    const char *fn = "plx_render_max_weight";
+    int rc = validate_grid(grid, true, fn);
+    if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
+    if (n_rays == 0) return PLX_OK;
+    if (!wmax) return fail(PLX_EINVAL, "%s: wmax is NULL", fn);
+    BinArgs a = {};
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.wmax = wmax;
+    a.n_rays = n_rays;
+    return render_binned<MODE_MAXW>(grid, a, as_stream(stream), fn);
 }
 
 int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,

@@ -132,6 +132,29 @@ class Grid:
         src = self.param_records()
         src_dt = B.PLX_F32 if self.master is not None else self.sh_dtype
         kept, pruned = B.plx_grid_prune_count(self.desc(src, src_dt), sigma_thresh, keep)
+        return self._compact(keep, kept), kept, pruned
+
+    def max_weight(self, rays_o, rays_d, batch: int = 1 << 20, wmax=None) -> torch.Tensor:
+        """Per-voxel maximum sample weight over all the rays (float32 [M]),
+        taken in batches of `batch` rays: the statistic of pruning by
+        weight.  Raises `wmax` in place when given."""
+        if wmax is None:
+            wmax = torch.zeros(self.n_vox, dtype=torch.float32, device=self.device)
+        g = self.desc()
+        for s in range(0, rays_o.shape[0], batch):
+            B.plx_render_max_weight(g, rays_o[s:s + batch], rays_d[s:s + batch], wmax)
+        return wmax
+
+    def prune_by_weight(self, wmax: torch.Tensor, w_thresh: float):
+        """Weight-threshold prune with dilation (wmax from max_weight);
+        returns (new grid, kept, pruned)."""
+        keep = torch.empty(self.n_cells, dtype=torch.uint8, device=self.device)
+        kept, pruned = B.plx_grid_prune_weight_count(self.desc(), wmax, w_thresh, keep)
+        return self._compact(keep, kept), kept, pruned
+
+    def _compact(self, keep: torch.Tensor, kept: int) -> "Grid":
+        src = self.param_records()
+        src_dt = B.PLX_F32 if self.master is not None else self.sh_dtype
         index = torch.empty(self.n_cells, dtype=torch.int32, device=self.device)
         new_src = _alloc_records(kept, src_dt, self.device)
         out = B.PlxGrid()
@@ -149,7 +172,7 @@ class Grid:
             B.plx_records_convert(B.PLX_F32, new_src, self.sh_dtype, rec16, kept)
             g = Grid(self.reso, index, rec16, self.sh_dtype, new_src, self.lo, self.hi,
                      self.step_voxels)
-        return g, kept, pruned
+        return g
 
     def upsample(self, new_reso) -> "Grid":
         """Trilinear resampling to new_reso (values from the FP32 records)."""

@@ -460,20 +460,6 @@ def test_16bit_forward_and_backward(sh_dtype):
 
 # ------------------------------------------------------------------ full size, sampled
 
-@pytest.fixture(scope="module")
-def c3_scene():
-    """512^3 at 5% occupancy (about 6.7M voxels), 100 cameras at 800x800,
-    a 1M-ray batch (seed 2)."""
-    say("building c3 scene")
-    sv = synth.blob_scene((512, 512, 512), n_blobs=32, occupancy=0.05, seed=2, device="cuda")
-    poses = synth.sphere_poses(100, seed=2)
-    o, d, _ = synth.sampled_camera_rays(poses, 800, 800, 1 << 20, seed=2, device="cuda")
-    gg = Grid.from_mask(sv.mask, sv.reso, sv.density, sv.sh)
-    og = O.make_grid(np.array(sv.reso, np.int32), sv.mask.cpu().numpy(),
-                     sv.density.cpu().double().numpy(), sv.sh.cpu().double().numpy())
-    return sv, gg, og, o, d
-
-
 def test_full_size_forward_sampled(c3_scene):
     sv, gg, og, o, d = c3_scene
     say("c3 fwd, M =", gg.n_vox)
