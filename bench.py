@@ -13,8 +13,8 @@ Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
 (render_train, algorithmic bytes from the library's work counters over its
 HIP-event duration), the same step with BF16/FP16 SH storage and with
 shuffled rays, separate forward/backward with and without stored per-sample
-state, the serving latency leg, and the FP64 oracle timed on a bounded sample
-of the same workload on the host cores.
+state, the pruning-by-weight pass, the serving latency leg, and the FP64
+oracle timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
 import json
@@ -216,6 +216,48 @@ def state_leg(grid, batch, steps, cap=640):
                        "rays_over_cap": over}}
 
 
+def prune_weight_leg(grid, batches, counts, thresh=0.01):
+    """Pruning by weight on the training workload: the per-voxel maximum
+    sample weight accumulated over the distinct 1M-ray batches from zeros
+    (plx_render_max_weight once per batch, brick order, density only), then
+    the dilated threshold count over the whole grid
+    (plx_grid_prune_weight_count), timed with HIP events on the stream the
+    calls are launched on.  Algorithmic bytes of one weight call: the index
+    entries read (4 B each), per voxel read its density (4 B) and one
+    read-modify-write of its maximum (8 B), and 24 B of ray per ray."""
+    wmax = torch.zeros(grid.n_vox, device="cuda")
+    keep = torch.empty(grid.n_cells, dtype=torch.uint8, device="cuda")
+    desc = grid.desc()
+    o, d, _ = batches[0]
+    B.plx_render_max_weight(desc, o, d, wmax)  # warm-up (library and allocator)
+    wmax.zero_()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for o, d, _ in batches:
+        B.plx_render_max_weight(desc, o, d, wmax)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / len(batches)
+    a.record()
+    kept, pruned = B.plx_grid_prune_weight_count(desc, wmax, thresh, keep)
+    b.record()
+    torch.cuda.synchronize()
+    ms_prune = a.elapsed_time(b)
+    n = batches[0][0].shape[0]
+    alg = 4 * counts[2] + 12 * counts[3] + 24 * n
+    gbs = alg / (ms * 1e-3) / 1e9
+    log(f"max weight {ms:.3f} ms per {n}-ray batch ({len(batches)} batches); prune count {ms_prune:.3f} ms "
+        f"(kept {kept})")
+    del wmax, keep
+    torch.cuda.empty_cache()
+    return {"max_weight_ms_per_batch": round(ms, 4), "batches": len(batches), "mrays_s": round(n / ms / 1e3, 2),
+            "roofline": {"bound": "hbm", "kernel": "max_weight (one plx_render_max_weight call)",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_gb": round(alg / 1e9, 3)},
+            "prune_count_ms": round(ms_prune, 3), "threshold": thresh, "kept": kept, "pruned": pruned}
+
+
 def serving_leg(n_sat=160, n_load=240):
     """8 resident scenes (4 at 256^3, 4 at 512^3, 5-10% occupancy, FP16 SH),
     requests at 200x200 .. 1920x1080 with random poses on the view sphere:
@@ -399,6 +441,7 @@ def main():
             del g3, tr3, shuffled
     if not args.no_compare:
         out["backward_state"] = state_leg(grid, batches[0], args.steps)
+    out["prune_by_weight"] = prune_weight_leg(grid, batches, counts)
     if not args.no_serving:
         out["serving"] = serving_leg()
     if not args.no_cpu_baseline:

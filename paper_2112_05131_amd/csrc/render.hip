@@ -1232,12 +1232,18 @@ __device__ __forceinline__ int slot_corner(int p, const int cell[3]) {
 }
 
 // Raises wmax of the cached corners in `mask` (non-negative floats order as
-// their bit patterns, so an unsigned maximum is the float maximum).
+// their bit patterns, so an unsigned maximum is the float maximum).  wmax only
+// grows, so a value already at least the candidate makes the atomic
+// unnecessary; after the first rays through a brick most candidates are.
 __device__ __forceinline__ void flush_max(const SigmaCache &sc, unsigned mask, float *wmax) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-        if (((mask >> p) & 1u) && sc.ids[p] >= 0 && sc.wm[p] > 0.0f)
-            atomicMax(reinterpret_cast<unsigned *>(wmax) + sc.ids[p], __float_as_uint(sc.wm[p]));
+    for (int p = 0; p < 8; ++p) {
+        if (((mask >> p) & 1u) && sc.ids[p] >= 0 && sc.wm[p] > 0.0f) {
+            unsigned *q = reinterpret_cast<unsigned *>(wmax) + sc.ids[p];
+            const unsigned cand = __float_as_uint(sc.wm[p]);
+            if (__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cand) atomicMax(q, cand);
+        }
+    }
 }
 
 // Makes `cell` the cached cell; leaving corners are flushed when MAXW.

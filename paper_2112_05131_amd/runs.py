@@ -2,10 +2,12 @@
 
 coarse_to_fine: the coarse-to-fine schedule of Sec. 3.6 / supplement B.1 at
   the 256^3 sparse-scene size: a dense 64^3 grid with the uniform init is
-  trained on 5000-ray batches drawn from all pixels of 100 cameras, pruned at
-  density 5 (with dilation), upsampled to 256^3 and trained further.  Reports
-  the time per step of each stage, the prune/upsample times and voxel counts,
-  and the held-out PSNR after each stage.
+  trained on 5000-ray batches drawn from all pixels of 100 cameras, pruned
+  (with dilation) by density or by the maximum sample weight over all the
+  training rays (Sec. 3.4), upsampled to 256^3 and trained further.  Reports
+  the time per step of each stage, the prune/upsample times (and the weight
+  pass's time and ray rate) and voxel counts, and the held-out PSNR after
+  each stage.
 
 precision_drift: the same training (same init, same batch sequence) with the
   SH coefficients stored as FP32, BF16 and FP16 (FP32 density, master
@@ -17,7 +19,7 @@ precision_drift: the same training (same init, same batch sequence) with the
 Host code only chooses the schedule; every step is the library's fused
 render/MSE/backward, TV and sparse RMSProp.
 
-    python -m paper_2112_05131_amd.runs coarse_to_fine
+    python -m paper_2112_05131_amd.runs coarse_to_fine [--prune weight --prune-thresh 0.256]
     python -m paper_2112_05131_amd.runs drift --steps 2000
 """
 from __future__ import annotations
@@ -80,8 +82,17 @@ def _timed_steps(trainer: Trainer, sampler: RaySampler, steps: int) -> float:
 
 def coarse_to_fine(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 5000,
                    gt_reso=(256, 256, 256), occupancy: float = 0.10, n_blobs: int = 32,
-                   coarse=(64, 64, 64), prune_sigma: float = 5.0, n_cams: int = 100,
-                   width: int = 800, height: int = 800, seed: int = 1, log=print) -> dict:
+                   coarse=(64, 64, 64), prune: str = "density", prune_thresh: float | None = None,
+                   n_cams: int = 100, width: int = 800, height: int = 800, seed: int = 1,
+                   log=print) -> dict:
+    """prune: "density" (threshold on the stored density, default 5) or
+    "weight" (threshold on the per-voxel maximum sample weight over all
+    training rays, default 0.256, the synthetic-scene value of supplement
+    B.1)."""
+    if prune not in ("density", "weight"):
+        raise ValueError("prune must be 'density' or 'weight'")
+    if prune_thresh is None:
+        prune_thresh = 5.0 if prune == "density" else 0.256
     dev = torch.device("cuda")
     t0 = time.time()
     gt = synth.blob_scene(gt_reso, n_blobs, occupancy, seed, device=dev)
@@ -106,10 +117,29 @@ def coarse_to_fine(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 
     log(f"c2 coarse {coarse}: M={grid.n_vox}, {ms_coarse:.3f} ms/step, held-out PSNR {p_coarse:.2f}")
 
     torch.cuda.synchronize()
+    t0w = time.perf_counter()
+    weight_pass = None
+    if prune == "weight":
+        wmax = trainer.grid.max_weight(o, d, batch=1 << 22)
+        torch.cuda.synchronize()
+        tw = time.perf_counter() - t0w
+        q = torch.quantile(wmax[wmax > 0][::7].double(), torch.tensor([0.5, 0.9, 0.99], dtype=torch.float64,
+                                                                       device=dev)).tolist()
+        weight_pass = {"rays": o.shape[0], "ms": round(tw * 1e3, 3),
+                       "mrays_per_s": round(o.shape[0] / tw / 1e6, 2),
+                       "voxels_seen": int((wmax > 0).sum()), "max_weight": float(wmax.max()),
+                       "weight_p50_p90_p99_of_seen": [round(v, 6) for v in q]}
+        log(f"c2 weight pass: {o.shape[0]} rays in {tw * 1e3:.1f} ms, {weight_pass}")
     t1 = time.perf_counter()
-    pruned_grid, kept, pruned = trainer.grid.prune(prune_sigma)
+    if prune == "weight":
+        pruned_grid, kept, pruned = trainer.grid.prune_by_weight(wmax, prune_thresh)
+        del wmax
+    else:
+        pruned_grid, kept, pruned = trainer.grid.prune(prune_thresh)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    if kept == 0:
+        raise RuntimeError(f"a {prune} threshold of {prune_thresh} prunes every voxel")
     fine = pruned_grid.upsample(gt_reso)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -125,8 +155,8 @@ def coarse_to_fine(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 
         "batch_rays": batch,
         "coarse": {"reso": list(coarse), "n_vox": n, "steps": steps_coarse,
                    "ms_per_step": round(ms_coarse, 4), "psnr_heldout": round(p_coarse, 3)},
-        "prune": {"sigma_thresh": prune_sigma, "kept": kept, "pruned": pruned,
-                  "ms": round((t2 - t1) * 1e3, 3)},
+        "prune": {"by": prune, "thresh": prune_thresh, "kept": kept, "pruned": pruned,
+                  "ms": round((t2 - t1) * 1e3, 3), "weight_pass": weight_pass},
         "upsample": {"reso": list(gt_reso), "n_vox": fine.n_vox, "ms": round((t3 - t2) * 1e3, 3),
                      "psnr_heldout": round(p_up, 3)},
         "fine": {"steps": steps_fine, "ms_per_step": round(ms_fine, 4),
@@ -183,12 +213,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("run", choices=["coarse_to_fine", "drift"])
     ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--prune", choices=["density", "weight"], default="density")
+    ap.add_argument("--prune-thresh", type=float, default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     if args.run == "coarse_to_fine":
         s = args.steps or 300
-        res = coarse_to_fine(steps_coarse=s, steps_fine=s, log=log)
+        res = coarse_to_fine(steps_coarse=s, steps_fine=s, prune=args.prune,
+                             prune_thresh=args.prune_thresh, log=log)
     else:
         res = precision_drift(steps=args.steps or 2000, log=log)
     print(json.dumps(res), flush=True)
