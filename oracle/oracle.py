@@ -86,6 +86,9 @@ def lib():
         L.orc_grid_create.restype = i64
         L.orc_max_weight.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P]
         L.orc_max_weight.restype = None
+        L.orc_regularisers.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, f64, f64, f64,
+                                       f64, _P, _P, _P]
+        L.orc_regularisers.restype = None
         L.orc_prune_mask.argtypes = [_P, _P, _P, f64, _P, _P]
         L.orc_prune_mask.restype = i64
         L.orc_upsample_count.argtypes = [_P, _P, _P]
@@ -273,6 +276,20 @@ def rmsprop(active, density, sh, v_density, v_sh, grad_density, grad_sh,
     lib().orc_rmsprop(act.shape[0], _ptr(act), _ptr(density), _ptr(sh), _ptr(v_density),
                       _ptr(v_sh), _ptr(grad_density), _ptr(grad_sh), float(lr_sigma),
                       float(lr_sh), float(beta), float(eps))
+
+
+def regularisers(g: Grid, rays_o, rays_d, lambda_s, lambda_b, eps=1e-3, gate_rel=0.0):
+    """Cauchy sparsity and beta transmittance priors (Sec. 3.7) over the
+    rays: returns (loss_s, loss_b, grad_density[M], mass_density[M])."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    loss = np.zeros(2, np.float64)
+    gd = np.zeros(g.n_vox, np.float64)
+    md = np.zeros(g.n_vox, np.float64)
+    lib().orc_regularisers(_ptr(g.reso), _ptr(g.scale), _ptr(g.offset), float(g.step), _ptr(g.index),
+                           _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d), o.shape[0], float(lambda_s),
+                           float(lambda_b), float(eps), float(gate_rel), _ptr(loss), _ptr(gd), _ptr(md))
+    return float(loss[0]), float(loss[1]), gd, md
 
 
 def max_weight(g: Grid, rays_o, rays_d, wmax=None):

@@ -29,6 +29,7 @@
  *     out; the paper's "gradient kernels", supplement B.1);
  *   - TV regulariser with the 256/D normalisation and the SH edge rule
  *     (Sec. 3.5, loss below Eq. (2); supplement B.1);
+ *   - the Cauchy sparsity and beta transmittance priors (Sec. 3.7);
  *   - RMSProp (Sec. 3.5);
  *   - density-threshold pruning with dilation, the per-voxel maximum sample
  *     weight that pruning by weight thresholds, and trilinear resampling to
@@ -552,6 +553,78 @@ void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
         }
         free(recs);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The two optional priors of Sec. 3.7, on the rays of a batch:
+ *   sparsity (Cauchy loss, after SNeRG):
+ *     L_s = lambda_s sum_{rays, samples} log(1 + 2 sigma_k^2),
+ *     sigma_k = the sample's density after the ReLU (the paper's "opacity"
+ *     of the sample; reading of the design notes);
+ *   beta prior on the foreground transmittance T = T_final of each ray
+ *   (after Neural Volumes):
+ *     L_b = lambda_b sum_rays [log(eps + T) + log(eps + 1 - T)],
+ *     eps > 0 keeps the loss finite at T = 0 and T = 1 (the paper gives
+ *     none; reading of the design notes), 1 - T = -expm1(-tau).
+ * loss_out[0] += L_s, loss_out[1] += L_b.  Only densities enter either term:
+ *   dL_s/dsigma_k = lambda_s 4 sigma_k / (1 + 2 sigma_k^2),
+ *   dL_b/dsigma_k = dL_b/dT dT/dsigma_k = -delta_k T lambda_b
+ *                   [1/(eps + T) - 1/(eps + 1 - T)]
+ * (T = exp(-sum sigma delta)); both behind the density ReLU (derivative 0
+ * at 0) and spread over the 8 corners by the trilinear weights into
+ * grad_density[M] (ADDED; may be NULL).  mass_density[M] (ADDED; may be NULL)
+ * gets the same sums in absolute value, with terms whose gate is ambiguous
+ * (|sigma_pre| <= gate_rel times the sum of the absolute terms forming it)
+ * counted whether or not the gate is open, as in orc_render_bwd_mass. */
+void orc_regularisers(const int32_t reso[3], const float scale[3],
+                      const float offset[3], float step, const int32_t *index,
+                      const double *density, const double *sh,
+                      const float *rays_o, const float *rays_d, int64_t n_rays,
+                      double lambda_s, double lambda_b, double eps,
+                      double gate_rel, double loss_out[2],
+                      double *grad_density, double *mass_density)
+{
+    const double no_bg[3] = {0.0, 0.0, 0.0};
+    double ls = 0.0, lb = 0.0;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
+        int n = count_samples(reso, scale, offset, step, o, d);
+        sample_rec *recs = n ? (sample_rec *)malloc((size_t)n * sizeof(sample_rec)) : NULL;
+        double rgb[3], tau, T;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, no_bg,
+                  recs, n, rgb, &tau, &T);
+        double one_minus_T = -expm1(-tau);
+        lb += lambda_b * (log(eps + T) + log(eps + one_minus_T));
+        double dLdT = lambda_b * (1.0 / (eps + T) - 1.0 / (eps + one_minus_T));
+        for (int k = 0; k < n; ++k) {
+            const sample_rec *s = &recs[k];
+            double sig = s->sigma;
+            ls += lambda_s * log1p(2.0 * sig * sig);
+            double abs_sig = 0.0;
+            for (int c = 0; c < 8; ++c)
+                if (s->ids[c] >= 0) abs_sig += s->w[c] * fabs(density[s->ids[c]]);
+            int open = s->sigma_pre > 0.0;
+            int maybe = open || fabs(s->sigma_pre) <= gate_rel * abs_sig;
+            double t_s = lambda_s * 4.0 * sig / (1.0 + 2.0 * sig * sig);
+            double t_b = -s->delta * T * dLdT;
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = s->ids[c];
+                if (id < 0) continue;
+                if (grad_density && open) grad_density[id] += s->w[c] * (t_s + t_b);
+                if (mass_density && maybe) {
+                    /* at an ambiguous gate the density may be rounded either
+                     * side of 0: the Cauchy term is then at most the one at
+                     * |sigma_pre| */
+                    double a = fabs(s->sigma_pre);
+                    double t_s_max = lambda_s * 4.0 * a / (1.0 + 2.0 * a * a);
+                    mass_density[id] += s->w[c] * (fabs(t_s) + t_s_max + fabs(t_b));
+                }
+            }
+        }
+        free(recs);
+    }
+    loss_out[0] += ls;
+    loss_out[1] += lb;
 }
 
 /* ------------------------------------------------------------------------ */

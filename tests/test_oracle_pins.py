@@ -513,6 +513,86 @@ def test_prune_single_dense_voxel_survives_as_block():
 
 
 # ----------------------------------------------------------------------------
+# Sparsity (Cauchy) and beta priors (Sec. 3.7)
+
+
+def test_regularisers_constant_density_axis_ray_closed_form():
+    # 2(n-1) samples, all with density s, h = 1/(2n), L = (n-1)/n, T = exp(-s L).
+    # Every sample's density gradient is t_s + t_b with t_s = lam_s 4s/(1+2s^2)
+    # and t_b = -h T lam_b (1/(eps+T) - 1/(eps+1-T)); along x a voxel collects
+    # trilinear weight 2 (1.5 at x = 0, 0.5 at x = n-1), across the ray the
+    # bilinear weights of the offsets (0.25, 0.5).
+    n, sig, lam_s, lam_b, eps = 16, 1.7, 0.3, 0.2, 1e-3
+    g = dense_grid((n, n, n), np.full(n ** 3, sig), np.zeros((n ** 3, 27)))
+    o, d = _axis_ray(n, 5.25, 9.5)
+    ls, lb, gd, md = O.regularisers(g, o, d, lam_s, lam_b, eps)
+    h, L = 0.5 / n, (n - 1) / n
+    T = math.exp(-sig * L)
+    assert abs(ls - lam_s * 2 * (n - 1) * math.log1p(2 * sig * sig)) < 1e-12
+    assert abs(lb - lam_b * (math.log(eps + T) + math.log(eps + 1 - T))) < 1e-12
+    t = lam_s * 4 * sig / (1 + 2 * sig * sig) - h * T * lam_b * (1 / (eps + T) - 1 / (eps + 1 - T))
+    wx = np.full(n, 2.0)
+    wx[0], wx[-1] = 1.5, 0.5
+    expect = np.zeros((n, n, n))
+    for jj, wy in ((5, 0.75), (6, 0.25)):
+        for kk, wz in ((9, 0.5), (10, 0.5)):
+            expect[:, jj, kk] = wx * wy * wz * t
+    got = np.zeros(n ** 3)
+    got[g.index >= 0] = gd[g.index[g.index >= 0]]
+    np.testing.assert_allclose(got.reshape(n, n, n), expect, rtol=1e-12, atol=1e-15)
+    assert np.all(md >= np.abs(gd) - 1e-15)
+
+
+def test_regularisers_fd_gradient_sparse_grid():
+    sv = synth.dense_random((7, 6, 8), seed=71, occupancy=0.6, sigma_lo=0.2, sigma_hi=30.0)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(40, seed=72)
+    o, d = o.numpy(), d.numpy()
+    lam_s, lam_b, eps = 0.05, 0.3, 1e-3
+    _, _, gd, md = O.regularisers(g, o, d, lam_s, lam_b, eps)
+
+    def loss():
+        a, b, _, _ = O.regularisers(g, o, d, lam_s, lam_b, eps)
+        return a + b
+
+    rng = np.random.default_rng(73)
+    ids = np.flatnonzero(gd != 0)
+    assert ids.size > 10
+    for m in rng.choice(ids, size=12, replace=False):
+        x0 = g.density[m]
+        hh = 1e-6 * max(1.0, abs(x0))
+        g.density[m] = x0 + hh
+        lp = loss()
+        g.density[m] = x0 - hh
+        lm = loss()
+        g.density[m] = x0
+        fd = (lp - lm) / (2 * hh)
+        assert abs(fd - gd[m]) <= 1e-5 * abs(gd[m]) + 1e-9, (m, fd, gd[m])
+    assert np.all(md >= np.abs(gd) * (1 - 1e-12))
+
+
+def test_regularisers_relu_and_beta_signs():
+    n = 8
+    o, d = _axis_ray(n, 3.5, 4.25)
+    # negative densities: clipped, no Cauchy loss and no gradient; T = 1 gives
+    # the constant beta loss of an empty ray
+    g = dense_grid((n, n, n), np.full(n ** 3, -2.0), np.zeros((n ** 3, 27)))
+    ls, lb, gd, _ = O.regularisers(g, o, d, 1.0, 1.0, 1e-3)
+    assert ls == 0.0 and np.all(gd == 0.0)
+    assert abs(lb - (math.log(1.001) + math.log(1e-3))) < 1e-12
+    # a miss contributes the same constant and nothing else
+    ls2, lb2, gd2, _ = O.regularisers(g, [[5.0, 5.0, 5.0]], [[1.0, 0.0, 0.0]], 1.0, 1.0, 1e-3)
+    assert ls2 == 0.0 and lb2 == lb and np.all(gd2 == 0.0)
+    # beta alone: a mostly transparent ray (T > 1/2) is pushed to empty (positive
+    # density gradient), a mostly opaque one (T < 1/2) to opaque (negative)
+    for sig, sign in ((0.3, 1.0), (40.0, -1.0)):
+        g = dense_grid((n, n, n), np.full(n ** 3, sig), np.zeros((n ** 3, 27)))
+        _, _, gd, _ = O.regularisers(g, o, d, 0.0, 1.0, 1e-3)
+        nz = gd[gd != 0]
+        assert nz.size > 0 and np.all(np.sign(nz) == sign)
+
+
+# ----------------------------------------------------------------------------
 # Pruning by weight (Sec. 3.4): per-voxel maximum of the compositing weight
 
 
