@@ -12,8 +12,9 @@ contiguous 1% segment of the cells, and sparse RMSProp on the active voxels.
 Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
 (render_train, algorithmic bytes from the library's work counters over its
 HIP-event duration), the same step with BF16/FP16 SH storage and with
-shuffled rays, separate forward/backward with and without stored per-sample
-state, the pruning-by-weight pass, the serving latency leg, and the FP64
+shuffled rays and with the sparsity and beta priors on, separate
+forward/backward with and without stored per-sample state, the
+pruning-by-weight pass, the serving latency leg, and the FP64
 oracle timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
@@ -94,7 +95,7 @@ def time_steps(trainer, batches, warmup, steps):
         lr_s, lr_h = trainer.learning_rates()
         e[0].record()
         B.plx_render_train(g.desc(), o, d, t, 1.0 / o.shape[0], trainer.grad, trainer.touched,
-                           trainer.loss_sum, None, c.background)
+                           trainer.loss_sum, None, c.background, trainer.priors())
         e[1].record()
         s0, cnt = trainer.tv_segment()
         B.plx_tv_grad(g.desc(), s0, cnt, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps, trainer.grad,
@@ -440,6 +441,15 @@ def main():
             log(f"random ray order: step {ms3:.3f} ms, render_train {k3[0]:.3f} ms")
             del g3, tr3, shuffled
     if not args.no_compare:
+        # the same step with the sparsity and beta priors of Sec. 3.7 on (the
+        # paper's 360-degree weights)
+        g4 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=sh_dtype)
+        tr4 = Trainer(g4, TrainConfig(lambda_sparsity=1e-11, lambda_beta=1e-5), seed=SEED)
+        ms4, _, k4 = time_steps(tr4, batches, 2, max(5, args.steps // 2))
+        out["with_priors"] = {"lambda_sparsity": 1e-11, "lambda_beta": 1e-5, "ms_per_step": round(ms4, 4),
+                              "mrays_s": round(BATCH / ms4 / 1e3, 3), "render_train_ms": round(float(k4[0]), 4)}
+        log(f"with priors: step {ms4:.3f} ms, render_train {k4[0]:.3f} ms")
+        del g4, tr4
         out["backward_state"] = state_leg(grid, batches[0], args.steps)
     out["prune_by_weight"] = prune_weight_leg(grid, batches, counts)
     if not args.no_serving:

@@ -81,11 +81,32 @@ typedef struct plx_grid {
     const uint32_t *occ;   /* device, plx_occ_bytes(reso) bytes */
 } plx_grid;
 
-/* Options of the render calls. */
+/* Options of the render calls.
+ *
+ * The two optional priors of Sec. 3.7 act in the gradient calls
+ * (plx_render_bwd, plx_render_train, plx_render_bwd_state) on the rays of
+ * the call; the other calls ignore them.  With sigma_k a sample's density
+ * after the ReLU and T the ray's foreground transmittance (exp(-tau), tau its
+ * optical depth):
+ *   sparsity (Cauchy):  L_s = lambda_sparsity sum_{rays, samples} log(1 + 2 sigma_k^2),
+ *   beta:               L_b = lambda_beta sum_rays [log(beta_eps + T) + log(beta_eps + 1 - T)].
+ * Their density gradients, dL_s/dsigma_k = lambda_sparsity 4 sigma_k /
+ * (1 + 2 sigma_k^2) and dL_b/dsigma_k = -delta_k T lambda_beta
+ * [1/(beta_eps + T) - 1/(beta_eps + 1 - T)], pass the density ReLU and the
+ * trilinear weights and are ADDED into grad with the colour gradient.  Samples
+ * in cells without a non-NULL corner have density 0 and add nothing; every
+ * ray adds its beta term (a miss: the constant of T = 1).  reg_loss_sum
+ * (device double[2], or NULL) gets L_s and L_b ADDED.  Zero-initialise the
+ * struct: zero weights turn both priors off. */
 typedef struct plx_render_opts {
     float background[3]; /* colour added with the transmittance left after the
                             last sample (white background of the synthetic
                             scenes, Sec. 4.1) */
+    float lambda_sparsity; /* weight of the Cauchy sparsity prior (0 = off) */
+    float lambda_beta;     /* weight of the beta transmittance prior (0 = off) */
+    float beta_eps;        /* > 0 when lambda_beta != 0: keeps L_b finite at
+                              T = 0 and T = 1 */
+    double *reg_loss_sum;  /* device double[2] or NULL: (L_s, L_b) ADDED */
 } plx_render_opts;
 
 /* ---------------------------------------------------------------- misc */

@@ -10,6 +10,7 @@ fails loudly (build it with ``python paper_2112_05131_amd/build.py``).
 from __future__ import annotations
 
 import ctypes
+from dataclasses import dataclass
 import os
 import re
 
@@ -49,7 +50,25 @@ class PlxGrid(ctypes.Structure):
 
 
 class PlxRenderOpts(ctypes.Structure):
-    _fields_ = [("background", ctypes.c_float * 3)]
+    _fields_ = [
+        ("background", ctypes.c_float * 3),
+        ("lambda_sparsity", ctypes.c_float),
+        ("lambda_beta", ctypes.c_float),
+        ("beta_eps", ctypes.c_float),
+        ("reg_loss_sum", ctypes.c_void_p),
+    ]
+
+
+@dataclass
+class Priors:
+    """The optional sparsity (Cauchy) and beta priors of the gradient calls
+    (plx_render_opts); `loss` is a device float64 tensor of 2 elements that
+    gets (L_s, L_b) added, or None."""
+
+    lambda_sparsity: float = 0.0
+    lambda_beta: float = 0.0
+    beta_eps: float = 1e-3
+    loss: torch.Tensor | None = None
 
 
 class PlxView(ctypes.Structure):
@@ -271,8 +290,14 @@ def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid):
 
 # --------------------------------------------------------------------- render
 
-def _opts(bg):
-    return PlxRenderOpts((ctypes.c_float * 3)(*[float(x) for x in bg]))
+def _opts(bg, priors: Priors | None = None):
+    o = PlxRenderOpts((ctypes.c_float * 3)(*[float(x) for x in bg]))
+    if priors is not None:
+        o.lambda_sparsity = float(priors.lambda_sparsity)
+        o.lambda_beta = float(priors.lambda_beta)
+        o.beta_eps = float(priors.beta_eps)
+        o.reg_loss_sum = _dptr(priors.loss, "priors.loss", torch.float64, 2)
+    return o
 
 
 def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0)):
@@ -286,9 +311,9 @@ def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1
 
 
 def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
-                   bg=(1.0, 1.0, 1.0)):
+                   bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
     n = rays_o.shape[0]
-    o = _opts(bg)
+    o = _opts(bg, priors)
     _check(lib().plx_render_bwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
@@ -299,9 +324,9 @@ def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
 
 
 def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
-                     rgb_out=None, bg=(1.0, 1.0, 1.0)):
+                     rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
     n = rays_o.shape[0]
-    o = _opts(bg)
+    o = _opts(bg, priors)
     _check(lib().plx_render_train(ctypes.byref(g), ctypes.byref(o),
                                   _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n),
@@ -346,9 +371,9 @@ def plx_render_fwd_state(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out, state, ca
 
 
 def plx_render_bwd_state(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, state, cap, grad, touched,
-                         bg=(1.0, 1.0, 1.0)):
+                         bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
     n = rays_o.shape[0]
-    o = _opts(bg)
+    o = _opts(bg, priors)
     sp, sb = _state_ptr(state, n, cap)
     _check(lib().plx_render_bwd_state(ctypes.byref(g), ctypes.byref(o),
                                       _dptr(rays_o, "rays_o", torch.float32, 3 * n),

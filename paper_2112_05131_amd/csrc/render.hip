@@ -42,11 +42,16 @@
 // replay the wave drains the queue two voxels at a time, 32 lanes per voxel,
 // so that each voxel's 28 gradient values go out as one float atomic
 // instruction covering its 128-byte gradient record (the access pattern for
-// which the L2 float atomics are fastest).  The fused training kernel replays
-// only the span between the first and last occupied sample of its forward
-// pass.
+// which the L2 float atomics are fastest).
+//
+// Priors (Sec. 3.7).  The Cauchy sparsity prior adds
+// lambda_s 4 sigma / (1 + 2 sigma^2) to each sample's density gradient; the
+// beta prior on T = T_final adds delta_k times one factor per ray,
+// -T dL_b/dT, computed once from the ray's optical depth.  Both ride on the
+// density slot of the same corner accumulators.
 #include <string.h>
 
+#include <cmath>
 #include <vector>
 
 #include "plx_internal.hpp"
@@ -63,6 +68,49 @@ constexpr int kQRow = kQCap + 8;       // LDS row stride of the queue values (ro
 constexpr float kSkipMargin = 0.05f;   // in steps
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2, MODE_MAXW = 3 };
+
+// The optional sparsity (Cauchy) and beta priors of Sec. 3.7, as the gradient
+// kernels see them.
+struct Priors {
+    float lambda_s;    // Cauchy weight (0 = off)
+    float lambda_b;    // beta weight (0 = off)
+    float eps;         // beta epsilon
+    double *loss;      // [2] (L_s, L_b) ADDED, or NULL
+};
+
+// Beta prior of one ray from its optical depth tau (FP64; 1 - T = -expm1(-tau)
+// stays accurate for a nearly empty ray): returns dL_b/dsigma_k / delta_k =
+// -T dL_b/dT, the factor of each of its samples' density gradient, and adds
+// the ray's L_b to *loss.
+__device__ inline float beta_factor(const Priors &p, double tau, double *loss) {
+    const double T = exp(-tau), omT = -expm1(-tau), e = (double)p.eps;
+    *loss += (double)p.lambda_b * (log(e + T) + log(e + omT));
+    return (float)(-T * (double)p.lambda_b * (1.0 / (e + T) - 1.0 / (e + omT)));
+}
+
+// Cauchy prior at a sample with pre-activation density s > 0: the density
+// gradient lambda_s 4 s / (1 + 2 s^2); log(1 + 2 s^2) goes to *ls.
+__device__ __forceinline__ float cauchy_grad(const Priors &p, float s, float *ls) {
+    if (p.lambda_s == 0.0f || !(s > 0.0f)) return 0.0f;
+    *ls += log1pf(2.0f * s * s);
+    return 4.0f * (p.lambda_s * s) / (1.0f + 2.0f * s * s);
+}
+
+// Adds a wave's prior losses to p.loss (one atomic per wave and term; the
+// per-lane Cauchy sums are FP32, the wave sum FP64).
+__device__ inline void add_prior_loss(const Priors &p, float ls_lane, double lb) {
+    if (!p.loss) return;
+    double ls = (double)ls_lane;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        ls += __shfl_xor(ls, m);
+        lb += __shfl_xor(lb, m);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (ls != 0.0) unsafeAtomicAdd(p.loss, (double)p.lambda_s * ls);
+        if (lb != 0.0) unsafeAtomicAdd(p.loss + 1, lb);
+    }
+}
 
 struct RenderArgs {
     const float *rays_o;
@@ -82,6 +130,7 @@ struct RenderArgs {
     int64_t n_rays;
     float bg[3];
     float loss_scale;
+    Priors pri;
     int n_blocks;
     int nb8;
 };
@@ -614,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void render_fwd_kernel(GridDev g, RenderA
 // forward pass replays them from the state (index loads only, no record
 // gathers or interpolation); a ray with more than st_cap samples replays by
 // traversal and recomputation.
-template <int DT, int MODE, bool STATE>
+template <int DT, bool STATE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void render_bwd_kernel(GridDev g, RenderArgs a) {
     __shared__ int q_count[kWavesPerBlock];
@@ -622,17 +671,11 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
     __shared__ float q_v[kWavesPerBlock * 4 * kQRow];
     __shared__ float q_y[kWavesPerBlock * kWave * 9];
-    __shared__ double blk_loss;
-    __shared__ unsigned blk_done;
 
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
     const int wid = threadIdx.x / kWave;
     const int L = lane_id();
-    if (threadIdx.x == 0) {
-        blk_loss = 0.0;
-        blk_done = 0u;
-    }
     if (L == 0) q_count[wid] = 0;
     __syncthreads();
     Queue qu;
@@ -667,47 +710,22 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 
     double tau = 0.0;
     float gr[3] = {0.f, 0.f, 0.f};
-    int k_hi = n - 1, k_lo = 0;
-    if (MODE == MODE_TRAIN) {
-        float C[3];
-        int k_first, k_last;
-        march_forward<DT>(g, r, n, y, cc, C, tau, &k_first, &k_last);
-        k_lo = k_first;
-        k_hi = k_last;
-        const float T_final = expf(-(float)tau);
-        double l2 = 0.0;
-        if (live) {
-#pragma unroll
-            for (int c3 = 0; c3 < 3; ++c3) {
-                const float Cc = C[c3] + T_final * a.bg[c3];
-                if (a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
-                const float diff = Cc - a.target[3 * ray + c3];
-                gr[c3] = 2.0f * a.loss_scale * diff;
-                l2 += (double)(diff * diff);
-            }
-        }
-        // block sum of the loss: wave sums in LDS, the last wave adds it to the total
-        double wl = (double)a.loss_scale * l2;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) wl += __shfl_xor(wl, m);
-        if (L == 0) {
-            atomicAdd(&blk_loss, wl);
-            __threadfence_block();
-            if (atomicAdd(&blk_done, 1u) == (unsigned)kWavesPerBlock - 1u) {
-                __threadfence_block();
-                const double tot = atomicAdd(&blk_loss, 0.0);
-                if (tot != 0.0) unsafeAtomicAdd(a.loss_sum, tot);
-            }
-        }
-    } else if (live) {
+    const int k_lo = 0, k_hi = n - 1;
+    float ls = 0.0f;
+    double lb = 0.0;
+    float gw = 0.0f;
+    if (live) {
 #pragma unroll
         for (int c3 = 0; c3 < 3; ++c3) gr[c3] = a.grad_rgb[3 * ray + c3];
         tau = (double)a.tau_in[ray];
+        if (a.pri.lambda_b != 0.0f) gw = beta_factor(a.pri, tau, &lb);
     }
 
     double tau_after = tau;
     float T_after = expf(-(float)tau_after);
-    float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]);
+    // g . R_k less the beta factor: dC/dsigma_k's delta (T_{k+1} g.c_k - g.R_k)
+    // and the beta term's delta gw then share one running sum
+    float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]) - gw;
     // the cache may hold the forward pass's last cell: its corners have
     // nothing accumulated yet, which is what the backward expects
     Cursor cur{k_hi, 0, 0u};
@@ -753,7 +771,8 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
                 const float wk = T_before * (-expm1f(-sd));
                 const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) +
                                  gr[2] * fmaxf(v.b, 0.0f);
-                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) : 0.0f;
+                const float cs = cauchy_grad(a.pri, v.s, &ls);
+                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) + cs : 0.0f;
                 const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
                 const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
                 const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
@@ -771,6 +790,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
         }
         drain(qu, a.grad, a.touched);
     }
+    add_prior_loss(a.pri, ls, lb);
 }
 
 // ------------------------------------------------------------ brick-binned training
@@ -892,7 +912,8 @@ struct BinArgs {
     float4 *c_seg;       // [n_seg] ray-major: colour the segment adds (before T_in)
     double *tau_in;      // [n_seg] ray-major: optical depth before the segment
     float *gr_after;     // [n_seg] ray-major: g . (radiance collected after the segment)
-    float4 *g_ray;       // [n_rays] dL/dC of each ray
+    float4 *g_ray;       // [n_rays] dL/dC of each ray; w: beta factor of its samples
+    Priors pri;
     float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
 
@@ -1051,7 +1072,7 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
     __shared__ double blk_loss[kWavesPerBlock];
     const int64_t ray = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    double l2 = 0.0;
+    double l2 = 0.0, lb = 0.0;
     if constexpr (MODE == MODE_MAXW) {
         if (ray < a.n_rays) {
             double tau = 0.0;
@@ -1093,7 +1114,8 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
         if (MODE == MODE_FWD) {
             if (a.tau_out) a.tau_out[ray] = (float)tau;
         } else {
-            a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], 0.0f);
+            const float gw = a.pri.lambda_b != 0.0f ? beta_factor(a.pri, tau, &lb) : 0.0f;
+            a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], gw);
             for (int64_t s = s1 - 1; s >= s0; --s) {
                 a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
                 const float T = expf(-(float)a.tau_in[s]);
@@ -1104,6 +1126,7 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
             }
         }
     }
+    if (MODE != MODE_FWD) add_prior_loss(a.pri, 0.0f, lb);
     if (MODE == MODE_TRAIN) {
         double wl = (double)a.loss_scale * l2;
 #pragma unroll
@@ -1119,7 +1142,7 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
 }
 
 // Backward replay of one segment, from its last occupied sample to its first.
-template <int DT>
+template <int DT, bool CAUCHY>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void seg_bwd_kernel(GridDev g, BinArgs a) {
     __shared__ int q_count[kWavesPerBlock];
@@ -1162,14 +1185,14 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
 
     float gr[3] = {0.f, 0.f, 0.f};
     double tau_after = 0.0;
-    float gR = 0.0f;
+    float gR = 0.0f, ls = 0.0f;
     if (live) {
         const float4 gg = a.g_ray[sg.x];
         gr[0] = gg.x;
         gr[1] = gg.y;
         gr[2] = gg.z;
         tau_after = a.tau_in[sg.w] + a.tau_seg[sg.w];
-        gR = a.gr_after[sg.w];
+        gR = a.gr_after[sg.w] - gg.w;  // the beta factor joins the running sum
     }
     float T_after = expf(-(float)tau_after);
     SpanCursor cur{sg.z, 0, 0u};
@@ -1192,7 +1215,8 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
                 const float wk = T_before * (-expm1f(-sd));
                 const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) +
                                  gr[2] * fmaxf(v.b, 0.0f);
-                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) : 0.0f;
+                const float cs = CAUCHY ? cauchy_grad(a.pri, v.s, &ls) : 0.0f;
+                const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) + cs : 0.0f;
                 const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
                 const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
                 const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
@@ -1210,6 +1234,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
         }
         drain(qu, a.grad, a.touched);
     }
+    if (CAUCHY) add_prior_loss(a.pri, ls, 0.0);
 }
 
 // ------------------------------------------------------------ maximum sample weight
@@ -1486,8 +1511,8 @@ int launch_render(const plx_grid *grid, RenderArgs &a, hipStream_t s, const char
         PLX_DISPATCH_DT(grid->sh_dtype, DT,
                         render_fwd_kernel<DT, STATE><<<a.nb8, kThreads, 0, s>>>(g, a));
     } else {
-        PLX_DISPATCH_DT(grid->sh_dtype, DT,
-                        render_bwd_kernel<DT, MODE, STATE && MODE == MODE_BWD><<<a.nb8, kThreads, 0, s>>>(g, a));
+        static_assert(MODE == MODE_BWD, "the ray-order backward serves plx_render_bwd_state");
+        PLX_DISPATCH_DT(grid->sh_dtype, DT, render_bwd_kernel<DT, STATE><<<a.nb8, kThreads, 0, s>>>(g, a));
     }
     return check_launch(fn);
 }
@@ -1633,9 +1658,27 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
     if ((rc = check_launch(fn))) return rc;
     if (MODE != MODE_FWD && n_seg > 0) {
-        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
+        // the Cauchy prior's per-sample terms only in an instance of their own
+        if (as.pri.lambda_s != 0.0f) {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
+        } else {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT, false><<<as.nb8, kThreads, 0, s>>>(g, as));
+        }
         if ((rc = check_launch(fn))) return rc;
     }
+    return PLX_OK;
+}
+
+// Priors of a gradient call from its options (validated).
+int priors_from(const plx_render_opts *opts, Priors &p, const char *fn) {
+    p.lambda_s = opts->lambda_sparsity;
+    p.lambda_b = opts->lambda_beta;
+    p.eps = opts->beta_eps;
+    p.loss = opts->reg_loss_sum;
+    if (!std::isfinite(p.lambda_s) || !std::isfinite(p.lambda_b))
+        return fail(PLX_EINVAL, "%s: prior weights must be finite", fn);
+    if (p.lambda_b != 0.0f && !(p.eps > 0.0f && std::isfinite(p.eps)))
+        return fail(PLX_EINVAL, "%s: beta_eps must be > 0 when lambda_beta != 0", fn);
     return PLX_OK;
 }
 
@@ -1685,6 +1728,7 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (!grad_rgb || !tau_fwd || !grad || !touched)
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
     BinArgs a = {};
+    if ((rc = priors_from(opts, a.pri, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.grad_rgb = grad_rgb;
@@ -1722,6 +1766,7 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     if (!target || !grad || !touched || !loss_sum)
         return fail(PLX_EINVAL, "%s: NULL target/grad/touched/loss_sum", fn);
     BinArgs a = {};
+    if ((rc = priors_from(opts, a.pri, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.target = target;
@@ -1768,6 +1813,7 @@ int plx_render_bwd_state(const plx_grid *grid, const plx_render_opts *opts, cons
     if (!grad_rgb || !tau_fwd || !grad || !touched)
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
     RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
+    if ((rc = priors_from(opts, a.pri, fn))) return rc;
     if ((rc = attach_state(a, const_cast<void *>(state), state_bytes, cap, fn))) return rc;
     a.grad_rgb = grad_rgb;
     a.tau_in = tau_fwd;

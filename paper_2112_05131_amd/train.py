@@ -34,6 +34,11 @@ class TrainConfig:
     tv_fraction: float = 0.01
     tv_eps: float = 1e-9
     background: tuple = (1.0, 1.0, 1.0)
+    # optional priors of Sec. 3.7 (0 = off; 1e-11 and 1e-5 on the paper's
+    # 360-degree scenes, supplement B.1)
+    lambda_sparsity: float = 0.0
+    lambda_beta: float = 0.0
+    beta_eps: float = 1e-3
 
 
 class RaySampler:
@@ -94,6 +99,7 @@ class Trainer:
         self.touched = torch.zeros(m, dtype=torch.uint8, device=dev)
         self.loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
         self.tv_loss_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.prior_loss_sum = torch.zeros(2, dtype=torch.float64, device=dev)
 
     def learning_rates(self, step=None):
         c = self.cfg
@@ -102,6 +108,14 @@ class Trainer:
                                  c.lr_sigma_delay_steps, c.lr_sigma_delay_mult)
         lr_h = B.plx_lr_schedule(t, c.lr_sh0, c.lr_sh1, c.lr_max_steps)
         return lr_s, lr_h
+
+    def priors(self):
+        """The sparsity and beta priors of the configuration (None if off);
+        their losses accumulate in prior_loss_sum."""
+        c = self.cfg
+        if c.lambda_sparsity == 0.0 and c.lambda_beta == 0.0:
+            return None
+        return B.Priors(c.lambda_sparsity, c.lambda_beta, c.beta_eps, self.prior_loss_sum)
 
     def tv_segment(self):
         n = self.grid.n_cells
@@ -115,7 +129,7 @@ class Trainer:
         lr_s, lr_h = self.learning_rates()
         n = rays_o.shape[0]
         B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
-                           self.touched, self.loss_sum, rgb_out, c.background)
+                           self.touched, self.loss_sum, rgb_out, c.background, self.priors())
         if tv and (c.lambda_tv_sigma > 0 or c.lambda_tv_sh > 0):
             start, count = self.tv_segment()
             B.plx_tv_grad(g.desc(), start, count, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps,
