@@ -70,6 +70,8 @@ def lib():
         L.orc_trace_ray.restype = i32
         L.orc_camera_rays.argtypes = [_P, f64, ctypes.c_int32, ctypes.c_int32, _P, _P]
         L.orc_camera_rays.restype = None
+        L.orc_rays_to_ndc.argtypes = [_P, _P, i64, ctypes.c_int32, ctypes.c_int32, f64, f64, _P, _P]
+        L.orc_rays_to_ndc.restype = None
         L.orc_ray_extent.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P]
         L.orc_ray_extent.restype = i32
         L.orc_render_bwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
@@ -242,6 +244,18 @@ def camera_rays(c2w, focal, width, height):
     d = np.empty((width * height, 3), np.float32)
     lib().orc_camera_rays(_ptr(m), float(focal), int(width), int(height), _ptr(o), _ptr(d))
     return o, d
+
+
+def rays_to_ndc(rays_o, rays_d, width, height, focal, near=1.0):
+    """NDC rays of forward-facing scenes (orc_rays_to_ndc): float32 [R, 3]
+    origins and unit directions."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    oo = np.empty_like(o)
+    dd = np.empty_like(d)
+    lib().orc_rays_to_ndc(_ptr(o), _ptr(d), o.shape[0], int(width), int(height), float(focal), float(near),
+                          _ptr(oo), _ptr(dd))
+    return oo, dd
 
 
 def ray_extent(g: Grid, o, d):

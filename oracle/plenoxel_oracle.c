@@ -30,6 +30,7 @@
  *   - TV regulariser with the 256/D normalisation and the SH edge rule
  *     (Sec. 3.5, loss below Eq. (2); supplement B.1);
  *   - the Cauchy sparsity and beta transmittance priors (Sec. 3.7);
+ *   - the NDC warp of rays for forward-facing scenes (Sec. 3.6);
  *   - RMSProp (Sec. 3.5);
  *   - density-threshold pruning with dilation, the per-voxel maximum sample
  *     weight that pruning by weight thresholds, and trilinear resampling to
@@ -392,6 +393,54 @@ void orc_camera_rays(const double c2w[12], double focal, int32_t width,
                 rays_o[3 * r + a] = (float)c2w[4 * a + 3];
             }
         }
+}
+
+/* Normalized device coordinates of forward-facing scenes (Sec. 3.6 and the
+ * forward-facing experiments: the NDC space derived in the NeRF paper).
+ * Rays are given in the frame of a reference pinhole camera that looks
+ * along -z (width x height pixels, focal length f in pixels) with its near
+ * plane at z = -near.  A world point (x, y, z), z < 0, maps to
+ *   (-(2f/W) x/z, -(2f/H) y/z, 1 + 2 near/z),
+ * which sends the near plane to NDC z = -1 and infinity to z = +1, and maps
+ * straight lines to straight lines.  A ray is first moved to its point on
+ * the near plane, o + t d with t = -(near + o_z)/d_z; with that point o:
+ *   o' = (-(2f/W) o_x/o_z, -(2f/H) o_y/o_z, 1 + 2 near/o_z),
+ *   d' = (-(2f/W)(d_x/d_z - o_x/o_z), -(2f/H)(d_y/d_z - o_y/o_z), -2 near/o_z),
+ * and d' is normalised (the renderer marches unit directions; distances,
+ * hence the sample intervals, are measured in NDC space).  FP64 with this
+ * operation order, rounded to FP32 once.  A ray with d_z = 0 never reaches
+ * the near plane: it gets origin and direction 0 (no samples). */
+void orc_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays,
+                     int32_t width, int32_t height, double focal, double near,
+                     float *o_out, float *d_out)
+{
+    const double ax = -(2.0 * focal / (double)width);
+    const double ay = -(2.0 * focal / (double)height);
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double o[3], d[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = (double)rays_o[3 * r + a];
+            d[a] = (double)rays_d[3 * r + a];
+        }
+        if (d[2] == 0.0) {
+            for (int a = 0; a < 3; ++a) o_out[3 * r + a] = d_out[3 * r + a] = 0.0f;
+            continue;
+        }
+        double t = -(near + o[2]) / d[2];
+        for (int a = 0; a < 3; ++a) o[a] = o[a] + t * d[a];
+        double op[3], dp[3];
+        op[0] = ax * (o[0] / o[2]);
+        op[1] = ay * (o[1] / o[2]);
+        op[2] = 1.0 + 2.0 * near / o[2];
+        dp[0] = ax * (d[0] / d[2] - o[0] / o[2]);
+        dp[1] = ay * (d[1] / d[2] - o[1] / o[2]);
+        dp[2] = -2.0 * near / o[2];
+        double nrm = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
+        for (int a = 0; a < 3; ++a) {
+            o_out[3 * r + a] = (float)op[a];
+            d_out[3 * r + a] = (float)(dp[a] / nrm);
+        }
+    }
 }
 
 /* Ray setup only, for tests: t_near/t_far of the FP32 recipe and the sample

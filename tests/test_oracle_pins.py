@@ -513,6 +513,65 @@ def test_prune_single_dense_voxel_survives_as_block():
 
 
 # ----------------------------------------------------------------------------
+# NDC warp of forward-facing scenes (Sec. 3.6)
+
+
+def _ndc_point(p, W, H, f, near):
+    return np.array([-(2 * f / W) * p[0] / p[2], -(2 * f / H) * p[1] / p[2], 1 + 2 * near / p[2]])
+
+
+def test_ndc_reference_camera_rays_are_parallel_to_z():
+    # pixel (px, py) of the reference camera starts at NDC
+    # ((px + 0.5 - W/2)/(W/2), -(py + 0.5 - H/2)/(H/2), -1) and runs along +z
+    W, H, f, near = 40, 30, 33.0, 1.0
+    c2w = np.array([[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 1.0, 0]])
+    o, d = O.camera_rays(c2w, f, W, H)
+    on, dn = O.rays_to_ndc(o, d, W, H, f, near)
+    px, py = np.meshgrid(np.arange(W), np.arange(H))
+    ex = (px.reshape(-1) + 0.5 - W / 2) / (W / 2)
+    ey = -(py.reshape(-1) + 0.5 - H / 2) / (H / 2)
+    np.testing.assert_allclose(on[:, 0], ex, atol=2e-6)
+    np.testing.assert_allclose(on[:, 1], ey, atol=2e-6)
+    np.testing.assert_allclose(on[:, 2], -1.0, atol=1e-6)
+    np.testing.assert_allclose(np.abs(dn), np.tile([0.0, 0.0, 1.0], (W * H, 1)), atol=2e-6)
+    assert np.all(dn[:, 2] > 0)
+
+
+def test_ndc_maps_world_points_onto_the_ray_in_order():
+    # the NDC images of the points of a world ray lie on the NDC ray, in the
+    # same order, and tend to z = 1 far away
+    W, H, f, near = 64, 48, 52.0, 1.0
+    rng = np.random.default_rng(5)
+    n = 60
+    o = np.column_stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.2, 0.2, n), rng.uniform(-0.2, 0.4, n)])
+    d = np.column_stack([rng.uniform(-0.4, 0.4, n), rng.uniform(-0.3, 0.3, n), rng.uniform(-1.0, -0.5, n)])
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o32, d32 = o.astype(np.float32), d.astype(np.float32)
+    on, dn = O.rays_to_ndc(o32, d32, W, H, f, near)
+    for r in range(n):
+        oo, dd = o32[r].astype(np.float64), d32[r].astype(np.float64)
+        t0 = -(near + oo[2]) / dd[2]
+        prev = -np.inf
+        for t in t0 + np.array([0.0, 0.3, 1.0, 4.0, 30.0, 1e4]):
+            P = _ndc_point(oo + t * dd, W, H, f, near)
+            rel = P - on[r].astype(np.float64)
+            s = rel @ dn[r]
+            assert np.linalg.norm(rel - s * dn[r]) < 1e-5 * (1 + abs(s)), (r, t)
+            assert s > prev - 1e-6
+            prev = s
+        assert abs(P[2] - 1.0) < 1e-3
+    # a ray parallel to the near plane never reaches it
+    zo, zd = O.rays_to_ndc([[0.1, 0.2, 0.0]], [[1.0, 0.0, 0.0]], W, H, f, near)
+    assert np.all(zo == 0) and np.all(zd == 0)
+
+
+def test_ndc_centre_ray_and_near_plane():
+    on, dn = O.rays_to_ndc([[0.0, 0.0, 0.0], [0.0, 0.0, 3.0]], [[0.0, 0.0, -1.0]] * 2, 80, 60, 70.0, 2.0)
+    np.testing.assert_array_equal(on, [[0.0, 0.0, -1.0]] * 2)
+    np.testing.assert_array_equal(np.abs(dn), [[0.0, 0.0, 1.0]] * 2)
+
+
+# ----------------------------------------------------------------------------
 # Sparsity (Cauchy) and beta priors (Sec. 3.7)
 
 
