@@ -234,6 +234,27 @@ int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int
  * device memory. */
 int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stream);
 
+/* ---------------------------------------------------------------- rays */
+
+/* NDC warp of forward-facing rays (Sec. 3.6: forward-facing scenes use the
+ * normalized device coordinates derived in the NeRF paper).  Rays are given
+ * in the frame of a reference pinhole camera looking along -z (width x
+ * height pixels, focal length in pixels, near plane at z = -near).  A world
+ * point (x, y, z), z < 0, maps to (-(2f/W) x/z, -(2f/H) y/z, 1 + 2 near/z):
+ * the near plane goes to NDC z = -1, infinity to z = +1.  Each ray is moved
+ * to its point o on the near plane and becomes
+ *   o' = (-(2f/W) o_x/o_z, -(2f/H) o_y/o_z, 1 + 2 near/o_z),
+ *   d' = (-(2f/W)(d_x/d_z - o_x/o_z), -(2f/H)(d_y/d_z - o_y/o_z), -2 near/o_z),
+ * normalised, so the render calls march it in NDC space (sample intervals
+ * are NDC distances).  FP64 in that operation order without contraction,
+ * rounded to FP32 once.  A ray with d_z = 0 gets origin and direction 0 (no
+ * samples).  rays_o/rays_d/o_out/d_out: device float32 [n_rays][3]; the
+ * outputs may alias the inputs.  Render the warped rays with a grid whose
+ * box is the NDC cube [-1, 1]^3 (any per-axis resolution). */
+int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, int32_t width,
+                    int32_t height, double focal, double near, float *o_out, float *d_out,
+                    plx_stream stream);
+
 /* ---------------------------------------------------------------- render */
 
 /* Forward rendering (Sec. 3.1-3.3).  Each ray (unit direction) is marched

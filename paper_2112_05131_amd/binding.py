@@ -111,6 +111,8 @@ _SIGS = {
     "plx_grid_prune_apply": ([_GP, _P, _GP, _P], ctypes.c_int),
     "plx_grid_upsample_count": ([_GP, _P, _P, _P], ctypes.c_int),
     "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
+    "plx_rays_to_ndc": ([_P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double, _P, _P, _P],
+                        ctypes.c_int),
     "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -298,6 +300,14 @@ def _opts(bg, priors: Priors | None = None):
         o.beta_eps = float(priors.beta_eps)
         o.reg_loss_sum = _dptr(priors.loss, "priors.loss", torch.float64, 2)
     return o
+
+
+def plx_rays_to_ndc(rays_o, rays_d, width, height, focal, near, o_out, d_out):
+    n = rays_o.shape[0]
+    _check(lib().plx_rays_to_ndc(_dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n, int(width), int(height),
+                                 float(focal), float(near), _dptr(o_out, "o_out", torch.float32, 3 * n),
+                                 _dptr(d_out, "d_out", torch.float32, 3 * n), _stream()))
 
 
 def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0)):

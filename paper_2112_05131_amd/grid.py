@@ -174,9 +174,12 @@ class Grid:
                      self.step_voxels)
         return g
 
-    def upsample(self, new_reso) -> "Grid":
-        """Trilinear resampling to new_reso (values from the FP32 records)."""
+    def upsample(self, new_reso, step_voxels: float | None = None) -> "Grid":
+        """Trilinear resampling to new_reso (values from the FP32 records);
+        the sample step stays step_voxels finest-axis voxels (this grid's
+        unless given)."""
         new_reso = tuple(int(r) for r in new_reso)
+        sv = self.step_voxels if step_voxels is None else float(step_voxels)
         src = self.param_records()
         src_dt = B.PLX_F32 if self.master is not None else self.sh_dtype
         n = B.plx_grid_upsample_count(self.desc(src, src_dt), new_reso)
@@ -191,9 +194,7 @@ class Grid:
         out.data = new_src.data_ptr() if n else None
         B.plx_grid_upsample_apply(self.desc(src, src_dt), out)
         if self.master is None:
-            return Grid(new_reso, index, new_src, self.sh_dtype, None, self.lo, self.hi,
-                        self.step_voxels)
+            return Grid(new_reso, index, new_src, self.sh_dtype, None, self.lo, self.hi, sv)
         rec16 = _alloc_records(n, self.sh_dtype, self.device)
         B.plx_records_convert(B.PLX_F32, new_src, self.sh_dtype, rec16, n)
-        return Grid(new_reso, index, rec16, self.sh_dtype, new_src, self.lo, self.hi,
-                    self.step_voxels)
+        return Grid(new_reso, index, rec16, self.sh_dtype, new_src, self.lo, self.hi, sv)

@@ -10,6 +10,9 @@ Scenes stand in for the paper's NeRF-synthetic data (not available here):
 isotropic Gaussian density blobs in the unit cube [-0.5, 0.5]^3 with peak
 density sigma_max, per-blob colour coefficients, and cameras on a sphere of
 radius 2 looking at the origin with a 45 degree pinhole and pixel-centred rays.
+Forward-facing captures (the LLFF scenes) are stood in for by cameras spread
+over a small square of the plane z = 0, looking along -z with small tilts;
+their scene values fill a grid over the NDC cube.
 
 Everything is computed in float64 with torch (CPU or GPU) and rounded to
 float32 once; a test generates its inputs once and feeds the same arrays to
@@ -160,6 +163,27 @@ def sphere_poses(n: int, seed: int, radius: float = 2.0) -> torch.Tensor:
     return poses
 
 
+def forward_facing_poses(n: int, seed: int, spread: float = 0.1, tilt_deg: float = 3.0) -> torch.Tensor:
+    """n camera-to-world matrices [n,3,4] (float64) of a forward-facing
+    capture: centres uniform in the square [-spread, spread]^2 of the plane
+    z = 0, each looking along -z turned by up to tilt_deg about the x and y
+    axes (the frame of the reference camera, which sits at the origin)."""
+    g = _gen(seed)
+    c = (torch.rand(n, 2, generator=g, dtype=torch.float64) * 2.0 - 1.0) * spread
+    ang = (torch.rand(n, 2, generator=g, dtype=torch.float64) * 2.0 - 1.0) * np.deg2rad(tilt_deg)
+    poses = torch.zeros(n, 3, 4, dtype=torch.float64)
+    for i in range(n):
+        a, b = float(ang[i, 0]), float(ang[i, 1])
+        rx = torch.tensor([[1.0, 0.0, 0.0], [0.0, np.cos(a), -np.sin(a)], [0.0, np.sin(a), np.cos(a)]],
+                          dtype=torch.float64)
+        ry = torch.tensor([[np.cos(b), 0.0, np.sin(b)], [0.0, 1.0, 0.0], [-np.sin(b), 0.0, np.cos(b)]],
+                          dtype=torch.float64)
+        poses[i, :, :3] = ry @ rx
+        poses[i, 0, 3] = c[i, 0]
+        poses[i, 1, 3] = c[i, 1]
+    return poses
+
+
 def camera_rays(pose: torch.Tensor, width: int, height: int, fov_deg: float = 45.0,
                 device="cpu"):
     """Pixel-centred pinhole rays of one camera, row-major.  Returns
@@ -198,6 +222,11 @@ def morton2(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         v = (v | (v << 1)) & 0x55555555
         return v
     return spread(x) | (spread(y) << 1)
+
+
+def focal_length(width: int, fov_deg: float = 45.0) -> float:
+    """Focal length in pixels of the pinhole cameras above (horizontal FOV)."""
+    return float(0.5 * width / np.tan(0.5 * np.deg2rad(fov_deg)))
 
 
 def sampled_camera_rays(poses: torch.Tensor, width: int, height: int, n: int, seed: int,
