@@ -62,7 +62,7 @@ def lib():
         L.orc_grid_geometry.restype = None
         L.orc_sh_basis.argtypes = [_P, _P]
         L.orc_sh_basis.restype = None
-        L.orc_render_fwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
+        L.orc_render_fwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P, i64,
                                      _P, _P, _P, _P]
         L.orc_render_fwd.restype = None
         L.orc_trace_ray.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i32, _P,
@@ -72,12 +72,16 @@ def lib():
         L.orc_camera_rays.restype = None
         L.orc_rays_to_ndc.argtypes = [_P, _P, i64, ctypes.c_int32, ctypes.c_int32, f64, f64, _P, _P]
         L.orc_rays_to_ndc.restype = None
+        L.orc_bg_render_fwd.argtypes = [_P, _P, _P, _P, _P, _P, i64, _P, _P, _P]
+        L.orc_bg_render_fwd.restype = None
+        L.orc_bg_render_bwd.argtypes = [_P, _P, _P, _P, _P, _P, i64, _P, _P, _P, _P, _P]
+        L.orc_bg_render_bwd.restype = None
         L.orc_ray_extent.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P]
         L.orc_ray_extent.restype = i32
-        L.orc_render_bwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
+        L.orc_render_bwd.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P, i64,
                                      _P, _P, _P, _P]
         L.orc_render_bwd.restype = None
-        L.orc_render_bwd_mass.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P,
+        L.orc_render_bwd_mass.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P, i64, _P, i64,
                                           _P, f64, _P, _P]
         L.orc_render_bwd_mass.restype = None
         L.orc_tv.argtypes = [_P, _P, _P, _P, i64, i64, f64, f64, f64, _P, _P, _P]
@@ -165,8 +169,19 @@ def _grid_args(g: Grid):
             _ptr(g.density), _ptr(g.sh))
 
 
+def _bg(bg, n):
+    """Background colours: one (3,) colour for every ray, or (n, 3) per ray."""
+    b = _c(bg, np.float64)
+    if b.size == 3 and b.ndim == 1:
+        return b, 0
+    b = b.reshape(-1, 3)
+    assert b.shape[0] == n
+    return b, 3
+
+
 def render_fwd(g: Grid, rays_o, rays_d, bg=(1.0, 1.0, 1.0)):
-    """Returns rgb[R,3], tau[R] (optical depth), t_final[R], n_samples[R]."""
+    """Returns rgb[R,3], tau[R] (optical depth), t_final[R], n_samples[R].
+    bg: one colour or one per ray ([R,3])."""
     o = _c(rays_o, np.float32).reshape(-1, 3)
     d = _c(rays_d, np.float32).reshape(-1, 3)
     n = o.shape[0]
@@ -174,7 +189,8 @@ def render_fwd(g: Grid, rays_o, rays_d, bg=(1.0, 1.0, 1.0)):
     tau = np.empty(n, np.float64)
     tf = np.empty(n, np.float64)
     ns = np.empty(n, np.int32)
-    lib().orc_render_fwd(*_grid_args(g), _ptr(o), _ptr(d), n, _ptr(_c(bg, np.float64)),
+    b, bs = _bg(bg, n)
+    lib().orc_render_fwd(*_grid_args(g), _ptr(o), _ptr(d), n, _ptr(b), bs,
                          _ptr(rgb), _ptr(tau), _ptr(tf), _ptr(ns))
     return rgb, tau, tf, ns
 
@@ -187,8 +203,9 @@ def render_bwd(g: Grid, rays_o, rays_d, grad_rgb, bg=(1.0, 1.0, 1.0)):
     gd = np.zeros(g.n_vox, np.float64)
     gs = np.zeros((g.n_vox, 27), np.float64)
     touched = np.zeros(g.n_vox, np.uint8)
+    b, bs = _bg(bg, o.shape[0])
     lib().orc_render_bwd(*_grid_args(g), _ptr(o), _ptr(d), o.shape[0],
-                         _ptr(_c(bg, np.float64)), _ptr(gr), _ptr(gd), _ptr(gs),
+                         _ptr(b), bs, _ptr(gr), _ptr(gd), _ptr(gs),
                          _ptr(touched))
     return gd, gs, touched
 
@@ -202,8 +219,9 @@ def render_bwd_mass(g: Grid, rays_o, rays_d, gabs_rgb, bg=(1.0, 1.0, 1.0), gate_
     ga = np.abs(_c(gabs_rgb, np.float64).reshape(-1, 3))
     md = np.zeros(g.n_vox, np.float64)
     ms = np.zeros((g.n_vox, 27), np.float64)
+    b, bs = _bg(bg, o.shape[0])
     lib().orc_render_bwd_mass(*_grid_args(g), _ptr(o), _ptr(d), o.shape[0],
-                              _ptr(_c(bg, np.float64)), _ptr(ga), float(gate_rel), _ptr(md),
+                              _ptr(b), bs, _ptr(ga), float(gate_rel), _ptr(md),
                               _ptr(ms))
     return md, ms
 
@@ -256,6 +274,46 @@ def rays_to_ndc(rays_o, rays_d, width, height, focal, near=1.0):
     lib().orc_rays_to_ndc(_ptr(o), _ptr(d), o.shape[0], int(width), int(height), float(focal), float(near),
                           _ptr(oo), _ptr(dd))
     return oo, dd
+
+
+def bg_grid(reso, mask, density, rgb_coef):
+    """MSI background grid of reso (L, H, W) from a mask and per-voxel
+    density [M] and degree-0 colour coefficients [M, 3] (SH slots 0, 9, 18)."""
+    index, m = grid_create(reso, mask)
+    dens = _c(density, np.float64).reshape(-1)
+    k = _c(rgb_coef, np.float64).reshape(-1, 3)
+    assert dens.shape[0] == m and k.shape[0] == m
+    sh = np.zeros((m, 27), np.float64)
+    sh[:, 0], sh[:, 9], sh[:, 18] = k[:, 0], k[:, 1], k[:, 2]
+    scale = np.ones(3, np.float32)
+    offset = np.zeros(3, np.float32)
+    return Grid(_c(reso, np.int32), scale, offset, np.float32(0.5), index, dens, sh)
+
+
+def bg_render_fwd(g: Grid, rays_o, rays_d, bg=(1.0, 1.0, 1.0)):
+    """Background colour of each ray and the transmittance left after it:
+    (rgb[R,3], t[R])."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    rgb = np.empty((o.shape[0], 3), np.float64)
+    t = np.empty(o.shape[0], np.float64)
+    lib().orc_bg_render_fwd(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d),
+                            o.shape[0], _ptr(_c(bg, np.float64)), _ptr(rgb), _ptr(t))
+    return rgb, t
+
+
+def bg_render_bwd(g: Grid, rays_o, rays_d, grad_rgb, bg=(1.0, 1.0, 1.0)):
+    """Gradient of the background colours for dL/dC_bg = grad_rgb:
+    (grad_density[M], grad_sh[M,27], touched[M])."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    gr = _c(grad_rgb, np.float64).reshape(-1, 3)
+    gd = np.zeros(g.n_vox, np.float64)
+    gs = np.zeros((g.n_vox, 27), np.float64)
+    touched = np.zeros(g.n_vox, np.uint8)
+    lib().orc_bg_render_bwd(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d),
+                            o.shape[0], _ptr(_c(bg, np.float64)), _ptr(gr), _ptr(gd), _ptr(gs), _ptr(touched))
+    return gd, gs, touched
 
 
 def ray_extent(g: Grid, o, d):

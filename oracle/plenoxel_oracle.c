@@ -31,6 +31,7 @@
  *     (Sec. 3.5, loss below Eq. (2); supplement B.1);
  *   - the Cauchy sparsity and beta transmittance priors (Sec. 3.7);
  *   - the NDC warp of rays for forward-facing scenes (Sec. 3.6);
+ *   - the MSI background model of 360-degree scenes (Sec. 3.6);
  *   - RMSProp (Sec. 3.5);
  *   - density-threshold pruning with dilation, the per-voxel maximum sample
  *     weight that pruning by weight thresholds, and trilinear resampling to
@@ -306,19 +307,21 @@ static int count_samples(const int32_t reso[3], const float scale[3],
 /* ------------------------------------------------------------------------ */
 /* Forward rendering of n_rays rays: rgb_out[3R], tau_out[R] (optical depth),
  * tfinal_out[R] (transmittance left after the last sample), nsamp_out[R]
- * (number of samples).  Any output may be NULL. */
+ * (number of samples).  Any output may be NULL.  The background colour of
+ * ray r is bg[bg_stride * r .. + 2]: bg_stride 0 gives every ray bg[0..2],
+ * 3 gives each ray its own (e.g. the MSI background behind it). */
 void orc_render_fwd(const int32_t reso[3], const float scale[3],
                     const float offset[3], float step, const int32_t *index,
                     const double *density, const double *sh,
                     const float *rays_o, const float *rays_d, int64_t n_rays,
-                    const double bg[3], double *rgb_out, double *tau_out,
+                    const double *bg, int64_t bg_stride, double *rgb_out, double *tau_out,
                     double *tfinal_out, int32_t *nsamp_out)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < n_rays; ++r) {
         double rgb[3], tau, tf;
         int n = march_ray(reso, scale, offset, step, index, density, sh,
-                          rays_o + 3 * r, rays_d + 3 * r, bg, NULL, 0, rgb,
+                          rays_o + 3 * r, rays_d + 3 * r, bg + bg_stride * r, NULL, 0, rgb,
                           &tau, &tf);
         if (rgb_out)
             for (int c = 0; c < 3; ++c) rgb_out[3 * r + c] = rgb[c];
@@ -443,6 +446,186 @@ void orc_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays,
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* MSI background of 360-degree scenes (Sec. 3.6, background model;
+ * supplement B.1).  A grid of reso = (L, H, W): L spheres around the origin,
+ * each an equirectangular image of H rows (polar angle theta from +z) and W
+ * columns (azimuth phi from +x towards +y), values at cell centres as in the
+ * foreground grid.  The radial grid coordinate is linear in inverse radius:
+ * u = (1 - 1/r) L - 0.5, so sphere l (u = l) has 1/r = 1 - (l + 1/2)/L,
+ * from just outside the unit sphere to far away (reading of the design
+ * notes).  Each voxel holds an opacity density and an RGB colour (only the
+ * degree-0 SH coefficient of each channel: sh slots 0, 9, 18; the others
+ * are ignored); NULL reads as zero.
+ *
+ * Samples of a ray (unit direction d, origin o inside the unit sphere): at
+ * u_k = k/2 for k = 0 .. 2(L-1)-1, at the point where the ray leaves the
+ * sphere of that inverse radius; a sample whose sphere does not contain o
+ * has no point in front and is skipped.  At the point p: phi = atan2(p_y,
+ * p_x) in [0, 2 pi), theta = acos(p_z/|p|), grid coordinates
+ * gx = phi/(2 pi) W - 1/2 (periodic: column W is column 0),
+ * gy = theta/pi H - 1/2 (clamped to [0, H-1] like the foreground lattice),
+ * gu = u_k; trilinear interpolation over the 8 surrounding voxels.
+ * Opacities are per unit of u (reading): alpha_k = 1 - exp(-sigma_k / 2),
+ * sigma_k = max(0, interpolated density), colour c = max(0, Y00 k) per
+ * channel (Y00 = 1/(2 sqrt(pi))), composited as in Eq. (1) and closed with
+ * the remaining transmittance times bg.  FP64 throughout. */
+
+#define ORC_Y00 0.28209479177387814
+#define ORC_PI 3.14159265358979323846
+
+typedef struct {
+    int64_t ids[8];
+    double w[8];
+} bg_sample_t;
+
+/* Corners and weights of background sample k; returns 0 when skipped. */
+static int bg_sample(const int32_t reso[3], const int32_t *index, const double o[3],
+                     const double d[3], int k, bg_sample_t *s)
+{
+    const int L = reso[0], H = reso[1], W = reso[2];
+    double u = 0.5 * k;
+    double inv_r = 1.0 - (u + 0.5) / (double)L;
+    double r = 1.0 / inv_r;
+    double b = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+    double c = o[0] * o[0] + o[1] * o[1] + o[2] * o[2] - r * r;
+    if (!(c < 0.0)) return 0;
+    double t = -b + sqrt(b * b - c);
+    double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    double pr = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    double cz = p[2] / pr;
+    cz = cz < -1.0 ? -1.0 : (cz > 1.0 ? 1.0 : cz);
+    double theta = acos(cz);
+    double phi = atan2(p[1], p[0]);
+    if (phi < 0.0) phi += 2.0 * ORC_PI;
+    double gx = phi / (2.0 * ORC_PI) * (double)W - 0.5;
+    double gy = theta / ORC_PI * (double)H - 0.5;
+    double fx0 = floor(gx);
+    double fx = gx - fx0;
+    int x0 = (int)fx0;
+    x0 = ((x0 % W) + W) % W;
+    int x1 = (x0 + 1) % W;
+    gy = gy < 0.0 ? 0.0 : (gy > (double)(H - 1) ? (double)(H - 1) : gy);
+    int y0 = (int)floor(gy);
+    if (y0 > H - 2) y0 = H - 2;
+    double fy = gy - y0;
+    int l0 = (int)floor(u);
+    if (l0 > L - 2) l0 = L - 2;
+    double fl = u - l0;
+    for (int cc = 0; cc < 8; ++cc) {
+        int dl = (cc >> 2) & 1, dy = (cc >> 1) & 1, dx = cc & 1;
+        int64_t cell = ((int64_t)(l0 + dl) * H + (y0 + dy)) * W + (dx ? x1 : x0);
+        s->ids[cc] = index[cell];
+        s->w[cc] = (dl ? fl : 1.0 - fl) * (dy ? fy : 1.0 - fy) * (dx ? fx : 1.0 - fx);
+    }
+    return 1;
+}
+
+/* Background colour of each ray: rgb_out[3R] = sum_k w_k c_k + T bg;
+ * t_out[R] (may be NULL) = the transmittance T left after the last sample. */
+void orc_bg_render_fwd(const int32_t reso[3], const int32_t *index, const double *density,
+                       const double *sh, const float *rays_o, const float *rays_d,
+                       int64_t n_rays, const double bg[3], double *rgb_out, double *t_out)
+{
+    const int L = reso[0];
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double o[3], d[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = (double)rays_o[3 * r + a];
+            d[a] = (double)rays_d[3 * r + a];
+        }
+        double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 2 * (L - 1); ++k) {
+            bg_sample_t s;
+            if (!bg_sample(reso, index, o, d, k, &s)) continue;
+            double sig = 0.0, kc[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 8; ++c) {
+                if (s.ids[c] < 0) continue;
+                sig += s.w[c] * density[s.ids[c]];
+                for (int ch = 0; ch < 3; ++ch) kc[ch] += s.w[c] * sh[s.ids[c] * ORC_NSH + 9 * ch];
+            }
+            double sigma = sig > 0.0 ? sig : 0.0;
+            double alpha = -expm1(-0.5 * sigma);
+            for (int ch = 0; ch < 3; ++ch) {
+                double col = ORC_Y00 * kc[ch];
+                C[ch] += T * alpha * (col > 0.0 ? col : 0.0);
+            }
+            T *= exp(-0.5 * sigma);
+        }
+        for (int ch = 0; ch < 3; ++ch) rgb_out[3 * r + ch] = C[ch] + T * bg[ch];
+        if (t_out) t_out[r] = T;
+    }
+}
+
+/* Gradient of the background colours for a given dL/dC_bg (grad_rgb[3R]),
+ * by the same chain rule as orc_render_bwd (R_k = what the ray collects
+ * after sample k, T_k before it):
+ *   dC/dsigma_k = (1/2)(T_{k+1} c_k - R_k),  dC/dc_k = w_k.
+ * ADDED into grad_density[M] and grad_sh[M*27] (slots 0, 9, 18 only);
+ * touched[M] = 1 for every non-NULL corner of every sample. */
+void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double *density,
+                       const double *sh, const float *rays_o, const float *rays_d,
+                       int64_t n_rays, const double bg[3], const double *grad_rgb,
+                       double *grad_density, double *grad_sh, uint8_t *touched)
+{
+    const int L = reso[0];
+    const int n_max = 2 * (L - 1);
+    bg_sample_t *smp = (bg_sample_t *)malloc(sizeof(bg_sample_t) * (size_t)n_max);
+    double *sg = (double *)malloc(sizeof(double) * (size_t)n_max * 8);
+    for (int64_t r = 0; r < n_rays; ++r) {
+        double o[3], d[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = (double)rays_o[3 * r + a];
+            d[a] = (double)rays_d[3 * r + a];
+        }
+        const double *g = grad_rgb + 3 * r;
+        /* forward, keeping each sample's values */
+        int n = 0;
+        double *sig_pre = sg, *col_pre = sg + n_max, *Tk = sg + 4 * n_max;
+        double T = 1.0;
+        for (int k = 0; k < n_max; ++k) {
+            if (!bg_sample(reso, index, o, d, k, &smp[n])) continue;
+            double sig = 0.0, kc[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = smp[n].ids[c];
+                if (id < 0) continue;
+                sig += smp[n].w[c] * density[id];
+                for (int ch = 0; ch < 3; ++ch) kc[ch] += smp[n].w[c] * sh[id * ORC_NSH + 9 * ch];
+            }
+            sig_pre[n] = sig;
+            for (int ch = 0; ch < 3; ++ch) col_pre[3 * n + ch] = ORC_Y00 * kc[ch];
+            Tk[n] = T;
+            T *= exp(-0.5 * (sig > 0.0 ? sig : 0.0));
+            ++n;
+        }
+        double R[3] = {T * bg[0], T * bg[1], T * bg[2]};
+        for (int j = n - 1; j >= 0; --j) {
+            double sigma = sig_pre[j] > 0.0 ? sig_pre[j] : 0.0;
+            double T_next = Tk[j] * exp(-0.5 * sigma);
+            double w = Tk[j] * -expm1(-0.5 * sigma);
+            double gc = 0.0, gR = 0.0, col[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                col[ch] = col_pre[3 * j + ch] > 0.0 ? col_pre[3 * j + ch] : 0.0;
+                gc += g[ch] * col[ch];
+                gR += g[ch] * R[ch];
+            }
+            double dsig = sig_pre[j] > 0.0 ? 0.5 * (T_next * gc - gR) : 0.0;
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = smp[j].ids[c];
+                if (id < 0) continue;
+                touched[id] = 1;
+                grad_density[id] += smp[j].w[c] * dsig;
+                for (int ch = 0; ch < 3; ++ch)
+                    if (col_pre[3 * j + ch] > 0.0)
+                        grad_sh[id * ORC_NSH + 9 * ch] += smp[j].w[c] * w * g[ch] * ORC_Y00;
+            }
+            for (int ch = 0; ch < 3; ++ch) R[ch] += w * col[ch];
+        }
+    }
+    free(sg);
+    free(smp);
+}
+
 /* Ray setup only, for tests: t_near/t_far of the FP32 recipe and the sample
  * count.  Returns 1 on hit. */
 int orc_ray_extent(const int32_t reso[3], const float scale[3],
@@ -474,7 +657,7 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
                     const float offset[3], float step, const int32_t *index,
                     const double *density, const double *sh,
                     const float *rays_o, const float *rays_d, int64_t n_rays,
-                    const double bg[3], const double *grad_rgb,
+                    const double *bg, int64_t bg_stride, const double *grad_rgb,
                     double *grad_density, double *grad_sh, uint8_t *touched)
 {
 #pragma omp parallel for schedule(dynamic, 16)
@@ -484,7 +667,8 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
         if (n == 0) continue;
         sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
         double rgb[3], tau, T_n;
-        march_ray(reso, scale, offset, step, index, density, sh, o, d, bg,
+        const double *bgr = bg + bg_stride * r;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, bgr,
                   recs, n, rgb, &tau, &T_n);
         double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
         double ylm[9];
@@ -493,7 +677,7 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
 
         /* R = what the ray collects after the current sample, built from the
          * back so that it is a plain sum. */
-        double R[3] = {T_n * bg[0], T_n * bg[1], T_n * bg[2]};
+        double R[3] = {T_n * bgr[0], T_n * bgr[1], T_n * bgr[2]};
         for (int k = n - 1; k >= 0; --k) {
             const sample_rec *s = &recs[k];
             double gc = 0.0, gR = 0.0;
@@ -545,7 +729,7 @@ void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
                          const int32_t *index, const double *density,
                          const double *sh, const float *rays_o,
                          const float *rays_d, int64_t n_rays,
-                         const double bg[3], const double *gabs_rgb,
+                         const double *bg, int64_t bg_stride, const double *gabs_rgb,
                          double gate_rel, double *mass_density, double *mass_sh)
 {
 #pragma omp parallel for schedule(dynamic, 16)
@@ -555,13 +739,14 @@ void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
         if (n == 0) continue;
         sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
         double rgb[3], tau, T_n;
-        march_ray(reso, scale, offset, step, index, density, sh, o, d, bg,
+        const double *bgr = bg + bg_stride * r;
+        march_ray(reso, scale, offset, step, index, density, sh, o, d, bgr,
                   recs, n, rgb, &tau, &T_n);
         double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
         double ylm[9];
         orc_sh_basis(dd, ylm);
         const double *g = gabs_rgb + 3 * r;
-        double R[3] = {T_n * fabs(bg[0]), T_n * fabs(bg[1]), T_n * fabs(bg[2])};
+        double R[3] = {T_n * fabs(bgr[0]), T_n * fabs(bgr[1]), T_n * fabs(bgr[2])};
         for (int k = n - 1; k >= 0; --k) {
             const sample_rec *s = &recs[k];
             /* absolute sums behind sigma_pre and the three colours */

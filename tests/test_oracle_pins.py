@@ -513,6 +513,121 @@ def test_prune_single_dense_voxel_survives_as_block():
 
 
 # ----------------------------------------------------------------------------
+# MSI background (Sec. 3.6)
+
+Y00 = 0.5 / math.sqrt(math.pi)
+
+
+def _bg_grid(reso, density, coef):
+    n = int(np.prod(reso))
+    return O.bg_grid(reso, np.ones(n, np.uint8), density, coef)
+
+
+def test_per_ray_background_colours():
+    # C is affine in the background colour with slope T_final, per ray; a
+    # per-ray colour array gives each ray what a call with its own colour does
+    sv = synth.dense_random((7, 8, 6), seed=14, occupancy=0.5)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(12, seed=15)
+    o, d = o.numpy(), d.numpy()
+    bgs = np.random.default_rng(16).uniform(0, 1, (12, 3))
+    rgb, _, tf, _ = O.render_fwd(g, o, d, bgs)
+    rgb0, _, _, _ = O.render_fwd(g, o, d, (0.0, 0.0, 0.0))
+    np.testing.assert_allclose(rgb, rgb0 + tf[:, None] * bgs, atol=1e-14)
+    for r in (0, 5, 11):
+        one, _, _, _ = O.render_fwd(g, o[r:r + 1], d[r:r + 1], bgs[r])
+        np.testing.assert_array_equal(rgb[r], one[0])
+    G = np.random.default_rng(17).normal(size=(12, 3))
+    gd, gs, _ = O.render_bwd(g, o, d, G, bgs)
+    for r in (2, 7):
+        gd1, gs1, _ = O.render_bwd(g, o[r:r + 1], d[r:r + 1], G[r:r + 1], bgs[r])
+        gd1b, gs1b, _ = O.render_bwd(g, o[r:r + 1], d[r:r + 1], G[r:r + 1], bgs[r:r + 1])
+        np.testing.assert_array_equal(gd1, gd1b)
+        np.testing.assert_array_equal(gs1, gs1b)
+
+
+def test_bg_constant_closed_form_and_skipped_spheres():
+    # constant opacity s and colour k: each of the 2(L-1) samples has
+    # alpha = 1 - exp(-s/2), so C = Y00 k (1 - T) + T bg with T = exp(-s (L-1)),
+    # from any origin inside the unit sphere in any direction
+    L, H, W, s0 = 9, 8, 16, 0.7
+    n = L * H * W
+    k = np.array([1.0, 2.0, -3.0])
+    g = _bg_grid((L, H, W), np.full(n, s0), np.tile(k, (n, 1)))
+    o, d = synth.random_rays(20, seed=11, radius=0.6, target_half=0.2)
+    bg = np.array([0.3, 0.5, 0.9])
+    rgb, t = O.bg_render_fwd(g, o.numpy(), d.numpy(), bg)
+    T = math.exp(-s0 * (L - 1))
+    np.testing.assert_allclose(t, T, rtol=1e-12)
+    np.testing.assert_allclose(rgb, np.tile(Y00 * np.maximum(k, 0) * (1 - T) + T * bg, (20, 1)), rtol=1e-12)
+    # from outside the unit sphere the spheres that do not contain the origin
+    # are skipped: sphere u has radius 1 / (1 - (u + 1/2)/L)
+    r_o = 1.3
+    u = 0.5 * np.arange(2 * (L - 1))
+    inside = (1.0 / (1.0 - (u + 0.5) / L)) > r_o
+    _, t2 = O.bg_render_fwd(g, [[0.0, 0.0, r_o]], [[0.0, 0.6, 0.8]], bg)
+    assert abs(t2[0] - math.exp(-0.5 * s0 * inside.sum())) < 1e-12 and 0 < inside.sum() < u.size
+
+
+def test_bg_equirectangular_lookup_and_wrap():
+    # an opaque first sphere (u = 0 holds only layer 0) with colour
+    # coefficient k(x, y) = x + 100 y: a ray from the centre sees the bilinear
+    # texel mix at its own direction; phi = 0 sits between the last and the
+    # first column (the image wraps), the poles clamp to the first/last row
+    L, H, W = 4, 6, 12
+    n = L * H * W
+    l, y, x = np.meshgrid(np.arange(L), np.arange(H), np.arange(W), indexing="ij")
+    dens = np.where(l.reshape(-1) == 0, 400.0, 0.0)
+    kr = (x + 100.0 * y).reshape(-1).astype(np.float64)
+    g = _bg_grid((L, H, W), dens, np.stack([kr, kr, kr], 1))
+    dirs = np.array([[1.0, 0, 0], [0, 1.0, 0], [-1.0, 0, 0], [0, 0, 1.0], [0, 0, -1.0]])
+    rgb, _ = O.bg_render_fwd(g, np.zeros((5, 3)), dirs, (0.0, 0.0, 0.0))
+    mid = 100.0 * (H / 2 - 0.5)  # the equator lies between rows H/2-1 and H/2
+    expect = [((W - 1) + 0) / 2 + mid, (W / 4 - 1 + W / 4) / 2 + mid, (W / 2 - 1 + W / 2) / 2 + mid, None, None]
+    a = 1.0 - math.exp(-200.0)
+    for i in range(3):
+        assert abs(rgb[i, 0] - a * Y00 * expect[i]) < 1e-9, i
+    # at the poles every column of the clamped row mixes in; the azimuth of a
+    # pole direction is atan2(0, 0) = 0 (phi = 0: the wrap columns)
+    assert abs(rgb[3, 0] - a * Y00 * ((W - 1) / 2 + 0.0)) < 1e-9
+    assert abs(rgb[4, 0] - a * Y00 * ((W - 1) / 2 + 100.0 * (H - 1))) < 1e-9
+
+
+def test_bg_fd_gradient():
+    L, H, W = 5, 6, 10
+    n = L * H * W
+    rng = np.random.default_rng(12)
+    dens = rng.uniform(0.0, 3.0, n)
+    coef = rng.uniform(-1.0, 3.0, (n, 3))
+    g = _bg_grid((L, H, W), dens, coef)
+    o, d = synth.random_rays(25, seed=13, radius=0.5, target_half=0.3)
+    o, d = o.numpy(), d.numpy()
+    bg = np.array([0.2, 0.7, 0.4])
+    G = rng.normal(size=(25, 3))
+    gd, gs, touched = O.bg_render_bwd(g, o, d, G, bg)
+    assert np.all(gs[:, [q for q in range(27) if q not in (0, 9, 18)]] == 0)
+
+    def loss():
+        return float((G * O.bg_render_fwd(g, o, d, bg)[0]).sum())
+
+    ids = np.flatnonzero(touched)
+    assert ids.size > 50
+    for m in rng.choice(ids, size=10, replace=False):
+        for arr, idx, an in ((g.density, m, gd[m]), (g.sh, (m, 9 * int(rng.integers(0, 3))), None)):
+            if an is None:
+                an = gs[idx]
+            x0 = arr[idx]
+            h = 1e-6 * max(1.0, abs(x0))
+            arr[idx] = x0 + h
+            lp = loss()
+            arr[idx] = x0 - h
+            lm = loss()
+            arr[idx] = x0
+            assert abs((lp - lm) / (2 * h) - an) <= 1e-6 * abs(an) + 1e-8, (m, idx)
+    assert np.all(gd[touched == 0] == 0) and np.all(gs[touched == 0] == 0)
+
+
+# ----------------------------------------------------------------------------
 # NDC warp of forward-facing scenes (Sec. 3.6)
 
 
