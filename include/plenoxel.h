@@ -97,7 +97,8 @@ typedef struct plx_grid {
  * in cells without a non-NULL corner have density 0 and add nothing; every
  * ray adds its beta term (a miss: the constant of T = 1).  reg_loss_sum
  * (device double[2], or NULL) gets L_s and L_b ADDED.  Zero-initialise the
- * struct: zero weights turn both priors off. */
+ * struct: zero weights turn both priors off, NULL per-ray arrays use
+ * background[].  A ray's colour is C = sum_k w_k c_k + T_final bg_ray. */
 typedef struct plx_render_opts {
     float background[3]; /* colour added with the transmittance left after the
                             last sample (white background of the synthetic
@@ -107,6 +108,15 @@ typedef struct plx_render_opts {
     float beta_eps;        /* > 0 when lambda_beta != 0: keeps L_b finite at
                               T = 0 and T = 1 */
     double *reg_loss_sum;  /* device double[2] or NULL: (L_s, L_b) ADDED */
+    const float *background_rgb; /* device [n_rays][3] or NULL: each ray's own
+                                    background colour, replacing background[]
+                                    (e.g. the MSI background behind it,
+                                    plx_bg_render_fwd); not used by
+                                    plx_render_views */
+    float *grad_background;      /* device [n_rays][3] or NULL: gradient calls
+                                    WRITE dL/d(background colour) = T_final
+                                    dL/dC per ray (the upstream gradient of
+                                    plx_bg_render_bwd) */
 } plx_render_opts;
 
 /* ---------------------------------------------------------------- misc */
@@ -254,6 +264,44 @@ int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stre
 int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, int32_t width,
                     int32_t height, double focal, double near, float *o_out, float *d_out,
                     plx_stream stream);
+
+/* ---------------------------------------------------------------- background */
+
+/* MSI background of 360-degree scenes (Sec. 3.6, background model;
+ * supplement B.1).  bg_grid is a grid of reso (L, H, W), L, H, W >= 2, with
+ * FP32 records (sh_dtype PLX_F32; its geometry fields must be valid but are
+ * not used): L spheres around the origin spaced linearly in inverse radius
+ * (radial grid coordinate u = (1 - 1/r) L - 1/2, sphere l at u = l, so
+ * 1/r = 1 - (l + 1/2)/L), each an equirectangular image of H rows (polar
+ * angle theta from +z: y = theta/pi H - 1/2, clamped to [0, H-1]) and W
+ * columns (azimuth phi in [0, 2 pi) from +x towards +y: x = phi/(2 pi) W - 1/2,
+ * periodic).  A voxel holds an opacity density (slot 28) and one colour
+ * coefficient per channel, the degree-0 SH term (slots 0, 9, 18; other
+ * slots are not read); NULL reads as zero.
+ *
+ * Ray samples: u_k = k/2, k = 0 .. 2(L-1)-1, at the point where the ray
+ * (unit direction, origin normally inside the unit sphere) leaves the sphere
+ * of that inverse radius (a sphere that does not contain the origin gives no
+ * sample); trilinear interpolation of density and coefficients; opacity per
+ * unit of u: alpha_k = 1 - exp(-max(0, sigma_k)/2); colour max(0, Y00 k)
+ * per channel (Y00 = 1/(2 sqrt(pi))); composited as in Eq. (1) and closed
+ * with the remaining transmittance times background[3] (host).  Sample
+ * geometry in FP64 (no contraction), values in FP32, optical depth in FP64.
+ *
+ * plx_bg_render_fwd: rgb_out (device [n_rays][3]) = the background colour of
+ * each ray, t_out (device [n_rays] or NULL) = its remaining transmittance.
+ * Pass rgb_out as plx_render_opts.background_rgb of the foreground calls.
+ * plx_bg_render_bwd: for dL/d(background colour) = grad_rgb (device
+ * [n_rays][3], e.g. plx_render_opts.grad_background of the foreground
+ * gradient call), ADDS the gradients of the densities and the three
+ * coefficients into grad (device [M] FP32 records, FP32 atomics) and sets
+ * touched (device uint8 [M]) to 1 for every non-NULL corner of every sample. */
+int plx_bg_render_fwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
+                      int64_t n_rays, const float background[3], float *rgb_out, float *t_out,
+                      plx_stream stream);
+int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
+                      int64_t n_rays, const float background[3], const float *grad_rgb, float *grad,
+                      uint8_t *touched, plx_stream stream);
 
 /* ---------------------------------------------------------------- render */
 

@@ -74,7 +74,7 @@ def lib():
         L.orc_rays_to_ndc.restype = None
         L.orc_bg_render_fwd.argtypes = [_P, _P, _P, _P, _P, _P, i64, _P, _P, _P]
         L.orc_bg_render_fwd.restype = None
-        L.orc_bg_render_bwd.argtypes = [_P, _P, _P, _P, _P, _P, i64, _P, _P, _P, _P, _P]
+        L.orc_bg_render_bwd.argtypes = [_P, _P, _P, _P, _P, _P, i64, _P, _P, f64, _P, _P, _P]
         L.orc_bg_render_bwd.restype = None
         L.orc_ray_extent.argtypes = [_P, _P, _P, f32, _P, _P, _P, _P, _P]
         L.orc_ray_extent.restype = i32
@@ -312,8 +312,24 @@ def bg_render_bwd(g: Grid, rays_o, rays_d, grad_rgb, bg=(1.0, 1.0, 1.0)):
     gs = np.zeros((g.n_vox, 27), np.float64)
     touched = np.zeros(g.n_vox, np.uint8)
     lib().orc_bg_render_bwd(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d),
-                            o.shape[0], _ptr(_c(bg, np.float64)), _ptr(gr), _ptr(gd), _ptr(gs), _ptr(touched))
+                            o.shape[0], _ptr(_c(bg, np.float64)), _ptr(gr), -1.0, _ptr(gd), _ptr(gs),
+                            _ptr(touched))
     return gd, gs, touched
+
+
+def bg_render_bwd_mass(g: Grid, rays_o, rays_d, gabs_rgb, bg=(1.0, 1.0, 1.0), gate_rel=0.0):
+    """Absolute-term sums of the background gradient for |dL/dC_bg| =
+    gabs_rgb (see orc_bg_render_bwd): (mass_density[M], mass_sh[M,27])."""
+    o = _c(rays_o, np.float32).reshape(-1, 3)
+    d = _c(rays_d, np.float32).reshape(-1, 3)
+    ga = np.abs(_c(gabs_rgb, np.float64).reshape(-1, 3))
+    md = np.zeros(g.n_vox, np.float64)
+    ms = np.zeros((g.n_vox, 27), np.float64)
+    touched = np.zeros(g.n_vox, np.uint8)
+    lib().orc_bg_render_bwd(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh), _ptr(o), _ptr(d),
+                            o.shape[0], _ptr(_c(bg, np.float64)), _ptr(ga), max(0.0, float(gate_rel)), _ptr(md),
+                            _ptr(ms), _ptr(touched))
+    return md, ms
 
 
 def ray_extent(g: Grid, o, d):

@@ -562,16 +562,22 @@ void orc_bg_render_fwd(const int32_t reso[3], const int32_t *index, const double
  * after sample k, T_k before it):
  *   dC/dsigma_k = (1/2)(T_{k+1} c_k - R_k),  dC/dc_k = w_k.
  * ADDED into grad_density[M] and grad_sh[M*27] (slots 0, 9, 18 only);
- * touched[M] = 1 for every non-NULL corner of every sample. */
+ * touched[M] = 1 for every non-NULL corner of every sample.
+ * With gate_rel >= 0 the call instead ADDS the absolute sizes of the terms
+ * (for tolerances, as orc_render_bwd_mass: grad_rgb holds |dL/dC|, the
+ * density term counts as (1/2)(T_{k+1} g.c + g.R), and a term behind a
+ * ReLU gate within gate_rel times its absolute sum of the kink counts as
+ * open); gate_rel < 0 gives the gradient. */
 void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double *density,
                        const double *sh, const float *rays_o, const float *rays_d,
                        int64_t n_rays, const double bg[3], const double *grad_rgb,
-                       double *grad_density, double *grad_sh, uint8_t *touched)
+                       double gate_rel, double *grad_density, double *grad_sh, uint8_t *touched)
 {
+    const int absolute = gate_rel >= 0.0;
     const int L = reso[0];
     const int n_max = 2 * (L - 1);
     bg_sample_t *smp = (bg_sample_t *)malloc(sizeof(bg_sample_t) * (size_t)n_max);
-    double *sg = (double *)malloc(sizeof(double) * (size_t)n_max * 8);
+    double *sg = (double *)malloc(sizeof(double) * (size_t)n_max * 9);
     for (int64_t r = 0; r < n_rays; ++r) {
         double o[3], d[3];
         for (int a = 0; a < 3; ++a) {
@@ -582,6 +588,7 @@ void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double
         /* forward, keeping each sample's values */
         int n = 0;
         double *sig_pre = sg, *col_pre = sg + n_max, *Tk = sg + 4 * n_max;
+        double *abs_sig = sg + 5 * n_max, *abs_col = sg + 6 * n_max;
         double T = 1.0;
         for (int k = 0; k < n_max; ++k) {
             if (!bg_sample(reso, index, o, d, k, &smp[n])) continue;
@@ -594,29 +601,43 @@ void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double
             }
             sig_pre[n] = sig;
             for (int ch = 0; ch < 3; ++ch) col_pre[3 * n + ch] = ORC_Y00 * kc[ch];
+            double as = 0.0, ac[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 8; ++c) {
+                int64_t id = smp[n].ids[c];
+                if (id < 0) continue;
+                as += smp[n].w[c] * fabs(density[id]);
+                for (int ch = 0; ch < 3; ++ch) ac[ch] += smp[n].w[c] * ORC_Y00 * fabs(sh[id * ORC_NSH + 9 * ch]);
+            }
+            abs_sig[n] = as;
+            for (int ch = 0; ch < 3; ++ch) abs_col[3 * n + ch] = ac[ch];
             Tk[n] = T;
             T *= exp(-0.5 * (sig > 0.0 ? sig : 0.0));
             ++n;
         }
-        double R[3] = {T * bg[0], T * bg[1], T * bg[2]};
+        double R[3];
+        for (int ch = 0; ch < 3; ++ch) R[ch] = T * (absolute ? fabs(bg[ch]) : bg[ch]);
         for (int j = n - 1; j >= 0; --j) {
             double sigma = sig_pre[j] > 0.0 ? sig_pre[j] : 0.0;
             double T_next = Tk[j] * exp(-0.5 * sigma);
             double w = Tk[j] * -expm1(-0.5 * sigma);
             double gc = 0.0, gR = 0.0, col[3];
+            int col_on[3];
             for (int ch = 0; ch < 3; ++ch) {
-                col[ch] = col_pre[3 * j + ch] > 0.0 ? col_pre[3 * j + ch] : 0.0;
+                double pre = col_pre[3 * j + ch];
+                col[ch] = pre > 0.0 ? pre : 0.0;
+                col_on[ch] = pre > 0.0 || (absolute && fabs(pre) <= gate_rel * abs_col[3 * j + ch]);
                 gc += g[ch] * col[ch];
                 gR += g[ch] * R[ch];
             }
-            double dsig = sig_pre[j] > 0.0 ? 0.5 * (T_next * gc - gR) : 0.0;
+            int sig_on = sig_pre[j] > 0.0 || (absolute && fabs(sig_pre[j]) <= gate_rel * abs_sig[j]);
+            double dsig = sig_on ? 0.5 * (absolute ? T_next * gc + gR : T_next * gc - gR) : 0.0;
             for (int c = 0; c < 8; ++c) {
                 int64_t id = smp[j].ids[c];
                 if (id < 0) continue;
                 touched[id] = 1;
                 grad_density[id] += smp[j].w[c] * dsig;
                 for (int ch = 0; ch < 3; ++ch)
-                    if (col_pre[3 * j + ch] > 0.0)
+                    if (col_on[ch])
                         grad_sh[id * ORC_NSH + 9 * ch] += smp[j].w[c] * w * g[ch] * ORC_Y00;
             }
             for (int ch = 0; ch < 3; ++ch) R[ch] += w * col[ch];

@@ -56,6 +56,8 @@ class PlxRenderOpts(ctypes.Structure):
         ("lambda_beta", ctypes.c_float),
         ("beta_eps", ctypes.c_float),
         ("reg_loss_sum", ctypes.c_void_p),
+        ("background_rgb", ctypes.c_void_p),
+        ("grad_background", ctypes.c_void_p),
     ]
 
 
@@ -113,6 +115,8 @@ _SIGS = {
     "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
     "plx_rays_to_ndc": ([_P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double, _P, _P, _P],
                         ctypes.c_int),
+    "plx_bg_render_fwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "plx_bg_render_bwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -292,8 +296,17 @@ def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid):
 
 # --------------------------------------------------------------------- render
 
-def _opts(bg, priors: Priors | None = None):
-    o = PlxRenderOpts((ctypes.c_float * 3)(*[float(x) for x in bg]))
+def _opts(bg, priors: Priors | None = None, n: int | None = None, grad_bg=None):
+    """bg: one colour (3 numbers) or a device float32 tensor [R, 3] of
+    per-ray background colours; priors: the optional priors; grad_bg: device
+    float32 [R, 3] that gradient calls fill with dL/d(background colour)."""
+    if isinstance(bg, torch.Tensor):
+        o = PlxRenderOpts((ctypes.c_float * 3)(0.0, 0.0, 0.0))
+        o.background_rgb = _dptr(bg, "background_rgb", torch.float32, None if n is None else 3 * n)
+    else:
+        o = PlxRenderOpts((ctypes.c_float * 3)(*[float(x) for x in bg]))
+    if grad_bg is not None:
+        o.grad_background = _dptr(grad_bg, "grad_bg", torch.float32, None if n is None else 3 * n)
     if priors is not None:
         o.lambda_sparsity = float(priors.lambda_sparsity)
         o.lambda_beta = float(priors.lambda_beta)
@@ -310,9 +323,28 @@ def plx_rays_to_ndc(rays_o, rays_d, width, height, focal, near, o_out, d_out):
                                  _dptr(d_out, "d_out", torch.float32, 3 * n), _stream()))
 
 
+def plx_bg_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, t_out=None, bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().plx_bg_render_fwd(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n), n, b,
+                                   _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                   _dptr(t_out, "t_out", torch.float32, n), _stream()))
+
+
+def plx_bg_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, grad, touched, bg=(1.0, 1.0, 1.0)):
+    n = rays_o.shape[0]
+    b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().plx_bg_render_bwd(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n), n, b,
+                                   _dptr(grad_rgb, "grad_rgb", torch.float32, 3 * n),
+                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                   _dptr(touched, "touched", torch.uint8), _stream()))
+
+
 def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0)):
     n = rays_o.shape[0]
-    o = _opts(bg)
+    o = _opts(bg, None, n)
     _check(lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
@@ -321,9 +353,9 @@ def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1
 
 
 def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
-                   bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
+                   bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None):
     n = rays_o.shape[0]
-    o = _opts(bg, priors)
+    o = _opts(bg, priors, n, grad_bg)
     _check(lib().plx_render_bwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
@@ -334,9 +366,9 @@ def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
 
 
 def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
-                     rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
+                     rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None):
     n = rays_o.shape[0]
-    o = _opts(bg, priors)
+    o = _opts(bg, priors, n, grad_bg)
     _check(lib().plx_render_train(ctypes.byref(g), ctypes.byref(o),
                                   _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n),
@@ -370,7 +402,7 @@ def plx_render_max_weight(g: PlxGrid, rays_o, rays_d, wmax):
 def plx_render_fwd_state(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out, state, cap,
                          bg=(1.0, 1.0, 1.0)):
     n = rays_o.shape[0]
-    o = _opts(bg)
+    o = _opts(bg, None, n)
     sp, sb = _state_ptr(state, n, cap)
     _check(lib().plx_render_fwd_state(ctypes.byref(g), ctypes.byref(o),
                                       _dptr(rays_o, "rays_o", torch.float32, 3 * n),
@@ -381,9 +413,9 @@ def plx_render_fwd_state(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out, state, ca
 
 
 def plx_render_bwd_state(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, state, cap, grad, touched,
-                         bg=(1.0, 1.0, 1.0), priors: Priors | None = None):
+                         bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None):
     n = rays_o.shape[0]
-    o = _opts(bg, priors)
+    o = _opts(bg, priors, n, grad_bg)
     sp, sb = _state_ptr(state, n, cap)
     _check(lib().plx_render_bwd_state(ctypes.byref(g), ctypes.byref(o),
                                       _dptr(rays_o, "rays_o", torch.float32, 3 * n),

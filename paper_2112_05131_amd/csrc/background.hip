@@ -1,0 +1,282 @@
+// background.hip -- the multi-sphere (MSI) background model of 360-degree
+// scenes (Sec. 3.6, background model; supplement B.1) for gfx950.
+//
+// The background is a grid of reso (L, H, W): L spheres around the origin,
+// spaced linearly in inverse radius (grid coordinate u = (1 - 1/r) L - 1/2,
+// sphere l at u = l), each an equirectangular image of H rows (polar angle
+// from +z) and W columns (azimuth from +x towards +y).  Voxels hold an
+// opacity density (record slot 28) and a degree-0 colour coefficient per
+// channel (slots 0, 9, 18) in FP32 records; NULL reads as zero.  A ray's
+// samples sit at u = k/2, k = 0 .. 2(L-1)-1, where the ray leaves that
+// sphere (spheres that do not contain the origin are skipped), and
+// interpolate trilinearly (the azimuth wraps, the poles clamp); opacities are
+// per unit of u, so alpha = 1 - exp(-sigma/2).  The foreground renderer takes
+// each ray's background colour from here and hands back T_final dL/dC, the
+// gradient of that colour (plx_render_opts).
+//
+// One ray per lane.  The sample geometry (sphere hit, angles, cell and
+// weights) is FP64 in the same operation order as the definition, without
+// contraction, so both the samples' cells and their weights are reproducible;
+// interpolation and compositing are FP32 with the optical depth in FP64, as
+// in the foreground.  The backward pass first recomputes the optical depth,
+// then replays the samples from the last to the first; a lane accumulates
+// the gradient of the 8 corners of its current cell and flushes them (FP32
+// atomics into the records) when the cell changes.
+#include <cmath>
+
+#include "plx_internal.hpp"
+
+namespace plx {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kY00 = 0.28209479177387814f;
+
+struct BgArgs {
+    const int32_t *index;
+    const float *rec;  // FP32 records
+    int L, H, W;
+    const float *rays_o;
+    const float *rays_d;
+    int64_t n_rays;
+    float bg[3];
+    float *rgb_out;        // fwd
+    float *t_out;          // fwd, optional
+    const float *grad_rgb; // bwd
+    float *grad;           // bwd
+    uint8_t *touched;      // bwd
+};
+
+// Corner ids and weights of sample k of the ray; false when the sample's
+// sphere does not contain the origin.  *cell gets the lower corner's id in
+// the grid (for cache keys).
+__device__ bool bg_sample(const BgArgs &a, const double o[3], const double d[3], int k, int ids[8],
+                          float w[8], int64_t *cell) {
+#pragma clang fp contract(off)
+    const double u = 0.5 * (double)k;
+    const double inv_r = 1.0 - (u + 0.5) / (double)a.L;
+    const double r = 1.0 / inv_r;
+    const double b = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+    const double c = o[0] * o[0] + o[1] * o[1] + o[2] * o[2] - r * r;
+    if (!(c < 0.0)) return false;
+    const double t = -b + sqrt(b * b - c);
+    const double p0 = o[0] + t * d[0], p1 = o[1] + t * d[1], p2 = o[2] + t * d[2];
+    const double pr = sqrt(p0 * p0 + p1 * p1 + p2 * p2);
+    double cz = p2 / pr;
+    cz = cz < -1.0 ? -1.0 : (cz > 1.0 ? 1.0 : cz);
+    const double theta = acos(cz);
+    double phi = atan2(p1, p0);
+    if (phi < 0.0) phi += 2.0 * kPi;
+    const double gx = phi / (2.0 * kPi) * (double)a.W - 0.5;
+    double gy = theta / kPi * (double)a.H - 0.5;
+    const double fx0 = floor(gx);
+    const double fx = gx - fx0;
+    int x0 = (int)fx0;
+    x0 = ((x0 % a.W) + a.W) % a.W;
+    const int x1 = (x0 + 1) % a.W;
+    gy = gy < 0.0 ? 0.0 : (gy > (double)(a.H - 1) ? (double)(a.H - 1) : gy);
+    int y0 = (int)floor(gy);
+    if (y0 > a.H - 2) y0 = a.H - 2;
+    const double fy = gy - y0;
+    int l0 = (int)floor(u);
+    if (l0 > a.L - 2) l0 = a.L - 2;
+    const double fl = u - l0;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+        const int dl = (cc >> 2) & 1, dy = (cc >> 1) & 1, dx = cc & 1;
+        const int64_t id = ((int64_t)(l0 + dl) * a.H + (y0 + dy)) * a.W + (dx ? x1 : x0);
+        ids[cc] = a.index[id];
+        w[cc] = (float)((dl ? fl : 1.0 - fl) * (dy ? fy : 1.0 - fy) * (dx ? fx : 1.0 - fx));
+    }
+    *cell = ((int64_t)l0 * a.H + y0) * a.W + x0;
+    return true;
+}
+
+struct BgVal {
+    float s, r, g, b;  // pre-activation density and colour coefficients
+};
+
+__device__ __forceinline__ BgVal bg_interp(const BgArgs &a, const int ids[8], const float w[8]) {
+    BgVal v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (ids[c] < 0) continue;
+        const float *p = a.rec + (int64_t)ids[c] * PLX_REC_SLOTS;
+        v.s += w[c] * p[PLX_SLOT_SIGMA];
+        v.r += w[c] * p[0];
+        v.g += w[c] * p[9];
+        v.b += w[c] * p[18];
+    }
+    return v;
+}
+
+__device__ __forceinline__ void load_ray(const BgArgs &a, int64_t ray, double o[3], double d[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        o[i] = (double)a.rays_o[3 * ray + i];
+        d[i] = (double)a.rays_d[3 * ray + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void bg_fwd_kernel(BgArgs a) {
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    double o[3], d[3];
+    load_ray(a, ray, o, d);
+    double tau = 0.0;
+    float C[3] = {0.f, 0.f, 0.f};
+    const int n = 2 * (a.L - 1);
+    for (int k = 0; k < n; ++k) {
+        int ids[8];
+        float w[8];
+        int64_t cell;
+        if (!bg_sample(a, o, d, k, ids, w, &cell)) continue;
+        const BgVal v = bg_interp(a, ids, w);
+        const float sd = 0.5f * fmaxf(v.s, 0.0f);
+        const float wk = expf(-(float)tau) * (-expm1f(-sd));
+        C[0] += wk * fmaxf(kY00 * v.r, 0.0f);
+        C[1] += wk * fmaxf(kY00 * v.g, 0.0f);
+        C[2] += wk * fmaxf(kY00 * v.b, 0.0f);
+        tau += (double)sd;
+    }
+    const float T = expf(-(float)tau);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.rgb_out[3 * ray + c] = C[c] + T * a.bg[c];
+    if (a.t_out) a.t_out[ray] = T;
+}
+
+__device__ __forceinline__ void bg_flush(const BgArgs &a, const int ids[8], const BgVal acc[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int id = ids[c];
+        if (id < 0) continue;
+        float *g = a.grad + (int64_t)id * PLX_REC_SLOTS;
+        if (acc[c].s != 0.0f) unsafeAtomicAdd(g + PLX_SLOT_SIGMA, acc[c].s);
+        if (acc[c].r != 0.0f) unsafeAtomicAdd(g + 0, acc[c].r);
+        if (acc[c].g != 0.0f) unsafeAtomicAdd(g + 9, acc[c].g);
+        if (acc[c].b != 0.0f) unsafeAtomicAdd(g + 18, acc[c].b);
+        a.touched[id] = 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
+    const int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ray >= a.n_rays) return;
+    double o[3], d[3];
+    load_ray(a, ray, o, d);
+    const int n = 2 * (a.L - 1);
+    // optical depth of the whole ray
+    double tau = 0.0;
+    for (int k = 0; k < n; ++k) {
+        int ids[8];
+        float w[8];
+        int64_t cell;
+        if (!bg_sample(a, o, d, k, ids, w, &cell)) continue;
+        tau += (double)(0.5f * fmaxf(bg_interp(a, ids, w).s, 0.0f));
+    }
+    const float g[3] = {a.grad_rgb[3 * ray], a.grad_rgb[3 * ray + 1], a.grad_rgb[3 * ray + 2]};
+    double tau_after = tau;
+    float T_after = expf(-(float)tau_after);
+    float gR = T_after * (g[0] * a.bg[0] + g[1] * a.bg[1] + g[2] * a.bg[2]);
+    int cur_ids[8];
+    BgVal acc[8];
+    int64_t cur_cell = -1;
+    for (int k = n - 1; k >= 0; --k) {
+        int ids[8];
+        float w[8];
+        int64_t cell;
+        if (!bg_sample(a, o, d, k, ids, w, &cell)) continue;
+        if (cell != cur_cell) {
+            if (cur_cell >= 0) bg_flush(a, cur_ids, acc);
+            cur_cell = cell;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                cur_ids[c] = ids[c];
+                acc[c] = BgVal{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        const BgVal v = bg_interp(a, ids, w);
+        const float sd = 0.5f * fmaxf(v.s, 0.0f);
+        const double tau_before = fmax(tau_after - (double)sd, 0.0);
+        const float T_before = expf(-(float)tau_before);
+        const float wk = T_before * (-expm1f(-sd));
+        const float cr = kY00 * v.r, cg = kY00 * v.g, cb = kY00 * v.b;
+        const float gc = g[0] * fmaxf(cr, 0.0f) + g[1] * fmaxf(cg, 0.0f) + g[2] * fmaxf(cb, 0.0f);
+        const float dsig = v.s > 0.0f ? 0.5f * (T_after * gc - gR) : 0.0f;
+        const float dr = cr > 0.0f ? wk * g[0] * kY00 : 0.0f;
+        const float dg = cg > 0.0f ? wk * g[1] * kY00 : 0.0f;
+        const float db = cb > 0.0f ? wk * g[2] * kY00 : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            acc[c].s += w[c] * dsig;
+            acc[c].r += w[c] * dr;
+            acc[c].g += w[c] * dg;
+            acc[c].b += w[c] * db;
+        }
+        gR += wk * gc;
+        tau_after = tau_before;
+        T_after = T_before;
+    }
+    if (cur_cell >= 0) bg_flush(a, cur_ids, acc);
+}
+
+int bg_args(const plx_grid *grid, const float *rays_o, const float *rays_d, int64_t n_rays,
+            const float background[3], BgArgs &a, const char *fn) {
+    int rc = validate_grid(grid, false, fn);
+    if (rc) return rc;
+    if (grid->sh_dtype != PLX_F32) return fail(PLX_EINVAL, "%s: background records must be FP32", fn);
+    if (n_rays < 0 || n_rays > ((int64_t)1 << 34)) return fail(PLX_EINVAL, "%s: bad n_rays", fn);
+    if (n_rays > 0 && (!rays_o || !rays_d)) return fail(PLX_EINVAL, "%s: rays are NULL", fn);
+    if (!background) return fail(PLX_EINVAL, "%s: background is NULL", fn);
+    a = BgArgs{};
+    a.index = grid->index;
+    a.rec = static_cast<const float *>(grid->data);
+    a.L = grid->reso[0];
+    a.H = grid->reso[1];
+    a.W = grid->reso[2];
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.n_rays = n_rays;
+    for (int i = 0; i < 3; ++i) a.bg[i] = background[i];
+    return PLX_OK;
+}
+
+}  // namespace
+}  // namespace plx
+
+using namespace plx;
+
+extern "C" {
+
+int plx_bg_render_fwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
+                      int64_t n_rays, const float background[3], float *rgb_out, float *t_out,
+                      plx_stream stream) {
+    const char *fn = "plx_bg_render_fwd";
+    BgArgs a;
+    int rc = bg_args(bg_grid, rays_o, rays_d, n_rays, background, a, fn);
+    if (rc) return rc;
+    if (n_rays == 0) return PLX_OK;
+    if (!rgb_out) return fail(PLX_EINVAL, "%s: rgb_out is NULL", fn);
+    a.rgb_out = rgb_out;
+    a.t_out = t_out;
+    bg_fwd_kernel<<<(unsigned)((n_rays + 255) / 256), 256, 0, as_stream(stream)>>>(a);
+    return check_launch(fn);
+}
+
+int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
+                      int64_t n_rays, const float background[3], const float *grad_rgb, float *grad,
+                      uint8_t *touched, plx_stream stream) {
+    const char *fn = "plx_bg_render_bwd";
+    BgArgs a;
+    int rc = bg_args(bg_grid, rays_o, rays_d, n_rays, background, a, fn);
+    if (rc) return rc;
+    if (n_rays == 0) return PLX_OK;
+    if (!grad_rgb || !grad || !touched) return fail(PLX_EINVAL, "%s: NULL grad_rgb/grad/touched", fn);
+    a.grad_rgb = grad_rgb;
+    a.grad = grad;
+    a.touched = touched;
+    bg_bwd_kernel<<<(unsigned)((n_rays + 255) / 256), 256, 0, as_stream(stream)>>>(a);
+    return check_launch(fn);
+}
+
+}  // extern "C"

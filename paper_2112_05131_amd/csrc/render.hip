@@ -78,6 +78,13 @@ struct Priors {
     double *loss;      // [2] (L_s, L_b) ADDED, or NULL
 };
 
+// Background colour of a ray: its own when the call gives one per ray.
+__device__ __forceinline__ void ray_background(const float *bg_rgb, const float bg[3], int64_t ray,
+                                               float out[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = bg_rgb ? bg_rgb[3 * ray + c] : bg[c];
+}
+
 // Beta prior of one ray from its optical depth tau (FP64; 1 - T = -expm1(-tau)
 // stays accurate for a nearly empty ray): returns dL_b/dsigma_k / delta_k =
 // -T dL_b/dT, the factor of each of its samples' density gradient, and adds
@@ -129,6 +136,8 @@ struct RenderArgs {
     int st_cap;
     int64_t n_rays;
     float bg[3];
+    const float *bg_rgb;    // optional per-ray background colours [n_rays][3]
+    float *grad_bg;         // BWD, optional: T_final dL/dC per ray [n_rays][3]
     float loss_scale;
     Priors pri;
     int n_blocks;
@@ -652,8 +661,10 @@ __global__ __launch_bounds__(kThreads) void render_fwd_kernel(GridDev g, RenderA
         march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
     }
     const float T_final = expf(-(float)tau);
+    float bgc[3];
+    ray_background(a.bg_rgb, a.bg, ray, bgc);
 #pragma unroll
-    for (int c3 = 0; c3 < 3; ++c3) a.rgb_out[3 * ray + c3] = C[c3] + T_final * a.bg[c3];
+    for (int c3 = 0; c3 < 3; ++c3) a.rgb_out[3 * ray + c3] = C[c3] + T_final * bgc[c3];
     if (a.tau_out) a.tau_out[ray] = (float)tau;
 }
 
@@ -723,9 +734,17 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 
     double tau_after = tau;
     float T_after = expf(-(float)tau_after);
+    float bgc[3] = {0.f, 0.f, 0.f};
+    if (live) {
+        ray_background(a.bg_rgb, a.bg, ray, bgc);
+        if (a.grad_bg) {
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) a.grad_bg[3 * ray + c3] = T_after * gr[c3];
+        }
+    }
     // g . R_k less the beta factor: dC/dsigma_k's delta (T_{k+1} g.c_k - g.R_k)
     // and the beta term's delta gw then share one running sum
-    float gR = T_after * (gr[0] * a.bg[0] + gr[1] * a.bg[1] + gr[2] * a.bg[2]) - gw;
+    float gR = T_after * (gr[0] * bgc[0] + gr[1] * bgc[1] + gr[2] * bgc[2]) - gw;
     // the cache may hold the forward pass's last cell: its corners have
     // nothing accumulated yet, which is what the backward expects
     Cursor cur{k_hi, 0, 0u};
@@ -899,6 +918,8 @@ struct BinArgs {
     int64_t n_rays;
     int64_t n_seg;
     float bg[3];
+    const float *bg_rgb;    // optional per-ray background colours [n_rays][3]
+    float *grad_bg;         // TRAIN/BWD, optional: T_final dL/dC per ray [n_rays][3]
     float loss_scale;
     int n_blocks;  // blocks of the launch at hand (rays or segments)
     int nb8;
@@ -1097,10 +1118,11 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
             tau += a.tau_seg[s];
         }
         const float T_final = expf(-(float)tau);
-        float gr[3], R[3];
+        float gr[3], R[3], bgc[3];
+        ray_background(a.bg_rgb, a.bg, ray, bgc);
 #pragma unroll
         for (int c3 = 0; c3 < 3; ++c3) {
-            const float Cc = C[c3] + T_final * a.bg[c3];
+            const float Cc = C[c3] + T_final * bgc[c3];
             if (MODE != MODE_BWD && a.rgb_out) a.rgb_out[3 * ray + c3] = Cc;
             if (MODE == MODE_TRAIN) {
                 const float diff = Cc - a.target[3 * ray + c3];
@@ -1109,13 +1131,17 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
             } else if (MODE == MODE_BWD) {
                 gr[c3] = a.grad_rgb[3 * ray + c3];
             }
-            R[c3] = T_final * a.bg[c3];
+            R[c3] = T_final * bgc[c3];
         }
         if (MODE == MODE_FWD) {
             if (a.tau_out) a.tau_out[ray] = (float)tau;
         } else {
             const float gw = a.pri.lambda_b != 0.0f ? beta_factor(a.pri, tau, &lb) : 0.0f;
             a.g_ray[ray] = make_float4(gr[0], gr[1], gr[2], gw);
+            if (a.grad_bg) {
+#pragma unroll
+                for (int c3 = 0; c3 < 3; ++c3) a.grad_bg[3 * ray + c3] = T_final * gr[c3];
+            }
             for (int64_t s = s1 - 1; s >= s0; --s) {
                 a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
                 const float T = expf(-(float)a.tau_in[s]);
@@ -1688,6 +1714,8 @@ RenderArgs base_args(const plx_render_opts *opts, const float *o, const float *d
     a.rays_d = d;
     a.n_rays = n;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    a.bg_rgb = opts->background_rgb;
+    a.grad_bg = opts->grad_background;
     return a;
 }
 
@@ -1714,6 +1742,8 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     a.tau_out = tau_out;
     a.n_rays = n_rays;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    a.bg_rgb = opts->background_rgb;
+    a.grad_bg = opts->grad_background;
     return render_binned<MODE_FWD>(grid, a, as_stream(stream), fn);
 }
 
@@ -1736,6 +1766,8 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     a.touched = touched;
     a.n_rays = n_rays;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    a.bg_rgb = opts->background_rgb;
+    a.grad_bg = opts->grad_background;
     return render_binned<MODE_BWD>(grid, a, as_stream(stream), fn);
 }
 
@@ -1776,6 +1808,8 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     a.touched = touched;
     a.n_rays = n_rays;
     for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    a.bg_rgb = opts->background_rgb;
+    a.grad_bg = opts->grad_background;
     a.loss_scale = loss_scale;
     return render_binned<MODE_TRAIN>(grid, a, as_stream(stream), fn);
 }

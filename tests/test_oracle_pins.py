@@ -625,6 +625,12 @@ def test_bg_fd_gradient():
             arr[idx] = x0
             assert abs((lp - lm) / (2 * h) - an) <= 1e-6 * abs(an) + 1e-8, (m, idx)
     assert np.all(gd[touched == 0] == 0) and np.all(gs[touched == 0] == 0)
+    # the absolute-term mass dominates the gradient and equals it where no
+    # terms cancel (colour slots with a positive upstream gradient)
+    md, ms = O.bg_render_bwd_mass(g, o, d, np.abs(G), bg)
+    assert np.all(md >= np.abs(gd) * (1 - 1e-12)) and np.all(ms >= np.abs(gs) * (1 - 1e-12))
+    gp, sp, _ = O.bg_render_bwd(g, o, d, np.abs(G), bg)
+    np.testing.assert_allclose(sp, ms, rtol=1e-12, atol=1e-300)
 
 
 # ----------------------------------------------------------------------------
