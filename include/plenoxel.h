@@ -276,8 +276,9 @@ int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, in
  * angle theta from +z: y = theta/pi H - 1/2, clamped to [0, H-1]) and W
  * columns (azimuth phi in [0, 2 pi) from +x towards +y: x = phi/(2 pi) W - 1/2,
  * periodic).  A voxel holds an opacity density (slot 28) and one colour
- * coefficient per channel, the degree-0 SH term (slots 0, 9, 18; other
- * slots are not read); NULL reads as zero.
+ * coefficient per channel, the degree-0 SH term (slots 24, 25, 26: with the
+ * density one 64-byte line of the record; other slots are not read); NULL
+ * reads as zero.
  *
  * Ray samples: u_k = k/2, k = 0 .. 2(L-1)-1, at the point where the ray
  * (unit direction, origin normally inside the unit sphere) leaves the sphere
@@ -294,7 +295,8 @@ int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, in
  * plx_bg_render_bwd: for dL/d(background colour) = grad_rgb (device
  * [n_rays][3], e.g. plx_render_opts.grad_background of the foreground
  * gradient call), ADDS the gradients of the densities and the three
- * coefficients into grad (device [M] FP32 records, FP32 atomics) and sets
+ * coefficients into grad (device [M] FP32 records, slots 24-26 and 28, FP32
+ * atomics) and sets
  * touched (device uint8 [M]) to 1 for every non-NULL corner of every sample. */
 int plx_bg_render_fwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
                       int64_t n_rays, const float background[3], float *rgb_out, float *t_out,

@@ -278,13 +278,13 @@ def rays_to_ndc(rays_o, rays_d, width, height, focal, near=1.0):
 
 def bg_grid(reso, mask, density, rgb_coef):
     """MSI background grid of reso (L, H, W) from a mask and per-voxel
-    density [M] and degree-0 colour coefficients [M, 3] (SH slots 0, 9, 18)."""
+    density [M] and degree-0 colour coefficients [M, 3] (sh slots 24-26)."""
     index, m = grid_create(reso, mask)
     dens = _c(density, np.float64).reshape(-1)
     k = _c(rgb_coef, np.float64).reshape(-1, 3)
     assert dens.shape[0] == m and k.shape[0] == m
     sh = np.zeros((m, 27), np.float64)
-    sh[:, 0], sh[:, 9], sh[:, 18] = k[:, 0], k[:, 1], k[:, 2]
+    sh[:, 24:27] = k
     scale = np.ones(3, np.float32)
     offset = np.zeros(3, np.float32)
     return Grid(_c(reso, np.int32), scale, offset, np.float32(0.5), index, dens, sh)

@@ -455,8 +455,9 @@ void orc_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays,
  * u = (1 - 1/r) L - 0.5, so sphere l (u = l) has 1/r = 1 - (l + 1/2)/L,
  * from just outside the unit sphere to far away (reading of the design
  * notes).  Each voxel holds an opacity density and an RGB colour (only the
- * degree-0 SH coefficient of each channel: sh slots 0, 9, 18; the others
- * are ignored); NULL reads as zero.
+ * degree-0 SH coefficient of each channel, kept in sh slots 24, 25, 26 of
+ * the record, next to the density; the others are ignored); NULL reads as
+ * zero.
  *
  * Samples of a ray (unit direction d, origin o inside the unit sphere): at
  * u_k = k/2 for k = 0 .. 2(L-1)-1, at the point where the ray leaves the
@@ -473,6 +474,7 @@ void orc_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays,
 
 #define ORC_Y00 0.28209479177387814
 #define ORC_PI 3.14159265358979323846
+#define ORC_BG_SLOT 24
 
 typedef struct {
     int64_t ids[8];
@@ -542,7 +544,7 @@ void orc_bg_render_fwd(const int32_t reso[3], const int32_t *index, const double
             for (int c = 0; c < 8; ++c) {
                 if (s.ids[c] < 0) continue;
                 sig += s.w[c] * density[s.ids[c]];
-                for (int ch = 0; ch < 3; ++ch) kc[ch] += s.w[c] * sh[s.ids[c] * ORC_NSH + 9 * ch];
+                for (int ch = 0; ch < 3; ++ch) kc[ch] += s.w[c] * sh[s.ids[c] * ORC_NSH + ORC_BG_SLOT + ch];
             }
             double sigma = sig > 0.0 ? sig : 0.0;
             double alpha = -expm1(-0.5 * sigma);
@@ -561,7 +563,7 @@ void orc_bg_render_fwd(const int32_t reso[3], const int32_t *index, const double
  * by the same chain rule as orc_render_bwd (R_k = what the ray collects
  * after sample k, T_k before it):
  *   dC/dsigma_k = (1/2)(T_{k+1} c_k - R_k),  dC/dc_k = w_k.
- * ADDED into grad_density[M] and grad_sh[M*27] (slots 0, 9, 18 only);
+ * ADDED into grad_density[M] and grad_sh[M*27] (slots 24, 25, 26 only);
  * touched[M] = 1 for every non-NULL corner of every sample.
  * With gate_rel >= 0 the call instead ADDS the absolute sizes of the terms
  * (for tolerances, as orc_render_bwd_mass: grad_rgb holds |dL/dC|, the
@@ -597,7 +599,7 @@ void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double
                 int64_t id = smp[n].ids[c];
                 if (id < 0) continue;
                 sig += smp[n].w[c] * density[id];
-                for (int ch = 0; ch < 3; ++ch) kc[ch] += smp[n].w[c] * sh[id * ORC_NSH + 9 * ch];
+                for (int ch = 0; ch < 3; ++ch) kc[ch] += smp[n].w[c] * sh[id * ORC_NSH + ORC_BG_SLOT + ch];
             }
             sig_pre[n] = sig;
             for (int ch = 0; ch < 3; ++ch) col_pre[3 * n + ch] = ORC_Y00 * kc[ch];
@@ -606,7 +608,7 @@ void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double
                 int64_t id = smp[n].ids[c];
                 if (id < 0) continue;
                 as += smp[n].w[c] * fabs(density[id]);
-                for (int ch = 0; ch < 3; ++ch) ac[ch] += smp[n].w[c] * ORC_Y00 * fabs(sh[id * ORC_NSH + 9 * ch]);
+                for (int ch = 0; ch < 3; ++ch) ac[ch] += smp[n].w[c] * ORC_Y00 * fabs(sh[id * ORC_NSH + ORC_BG_SLOT + ch]);
             }
             abs_sig[n] = as;
             for (int ch = 0; ch < 3; ++ch) abs_col[3 * n + ch] = ac[ch];
@@ -638,7 +640,7 @@ void orc_bg_render_bwd(const int32_t reso[3], const int32_t *index, const double
                 grad_density[id] += smp[j].w[c] * dsig;
                 for (int ch = 0; ch < 3; ++ch)
                     if (col_on[ch])
-                        grad_sh[id * ORC_NSH + 9 * ch] += smp[j].w[c] * w * g[ch] * ORC_Y00;
+                        grad_sh[id * ORC_NSH + ORC_BG_SLOT + ch] += smp[j].w[c] * w * g[ch] * ORC_Y00;
             }
             for (int ch = 0; ch < 3; ++ch) R[ch] += w * col[ch];
         }

@@ -39,6 +39,14 @@ class TrainConfig:
     lambda_sparsity: float = 0.0
     lambda_beta: float = 0.0
     beta_eps: float = 1e-3
+    # MSI background of 360-degree scenes (used when the trainer has one):
+    # pure exponential decay of its learning rates (supplement B.1: no delay
+    # for the background), and the colour behind its last sphere
+    lr_bg_sigma0: float = 3.0
+    lr_bg_sigma1: float = 0.05
+    lr_bg_color0: float = 1e-2
+    lr_bg_color1: float = 5e-6
+    bg_background: tuple = (0.0, 0.0, 0.0)
 
 
 class RaySampler:
@@ -81,13 +89,33 @@ class RaySampler:
 
 
 class Trainer:
-    """Holds the optimiser state of one grid and runs training steps."""
+    """Holds the optimiser state of one grid (and of an optional MSI
+    background grid) and runs training steps."""
 
-    def __init__(self, grid: Grid, cfg: TrainConfig | None = None, seed: int = 0):
+    def __init__(self, grid: Grid, cfg: TrainConfig | None = None, seed: int = 0,
+                 background: Grid | None = None):
         self.cfg = cfg or TrainConfig()
         self.rng = np.random.default_rng(seed)
         self.step_id = 0
         self.set_grid(grid)
+        self.set_background(background)
+
+    def set_background(self, bg: Grid | None):
+        """Attach an MSI background grid (reso (L, H, W), FP32 records); its
+        optimiser state starts from zero."""
+        self.bg = bg
+        self._bg_bufs = None
+        if bg is not None:
+            m = bg.n_vox
+            self.bg_grad = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=bg.device)
+            self.bg_vstate = torch.zeros(m, B.REC_SLOTS, dtype=torch.float32, device=bg.device)
+            self.bg_touched = torch.zeros(m, dtype=torch.uint8, device=bg.device)
+
+    def _bg_buffers(self, n):
+        if self._bg_bufs is None or self._bg_bufs[0].shape[0] != n:
+            dev = self.bg.device
+            self._bg_bufs = (torch.empty(n, 3, device=dev), torch.empty(n, 3, device=dev))
+        return self._bg_bufs
 
     def set_grid(self, grid: Grid):
         """Attach a (new) grid; the optimiser state starts from zero."""
@@ -128,12 +156,28 @@ class Trainer:
         c, g = self.cfg, self.grid
         lr_s, lr_h = self.learning_rates()
         n = rays_o.shape[0]
-        B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
-                           self.touched, self.loss_sum, rgb_out, c.background, self.priors())
+        if self.bg is None:
+            B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
+                               self.touched, self.loss_sum, rgb_out, c.background, self.priors())
+        else:
+            # background colours -> fused foreground step (which hands back
+            # their gradient) -> background gradient
+            cbg, gbg = self._bg_buffers(n)
+            B.plx_bg_render_fwd(self.bg.desc(), rays_o, rays_d, cbg, None, c.bg_background)
+            B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
+                               self.touched, self.loss_sum, rgb_out, cbg, self.priors(), gbg)
+            B.plx_bg_render_bwd(self.bg.desc(), rays_o, rays_d, gbg, self.bg_grad, self.bg_touched,
+                                c.bg_background)
         if tv and (c.lambda_tv_sigma > 0 or c.lambda_tv_sh > 0):
             start, count = self.tv_segment()
             B.plx_tv_grad(g.desc(), start, count, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps,
                           self.grad, self.touched, self.tv_loss_sum)
         B.plx_rmsprop_step(g.desc(), g.master, self.vstate, self.grad, self.touched, lr_s, lr_h,
                            c.beta, c.eps)
+        if self.bg is not None:
+            t = self.step_id
+            lr_bs = B.plx_lr_schedule(t, c.lr_bg_sigma0, c.lr_bg_sigma1, c.lr_max_steps)
+            lr_bc = B.plx_lr_schedule(t, c.lr_bg_color0, c.lr_bg_color1, c.lr_max_steps)
+            B.plx_rmsprop_step(self.bg.desc(), None, self.bg_vstate, self.bg_grad, self.bg_touched, lr_bs, lr_bc,
+                               c.beta, c.eps)
         self.step_id += 1

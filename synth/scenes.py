@@ -163,6 +163,29 @@ def sphere_poses(n: int, seed: int, radius: float = 2.0) -> torch.Tensor:
     return poses
 
 
+def sky_background(reso, seed: int, shell=(0.4, 0.5), sigma: float = 12.0):
+    """Values of an MSI background grid of reso (L, H, W) for the 360-degree
+    scenes: every voxel stored; density `sigma` in the layers between the
+    fractions shell[0] and shell[1] of L (0 elsewhere); degree-0 colour
+    coefficients smooth in the voxel-centre angles (theta = pi (y + 1/2)/H,
+    phi = 2 pi (x + 1/2)/W) with seeded frequencies and phases.  Returns
+    (mask uint8 [L*H*W], density float32 [M], coef float32 [M, 3])."""
+    L, H, W = (int(r) for r in reso)
+    g = _gen(seed)
+    f1 = torch.randint(1, 4, (3,), generator=g).double()
+    f2 = torch.randint(1, 3, (3,), generator=g).double()
+    ph = torch.rand(3, 2, generator=g, dtype=torch.float64) * 2.0 * np.pi
+    l = torch.arange(L, dtype=torch.float64)[:, None, None]
+    th = (np.pi * (torch.arange(H, dtype=torch.float64) + 0.5) / H)[None, :, None]
+    phi = (2.0 * np.pi * (torch.arange(W, dtype=torch.float64) + 0.5) / W)[None, None, :]
+    dens = torch.where((l >= shell[0] * L) & (l < shell[1] * L), sigma, 0.0).expand(L, H, W)
+    coef = torch.stack([1.8 + 0.9 * torch.sin(f1[c] * phi + ph[c, 0]) * torch.sin(th) +
+                        0.5 * torch.cos(f2[c] * th + ph[c, 1]) + 0.0 * l for c in range(3)], dim=-1)
+    coef = coef.expand(L, H, W, 3)
+    mask = torch.ones(L * H * W, dtype=torch.uint8)
+    return mask, dens.reshape(-1).float().contiguous(), coef.reshape(-1, 3).float().contiguous()
+
+
 def forward_facing_poses(n: int, seed: int, spread: float = 0.1, tilt_deg: float = 3.0) -> torch.Tensor:
     """n camera-to-world matrices [n,3,4] (float64) of a forward-facing
     capture: centres uniform in the square [-spread, spread]^2 of the plane

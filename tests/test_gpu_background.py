@@ -33,7 +33,7 @@ def bg_pair(reso, seed, occupancy=0.7, sigma_hi=4.0):
     dens = (torch.rand(m, generator=g, dtype=torch.float64) * sigma_hi).float()
     coef = (torch.rand(m, 3, generator=g, dtype=torch.float64) * 4.0 - 1.0).float()
     sh = torch.zeros(m, 27)
-    sh[:, 0], sh[:, 9], sh[:, 18] = coef[:, 0], coef[:, 1], coef[:, 2]
+    sh[:, 24:27] = coef
     og = O.bg_grid(reso, mask.numpy(), dens.double().numpy(), coef.double().numpy())
     gg = Grid.from_mask(mask.cuda(), reso, dens.cuda(), sh.cuda())
     return og, gg
@@ -83,8 +83,8 @@ def test_bg_forward_backward_match_oracle(reso, seed):
     gd, gs, t_touch = O.bg_render_bwd(og, o.numpy(), d.numpy(), G.double().numpy(), bgc)
     assert_touched_equal(touched, t_touch, "bg bwd")
     assert_grads_close(grad, gd, gs, "bg bwd", bg_mass(og, o.numpy(), d.numpy(), G.double().numpy(), bgc))
-    # only the density and the three degree-0 slots are written
-    used = [0, 9, 18, 28]
+    # only the density and the three colour slots are written
+    used = [24, 25, 26, 28]
     rest = [q for q in range(32) if q not in used]
     assert torch.all(grad[:, rest] == 0)
 
