@@ -86,6 +86,8 @@ def lib():
         L.orc_render_bwd_mass.restype = None
         L.orc_tv.argtypes = [_P, _P, _P, _P, i64, i64, f64, f64, f64, _P, _P, _P]
         L.orc_tv.restype = f64
+        L.orc_bg_tv.argtypes = [_P, _P, _P, _P, i64, i64, f64, f64, f64, _P, _P, _P]
+        L.orc_bg_tv.restype = f64
         L.orc_rmsprop.argtypes = [i64, _P, _P, _P, _P, _P, _P, _P, f64, f64, f64, f64]
         L.orc_rmsprop.restype = None
         L.orc_grid_create.argtypes = [_P, _P, _P]
@@ -352,6 +354,18 @@ def tv(g: Grid, start, count, lambda_sigma, lambda_sh, eps=1e-9):
     loss = lib().orc_tv(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh),
                         int(start), int(count), float(lambda_sigma), float(lambda_sh),
                         float(eps), _ptr(gd), _ptr(gs), _ptr(touched))
+    return float(loss), gd, gs, touched
+
+
+def bg_tv(g: Grid, start, count, lambda_sigma, lambda_color, eps=1e-9):
+    """TV of an MSI background grid (azimuth wraps, colour slots 24-26):
+    loss, grad_density[M], grad_sh[M,27], touched[M]."""
+    gd = np.zeros(g.n_vox, np.float64)
+    gs = np.zeros((g.n_vox, 27), np.float64)
+    touched = np.zeros(g.n_vox, np.uint8)
+    loss = lib().orc_bg_tv(_ptr(g.reso), _ptr(g.index), _ptr(g.density), _ptr(g.sh),
+                           int(start), int(count), float(lambda_sigma), float(lambda_color),
+                           float(eps), _ptr(gd), _ptr(gs), _ptr(touched))
     return float(loss), gd, gs, touched
 
 

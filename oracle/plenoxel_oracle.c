@@ -48,6 +48,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* record slots of the MSI background's three colour coefficients */
+#define ORC_BG_SLOT 24
+
 #define ORC_NSH 27 /* 3 colour channels x 9 degree-2 SH coefficients */
 
 /* ------------------------------------------------------------------------ */
@@ -474,7 +477,6 @@ void orc_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays,
 
 #define ORC_Y00 0.28209479177387814
 #define ORC_PI 3.14159265358979323846
-#define ORC_BG_SLOT 24
 
 typedef struct {
     int64_t ids[8];
@@ -896,10 +898,11 @@ void orc_regularisers(const int32_t reso[3], const float scale[3],
  * lambda_sh/|V| sum term_sh with |V| = count.  Gradients are ADDED; every
  * non-NULL voxel among v and its three forward neighbours is marked touched.
  * Returns the loss. */
-double orc_tv(const int32_t reso[3], const int32_t *index,
-              const double *density, const double *sh, int64_t start,
-              int64_t count, double lambda_sigma, double lambda_sh, double eps,
-              double *grad_density, double *grad_sh, uint8_t *touched)
+static double tv_impl(const int32_t reso[3], const int32_t *index,
+                      const double *density, const double *sh, int64_t start,
+                      int64_t count, double lambda_sigma, double lambda_sh, double eps,
+                      double *grad_density, double *grad_sh, uint8_t *touched,
+                      int q_lo, int q_hi, int wrap_last)
 {
     const int64_t ncell = (int64_t)reso[0] * reso[1] * reso[2];
     double s_axis[3];
@@ -914,10 +917,10 @@ double orc_tv(const int32_t reso[3], const int32_t *index,
         int k = (int)(v % reso[2]);
         int64_t id = index[v];
         int64_t nid[3];
-        int in_range[3] = {i + 1 < reso[0], j + 1 < reso[1], k + 1 < reso[2]};
+        int in_range[3] = {i + 1 < reso[0], j + 1 < reso[1], wrap_last || k + 1 < reso[2]};
         nid[0] = in_range[0] ? index[lin_id(reso, i + 1, j, k)] : -1;
         nid[1] = in_range[1] ? index[lin_id(reso, i, j + 1, k)] : -1;
-        nid[2] = in_range[2] ? index[lin_id(reso, i, j, k + 1)] : -1;
+        nid[2] = in_range[2] ? index[lin_id(reso, i, j, (k + 1) % reso[2])] : -1;
 
         /* density channel */
         {
@@ -945,7 +948,7 @@ double orc_tv(const int32_t reso[3], const int32_t *index,
         }
         /* SH channels */
         if (id >= 0) {
-            for (int q = 0; q < ORC_NSH; ++q) {
+            for (int q = q_lo; q < q_hi; ++q) {
                 double x0 = sh[id * ORC_NSH + q];
                 double dlt[3], ss = 0.0;
                 for (int a = 0; a < 3; ++a) {
@@ -968,6 +971,29 @@ double orc_tv(const int32_t reso[3], const int32_t *index,
         }
     }
     return lambda_sigma * inv_v * sum_sigma + lambda_sh * inv_v * sum_sh;
+}
+
+double orc_tv(const int32_t reso[3], const int32_t *index,
+              const double *density, const double *sh, int64_t start,
+              int64_t count, double lambda_sigma, double lambda_sh, double eps,
+              double *grad_density, double *grad_sh, uint8_t *touched)
+{
+    return tv_impl(reso, index, density, sh, start, count, lambda_sigma, lambda_sh, eps,
+                   grad_density, grad_sh, touched, 0, ORC_NSH, 0);
+}
+
+/* The same TV on an MSI background grid (reso (L, H, W)): the colour terms
+ * are its three colour coefficients (sh slots 24-26) instead of the 27 SH
+ * coefficients, and the azimuth axis (the last) wraps around: the
+ * neighbour of column W-1 is column 0 (supplement B.1: the background's TV
+ * wraps around the edges of the equirectangular image). */
+double orc_bg_tv(const int32_t reso[3], const int32_t *index,
+                 const double *density, const double *sh, int64_t start,
+                 int64_t count, double lambda_sigma, double lambda_color, double eps,
+                 double *grad_density, double *grad_sh, uint8_t *touched)
+{
+    return tv_impl(reso, index, density, sh, start, count, lambda_sigma, lambda_color, eps,
+                   grad_density, grad_sh, touched, ORC_BG_SLOT, ORC_BG_SLOT + 3, 1);
 }
 
 /* ------------------------------------------------------------------------ */

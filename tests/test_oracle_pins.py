@@ -523,6 +523,49 @@ def _bg_grid(reso, density, coef):
     return O.bg_grid(reso, np.ones(n, np.uint8), density, coef)
 
 
+def test_bg_tv_wraps_the_azimuth_closed_form():
+    # colour coefficient k = column x in all three slots, constant along rows
+    # and layers: only the azimuth differences count, (W/256) per step and
+    # (W/256)(0 - (W-1)) from the last column back to the first
+    L, H, W = 3, 4, 10
+    l, y, x = np.meshgrid(np.arange(L), np.arange(H), np.arange(W), indexing="ij")
+    g = _bg_grid((L, H, W), np.zeros(L * H * W), np.repeat(x.reshape(-1, 1).astype(float), 3, 1))
+    n = L * H * W
+    loss, gd, gs, touched = O.bg_tv(g, 0, n, 0.0, 1.0, 1e-14)
+    expect = 3 * L * H * 2 * (W - 1) * (W / 256.0) / n
+    assert abs(loss - expect) < 1e-9
+    assert np.all(gs[:, :24] == 0) and np.all(gd == 0) and touched.all()
+    # without the wrap the last column would add nothing: the plain TV of the
+    # same values (colour slots 24-26 are SH slots there) is smaller
+    loss_plain, _, gs_plain, _ = O.tv(g, 0, n, 0.0, 1.0, 1e-14)
+    # (terms without a difference add sqrt(eps) = 1e-7 each: the 24 other SH
+    # slots of every cell and the 3 colour slots of the last column)
+    sq = (24 * n + 3 * L * H) * 1e-7
+    assert abs(loss_plain - (3 * L * H * (W - 1) * (W / 256.0) + sq) / n) < 1e-9
+
+
+def test_bg_tv_finite_differences():
+    L, H, W = 4, 5, 6
+    n = L * H * W
+    rng = np.random.default_rng(18)
+    mask = (rng.uniform(size=n) < 0.7).astype(np.uint8)
+    m = int(mask.sum())
+    g = O.bg_grid((L, H, W), mask, rng.uniform(0, 3, m), rng.uniform(-1, 2, (m, 3)))
+    start, count, eps = n - 40, 90, 1e-6
+    _, gd, gs, touched = O.bg_tv(g, start, count, 0.7, 1.1, eps)
+    for mm in rng.choice(np.flatnonzero(touched), size=15, replace=False):
+        for arr, idx, an in ((g.density, mm, gd[mm]), (g.sh, (mm, 24 + int(rng.integers(0, 3))), None)):
+            an = gs[idx] if an is None else an
+            x0 = arr[idx]
+            h = 1e-6
+            arr[idx] = x0 + h
+            lp = O.bg_tv(g, start, count, 0.7, 1.1, eps)[0]
+            arr[idx] = x0 - h
+            lm = O.bg_tv(g, start, count, 0.7, 1.1, eps)[0]
+            arr[idx] = x0
+            assert abs((lp - lm) / (2 * h) - an) <= 1e-6 * abs(an) + 1e-10
+
+
 def test_per_ray_background_colours():
     # C is affine in the background colour with slope T_final, per ray; a
     # per-ray colour array gives each ray what a call with its own colour does
