@@ -298,6 +298,16 @@ int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, in
  * coefficients into grad (device [M] FP32 records, slots 24-26 and 28, FP32
  * atomics) and sets
  * touched (device uint8 [M]) to 1 for every non-NULL corner of every sample. */
+/* TV of the MSI background (supplement B.1: the same TV as plx_tv_grad,
+ * wrapping around the edges of the equirectangular image): plx_tv_grad's
+ * terms, normalisation, segment and errors, with the colour terms taken over
+ * the three colour coefficients (slots 24-26, weight lambda_color) and the
+ * last (azimuth) axis periodic: column W-1's neighbour is column 0.  FP32
+ * records only. */
+int plx_bg_tv_grad(const plx_grid *bg_grid, int64_t cell_start, int64_t cell_count,
+                   float lambda_sigma, float lambda_color, float eps, float *grad, uint8_t *touched,
+                   double *loss_sum, plx_stream stream);
+
 int plx_bg_render_fwd(const plx_grid *bg_grid, const float *rays_o, const float *rays_d,
                       int64_t n_rays, const float background[3], float *rgb_out, float *t_out,
                       plx_stream stream);

@@ -115,6 +115,7 @@ _SIGS = {
     "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
     "plx_rays_to_ndc": ([_P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double, _P, _P, _P],
                         ctypes.c_int),
+    "plx_bg_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_bg_render_fwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "plx_bg_render_bwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
@@ -465,6 +466,15 @@ def plx_tv_grad(g: PlxGrid, cell_start, cell_count, lambda_sigma, lambda_sh, eps
                              _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
                              _dptr(touched, "touched", torch.uint8),
                              _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_bg_tv_grad(g: PlxGrid, cell_start, cell_count, lambda_sigma, lambda_color, eps, grad, touched,
+                   loss_sum=None):
+    _check(lib().plx_bg_tv_grad(ctypes.byref(g), int(cell_start), int(cell_count), float(lambda_sigma),
+                                float(lambda_color), float(eps),
+                                _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                _dptr(touched, "touched", torch.uint8),
+                                _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
 
 
 def plx_touched_count(touched, n_vox) -> int:

@@ -10,6 +10,8 @@
 // difference): the block collects its non-NULL cells in LDS and then handles
 // each with 32 lanes, lane q = coefficient q, so the four records are read and
 // the four gradient records updated with one line-wide access each.
+// The MSI background's instance uses its three colour coefficients as the
+// colour terms and wraps its last (azimuth) axis.
 // Gradients go to the cell and its neighbours with float atomics
 // (neighbouring cells share voxels); the loss is reduced per block and added
 // once in FP64.
@@ -18,7 +20,11 @@
 namespace plx {
 namespace {
 
-template <int DT>
+// BG: the MSI background grid's TV, whose colour terms are its three colour
+// coefficients (record slots 24-26) and whose last (azimuth) axis wraps.
+constexpr int kBgSlot = 24;
+
+template <int DT, bool BG>
 __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64_t count,
                                                  int64_t ncell, float lam_sig_v, float lam_sh_v,
                                                  float eps, float s0, float s1, float s2,
@@ -41,7 +47,7 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
         const int64_t sy = g.nz, sx = (int64_t)g.ny * g.nz;
         const int id = g.index[v];
         const int nid[3] = {i + 1 < g.nx ? g.index[v + sx] : -1, j + 1 < g.ny ? g.index[v + sy] : -1,
-                            k + 1 < g.nz ? g.index[v + 1] : -1};
+                            k + 1 < g.nz ? g.index[v + 1] : (BG ? g.index[v - k] : -1)};
 
         // density channel: NULL or out-of-range reads 0
         {
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
         const int4 cl = cells[e];
         const int nb[3] = {cl.y, cl.z, cl.w};
         float term = 0.0f;
-        if (q < PLX_NSH) {
+        if (BG ? (q >= kBgSlot && q < kBgSlot + 3) : q < PLX_NSH) {
             const float x0 = rec_slot<DT>(g.data, cl.x, q);
             float dl[3], ss = 0.0f;
 #pragma unroll
@@ -122,12 +128,15 @@ __global__ __launch_bounds__(256) void tv_kernel(GridDev g, int64_t start, int64
 
 using namespace plx;
 
-extern "C" int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
-                           float lambda_sigma, float lambda_sh, float eps, float *grad,
-                           uint8_t *touched, double *loss_sum, plx_stream stream) {
-    const char *fn = "plx_tv_grad";
+namespace plx {
+namespace {
+
+int tv_launch(const plx_grid *grid, int64_t cell_start, int64_t cell_count, float lambda_sigma,
+              float lambda_sh, float eps, float *grad, uint8_t *touched, double *loss_sum,
+              plx_stream stream, bool bg, const char *fn) {
     int rc = validate_grid(grid, false, fn);
     if (rc) return rc;
+    if (bg && grid->sh_dtype != PLX_F32) return fail(PLX_EINVAL, "%s: background records must be FP32", fn);
     if (cell_count < 0) return fail(PLX_EINVAL, "%s: cell_count < 0", fn);
     if (cell_count == 0) return PLX_OK;
     if (!grad || !touched) return fail(PLX_EINVAL, "%s: grad/touched is NULL", fn);
@@ -139,9 +148,32 @@ extern "C" int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cel
     const unsigned nb = (unsigned)((cell_count + 255) / 256);
     GridDev g = to_dev(grid);
     const float s0 = grid->reso[0] / 256.0f, s1 = grid->reso[1] / 256.0f, s2 = grid->reso[2] / 256.0f;
-    PLX_DISPATCH_DT(grid->sh_dtype, DT,
-                    tv_kernel<DT><<<nb, 256, 0, s>>>(g, start, cell_count, ncell, lambda_sigma * inv,
-                                                     lambda_sh * inv, eps, s0, s1, s2, grad, touched,
-                                                     loss_sum));
+    if (bg) {
+        tv_kernel<PLX_F32, true><<<nb, 256, 0, s>>>(g, start, cell_count, ncell, lambda_sigma * inv,
+                                                    lambda_sh * inv, eps, s0, s1, s2, grad, touched,
+                                                    loss_sum);
+    } else {
+        PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                        tv_kernel<DT, false><<<nb, 256, 0, s>>>(g, start, cell_count, ncell,
+                                                                lambda_sigma * inv, lambda_sh * inv, eps,
+                                                                s0, s1, s2, grad, touched, loss_sum));
+    }
     return check_launch(fn);
+}
+
+}  // namespace
+}  // namespace plx
+
+extern "C" int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
+                           float lambda_sigma, float lambda_sh, float eps, float *grad,
+                           uint8_t *touched, double *loss_sum, plx_stream stream) {
+    return tv_launch(grid, cell_start, cell_count, lambda_sigma, lambda_sh, eps, grad, touched, loss_sum,
+                     stream, false, "plx_tv_grad");
+}
+
+extern "C" int plx_bg_tv_grad(const plx_grid *bg_grid, int64_t cell_start, int64_t cell_count,
+                              float lambda_sigma, float lambda_color, float eps, float *grad,
+                              uint8_t *touched, double *loss_sum, plx_stream stream) {
+    return tv_launch(bg_grid, cell_start, cell_count, lambda_sigma, lambda_color, eps, grad, touched,
+                     loss_sum, stream, true, "plx_bg_tv_grad");
 }

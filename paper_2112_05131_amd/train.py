@@ -47,6 +47,10 @@ class TrainConfig:
     lr_bg_color0: float = 1e-2
     lr_bg_color1: float = 5e-6
     bg_background: tuple = (0.0, 0.0, 0.0)
+    # TV of the background (wrapping its azimuth), on tv_fraction of its cells
+    # (supplement B.1: 1e-3 for both on the 360-degree scenes)
+    lambda_tv_bg_sigma: float = 1e-3
+    lambda_tv_bg_color: float = 1e-3
 
 
 class RaySampler:
@@ -175,6 +179,11 @@ class Trainer:
         B.plx_rmsprop_step(g.desc(), g.master, self.vstate, self.grad, self.touched, lr_s, lr_h,
                            c.beta, c.eps)
         if self.bg is not None:
+            if tv and (c.lambda_tv_bg_sigma > 0 or c.lambda_tv_bg_color > 0):
+                nb = self.bg.n_cells
+                count = max(1, int(math.ceil(c.tv_fraction * nb)))
+                B.plx_bg_tv_grad(self.bg.desc(), int(self.rng.integers(0, nb)), count, c.lambda_tv_bg_sigma,
+                                 c.lambda_tv_bg_color, c.tv_eps, self.bg_grad, self.bg_touched, self.tv_loss_sum)
             t = self.step_id
             lr_bs = B.plx_lr_schedule(t, c.lr_bg_sigma0, c.lr_bg_sigma1, c.lr_max_steps)
             lr_bc = B.plx_lr_schedule(t, c.lr_bg_color0, c.lr_bg_color1, c.lr_max_steps)

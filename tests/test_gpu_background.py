@@ -178,6 +178,22 @@ def test_training_step_foreground_and_background_matches_oracle():
     assert bt_ref.sum() > 100 and t_ref.sum() > 100
 
 
+@pytest.mark.parametrize("start,count", [(0, 6 * 12 * 24), (1500, 900)])
+def test_bg_tv_matches_oracle(start, count):
+    say("bg tv", start, count)
+    og, gg = bg_pair((6, 12, 24), 134, occupancy=0.8)
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    B.plx_bg_tv_grad(gg.desc(), start, count, 0.9, 1.3, 1e-9, grad, touched, loss)
+    torch.cuda.synchronize()
+    l_ref, gd, gs, t_ref = O.bg_tv(og, start, count, 0.9, 1.3, 1e-9)
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+    assert_touched_equal(touched, t_ref, "bg tv")
+    assert_grads_close(grad, gd, gs, "bg tv")
+    assert torch.all(grad[:, :24] == 0) and torch.all(grad[:, 29:] == 0)
+
+
 def test_bg_full_size_sampled():
     """The paper's background size, 64 spheres of 1024 x 2048 (10% of the
     voxels stored), 1M rays from inside the unit sphere; 1000 of them
