@@ -44,6 +44,7 @@ render/MSE/backward, TV and sparse RMSProp.
     python -m paper_2112_05131_amd.runs drift --steps 2000
     python -m paper_2112_05131_amd.runs forward_facing --steps 300 [--prune-thresh 1]
     python -m paper_2112_05131_amd.runs unbounded_360 --steps 300
+    python -m paper_2112_05131_amd.runs bg_kernels
 """
 from __future__ import annotations
 
@@ -381,6 +382,43 @@ def unbounded_360(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 5
     }
 
 
+def bg_kernels(reso=(64, 1024, 2048), sizes=(5000, 65536, 131071, 131072, 1 << 20), reps: int = 5,
+               seed: int = 4, log=print) -> dict:
+    """HIP-event times of plx_bg_render_fwd / plx_bg_render_bwd on the
+    paper's background size (procedural sky values, every voxel stored) for
+    batches of rays from inside the unit sphere (synth.random_rays, radius
+    0.8), the first n of 1M rays."""
+    dev = torch.device("cuda")
+    _, bd, bc = synth.sky_background(reso, seed)
+    bg = _bg_grid(reso, bd.to(dev), bc.to(dev), dev)
+    grad = torch.zeros(bg.n_vox, B.REC_SLOTS, device=dev)
+    touched = torch.zeros(bg.n_vox, dtype=torch.uint8, device=dev)
+    o, d = synth.random_rays(max(sizes), seed=seed + 1, radius=0.8, target_half=0.45)
+    o, d = o.to(dev), d.to(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"bg_reso": list(reso), "runs": []}
+    for n in sizes:
+        oo, dd = o[:n].contiguous(), d[:n].contiguous()
+        c = torch.empty(n, 3, device=dev)
+        g = torch.full((n, 3), 1e-3, device=dev)
+        f = timed(lambda: B.plx_bg_render_fwd(bg.desc(), oo, dd, c, None, (0.0, 0.0, 0.0)))
+        bw = timed(lambda: B.plx_bg_render_bwd(bg.desc(), oo, dd, g, grad, touched, (0.0, 0.0, 0.0)))
+        log(f"bg kernels n={n}: fwd {f:.3f} ms, bwd {bw:.3f} ms")
+        out["runs"].append({"rays": n, "fwd_ms": round(f, 4), "bwd_ms": round(bw, 4)})
+    return out
+
+
 def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512),
                     occupancy: float = 0.05, n_blobs: int = 32, n_cams: int = 100,
                     width: int = 800, height: int = 800, seed: int = 2, log=print) -> dict:
@@ -428,7 +466,7 @@ def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360"])
+    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360", "bg_kernels"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--prune", choices=["density", "weight"], default="density")
     ap.add_argument("--prune-thresh", type=float, default=None)
@@ -440,6 +478,8 @@ def main(argv=None):
         s = args.steps or 300
         res = coarse_to_fine(steps_coarse=s, steps_fine=s, prune=args.prune,
                              prune_thresh=args.prune_thresh, log=log)
+    elif args.run == "bg_kernels":
+        res = bg_kernels(log=log)
     elif args.run == "unbounded_360":
         s = args.steps or 300
         res = unbounded_360(steps_coarse=s, steps_fine=s, log=log,
