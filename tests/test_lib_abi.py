@@ -172,3 +172,44 @@ def test_state_buffer_layout_and_validation():
     # zero rays: no-op
     assert L.plx_render_fwd_state(ctypes.byref(g), ctypes.byref(opts), None, None, 0, None, None,
                                   None, 0, 3, None) == B.PLX_OK
+
+
+def test_newer_entry_points_validate_before_launch():
+    # pruning by weight, NDC warp, MSI background, background TV, priors:
+    # bad arguments are rejected and empty work returns PLX_OK, all without
+    # touching HIP
+    L = B.lib()
+    g = _grid_desc()
+    p = ctypes.c_void_p
+    assert L.plx_render_max_weight(ctypes.byref(g), p(0x40000), p(0x50000), 4, None, None) == B.PLX_EINVAL
+    assert "wmax" in L.plx_last_error().decode()
+    assert L.plx_render_max_weight(ctypes.byref(g), None, None, 0, None, None) == B.PLX_OK
+    assert L.plx_grid_prune_weight_count(ctypes.byref(g), None, 0.5, p(0x1000), p(0x2000), p(0x3000),
+                                         None) == B.PLX_EINVAL
+    # NDC: bad focal / near / size, NULL outputs; zero rays is a no-op
+    for w, h, f, near in [(0, 10, 5.0, 1.0), (10, 10, -5.0, 1.0), (10, 10, 5.0, 0.0),
+                          (10, 10, float("nan"), 1.0)]:
+        assert L.plx_rays_to_ndc(p(0x40000), p(0x50000), 3, w, h, f, near, p(0x60000), p(0x70000),
+                                 None) == B.PLX_EINVAL
+    assert L.plx_rays_to_ndc(p(0x40000), p(0x50000), 3, 10, 10, 5.0, 1.0, None, p(0x70000),
+                             None) == B.PLX_EINVAL
+    assert L.plx_rays_to_ndc(None, None, 0, 10, 10, 5.0, 1.0, None, None, None) == B.PLX_OK
+    # background: FP32 records only, NULL outputs, empty work
+    bgc = (ctypes.c_float * 3)(0, 0, 0)
+    g16 = _grid_desc(sh_dtype=B.PLX_F16)
+    assert L.plx_bg_render_fwd(ctypes.byref(g16), p(0x40000), p(0x50000), 4, bgc, p(0x60000), None,
+                               None) == B.PLX_EINVAL
+    assert "FP32" in L.plx_last_error().decode()
+    assert L.plx_bg_render_fwd(ctypes.byref(g), p(0x40000), p(0x50000), 4, bgc, None, None,
+                               None) == B.PLX_EINVAL
+    assert L.plx_bg_render_bwd(ctypes.byref(g), p(0x40000), p(0x50000), 4, bgc, None, None, None,
+                               None) == B.PLX_EINVAL
+    assert L.plx_bg_render_fwd(ctypes.byref(g), None, None, 0, bgc, None, None, None) == B.PLX_OK
+    assert L.plx_bg_tv_grad(ctypes.byref(g16), 0, 10, 1.0, 1.0, 1e-9, p(0x1000), p(0x2000), None,
+                            None) == B.PLX_EINVAL
+    # priors: the beta weight needs a positive epsilon, weights must be finite
+    for ls, lb, eps in [(0.0, 1.0, 0.0), (0.0, 1.0, -1.0), (float("inf"), 0.0, 1e-3)]:
+        opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+        opts.lambda_sparsity, opts.lambda_beta, opts.beta_eps = ls, lb, eps
+        assert L.plx_render_bwd(ctypes.byref(g), ctypes.byref(opts), p(0x40000), p(0x50000), 3,
+                                p(0x60000), p(0x70000), p(0x80000), p(0x90000), None) == B.PLX_EINVAL
