@@ -119,17 +119,17 @@ __device__ inline void add_prior_loss(const Priors &p, float ls_lane, double lb)
     }
 }
 
+// Arguments of the ray-order kernels of the stored-state calls (forward
+// recording the samples, backward replaying them).
 struct RenderArgs {
     const float *rays_o;
     const float *rays_d;
-    const float *target;    // TRAIN
     const float *grad_rgb;  // BWD
     const float *tau_in;    // BWD
-    float *rgb_out;         // FWD (required), TRAIN (optional)
+    float *rgb_out;         // FWD
     float *tau_out;         // FWD (optional)
-    float *grad;            // BWD, TRAIN
-    uint8_t *touched;       // BWD, TRAIN
-    double *loss_sum;       // TRAIN
+    float *grad;            // BWD
+    uint8_t *touched;       // BWD
     int *st_count;          // per-ray sample state (optional): occupied samples of each ray
     int *st_kidx;           // [n_rays][st_cap] their sample indices
     float4 *st_vals;        // [n_rays][st_cap] pre-activation density and projected colour
@@ -138,7 +138,6 @@ struct RenderArgs {
     float bg[3];
     const float *bg_rgb;    // optional per-ray background colours [n_rays][3]
     float *grad_bg;         // BWD, optional: T_final dL/dC per ray [n_rays][3]
-    float loss_scale;
     Priors pri;
     int n_blocks;
     int nb8;
@@ -581,27 +580,23 @@ __device__ __forceinline__ int next_backward(const GridDev &g, const RayGeom &r,
 // ------------------------------------------------------------ forward march
 
 // Front-to-back march of one ray (Eq. (1)).  Returns the colour before the
-// background is added in C and the optical depth in tau; with the span
-// pointers, the first and last occupied sample (k_first > k_last if none).
-// With STORE, the first `cap` occupied samples (index and pre-activation
-// values) go to kidx/vals and their total count to *count.
+// background is added in C and the optical depth in tau.  With STORE, the
+// first `cap` occupied samples (index and pre-activation values) go to
+// kidx/vals and their total count to *count.
 template <int DT, bool STORE = false>
 __device__ __forceinline__ void march_forward(const GridDev &g, const RayGeom &r, int n,
                                               const float y[9], CornerCache &cc, float C[3],
-                                              double &tau, int *k_first, int *k_last,
-                                              int *count = nullptr, int *kidx = nullptr,
+                                              double &tau, int *count = nullptr, int *kidx = nullptr,
                                               float4 *vals = nullptr, int cap = 0) {
     C[0] = C[1] = C[2] = 0.0f;
     tau = 0.0;
     Cursor cur{0, 0, 0u};
     Q4 none[8];
     Queue noq{};
-    int first = n, last = -1, stored = 0;
+    int stored = 0;
     while (true) {
         const int k = next_forward(g, r, n, cur);
         if (k < 0) break;
-        if (first == n) first = k;
-        last = k;
         const Sample s = sample_at(g, r, k);
         move_to<DT, false>(g, cc, s.cell, none, noq, y);
         float w[8];
@@ -621,8 +616,6 @@ __device__ __forceinline__ void march_forward(const GridDev &g, const RayGeom &r
         C[2] += wk * fmaxf(v.b, 0.0f);
         tau += (double)sd;
     }
-    if (k_first) *k_first = first;
-    if (k_last) *k_last = last;
     if (STORE) *count = stored;
 }
 
@@ -655,10 +648,10 @@ __global__ __launch_bounds__(kThreads) void render_fwd_kernel(GridDev g, RenderA
     double tau;
     if (STORE) {
         const int64_t base = ray * a.st_cap;
-        march_forward<DT, true>(g, r, n, y, cc, C, tau, nullptr, nullptr, a.st_count + ray,
+        march_forward<DT, true>(g, r, n, y, cc, C, tau, a.st_count + ray,
                                 a.st_kidx + base, a.st_vals + base, a.st_cap);
     } else {
-        march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
+        march_forward<DT>(g, r, n, y, cc, C, tau);
     }
     const float T_final = expf(-(float)tau);
     float bgc[3];
@@ -668,12 +661,12 @@ __global__ __launch_bounds__(kThreads) void render_fwd_kernel(GridDev g, RenderA
     if (a.tau_out) a.tau_out[ray] = (float)tau;
 }
 
-// Backward (MODE_BWD) and fused training (MODE_TRAIN).  Every lane of a
-// block stays until its wave is done (the queue drains need all 64 lanes).
-// With STATE (MODE_BWD), a ray whose occupied samples were all stored by the
-// forward pass replays them from the state (index loads only, no record
-// gathers or interpolation); a ray with more than st_cap samples replays by
-// traversal and recomputation.
+// Ray-order backward of the stored-state call.  Every lane of a block stays
+// until its wave is done (the queue drains need all 64 lanes).  With STATE,
+// a ray whose occupied samples were all stored by the forward pass replays
+// them from the state (index loads only, no record gathers or
+// interpolation); a ray with more than st_cap samples replays by traversal
+// and recomputation.
 template <int DT, bool STATE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void render_bwd_kernel(GridDev g, RenderArgs a) {
@@ -1455,7 +1448,7 @@ void views_kernel(ViewsArgs a) {
             cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
             float C[3];
             double tau;
-            march_forward<DT>(g, r, n, y, cc, C, tau, nullptr, nullptr);
+            march_forward<DT>(g, r, n, y, cc, C, tau);
             const float T_final = expf(-(float)tau);
             float *out = a.rgb_out + 3 * (uni64(v.out_offset) + (int64_t)py * width + px);
 #pragma unroll
