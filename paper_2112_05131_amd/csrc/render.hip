@@ -469,17 +469,32 @@ __device__ __forceinline__ Q4 interpolate(const CornerCache &cc, const float w[8
 
 // Occupancy of samples k0 .. k0+15 (bit i: sample k0+i exists and its cell
 // is occupied); the 16 bitmap loads are independent.
+// The loads are unconditional (indices outside [0, n) are clamped and their
+// bits masked off afterwards): a load under a per-sample branch would be
+// waited for inside that branch, serialising the 16 round trips.
 __device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &r, int n, int k0) {
-    uint32_t m = 0;
+    const int k_max = n > 0 ? n - 1 : 0;
+    uint32_t word[kChunk];
+    int bit[kChunk];
 #pragma unroll
     for (int i = 0; i < kChunk; ++i) {
-        const int k = k0 + i;
-        if (k >= 0 && k < n) {
-            const Sample s = sample_at(g, r, k);
-            if (cell_occupied(g, s.cell)) m |= 1u << i;
-        }
+        int k = k0 + i;
+        k = k < 0 ? 0 : (k > k_max ? k_max : k);
+        const Sample s = sample_at(g, r, k);
+        const int64_t b = ((int64_t)(s.cell[0] >> 3) * g.by + (s.cell[1] >> 3)) * g.bz + (s.cell[2] >> 3);
+        const int bb = ((s.cell[0] & 7) << 6) | ((s.cell[1] & 7) << 3) | (s.cell[2] & 7);
+        word[i] = g.occ[b * 16 + (bb >> 5)];
+        bit[i] = bb & 31;
     }
-    return m;
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) m |= ((word[i] >> bit[i]) & 1u) << i;
+    // samples k0 + i inside [0, n)
+    const int lo = k0 < 0 ? -k0 : 0;
+    const int hi = n - k0;  // first i past the end
+    uint32_t valid = hi <= 0 ? 0u : (hi >= kChunk ? 0xffffu : ((1u << hi) - 1u));
+    valid &= lo >= kChunk ? 0u : (0xffffu << lo);
+    return m & valid;
 }
 
 // Brick-level skip.  Returns the distance D of the brick of sample k (0 when
