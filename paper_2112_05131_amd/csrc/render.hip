@@ -326,7 +326,10 @@ __device__ __forceinline__ void push_corners(const Queue &qu, const CornerCache 
 
 // Sends every queued voxel's gradient to its FP32 record: lanes 0..31 take
 // one entry and lanes 32..63 the next, lane L & 31 = record slot (0..26 SH,
-// 28 density, 29 marks the voxel touched).  Called by the whole wave.
+// 28 density, 29 marks the voxel touched).  Called by the whole wave.  The
+// LDS reads are unconditional (positions past the count are clamped into the
+// queue and their values discarded), so the reads of a round overlap and
+// the only branches are the ones around the stores.
 __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *touched) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -334,32 +337,34 @@ __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *tou
     if (E == 0) return;
     const int L = lane_id();
     const int s = L & 31;
-    const int ch = s < PLX_NSH ? 1 + s / 9 : 0;  // v row: 0 density, 1..3 colour
-    const int l = s < PLX_NSH ? s % 9 : 0;
-    const bool writes = s < PLX_NSH || s == PLX_SLOT_SIGMA;
-    // eight pairs of entries per round, so that their LDS reads overlap
+    const bool sh = s < PLX_NSH;
+    const int vrow = (sh ? 1 + s / 9 : 0) * kQRow;  // v row: 0 density, 1..3 colour
+    const int l = sh ? s % 9 : 0;
+    const bool writes = sh || s == PLX_SLOT_SIGMA;
+    const bool marks = s == PLX_SLOT_SIGMA + 1;
+    float *gs = grad + s;
+    const int half = L >> 5;
+    // eight pairs of entries per round
     constexpr int U = 8;
-    for (int e0 = 0; e0 < E; e0 += 2 * U) {
+    for (int b0 = 0; b0 < E; b0 += 2 * U) {
+        const int e0 = b0 + half;
         int id[U], src[U];
         float a[U], yv[U];
-        bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + 2 * u + (L >> 5);
-            ok[u] = e < E;
-            id[u] = ok[u] ? qu.id[e] : 0;
-            src[u] = ok[u] ? (int)qu.src[e] : 0;
-            a[u] = ok[u] ? qu.v[ch * kQRow + e] : 0.0f;
+            const int e = min(e0 + 2 * u, kQCap - 1);
+            id[u] = qu.id[e];
+            src[u] = (int)qu.src[e] & (kWave - 1);
+            a[u] = qu.v[vrow + e];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) yv[u] = s < PLX_NSH ? qu.y[src[u] * 9 + l] : 1.0f;
+        for (int u = 0; u < U; ++u) yv[u] = qu.y[src[u] * 9 + l];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!ok[u]) continue;
-            const float val = yv[u] * a[u];
-            if (writes && val != 0.0f)
-                unsafeAtomicAdd(grad + (int64_t)id[u] * PLX_REC_SLOTS + s, val);
-            if (s == PLX_SLOT_SIGMA + 1) touched[id[u]] = 1;
+            const bool ok = e0 + 2 * u < E;
+            const float val = (ok && writes) ? (sh ? yv[u] : 1.0f) * a[u] : 0.0f;
+            if (val != 0.0f) unsafeAtomicAdd(gs + (int64_t)id[u] * PLX_REC_SLOTS, val);
+            if (ok && marks) touched[id[u]] = 1;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
