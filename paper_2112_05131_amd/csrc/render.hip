@@ -64,7 +64,6 @@ constexpr int kThreads = 256;          // rays per block
 constexpr int kWavesPerBlock = kThreads / kWave;
 constexpr int kChunk = 16;             // candidate samples tested per round
 constexpr int kQCap = 8 * kWave;       // queue entries per wave (8 corners per lane per step)
-constexpr int kQRow = kQCap + 8;       // LDS row stride of the queue values (rows on distinct banks)
 constexpr float kSkipMargin = 0.05f;   // in steps
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2, MODE_MAXW = 3 };
@@ -272,7 +271,7 @@ struct Queue {
     int *count;     // entries in use
     int *id;        // [kQCap] voxel id
     uint8_t *src;   // [kQCap] lane that flushed it (selects the SH basis)
-    float *v;       // [4][kQRow] accumulated density, R, G, B gradients
+    float4 *v;      // [kQCap] accumulated density, R, G, B gradients
     float *y;       // [64][9] SH basis of each lane's ray
 };
 
@@ -315,10 +314,7 @@ __device__ __forceinline__ void push_corners(const Queue &qu, const CornerCache 
         if ((m >> c) & 1u) {
             qu.id[e] = cc.ids[c];
             qu.src[e] = (uint8_t)lane_id();
-            qu.v[e] = acc[c].s;
-            qu.v[kQRow + e] = acc[c].r;
-            qu.v[2 * kQRow + e] = acc[c].g;
-            qu.v[3 * kQRow + e] = acc[c].b;
+            qu.v[e] = make_float4(acc[c].s, acc[c].r, acc[c].g, acc[c].b);
             ++e;
         }
     }
@@ -338,7 +334,7 @@ __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *tou
     const int L = lane_id();
     const int s = L & 31;
     const bool sh = s < PLX_NSH;
-    const int vrow = (sh ? 1 + s / 9 : 0) * kQRow;  // v row: 0 density, 1..3 colour
+    const int ch = sh ? 1 + s / 9 : 0;  // v component: 0 density, 1..3 colour
     const int l = sh ? s % 9 : 0;
     const bool writes = sh || s == PLX_SLOT_SIGMA;
     const bool marks = s == PLX_SLOT_SIGMA + 1;
@@ -355,7 +351,7 @@ __device__ __forceinline__ void drain(const Queue &qu, float *grad, uint8_t *tou
             const int e = min(e0 + 2 * u, kQCap - 1);
             id[u] = qu.id[e];
             src[u] = (int)qu.src[e] & (kWave - 1);
-            a[u] = qu.v[vrow + e];
+            a[u] = reinterpret_cast<const float *>(qu.v)[4 * e + ch];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) yv[u] = qu.y[src[u] * 9 + l];
@@ -693,7 +689,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     __shared__ int q_count[kWavesPerBlock];
     __shared__ int q_id[kWavesPerBlock * kQCap];
     __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
-    __shared__ float q_v[kWavesPerBlock * 4 * kQRow];
+    __shared__ float4 q_v[kWavesPerBlock * kQCap];
     __shared__ float q_y[kWavesPerBlock * kWave * 9];
 
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
@@ -706,7 +702,7 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
     qu.count = q_count + wid;
     qu.id = q_id + wid * kQCap;
     qu.src = q_src + wid * kQCap;
-    qu.v = q_v + wid * 4 * kQRow;
+    qu.v = q_v + wid * kQCap;
     qu.y = q_y + wid * kWave * 9;
 
     const int64_t ray = (int64_t)blk * kThreads + threadIdx.x;
@@ -1187,7 +1183,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
     __shared__ int q_count[kWavesPerBlock];
     __shared__ int q_id[kWavesPerBlock * kQCap];
     __shared__ uint8_t q_src[kWavesPerBlock * kQCap];
-    __shared__ float q_v[kWavesPerBlock * 4 * kQRow];
+    __shared__ float4 q_v[kWavesPerBlock * kQCap];
     __shared__ float q_y[kWavesPerBlock * kWave * 9];
 
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
@@ -1200,7 +1196,7 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
     qu.count = q_count + wid;
     qu.id = q_id + wid * kQCap;
     qu.src = q_src + wid * kQCap;
-    qu.v = q_v + wid * 4 * kQRow;
+    qu.v = q_v + wid * kQCap;
     qu.y = q_y + wid * kWave * 9;
 
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
