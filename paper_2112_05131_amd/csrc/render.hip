@@ -837,6 +837,24 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 // T_in(s) = exp(-sum_{s'<s} tau_s'), and the backward replay of a segment
 // starts from the optical depth after it and the radiance the ray collects
 // after it (g . R), so every sample sees the same T_k, w_k and R_k.
+//
+// The lanes of a wave march in step, so a wave takes as many trips as its
+// longest segment.  Inside a brick the segments are therefore ordered by
+// length class (the segment's number of samples in steps of kLenStep): the
+// bins are keyed by (brick, class).  A wave's segments then have closer
+// lengths while the order stays by brick (ordering by class first, across
+// bricks, evens the lengths out further but loses more to the scattered
+// record reads than it gains).
+
+constexpr int kLenClasses = 8;
+constexpr int kLenStep = 4;
+
+__host__ __device__ inline int64_t n_bins(int64_t n_bricks) { return n_bricks * kLenClasses; }
+
+__device__ __forceinline__ int64_t seg_bin(int64_t brick, int k0, int k1, int64_t n_bricks) {
+    const int c = min((k1 - k0) / kLenStep, kLenClasses - 1);
+    return brick * kLenClasses + c;
+}
 
 constexpr int kScanT = 256, kScanI = 16, kScanTile = kScanT * kScanI;
 
@@ -934,10 +952,11 @@ struct BinArgs {
     int nb8;
     unsigned *nseg;      // [n_rays] segments of each ray
     int64_t *seg_off;    // [n_rays + 1] first ray-major slot of each ray
-    unsigned *bcount;    // [n_bricks] segments in each brick
-    unsigned *bcursor;   // [n_bricks] placement cursors
-    int64_t *boff;       // [n_bricks + 1] first brick-major position of each brick
-    int4 *bseg;          // [n_seg] brick-major: ray, first sample, last sample, ray-major slot
+    int64_t n_bricks;
+    unsigned *bcount;    // [n_bins] segments in each (length class, brick) bin
+    unsigned *bcursor;   // [n_bins] placement cursors
+    int64_t *boff;       // [n_bins + 1] first bin-major position of each bin
+    int4 *bseg;          // [n_seg] bin-major: ray, first sample, last sample, ray-major slot
     double *tau_seg;     // [n_seg] ray-major: optical depth of the segment
     float4 *c_seg;       // [n_seg] ray-major: colour the segment adds (before T_in)
     double *tau_in;      // [n_seg] ray-major: optical depth before the segment
@@ -995,9 +1014,9 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(GridDev g, BinArgs 
     RayGeom r;
     const int n = ray_setup(g, o, d, r);
     unsigned cnt = 0;
-    walk_bricks(g, r, n, [&](int64_t bid, int, int) {
+    walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         ++cnt;
-        atomicAdd(a.bcount + bid, 1u);
+        atomicAdd(a.bcount + seg_bin(bid, k0, k1, a.n_bricks), 1u);
     });
     a.nseg[ray] = cnt;
 }
@@ -1013,7 +1032,8 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
     const int n = ray_setup(g, o, d, r);
     int64_t slot = a.seg_off[ray];
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
-        const int64_t pos = a.boff[bid] + atomicAdd(a.bcursor + bid, 1u);
+        const int64_t bin = seg_bin(bid, k0, k1, a.n_bricks);
+        const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
         a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
         ++slot;
     });
@@ -1610,7 +1630,8 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     const int64_t n_rays = a.n_rays;
     if (n_rays > 0x7fffffffLL - kThreads) return fail(PLX_EINVAL, "%s: too many rays", fn);
     GridDev g = to_dev(grid);
-    const int64_t nbk = n_bricks(grid->reso);
+    a.n_bricks = n_bricks(grid->reso);
+    const int64_t nbk = n_bins(a.n_bricks);
     // per-ray and per-brick temporaries
     int64_t off = 0;
     const int64_t o_nseg = off; off += align256(n_rays * 4);
