@@ -846,14 +846,33 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 // bricks, evens the lengths out further but loses more to the scattered
 // record reads than it gains).
 
+//
+// The bricks themselves are ordered by tiles of kTile^3 bricks (tiles in
+// storage order, bricks inside a tile in storage order), so that the
+// segments of consecutive waves stay within a compact block of the grid
+// rather than a row of bricks along z.
+
 constexpr int kLenClasses = 8;
 constexpr int kLenStep = 4;
+constexpr int kTile = 4;
 
-__host__ __device__ inline int64_t n_bins(int64_t n_bricks) { return n_bricks * kLenClasses; }
+inline int tiles_along(int bricks) { return (bricks + kTile - 1) / kTile; }
+// Number of (brick, class) bins: brick order positions times classes.
+inline int64_t n_bins(const GridDev &g) {
+    return (int64_t)tiles_along(g.bx) * tiles_along(g.by) * tiles_along(g.bz) * (kTile * kTile * kTile) *
+           kLenClasses;
+}
 
-__device__ __forceinline__ int64_t seg_bin(int64_t brick, int k0, int k1, int64_t n_bricks) {
+// Position of brick b in the binning order.
+__device__ __forceinline__ int64_t brick_order(const GridDev &g, const int b[3]) {
+    const int nty = (g.by + kTile - 1) / kTile, ntz = (g.bz + kTile - 1) / kTile;
+    const int64_t tile = ((int64_t)(b[0] / kTile) * nty + b[1] / kTile) * ntz + b[2] / kTile;
+    return tile * (kTile * kTile * kTile) + ((b[0] % kTile) * kTile + b[1] % kTile) * kTile + b[2] % kTile;
+}
+
+__device__ __forceinline__ int64_t seg_bin(int64_t order, int k0, int k1) {
     const int c = min((k1 - k0) / kLenStep, kLenClasses - 1);
-    return brick * kLenClasses + c;
+    return order * kLenClasses + c;
 }
 
 constexpr int kScanT = 256, kScanI = 16, kScanTile = kScanT * kScanI;
@@ -952,7 +971,6 @@ struct BinArgs {
     int nb8;
     unsigned *nseg;      // [n_rays] segments of each ray
     int64_t *seg_off;    // [n_rays + 1] first ray-major slot of each ray
-    int64_t n_bricks;
     unsigned *bcount;    // [n_bins] segments in each (length class, brick) bin
     unsigned *bcursor;   // [n_bins] placement cursors
     int64_t *boff;       // [n_bins + 1] first bin-major position of each bin
@@ -974,7 +992,7 @@ __device__ __forceinline__ void load_ray_lane(const BinArgs &a, int64_t ray, flo
     }
 }
 
-// Calls f(brick, first sample, last sample) for every brick with an occupied
+// Calls f(brick order position, first sample, last sample) for every brick with an occupied
 // cell that the ray's samples enter, in ray order; boxes of empty bricks are
 // skipped with the distance field, and inside a brick only the samples near
 // its exit face are placed.
@@ -999,7 +1017,7 @@ __device__ __forceinline__ void walk_bricks(const GridDev &g, const RayGeom &r, 
                 break;
             ++ke;
         }
-        f(bid, k, ke);
+        f(brick_order(g, b), k, ke);
         k = ke + 1;
     }
 }
@@ -1016,7 +1034,7 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(GridDev g, BinArgs 
     unsigned cnt = 0;
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         ++cnt;
-        atomicAdd(a.bcount + seg_bin(bid, k0, k1, a.n_bricks), 1u);
+        atomicAdd(a.bcount + seg_bin(bid, k0, k1), 1u);
     });
     a.nseg[ray] = cnt;
 }
@@ -1032,7 +1050,7 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
     const int n = ray_setup(g, o, d, r);
     int64_t slot = a.seg_off[ray];
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
-        const int64_t bin = seg_bin(bid, k0, k1, a.n_bricks);
+        const int64_t bin = seg_bin(bid, k0, k1);
         const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
         a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
         ++slot;
@@ -1630,8 +1648,7 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     const int64_t n_rays = a.n_rays;
     if (n_rays > 0x7fffffffLL - kThreads) return fail(PLX_EINVAL, "%s: too many rays", fn);
     GridDev g = to_dev(grid);
-    a.n_bricks = n_bricks(grid->reso);
-    const int64_t nbk = n_bins(a.n_bricks);
+    const int64_t nbk = n_bins(g);
     // per-ray and per-brick temporaries
     int64_t off = 0;
     const int64_t o_nseg = off; off += align256(n_rays * 4);
