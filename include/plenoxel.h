@@ -23,8 +23,11 @@
  *    synchronising call is reported as PLX_EDEVICE.  plx_last_error() returns
  *    the message of the last failure on the calling thread.
  *  - Some calls (marked "temporary device memory") take stream-ordered
- *    scratch with hipMallocAsync and release it with hipFreeAsync on the
- *    same stream.
+ *    scratch (hipMallocFromPoolAsync) and release it with hipFreeAsync on
+ *    the same stream.  The scratch comes from a memory pool the library
+ *    creates per device on first use; the pool keeps freed memory for later
+ *    calls (up to the largest scratch a call has needed) until the process
+ *    ends.
  *  - Index grids are int32, z fastest: cell (i,j,k) has storage id
  *    (i*Ny + j)*Nz + k; -1 marks NULL.  Table ids of occupied voxels follow
  *    increasing storage id.
