@@ -1132,6 +1132,11 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
     a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
 }
 
+// Segments of a ray are walked kSegU at a time: the loads of a group are
+// issued together (positions past the last segment are clamped to it and
+// their values unused), then the group is composed in order.
+constexpr int kSegU = 4;
+
 // Per ray: composes its segments into the colour (and optical depth).  FWD
 // writes them out; TRAIN also forms the loss and dL/dC = 2 loss_scale (C -
 // target), BWD takes dL/dC as given; both then record, for every segment,
@@ -1143,10 +1148,19 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
     double l2 = 0.0, lb = 0.0;
     if constexpr (MODE == MODE_MAXW) {
         if (ray < a.n_rays) {
+            const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
             double tau = 0.0;
-            for (int64_t s = a.seg_off[ray]; s < a.seg_off[ray + 1]; ++s) {
-                a.tau_in[s] = tau;
-                tau += a.tau_seg[s];
+            for (int64_t s = s0; s < s1; s += kSegU) {
+                double ts[kSegU];
+#pragma unroll
+                for (int u = 0; u < kSegU; ++u) ts[u] = a.tau_seg[min(s + u, s1 - 1)];
+#pragma unroll
+                for (int u = 0; u < kSegU; ++u) {
+                    if (s + u < s1) {
+                        a.tau_in[s + u] = tau;
+                        tau += ts[u];
+                    }
+                }
             }
         }
         return;
@@ -1155,14 +1169,26 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
         const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
         double tau = 0.0;
         float C[3] = {0.0f, 0.0f, 0.0f};
-        for (int64_t s = s0; s < s1; ++s) {
-            if (MODE != MODE_FWD) a.tau_in[s] = tau;
-            const float T = expf(-(float)tau);
-            const float4 c = a.c_seg[s];
-            C[0] += T * c.x;
-            C[1] += T * c.y;
-            C[2] += T * c.z;
-            tau += a.tau_seg[s];
+        for (int64_t s = s0; s < s1; s += kSegU) {
+            double ts[kSegU];
+            float4 cs[kSegU];
+#pragma unroll
+            for (int u = 0; u < kSegU; ++u) {
+                const int64_t sc = min(s + u, s1 - 1);
+                ts[u] = a.tau_seg[sc];
+                cs[u] = a.c_seg[sc];
+            }
+#pragma unroll
+            for (int u = 0; u < kSegU; ++u) {
+                if (s + u < s1) {
+                    if (MODE != MODE_FWD) a.tau_in[s + u] = tau;
+                    const float T = expf(-(float)tau);
+                    C[0] += T * cs[u].x;
+                    C[1] += T * cs[u].y;
+                    C[2] += T * cs[u].z;
+                    tau += ts[u];
+                }
+            }
         }
         const float T_final = expf(-(float)tau);
         float gr[3], R[3], bgc[3];
@@ -1189,13 +1215,25 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
 #pragma unroll
                 for (int c3 = 0; c3 < 3; ++c3) a.grad_bg[3 * ray + c3] = T_final * gr[c3];
             }
-            for (int64_t s = s1 - 1; s >= s0; --s) {
-                a.gr_after[s] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
-                const float T = expf(-(float)a.tau_in[s]);
-                const float4 c = a.c_seg[s];
-                R[0] += T * c.x;
-                R[1] += T * c.y;
-                R[2] += T * c.z;
+            for (int64_t s = s1 - 1; s >= s0; s -= kSegU) {
+                double ti[kSegU];
+                float4 cs[kSegU];
+#pragma unroll
+                for (int u = 0; u < kSegU; ++u) {
+                    const int64_t sc = max(s - u, s0);
+                    ti[u] = a.tau_in[sc];
+                    cs[u] = a.c_seg[sc];
+                }
+#pragma unroll
+                for (int u = 0; u < kSegU; ++u) {
+                    if (s - u >= s0) {
+                        a.gr_after[s - u] = gr[0] * R[0] + gr[1] * R[1] + gr[2] * R[2];
+                        const float T = expf(-(float)ti[u]);
+                        R[0] += T * cs[u].x;
+                        R[1] += T * cs[u].y;
+                        R[2] += T * cs[u].z;
+                    }
+                }
             }
         }
     }
