@@ -163,38 +163,57 @@ struct PruneWriter {
 };
 
 // ---- small kernels
-__global__ void count_nonzero_kernel(const uint8_t *m, int64_t n, unsigned long long *out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long b = __ballot(i < n && m[i] != 0);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+
+// Counting kernels run a fixed grid of kCountBlocks x kCountThreads threads
+// that stride over the input; each block adds its total to the counter with
+// one atomic (one atomic per wave on a single address serialises: 2M of them
+// for a 512^3 mask).
+constexpr int kCountThreads = 256;
+constexpr int64_t kCountBlocks = 2048;
+
+inline unsigned count_blocks(int64_t n) {
+    const int64_t b = (n + kCountThreads - 1) / kCountThreads;
+    return (unsigned)(b < 1 ? 1 : (b > kCountBlocks ? kCountBlocks : b));
 }
 
-__global__ void nonzero_bytes_kernel(const uint8_t *b, int64_t n, unsigned long long *out) {
-    // 4 bytes per thread
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    int c = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        if (i + e < n && b[i + e]) ++c;
-    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+__device__ void block_add(unsigned long long v, unsigned long long *out) {
+    __shared__ unsigned long long part[kCountThreads / 64];
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kCountThreads / 64; ++w) t += part[w];
+        if (t) atomicAdd(out, t);
+    }
 }
 
-__global__ void popcount_kernel(const uint32_t *w, int64_t nw, int64_t nbits,
-                                unsigned long long *out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int c = 0;
-    if (i < nw) {
+// Number of non-zero bytes of m[0..n).
+__global__ __launch_bounds__(kCountThreads) void count_nonzero_kernel(const uint8_t *m, int64_t n,
+                                                                      unsigned long long *out) {
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; i < n; i += stride)
+        c += m[i] != 0;
+    block_add(c, out);
+}
+
+// Number of set bits among the first nbits bits of w[0..nw).
+__global__ __launch_bounds__(kCountThreads) void popcount_kernel(const uint32_t *w, int64_t nw,
+                                                                 int64_t nbits,
+                                                                 unsigned long long *out) {
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; i < nw; i += stride) {
         uint32_t x = w[i];
-        int64_t first = i * 32;
+        const int64_t first = i * 32;
         if (first + 32 > nbits) {
-            int keep = (int)(nbits - first);
+            const int keep = (int)(nbits - first);
             x &= keep >= 32 ? 0xffffffffu : ((1u << keep) - 1u);
         }
-        c = __popc(x);
+        c += __popc(x);
     }
-    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+    block_add(c, out);
 }
 
 template <int DT>
@@ -368,10 +387,13 @@ __global__ void prune_keep_kernel(GridDev g, int64_t ncell, const uint8_t *occ8,
     }
 }
 
-__global__ void upsample_count_kernel(ParentPred pred, int64_t n, unsigned long long *out) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long b = __ballot(v < n && pred(v));
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+__global__ __launch_bounds__(kCountThreads) void upsample_count_kernel(ParentPred pred, int64_t n,
+                                                                       unsigned long long *out) {
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    unsigned long long c = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; v < n; v += stride)
+        c += pred(v) ? 1 : 0;
+    block_add(c, out);
 }
 
 // Old-grid coordinate of new voxel j (FP64, same operation order as the
@@ -519,7 +541,7 @@ int plx_mask_count(const uint8_t *mask, int64_t n, int64_t *count_out, plx_strea
     if (rc) return rc;
     auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
     PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_mask_count");
-    count_nonzero_kernel<<<blocks_for(n, 256), 256, 0, s>>>(mask, n, cnt);
+    count_nonzero_kernel<<<count_blocks(n), kCountThreads, 0, s>>>(mask, n, cnt);
     if ((rc = check_launch("plx_mask_count"))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, "plx_mask_count");
 }
@@ -639,7 +661,7 @@ int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int
     if ((rc = tmp.alloc(sizeof(unsigned long long), s))) return rc;
     auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
     PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_grid_upsample_count");
-    upsample_count_kernel<<<blocks_for(n, 256), 256, 0, s>>>(pred, n, cnt);
+    upsample_count_kernel<<<count_blocks(n), kCountThreads, 0, s>>>(pred, n, cnt);
     if ((rc = check_launch("plx_grid_upsample_count"))) return rc;
     return sync_read_u64(cnt, 1, n_out, s, "plx_grid_upsample_count");
 }
@@ -680,7 +702,7 @@ int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
     if (rc) return rc;
     auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
     PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_touched_count");
-    nonzero_bytes_kernel<<<blocks_for((n_vox + 3) / 4, 256), 256, 0, s>>>(touched, n_vox, cnt);
+    count_nonzero_kernel<<<count_blocks(n_vox), kCountThreads, 0, s>>>(touched, n_vox, cnt);
     if ((rc = check_launch("plx_touched_count"))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, "plx_touched_count");
 }
@@ -701,7 +723,7 @@ int count_set_bits(const uint32_t *words, int64_t n_bits, int64_t *count_out, hi
     if (rc) return rc;
     auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
     PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), fn);
-    popcount_kernel<<<blocks_for(nw, 256), 256, 0, s>>>(words, nw, n_bits, cnt);
+    popcount_kernel<<<count_blocks(nw), kCountThreads, 0, s>>>(words, nw, n_bits, cnt);
     if ((rc = check_launch(fn))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, fn);
 }
