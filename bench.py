@@ -259,7 +259,7 @@ def prune_weight_leg(grid, batches, counts, thresh=0.01):
             "prune_count_ms": round(ms_prune, 3), "threshold": thresh, "kept": kept, "pruned": pruned}
 
 
-def serving_leg(n_sat=160, n_load=240):
+def serving_leg(n_sat=400, n_load=2000):
     """8 resident scenes (4 at 256^3, 4 at 512^3, 5-10% occupancy, FP16 SH),
     requests at 200x200 .. 1920x1080 with random poses on the view sphere:
     saturation throughput (all requests at once), then Poisson arrivals at 50,
