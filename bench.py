@@ -46,9 +46,9 @@ N_CAMS, W, H = 100, 800, 800
 # HBM bytes moved by one plx_render_train call of this workload (FP32
 # records), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
 # `bench.py --counters`, each scaled by its reading for a 1 GiB device copy
-# (FETCH x2, WRITE x1): 10.010 GB fetched + 8.710 GB written.  Re-measure
+# (FETCH x2, WRITE x1): 9.811 GB fetched + 8.766 GB written.  Re-measure
 # whenever the render kernels change.
-RENDER_TRAIN_TRAFFIC_GB_F32 = 18.72
+RENDER_TRAIN_TRAFFIC_GB_F32 = 18.58
 
 
 def log(*a):
