@@ -22,9 +22,10 @@
 // FP64 in the same operation order as the definition, without contraction,
 // so the samples' cells and weights are reproducible; interpolation and
 // compositing are FP32 with the optical depth in FP64, as in the foreground.
-// The backward pass sums the optical depth, then walks the rounds of samples
-// from the last to the first with suffix scans for the depth and the
-// radiance after each sample.
+// The backward pass sums the optical depth (from the same gathers as the
+// replay when the ray's samples fit one round of the wave), then walks the
+// rounds of samples from the last to the first with suffix scans for the
+// depth and the radiance after each sample.
 #include <cmath>
 
 #include "plx_internal.hpp"
@@ -179,6 +180,11 @@ struct BgSmp {
 __device__ __forceinline__ void bg_load(const BgArgs &a, const double o[3], const double d[3], int k, int n,
                                         BgSmp &s) {
     s.ok = k < n && bg_sample(a, o, d, k, s.ids, s.w, &s.cell);
+    if (!s.ok) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s.ids[c] = -1;
+        s.cell = -1;
+    }
     s.v = s.ok ? bg_interp(a, s.ids, s.w) : BgVal{0.f, 0.f, 0.f, 0.f};
 }
 
@@ -221,18 +227,45 @@ __global__ __launch_bounds__(256) void bg_fwd_kernel(BgArgs a) {
     }
 }
 
-__device__ __forceinline__ void bg_flush(const BgArgs &a, const int ids[8], const BgVal acc[8]) {
+// Value of lane 4*(L/4) + i for every lane L of a quad (all lanes active).
+__device__ __forceinline__ int quad_bcast(int x, int i) {
+    switch (i) {
+    case 0: return __builtin_amdgcn_mov_dpp(x, 0x00, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0x55, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0xaa, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_mov_dpp(x, 0xff, 0xf, 0xf, false);
+    }
+}
+__device__ __forceinline__ float quad_bcast(float x, int i) {
+    return __builtin_bit_cast(float, quad_bcast(__builtin_bit_cast(int, x), i));
+}
+
+// Adds the gradients acc of corners ids (skipped where !on) to their FP32
+// records.  The four values of a voxel (colour slots 24..26 and density slot
+// 28, one 64-byte line) are sent by the four lanes of a quad in one
+// instruction, one entry of each quad per instruction, so they reach memory
+// as one request rather than four.  Called by the whole wave.
+__device__ __forceinline__ void bg_flush(const BgArgs &a, const int ids[8], const BgVal acc[8], bool on) {
+    const int j = (int)(threadIdx.x & 3);
+    const int slot = j < 3 ? kSlotR + j : PLX_SLOT_SIGMA;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int id = ids[c];
-        if (id < 0) continue;
-        float *g = a.grad + (int64_t)id * PLX_REC_SLOTS;
-        if (acc[c].s != 0.0f) unsafeAtomicAdd(g + PLX_SLOT_SIGMA, acc[c].s);
-        if (acc[c].r != 0.0f) unsafeAtomicAdd(g + kSlotR, acc[c].r);
-        if (acc[c].g != 0.0f) unsafeAtomicAdd(g + kSlotR + 1, acc[c].g);
-        if (acc[c].b != 0.0f) unsafeAtomicAdd(g + kSlotR + 2, acc[c].b);
-        a.touched[id] = 1;
+        const int id = on ? ids[c] : -1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idi = quad_bcast(id, i);
+            const float t0 = quad_bcast(acc[c].r, i), t1 = quad_bcast(acc[c].g, i);
+            const float t2 = quad_bcast(acc[c].b, i), t3 = quad_bcast(acc[c].s, i);
+            const float v = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : t3));
+            if (idi >= 0 && v != 0.0f) unsafeAtomicAdd(a.grad + (int64_t)idi * PLX_REC_SLOTS + slot, v);
+        }
     }
+}
+
+__device__ __forceinline__ void bg_mark(const BgArgs &a, const int ids[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (ids[c] >= 0) a.touched[ids[c]] = 1;
 }
 
 // Gradient terms of one sample (dC/dsigma = 1/2 (T_after c - R_after),
@@ -258,7 +291,10 @@ __device__ __forceinline__ void bg_terms(const BgSmp &s, float w, float T_after,
 // rounds from the last to the first, each lane's optical depth after its
 // samples and the radiance g . R collected after them from wave-wide suffix
 // sums; a lane adds its two samples' terms (one set of corners when both lie
-// in the same cell) with FP32 atomics.
+// in the same cell) with FP32 atomics.  A lane's second sample lies halfway
+// to the next sphere, whose corners at the same angular cell are the lower
+// corners of the next lane's first sample: when the cells agree, those four
+// corners are handed to the next lane and sent once.
 __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
     const int64_t ray = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ray >= a.n_rays) return;
@@ -266,17 +302,27 @@ __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
     double o[3], d[3];
     load_ray(a, ray, o, d);
     const int n = 2 * (a.L - 1);
+    // With at most 128 samples (64 spheres or fewer) there is one round: its
+    // samples give the optical depth as well, so they are gathered once.
+    const bool one_round = n <= 128;
     double tau = 0.0;
-    for (int base = 0; base < n; base += 128) {
-        BgSmp s0, s1;
-        bg_load(a, o, d, base + 2 * L, n, s0);
-        bg_load(a, o, d, base + 2 * L + 1, n, s1);
-        tau += (double)(0.5f * fmaxf(s0.v.s, 0.0f)) + (double)(0.5f * fmaxf(s1.v.s, 0.0f));
+    if (!one_round) {
+        for (int base = 0; base < n; base += 128) {
+            BgSmp s0, s1;
+            bg_load(a, o, d, base + 2 * L, n, s0);
+            bg_load(a, o, d, base + 2 * L + 1, n, s1);
+            tau += (double)(0.5f * fmaxf(s0.v.s, 0.0f)) + (double)(0.5f * fmaxf(s1.v.s, 0.0f));
+        }
     }
-    tau = wave_sum_d(tau);
     const float g[3] = {a.grad_rgb[3 * ray], a.grad_rgb[3 * ray + 1], a.grad_rgb[3 * ray + 2]};
-    double tau_end = tau;  // optical depth after the current round
-    float gR_end = expf(-(float)tau) * (g[0] * a.bg[0] + g[1] * a.bg[1] + g[2] * a.bg[2]);
+    const float g_bg = g[0] * a.bg[0] + g[1] * a.bg[1] + g[2] * a.bg[2];
+    double tau_end = 0.0;  // optical depth after the current round
+    float gR_end = 0.0f;
+    if (!one_round) {
+        tau = wave_sum_d(tau);
+        tau_end = tau;
+        gR_end = expf(-(float)tau) * g_bg;
+    }
     const int last = ((n - 1) / 128) * 128;
     for (int base = last; base >= 0; base -= 128) {
         BgSmp s0, s1;
@@ -284,6 +330,10 @@ __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
         bg_load(a, o, d, base + 2 * L + 1, n, s1);
         const float sd0 = 0.5f * fmaxf(s0.v.s, 0.0f), sd1 = 0.5f * fmaxf(s1.v.s, 0.0f);
         const double lane_sd = (double)sd0 + (double)sd1;
+        if (one_round) {
+            tau_end = wave_sum_d(lane_sd);
+            gR_end = expf(-(float)tau_end) * g_bg;
+        }
         const double tau_after1 = tau_end - wave_excl_suffix_d(lane_sd);
         const double tau_after0 = fmax(tau_after1 - (double)sd1, 0.0);
         const double tau_before0 = fmax(tau_after0 - (double)sd0, 0.0);
@@ -297,18 +347,50 @@ __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
         const float lane_gR = w0 * gc0 + w1 * gc1;
         const float gR_after1 = gR_end + wave_excl_suffix(lane_gR);
         const float gR_after0 = gR_after1 + w1 * gc1;
-        BgVal acc[8];
+        // a1: the second sample's corners; a0: the first's (and the second's
+        // when both lie in one cell)
+        BgVal a0[8], a1[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] = BgVal{0.f, 0.f, 0.f, 0.f};
-        if (s1.ok) bg_terms(s1, w1, T_after1, gR_after1, g, acc);
-        if (s0.ok && s1.ok && s0.cell != s1.cell) {
-            bg_flush(a, s1.ids, acc);
+        for (int c = 0; c < 8; ++c) a0[c] = a1[c] = BgVal{0.f, 0.f, 0.f, 0.f};
+        if (s1.ok) bg_terms(s1, w1, T_after1, gR_after1, g, a1);
+        if (s0.ok) bg_terms(s0, w0, T_after0, gR_after0, g, a0);
+        const bool same = s0.ok && s1.ok && s0.cell == s1.cell;
+        if (same) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc[c] = BgVal{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < 8; ++c) {
+                a0[c].s += a1[c].s;
+                a0[c].r += a1[c].r;
+                a0[c].g += a1[c].g;
+                a0[c].b += a1[c].b;
+                a1[c] = BgVal{0.f, 0.f, 0.f, 0.f};
+            }
         }
-        if (s0.ok) bg_terms(s0, w0, T_after0, gR_after0, g, acc);
-        if (s0.ok) bg_flush(a, s0.ids, acc);
-        else if (s1.ok) bg_flush(a, s1.ids, acc);
+        // hand the second sample's upper corners to the next lane when they
+        // are its first sample's lower corners
+        const int64_t up_cell = s1.ok ? s1.cell + (int64_t)a.H * a.W : -1;
+        const int64_t next_cell = __shfl_down(s0.ok ? s0.cell : (int64_t)-2, 1);
+        const bool give = L < 63 && up_cell == next_cell;
+        const bool take = __shfl_up(give ? 1 : 0, 1) != 0 && L > 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const BgVal u = same ? a0[4 + c] : a1[4 + c];
+            const float rs = __shfl_up(u.s, 1), rr = __shfl_up(u.r, 1);
+            const float rg = __shfl_up(u.g, 1), rb = __shfl_up(u.b, 1);
+            if (take) {
+                a0[c].s += rs;
+                a0[c].r += rr;
+                a0[c].g += rg;
+                a0[c].b += rb;
+            }
+            if (give) {
+                if (same) a0[4 + c] = BgVal{0.f, 0.f, 0.f, 0.f};
+                else a1[4 + c] = BgVal{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        bg_flush(a, s1.ids, a1, s1.ok && !same);
+        bg_flush(a, s0.ids, a0, s0.ok);
+        if (s1.ok) bg_mark(a, s1.ids);
+        if (s0.ok && !same) bg_mark(a, s0.ids);
         tau_end -= __shfl(wave_incl_prefix(lane_sd), 63);
         gR_end += wave_sum(lane_gR);
     }

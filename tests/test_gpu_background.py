@@ -62,8 +62,10 @@ def bg_rays(n, seed):
     return torch.cat([o, o2, torch.zeros(6, 3)]), torch.cat([d, d2, ax])
 
 
-@pytest.mark.parametrize("reso,seed", [((8, 16, 32), 121), ((5, 7, 9), 122)])
+@pytest.mark.parametrize("reso,seed", [((8, 16, 32), 121), ((5, 7, 9), 122), ((80, 6, 10), 123)])
 def test_bg_forward_backward_match_oracle(reso, seed):
+    """(80, 6, 10): 158 samples per ray, more than one 128-sample round of
+    the wave-per-ray kernels."""
     say("bg fwd/bwd", reso)
     og, gg = bg_pair(reso, seed)
     o, d = bg_rays(1500, seed + 10)
