@@ -105,20 +105,6 @@ struct BgVal {
     float s, r, g, b;  // pre-activation density and colour coefficients
 };
 
-__device__ __forceinline__ BgVal bg_interp(const BgArgs &a, const int ids[8], const float w[8]) {
-    BgVal v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (ids[c] < 0) continue;
-        const float *p = a.rec + (int64_t)ids[c] * PLX_REC_SLOTS;
-        v.s += w[c] * p[PLX_SLOT_SIGMA];
-        v.r += w[c] * p[kSlotR];
-        v.g += w[c] * p[kSlotR + 1];
-        v.b += w[c] * p[kSlotR + 2];
-    }
-    return v;
-}
-
 __device__ __forceinline__ void load_ray(const BgArgs &a, int64_t ray, double o[3], double d[3]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -177,15 +163,69 @@ struct BgSmp {
     BgVal v;
 };
 
-__device__ __forceinline__ void bg_load(const BgArgs &a, const double o[3], const double d[3], int k, int n,
+__device__ __forceinline__ void bg_geom(const BgArgs &a, const double o[3], const double d[3], int k, int n,
                                         BgSmp &s) {
     s.ok = k < n && bg_sample(a, o, d, k, s.ids, s.w, &s.cell);
     if (!s.ok) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) s.ids[c] = -1;
+        for (int c = 0; c < 8; ++c) {
+            s.ids[c] = -1;
+            s.w[c] = 0.0f;
+        }
         s.cell = -1;
     }
-    s.v = s.ok ? bg_interp(a, s.ids, s.w) : BgVal{0.f, 0.f, 0.f, 0.f};
+}
+
+// Colour slots 24..26 and the density (slot 28) of record id.
+__device__ __forceinline__ float4 bg_rec(const BgArgs &a, int id) {
+    const float *p = a.rec + (int64_t)id * PLX_REC_SLOTS;
+    const float4 c = *reinterpret_cast<const float4 *>(p + kSlotR);
+    return make_float4(c.x, c.y, c.z, p[PLX_SLOT_SIGMA]);
+}
+
+// Samples k (even: on sphere k/2) and k + 1 (halfway to the next sphere)
+// with their interpolated values.  A corner's record is read only where its
+// weight is non-zero (the even sample's upper corners have weight 0), and
+// the odd sample takes its lower corners from the even one when both lie in
+// one cell, so a pair reads 8 records where 16 corners are interpolated.
+// The sums run over the corners in order, as bg_interp's.
+__device__ __forceinline__ void bg_load_pair(const BgArgs &a, const double o[3], const double d[3], int k,
+                                             int n, BgSmp &s0, BgSmp &s1) {
+    bg_geom(a, o, d, k, n, s0);
+    bg_geom(a, o, d, k + 1, n, s1);
+    float4 r0[8];
+    BgVal v0{0.f, 0.f, 0.f, 0.f}, v1{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const bool need = s0.ids[c] >= 0 && s0.w[c] != 0.0f;
+        r0[c] = need ? bg_rec(a, s0.ids[c]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!(s0.ids[c] >= 0 && s0.w[c] != 0.0f)) continue;
+        v0.s += s0.w[c] * r0[c].w;
+        v0.r += s0.w[c] * r0[c].x;
+        v0.g += s0.w[c] * r0[c].y;
+        v0.b += s0.w[c] * r0[c].z;
+    }
+    const bool same = s0.ok && s1.ok && s0.cell == s1.cell;
+    float4 r1[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const bool need = s1.ids[c] >= 0 && s1.w[c] != 0.0f;
+        const bool reuse = same && s0.w[c] != 0.0f;
+        r1[c] = reuse ? r0[c] : (need ? bg_rec(a, s1.ids[c]) : make_float4(0.f, 0.f, 0.f, 0.f));
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!(s1.ids[c] >= 0 && s1.w[c] != 0.0f)) continue;
+        v1.s += s1.w[c] * r1[c].w;
+        v1.r += s1.w[c] * r1[c].x;
+        v1.g += s1.w[c] * r1[c].y;
+        v1.b += s1.w[c] * r1[c].z;
+    }
+    s0.v = v0;
+    s1.v = v1;
 }
 
 // One wave per ray; a round covers 128 samples, lane L taking samples
@@ -203,8 +243,7 @@ __global__ __launch_bounds__(256) void bg_fwd_kernel(BgArgs a) {
     float C[3] = {0.f, 0.f, 0.f};
     for (int base = 0; base < n; base += 128) {
         BgSmp s0, s1;
-        bg_load(a, o, d, base + 2 * L, n, s0);
-        bg_load(a, o, d, base + 2 * L + 1, n, s1);
+        bg_load_pair(a, o, d, base + 2 * L, n, s0, s1);
         const float sd0 = 0.5f * fmaxf(s0.v.s, 0.0f), sd1 = 0.5f * fmaxf(s1.v.s, 0.0f);
         const double lane_sd = (double)sd0 + (double)sd1;
         const double incl = wave_incl_prefix(lane_sd);
@@ -309,8 +348,7 @@ __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
     if (!one_round) {
         for (int base = 0; base < n; base += 128) {
             BgSmp s0, s1;
-            bg_load(a, o, d, base + 2 * L, n, s0);
-            bg_load(a, o, d, base + 2 * L + 1, n, s1);
+            bg_load_pair(a, o, d, base + 2 * L, n, s0, s1);
             tau += (double)(0.5f * fmaxf(s0.v.s, 0.0f)) + (double)(0.5f * fmaxf(s1.v.s, 0.0f));
         }
     }
@@ -326,8 +364,7 @@ __global__ __launch_bounds__(256) void bg_bwd_kernel(BgArgs a) {
     const int last = ((n - 1) / 128) * 128;
     for (int base = last; base >= 0; base -= 128) {
         BgSmp s0, s1;
-        bg_load(a, o, d, base + 2 * L, n, s0);
-        bg_load(a, o, d, base + 2 * L + 1, n, s1);
+        bg_load_pair(a, o, d, base + 2 * L, n, s0, s1);
         const float sd0 = 0.5f * fmaxf(s0.v.s, 0.0f), sd1 = 0.5f * fmaxf(s1.v.s, 0.0f);
         const double lane_sd = (double)sd0 + (double)sd1;
         if (one_round) {
@@ -409,18 +446,20 @@ __global__ __launch_bounds__(256) void bg_fwd_lane_kernel(BgArgs a) {
     double tau = 0.0;
     float C[3] = {0.f, 0.f, 0.f};
     const int n = 2 * (a.L - 1);
-    for (int k = 0; k < n; ++k) {
-        int ids[8];
-        float w[8];
-        int64_t cell;
-        if (!bg_sample(a, o, d, k, ids, w, &cell)) continue;
-        const BgVal v = bg_interp(a, ids, w);
-        const float sd = 0.5f * fmaxf(v.s, 0.0f);
-        const float wk = expf(-(float)tau) * (-expm1f(-sd));
-        C[0] += wk * fmaxf(kY00 * v.r, 0.0f);
-        C[1] += wk * fmaxf(kY00 * v.g, 0.0f);
-        C[2] += wk * fmaxf(kY00 * v.b, 0.0f);
-        tau += (double)sd;
+    for (int k = 0; k < n; k += 2) {
+        BgSmp sp[2];
+        bg_load_pair(a, o, d, k, n, sp[0], sp[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!sp[h].ok) continue;
+            const BgVal v = sp[h].v;
+            const float sd = 0.5f * fmaxf(v.s, 0.0f);
+            const float wk = expf(-(float)tau) * (-expm1f(-sd));
+            C[0] += wk * fmaxf(kY00 * v.r, 0.0f);
+            C[1] += wk * fmaxf(kY00 * v.g, 0.0f);
+            C[2] += wk * fmaxf(kY00 * v.b, 0.0f);
+            tau += (double)sd;
+        }
     }
     const float T = expf(-(float)tau);
 #pragma unroll
