@@ -188,6 +188,29 @@ __device__ void block_add(unsigned long long v, unsigned long long *out) {
     }
 }
 
+// Adds the block's totals of v0 and v1 to out[0] and out[1].
+__device__ void block_add2(unsigned long long v0, unsigned long long v1, unsigned long long *out) {
+    __shared__ unsigned long long part[2][kCountThreads / 64];
+    for (int o = 32; o >= 1; o >>= 1) {
+        v0 += __shfl_xor(v0, o);
+        v1 += __shfl_xor(v1, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = v0;
+        part[1][threadIdx.x >> 6] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t0 = 0, t1 = 0;
+        for (int w = 0; w < kCountThreads / 64; ++w) {
+            t0 += part[0][w];
+            t1 += part[1][w];
+        }
+        if (t0) atomicAdd(out, t0);
+        if (t1) atomicAdd(out + 1, t1);
+    }
+}
+
 // Number of non-zero bytes of m[0..n).
 __global__ __launch_bounds__(kCountThreads) void count_nonzero_kernel(const uint8_t *m, int64_t n,
                                                                       unsigned long long *out) {
@@ -350,11 +373,13 @@ __global__ void prune_occ_value_kernel(GridDev g, int64_t ncell, const float *va
     occ8[v] = (id >= 0 && value[id] >= thresh) ? 1 : 0;
 }
 
-__global__ void prune_keep_kernel(GridDev g, int64_t ncell, const uint8_t *occ8, uint8_t *keep,
-                                  unsigned long long *counts) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool nonnull = false, kept = false;
-    if (v < ncell) {
+__global__ __launch_bounds__(kCountThreads) void prune_keep_kernel(GridDev g, int64_t ncell,
+                                                                   const uint8_t *occ8, uint8_t *keep,
+                                                                   unsigned long long *counts) {
+    const int64_t stride = (int64_t)gridDim.x * kCountThreads;
+    unsigned long long n_kept = 0, n_nonnull = 0;
+    for (int64_t v = (int64_t)blockIdx.x * kCountThreads + threadIdx.x; v < ncell; v += stride) {
+        bool nonnull = false, kept = false;
         int k = (int)(v % g.nz);
         int64_t r = v / g.nz;
         int j = (int)(r % g.ny);
@@ -379,12 +404,10 @@ __global__ void prune_keep_kernel(GridDev g, int64_t ncell, const uint8_t *occ8,
             }
         }
         keep[v] = kept ? 1 : 0;
+        n_kept += kept;
+        n_nonnull += nonnull;
     }
-    unsigned long long bk = __ballot(kept), bn = __ballot(nonnull);
-    if ((threadIdx.x & 63) == 0) {
-        if (bk) atomicAdd(&counts[0], (unsigned long long)__popcll(bk));
-        if (bn) atomicAdd(&counts[1], (unsigned long long)__popcll(bn));
-    }
+    block_add2(n_kept, n_nonnull, counts);
 }
 
 __global__ __launch_bounds__(kCountThreads) void upsample_count_kernel(ParentPred pred, int64_t n,
@@ -511,7 +534,7 @@ int prune_count(const plx_grid *grid, const float *value, float thresh, uint8_t 
                         prune_occ_kernel<DT><<<nb, 256, 0, s>>>(g, ncell, thresh, occ8));
     }
     if ((rc = check_launch(fn))) return rc;
-    prune_keep_kernel<<<nb, 256, 0, s>>>(g, ncell, occ8, keep_out, counts);
+    prune_keep_kernel<<<count_blocks(ncell), kCountThreads, 0, s>>>(g, ncell, occ8, keep_out, counts);
     if ((rc = check_launch(fn))) return rc;
     int64_t h[2];
     if ((rc = sync_read_u64(counts, 2, h, s, fn))) return rc;
