@@ -67,8 +67,8 @@ int validate_grid(const plx_grid *g, bool need_occ, const char *fn) {
 // Temporaries come from a stream-ordered memory pool of the library's own,
 // one per device, created on first use and kept until the process ends.  Its
 // release threshold is unlimited: memory freed at the end of a call stays in
-// the pool for the next one.  (The default pool hands freed memory back to
-// the driver at synchronisation points, and the render calls synchronise
+// the pool for the next one.  (The default pool releases freed memory to
+// the system at synchronisation points, and the render calls synchronise
 // once for their segment count, so their per-segment buffers, about 130 MB
 // for a 1M-ray batch, were mapped anew on every call.)
 namespace {
