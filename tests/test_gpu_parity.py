@@ -394,10 +394,13 @@ def test_train_step_c1_matches_oracle():
     assert torch.all(grad == 0) and torch.all(touched == 0)
 
 
-def test_fused_train_equals_fwd_mse_bwd():
-    say("fused vs separate")
+@pytest.mark.parametrize("step_voxels", [0.5, 0.05])
+def test_fused_train_equals_fwd_mse_bwd(step_voxels):
+    """Also at a step of 0.05 voxel: up to 279 samples per brick crossing,
+    so a segment spans several 16-sample occupancy chunks."""
+    say("fused vs separate", step_voxels)
     sv = synth.dense_random((24, 24, 24), seed=61, occupancy=0.4, ho_scale=0.2)
-    _, gg = make_pair(sv)
+    _, gg = make_pair(sv, step_voxels=step_voxels)
     o, d = synth.random_rays(5000, seed=62)
     o, d = o.cuda(), d.cuda()
     tgt = synth.targets_uniform(5000, seed=63).cuda()
@@ -419,7 +422,7 @@ def test_fused_train_equals_fwd_mse_bwd():
     assert torch.equal(t1, t2)
     assert abs(loss.item() - ((rgb.double() - tgt.double()) ** 2).sum().item() / n) <= 1e-6 * loss.item()
     # both against the oracle
-    og = make_pair(sv)[0]
+    og = make_pair(sv, step_voxels=step_voxels)[0]
     on, dn, tn = o.cpu().numpy(), d.cpu().numpy(), tgt.cpu().double().numpy()
     rgb_ref = O.render_fwd(og, on, dn)[0]
     g_rgb, loss_ref = O.mse_grad(rgb_ref, tn)
