@@ -341,7 +341,9 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
  * sigma and the SH coefficients are ADDED (FP32 atomics) into grad (device
  * [M] FP32 records); touched (device uint8[M], one byte per voxel) is set to 1
  * for every non-NULL corner voxel of every sample in an occupied cell (plain
- * byte stores: set bytes are never cleared here).  plx_render_fwd,
+ * byte stores: set bytes are never cleared here).  grad and touched may be
+ * NULL when the grid has no occupied voxel (nothing is written then).
+ * plx_render_fwd,
  * plx_render_bwd and plx_render_train process the rays in brick order
  * (temporary device memory; synchronising once, to size the per-brick ray
  * segments). */

@@ -1840,7 +1840,7 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_rays == 0) return PLX_OK;
-    if (!grad_rgb || !tau_fwd || !grad || !touched)
+    if (!grad_rgb || !tau_fwd || (grid->n_vox > 0 && (!grad || !touched)))
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
@@ -1880,7 +1880,7 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_rays == 0) return PLX_OK;
-    if (!target || !grad || !touched || !loss_sum)
+    if (!target || !loss_sum || (grid->n_vox > 0 && (!grad || !touched)))
         return fail(PLX_EINVAL, "%s: NULL target/grad/touched/loss_sum", fn);
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
@@ -1929,7 +1929,7 @@ int plx_render_bwd_state(const plx_grid *grid, const plx_render_opts *opts, cons
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_rays == 0) return PLX_OK;
-    if (!grad_rgb || !tau_fwd || !grad || !touched)
+    if (!grad_rgb || !tau_fwd || (grid->n_vox > 0 && (!grad || !touched)))
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
     RenderArgs a = base_args(opts, rays_o, rays_d, n_rays);
     if ((rc = priors_from(opts, a.pri, fn))) return rc;

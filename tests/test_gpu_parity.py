@@ -171,6 +171,52 @@ def test_forward_empty_inputs():
     assert torch.all(out == 7.0)
 
 
+def test_train_and_backward_without_segments():
+    """No segment is cut: rays that miss the grid, a grid with no occupied
+    voxel, zero rays.  The colour is the background, the loss is the
+    background's, and no gradient or touched byte is written (an empty grid
+    takes NULL gradient buffers)."""
+    say("no segments")
+    bg = (0.2, 0.4, 0.6)
+    reso = (12, 10, 9)
+    sv = synth.dense_random(reso, seed=71, occupancy=0.5)
+    og, gg = make_pair(sv)
+    empty = Grid.from_mask(torch.zeros(int(np.prod(reso)), dtype=torch.uint8, device="cuda"), reso)
+    assert empty.n_vox == 0
+    away_o = torch.tensor([[2.0, 0.0, 0.0], [0.0, -3.0, 0.5], [0.1, 0.2, 5.0]]).repeat(50, 1)
+    away_d = torch.tensor([[1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, 1.0]]).repeat(50, 1)
+    o_in, d_in = synth.random_rays(150, seed=72)
+    for grid, o, d, name in ((gg, away_o, away_d, "miss"), (empty, o_in, d_in, "empty grid")):
+        n = o.shape[0]
+        tgt = synth.targets_uniform(n, seed=73)
+        m = grid.n_vox
+        grad = torch.zeros(m, 32, device="cuda")
+        touched = torch.zeros(m, dtype=torch.uint8, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        rgb = torch.empty(n, 3, device="cuda")
+        B.plx_render_train(grid.desc(), o.cuda(), d.cuda(), tgt.cuda(), 1.0 / n, grad, touched, loss, rgb, bg)
+        B.plx_render_bwd(grid.desc(), o.cuda(), d.cuda(), torch.ones(n, 3, device="cuda"),
+                         torch.zeros(n, device="cuda"), grad, touched, bg)
+        torch.cuda.synchronize()
+        if name == "miss":
+            rgb_ref = O.render_fwd(og, o.numpy(), d.numpy(), bg)[0]
+        else:  # no medium: the background alone
+            rgb_ref = np.tile(np.array(bg, np.float64), (n, 1))
+        _, loss_ref = O.mse_grad(rgb_ref, tgt.double().numpy())
+        assert np.abs(rgb.cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL, name
+        assert abs(loss.item() - loss_ref) <= 1e-6 * loss_ref, name
+        assert not torch.any(grad != 0) and not torch.any(touched != 0), name
+    # zero rays: nothing is read or written
+    z = torch.zeros(0, 3, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
+    B.plx_render_train(gg.desc(), z, z, z, 1.0, grad, touched, loss)
+    B.plx_render_bwd(gg.desc(), z, z, z, torch.zeros(0, device="cuda"), grad, touched)
+    torch.cuda.synchronize()
+    assert loss.item() == 0.0 and not torch.any(grad != 0) and not torch.any(touched != 0)
+
+
 # ------------------------------------------------------------------ backward
 
 @pytest.mark.parametrize("case", ["c1", "sparse"])
