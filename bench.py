@@ -11,7 +11,9 @@ contiguous 1% segment of the cells, and sparse RMSProp on the active voxels.
 
 Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
 (render_train, algorithmic bytes from the library's work counters over its
-HIP-event duration), the same step with BF16/FP16 SH storage and with
+HIP-event duration; beside it the bytes rocprofv3's counters measured for
+the same call, over the same duration, and their ratio to the algorithmic
+bytes), the same step with BF16/FP16 SH storage and with
 shuffled rays and with the sparsity and beta priors on, separate
 forward/backward with and without stored per-sample state, the
 pruning-by-weight pass, the serving latency leg, and the FP64
@@ -400,6 +402,14 @@ def main():
             "traffic": RENDER_TRAIN_TRAFFIC_GB_F32 if sh_dtype == B.PLX_F32 else None,
             "traffic_unit": "GB per call (measured)",
             "algorithmic_gb": round(alg_render / 1e9, 3),
+            # the measured bytes over this run's call time, and their ratio to
+            # the algorithmic bytes
+            "traffic_gbs": (round(RENDER_TRAIN_TRAFFIC_GB_F32 / (k_ms[0] * 1e-3), 1)
+                            if sh_dtype == B.PLX_F32 else None),
+            "traffic_frac": (round(RENDER_TRAIN_TRAFFIC_GB_F32 / (k_ms[0] * 1e-3) / HBM_PEAK_GBS, 4)
+                             if sh_dtype == B.PLX_F32 else None),
+            "amplification": (round(RENDER_TRAIN_TRAFFIC_GB_F32 * 1e9 / alg_render, 2)
+                              if sh_dtype == B.PLX_F32 else None),
         },
         "kernels_ms": {"render_train": round(float(k_ms[0]), 4), "tv_grad": round(float(k_ms[1]), 4),
                        "rmsprop_step": round(float(k_ms[2]), 4)},
