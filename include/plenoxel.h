@@ -200,9 +200,10 @@ int plx_records_convert(int32_t src_dtype, const void *src, int32_t dst_dtype, v
  * cell (i,j,k) (lower corner, i < Nx-1, j < Ny-1, k < Nz-1) is set when the
  * cell has at least one non-NULL corner voxel, and each brick gets its
  * distance to the nearest brick with a set bit.  The bitmap is brick-major so
- * that the cells a ray crosses inside one brick share one 64-byte line.  A sample in a cell without that bit reads
- * only zeros and adds nothing to colour, transmittance or gradient, so the
- * render kernels skip such samples, and whole boxes of empty bricks, exactly.
+ * that the cells a ray crosses inside one brick share one 64-byte line.  A
+ * sample in a cell without that bit reads only zeros and adds nothing to
+ * colour, transmittance or gradient, so the render kernels skip such
+ * samples, and whole boxes of empty bricks, exactly.
  * occ_out: device, plx_occ_bytes(reso) bytes.  Temporary device memory is not
  * used. */
 int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream stream);

@@ -702,7 +702,9 @@ int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stre
     ParentPred pred{grid->index, {grid->reso[0], grid->reso[1], grid->reso[2]},
                     {out->reso[0], out->reso[1], out->reso[2]}};
     int64_t n = n_cells(out->reso);
-    if ((rc = run_scan(pred, IndexWriter{const_cast<int32_t *>(out->index)}, n, s, "plx_grid_upsample_apply"))) return rc;
+    if ((rc = run_scan(pred, IndexWriter{const_cast<int32_t *>(out->index)}, n, s,
+                       "plx_grid_upsample_apply")))
+        return rc;
     GridDev g = to_dev(grid);
     PLX_DISPATCH_DT(grid->sh_dtype, DT,
                     upsample_values_kernel<DT><<<blocks_for(n, 256), 256, 0, s>>>(

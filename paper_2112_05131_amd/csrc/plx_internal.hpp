@@ -42,7 +42,9 @@ inline int64_t n_bricks(const int32_t r[3]) {
     return (int64_t)bricks_along(r[0]) * bricks_along(r[1]) * bricks_along(r[2]);
 }
 // Cell bitmap: 512 bits (16 words) per brick, bricks in storage order.
-inline int64_t occ_words(const int32_t r[3]) { return n_bricks(r) * (PLX_BRICK * PLX_BRICK * PLX_BRICK / 32); }
+inline int64_t occ_words(const int32_t r[3]) {
+    return n_bricks(r) * (PLX_BRICK * PLX_BRICK * PLX_BRICK / 32);
+}
 inline int64_t occ_brick_offset(const int32_t r[3]) { return (occ_words(r) * 4 + 255) / 256 * 256; }
 
 // -------------------------------------------------------- kernel-side grid

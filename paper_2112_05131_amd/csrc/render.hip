@@ -992,10 +992,10 @@ __device__ __forceinline__ void load_ray_lane(const BinArgs &a, int64_t ray, flo
     }
 }
 
-// Calls f(brick order position, first sample, last sample) for every brick with an occupied
-// cell that the ray's samples enter, in ray order; boxes of empty bricks are
-// skipped with the distance field, and inside a brick only the samples near
-// its exit face are placed.
+// Calls f(brick order position, first sample, last sample) for every brick
+// with an occupied cell that the ray's samples enter, in ray order; boxes of
+// empty bricks are skipped with the distance field, and inside a brick only
+// the samples near its exit face are placed.
 template <class F>
 __device__ __forceinline__ void walk_bricks(const GridDev &g, const RayGeom &r, int n, F &&f) {
     int k = 0;
