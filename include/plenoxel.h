@@ -301,7 +301,8 @@ int plx_rays_to_ndc(const float *rays_o, const float *rays_d, int64_t n_rays, in
  * gradient call), ADDS the gradients of the densities and the three
  * coefficients into grad (device [M] FP32 records, slots 24-26 and 28, FP32
  * atomics) and sets
- * touched (device uint8 [M]) to 1 for every non-NULL corner of every sample. */
+ * touched (device uint8 [M]) to 1 for every non-NULL corner of every sample
+ * (both may be NULL for a background with no stored voxel). */
 /* TV of the MSI background (supplement B.1: the same TV as plx_tv_grad,
  * wrapping around the edges of the equirectangular image): plx_tv_grad's
  * terms, normalisation, segment and errors, with the colour terms taken over

@@ -521,7 +521,8 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
     int rc = bg_args(bg_grid, rays_o, rays_d, n_rays, background, a, fn);
     if (rc) return rc;
     if (n_rays == 0) return PLX_OK;
-    if (!grad_rgb || !grad || !touched) return fail(PLX_EINVAL, "%s: NULL grad_rgb/grad/touched", fn);
+    if (!grad_rgb || (bg_grid->n_vox > 0 && (!grad || !touched)))
+        return fail(PLX_EINVAL, "%s: NULL grad_rgb/grad/touched", fn);
     a.grad_rgb = grad_rgb;
     a.grad = grad;
     a.touched = touched;

@@ -39,6 +39,40 @@ def bg_pair(reso, seed, occupancy=0.7, sigma_hi=4.0):
     return og, gg
 
 
+def test_background_empty_inputs():
+    """Zero rays write nothing (background passes, NDC warp); a zero-cell
+    background TV adds nothing; a background with no stored voxel renders
+    the constant colour with transmittance 1 and writes no gradient (NULL
+    gradient buffers)."""
+    say("bg empty")
+    reso = (6, 8, 10)
+    _, gg = bg_pair(reso, 131)
+    bgc = (0.1, 0.2, 0.3)
+    z = torch.zeros(0, 3, device="cuda")
+    out = torch.full((1, 3), 7.0, device="cuda")
+    grad = torch.zeros(gg.n_vox, 32, device="cuda")
+    touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    B.plx_bg_render_fwd(gg.desc(), z, z, out[:0], None, bgc)
+    B.plx_bg_render_bwd(gg.desc(), z, z, z, grad, touched, bgc)
+    B.plx_rays_to_ndc(z, z, 64, 48, 50.0, 1.0, z, z)
+    B.plx_bg_tv_grad(gg.desc(), 0, 0, 1e-3, 1e-3, 1e-9, grad, touched, loss)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0) and loss.item() == 0.0
+    assert not torch.any(grad != 0) and not torch.any(touched != 0)
+    empty = Grid.from_mask(torch.zeros(int(np.prod(reso)), dtype=torch.uint8, device="cuda"), reso)
+    assert empty.n_vox == 0
+    o, d = bg_rays(200, 132)
+    n = o.shape[0]
+    rgb = torch.empty(n, 3, device="cuda")
+    t = torch.empty(n, device="cuda")
+    B.plx_bg_render_fwd(empty.desc(), o.cuda(), d.cuda(), rgb, t, bgc)
+    B.plx_bg_render_bwd(empty.desc(), o.cuda(), d.cuda(), torch.ones(n, 3, device="cuda"),
+                        torch.zeros(0, 32, device="cuda"), torch.zeros(0, dtype=torch.uint8, device="cuda"), bgc)
+    torch.cuda.synchronize()
+    assert torch.all(rgb.cpu() == torch.tensor([bgc] * n)) and torch.all(t == 1.0)
+
+
 def bg_mass(og, o, d, gabs, bg, extra_gabs=None):
     """Tolerance mass of the background gradient, by the rule of grad_mass:
     GRAD_MASS times the absolute-term sums for |dL/dC_bg|, terms at
