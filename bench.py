@@ -337,6 +337,9 @@ def main():
                     help="for counter runs under rocprofv3: one warm-up and one timed-shape "
                          "training step on one batch, then a 1 GiB device copy that calibrates "
                          "the byte counters; prints no JSON line")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="for trace runs under rocprofv3: only the serving leg, printed as its "
+                         "own JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -346,6 +349,9 @@ def main():
     sh_dtype = B.DTYPES[args.dtype]
     if args.counters:
         counter_run(sh_dtype, args.ray_order == "coherent")
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg()}), flush=True)
         return
     n_batches = min(args.warmup + args.steps, 8)
     gt, grid, batches, vals = build_workload(sh_dtype, n_batches, args.ray_order == "coherent")
