@@ -25,6 +25,17 @@ def test_library_exports_every_header_function():
     assert sorted(B._SIGS) == names
 
 
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library every entry point raises: there is no
+    CPU fallback behind the binding."""
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libplenoxel_hip.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="HIP library not built"):
+        B.lib()
+    with pytest.raises(RuntimeError, match="HIP library not built"):
+        B.plx_version()
+
+
 def test_version_and_record_sizes():
     assert "gfx950" in B.plx_version()
     assert B.plx_record_bytes(B.PLX_F32) == 128
