@@ -37,6 +37,11 @@ unbounded_360: a 360-degree scene (Sec. 3.6): a 256^3 blob scene inside the
   with the background at the paper's 64 x 1024 x 2048.  Reports times,
   voxel counts and held-out PSNR.
 
+serving_sweep: the multi-scene view server (8 resident scenes, 4 at 256^3
+  and 4 at 512^3, FP16 SH) for several numbers of streams and requests per
+  launch: the saturation rate (300 requests at once) and p50/p99 latency of
+  600 Poisson arrivals at 80% of it.
+
 Host code only chooses the schedule; every step is the library's fused
 render/MSE/backward, TV and sparse RMSProp.
 
@@ -45,6 +50,7 @@ render/MSE/backward, TV and sparse RMSProp.
     python -m paper_2112_05131_amd.runs forward_facing --steps 300 [--prune-thresh 1]
     python -m paper_2112_05131_amd.runs unbounded_360 --steps 300
     python -m paper_2112_05131_amd.runs bg_kernels
+    python -m paper_2112_05131_amd.runs serving_sweep
 """
 from __future__ import annotations
 
@@ -464,9 +470,42 @@ def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512
     return out
 
 
+def serving_sweep(settings=((1, 32), (2, 32), (4, 32), (8, 32), (4, 8), (4, 64)), n_sat: int = 300,
+                  n_load: int = 600, log=print) -> dict:
+    """Saturation rate and 80%-load latency of the view server per (streams,
+    requests per launch) setting, on 8 resident scenes."""
+    from .serve import Server, random_requests, run_load
+    scenes = []
+    for i, seed in enumerate(range(3, 11)):
+        reso = (256,) * 3 if i < 4 else (512,) * 3
+        occ = 0.05 + 0.05 * (i % 4) / 3.0
+        sv = synth.blob_scene(reso, 32, occ, seed, device="cuda")
+        scenes.append(Grid.from_mask(sv.mask, reso, sv.density, sv.sh, sh_dtype=B.PLX_F16))
+        del sv
+    torch.cuda.synchronize()
+    out = {"scenes": "4x256^3 + 4x512^3, 5-10% occupancy, FP16 SH", "runs": []}
+    for ns, mb in settings:
+        srv = Server(scenes, hbm_budget=1 << 30, n_streams=ns, max_batch=mb, keep_outputs=False)
+        run_load(srv, random_requests(16, 8, seed=99), None)  # warm-up
+        reqs = random_requests(n_sat, 8, seed=100)
+        _, wall = run_load(srv, reqs, None)
+        pix = sum(r.n_pixels for r in reqs)
+        sat = n_sat / wall
+        lat, _ = run_load(srv, random_requests(n_load, 8, seed=180), sat * 0.8, seed=7)
+        r = {"streams": ns, "max_batch": mb, "saturation_requests_s": round(sat, 1),
+             "saturation_mrays_s": round(pix / wall / 1e6, 1),
+             "p50_ms_at_80": round(float(np.percentile(lat, 50)) * 1e3, 2),
+             "p99_ms_at_80": round(float(np.percentile(lat, 99)) * 1e3, 2)}
+        log(f"serving streams={ns} max_batch={mb}: {r}")
+        out["runs"].append(r)
+        del srv
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360", "bg_kernels"])
+    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360", "bg_kernels",
+                                    "serving_sweep"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--prune", choices=["density", "weight"], default="density")
     ap.add_argument("--prune-thresh", type=float, default=None)
@@ -480,6 +519,8 @@ def main(argv=None):
                              prune_thresh=args.prune_thresh, log=log)
     elif args.run == "bg_kernels":
         res = bg_kernels(log=log)
+    elif args.run == "serving_sweep":
+        res = serving_sweep(log=log)
     elif args.run == "unbounded_360":
         s = args.steps or 300
         res = unbounded_360(steps_coarse=s, steps_fine=s, log=log,
