@@ -51,6 +51,8 @@ N_CAMS, W, H = 100, 800, 800
 # (FETCH x2, WRITE x1): 9.811 GB fetched + 8.766 GB written.  Re-measure
 # whenever the render kernels change.
 RENDER_TRAIN_TRAFFIC_GB_F32 = 18.58
+# the same with BF16 SH records (`--dtype bf16`): 4.765 GB + 8.744 GB
+RENDER_TRAIN_TRAFFIC_GB_BF16 = 13.51
 
 
 def log(*a):
@@ -370,6 +372,7 @@ def main():
     P = 112 if sh_dtype == B.PLX_F32 else 58
     alg_render = 4 * counts[2] + (P + 224) * counts[3] + 36 * BATCH
     achieved = alg_render / (k_ms[0] * 1e-3) / 1e9
+    traffic_gb = {B.PLX_F32: RENDER_TRAIN_TRAFFIC_GB_F32, B.PLX_BF16: RENDER_TRAIN_TRAFFIC_GB_BF16}.get(sh_dtype)
     alg_rms = n_act * (672 if sh_dtype == B.PLX_F32 else 726)
     alg_tv = 4 * 4 * tv_cells
     step_gbs = (alg_render + alg_rms + alg_tv) / (ms * 1e-3) / 1e9
@@ -405,17 +408,17 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": RENDER_TRAIN_TRAFFIC_GB_F32 if sh_dtype == B.PLX_F32 else None,
+            "traffic": traffic_gb,
             "traffic_unit": "GB per call (measured)",
             "algorithmic_gb": round(alg_render / 1e9, 3),
             # the measured bytes over this run's call time, and their ratio to
             # the algorithmic bytes
-            "traffic_gbs": (round(RENDER_TRAIN_TRAFFIC_GB_F32 / (k_ms[0] * 1e-3), 1)
-                            if sh_dtype == B.PLX_F32 else None),
-            "traffic_frac": (round(RENDER_TRAIN_TRAFFIC_GB_F32 / (k_ms[0] * 1e-3) / HBM_PEAK_GBS, 4)
-                             if sh_dtype == B.PLX_F32 else None),
-            "amplification": (round(RENDER_TRAIN_TRAFFIC_GB_F32 * 1e9 / alg_render, 2)
-                              if sh_dtype == B.PLX_F32 else None),
+            "traffic_gbs": (round(traffic_gb / (k_ms[0] * 1e-3), 1)
+                            if traffic_gb else None),
+            "traffic_frac": (round(traffic_gb / (k_ms[0] * 1e-3) / HBM_PEAK_GBS, 4)
+                             if traffic_gb else None),
+            "amplification": (round(traffic_gb * 1e9 / alg_render, 2)
+                              if traffic_gb else None),
         },
         "kernels_ms": {"render_train": round(float(k_ms[0]), 4), "tv_grad": round(float(k_ms[1]), 4),
                        "rmsprop_step": round(float(k_ms[2]), 4)},
