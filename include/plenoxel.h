@@ -22,12 +22,17 @@
  *    are validated before any launch (PLX_EINVAL); a HIP error at launch or a
  *    synchronising call is reported as PLX_EDEVICE.  plx_last_error() returns
  *    the message of the last failure on the calling thread.
- *  - Some calls (marked "temporary device memory") take stream-ordered
- *    scratch (hipMallocFromPoolAsync) and release it with hipFreeAsync on
- *    the same stream.  The scratch comes from a memory pool the library
- *    creates per device on first use; the pool keeps freed memory for later
- *    calls (up to the largest scratch a call has needed) until the process
- *    ends.
+ *  - The library never allocates device memory.  Calls that need scratch
+ *    take a caller-owned workspace (`ws`, `ws_bytes`: device memory, 256-byte
+ *    aligned, of at least the size the matching *_bytes query returns); a
+ *    smaller or misaligned workspace is PLX_EINVAL before any launch.  The
+ *    workspace holds nothing between calls, but two calls that share one
+ *    must be ordered on a stream.
+ *  - The render calls (plx_render_fwd/bwd/train/max_weight) take the ray
+ *    batch's segment lists (plx_bins), made by plx_bins_count (synchronising)
+ *    and plx_bins_apply (asynchronous) into caller-owned buffers; the render
+ *    calls themselves neither allocate nor synchronise, so they can be
+ *    captured in a graph.
  *  - Index grids are int32, z fastest: cell (i,j,k) has storage id
  *    (i*Ny + j)*Nz + k; -1 marks NULL.  Table ids of occupied voxels follow
  *    increasing storage id.
@@ -58,8 +63,14 @@ enum {
     PLX_OK = 0,
     PLX_EINVAL = 1,      /* bad argument; nothing was launched */
     PLX_EDEVICE = 2,     /* HIP reported an error */
-    PLX_EUNSUPPORTED = 3 /* valid request this build does not implement */
+    PLX_EUNSUPPORTED = 3, /* valid request this build does not implement */
+    PLX_ENOMEM = 4        /* the request does not fit the fixed scratch of a
+                             call that cannot allocate */
 };
+
+/* Workspace of the counting calls over a plain array (plx_mask_count,
+ * plx_touched_count, plx_grid_upsample_count, plx_render_stats). */
+#define PLX_COUNT_WORKSPACE_BYTES 256
 
 enum { PLX_F32 = 0, PLX_BF16 = 1, PLX_F16 = 2 };
 
@@ -168,16 +179,24 @@ double plx_lr_schedule(double step, double lr0, double lr1, double max_steps,
 
 /* ---------------------------------------------------------------- grid */
 
-/* Number of non-zero bytes of mask[n] (device).  Synchronising;
- * temporary device memory. */
-int plx_mask_count(const uint8_t *mask, int64_t n, int64_t *count_out, plx_stream stream);
+/* Bytes of workspace of the grid calls that take one (plx_grid_create,
+ * plx_grid_prune_count, plx_grid_prune_weight_count, plx_grid_prune_apply,
+ * plx_grid_upsample_apply) for a grid of resolution reso (for
+ * plx_grid_upsample_apply: the new resolution); 0 for a bad reso.  About one
+ * byte per cell. */
+int64_t plx_grid_workspace_bytes(const int32_t reso[3]);
+
+/* Number of non-zero bytes of mask[n] (device).  ws: PLX_COUNT_WORKSPACE_BYTES
+ * of workspace.  Synchronising. */
+int plx_mask_count(const uint8_t *mask, int64_t n, void *ws, int64_t ws_bytes, int64_t *count_out,
+                   plx_stream stream);
 
 /* Index grid from an occupancy mask (Sec. 3.2, supplement B.1): index_out[v]
  * = number of set mask bytes before v, or -1 where mask[v] == 0.  mask and
- * index_out are device arrays of Nx*Ny*Nz entries.  Temporary device
- * memory. */
-int plx_grid_create(const uint8_t *mask, const int32_t reso[3], int32_t *index_out,
-                    plx_stream stream);
+ * index_out are device arrays of Nx*Ny*Nz entries; ws: workspace of
+ * plx_grid_workspace_bytes(reso). */
+int plx_grid_create(const uint8_t *mask, const int32_t reso[3], int32_t *index_out, void *ws,
+                    int64_t ws_bytes, plx_stream stream);
 
 /* Writes n records of sh_dtype into out (device): density[n] and sh[n][27]
  * (device float32) when given, else the constant sigma0 and DC coefficient
@@ -212,10 +231,10 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
  * voxel is occupied when non-NULL with stored density >= sigma_thresh; a
  * non-NULL voxel is kept when it or one of its 26 neighbours is occupied.
  * keep_out (device u8 [Nx*Ny*Nz]) gets 1 for kept voxels.  Returns the
- * numbers kept and removed (exact integers).  Synchronising; temporary
- * device memory. */
-int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,
-                         int64_t *n_kept, int64_t *n_pruned, plx_stream stream);
+ * numbers kept and removed (exact integers).  ws: workspace of
+ * plx_grid_workspace_bytes(grid->reso).  Synchronising. */
+int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out, void *ws,
+                         int64_t ws_bytes, int64_t *n_kept, int64_t *n_pruned, plx_stream stream);
 
 /* Weight-threshold pruning with dilation (Sec. 3.4, pruning by weight as in
  * PlenOctrees; thresholds in supplement B.1): as plx_grid_prune_count, with a
@@ -223,30 +242,31 @@ int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep
  * float32 [n_vox], the per-voxel maximum sample weight of
  * plx_render_max_weight over the training rays.  keep_out, the counts and the
  * errors are those of plx_grid_prune_count; compact with
- * plx_grid_prune_apply.  Synchronising; temporary device memory. */
+ * plx_grid_prune_apply.  ws as plx_grid_prune_count.  Synchronising. */
 int plx_grid_prune_weight_count(const plx_grid *grid, const float *wmax, float w_thresh,
-                                uint8_t *keep_out, int64_t *n_kept, int64_t *n_pruned,
-                                plx_stream stream);
+                                uint8_t *keep_out, void *ws, int64_t ws_bytes, int64_t *n_kept,
+                                int64_t *n_pruned, plx_stream stream);
 
 /* Compacts a pruned grid: out->index and out->data (sized n_kept from
  * plx_grid_prune_count, same reso and dtype as grid) get the kept voxels in
- * the original order.  Temporary device memory. */
-int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out,
-                         plx_stream stream);
+ * the original order.  ws: workspace of plx_grid_workspace_bytes(grid->reso). */
+int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out, void *ws,
+                         int64_t ws_bytes, plx_stream stream);
 
 /* Number of voxels of the grid resampled to new_reso: new voxel j (per
  * axis) is occupied when its parent cell floor((2j+1) N_old / (2 N_new)) is
- * occupied.  Synchronising; temporary device memory. */
-int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int64_t *n_out,
-                            plx_stream stream);
+ * occupied.  ws: PLX_COUNT_WORKSPACE_BYTES of workspace.  Synchronising. */
+int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], void *ws,
+                            int64_t ws_bytes, int64_t *n_out, plx_stream stream);
 
 /* Resamples to out->reso (Sec. 3.4: trilinear initialisation after
  * subdivision; any ratio): occupancy as in plx_grid_upsample_count, values
  * by trilinear interpolation of the old field (NULL = 0) at old grid
  * coordinate ((j + 0.5) N_old / N_new) - 0.5 clamped to [0, N_old - 1]
- * (computed in FP64).  out->data has out->sh_dtype records.  Temporary
- * device memory. */
-int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stream);
+ * (computed in FP64).  out->data has out->sh_dtype records.  ws: workspace
+ * of plx_grid_workspace_bytes(out->reso). */
+int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, void *ws, int64_t ws_bytes,
+                            plx_stream stream);
 
 /* ---------------------------------------------------------------- rays */
 
@@ -322,6 +342,61 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
 
 /* ---------------------------------------------------------------- render */
 
+/* Segment lists of a ray batch (the work lists of the render calls).
+ *
+ * The render calls process a batch in brick order: each ray is cut into
+ * segments, one per 8x8x8-cell brick with an occupied cell that its samples
+ * enter (Sec. 3.1-3.3 fix the samples; the cut changes only the order of
+ * the work, not what is computed), and the segments are sorted by brick so
+ * that rays crossing the same voxels run together.  The lists depend only on
+ * the rays, the grid's geometry and its occupancy structure (not on the
+ * voxel values), so one set serves every render call on those rays until the
+ * occupancy is rebuilt.
+ *
+ * Two phases, both on caller-owned device buffers (256-byte aligned):
+ *  1. plx_bins_count fills the ray buffer (plx_bins_ray_bytes(reso, n_rays)
+ *     bytes: per-ray and per-bin counts and offsets, scan temporaries, a
+ *     status word) and returns the number of segments.  Synchronising.
+ *  2. plx_bins_apply writes the bin-major segment records into the segment
+ *     buffer (plx_bins_seg_bytes(n_seg) bytes).  Asynchronous.
+ * The render calls then use both buffers as their scratch (per-ray and
+ * per-segment values passed between their kernels), so render calls that
+ * share one plx_bins must be ordered on a stream; counting the next batch
+ * into other buffers may overlap them.  plx_bins_verify (synchronising)
+ * reports whether the emitting walk of plx_bins_apply met a segment the
+ * count did not reserve (never expected: both walks run the same FP32
+ * recipe; such a segment is dropped rather than written out of range).
+ * Limits: n_rays and n_seg below 2^31 - 256. */
+typedef struct plx_bins {
+    int64_t n_rays;        /* rays the lists were made for */
+    int64_t n_seg;         /* segments (plx_bins_count's result) */
+    void *ray_buf;         /* device, ray_buf_bytes */
+    int64_t ray_buf_bytes;
+    void *seg_buf;         /* device, seg_buf_bytes (may be NULL when n_seg == 0) */
+    int64_t seg_buf_bytes;
+} plx_bins;
+
+/* Bytes of the ray buffer for n_rays rays on a grid of resolution reso, and
+ * of the segment buffer for n_seg segments (0 for bad arguments). */
+int64_t plx_bins_ray_bytes(const int32_t reso[3], int64_t n_rays);
+int64_t plx_bins_seg_bytes(int64_t n_seg);
+
+/* Phase 1: counts the segments of the rays (rays_o/rays_d: device float32
+ * [n_rays][3]) into ray_buf and returns their number in *n_seg (host).
+ * Synchronising (waits for `stream`). */
+int plx_bins_count(const plx_grid *grid, const float *rays_o, const float *rays_d, int64_t n_rays,
+                   void *ray_buf, int64_t ray_buf_bytes, int64_t *n_seg, plx_stream stream);
+
+/* Phase 2: writes the segment records of bins->n_rays rays (the same rays and
+ * grid as phase 1; bins->ray_buf as filled by it, bins->n_seg its result)
+ * into bins->seg_buf.  Asynchronous. */
+int plx_bins_apply(const plx_grid *grid, const float *rays_o, const float *rays_d,
+                   const plx_bins *bins, plx_stream stream);
+
+/* PLX_OK when every segment of plx_bins_apply went where plx_bins_count
+ * reserved it, PLX_EDEVICE otherwise.  Synchronising. */
+int plx_bins_verify(const plx_grid *grid, const plx_bins *bins, plx_stream stream);
+
 /* Forward rendering (Sec. 3.1-3.3).  Each ray (unit direction) is marched
  * through the lattice hull [0,N-1]^3 at t_k = t_near + k*step while
  * t_k < t_far; sample k stands for the interval min(step, t_far - t_k).
@@ -330,10 +405,10 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
  * is composited with Eq. (1) and the background is added with the remaining
  * transmittance.  Outputs (device float32): rgb_out[n_rays][3] and tau_out[n_rays]
  * = sum sigma_k delta_k (the optical depth, so T_final = exp(-tau)).  tau_out
- * may be NULL. */
+ * may be NULL.  bins: the segment lists of these rays (plx_bins). */
 int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
-                   const float *rays_d, int64_t n_rays, float *rgb_out, float *tau_out,
-                   plx_stream stream);
+                   const float *rays_d, int64_t n_rays, const plx_bins *bins, float *rgb_out,
+                   float *tau_out, plx_stream stream);
 
 /* Backward pass of plx_render_fwd for a given dL/dC (grad_rgb[n_rays][3]).
  * Each ray is replayed from its last sample to its first with the
@@ -345,12 +420,9 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
  * for every non-NULL corner voxel of every sample in an occupied cell (plain
  * byte stores: set bytes are never cleared here).  grad and touched may be
  * NULL when the grid has no occupied voxel (nothing is written then).
- * plx_render_fwd,
- * plx_render_bwd and plx_render_train process the rays in brick order
- * (temporary device memory; synchronising once, to size the per-brick ray
- * segments). */
+ * bins: the segment lists of these rays (plx_bins). */
 int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
-                   const float *rays_d, int64_t n_rays, const float *grad_rgb,
+                   const float *rays_d, int64_t n_rays, const plx_bins *bins, const float *grad_rgb,
                    const float *tau_fwd, float *grad, uint8_t *touched, plx_stream stream);
 
 /* One fused training pass over a ray batch: forward, the MSE reconstruction
@@ -358,11 +430,11 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
  * the backward pass into grad/touched as in plx_render_bwd.  loss_scale is
  * 1/(number of rays of the batch) for the paper's mean; loss_sum (device
  * double, ADDED) accumulates loss_scale * sum ||C - target||^2.  rgb_out may
- * be NULL. */
+ * be NULL.  bins: the segment lists of these rays (plx_bins). */
 int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
                      const float *rays_d, const float *target, int64_t n_rays,
-                     float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
-                     double *loss_sum, plx_stream stream);
+                     const plx_bins *bins, float loss_scale, float *rgb_out, float *grad,
+                     uint8_t *touched, double *loss_sum, plx_stream stream);
 
 /* Per-voxel maximum sample weight, the statistic of pruning by weight
  * (Sec. 3.4, the method of PlenOctrees).  Sample k of a ray has the weight
@@ -374,10 +446,9 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
  * and caller-initialised (zeros before the first batch); calls over batches
  * of rays accumulate the maximum over all of them, in any order.  Samples in
  * cells without a non-NULL corner have no voxel to raise and are skipped.
- * Brick order as plx_render_fwd (temporary device memory; synchronising
- * once). */
+ * bins: the segment lists of these rays (plx_bins). */
 int plx_render_max_weight(const plx_grid *grid, const float *rays_o, const float *rays_d,
-                          int64_t n_rays, float *wmax, plx_stream stream);
+                          int64_t n_rays, const plx_bins *bins, float *wmax, plx_stream stream);
 
 /* Backward without recomputing the samples (the stored-state variant of the
  * backward pass of Sec. 3.1-3.3).  plx_render_fwd_state is plx_render_fwd
@@ -444,10 +515,10 @@ int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *v
  * counts[2] = distinct index entries read (corners of occupied cells),
  * counts[3] = distinct non-NULL voxels read.  cell_mark is device scratch of
  * ceil(Nx*Ny*Nz/32) words and vox_mark of ceil(M/32) words; both are cleared
- * by the call.  Synchronising. */
+ * by the call; ws: PLX_COUNT_WORKSPACE_BYTES of workspace.  Synchronising. */
 int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,
-                     int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark,
-                     int64_t counts[4], plx_stream stream);
+                     int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark, void *ws,
+                     int64_t ws_bytes, int64_t counts[4], plx_stream stream);
 
 /* ---------------------------------------------------------------- TV */
 
@@ -460,7 +531,9 @@ int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *ray
  * cell.  Adds lambda_sigma/count * d(sum term_sigma) + lambda_sh/count *
  * d(sum term_sh) into grad (device [M] FP32 records), sets the touched byte
  * of every non-NULL voxel among v and its three forward neighbours, and ADDS the
- * loss to loss_sum (device double; may be NULL). */
+ * loss to loss_sum (device double; may be NULL).  eps must be positive and
+ * finite (PLX_EINVAL otherwise): with eps = 0 a cell whose differences all
+ * vanish would have an infinite derivative. */
 int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
                 float lambda_sigma, float lambda_sh, float eps, float *grad,
                 uint8_t *touched, double *loss_sum, plx_stream stream);
@@ -468,9 +541,9 @@ int plx_tv_grad(const plx_grid *grid, int64_t cell_start, int64_t cell_count,
 /* ---------------------------------------------------------------- optimiser */
 
 /* Number of nonzero bytes among touched[0..n_vox) (the active set of a
- * step).  Synchronising; temporary device memory. */
-int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
-                      plx_stream stream);
+ * step).  ws: PLX_COUNT_WORKSPACE_BYTES of workspace.  Synchronising. */
+int plx_touched_count(const uint8_t *touched, int64_t n_vox, void *ws, int64_t ws_bytes,
+                      int64_t *count_out, plx_stream stream);
 
 /* RMSProp (Sec. 3.5) on the active voxels (nonzero touched bytes): for each
  * of the 28 values, v <- beta v + (1-beta) g^2 and p <- p - lr g / (sqrt(v) +

@@ -347,7 +347,10 @@ def ray_extent(g: Grid, o, d):
 
 
 def tv(g: Grid, start, count, lambda_sigma, lambda_sh, eps=1e-9):
-    """Returns loss, grad_density[M], grad_sh[M,27], touched[M]."""
+    """Returns loss, grad_density[M], grad_sh[M,27], touched[M].  eps > 0
+    (the square root's derivative is unbounded at 0)."""
+    if not eps > 0.0:
+        raise ValueError("TV eps must be positive")
     gd = np.zeros(g.n_vox, np.float64)
     gs = np.zeros((g.n_vox, 27), np.float64)
     touched = np.zeros(g.n_vox, np.uint8)
@@ -359,7 +362,9 @@ def tv(g: Grid, start, count, lambda_sigma, lambda_sh, eps=1e-9):
 
 def bg_tv(g: Grid, start, count, lambda_sigma, lambda_color, eps=1e-9):
     """TV of an MSI background grid (azimuth wraps, colour slots 24-26):
-    loss, grad_density[M], grad_sh[M,27], touched[M]."""
+    loss, grad_density[M], grad_sh[M,27], touched[M]; eps > 0 as for tv."""
+    if not eps > 0.0:
+        raise ValueError("TV eps must be positive")
     gd = np.zeros(g.n_vox, np.float64)
     gs = np.zeros((g.n_vox, 27), np.float64)
     touched = np.zeros(g.n_vox, np.uint8)

@@ -47,6 +47,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* record slots of the MSI background's three colour coefficients */
 #define ORC_BG_SLOT 24
@@ -667,6 +670,118 @@ int orc_ray_extent(const int32_t reso[3], const float scale[3],
 }
 
 /* ------------------------------------------------------------------------ */
+/* Deterministic accumulation of per-voxel sums over rays.
+ *
+ * The rays are taken in fixed blocks of ORC_RAY_BLOCK consecutive rays.  A
+ * block's terms are summed, ray after ray and sample after sample, into a
+ * private sparse accumulator (a slot per voxel it touches, in first-touch
+ * order); the blocks' partial sums are then added into the output arrays in
+ * block order.  Every voxel's sum is therefore formed in one fixed order,
+ * whatever the number of threads or their scheduling, and the results are
+ * the same bits from run to run.  OpenMP only runs several blocks at once. */
+#define ORC_RAY_BLOCK 1024
+#define ORC_ACC_W (ORC_NSH + 1) /* 27 SH values, then sigma */
+
+typedef struct {
+    int32_t *slot;   /* [M]: slot of a voxel in this block, -1 if none */
+    int64_t *ids;    /* voxels in first-touch order */
+    double *val;     /* [n][ORC_ACC_W] */
+    int64_t n, cap;
+} sparse_acc;
+
+static void acc_init(sparse_acc *a, int64_t n_vox)
+{
+    a->slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_vox > 0 ? n_vox : 1));
+    for (int64_t i = 0; i < n_vox; ++i) a->slot[i] = -1;
+    a->cap = 1024;
+    a->n = 0;
+    a->ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)a->cap);
+    a->val = (double *)malloc(sizeof(double) * ORC_ACC_W * (size_t)a->cap);
+}
+
+static void acc_free(sparse_acc *a)
+{
+    free(a->slot);
+    free(a->ids);
+    free(a->val);
+}
+
+/* Row of voxel id, created (zeroed) on first touch. */
+static double *acc_row(sparse_acc *a, int64_t id)
+{
+    int32_t k = a->slot[id];
+    if (k < 0) {
+        if (a->n == a->cap) {
+            a->cap *= 2;
+            a->ids = (int64_t *)realloc(a->ids, sizeof(int64_t) * (size_t)a->cap);
+            a->val = (double *)realloc(a->val, sizeof(double) * ORC_ACC_W * (size_t)a->cap);
+        }
+        k = (int32_t)a->n++;
+        a->slot[id] = k;
+        a->ids[k] = id;
+        memset(a->val + (size_t)k * ORC_ACC_W, 0, sizeof(double) * ORC_ACC_W);
+    }
+    return a->val + (size_t)k * ORC_ACC_W;
+}
+
+/* Adds a block's sums into out_density[M] / out_sh[M*27] (and marks
+ * touched[M] when given), then empties the accumulator. */
+static void acc_flush(sparse_acc *a, double *out_density, double *out_sh, uint8_t *touched)
+{
+    for (int64_t k = 0; k < a->n; ++k) {
+        const int64_t id = a->ids[k];
+        const double *v = a->val + (size_t)k * ORC_ACC_W;
+        for (int q = 0; q < ORC_NSH; ++q) out_sh[id * ORC_NSH + q] += v[q];
+        out_density[id] += v[ORC_NSH];
+        if (touched) touched[id] = 1;
+        a->slot[id] = -1;
+    }
+    a->n = 0;
+}
+
+typedef void (*ray_body_fn)(const void *ctx, int64_t r, sparse_acc *acc);
+
+/* Runs body over every ray, block by block, and adds the block sums into the
+ * outputs in block order (see above). */
+static void accumulate_over_rays(int64_t n_rays, int64_t n_vox, ray_body_fn body, const void *ctx,
+                                 double *out_density, double *out_sh, uint8_t *touched)
+{
+    const int64_t n_blocks = (n_rays + ORC_RAY_BLOCK - 1) / ORC_RAY_BLOCK;
+    int n_thr = 1;
+#ifdef _OPENMP
+    n_thr = omp_get_max_threads();
+#endif
+    sparse_acc *acc = (sparse_acc *)malloc(sizeof(sparse_acc) * (size_t)n_thr);
+    for (int t = 0; t < n_thr; ++t) acc_init(&acc[t], n_vox);
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += n_thr) {
+        /* blocks b0 .. b0 + n_thr - 1, one per accumulator */
+#pragma omp parallel for schedule(static, 1)
+        for (int t = 0; t < n_thr; ++t) {
+            const int64_t b = b0 + t;
+            if (b >= n_blocks) continue;
+            const int64_t r1 = (b + 1) * ORC_RAY_BLOCK < n_rays ? (b + 1) * ORC_RAY_BLOCK : n_rays;
+            for (int64_t r = b * ORC_RAY_BLOCK; r < r1; ++r) body(ctx, r, &acc[t]);
+        }
+        for (int t = 0; t < n_thr && b0 + t < n_blocks; ++t)
+            acc_flush(&acc[t], out_density, out_sh, touched);
+    }
+    for (int t = 0; t < n_thr; ++t) acc_free(&acc[t]);
+    free(acc);
+}
+
+typedef struct {
+    const int32_t *reso;
+    const float *scale, *offset;
+    float step;
+    const int32_t *index;
+    const double *density, *sh;
+    const float *rays_o, *rays_d;
+    const double *bg;
+    int64_t bg_stride;
+    const double *g_rgb;  /* dL/dC, or |dL/dC| for the mass */
+    double gate_rel;      /* mass only */
+} bwd_ctx;
+
 /* Gradient of the rendered colour for a given dL/dC (grad_rgb[3R]).
  *
  * With C = sum_k w_k c_k + T_n bg, w_k = T_k (1 - exp(-sigma_k delta_k)),
@@ -678,6 +793,53 @@ int orc_ray_extent(const int32_t reso[3], const float scale[3],
  * weights this gives the gradient of every corner value.  Gradients are
  * ADDED into grad_density[M] and grad_sh[M*27]; touched[M] is set to 1 for
  * every non-NULL corner of every sample of every ray (the active set). */
+static void bwd_ray(const void *vctx, int64_t r, sparse_acc *acc)
+{
+    const bwd_ctx *cx = (const bwd_ctx *)vctx;
+    const float *o = cx->rays_o + 3 * r, *d = cx->rays_d + 3 * r;
+    int n = count_samples(cx->reso, cx->scale, cx->offset, cx->step, o, d);
+    if (n == 0) return;
+    sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
+    double rgb[3], tau, T_n;
+    const double *bgr = cx->bg + cx->bg_stride * r;
+    march_ray(cx->reso, cx->scale, cx->offset, cx->step, cx->index, cx->density, cx->sh, o, d, bgr,
+              recs, n, rgb, &tau, &T_n);
+    double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+    double ylm[9];
+    orc_sh_basis(dd, ylm);
+    const double *g = cx->g_rgb + 3 * r;
+
+    /* R = what the ray collects after the current sample, built from the
+     * back so that it is a plain sum. */
+    double R[3] = {T_n * bgr[0], T_n * bgr[1], T_n * bgr[2]};
+    for (int k = n - 1; k >= 0; --k) {
+        const sample_rec *s = &recs[k];
+        double gc = 0.0, gR = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            gc += g[ch] * s->rgb[ch];
+            gR += g[ch] * R[ch];
+        }
+        double dsig = s->sigma_pre > 0.0
+                          ? s->delta * (s->T_next * gc - gR)
+                          : 0.0;
+        double dk[ORC_NSH];
+        for (int ch = 0; ch < 3; ++ch) {
+            double dcol = s->rgb_pre[ch] > 0.0 ? s->weight * g[ch] : 0.0;
+            for (int l = 0; l < 9; ++l) dk[ch * 9 + l] = dcol * ylm[l];
+        }
+        for (int c = 0; c < 8; ++c) {
+            int64_t id = s->ids[c];
+            if (id < 0) continue;
+            double wc = s->w[c];
+            double *row = acc_row(acc, id);
+            row[ORC_NSH] += wc * dsig;
+            for (int q = 0; q < ORC_NSH; ++q) row[q] += wc * dk[q];
+        }
+        for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
+    }
+    free(recs);
+}
+
 void orc_render_bwd(const int32_t reso[3], const float scale[3],
                     const float offset[3], float step, const int32_t *index,
                     const double *density, const double *sh,
@@ -685,55 +847,12 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
                     const double *bg, int64_t bg_stride, const double *grad_rgb,
                     double *grad_density, double *grad_sh, uint8_t *touched)
 {
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t r = 0; r < n_rays; ++r) {
-        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
-        int n = count_samples(reso, scale, offset, step, o, d);
-        if (n == 0) continue;
-        sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
-        double rgb[3], tau, T_n;
-        const double *bgr = bg + bg_stride * r;
-        march_ray(reso, scale, offset, step, index, density, sh, o, d, bgr,
-                  recs, n, rgb, &tau, &T_n);
-        double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
-        double ylm[9];
-        orc_sh_basis(dd, ylm);
-        const double *g = grad_rgb + 3 * r;
-
-        /* R = what the ray collects after the current sample, built from the
-         * back so that it is a plain sum. */
-        double R[3] = {T_n * bgr[0], T_n * bgr[1], T_n * bgr[2]};
-        for (int k = n - 1; k >= 0; --k) {
-            const sample_rec *s = &recs[k];
-            double gc = 0.0, gR = 0.0;
-            for (int ch = 0; ch < 3; ++ch) {
-                gc += g[ch] * s->rgb[ch];
-                gR += g[ch] * R[ch];
-            }
-            double dsig = s->sigma_pre > 0.0
-                              ? s->delta * (s->T_next * gc - gR)
-                              : 0.0;
-            double dk[ORC_NSH];
-            for (int ch = 0; ch < 3; ++ch) {
-                double dcol = s->rgb_pre[ch] > 0.0 ? s->weight * g[ch] : 0.0;
-                for (int l = 0; l < 9; ++l) dk[ch * 9 + l] = dcol * ylm[l];
-            }
-            for (int c = 0; c < 8; ++c) {
-                int64_t id = s->ids[c];
-                if (id < 0) continue;
-                double wc = s->w[c];
-#pragma omp atomic
-                grad_density[id] += wc * dsig;
-                for (int q = 0; q < ORC_NSH; ++q) {
-#pragma omp atomic
-                    grad_sh[id * ORC_NSH + q] += wc * dk[q];
-                }
-                touched[id] = 1;
-            }
-            for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
-        }
-        free(recs);
-    }
+    bwd_ctx cx = {reso, scale, offset, step, index, density, sh, rays_o, rays_d, bg, bg_stride,
+                  grad_rgb, 0.0};
+    int64_t n_vox = 0;
+    for (int64_t v = 0; v < (int64_t)reso[0] * reso[1] * reso[2]; ++v)
+        if (index[v] >= n_vox) n_vox = index[v] + 1;
+    accumulate_over_rays(n_rays, n_vox, bwd_ray, &cx, grad_density, grad_sh, touched);
 }
 
 /* Conditioning of the gradient sums, for tolerances: the same walk as
@@ -749,6 +868,62 @@ void orc_render_bwd(const int32_t reso[3], const float scale[3],
  * terms that form it, float32 may decide it either way, and both gradients
  * are correct.  Such terms enter the mass whether or not the gate is open
  * here, so the tolerance admits either decision. */
+static void mass_ray(const void *vctx, int64_t r, sparse_acc *acc)
+{
+    const bwd_ctx *cx = (const bwd_ctx *)vctx;
+    const double *density = cx->density, *sh = cx->sh;
+    const double gate_rel = cx->gate_rel;
+    const float *o = cx->rays_o + 3 * r, *d = cx->rays_d + 3 * r;
+    int n = count_samples(cx->reso, cx->scale, cx->offset, cx->step, o, d);
+    if (n == 0) return;
+    sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
+    double rgb[3], tau, T_n;
+    const double *bgr = cx->bg + cx->bg_stride * r;
+    march_ray(cx->reso, cx->scale, cx->offset, cx->step, cx->index, density, sh, o, d, bgr,
+              recs, n, rgb, &tau, &T_n);
+    double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+    double ylm[9];
+    orc_sh_basis(dd, ylm);
+    const double *g = cx->g_rgb + 3 * r;
+    double R[3] = {T_n * fabs(bgr[0]), T_n * fabs(bgr[1]), T_n * fabs(bgr[2])};
+    for (int k = n - 1; k >= 0; --k) {
+        const sample_rec *s = &recs[k];
+        /* absolute sums behind sigma_pre and the three colours */
+        double abs_sig = 0.0, abs_col[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 8; ++c) {
+            int64_t id = s->ids[c];
+            if (id < 0) continue;
+            abs_sig += s->w[c] * fabs(density[id]);
+            for (int ch = 0; ch < 3; ++ch)
+                for (int l = 0; l < 9; ++l)
+                    abs_col[ch] += s->w[c] * fabs(sh[id * ORC_NSH + ch * 9 + l] * ylm[l]);
+        }
+        double gc = 0.0, gR = 0.0;
+        for (int ch = 0; ch < 3; ++ch) {
+            gc += g[ch] * fabs(s->rgb_pre[ch]);
+            gR += g[ch] * R[ch];
+        }
+        int sig_on = s->sigma_pre > 0.0 || fabs(s->sigma_pre) <= gate_rel * abs_sig;
+        double msig = sig_on ? s->delta * (s->T_next * gc + gR) : 0.0;
+        double mk[ORC_NSH];
+        for (int ch = 0; ch < 3; ++ch) {
+            int on = s->rgb_pre[ch] > 0.0 || fabs(s->rgb_pre[ch]) <= gate_rel * abs_col[ch];
+            double dcol = on ? s->weight * g[ch] : 0.0;
+            for (int l = 0; l < 9; ++l) mk[ch * 9 + l] = dcol * fabs(ylm[l]);
+        }
+        for (int c = 0; c < 8; ++c) {
+            int64_t id = s->ids[c];
+            if (id < 0) continue;
+            double wc = s->w[c];
+            double *row = acc_row(acc, id);
+            row[ORC_NSH] += wc * msig;
+            for (int q = 0; q < ORC_NSH; ++q) row[q] += wc * mk[q];
+        }
+        for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
+    }
+    free(recs);
+}
+
 void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
                          const float offset[3], float step,
                          const int32_t *index, const double *density,
@@ -757,61 +932,12 @@ void orc_render_bwd_mass(const int32_t reso[3], const float scale[3],
                          const double *bg, int64_t bg_stride, const double *gabs_rgb,
                          double gate_rel, double *mass_density, double *mass_sh)
 {
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t r = 0; r < n_rays; ++r) {
-        const float *o = rays_o + 3 * r, *d = rays_d + 3 * r;
-        int n = count_samples(reso, scale, offset, step, o, d);
-        if (n == 0) continue;
-        sample_rec *recs = (sample_rec *)malloc(sizeof(sample_rec) * (size_t)n);
-        double rgb[3], tau, T_n;
-        const double *bgr = bg + bg_stride * r;
-        march_ray(reso, scale, offset, step, index, density, sh, o, d, bgr,
-                  recs, n, rgb, &tau, &T_n);
-        double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
-        double ylm[9];
-        orc_sh_basis(dd, ylm);
-        const double *g = gabs_rgb + 3 * r;
-        double R[3] = {T_n * fabs(bgr[0]), T_n * fabs(bgr[1]), T_n * fabs(bgr[2])};
-        for (int k = n - 1; k >= 0; --k) {
-            const sample_rec *s = &recs[k];
-            /* absolute sums behind sigma_pre and the three colours */
-            double abs_sig = 0.0, abs_col[3] = {0.0, 0.0, 0.0};
-            for (int c = 0; c < 8; ++c) {
-                int64_t id = s->ids[c];
-                if (id < 0) continue;
-                abs_sig += s->w[c] * fabs(density[id]);
-                for (int ch = 0; ch < 3; ++ch)
-                    for (int l = 0; l < 9; ++l)
-                        abs_col[ch] += s->w[c] * fabs(sh[id * ORC_NSH + ch * 9 + l] * ylm[l]);
-            }
-            double gc = 0.0, gR = 0.0;
-            for (int ch = 0; ch < 3; ++ch) {
-                gc += g[ch] * fabs(s->rgb_pre[ch]);
-                gR += g[ch] * R[ch];
-            }
-            int sig_on = s->sigma_pre > 0.0 || fabs(s->sigma_pre) <= gate_rel * abs_sig;
-            double msig = sig_on ? s->delta * (s->T_next * gc + gR) : 0.0;
-            double mk[ORC_NSH];
-            for (int ch = 0; ch < 3; ++ch) {
-                int on = s->rgb_pre[ch] > 0.0 || fabs(s->rgb_pre[ch]) <= gate_rel * abs_col[ch];
-                double dcol = on ? s->weight * g[ch] : 0.0;
-                for (int l = 0; l < 9; ++l) mk[ch * 9 + l] = dcol * fabs(ylm[l]);
-            }
-            for (int c = 0; c < 8; ++c) {
-                int64_t id = s->ids[c];
-                if (id < 0) continue;
-                double wc = s->w[c];
-#pragma omp atomic
-                mass_density[id] += wc * msig;
-                for (int q = 0; q < ORC_NSH; ++q) {
-#pragma omp atomic
-                    mass_sh[id * ORC_NSH + q] += wc * mk[q];
-                }
-            }
-            for (int ch = 0; ch < 3; ++ch) R[ch] += s->weight * s->rgb[ch];
-        }
-        free(recs);
-    }
+    bwd_ctx cx = {reso, scale, offset, step, index, density, sh, rays_o, rays_d, bg, bg_stride,
+                  gabs_rgb, gate_rel};
+    int64_t n_vox = 0;
+    for (int64_t v = 0; v < (int64_t)reso[0] * reso[1] * reso[2]; ++v)
+        if (index[v] >= n_vox) n_vox = index[v] + 1;
+    accumulate_over_rays(n_rays, n_vox, mass_ray, &cx, mass_density, mass_sh, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,6 +1,6 @@
 """torch.autograd binding of the renderer: forward = plx_render_fwd, backward
-= plx_render_bwd (reverse replay with recomputed transmittance; only the rays
-and the per-ray optical depth are saved)."""
+= plx_render_bwd (reverse replay with recomputed transmittance; only the rays,
+the per-ray optical depth and the batch's segment lists are saved)."""
 from __future__ import annotations
 
 import torch
@@ -21,9 +21,12 @@ class RenderFn(torch.autograd.Function):
         n = rays_o.shape[0]
         rgb = torch.empty(n, 3, dtype=torch.float32, device=rays_o.device)
         tau = torch.empty(n, dtype=torch.float32, device=rays_o.device)
-        B.plx_render_fwd(grid.desc(), rays_o, rays_d, rgb, tau, bg)
+        desc = grid.desc()
+        bins = B.make_bins(desc, rays_o, rays_d)
+        B.plx_render_fwd(desc, rays_o, rays_d, rgb, tau, bg, bins=bins)
         ctx.save_for_backward(rays_o, rays_d, tau)
         ctx.grid = grid
+        ctx.bins = bins
         ctx.bg = tuple(bg)
         return rgb
 
@@ -34,7 +37,7 @@ class RenderFn(torch.autograd.Function):
         grad = torch.zeros(g.n_vox, B.REC_SLOTS, dtype=torch.float32, device=rays_o.device)
         touched = torch.zeros(g.n_vox, dtype=torch.uint8, device=rays_o.device)
         B.plx_render_bwd(g.desc(), rays_o, rays_d, grad_rgb.contiguous().float(), tau, grad,
-                         touched, ctx.bg)
+                         touched, ctx.bg, bins=ctx.bins)
         return grad, None, None, None, None
 
 

@@ -21,7 +21,8 @@ ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "_build", "libplenoxel_hip.so")
 HEADER = os.path.join(ROOT, "include", "plenoxel.h")
 
-PLX_OK, PLX_EINVAL, PLX_EDEVICE, PLX_EUNSUPPORTED = 0, 1, 2, 3
+PLX_OK, PLX_EINVAL, PLX_EDEVICE, PLX_EUNSUPPORTED, PLX_ENOMEM = 0, 1, 2, 3, 4
+COUNT_WORKSPACE_BYTES = 256
 PLX_F32, PLX_BF16, PLX_F16 = 0, 1, 2
 REC_SLOTS = 32
 SLOT_SIGMA = 28
@@ -73,6 +74,17 @@ class Priors:
     loss: torch.Tensor | None = None
 
 
+class PlxBins(ctypes.Structure):
+    _fields_ = [
+        ("n_rays", ctypes.c_int64),
+        ("n_seg", ctypes.c_int64),
+        ("ray_buf", ctypes.c_void_p),
+        ("ray_buf_bytes", ctypes.c_int64),
+        ("seg_buf", ctypes.c_void_p),
+        ("seg_buf_bytes", ctypes.c_int64),
+    ]
+
+
 class PlxView(ctypes.Structure):
     _fields_ = [
         ("c2w", ctypes.c_double * 12),
@@ -92,6 +104,7 @@ _F = ctypes.c_float
 _I32 = ctypes.c_int32
 _GP = ctypes.POINTER(PlxGrid)
 _OP = ctypes.POINTER(PlxRenderOpts)
+_BP = ctypes.POINTER(PlxBins)
 
 _SIGS = {
     "plx_last_error": ([], ctypes.c_char_p),
@@ -102,35 +115,41 @@ _SIGS = {
     "plx_occ_brick_offset": ([_P], _I64),
     "plx_grid_geometry": ([_P, _P, _P, ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "plx_lr_schedule": ([ctypes.c_double] * 6, ctypes.c_double),
-    "plx_mask_count": ([_P, _I64, _P, _P], ctypes.c_int),
-    "plx_grid_create": ([_P, _P, _P, _P], ctypes.c_int),
+    "plx_grid_workspace_bytes": ([_P], _I64),
+    "plx_mask_count": ([_P, _I64, _P, _I64, _P, _P], ctypes.c_int),
+    "plx_grid_create": ([_P, _P, _P, _P, _I64, _P], ctypes.c_int),
     "plx_records_pack": ([_I32, _I64, _P, _P, _F, _F, _P, _P], ctypes.c_int),
     "plx_records_unpack": ([_I32, _I64, _P, _P, _P, _P], ctypes.c_int),
     "plx_records_convert": ([_I32, _P, _I32, _P, _I64, _P], ctypes.c_int),
     "plx_grid_build_occupancy": ([_GP, _P, _P], ctypes.c_int),
-    "plx_grid_prune_count": ([_GP, _F, _P, _P, _P, _P], ctypes.c_int),
-    "plx_grid_prune_weight_count": ([_GP, _P, _F, _P, _P, _P, _P], ctypes.c_int),
-    "plx_grid_prune_apply": ([_GP, _P, _GP, _P], ctypes.c_int),
-    "plx_grid_upsample_count": ([_GP, _P, _P, _P], ctypes.c_int),
-    "plx_grid_upsample_apply": ([_GP, _GP, _P], ctypes.c_int),
+    "plx_grid_prune_count": ([_GP, _F, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "plx_grid_prune_weight_count": ([_GP, _P, _F, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "plx_grid_prune_apply": ([_GP, _P, _GP, _P, _I64, _P], ctypes.c_int),
+    "plx_grid_upsample_count": ([_GP, _P, _P, _I64, _P, _P], ctypes.c_int),
+    "plx_grid_upsample_apply": ([_GP, _GP, _P, _I64, _P], ctypes.c_int),
     "plx_rays_to_ndc": ([_P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double, _P, _P, _P],
                         ctypes.c_int),
     "plx_bg_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_bg_render_fwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
     "plx_bg_render_bwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
-    "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
-    "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
-    "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
-    "plx_render_max_weight": ([_GP, _P, _P, _I64, _P, _P], ctypes.c_int),
+    "plx_bins_ray_bytes": ([_P, _I64], _I64),
+    "plx_bins_seg_bytes": ([_I64], _I64),
+    "plx_bins_count": ([_GP, _P, _P, _I64, _P, _I64, _P, _P], ctypes.c_int),
+    "plx_bins_apply": ([_GP, _P, _P, _BP, _P], ctypes.c_int),
+    "plx_bins_verify": ([_GP, _BP, _P], ctypes.c_int),
+    "plx_render_fwd": ([_GP, _OP, _P, _P, _I64, _BP, _P, _P, _P], ctypes.c_int),
+    "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _BP, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _BP, _F, _P, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_max_weight": ([_GP, _P, _P, _I64, _BP, _P, _P], ctypes.c_int),
     "plx_render_state_bytes": ([_I64, _I32], _I64),
     "plx_render_fwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P], ctypes.c_int),
     "plx_render_bwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P],
                              ctypes.c_int),
-    "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _P], ctypes.c_int),
+    "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "plx_render_views_workspace": ([_I32, _I32], _I64),
     "plx_render_views": ([_GP, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
     "plx_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
-    "plx_touched_count": ([_P, _I64, _P, _P], ctypes.c_int),
+    "plx_touched_count": ([_P, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "plx_rmsprop_step": ([_GP, _P, _P, _P, _P, _F, _F, _F, _F, _P], ctypes.c_int),
 }
 
@@ -186,6 +205,20 @@ def _i3(v):
     return (ctypes.c_int32 * 3)(*[int(x) for x in v])
 
 
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A device buffer for a call's workspace argument (torch allocations
+    are 256-byte aligned)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+def _ws(ws, nbytes: int, device=None):
+    """(pointer, bytes) of a given workspace tensor, or of a new one."""
+    if ws is None:
+        ws = workspace(nbytes, device)
+    return _dptr(ws, "ws", torch.uint8), ws.numel(), ws
+
+
 # --------------------------------------------------------------------- misc
 
 def plx_version() -> str:
@@ -227,17 +260,23 @@ def plx_lr_schedule(step, lr0, lr1, max_steps, delay_steps=0.0, delay_mult=1.0) 
 
 # --------------------------------------------------------------------- grid
 
-def plx_mask_count(mask: torch.Tensor) -> int:
+def plx_grid_workspace_bytes(reso) -> int:
+    return int(lib().plx_grid_workspace_bytes(ctypes.cast(_i3(reso), _P)))
+
+
+def plx_mask_count(mask: torch.Tensor, ws=None) -> int:
     out = ctypes.c_int64()
-    _check(lib().plx_mask_count(_dptr(mask, "mask", torch.uint8), mask.numel(), ctypes.byref(out),
-                                _stream()))
+    wp, wb, _keep = _ws(ws, COUNT_WORKSPACE_BYTES, mask.device)
+    _check(lib().plx_mask_count(_dptr(mask, "mask", torch.uint8), mask.numel(), wp, wb,
+                                ctypes.byref(out), _stream()))
     return int(out.value)
 
 
-def plx_grid_create(mask: torch.Tensor, reso, index_out: torch.Tensor):
+def plx_grid_create(mask: torch.Tensor, reso, index_out: torch.Tensor, ws=None):
     n = int(reso[0]) * int(reso[1]) * int(reso[2])
+    wp, wb, _keep = _ws(ws, plx_grid_workspace_bytes(reso), mask.device)
     _check(lib().plx_grid_create(_dptr(mask, "mask", torch.uint8, n), ctypes.cast(_i3(reso), _P),
-                                 _dptr(index_out, "index_out", torch.int32, n), _stream()))
+                                 _dptr(index_out, "index_out", torch.int32, n), wp, wb, _stream()))
 
 
 def plx_records_pack(sh_dtype, n, density, sh, sigma0, dc, out):
@@ -262,37 +301,43 @@ def plx_grid_build_occupancy(g: PlxGrid, occ_out: torch.Tensor):
                                           _stream()))
 
 
-def plx_grid_prune_count(g: PlxGrid, sigma_thresh, keep_out: torch.Tensor):
+def plx_grid_prune_count(g: PlxGrid, sigma_thresh, keep_out: torch.Tensor, ws=None):
     kept, pruned = ctypes.c_int64(), ctypes.c_int64()
+    wp, wb, _keep = _ws(ws, plx_grid_workspace_bytes(tuple(g.reso)), keep_out.device)
     _check(lib().plx_grid_prune_count(ctypes.byref(g), float(sigma_thresh),
-                                      _dptr(keep_out, "keep_out", torch.uint8), ctypes.byref(kept),
-                                      ctypes.byref(pruned), _stream()))
+                                      _dptr(keep_out, "keep_out", torch.uint8), wp, wb,
+                                      ctypes.byref(kept), ctypes.byref(pruned), _stream()))
     return int(kept.value), int(pruned.value)
 
 
-def plx_grid_prune_weight_count(g: PlxGrid, wmax: torch.Tensor, w_thresh, keep_out: torch.Tensor):
+def plx_grid_prune_weight_count(g: PlxGrid, wmax: torch.Tensor, w_thresh, keep_out: torch.Tensor,
+                                ws=None):
     kept, pruned = ctypes.c_int64(), ctypes.c_int64()
+    wp, wb, _keep = _ws(ws, plx_grid_workspace_bytes(tuple(g.reso)), keep_out.device)
     _check(lib().plx_grid_prune_weight_count(ctypes.byref(g), _dptr(wmax, "wmax", torch.float32, g.n_vox),
                                              float(w_thresh),
-                                             _dptr(keep_out, "keep_out", torch.uint8),
+                                             _dptr(keep_out, "keep_out", torch.uint8), wp, wb,
                                              ctypes.byref(kept), ctypes.byref(pruned), _stream()))
     return int(kept.value), int(pruned.value)
 
 
-def plx_grid_prune_apply(g: PlxGrid, keep: torch.Tensor, out: PlxGrid):
+def plx_grid_prune_apply(g: PlxGrid, keep: torch.Tensor, out: PlxGrid, ws=None):
+    wp, wb, _keep = _ws(ws, plx_grid_workspace_bytes(tuple(g.reso)), keep.device)
     _check(lib().plx_grid_prune_apply(ctypes.byref(g), _dptr(keep, "keep", torch.uint8),
-                                      ctypes.byref(out), _stream()))
+                                      ctypes.byref(out), wp, wb, _stream()))
 
 
-def plx_grid_upsample_count(g: PlxGrid, new_reso) -> int:
+def plx_grid_upsample_count(g: PlxGrid, new_reso, ws=None) -> int:
     n = ctypes.c_int64()
-    _check(lib().plx_grid_upsample_count(ctypes.byref(g), ctypes.cast(_i3(new_reso), _P),
+    wp, wb, _keep = _ws(ws, COUNT_WORKSPACE_BYTES)
+    _check(lib().plx_grid_upsample_count(ctypes.byref(g), ctypes.cast(_i3(new_reso), _P), wp, wb,
                                          ctypes.byref(n), _stream()))
     return int(n.value)
 
 
-def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid):
-    _check(lib().plx_grid_upsample_apply(ctypes.byref(g), ctypes.byref(out), _stream()))
+def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid, ws=None):
+    wp, wb, _keep = _ws(ws, plx_grid_workspace_bytes(tuple(out.reso)))
+    _check(lib().plx_grid_upsample_apply(ctypes.byref(g), ctypes.byref(out), wp, wb, _stream()))
 
 
 # --------------------------------------------------------------------- render
@@ -343,23 +388,101 @@ def plx_bg_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, grad, touched, bg=(1
                                    _dptr(touched, "touched", torch.uint8), _stream()))
 
 
-def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0)):
+class Bins:
+    """Caller-owned segment lists of one ray batch (plx_bins): the two device
+    buffers and their descriptor.  Made by make_bins (count, then apply);
+    serves every render call on the same rays until the grid's occupancy is
+    rebuilt."""
+
+    def __init__(self, n_rays: int, n_seg: int, ray_buf: torch.Tensor, seg_buf: torch.Tensor | None):
+        self.ray_buf, self.seg_buf = ray_buf, seg_buf
+        self.desc = PlxBins(int(n_rays), int(n_seg), ray_buf.data_ptr(), ray_buf.numel(),
+                            seg_buf.data_ptr() if seg_buf is not None and seg_buf.numel() else None,
+                            seg_buf.numel() if seg_buf is not None else 0)
+
+    @property
+    def n_rays(self) -> int:
+        return int(self.desc.n_rays)
+
+    @property
+    def n_seg(self) -> int:
+        return int(self.desc.n_seg)
+
+
+def plx_bins_ray_bytes(reso, n_rays: int) -> int:
+    return int(lib().plx_bins_ray_bytes(ctypes.cast(_i3(reso), _P), int(n_rays)))
+
+
+def plx_bins_seg_bytes(n_seg: int) -> int:
+    return int(lib().plx_bins_seg_bytes(int(n_seg)))
+
+
+def plx_bins_count(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor) -> int:
+    n = rays_o.shape[0]
+    out = ctypes.c_int64()
+    _check(lib().plx_bins_count(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                _dptr(ray_buf, "ray_buf", torch.uint8), ray_buf.numel(),
+                                ctypes.byref(out), _stream()))
+    return int(out.value)
+
+
+def plx_bins_apply(g: PlxGrid, rays_o, rays_d, bins: Bins):
+    n = rays_o.shape[0]
+    _check(lib().plx_bins_apply(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                _dptr(rays_d, "rays_d", torch.float32, 3 * n),
+                                ctypes.byref(bins.desc), _stream()))
+
+
+def plx_bins_verify(g: PlxGrid, bins: Bins):
+    _check(lib().plx_bins_verify(ctypes.byref(g), ctypes.byref(bins.desc), _stream()))
+
+
+def make_bins(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor | None = None,
+              seg_buf: torch.Tensor | None = None) -> Bins:
+    """Segment lists of a ray batch: plx_bins_count then plx_bins_apply on
+    the current stream, into the given buffers when they are large enough,
+    else into new ones."""
+    n = rays_o.shape[0]
+    need = plx_bins_ray_bytes(tuple(g.reso), n)
+    if ray_buf is None or ray_buf.numel() < need:
+        ray_buf = workspace(need, rays_o.device)
+    n_seg = plx_bins_count(g, rays_o, rays_d, ray_buf)
+    sneed = plx_bins_seg_bytes(n_seg)
+    if n_seg > 0 and (seg_buf is None or seg_buf.numel() < sneed):
+        seg_buf = workspace(sneed, rays_o.device)
+    bins = Bins(n, n_seg, ray_buf, seg_buf if n_seg > 0 else None)
+    plx_bins_apply(g, rays_o, rays_d, bins)
+    return bins
+
+
+def _bins_for(g: PlxGrid, rays_o, rays_d, bins: Bins | None) -> Bins:
+    return make_bins(g, rays_o, rays_d) if bins is None else bins
+
+
+def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0),
+                   bins: Bins | None = None):
     n = rays_o.shape[0]
     o = _opts(bg, None, n)
+    b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                ctypes.byref(b.desc),
                                 _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
                                 _dptr(tau_out, "tau_out", torch.float32, n), _stream()))
 
 
 def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
-                   bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None):
+                   bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None,
+                   bins: Bins | None = None):
     n = rays_o.shape[0]
     o = _opts(bg, priors, n, grad_bg)
+    b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_bwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                ctypes.byref(b.desc),
                                 _dptr(grad_rgb, "grad_rgb", torch.float32, 3 * n),
                                 _dptr(tau_fwd, "tau_fwd", torch.float32, n),
                                 _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
@@ -367,14 +490,16 @@ def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
 
 
 def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
-                     rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None):
+                     rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None,
+                     bins: Bins | None = None):
     n = rays_o.shape[0]
     o = _opts(bg, priors, n, grad_bg)
+    b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_train(ctypes.byref(g), ctypes.byref(o),
                                   _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n),
                                   _dptr(target, "target", torch.float32, 3 * n), n,
-                                  float(loss_scale), _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                  ctypes.byref(b.desc), float(loss_scale), _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
                                   _dptr(touched, "touched", torch.uint8),
                                   _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
@@ -392,11 +517,13 @@ def _state_ptr(state, n, cap):
     return ctypes.c_void_p(state.data_ptr()), state.numel()
 
 
-def plx_render_max_weight(g: PlxGrid, rays_o, rays_d, wmax):
+def plx_render_max_weight(g: PlxGrid, rays_o, rays_d, wmax, bins: Bins | None = None):
     n = rays_o.shape[0]
+    b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_max_weight(ctypes.byref(g),
                                        _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                        _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
+                                       ctypes.byref(b.desc),
                                        _dptr(wmax, "wmax", torch.float32, g.n_vox), _stream()))
 
 
@@ -446,13 +573,14 @@ def plx_render_views(scenes, views, rgb_out, workspace, bg=(1.0, 1.0, 1.0), stre
                                   s))
 
 
-def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark):
+def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark, ws=None):
     n = rays_o.shape[0]
     counts = (ctypes.c_int64 * 4)()
+    wp, wb, _keep = _ws(ws, COUNT_WORKSPACE_BYTES, rays_o.device)
     _check(lib().plx_render_stats(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                   _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
                                   _dptr(cell_mark, "cell_mark", torch.int32),
-                                  _dptr(vox_mark, "vox_mark", torch.int32),
+                                  _dptr(vox_mark, "vox_mark", torch.int32), wp, wb,
                                   ctypes.cast(counts, _P), _stream()))
     return tuple(int(c) for c in counts)
 
@@ -477,9 +605,10 @@ def plx_bg_tv_grad(g: PlxGrid, cell_start, cell_count, lambda_sigma, lambda_colo
                                 _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
 
 
-def plx_touched_count(touched, n_vox) -> int:
+def plx_touched_count(touched, n_vox, ws=None) -> int:
     out = ctypes.c_int64()
-    _check(lib().plx_touched_count(_dptr(touched, "touched", torch.uint8), int(n_vox),
+    wp, wb, _keep = _ws(ws, COUNT_WORKSPACE_BYTES, touched.device)
+    _check(lib().plx_touched_count(_dptr(touched, "touched", torch.uint8), int(n_vox), wp, wb,
                                    ctypes.byref(out), _stream()))
     return int(out.value)
 

@@ -5,8 +5,6 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <mutex>
-
 #include "plx_internal.hpp"
 
 namespace plx {
@@ -62,63 +60,6 @@ int validate_grid(const plx_grid *g, bool need_occ, const char *fn) {
     if ((reinterpret_cast<uintptr_t>(g->data) & 63u) != 0)
         return fail(PLX_EINVAL, "%s: records must be 64-byte aligned", fn);
     return PLX_OK;
-}
-
-// Temporaries come from a stream-ordered memory pool of the library's own,
-// one per device, created on first use and kept until the process ends.  Its
-// release threshold is unlimited: memory freed at the end of a call stays in
-// the pool for the next one.  (The default pool releases freed memory to
-// the system at synchronisation points, and the render calls synchronise
-// once for their segment count, so their per-segment buffers, about 130 MB
-// for a 1M-ray batch, were mapped anew on every call.)
-namespace {
-constexpr int kMaxDevices = 64;
-std::mutex g_pool_mu;
-hipMemPool_t g_pools[kMaxDevices] = {};
-
-int temp_pool(hipMemPool_t *out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail(PLX_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
-    if (dev < 0 || dev >= kMaxDevices) return fail(PLX_EDEVICE, "device %d out of range", dev);
-    std::lock_guard<std::mutex> lock(g_pool_mu);
-    if (!g_pools[dev]) {
-        hipMemPoolProps props = {};
-        props.allocType = hipMemAllocationTypePinned;
-        props.location.type = hipMemLocationTypeDevice;
-        props.location.id = dev;
-        hipMemPool_t pool = nullptr;
-        e = hipMemPoolCreate(&pool, &props);
-        if (e != hipSuccess) return fail(PLX_EDEVICE, "hipMemPoolCreate: %s", hipGetErrorString(e));
-        uint64_t keep = UINT64_MAX;
-        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        if (e != hipSuccess) {
-            (void)hipMemPoolDestroy(pool);
-            return fail(PLX_EDEVICE, "hipMemPoolSetAttribute: %s", hipGetErrorString(e));
-        }
-        g_pools[dev] = pool;
-    }
-    *out = g_pools[dev];
-    return PLX_OK;
-}
-}  // namespace
-
-int TempBuf::alloc(size_t bytes, hipStream_t s) {
-    stream = s;
-    if (bytes == 0) bytes = 16;
-    hipMemPool_t pool = nullptr;
-    int rc = temp_pool(&pool);
-    if (rc) return rc;
-    hipError_t e = hipMallocFromPoolAsync(&ptr, bytes, pool, s);
-    if (e != hipSuccess) {
-        ptr = nullptr;
-        return fail(PLX_EDEVICE, "hipMallocFromPoolAsync(%zu): %s", bytes, hipGetErrorString(e));
-    }
-    return PLX_OK;
-}
-
-TempBuf::~TempBuf() {
-    if (ptr) (void)hipFreeAsync(ptr, stream);
 }
 
 }  // namespace plx

@@ -123,16 +123,53 @@ __global__ __launch_bounds__(kScanThreads) void scan_write_kernel(Pred pred, Wri
     }
 }
 
+// Workspace of the grid calls (caller-owned, plx_grid_workspace_bytes): a
+// 256-byte block of counters, then one byte per cell (the prune occupancy
+// flags), then the per-block counts and offsets of the compaction scan.
+struct WsLayout {
+    int64_t counters, bytes8, scan, bytes;
+};
+inline int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
+inline int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+WsLayout ws_layout(int64_t ncell) {
+    WsLayout l;
+    l.counters = 0;
+    l.bytes8 = 256;
+    l.scan = l.bytes8 + up256(ncell);
+    const int64_t nb = scan_blocks(ncell);
+    l.bytes = l.scan + up256((nb + 1) * 8) + up256(nb * 4);
+    return l;
+}
+
+int check_ws(const void *ws, int64_t ws_bytes, int64_t need, const char *fn) {
+    if (!ws) return fail(PLX_EINVAL, "%s: workspace is NULL", fn);
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(PLX_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+    if (ws_bytes < need)
+        return fail(PLX_EINVAL, "%s: workspace of %lld bytes, need %lld", fn, (long long)ws_bytes, (long long)need);
+    return PLX_OK;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0ull;
+}
+
+// Clears the workspace's counters (a kernel rather than a memset node, so
+// that a captured graph replays it like any other launch).
+int zero_counters(void *ws, hipStream_t s, const char *fn) {
+    zero_u64_kernel<<<1, 32, 0, s>>>(static_cast<unsigned long long *>(ws), 32);
+    return check_launch(fn);
+}
+
 template <class Pred, class Writer>
-int run_scan(Pred pred, Writer wr, int64_t n, hipStream_t s, const char *what) {
+int run_scan(Pred pred, Writer wr, int64_t n, void *ws, hipStream_t s, const char *what) {
     if (n <= 0) return PLX_OK;
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int64_t nb = scan_blocks(n);
     if (nb > 0x7fffffff) return fail(PLX_EINVAL, "%s: too many cells", what);
-    TempBuf tmp;
-    int rc = tmp.alloc(nb * sizeof(int) + (nb + 1) * sizeof(int64_t) + 16, s);
-    if (rc) return rc;
-    int64_t *offsets = static_cast<int64_t *>(tmp.ptr);
-    int *counts = reinterpret_cast<int *>(offsets + nb + 1);
+    const WsLayout l = ws_layout(n);
+    int64_t *offsets = reinterpret_cast<int64_t *>(static_cast<char *>(ws) + l.scan);
+    int *counts = reinterpret_cast<int *>(static_cast<char *>(ws) + l.scan + up256((nb + 1) * 8));
+    int rc;
     scan_count_kernel<<<(unsigned)nb, kScanThreads, 0, s>>>(pred, n, counts);
     if ((rc = check_launch(what))) return rc;
     scan_offsets_kernel<<<1, kScanThreads, 0, s>>>(counts, nb, offsets);
@@ -513,18 +550,19 @@ inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + thre
 // Shared by both prune counts: occupied = non-NULL with density (value ==
 // NULL) or value[id] at least thresh; kept = non-NULL with an occupied voxel
 // in its 3x3x3 neighbourhood.
-int prune_count(const plx_grid *grid, const float *value, float thresh, uint8_t *keep_out,
-                int64_t *n_kept, int64_t *n_pruned, plx_stream stream, const char *fn) {
+int prune_count(const plx_grid *grid, const float *value, float thresh, uint8_t *keep_out, void *ws,
+                int64_t ws_bytes, int64_t *n_kept, int64_t *n_pruned, plx_stream stream,
+                const char *fn) {
     int rc = validate_grid(grid, false, fn);
     if (rc) return rc;
     if (!keep_out || !n_kept || !n_pruned) return fail(PLX_EINVAL, "%s: NULL argument", fn);
     hipStream_t s = as_stream(stream);
     int64_t ncell = n_cells(grid->reso);
-    TempBuf tmp;
-    if ((rc = tmp.alloc(ncell + 64, s))) return rc;
-    auto *counts = static_cast<unsigned long long *>(tmp.ptr);
-    uint8_t *occ8 = static_cast<uint8_t *>(tmp.ptr) + 64;
-    PLX_CHECK_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s), fn);
+    const WsLayout l = ws_layout(ncell);
+    if ((rc = check_ws(ws, ws_bytes, l.bytes, fn))) return rc;
+    auto *counts = static_cast<unsigned long long *>(ws);
+    uint8_t *occ8 = static_cast<uint8_t *>(ws) + l.bytes8;
+    if ((rc = zero_counters(ws, s, fn))) return rc;
     GridDev g = to_dev(grid);
     unsigned nb = blocks_for(ncell, 256);
     if (value) {
@@ -550,32 +588,39 @@ using namespace plx;
 
 extern "C" {
 
-int plx_mask_count(const uint8_t *mask, int64_t n, int64_t *count_out, plx_stream stream) {
+int64_t plx_grid_workspace_bytes(const int32_t reso[3]) {
+    if (!reso || reso[0] < 2 || reso[1] < 2 || reso[2] < 2) return 0;
+    return ws_layout(n_cells(reso)).bytes;
+}
+
+int plx_mask_count(const uint8_t *mask, int64_t n, void *ws, int64_t ws_bytes, int64_t *count_out,
+                   plx_stream stream) {
     if (!count_out) return fail(PLX_EINVAL, "plx_mask_count: count_out is NULL");
     if (n < 0) return fail(PLX_EINVAL, "plx_mask_count: n < 0");
+    int rc = check_ws(ws, ws_bytes, PLX_COUNT_WORKSPACE_BYTES, "plx_mask_count");
+    if (rc) return rc;
     if (n == 0) {
         *count_out = 0;
         return PLX_OK;
     }
     if (!mask) return fail(PLX_EINVAL, "plx_mask_count: mask is NULL");
     hipStream_t s = as_stream(stream);
-    TempBuf tmp;
-    int rc = tmp.alloc(sizeof(unsigned long long), s);
-    if (rc) return rc;
-    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
-    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_mask_count");
+    auto *cnt = static_cast<unsigned long long *>(ws);
+    if ((rc = zero_counters(ws, s, "plx_mask_count"))) return rc;
     count_nonzero_kernel<<<count_blocks(n), kCountThreads, 0, s>>>(mask, n, cnt);
     if ((rc = check_launch("plx_mask_count"))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, "plx_mask_count");
 }
 
-int plx_grid_create(const uint8_t *mask, const int32_t reso[3], int32_t *index_out,
-                    plx_stream stream) {
+int plx_grid_create(const uint8_t *mask, const int32_t reso[3], int32_t *index_out, void *ws,
+                    int64_t ws_bytes, plx_stream stream) {
     if (!mask || !reso || !index_out) return fail(PLX_EINVAL, "plx_grid_create: NULL argument");
     for (int a = 0; a < 3; ++a)
         if (reso[a] < 2) return fail(PLX_EINVAL, "plx_grid_create: reso[%d] < 2", a);
     int64_t n = n_cells(reso);
-    return run_scan(MaskPred{mask}, IndexWriter{index_out}, n, as_stream(stream), "plx_grid_create");
+    int rc = check_ws(ws, ws_bytes, ws_layout(n).bytes, "plx_grid_create");
+    if (rc) return rc;
+    return run_scan(MaskPred{mask}, IndexWriter{index_out}, n, ws, as_stream(stream), "plx_grid_create");
 }
 
 int plx_records_pack(int32_t sh_dtype, int64_t n, const float *density, const float *sh,
@@ -638,22 +683,22 @@ int plx_grid_build_occupancy(const plx_grid *grid, uint32_t *occ_out, plx_stream
     return PLX_OK;
 }
 
-int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out,
-                         int64_t *n_kept, int64_t *n_pruned, plx_stream stream) {
-    return plx::prune_count(grid, nullptr, sigma_thresh, keep_out, n_kept, n_pruned, stream,
-                            "plx_grid_prune_count");
+int plx_grid_prune_count(const plx_grid *grid, float sigma_thresh, uint8_t *keep_out, void *ws,
+                         int64_t ws_bytes, int64_t *n_kept, int64_t *n_pruned, plx_stream stream) {
+    return plx::prune_count(grid, nullptr, sigma_thresh, keep_out, ws, ws_bytes, n_kept, n_pruned,
+                            stream, "plx_grid_prune_count");
 }
 
 int plx_grid_prune_weight_count(const plx_grid *grid, const float *wmax, float w_thresh,
-                                uint8_t *keep_out, int64_t *n_kept, int64_t *n_pruned,
-                                plx_stream stream) {
+                                uint8_t *keep_out, void *ws, int64_t ws_bytes, int64_t *n_kept,
+                                int64_t *n_pruned, plx_stream stream) {
     if (!wmax) return plx::fail(PLX_EINVAL, "plx_grid_prune_weight_count: wmax is NULL");
-    return plx::prune_count(grid, wmax, w_thresh, keep_out, n_kept, n_pruned, stream,
+    return plx::prune_count(grid, wmax, w_thresh, keep_out, ws, ws_bytes, n_kept, n_pruned, stream,
                             "plx_grid_prune_weight_count");
 }
 
-int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out,
-                         plx_stream stream) {
+int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *out, void *ws,
+                         int64_t ws_bytes, plx_stream stream) {
     int rc = validate_grid(grid, false, "plx_grid_prune_apply");
     if (rc) return rc;
     if (!keep || !out || !out->index) return fail(PLX_EINVAL, "plx_grid_prune_apply: NULL argument");
@@ -666,11 +711,12 @@ int plx_grid_prune_apply(const plx_grid *grid, const uint8_t *keep, plx_grid *ou
     int chunks = (int)(plx_record_bytes(grid->sh_dtype) / 16);
     PruneWriter w{const_cast<int32_t *>(out->index), grid->index, static_cast<const uint4 *>(grid->data),
                   static_cast<uint4 *>(out->data), chunks};
-    return run_scan(MaskPred{keep}, w, n_cells(grid->reso), as_stream(stream), "plx_grid_prune_apply");
+    if ((rc = check_ws(ws, ws_bytes, ws_layout(n_cells(grid->reso)).bytes, "plx_grid_prune_apply"))) return rc;
+    return run_scan(MaskPred{keep}, w, n_cells(grid->reso), ws, as_stream(stream), "plx_grid_prune_apply");
 }
 
-int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int64_t *n_out,
-                            plx_stream stream) {
+int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], void *ws,
+                            int64_t ws_bytes, int64_t *n_out, plx_stream stream) {
     int rc = validate_grid(grid, false, "plx_grid_upsample_count");
     if (rc) return rc;
     if (!new_reso || !n_out) return fail(PLX_EINVAL, "plx_grid_upsample_count: NULL argument");
@@ -680,16 +726,16 @@ int plx_grid_upsample_count(const plx_grid *grid, const int32_t new_reso[3], int
     ParentPred pred{grid->index, {grid->reso[0], grid->reso[1], grid->reso[2]},
                     {new_reso[0], new_reso[1], new_reso[2]}};
     int64_t n = n_cells(new_reso);
-    TempBuf tmp;
-    if ((rc = tmp.alloc(sizeof(unsigned long long), s))) return rc;
-    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
-    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_grid_upsample_count");
+    if ((rc = check_ws(ws, ws_bytes, PLX_COUNT_WORKSPACE_BYTES, "plx_grid_upsample_count"))) return rc;
+    auto *cnt = static_cast<unsigned long long *>(ws);
+    if ((rc = zero_counters(ws, s, "plx_grid_upsample_count"))) return rc;
     upsample_count_kernel<<<count_blocks(n), kCountThreads, 0, s>>>(pred, n, cnt);
     if ((rc = check_launch("plx_grid_upsample_count"))) return rc;
     return sync_read_u64(cnt, 1, n_out, s, "plx_grid_upsample_count");
 }
 
-int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stream) {
+int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, void *ws, int64_t ws_bytes,
+                            plx_stream stream) {
     int rc = validate_grid(grid, false, "plx_grid_upsample_apply");
     if (rc) return rc;
     if (!out || !out->index) return fail(PLX_EINVAL, "plx_grid_upsample_apply: NULL argument");
@@ -702,7 +748,8 @@ int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stre
     ParentPred pred{grid->index, {grid->reso[0], grid->reso[1], grid->reso[2]},
                     {out->reso[0], out->reso[1], out->reso[2]}};
     int64_t n = n_cells(out->reso);
-    if ((rc = run_scan(pred, IndexWriter{const_cast<int32_t *>(out->index)}, n, s,
+    if ((rc = check_ws(ws, ws_bytes, ws_layout(n).bytes, "plx_grid_upsample_apply"))) return rc;
+    if ((rc = run_scan(pred, IndexWriter{const_cast<int32_t *>(out->index)}, n, ws, s,
                        "plx_grid_upsample_apply")))
         return rc;
     GridDev g = to_dev(grid);
@@ -712,21 +759,20 @@ int plx_grid_upsample_apply(const plx_grid *grid, plx_grid *out, plx_stream stre
     return check_launch("plx_grid_upsample_apply");
 }
 
-int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
-                      plx_stream stream) {
+int plx_touched_count(const uint8_t *touched, int64_t n_vox, void *ws, int64_t ws_bytes,
+                      int64_t *count_out, plx_stream stream) {
     if (!count_out) return fail(PLX_EINVAL, "plx_touched_count: count_out is NULL");
     if (n_vox < 0) return fail(PLX_EINVAL, "plx_touched_count: n_vox < 0");
+    int rc = check_ws(ws, ws_bytes, PLX_COUNT_WORKSPACE_BYTES, "plx_touched_count");
+    if (rc) return rc;
     if (n_vox == 0) {
         *count_out = 0;
         return PLX_OK;
     }
     if (!touched) return fail(PLX_EINVAL, "plx_touched_count: touched is NULL");
     hipStream_t s = as_stream(stream);
-    TempBuf tmp;
-    int rc = tmp.alloc(sizeof(unsigned long long), s);
-    if (rc) return rc;
-    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
-    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), "plx_touched_count");
+    auto *cnt = static_cast<unsigned long long *>(ws);
+    if ((rc = zero_counters(ws, s, "plx_touched_count"))) return rc;
     count_nonzero_kernel<<<count_blocks(n_vox), kCountThreads, 0, s>>>(touched, n_vox, cnt);
     if ((rc = check_launch("plx_touched_count"))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, "plx_touched_count");
@@ -736,18 +782,16 @@ int plx_touched_count(const uint8_t *touched, int64_t n_vox, int64_t *count_out,
 
 namespace plx {
 
-int count_set_bits(const uint32_t *words, int64_t n_bits, int64_t *count_out, hipStream_t s,
-                   const char *fn) {
+int count_set_bits(const uint32_t *words, int64_t n_bits, void *ws, int64_t *count_out,
+                   hipStream_t s, const char *fn) {
     if (n_bits <= 0) {
         *count_out = 0;
         return PLX_OK;
     }
     const int64_t nw = (n_bits + 31) / 32;
-    TempBuf tmp;
-    int rc = tmp.alloc(sizeof(unsigned long long), s);
+    auto *cnt = static_cast<unsigned long long *>(ws);
+    int rc = zero_counters(ws, s, fn);
     if (rc) return rc;
-    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
-    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), s), fn);
     popcount_kernel<<<count_blocks(nw), kCountThreads, 0, s>>>(words, nw, n_bits, cnt);
     if ((rc = check_launch(fn))) return rc;
     return sync_read_u64(cnt, 1, count_out, s, fn);

@@ -27,9 +27,9 @@ int check_launch(const char *what);
 inline hipStream_t as_stream(plx_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Number of set bits among the first n_bits bits of a device bitmap
-// (synchronising).
-int count_set_bits(const uint32_t *words, int64_t n_bits, int64_t *count_out, hipStream_t s,
-                   const char *fn);
+// (synchronising; ws: caller workspace of PLX_COUNT_WORKSPACE_BYTES).
+int count_set_bits(const uint32_t *words, int64_t n_bits, void *ws, int64_t *count_out,
+                   hipStream_t s, const char *fn);
 
 // Validates a grid descriptor for kernels; need_occ for the render calls.
 int validate_grid(const plx_grid *g, bool need_occ, const char *fn);
@@ -319,14 +319,5 @@ template <int DT> __device__ inline uint32_t to16(float x) {
     case PLX_F16: { constexpr int DTV = PLX_F16; __VA_ARGS__; } break;         \
     default: return fail(PLX_EINVAL, "unknown sh_dtype %d", (int)(dt));         \
     }
-
-// ------------------------------------------------------ device scratch
-// Stream-ordered temporary device memory.
-struct TempBuf {
-    void *ptr = nullptr;
-    hipStream_t stream = nullptr;
-    int alloc(size_t bytes, hipStream_t s);
-    ~TempBuf();
-};
 
 }  // namespace plx

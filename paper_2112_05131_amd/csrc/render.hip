@@ -498,17 +498,17 @@ __device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &
     return m & valid;
 }
 
-// Brick-level skip.  Returns the distance D of the brick of sample k (0 when
-// it has an occupied cell); for D > 0 also the number of further samples m
-// (in the direction of travel) that certainly stay in the empty box of bricks
-// within D-1 of it.
 // Number of further samples after sample k (in the direction of travel)
 // that certainly stay inside the box of bricks within R of brick b, where
 // sample k lies (at t = t_near + k*step): the box's exit parameter along the
 // ray, less a margin of 5% of a step.
+// Both walks over a ray's bricks (counting and emitting its segments) must
+// cut identical segments, so this runs without FMA contraction like the
+// sample recipe itself.
 template <bool FORWARD>
 __device__ __forceinline__ int samples_in_box(const GridDev &g, const RayGeom &r, int k,
                                               const int b[3], int R) {
+#pragma clang fp contract(off)
     const int nb[3] = {g.bx, g.by, g.bz};
     const float t = r.t_near + (float)k * g.step;
     float t_edge = FORWARD ? __builtin_inff() : -__builtin_inff();
@@ -980,9 +980,25 @@ struct BinArgs {
     double *tau_in;      // [n_seg] ray-major: optical depth before the segment
     float *gr_after;     // [n_seg] ray-major: g . (radiance collected after the segment)
     float4 *g_ray;       // [n_rays] dL/dC of each ray; w: beta factor of its samples
+    unsigned *status;    // set to 1 when the emitting walk disagrees with the counting walk
+    const int64_t *n_seg_dev;  // when set, the segment count is read here instead of n_seg
     Priors pri;
     float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
+
+// Number of segments of the call: the host's count, or the device copy when
+// the launch was sized by a bound instead.
+__device__ __forceinline__ int64_t seg_count_of(const BinArgs &a) {
+    return a.n_seg_dev ? *a.n_seg_dev : a.n_seg;
+}
+
+// A segment record with its ray and slot inside the call's arrays.  The emit
+// walk repeats the count walk exactly, so every position holds a valid
+// record; the check keeps a record that is not (a disagreement, which the
+// emit kernel reports in the status word) from indexing outside the arrays.
+__device__ __forceinline__ bool seg_valid(const BinArgs &a, const int4 &sg, int64_t n_seg) {
+    return (uint64_t)(int64_t)sg.x < (uint64_t)a.n_rays && (uint64_t)(int64_t)sg.w < (uint64_t)n_seg;
+}
 
 __device__ __forceinline__ void load_ray_lane(const BinArgs &a, int64_t ray, float o[3], float d[3]) {
 #pragma unroll
@@ -1049,12 +1065,17 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
     RayGeom r;
     const int n = ray_setup(g, o, d, r);
     int64_t slot = a.seg_off[ray];
+    const int64_t slot_end = a.seg_off[ray + 1];
+    bool bad = false;
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         const int64_t bin = seg_bin(bid, k0, k1);
         const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
-        a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
+        // positions and slots stay inside the ranges the count reserved
+        if (pos < a.boff[bin + 1] && slot < slot_end) a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
+        else bad = true;
         ++slot;
     });
+    if (bad || slot != slot_end) *a.status = 1u;
 }
 
 // Occupied samples of [k_lo, k_hi] in increasing / decreasing order.
@@ -1098,8 +1119,10 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-    if (i >= a.n_seg) return;
+    const int64_t n_seg = seg_count_of(a);
+    if (i >= n_seg) return;
     const int4 sg = a.bseg[i];
+    if (!seg_valid(a, sg, n_seg)) return;
     float o[3], d[3];
     load_ray_lane(a, sg.x, o, d);
     RayGeom r;
@@ -1276,13 +1299,12 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
     qu.y = q_y + wid * kWave * 9;
 
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-    const bool live = i < a.n_seg;
+    const int64_t n_seg = seg_count_of(a);
     int4 sg = make_int4(0, 0, -1, 0);
+    if (i < n_seg) sg = a.bseg[i];
+    const bool live = i < n_seg && seg_valid(a, sg, n_seg);
     float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
-    if (live) {
-        sg = a.bseg[i];
-        load_ray_lane(a, sg.x, o, d);
-    }
+    if (live) load_ray_lane(a, sg.x, o, d);
     RayGeom r;
     const int n = live ? ray_setup(g, o, d, r) : 0;
     float *y = qu.y + L * 9;
@@ -1431,8 +1453,10 @@ __global__ __launch_bounds__(kThreads) void seg_weight_kernel(GridDev g, BinArgs
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-    if (i >= a.n_seg) return;
+    const int64_t n_seg = seg_count_of(a);
+    if (i >= n_seg) return;
     const int4 sg = a.bseg[i];
+    if (!seg_valid(a, sg, n_seg)) return;
     float o[3], d[3];
     load_ray_lane(a, sg.x, o, d);
     RayGeom r;
@@ -1679,82 +1703,136 @@ int scan_counts(const unsigned *c, int64_t n, int64_t *out, int64_t *tmp, hipStr
 inline int64_t scan_tmp_words(int64_t n) { return 2 * ((n + kScanTile - 1) / kScanTile) + 1; }
 inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
-// The brick-binned passes (see the comment above BinArgs): MODE_FWD renders,
-// MODE_BWD and MODE_TRAIN also run the backward replay.
-template <int MODE>
-int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
-    const int64_t n_rays = a.n_rays;
-    if (n_rays > 0x7fffffffLL - kThreads) return fail(PLX_EINVAL, "%s: too many rays", fn);
-    GridDev g = to_dev(grid);
-    const int64_t nbk = n_bins(g);
-    // per-ray and per-brick temporaries
+// ------------------------------------------------------------ caller-owned bins
+//
+// The work lists of a batch live in two caller-owned buffers (plx_bins):
+// the ray buffer holds the per-ray segment counts and offsets, the per-bin
+// counts, cursors and offsets, the scan temporaries and a status word; the
+// segment buffer holds the bin-major segment records and the per-segment
+// values the render passes hand from one kernel to the next.
+
+struct RayBufLayout {
+    int64_t nseg, segoff, gray, bcount, bcursor, status, boff, scan, bytes;
+};
+
+RayBufLayout ray_buf_layout(int64_t n_rays, int64_t nbk) {
+    RayBufLayout l;
     int64_t off = 0;
-    const int64_t o_nseg = off; off += align256(n_rays * 4);
-    const int64_t o_segoff = off; off += align256((n_rays + 1) * 8);
-    const int64_t o_gray = off; off += align256(n_rays * 16);
-    const int64_t o_bcount = off; off += align256(nbk * 4);
-    const int64_t o_bcursor = off; off += align256(nbk * 4);
-    const int64_t o_boff = off; off += align256((nbk + 1) * 8);
-    const int64_t o_scan = off; off += align256((scan_tmp_words(n_rays) + scan_tmp_words(nbk)) * 8);
-    TempBuf t1;
-    int rc = t1.alloc((size_t)off, s);
+    l.nseg = off; off += align256(n_rays * 4);
+    l.segoff = off; off += align256((n_rays + 1) * 8);
+    l.gray = off; off += align256(n_rays * 16);
+    // bin counts, cursors and the status word are cleared by one launch
+    l.bcount = off; off += nbk * 4;
+    l.bcursor = off; off += nbk * 4;
+    l.status = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
+    l.boff = off; off += align256((nbk + 1) * 8);
+    l.scan = off; off += align256((scan_tmp_words(n_rays) + scan_tmp_words(nbk)) * 8);
+    l.bytes = off;
+    return l;
+}
+
+struct SegBufLayout {
+    int64_t bseg, tseg, cseg, tin, gra, bytes;
+};
+
+SegBufLayout seg_buf_layout(int64_t n_seg) {
+    SegBufLayout l;
+    int64_t off = 0;
+    l.bseg = off; off += align256(n_seg * 16);
+    l.tseg = off; off += align256(n_seg * 8);
+    l.cseg = off; off += align256(n_seg * 16);
+    l.tin = off; off += align256(n_seg * 8);
+    l.gra = off; off += align256(n_seg * 4);
+    l.bytes = off;
+    return l;
+}
+
+constexpr int64_t kMaxRaysBinned = 0x7fffffffLL - kThreads;
+
+// Points a's per-ray and per-bin arrays into a ray buffer.
+void attach_ray_buf(BinArgs &a, void *ray_buf, const RayBufLayout &l) {
+    char *base = static_cast<char *>(ray_buf);
+    a.nseg = reinterpret_cast<unsigned *>(base + l.nseg);
+    a.seg_off = reinterpret_cast<int64_t *>(base + l.segoff);
+    a.g_ray = reinterpret_cast<float4 *>(base + l.gray);
+    a.bcount = reinterpret_cast<unsigned *>(base + l.bcount);
+    a.bcursor = reinterpret_cast<unsigned *>(base + l.bcursor);
+    a.status = reinterpret_cast<unsigned *>(base + l.status);
+    a.boff = reinterpret_cast<int64_t *>(base + l.boff);
+}
+
+// Points a's per-segment arrays into a segment buffer.
+void attach_seg_buf(BinArgs &a, void *seg_buf, const SegBufLayout &l) {
+    char *b2 = static_cast<char *>(seg_buf);
+    a.bseg = reinterpret_cast<int4 *>(b2 + l.bseg);
+    a.tau_seg = reinterpret_cast<double *>(b2 + l.tseg);
+    a.c_seg = reinterpret_cast<float4 *>(b2 + l.cseg);
+    a.tau_in = reinterpret_cast<double *>(b2 + l.tin);
+    a.gr_after = reinterpret_cast<float *>(b2 + l.gra);
+}
+
+int check_buf(const void *p, int64_t have, int64_t need, const char *what, const char *fn) {
+    if (!p) return fail(PLX_EINVAL, "%s: %s is NULL", fn, what);
+    if (reinterpret_cast<uintptr_t>(p) % 256) return fail(PLX_EINVAL, "%s: %s must be 256-byte aligned", fn, what);
+    if (have < need)
+        return fail(PLX_EINVAL, "%s: %s of %lld bytes, need %lld", fn, what, (long long)have, (long long)need);
+    return PLX_OK;
+}
+
+// Validates bins against the grid and batch of a render call and points a's
+// arrays into them.
+int attach_bins(const plx_grid *grid, const plx_bins *bins, int64_t n_rays, BinArgs &a, const char *fn) {
+    if (!bins) return fail(PLX_EINVAL, "%s: bins is NULL", fn);
+    if (bins->n_rays != n_rays)
+        return fail(PLX_EINVAL, "%s: bins were made for %lld rays, the call has %lld", fn,
+                    (long long)bins->n_rays, (long long)n_rays);
+    if (bins->n_seg < 0 || bins->n_seg > kMaxRaysBinned)
+        return fail(PLX_EINVAL, "%s: bins->n_seg = %lld out of range", fn, (long long)bins->n_seg);
+    const RayBufLayout rl = ray_buf_layout(n_rays, n_bins(to_dev(grid)));
+    int rc = check_buf(bins->ray_buf, bins->ray_buf_bytes, rl.bytes, "bins->ray_buf", fn);
     if (rc) return rc;
-    char *base = static_cast<char *>(t1.ptr);
-    a.nseg = reinterpret_cast<unsigned *>(base + o_nseg);
-    a.seg_off = reinterpret_cast<int64_t *>(base + o_segoff);
-    a.g_ray = reinterpret_cast<float4 *>(base + o_gray);
-    a.bcount = reinterpret_cast<unsigned *>(base + o_bcount);
-    a.bcursor = reinterpret_cast<unsigned *>(base + o_bcursor);
-    a.boff = reinterpret_cast<int64_t *>(base + o_boff);
-    int64_t *scan_tmp = reinterpret_cast<int64_t *>(base + o_scan);
+    attach_ray_buf(a, bins->ray_buf, rl);
+    a.n_seg = bins->n_seg;
+    if (bins->n_seg > 0) {
+        const SegBufLayout sl = seg_buf_layout(bins->n_seg);
+        if ((rc = check_buf(bins->seg_buf, bins->seg_buf_bytes, sl.bytes, "bins->seg_buf", fn))) return rc;
+        attach_seg_buf(a, bins->seg_buf, sl);
+    }
+    return PLX_OK;
+}
 
-    const unsigned zb = (unsigned)((nbk + 255) / 256);
-    zero_u32_kernel<<<zb, 256, 0, s>>>(a.bcount, nbk);
-    if ((rc = check_launch(fn))) return rc;
-    zero_u32_kernel<<<zb, 256, 0, s>>>(a.bcursor, nbk);
-    if ((rc = check_launch(fn))) return rc;
-
+// Counting phase: per-ray and per-bin segment counts and their scans.
+// Leaves the total at seg_off[n_rays] on the device.
+int bin_count_launch(const GridDev &g, BinArgs &a, int64_t nbk, int64_t *scan_tmp, hipStream_t s,
+                     const char *fn) {
+    const int64_t n_rays = a.n_rays;
+    const int64_t nz = 2 * nbk + 1;  // bcount, bcursor, status
+    zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(a.bcount, nz);
+    int rc = check_launch(fn);
+    if (rc) return rc;
     const int64_t nbr = (n_rays + kThreads - 1) / kThreads;
     a.n_blocks = (int)nbr;
     a.nb8 = round_up8(nbr);
     seg_count_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
     if ((rc = check_launch(fn))) return rc;
     if ((rc = scan_counts(a.nseg, n_rays, a.seg_off, scan_tmp, s, fn))) return rc;
-    if ((rc = scan_counts(a.bcount, nbk, a.boff, scan_tmp + scan_tmp_words(n_rays), s, fn)))
-        return rc;
-    int64_t n_seg = 0;
-    PLX_CHECK_HIP(hipMemcpyAsync(&n_seg, a.seg_off + n_rays, sizeof(n_seg), hipMemcpyDeviceToHost, s), fn);
-    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
-    if (n_seg < 0 || n_seg > 0x7fffffffLL - kThreads)
-        return fail(PLX_EINVAL, "%s: %lld ray segments, more than this pass handles", fn,
-                    (long long)n_seg);
-    a.n_seg = n_seg;
+    return scan_counts(a.bcount, nbk, a.boff, scan_tmp + scan_tmp_words(n_rays), s, fn);
+}
 
-    // per-segment temporaries
-    TempBuf t2;
-    int64_t o2 = 0;
-    const int64_t o_bseg = o2; o2 += align256(n_seg * 16);
-    const int64_t o_tseg = o2; o2 += align256(n_seg * 8);
-    const int64_t o_cseg = o2; o2 += align256(n_seg * 16);
-    const int64_t o_tin = o2; o2 += align256(n_seg * 8);
-    const int64_t o_gra = o2; o2 += align256(n_seg * 4);
-    if (n_seg > 0) {
-        if ((rc = t2.alloc((size_t)o2, s))) return rc;
-        char *b2 = static_cast<char *>(t2.ptr);
-        a.bseg = reinterpret_cast<int4 *>(b2 + o_bseg);
-        a.tau_seg = reinterpret_cast<double *>(b2 + o_tseg);
-        a.c_seg = reinterpret_cast<float4 *>(b2 + o_cseg);
-        a.tau_in = reinterpret_cast<double *>(b2 + o_tin);
-        a.gr_after = reinterpret_cast<float *>(b2 + o_gra);
-        seg_emit_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
-        if ((rc = check_launch(fn))) return rc;
-    }
-    const int64_t nbs = (n_seg + kThreads - 1) / kThreads;
+// Render passes over binned segments: MODE_FWD renders, MODE_BWD and
+// MODE_TRAIN also run the backward replay, MODE_MAXW the weight passes.
+// Launch sizes come from a.n_seg, an upper bound when a.n_seg_dev is set.
+template <int MODE>
+int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
+    GridDev g = to_dev(grid);
+    const int64_t nbr = (a.n_rays + kThreads - 1) / kThreads;
+    const int64_t nbs = (a.n_seg + kThreads - 1) / kThreads;
     BinArgs as = a;
     as.n_blocks = (int)nbs;
     as.nb8 = round_up8(nbs);
+    int rc;
     if constexpr (MODE == MODE_MAXW) {
-        if (n_seg == 0) return PLX_OK;
+        if (a.n_seg == 0) return PLX_OK;
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_weight_kernel<DT, 0><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
         seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
@@ -1762,13 +1840,13 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_weight_kernel<DT, 1><<<as.nb8, kThreads, 0, s>>>(g, as));
         return check_launch(fn);
     }
-    if (n_seg > 0) {
+    if (a.n_seg > 0) {
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
     }
     seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
     if ((rc = check_launch(fn))) return rc;
-    if (MODE != MODE_FWD && n_seg > 0) {
+    if (MODE != MODE_FWD && a.n_seg > 0) {
         // the Cauchy prior's per-sample terms only in an instance of their own
         if (as.pri.lambda_s != 0.0f) {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
@@ -1811,9 +1889,88 @@ using namespace plx;
 
 extern "C" {
 
+int64_t plx_bins_ray_bytes(const int32_t reso[3], int64_t n_rays) {
+    if (!reso || reso[0] < 2 || reso[1] < 2 || reso[2] < 2 || n_rays < 0 || n_rays > kMaxRaysBinned)
+        return 0;
+    plx_grid tmp = {};
+    for (int a = 0; a < 3; ++a) tmp.reso[a] = reso[a];
+    return ray_buf_layout(n_rays, n_bins(to_dev(&tmp))).bytes;
+}
+
+int64_t plx_bins_seg_bytes(int64_t n_seg) {
+    if (n_seg < 0 || n_seg > kMaxRaysBinned) return 0;
+    return seg_buf_layout(n_seg).bytes;
+}
+
+int plx_bins_count(const plx_grid *grid, const float *rays_o, const float *rays_d, int64_t n_rays,
+                   void *ray_buf, int64_t ray_buf_bytes, int64_t *n_seg, plx_stream stream) {
+    const char *fn = "plx_bins_count";
+    int rc = validate_grid(grid, true, fn);
+    if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
+    if (!n_seg) return fail(PLX_EINVAL, "%s: n_seg is NULL", fn);
+    if (n_rays > kMaxRaysBinned) return fail(PLX_EINVAL, "%s: too many rays", fn);
+    const GridDev g = to_dev(grid);
+    const int64_t nbk = n_bins(g);
+    const RayBufLayout l = ray_buf_layout(n_rays, nbk);
+    if ((rc = check_buf(ray_buf, ray_buf_bytes, l.bytes, "ray_buf", fn))) return rc;
+    *n_seg = 0;
+    if (n_rays == 0) return PLX_OK;
+    hipStream_t s = as_stream(stream);
+    BinArgs a = {};
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.n_rays = n_rays;
+    attach_ray_buf(a, ray_buf, l);
+    int64_t *scan_tmp = reinterpret_cast<int64_t *>(static_cast<char *>(ray_buf) + l.scan);
+    if ((rc = bin_count_launch(g, a, nbk, scan_tmp, s, fn))) return rc;
+    int64_t total = 0;
+    PLX_CHECK_HIP(hipMemcpyAsync(&total, a.seg_off + n_rays, sizeof(total), hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
+    if (total < 0 || total > kMaxRaysBinned)
+        return fail(PLX_EINVAL, "%s: %lld ray segments, more than one call handles", fn, (long long)total);
+    *n_seg = total;
+    return PLX_OK;
+}
+
+int plx_bins_apply(const plx_grid *grid, const float *rays_o, const float *rays_d,
+                   const plx_bins *bins, plx_stream stream) {
+    const char *fn = "plx_bins_apply";
+    int rc = validate_grid(grid, true, fn);
+    if (rc) return rc;
+    if (!bins) return fail(PLX_EINVAL, "%s: bins is NULL", fn);
+    if ((rc = validate_rays(rays_o, rays_d, bins->n_rays, fn))) return rc;
+    BinArgs a = {};
+    if ((rc = attach_bins(grid, bins, bins->n_rays, a, fn))) return rc;
+    if (bins->n_seg == 0) return PLX_OK;
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.n_rays = bins->n_rays;
+    const int64_t nbr = (a.n_rays + kThreads - 1) / kThreads;
+    a.n_blocks = (int)nbr;
+    a.nb8 = round_up8(nbr);
+    seg_emit_kernel<<<a.nb8, kThreads, 0, as_stream(stream)>>>(to_dev(grid), a);
+    return check_launch(fn);
+}
+
+int plx_bins_verify(const plx_grid *grid, const plx_bins *bins, plx_stream stream) {
+    const char *fn = "plx_bins_verify";
+    int rc = validate_grid(grid, true, fn);
+    if (rc) return rc;
+    BinArgs a = {};
+    if (!bins) return fail(PLX_EINVAL, "%s: bins is NULL", fn);
+    if ((rc = attach_bins(grid, bins, bins->n_rays, a, fn))) return rc;
+    if (bins->n_rays == 0) return PLX_OK;
+    hipStream_t s = as_stream(stream);
+    unsigned st = 0;
+    PLX_CHECK_HIP(hipMemcpyAsync(&st, a.status, sizeof(st), hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
+    if (st != 0) return fail(PLX_EDEVICE, "%s: the segment walk of plx_bins_apply disagreed with plx_bins_count", fn);
+    return PLX_OK;
+}
+
 int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
-                   const float *rays_d, int64_t n_rays, float *rgb_out, float *tau_out,
-                   plx_stream stream) {
+                   const float *rays_d, int64_t n_rays, const plx_bins *bins, float *rgb_out,
+                   float *tau_out, plx_stream stream) {
     const char *fn = "plx_render_fwd";
     int rc = validate_grid(grid, true, fn);
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
@@ -1821,6 +1978,7 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (n_rays == 0) return PLX_OK;
     if (!rgb_out) return fail(PLX_EINVAL, "%s: rgb_out is NULL", fn);
     BinArgs a = {};
+    if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.rgb_out = rgb_out;
@@ -1833,7 +1991,7 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
 }
 
 int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
-                   const float *rays_d, int64_t n_rays, const float *grad_rgb,
+                   const float *rays_d, int64_t n_rays, const plx_bins *bins, const float *grad_rgb,
                    const float *tau_fwd, float *grad, uint8_t *touched, plx_stream stream) {
     const char *fn = "plx_render_bwd";
     int rc = validate_grid(grid, true, fn);
@@ -1844,6 +2002,7 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
         return fail(PLX_EINVAL, "%s: NULL grad_rgb/tau_fwd/grad/touched", fn);
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
+    if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.grad_rgb = grad_rgb;
@@ -1857,13 +2016,14 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
 }
 
 int plx_render_max_weight(const plx_grid *grid, const float *rays_o, const float *rays_d,
-                          int64_t n_rays, float *wmax, plx_stream stream) {
+                          int64_t n_rays, const plx_bins *bins, float *wmax, plx_stream stream) {
     const char *fn = "plx_render_max_weight";
     int rc = validate_grid(grid, true, fn);
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (n_rays == 0) return PLX_OK;
     if (!wmax) return fail(PLX_EINVAL, "%s: wmax is NULL", fn);
     BinArgs a = {};
+    if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.wmax = wmax;
@@ -1872,9 +2032,9 @@ int plx_render_max_weight(const plx_grid *grid, const float *rays_o, const float
 }
 
 int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
-                     const float *rays_d, const float *target, int64_t n_rays, float loss_scale,
-                     float *rgb_out, float *grad, uint8_t *touched, double *loss_sum,
-                     plx_stream stream) {
+                     const float *rays_d, const float *target, int64_t n_rays, const plx_bins *bins,
+                     float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
+                     double *loss_sum, plx_stream stream) {
     const char *fn = "plx_render_train";
     int rc = validate_grid(grid, true, fn);
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
@@ -1884,6 +2044,7 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
         return fail(PLX_EINVAL, "%s: NULL target/grad/touched/loss_sum", fn);
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
+    if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.target = target;
@@ -2003,20 +2164,26 @@ int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *v
 }
 
 int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,
-                     int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark, int64_t counts[4],
-                     plx_stream stream) {
+                     int64_t n_rays, uint32_t *cell_mark, uint32_t *vox_mark, void *ws,
+                     int64_t ws_bytes, int64_t counts[4], plx_stream stream) {
     const char *fn = "plx_render_stats";
     int rc = validate_grid(grid, true, fn);
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
     if (!cell_mark || !vox_mark || !counts) return fail(PLX_EINVAL, "%s: NULL argument", fn);
+    if ((rc = check_buf(ws, ws_bytes, PLX_COUNT_WORKSPACE_BYTES, "workspace", fn))) return rc;
     hipStream_t s = as_stream(stream);
     const int64_t cw = (n_cells(grid->reso) + 31) / 32, vw = (grid->n_vox + 31) / 32;
-    PLX_CHECK_HIP(hipMemsetAsync(cell_mark, 0, cw * 4, s), fn);
-    if (vw) PLX_CHECK_HIP(hipMemsetAsync(vox_mark, 0, vw * 4, s), fn);
-    TempBuf tmp;
-    if ((rc = tmp.alloc(2 * sizeof(unsigned long long), s))) return rc;
-    auto *cnt = static_cast<unsigned long long *>(tmp.ptr);
-    PLX_CHECK_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), s), fn);
+    zero_u32_kernel<<<(unsigned)((cw + 255) / 256), 256, 0, s>>>(cell_mark, cw);
+    if ((rc = check_launch(fn))) return rc;
+    if (vw) {
+        zero_u32_kernel<<<(unsigned)((vw + 255) / 256), 256, 0, s>>>(vox_mark, vw);
+        if ((rc = check_launch(fn))) return rc;
+    }
+    // two sample counters at the start of the workspace (the bit counts
+    // below reuse its first word after these are read back)
+    auto *cnt = static_cast<unsigned long long *>(ws);
+    zero_u32_kernel<<<1, 256, 0, s>>>(static_cast<unsigned *>(ws), 4);
+    if ((rc = check_launch(fn))) return rc;
     if (n_rays > 0) {
         stats_kernel<<<(unsigned)((n_rays + 255) / 256), 256, 0, s>>>(to_dev(grid), rays_o, rays_d,
                                                                       n_rays, cell_mark, vox_mark, cnt);
@@ -2028,8 +2195,8 @@ int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *ray
     counts[0] = (int64_t)h[0];
     counts[1] = (int64_t)h[1];
     int64_t cells = 0, vox = 0;
-    if ((rc = count_set_bits(cell_mark, n_cells(grid->reso), &cells, s, fn))) return rc;
-    if ((rc = count_set_bits(vox_mark, grid->n_vox, &vox, s, fn))) return rc;
+    if ((rc = count_set_bits(cell_mark, n_cells(grid->reso), ws, &cells, s, fn))) return rc;
+    if ((rc = count_set_bits(vox_mark, grid->n_vox, ws, &vox, s, fn))) return rc;
     counts[2] = cells;
     counts[3] = vox;
     return PLX_OK;

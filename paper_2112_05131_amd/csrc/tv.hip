@@ -140,7 +140,9 @@ int tv_launch(const plx_grid *grid, int64_t cell_start, int64_t cell_count, floa
     if (cell_count < 0) return fail(PLX_EINVAL, "%s: cell_count < 0", fn);
     if (cell_count == 0) return PLX_OK;
     if (!grad || !touched) return fail(PLX_EINVAL, "%s: grad/touched is NULL", fn);
-    if (!(eps >= 0.0f)) return fail(PLX_EINVAL, "%s: eps must be >= 0", fn);
+    // eps > 0 keeps the square root and its derivative finite where all three
+    // differences vanish (constant regions, the uniform initial grid)
+    if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(PLX_EINVAL, "%s: eps must be positive and finite", fn);
     const int64_t ncell = n_cells(grid->reso);
     const int64_t start = ((cell_start % ncell) + ncell) % ncell;
     const float inv = (float)(1.0 / (double)cell_count);

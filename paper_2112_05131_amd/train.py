@@ -155,21 +155,25 @@ class Trainer:
         start = int(self.rng.integers(0, n))
         return start, count
 
-    def step(self, rays_o, rays_d, target, tv: bool = True, rgb_out=None):
-        """One optimisation step on a ray batch (all device tensors)."""
+    def step(self, rays_o, rays_d, target, tv: bool = True, rgb_out=None, bins=None):
+        """One optimisation step on a ray batch (all device tensors).  bins:
+        the batch's segment lists (binding.make_bins), made here when not
+        given."""
         c, g = self.cfg, self.grid
         lr_s, lr_h = self.learning_rates()
         n = rays_o.shape[0]
         if self.bg is None:
             B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
-                               self.touched, self.loss_sum, rgb_out, c.background, self.priors())
+                               self.touched, self.loss_sum, rgb_out, c.background, self.priors(),
+                               bins=bins)
         else:
             # background colours -> fused foreground step (which hands back
             # their gradient) -> background gradient
             cbg, gbg = self._bg_buffers(n)
             B.plx_bg_render_fwd(self.bg.desc(), rays_o, rays_d, cbg, None, c.bg_background)
             B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
-                               self.touched, self.loss_sum, rgb_out, cbg, self.priors(), gbg)
+                               self.touched, self.loss_sum, rgb_out, cbg, self.priors(), gbg,
+                               bins=bins)
             B.plx_bg_render_bwd(self.bg.desc(), rays_o, rays_d, gbg, self.bg_grad, self.bg_touched,
                                 c.bg_background)
         if tv and (c.lambda_tv_sigma > 0 or c.lambda_tv_sh > 0):
@@ -190,3 +194,44 @@ class Trainer:
             B.plx_rmsprop_step(self.bg.desc(), None, self.bg_vstate, self.bg_grad, self.bg_touched, lr_bs, lr_bc,
                                c.beta, c.eps)
         self.step_id += 1
+
+    def run(self, sampler: RaySampler, n_steps: int, overlap: bool = True, tv: bool = True):
+        """n_steps optimisation steps on consecutive batches of the sampler.
+
+        With overlap, batch t+1 is gathered and binned on a second stream
+        while step t runs on the current one: the binning reads only the rays
+        and the grid's occupancy, which a step does not change, and its one
+        synchronising call (the segment count) then waits for that stream
+        alone, so the device never idles on it.  The two sets of bin buffers
+        alternate; a set is refilled only after the step that used it has
+        finished."""
+        main = torch.cuda.current_stream()
+        side = torch.cuda.Stream(device=self.grid.device) if overlap else main
+        bufs = [[None, None], [None, None]]
+        done = [None, None]
+
+        def prepare(slot):
+            with torch.cuda.stream(side):
+                if done[slot] is not None:
+                    side.wait_event(done[slot])
+                o, d, t = sampler.next_batch()
+                b = B.make_bins(self.grid.desc(), o, d, bufs[slot][0], bufs[slot][1])
+                bufs[slot] = [b.ray_buf, b.seg_buf]
+                ev = torch.cuda.Event()
+                ev.record(side)
+            return o, d, t, b, ev
+
+        nxt = prepare(0)
+        for i in range(n_steps):
+            o, d, t, b, ev = nxt
+            if side is not main:
+                main.wait_event(ev)
+                for x in (o, d, t, b.ray_buf, b.seg_buf):
+                    if x is not None:
+                        x.record_stream(main)
+            self.step(o, d, t, tv=tv, bins=b)
+            ev_done = torch.cuda.Event()
+            ev_done.record(main)
+            done[i % 2] = ev_done
+            if i + 1 < n_steps:
+                nxt = prepare((i + 1) % 2)

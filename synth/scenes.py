@@ -128,6 +128,20 @@ def dense_random(reso, seed: int, sigma_lo=0.5, sigma_hi=40.0, dc_lo=1.0, dc_hi=
                        sh.reshape(m, NSH).float().to(device), m)
 
 
+def perturbed(sv: SceneValues, seed: int, device=None) -> SceneValues:
+    """The same occupancy with every density scaled by U(0.5, 1.5) and every
+    colour coefficient shifted by N(0, 0.05): a grid part-way through
+    training towards sv."""
+    g = _gen(seed)
+    m = sv.n_vox
+    scale = 0.5 + torch.rand(m, generator=g, dtype=torch.float64)
+    noise = 0.05 * torch.randn(m, NSH, generator=g, dtype=torch.float64)
+    dev = sv.density.device if device is None else device
+    density = (sv.density.double().cpu() * scale).float().to(dev)
+    sh = (sv.sh.double().cpu() + noise).float().to(dev)
+    return SceneValues(sv.reso, sv.mask.to(dev), density, sh, m)
+
+
 def uniform_values(reso, mask: torch.Tensor, sigma0: float, dc: float) -> SceneValues:
     """Constant init on a given mask: density sigma0, DC coefficient dc in
     every channel, higher orders 0."""

@@ -116,13 +116,21 @@ def assert_grads_close(gpu_rec, ref_d, ref_s, what="", mass=None):
         bad = err > tol
         rel = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
         worst = float((err / np.maximum(tol, 1e-300)).max()) if err.size else 0.0
+        # the plain relative criterion with a floor of 1e-3 of the group's
+        # largest value, reported beside the mass criterion above (which is
+        # the one asserted): where they disagree, a sum cancels
+        o10 = GRAD_RTOL * (np.abs(b) + GRAD_FLOOR * mx) + FLT_MIN
+        o10_worst = float((err / o10).max()) if err.size else 0.0
         stats[name] = dict(max_ref=mx, max_err=float(err.max()) if err.size else 0.0,
-                           rel_l2=rel, worst_ratio=worst)
+                           rel_l2=rel, worst_ratio=worst, floor_rel_worst=o10_worst,
+                           floor_rel_over=int((err > o10).sum()))
         assert not bad.any(), (
             f"{what} {name}: {int(bad.sum())} of {bad.size} elements outside tolerance; "
             f"worst err {float(err.max()):.3e} at ref {float(b.reshape(-1)[np.argmax((err - tol).reshape(-1))]):.3e}, "
             f"max|ref| {mx:.3e}, worst err/tol {worst:.2f}")
-    say(f"  {what}: " + ", ".join(f"{k} rel_l2={v['rel_l2']:.2e} worst_err/tol={v['worst_ratio']:.3f}"
+    say(f"  {what}: " + ", ".join(f"{k} rel_l2={v['rel_l2']:.2e} worst_err/tol={v['worst_ratio']:.3f} "
+                                  f"(floor-relative: worst {v['floor_rel_worst']:.3f}, "
+                                  f"{v['floor_rel_over']} over)"
                                   for k, v in stats.items()))
     return stats
 

@@ -104,7 +104,7 @@ def test_render_rejects_bad_grid_before_launch(field, value, needle):
     g = _grid_desc(**{field: value})
     opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
     rc = B.lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(0x40000),
-                                ctypes.c_void_p(0x50000), 4, ctypes.c_void_p(0x60000), None, None)
+                                ctypes.c_void_p(0x50000), 4, None, ctypes.c_void_p(0x60000), None, None)
     assert rc == B.PLX_EINVAL
     assert needle in B.lib().plx_last_error().decode()
 
@@ -114,14 +114,19 @@ def test_other_entry_points_reject_bad_arguments():
     g = _grid_desc()
     opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
     # negative ray count, NULL outputs, NULL options
-    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, -1, None, None,
+    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, -1, None, None, None,
                             None) == B.PLX_EINVAL
-    assert L.plx_render_fwd(ctypes.byref(g), None, None, None, 0, None, None, None) == B.PLX_EINVAL
+    assert L.plx_render_fwd(ctypes.byref(g), None, None, None, 0, None, None, None, None) == B.PLX_EINVAL
     assert L.plx_render_bwd(ctypes.byref(g), ctypes.byref(opts), ctypes.c_void_p(0x40000),
-                            ctypes.c_void_p(0x50000), 3, None, None, None, None,
+                            ctypes.c_void_p(0x50000), 3, None, None, None, None, None,
                             None) == B.PLX_EINVAL
     assert L.plx_tv_grad(ctypes.byref(g), 0, -5, 1.0, 1.0, 1e-9, None, None, None,
                          None) == B.PLX_EINVAL
+    # eps = 0 would give 0/0 on a constant region: rejected, like a negative eps
+    for eps in (0.0, -1e-9, float("nan")):
+        assert L.plx_tv_grad(ctypes.byref(g), 0, 5, 1.0, 1.0, eps, ctypes.c_void_p(0x1000),
+                             ctypes.c_void_p(0x2000), None, None) == B.PLX_EINVAL
+        assert "eps" in L.plx_last_error().decode()
     assert L.plx_rmsprop_step(ctypes.byref(g), ctypes.c_void_p(0x70000), ctypes.c_void_p(0x80000),
                               ctypes.c_void_p(0x90000), ctypes.c_void_p(0xa0000), 0.1, 0.1, 0.95,
                               1e-8, None) == B.PLX_EINVAL  # master given for an FP32 grid
@@ -135,8 +140,9 @@ def test_other_entry_points_reject_bad_arguments():
                               1e-8, None) == B.PLX_EINVAL
     reso = (ctypes.c_int32 * 3)(1, 4, 4)
     assert L.plx_grid_create(ctypes.c_void_p(0x1000), ctypes.cast(reso, ctypes.c_void_p),
-                             ctypes.c_void_p(0x2000), None) == B.PLX_EINVAL
-    assert L.plx_mask_count(None, 5, None, None) == B.PLX_EINVAL
+                             ctypes.c_void_p(0x2000), ctypes.c_void_p(0x100000), 1 << 20,
+                             None) == B.PLX_EINVAL
+    assert L.plx_mask_count(None, 5, ctypes.c_void_p(0x100000), 256, None, None) == B.PLX_EINVAL
     assert L.plx_records_pack(B.PLX_F32, -2, None, None, 0.0, 0.0, None, None) == B.PLX_EINVAL
 
 
@@ -145,11 +151,12 @@ def test_empty_work_is_a_no_op_without_device():
     L = B.lib()
     g = _grid_desc()
     opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
-    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, 0, None, None,
+    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), None, None, 0, None, None, None,
                             None) == B.PLX_OK
     assert L.plx_tv_grad(ctypes.byref(g), 0, 0, 1.0, 1.0, 1e-9, None, None, None, None) == B.PLX_OK
     out = ctypes.c_int64(-1)
-    assert L.plx_mask_count(None, 0, ctypes.byref(out), None) == B.PLX_OK and out.value == 0
+    assert L.plx_mask_count(None, 0, ctypes.c_void_p(0x100000), 256, ctypes.byref(out),
+                            None) == B.PLX_OK and out.value == 0
     g0 = _grid_desc(n_vox=0, data=None)
     assert L.plx_rmsprop_step(ctypes.byref(g0), None, None, None, None, 0.1, 0.1, 0.95, 1e-8,
                               None) == B.PLX_OK
@@ -192,11 +199,12 @@ def test_newer_entry_points_validate_before_launch():
     L = B.lib()
     g = _grid_desc()
     p = ctypes.c_void_p
-    assert L.plx_render_max_weight(ctypes.byref(g), p(0x40000), p(0x50000), 4, None, None) == B.PLX_EINVAL
+    assert L.plx_render_max_weight(ctypes.byref(g), p(0x40000), p(0x50000), 4, None, None,
+                                   None) == B.PLX_EINVAL
     assert "wmax" in L.plx_last_error().decode()
-    assert L.plx_render_max_weight(ctypes.byref(g), None, None, 0, None, None) == B.PLX_OK
-    assert L.plx_grid_prune_weight_count(ctypes.byref(g), None, 0.5, p(0x1000), p(0x2000), p(0x3000),
-                                         None) == B.PLX_EINVAL
+    assert L.plx_render_max_weight(ctypes.byref(g), None, None, 0, None, None, None) == B.PLX_OK
+    assert L.plx_grid_prune_weight_count(ctypes.byref(g), None, 0.5, p(0x1000), p(0x100000), 1 << 20,
+                                         p(0x2000), p(0x3000), None) == B.PLX_EINVAL
     # NDC: bad focal / near / size, NULL outputs; zero rays is a no-op
     for w, h, f, near in [(0, 10, 5.0, 1.0), (10, 10, -5.0, 1.0), (10, 10, 5.0, 0.0),
                           (10, 10, float("nan"), 1.0)]:
@@ -222,5 +230,88 @@ def test_newer_entry_points_validate_before_launch():
     for ls, lb, eps in [(0.0, 1.0, 0.0), (0.0, 1.0, -1.0), (float("inf"), 0.0, 1e-3)]:
         opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
         opts.lambda_sparsity, opts.lambda_beta, opts.beta_eps = ls, lb, eps
-        assert L.plx_render_bwd(ctypes.byref(g), ctypes.byref(opts), p(0x40000), p(0x50000), 3,
+        assert L.plx_render_bwd(ctypes.byref(g), ctypes.byref(opts), p(0x40000), p(0x50000), 3, None,
                                 p(0x60000), p(0x70000), p(0x80000), p(0x90000), None) == B.PLX_EINVAL
+
+
+def test_bins_layout_and_validation():
+    """Segment lists: buffer sizes, and every render call rejects missing,
+    short, misaligned or mismatched lists before launching anything."""
+    L = B.lib()
+    p = ctypes.c_void_p
+    g = _grid_desc()
+    reso = tuple(g.reso)
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    # the segment buffer: record, two depths, colour and g.R per segment
+    for n_seg in (0, 1, 1000, 123457):
+        assert B.plx_bins_seg_bytes(n_seg) == (up(16 * n_seg) + 2 * up(8 * n_seg) + up(16 * n_seg)
+                                               + up(4 * n_seg))
+    assert B.plx_bins_seg_bytes(-1) == 0 and B.plx_bins_ray_bytes(reso, -1) == 0
+    assert B.plx_bins_ray_bytes((1, 8, 8), 10) == 0
+    # the ray buffer grows with the rays (per-ray counts, offsets, dL/dC)
+    # and with the grid (per-bin counts)
+    r1, r2 = B.plx_bins_ray_bytes(reso, 1000), B.plx_bins_ray_bytes(reso, 2000)
+    assert r2 - r1 >= 1000 * (4 + 8 + 16) - 3 * 256
+    assert B.plx_bins_ray_bytes((64, 64, 64), 1000) > r1
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    o, d, rgb = p(0x40000), p(0x50000), p(0x60000)
+    need_r = B.plx_bins_ray_bytes(reso, 4)
+    need_s = B.plx_bins_seg_bytes(7)
+    good = B.PlxBins(4, 7, 0x1000000, need_r, 0x2000000, need_s)
+    cases = [(B.PlxBins(5, 7, 0x1000000, need_r, 0x2000000, need_s), "made for 5 rays"),
+             (B.PlxBins(4, 7, 0x1000000, need_r - 1, 0x2000000, need_s), "need"),
+             (B.PlxBins(4, 7, 0x1000010, need_r, 0x2000000, need_s), "aligned"),
+             (B.PlxBins(4, 7, None, need_r, 0x2000000, need_s), "NULL"),
+             (B.PlxBins(4, 7, 0x1000000, need_r, 0x2000000, need_s - 1), "need"),
+             (B.PlxBins(4, 7, 0x1000000, need_r, None, need_s), "NULL"),
+             (B.PlxBins(4, -3, 0x1000000, need_r, 0x2000000, need_s), "n_seg")]
+    for bins, needle in cases:
+        rc = L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), o, d, 4, ctypes.byref(bins), rgb,
+                              None, None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+        rc = L.plx_render_train(ctypes.byref(g), ctypes.byref(opts), o, d, p(0x70000), 4,
+                                ctypes.byref(bins), 0.25, None, p(0x80000), p(0x90000), p(0xa0000),
+                                None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+        rc = L.plx_bins_apply(ctypes.byref(g), o, d, ctypes.byref(bins), None)
+        if bins.n_rays == 4:
+            assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+    # NULL bins
+    assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), o, d, 4, None, rgb, None,
+                            None) == B.PLX_EINVAL
+    assert "bins" in L.plx_last_error().decode()
+    del good
+    # counting: NULL count, short or misaligned ray buffer; zero rays
+    n_seg = ctypes.c_int64(-1)
+    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000000), need_r, None, None) == B.PLX_EINVAL
+    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000000), need_r - 8, ctypes.byref(n_seg),
+                            None) == B.PLX_EINVAL
+    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000080), need_r, ctypes.byref(n_seg),
+                            None) == B.PLX_EINVAL
+    z = B.plx_bins_ray_bytes(reso, 0)
+    assert L.plx_bins_count(ctypes.byref(g), None, None, 0, p(0x1000000), z, ctypes.byref(n_seg),
+                            None) == B.PLX_OK and n_seg.value == 0
+
+
+def test_grid_workspace_validation():
+    """The grid calls take a caller workspace of plx_grid_workspace_bytes and
+    reject a short, misaligned or missing one before any launch."""
+    L = B.lib()
+    p = ctypes.c_void_p
+    reso = (10, 12, 14)
+    n = 10 * 12 * 14
+    need = B.plx_grid_workspace_bytes(reso)
+    assert need >= n and B.plx_grid_workspace_bytes((1, 2, 3)) == 0
+    assert B.plx_grid_workspace_bytes((512, 512, 512)) >= 512 ** 3
+    r3 = (ctypes.c_int32 * 3)(*reso)
+    for ws, nbytes, needle in [(0x100000, need - 1, "need"), (0x100040, need, "aligned"),
+                               (None, need, "NULL")]:
+        rc = L.plx_grid_create(p(0x1000), ctypes.cast(r3, p), p(0x2000), p(ws) if ws else None, nbytes,
+                               None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+    g = _grid_desc(reso=reso)
+    kept, pruned = ctypes.c_int64(), ctypes.c_int64()
+    assert L.plx_grid_prune_count(ctypes.byref(g), 1.0, p(0x1000), p(0x100000), need - 1,
+                                  ctypes.byref(kept), ctypes.byref(pruned), None) == B.PLX_EINVAL
+    assert L.plx_mask_count(p(0x1000), 5, p(0x100000), 255, ctypes.byref(kept), None) == B.PLX_EINVAL
+    assert L.plx_touched_count(p(0x1000), 5, None, 256, ctypes.byref(kept), None) == B.PLX_EINVAL

@@ -356,6 +356,22 @@ def test_tv_density_constant_field_edge_rule():
     assert np.all(gs == 0.0)
 
 
+def test_tv_uniform_grid_is_finite_and_eps_must_be_positive():
+    # the uniform initial grid: every SH difference is 0, so each SH term is
+    # sqrt(eps) and its derivative 0 (finite only because eps > 0); eps = 0
+    # is refused rather than dividing 0 by 0
+    n, eps = 5, 1e-9
+    sh = np.zeros((n ** 3, 27))
+    sh[:, 0] = sh[:, 9] = sh[:, 18] = math.sqrt(math.pi)
+    g = dense_grid((n, n, n), np.full(n ** 3, 0.1), sh)
+    loss, gd, gs, touched = O.tv(g, 0, n ** 3, 0.0, 1.0, eps)
+    assert np.all(np.isfinite(gs)) and np.all(gs == 0.0)
+    assert abs(loss - 27 * math.sqrt(eps)) < 1e-15
+    for bad in (0.0, -1e-9, float("nan")):
+        with pytest.raises(ValueError):
+            O.tv(g, 0, n ** 3, 1.0, 1.0, bad)
+
+
 def test_tv_single_voxel_null_rules():
     n, c, eps = 7, 3.0, 1e-9
     mask = np.zeros(n ** 3, np.uint8)
