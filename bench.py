@@ -2,24 +2,28 @@
 
 Workload (the differentiation/scale configuration): a 512^3 sparse grid at 5%
 occupancy (6.71M voxels, FP32 records) built from 32 seeded Gaussian density
-blobs, 100 cameras on the radius-2 sphere at 800x800, and 1M-ray batches drawn
-uniformly from all their pixels (listed in camera / Morton-pixel order; the
-same rays shuffled are timed too); targets are renders of the ground-truth
-grid.  The trained grid has the same occupancy with perturbed values.  One
-step = fused render + MSE + backward over the batch, TV on a random
-contiguous 1% segment of the cells, and sparse RMSProp on the active voxels.
+blobs, and all 64M pixels of 100 cameras on the radius-2 sphere at 800x800
+resident on the device with their targets (renders of the ground-truth
+grid).  The trained grid has the ground-truth occupancy with perturbed
+values.  One step = gather of a 1M-ray batch (a slice of a per-epoch
+permutation of all pixels, listed in camera / Morton-pixel order), its
+segment lists (count + apply), fused render + MSE + backward, TV on a random
+contiguous 1% segment of the cells, and sparse RMSProp on the active voxels;
+the gather and segment lists of batch t+1 run on a second stream during step
+t (Trainer.run), and the timed region holds every part of every step.
 
-Prints one JSON line: whole-step Mrays/s, the roofline of the dominant kernel
-(render_train, algorithmic bytes from the library's work counters over its
-HIP-event duration; beside it the bytes rocprofv3's counters measured for
-the same call, over the same duration, and their ratio to the algorithmic
-bytes), the same step with BF16/FP16 SH storage and with
-shuffled rays and with the sparsity and beta priors on, separate
-forward/backward with and without stored per-sample state, the
-pruning-by-weight pass, the serving latency leg, and the FP64
-oracle timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line: whole-step Mrays/s; the roofline of the dominant kernel
+(seg_bwd, the segment backward: the algorithmic bytes of the backward pass
+from the library's work counters over its duration measured with HIP events
+recorded on its stream), with the per-kernel times and fractions beside it;
+the same step with BF16/FP16 SH storage, with shuffled rays, without the
+second stream and with the sparsity and beta priors on; separate
+forward/backward with and without stored per-sample state; the
+pruning-by-weight pass; the serving latency leg; and the FP64 oracle timed
+on a bounded sample of the same workload on all host cores and on one.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -35,7 +39,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 from paper_2112_05131_amd import binding as B  # noqa: E402
 from paper_2112_05131_amd.grid import Grid  # noqa: E402
-from paper_2112_05131_amd.train import TrainConfig, Trainer  # noqa: E402
+from paper_2112_05131_amd.runs import _camera_set, render_rays  # noqa: E402
+from paper_2112_05131_amd.train import RaySampler, TrainConfig, Trainer  # noqa: E402
 
 METRIC = "fwd+bwd Mrays/s & HBM GB/s vs plain FP32; p50/p99 view-render latency"
 HBM_PEAK_GBS = 8000.0
@@ -45,77 +50,77 @@ N_BLOBS = 32
 SEED = 2
 BATCH = 1 << 20
 N_CAMS, W, H = 100, 800, 800
-# HBM bytes moved by one plx_render_train call of this workload (FP32
-# records), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
-# `bench.py --counters`, each scaled by its reading for a 1 GiB device copy
-# (FETCH x2, WRITE x1): 9.811 GB fetched + 8.766 GB written.  Re-measure
-# whenever the render kernels change.
-RENDER_TRAIN_TRAFFIC_GB_F32 = 18.58
-# the same with BF16 SH records (`--dtype bf16`): 4.765 GB + 8.744 GB
-RENDER_TRAIN_TRAFFIC_GB_BF16 = 13.51
+# HBM bytes per seg_bwd launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (scaled by a plain copy's readings), with the hash of the kernel
+# source they were taken on; a changed source makes them stale (null).
+COUNTERS = os.path.join(ROOT, "profiles", "seg_bwd_512cubed_1Mrays_counters.json")
+RENDER_SRC = os.path.join(ROOT, "paper_2112_05131_amd", "csrc", "render.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(sh_dtype, n_batches, coherent=True):
-    t0 = time.time()
-    gt = synth.blob_scene(RESO, N_BLOBS, OCC, SEED, device="cuda")
-    gt_grid = Grid.from_mask(gt.mask, RESO, gt.density, gt.sh)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(SEED + 1000)
-    dens = gt.density * (0.5 + torch.rand(gt.n_vox, device="cuda", generator=gen))
-    sh = gt.sh + 0.05 * torch.randn(gt.n_vox, 27, device="cuda", generator=gen)
-    grid = Grid.from_mask(gt.mask, RESO, dens, sh, sh_dtype=sh_dtype)
-    poses = synth.sphere_poses(N_CAMS, seed=SEED)
-    batches = []
-    for b in range(n_batches):
-        o, d, _ = synth.sampled_camera_rays(poses, W, H, BATCH, seed=SEED + 10 * b, device="cuda",
-                                            coherent=coherent)
-        tgt = torch.empty(BATCH, 3, device="cuda")
-        B.plx_render_fwd(gt_grid.desc(), o, d, tgt)
-        batches.append((o, d, tgt))
-    torch.cuda.synchronize()
-    log(f"workload built in {time.time() - t0:.1f}s: M={grid.n_vox}, batches={n_batches}")
-    return gt, grid, batches, (dens, sh)
+def source_hash(path=RENDER_SRC) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def time_steps(trainer, batches, warmup, steps):
-    g = trainer.grid
-    c = trainer.cfg
-    for i in range(warmup):
-        o, d, t = batches[i % len(batches)]
-        trainer.step(o, d, t)
+def measured_traffic(sh_dtype):
+    """(bytes per seg_bwd launch, source of the figure) from the committed
+    counter summary when it was taken on this kernel source, else (None,
+    reason)."""
+    try:
+        c = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None, "no counter summary"
+    key = {B.PLX_F32: "f32", B.PLX_BF16: "bf16", B.PLX_F16: "f16"}[sh_dtype]
+    e = c.get(key)
+    if not e:
+        return None, f"no {key} counters"
+    if e.get("render_hip_sha16") != source_hash():
+        return None, "stale: render.hip changed since the counters were taken"
+    return e["fetch_bytes"] + e["write_bytes"], e.get("command", "")
+
+
+class Workload:
+    """Ground truth, the resident ray pool with its targets, and the initial
+    values of the trained grid."""
+
+    def __init__(self):
+        t0 = time.time()
+        self.gt = synth.blob_scene(RESO, N_BLOBS, OCC, SEED, device="cuda")
+        gt_grid = Grid.from_mask(self.gt.mask, RESO, self.gt.density, self.gt.sh)
+        self.o, self.d = _camera_set(N_CAMS, W, H, SEED, torch.device("cuda"))
+        self.t = render_rays(gt_grid, self.o, self.d)
+        del gt_grid
+        self.init = synth.perturbed(self.gt, seed=SEED + 1000, device="cuda")
+        torch.cuda.synchronize()
+        log(f"workload built in {time.time() - t0:.1f}s: M={self.gt.n_vox}, pool={self.o.shape[0]} rays")
+
+    def grid(self, sh_dtype):
+        return Grid.from_mask(self.init.mask, RESO, self.init.density, self.init.sh, sh_dtype=sh_dtype)
+
+    def sampler(self, coherent=True, seed=SEED):
+        return RaySampler(self.o, self.d, self.t, BATCH, seed=seed, coherent=coherent)
+
+
+def time_steps(trainer, sampler, warmup, steps, overlap=True):
+    """W untimed steps, then exactly K steps between two synchronisations;
+    returns (ms per step, wall s, mean per-part ms)."""
+    trainer.run(sampler, warmup, overlap=overlap)
     torch.cuda.synchronize()
     evs = []
-    t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     start.record()
-    for i in range(steps):
-        o, d, t = batches[(warmup + i) % len(batches)]
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        lr_s, lr_h = trainer.learning_rates()
-        e[0].record()
-        B.plx_render_train(g.desc(), o, d, t, 1.0 / o.shape[0], trainer.grad, trainer.touched,
-                           trainer.loss_sum, None, c.background, trainer.priors())
-        e[1].record()
-        s0, cnt = trainer.tv_segment()
-        B.plx_tv_grad(g.desc(), s0, cnt, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps, trainer.grad,
-                      trainer.touched, trainer.tv_loss_sum)
-        e[2].record()
-        B.plx_rmsprop_step(g.desc(), g.master, trainer.vstate, trainer.grad, trainer.touched, lr_s,
-                           lr_h, c.beta, c.eps)
-        e[3].record()
-        trainer.step_id += 1
-        evs.append(e)
+    trainer.run(sampler, steps, overlap=overlap, events=evs)
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(end) / steps
-    k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-                     for e in evs]).mean(axis=0)
+    parts = [e.durations() for e in evs]
+    k_ms = {k: float(np.mean([p[k] for p in parts])) for k in parts[0]}
     return ms, wall, k_ms
 
 
@@ -143,14 +148,25 @@ def active_count(trainer, batch):
     return a, cnt
 
 
-def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, batch, budget_s=12.0):
     """The FP64 oracle on a bounded sample of the same workload: fwd + MSE +
     bwd over S rays of the batch, TV on S/R of the step's segment and RMSProp
-    on the sample's active voxels, timed on the host."""
+    on the sample's active voxels, timed on the host with all its threads,
+    then with one thread on a smaller sample."""
     from oracle import oracle as O
-    dens, sh = grid_vals
-    og = O.make_grid(np.array(RESO, np.int32), gt.mask.cpu().numpy(), dens.cpu().double().numpy(),
-                     sh.cpu().double().numpy())
+    init = wl.init
+    og = O.make_grid(np.array(RESO, np.int32), init.mask.cpu().numpy(), init.density.cpu().double().numpy(),
+                     init.sh.cpu().double().numpy())
     o, d, t = (x.cpu().numpy() for x in batch)
     ncell = RESO[0] * RESO[1] * RESO[2]
 
@@ -167,16 +183,30 @@ def cpu_baseline(gt, grid_vals, batch, budget_s=15.0):
                   1.0, 0.01)
         return time.perf_counter() - t0
 
-    run(500)  # first touch of the grid arrays
-    s = 4000
-    ts_ = run(s)
-    while ts_ < 0.5 * budget_s and s < BATCH:
-        s = int(min(BATCH, s * min(8.0, budget_s / max(ts_, 1e-6))))
+    def sized(budget):
+        s = 2000
         ts_ = run(s)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(s / ts_ / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
-            "sample": f"{s} rays of one 1M-ray batch (fwd+MSE+bwd), TV on {s}/{BATCH} of the 1% "
-                      f"segment, RMSProp on the sample's active voxels; {ts_:.1f} s FP64"}
+        while ts_ < 0.5 * budget and s < BATCH:
+            s = int(min(BATCH, s * min(8.0, budget / max(ts_, 1e-6))))
+            ts_ = run(s)
+        return s, ts_
+
+    run(500)  # first touch of the grid arrays
+    n0 = O.max_threads()
+    s, ts_ = sized(budget_s)
+    out = {"value": round(s / ts_ / 1e6, 6), "unit": "Mrays/s", "cores": n0, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{s} rays of one 1M-ray batch (fwd+MSE+bwd), TV on {s}/{BATCH} of the 1% "
+                     f"segment, RMSProp on the sample's active voxels; {ts_:.1f} s FP64"}
+    try:
+        O.set_threads(1)
+        s1, t1 = sized(budget_s / 2)
+    finally:
+        O.set_threads(n0)
+    out["one_core"] = {"value": round(s1 / t1 / 1e6, 6), "unit": "Mrays/s", "cores": 1,
+                       "sample": f"{s1} rays, {t1:.1f} s FP64"}
+    log(f"oracle: {out['value']} Mrays/s on {n0} threads, {out['one_core']['value']} on 1 ({out['cpu_model']})")
+    return out
 
 
 def state_leg(grid, batch, steps, cap=640):
@@ -205,17 +235,19 @@ def state_leg(grid, batch, steps, cap=640):
         return a.elapsed_time(b) / reps
 
     desc = grid.desc()
-    fwd = timed(lambda: B.plx_render_fwd(desc, o, d, rgb, tau))
+    bins = B.make_bins(desc, o, d)
+    fwd = timed(lambda: B.plx_render_fwd(desc, o, d, rgb, tau, bins=bins))
     torch.sub(rgb, t, out=g_rgb).mul_(2.0 / n)
-    bwd = timed(lambda: B.plx_render_bwd(desc, o, d, g_rgb, tau, grad, touched))
+    bwd = timed(lambda: B.plx_render_bwd(desc, o, d, g_rgb, tau, grad, touched, bins=bins))
     fwd_s = timed(lambda: B.plx_render_fwd_state(desc, o, d, rgb, tau, state, cap))
     bwd_s = timed(lambda: B.plx_render_bwd_state(desc, o, d, g_rgb, tau, state, cap, grad, touched))
     counts = state[:4 * n].view(torch.int32)
     over = int((counts > cap).sum())
-    del state, grad
+    del state, grad, bins
     torch.cuda.empty_cache()
     log(f"recompute fwd {fwd:.3f} bwd {bwd:.3f} ms; stored state fwd {fwd_s:.3f} bwd {bwd_s:.3f} ms")
-    return {"recompute": {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4)},
+    return {"recompute": {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+                          "note": "segment lists made once, outside the timed calls"},
             "stored": {"fwd_ms": round(fwd_s, 4), "bwd_ms": round(bwd_s, 4), "cap": cap,
                        "state_gb": round(B.plx_render_state_bytes(n, cap) / 1e9, 3),
                        "rays_over_cap": over}}
@@ -227,23 +259,26 @@ def prune_weight_leg(grid, batches, counts, thresh=0.01):
     (plx_render_max_weight once per batch, brick order, density only), then
     the dilated threshold count over the whole grid
     (plx_grid_prune_weight_count), timed with HIP events on the stream the
-    calls are launched on.  Algorithmic bytes of one weight call: the index
+    calls are launched on (segment lists made beforehand).  Algorithmic
+    bytes of one weight call: the index
     entries read (4 B each), per voxel read its density (4 B) and one
     read-modify-write of its maximum (8 B), and 24 B of ray per ray."""
     wmax = torch.zeros(grid.n_vox, device="cuda")
     keep = torch.empty(grid.n_cells, dtype=torch.uint8, device="cuda")
     desc = grid.desc()
+    bins = [B.make_bins(desc, o, d) for o, d, _ in batches]
     o, d, _ = batches[0]
-    B.plx_render_max_weight(desc, o, d, wmax)  # warm-up (library and allocator)
+    B.plx_render_max_weight(desc, o, d, wmax, bins=bins[0])  # warm-up
     wmax.zero_()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    for o, d, _ in batches:
-        B.plx_render_max_weight(desc, o, d, wmax)
+    for (o, d, _), bb in zip(batches, bins):
+        B.plx_render_max_weight(desc, o, d, wmax, bins=bb)
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / len(batches)
+    del bins
     a.record()
     kept, pruned = B.plx_grid_prune_weight_count(desc, wmax, thresh, keep)
     b.record()
@@ -306,15 +341,16 @@ def serving_leg(n_sat=400, n_load=2000):
 
 
 def counter_run(sh_dtype, coherent):
-    """Dispatch sequence for rocprofv3 --pmc passes: a warm-up step, one
-    training step (render_train's kernels, tv_kernel, rmsprop_kernel), then a
-    1 GiB device-to-device copy (1 GiB read + 1 GiB written) whose counter
-    readings give the scale of FETCH_SIZE / WRITE_SIZE."""
-    gt, grid, batches, vals = build_workload(sh_dtype, 1, coherent)
-    trainer = Trainer(grid, TrainConfig(), seed=SEED)
-    o, d, t = batches[0]
-    for _ in range(2):
-        trainer.step(o, d, t)
+    """Dispatch sequence for rocprofv3 --pmc passes: two warm-up steps, one
+    training step (its gather, segment lists, seg_fwd, seg_combine, seg_bwd,
+    tv and rmsprop kernels), then a 1 GiB device-to-device copy (1 GiB read
+    + 1 GiB written) whose counter readings give the scale of FETCH_SIZE /
+    WRITE_SIZE."""
+    wl = Workload()
+    trainer = Trainer(wl.grid(sh_dtype), TrainConfig(), seed=SEED)
+    sampler = wl.sampler(coherent)
+    for _ in range(3):
+        trainer.run(sampler, 1, overlap=False)
         torch.cuda.synchronize()
     src = torch.ones(1 << 28, device="cuda")
     dst = torch.empty_like(src)
@@ -324,6 +360,51 @@ def counter_run(sh_dtype, coherent):
     log("counter run done")
 
 
+def c2_leg(steps=200, warmup=20):
+    """The coarse-to-fine configuration's step: 5000-ray batches on the 256^3
+    grid at 10% occupancy (32 blobs, seed 1; 100 cameras at 800x800 as the
+    ray pool, ground-truth renders as targets), with the next batch binned on
+    the second stream and without."""
+    reso = (256, 256, 256)
+    gt = synth.blob_scene(reso, N_BLOBS, 0.10, 1, device="cuda")
+    gt_grid = Grid.from_mask(gt.mask, reso, gt.density, gt.sh)
+    o, d = _camera_set(N_CAMS, W, H, 1, torch.device("cuda"))
+    t = render_rays(gt_grid, o, d)
+    del gt_grid
+    init = synth.perturbed(gt, seed=1001, device="cuda")
+    out = {"grid": list(reso), "n_vox": gt.n_vox, "batch_rays": 5000, "steps": steps}
+    for overlap in (True, False):
+        g = Grid.from_mask(init.mask, reso, init.density, init.sh)
+        tr = Trainer(g, TrainConfig(), seed=1)
+        smp = RaySampler(o, d, t, 5000, seed=1)
+        ms, wall, k = time_steps(tr, smp, warmup, steps, overlap=overlap)
+        key = "overlapped" if overlap else "sequential"
+        out[key] = {"ms_per_step": round(ms, 4), "mrays_s": round(5000 / ms / 1e3, 3),
+                    "wall_ms_per_step": round(wall / steps * 1e3, 4),
+                    "kernels_ms": {kk: round(v, 4) for kk, v in k.items()}}
+        log(f"c2 {key}: {ms:.4f} ms per 5000-ray step (wall {wall / steps * 1e3:.4f})")
+        del g, tr
+    del o, d, t
+    torch.cuda.empty_cache()
+    return out
+
+
+def byte_model(counts, n_rays, sh_dtype):
+    """Algorithmic bytes of the forward and backward passes over one batch
+    from the library's work counters (U_idx distinct index entries read,
+    U_occ distinct non-NULL voxels read): forward 4 U_idx + P U_occ + 40 R
+    (rays 24 B, colour 12 B, optical depth 4 B per ray), backward with
+    recomputation 4 U_idx + P U_occ + 224 U_occ + 28 R (the gradient record
+    read and written, rays and dL/dC), P = 112 B (FP32) or 58 B (16-bit) of
+    payload per voxel."""
+    P = 112 if sh_dtype == B.PLX_F32 else 58
+    u_idx, u_occ = counts[2], counts[3]
+    fwd = 4 * u_idx + P * u_occ + 40 * n_rays
+    bwd = 4 * u_idx + P * u_occ + 224 * u_occ + 28 * n_rays
+    fused = 4 * u_idx + (P + 224) * u_occ + 36 * n_rays
+    return fwd, bwd, fused
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,14 +412,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the BF16/FP16-SH steps")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the BF16/FP16-SH, shuffled, sequential and priors steps")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 5000-ray 256^3 step leg")
     ap.add_argument("--ray-order", default="coherent", choices=["coherent", "random"],
                     help="order of the rays inside each batch (the same rays either way)")
     ap.add_argument("--counters", action="store_true",
-                    help="for counter runs under rocprofv3: one warm-up and one timed-shape "
-                         "training step on one batch, then a 1 GiB device copy that calibrates "
-                         "the byte counters; prints no JSON line")
+                    help="for counter runs under rocprofv3: warm-up steps and one training "
+                         "step, then a 1 GiB device copy that calibrates the byte counters; "
+                         "prints no JSON line")
     ap.add_argument("--serving-only", action="store_true",
                     help="for trace runs under rocprofv3: only the serving leg, printed as its "
                          "own JSON object")
@@ -355,27 +438,33 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": serving_leg()}), flush=True)
         return
-    n_batches = min(args.warmup + args.steps, 8)
-    gt, grid, batches, vals = build_workload(sh_dtype, n_batches, args.ray_order == "coherent")
+    coherent = args.ray_order == "coherent"
+    wl = Workload()
+    grid = wl.grid(sh_dtype)
     trainer = Trainer(grid, TrainConfig(), seed=SEED)
-
-    counts = work_counters(grid, batches[0])
-    n_act, tv_cells = active_count(trainer, batches[0])
+    # the first batch of the timed run's sampler, for the work counters
+    batch0 = wl.sampler(coherent).next_batch()
+    counts = work_counters(grid, batch0)
+    n_act, tv_cells = active_count(trainer, batch0)
     log(f"counters: samples={counts[0]} occupied_samples={counts[1]} U_idx={counts[2]} "
         f"U_occ={counts[3]} active={n_act}")
 
-    ms, wall, k_ms = time_steps(trainer, batches, args.warmup, args.steps)
+    ms, wall, k_ms = time_steps(trainer, wl.sampler(coherent), args.warmup, args.steps)
     mrays = BATCH / (ms * 1e-3) / 1e6
     log(f"step {ms:.3f} ms (wall {wall / args.steps * 1e3:.3f} ms/step); kernels ms: "
-        f"render_train {k_ms[0]:.3f} tv {k_ms[1]:.3f} rmsprop {k_ms[2]:.3f}")
+        + ", ".join(f"{k} {v:.3f}" for k, v in k_ms.items()))
 
-    P = 112 if sh_dtype == B.PLX_F32 else 58
-    alg_render = 4 * counts[2] + (P + 224) * counts[3] + 36 * BATCH
-    achieved = alg_render / (k_ms[0] * 1e-3) / 1e9
-    traffic_gb = {B.PLX_F32: RENDER_TRAIN_TRAFFIC_GB_F32, B.PLX_BF16: RENDER_TRAIN_TRAFFIC_GB_BF16}.get(sh_dtype)
+    fwd_b, bwd_b, fused_b = byte_model(counts, BATCH, sh_dtype)
+    gbs = lambda b, t_ms: b / (t_ms * 1e-3) / 1e9  # noqa: E731
+    achieved = gbs(bwd_b, k_ms["seg_bwd"])
+    traffic, traffic_src = measured_traffic(sh_dtype)
     alg_rms = n_act * (672 if sh_dtype == B.PLX_F32 else 726)
-    alg_tv = 4 * 4 * tv_cells
-    step_gbs = (alg_render + alg_rms + alg_tv) / (ms * 1e-3) / 1e9
+    alg_tv = 16 * tv_cells
+    step_gbs = gbs(fwd_b + bwd_b + alg_rms + alg_tv, ms)
+
+    def frac(b, t_ms):
+        return {"ms": round(t_ms, 4), "algorithmic_gb": round(b / 1e9, 4),
+                "achieved_gbs": round(gbs(b, t_ms), 1), "frac": round(gbs(b, t_ms) / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": METRIC,
@@ -392,8 +481,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "512^3 sparse grid, 5% occupancy (6.71M voxels), SH deg 2, "
-                        "1M-ray batches from 100 cameras at 800x800; step = fused "
-                        "render+MSE+backward, TV on a 1% contiguous segment, sparse RMSProp",
+                        "1M-ray batches from all pixels of 100 cameras at 800x800; step = batch "
+                        "gather + segment lists (next batch on a second stream) + fused "
+                        "render+MSE+backward + TV on a 1% contiguous segment + sparse RMSProp",
             "sh_storage": args.dtype,
             "batch_rays": BATCH,
             "ray_order": args.ray_order,
@@ -402,79 +492,86 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "render_train (one plx_render_train call: seg_count, count scans, seg_emit, "
-                      "seg_fwd, seg_combine, seg_bwd)",
+            "kernel": "seg_bwd (segment backward replay of plx_render_train)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_gb,
-            "traffic_unit": "GB per call (measured)",
-            "algorithmic_gb": round(alg_render / 1e9, 3),
-            # the measured bytes over this run's call time, and their ratio to
-            # the algorithmic bytes
-            "traffic_gbs": (round(traffic_gb / (k_ms[0] * 1e-3), 1)
-                            if traffic_gb else None),
-            "traffic_frac": (round(traffic_gb / (k_ms[0] * 1e-3) / HBM_PEAK_GBS, 4)
-                             if traffic_gb else None),
-            "amplification": (round(traffic_gb * 1e9 / alg_render, 2)
-                              if traffic_gb else None),
+            "traffic": round(traffic / 1e9, 3) if traffic else None,
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "traffic_source": traffic_src,
+            "algorithmic_gb": round(bwd_b / 1e9, 4),
+            "bytes_model": "backward with recomputation: 4 U_idx + P U_occ + 224 U_occ + 28 R",
         },
-        "kernels_ms": {"render_train": round(float(k_ms[0]), 4), "tv_grad": round(float(k_ms[1]), 4),
-                       "rmsprop_step": round(float(k_ms[2]), 4)},
+        "kernels": {
+            "seg_fwd": frac(fwd_b, k_ms["seg_fwd"]),
+            "seg_bwd": frac(bwd_b, k_ms["seg_bwd"]),
+            "seg_combine_ms": round(k_ms["seg_combine"], 4),
+            "render_train_call": dict(frac(fwd_b + bwd_b, k_ms["render_train"]),
+                                      bytes_model="forward + backward with recomputation"),
+            "render_train_call_fused_model": dict(frac(fused_b, k_ms["render_train"]),
+                                                  bytes_model="4 U_idx + (P + 224) U_occ + 36 R: one "
+                                                              "read of each voxel for the whole call"),
+            "tv_grad_ms": round(k_ms["tv"], 4),
+            "rmsprop_step": frac(alg_rms, k_ms["rmsprop"]),
+            "bins_ms_second_stream": round(k_ms.get("bins", 0.0), 4),
+        },
         "step_hbm_gbs_algorithmic": round(step_gbs, 1),
         "work": {"samples": counts[0], "occupied_samples": counts[1], "index_entries": counts[2],
                  "voxels_read": counts[3], "active_voxels": n_act, "tv_cells": tv_cells},
     }
     if not args.no_compare:
         # the same step with SH stored in FP32, BF16 and FP16 (FP32 optimiser
-        # state and accumulation in all three)
+        # state and accumulation in all three), the same batches
         prec = {args.dtype: {"ms_per_step": round(ms, 4), "mrays_s": round(mrays, 3),
-                             "render_train_ms": round(float(k_ms[0]), 4)}}
+                             "render_train_ms": round(k_ms["render_train"], 4),
+                             "seg_fwd_ms": round(k_ms["seg_fwd"], 4), "seg_bwd_ms": round(k_ms["seg_bwd"], 4)}}
         for name in ("f32", "bf16", "f16"):
             if name in prec:
                 continue
-            g2 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=B.DTYPES[name])
-            tr2 = Trainer(g2, TrainConfig(), seed=SEED)
-            ms2, _, k2 = time_steps(tr2, batches, 2, max(5, args.steps // 2))
+            tr2 = Trainer(wl.grid(B.DTYPES[name]), TrainConfig(), seed=SEED)
+            ms2, _, k2 = time_steps(tr2, wl.sampler(coherent), 2, max(5, args.steps // 2))
             prec[name] = {"ms_per_step": round(ms2, 4), "mrays_s": round(BATCH / ms2 / 1e3, 3),
-                          "render_train_ms": round(float(k2[0]), 4)}
-            log(f"{name}: step {ms2:.3f} ms, render_train {k2[0]:.3f} ms")
-            del g2, tr2
+                          "render_train_ms": round(k2["render_train"], 4),
+                          "seg_fwd_ms": round(k2["seg_fwd"], 4), "seg_bwd_ms": round(k2["seg_bwd"], 4)}
+            log(f"{name}: step {ms2:.3f} ms, render_train {k2['render_train']:.3f} ms")
+            del tr2
         for name in prec:
             prec[name]["speedup_vs_f32"] = round(prec["f32"]["ms_per_step"] / prec[name]["ms_per_step"], 4)
         out["precision"] = prec
-        if args.ray_order == "coherent":
-            # the same rays, shuffled inside each batch
-            gen = torch.Generator(device="cuda")
-            gen.manual_seed(SEED + 77)
-            shuffled = []
-            for o, d, t in batches:
-                p = torch.randperm(BATCH, device="cuda", generator=gen)
-                shuffled.append((o[p].contiguous(), d[p].contiguous(), t[p].contiguous()))
-            g3 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=sh_dtype)
-            tr3 = Trainer(g3, TrainConfig(), seed=SEED)
-            ms3, _, k3 = time_steps(tr3, shuffled, 2, max(5, args.steps // 2))
+        if coherent:
+            # the same pixels, each batch in the permutation's order
+            tr3 = Trainer(wl.grid(sh_dtype), TrainConfig(), seed=SEED)
+            ms3, _, k3 = time_steps(tr3, wl.sampler(False), 2, max(5, args.steps // 2))
             out["random_order"] = {"ms_per_step": round(ms3, 4), "mrays_s": round(BATCH / ms3 / 1e3, 3),
-                                   "render_train_ms": round(float(k3[0]), 4)}
-            log(f"random ray order: step {ms3:.3f} ms, render_train {k3[0]:.3f} ms")
-            del g3, tr3, shuffled
-    if not args.no_compare:
+                                   "render_train_ms": round(k3["render_train"], 4)}
+            log(f"random ray order: step {ms3:.3f} ms, render_train {k3['render_train']:.3f} ms")
+            del tr3
+        # the segment lists made on the training stream itself (their count's
+        # synchronisation then stalls the device once per step)
+        tr5 = Trainer(wl.grid(sh_dtype), TrainConfig(), seed=SEED)
+        ms5, _, k5 = time_steps(tr5, wl.sampler(coherent), 2, max(5, args.steps // 2), overlap=False)
+        out["sequential_binning"] = {"ms_per_step": round(ms5, 4), "mrays_s": round(BATCH / ms5 / 1e3, 3)}
+        log(f"sequential binning: step {ms5:.3f} ms")
+        del tr5
         # the same step with the sparsity and beta priors of Sec. 3.7 on (the
         # paper's 360-degree weights)
-        g4 = Grid.from_mask(gt.mask, RESO, vals[0], vals[1], sh_dtype=sh_dtype)
-        tr4 = Trainer(g4, TrainConfig(lambda_sparsity=1e-11, lambda_beta=1e-5), seed=SEED)
-        ms4, _, k4 = time_steps(tr4, batches, 2, max(5, args.steps // 2))
+        tr4 = Trainer(wl.grid(sh_dtype), TrainConfig(lambda_sparsity=1e-11, lambda_beta=1e-5), seed=SEED)
+        ms4, _, k4 = time_steps(tr4, wl.sampler(coherent), 2, max(5, args.steps // 2))
         out["with_priors"] = {"lambda_sparsity": 1e-11, "lambda_beta": 1e-5, "ms_per_step": round(ms4, 4),
-                              "mrays_s": round(BATCH / ms4 / 1e3, 3), "render_train_ms": round(float(k4[0]), 4)}
-        log(f"with priors: step {ms4:.3f} ms, render_train {k4[0]:.3f} ms")
-        del g4, tr4
-        out["backward_state"] = state_leg(grid, batches[0], args.steps)
-    out["prune_by_weight"] = prune_weight_leg(grid, batches, counts)
+                              "mrays_s": round(BATCH / ms4 / 1e3, 3),
+                              "render_train_ms": round(k4["render_train"], 4)}
+        log(f"with priors: step {ms4:.3f} ms, render_train {k4['render_train']:.3f} ms")
+        del tr4
+        out["backward_state"] = state_leg(grid, batch0, args.steps)
+    smp = wl.sampler(coherent, seed=SEED + 5)
+    out["prune_by_weight"] = prune_weight_leg(grid, [smp.next_batch() for _ in range(4)], counts)
+    if not args.no_c2:
+        out["c2_step"] = c2_leg()
     if not args.no_serving:
         out["serving"] = serving_leg()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(gt, vals, batches[0])
+        out["cpu_baseline"] = cpu_baseline(wl, batch0)
     print(json.dumps(out), flush=True)
 
 

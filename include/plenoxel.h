@@ -131,6 +131,14 @@ typedef struct plx_render_opts {
                                     WRITE dL/d(background colour) = T_final
                                     dL/dC per ray (the upstream gradient of
                                     plx_bg_render_bwd) */
+    void **kernel_events;        /* NULL, or 4 caller-created hipEvent_t that
+                                    the binned render calls record on the
+                                    stream (for timing): before the first
+                                    segment kernel, after the segment
+                                    forward, after the per-ray combine, and
+                                    after the segment backward (the last is
+                                    recorded at the end of forward-only
+                                    calls too) */
 } plx_render_opts;
 
 /* ---------------------------------------------------------------- misc */

@@ -105,6 +105,10 @@ def lib():
         L.orc_upsample.restype = i64
         L.orc_lr_schedule.argtypes = [f64, f64, f64, f64, f64, f64]
         L.orc_lr_schedule.restype = f64
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = i32
         _lib = L
     return _lib
 
@@ -452,3 +456,13 @@ def upsample(g: Grid, new_reso, lo=(-0.5,) * 3, hi=(0.5,) * 3, step_voxels=0.5) 
 def lr_schedule(step, lr0, lr1, max_steps, delay_steps=0.0, delay_mult=1.0) -> float:
     return float(lib().orc_lr_schedule(float(step), float(lr0), float(lr1), float(max_steps),
                                        float(delay_steps), float(delay_mult)))
+
+
+def set_threads(n: int):
+    """Host threads of the oracle's parallel loops (results do not depend on
+    it: sums are formed in a fixed order)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

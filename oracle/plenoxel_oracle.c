@@ -56,6 +56,26 @@
 
 #define ORC_NSH 27 /* 3 colour channels x 9 degree-2 SH coefficients */
 
+/* Number of host threads the oracle's parallel loops use (timing runs set
+ * it; results do not depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid coordinate frame.  Voxel values live at voxel centres: voxel i of an
  * axis of N voxels spanning [lo, hi] sits at world lo + (i + 0.5) (hi-lo)/N,

@@ -59,6 +59,7 @@ class PlxRenderOpts(ctypes.Structure):
         ("reg_loss_sum", ctypes.c_void_p),
         ("background_rgb", ctypes.c_void_p),
         ("grad_background", ctypes.c_void_p),
+        ("kernel_events", ctypes.c_void_p),
     ]
 
 
@@ -342,10 +343,24 @@ def plx_grid_upsample_apply(g: PlxGrid, out: PlxGrid, ws=None):
 
 # --------------------------------------------------------------------- render
 
-def _opts(bg, priors: Priors | None = None, n: int | None = None, grad_bg=None):
+def event_handles(events):
+    """A C array of the raw HIP handles of 4 torch.cuda.Event objects, for
+    plx_render_opts.kernel_events (each event is created by recording it
+    once on the current stream; the library records it again)."""
+    if events is None:
+        return None
+    if len(events) != 4:
+        raise ValueError("kernel_events takes 4 events")
+    for e in events:
+        e.record()
+    return (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
+
+
+def _opts(bg, priors: Priors | None = None, n: int | None = None, grad_bg=None, events=None):
     """bg: one colour (3 numbers) or a device float32 tensor [R, 3] of
     per-ray background colours; priors: the optional priors; grad_bg: device
-    float32 [R, 3] that gradient calls fill with dL/d(background colour)."""
+    float32 [R, 3] that gradient calls fill with dL/d(background colour);
+    events: 4 torch.cuda.Event recorded between the render kernels."""
     if isinstance(bg, torch.Tensor):
         o = PlxRenderOpts((ctypes.c_float * 3)(0.0, 0.0, 0.0))
         o.background_rgb = _dptr(bg, "background_rgb", torch.float32, None if n is None else 3 * n)
@@ -358,6 +373,9 @@ def _opts(bg, priors: Priors | None = None, n: int | None = None, grad_bg=None):
         o.lambda_beta = float(priors.lambda_beta)
         o.beta_eps = float(priors.beta_eps)
         o.reg_loss_sum = _dptr(priors.loss, "priors.loss", torch.float64, 2)
+    if events is not None:
+        o._events = event_handles(events)  # kept alive with the struct
+        o.kernel_events = ctypes.cast(o._events, ctypes.c_void_p)
     return o
 
 
@@ -461,9 +479,9 @@ def _bins_for(g: PlxGrid, rays_o, rays_d, bins: Bins | None) -> Bins:
 
 
 def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1.0, 1.0),
-                   bins: Bins | None = None):
+                   bins: Bins | None = None, events=None):
     n = rays_o.shape[0]
-    o = _opts(bg, None, n)
+    o = _opts(bg, None, n, None, events)
     b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_fwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
@@ -475,9 +493,9 @@ def plx_render_fwd(g: PlxGrid, rays_o, rays_d, rgb_out, tau_out=None, bg=(1.0, 1
 
 def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
                    bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None,
-                   bins: Bins | None = None):
+                   bins: Bins | None = None, events=None):
     n = rays_o.shape[0]
-    o = _opts(bg, priors, n, grad_bg)
+    o = _opts(bg, priors, n, grad_bg, events)
     b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_bwd(ctypes.byref(g), ctypes.byref(o),
                                 _dptr(rays_o, "rays_o", torch.float32, 3 * n),
@@ -491,9 +509,9 @@ def plx_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, grad, touched,
 
 def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
                      rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None, grad_bg=None,
-                     bins: Bins | None = None):
+                     bins: Bins | None = None, events=None):
     n = rays_o.shape[0]
-    o = _opts(bg, priors, n, grad_bg)
+    o = _opts(bg, priors, n, grad_bg, events)
     b = _bins_for(g, rays_o, rays_d, bins)
     _check(lib().plx_render_train(ctypes.byref(g), ctypes.byref(o),
                                   _dptr(rays_o, "rays_o", torch.float32, 3 * n),

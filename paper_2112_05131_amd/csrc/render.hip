@@ -982,6 +982,7 @@ struct BinArgs {
     float4 *g_ray;       // [n_rays] dL/dC of each ray; w: beta factor of its samples
     unsigned *status;    // set to 1 when the emitting walk disagrees with the counting walk
     const int64_t *n_seg_dev;  // when set, the segment count is read here instead of n_seg
+    void **events;       // optional hipEvent_t[4] recorded between the render kernels
     Priors pri;
     float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
@@ -1822,6 +1823,13 @@ int bin_count_launch(const GridDev &g, BinArgs &a, int64_t nbk, int64_t *scan_tm
 // Render passes over binned segments: MODE_FWD renders, MODE_BWD and
 // MODE_TRAIN also run the backward replay, MODE_MAXW the weight passes.
 // Launch sizes come from a.n_seg, an upper bound when a.n_seg_dev is set.
+// Records the caller's timing event i (when given) on the stream.
+int mark_event(void **events, int i, hipStream_t s, const char *fn) {
+    if (!events || !events[i]) return PLX_OK;
+    PLX_CHECK_HIP(hipEventRecord(static_cast<hipEvent_t>(events[i]), s), fn);
+    return PLX_OK;
+}
+
 template <int MODE>
 int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn) {
     GridDev g = to_dev(grid);
@@ -1831,6 +1839,7 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     as.n_blocks = (int)nbs;
     as.nb8 = round_up8(nbs);
     int rc;
+    if ((rc = mark_event(a.events, 0, s, fn))) return rc;
     if constexpr (MODE == MODE_MAXW) {
         if (a.n_seg == 0) return PLX_OK;
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_weight_kernel<DT, 0><<<as.nb8, kThreads, 0, s>>>(g, as));
@@ -1844,8 +1853,10 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
         PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
         if ((rc = check_launch(fn))) return rc;
     }
+    if ((rc = mark_event(a.events, 1, s, fn))) return rc;
     seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
     if ((rc = check_launch(fn))) return rc;
+    if ((rc = mark_event(a.events, 2, s, fn))) return rc;
     if (MODE != MODE_FWD && a.n_seg > 0) {
         // the Cauchy prior's per-sample terms only in an instance of their own
         if (as.pri.lambda_s != 0.0f) {
@@ -1855,7 +1866,7 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
         }
         if ((rc = check_launch(fn))) return rc;
     }
-    return PLX_OK;
+    return mark_event(a.events, 3, s, fn);
 }
 
 // Priors of a gradient call from its options (validated).
@@ -1979,6 +1990,7 @@ int plx_render_fwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     if (!rgb_out) return fail(PLX_EINVAL, "%s: rgb_out is NULL", fn);
     BinArgs a = {};
     if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
+    a.events = opts->kernel_events;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.rgb_out = rgb_out;
@@ -2003,6 +2015,7 @@ int plx_render_bwd(const plx_grid *grid, const plx_render_opts *opts, const floa
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
     if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
+    a.events = opts->kernel_events;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.grad_rgb = grad_rgb;
@@ -2045,6 +2058,7 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     BinArgs a = {};
     if ((rc = priors_from(opts, a.pri, fn))) return rc;
     if ((rc = attach_bins(grid, bins, n_rays, a, fn))) return rc;
+    a.events = opts->kernel_events;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.target = target;

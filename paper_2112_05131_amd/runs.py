@@ -37,11 +37,6 @@ unbounded_360: a 360-degree scene (Sec. 3.6): a 256^3 blob scene inside the
   with the background at the paper's 64 x 1024 x 2048.  Reports times,
   voxel counts and held-out PSNR.
 
-serving_sweep: the multi-scene view server (8 resident scenes, 4 at 256^3
-  and 4 at 512^3, FP16 SH) for several numbers of streams and requests per
-  launch: the saturation rate (300 requests at once) and p50/p99 latency of
-  600 Poisson arrivals at 80% of it.
-
 Host code only chooses the schedule; every step is the library's fused
 render/MSE/backward, TV and sparse RMSProp.
 
@@ -49,8 +44,6 @@ render/MSE/backward, TV and sparse RMSProp.
     python -m paper_2112_05131_amd.runs drift --steps 2000
     python -m paper_2112_05131_amd.runs forward_facing --steps 300 [--prune-thresh 1]
     python -m paper_2112_05131_amd.runs unbounded_360 --steps 300
-    python -m paper_2112_05131_amd.runs bg_kernels
-    python -m paper_2112_05131_amd.runs serving_sweep
 """
 from __future__ import annotations
 
@@ -97,14 +90,14 @@ def _camera_set(n_cams: int, width: int, height: int, seed: int, device):
 
 def _timed_steps(trainer: Trainer, sampler: RaySampler, steps: int) -> float:
     """Runs `steps` training steps; returns the mean ms per step (device
-    events around the steps, batch gathers included)."""
+    events around the steps; batch gathers and segment lists included, the
+    next batch's made on a second stream during each step)."""
     if steps <= 0:
         return 0.0
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    for _ in range(steps):
-        trainer.step(*sampler.next_batch())
+    trainer.run(sampler, steps)
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps
@@ -388,46 +381,13 @@ def unbounded_360(steps_coarse: int = 300, steps_fine: int = 300, batch: int = 5
     }
 
 
-def bg_kernels(reso=(64, 1024, 2048), sizes=(5000, 65536, 131071, 131072, 1 << 20), reps: int = 5,
-               seed: int = 4, log=print) -> dict:
-    """HIP-event times of plx_bg_render_fwd / plx_bg_render_bwd on the
-    paper's background size (procedural sky values, every voxel stored) for
-    batches of rays from inside the unit sphere (synth.random_rays, radius
-    0.8), the first n of 1M rays."""
-    dev = torch.device("cuda")
-    _, bd, bc = synth.sky_background(reso, seed)
-    bg = _bg_grid(reso, bd.to(dev), bc.to(dev), dev)
-    grad = torch.zeros(bg.n_vox, B.REC_SLOTS, device=dev)
-    touched = torch.zeros(bg.n_vox, dtype=torch.uint8, device=dev)
-    o, d = synth.random_rays(max(sizes), seed=seed + 1, radius=0.8, target_half=0.45)
-    o, d = o.to(dev), d.to(dev)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
-
-    out = {"bg_reso": list(reso), "runs": []}
-    for n in sizes:
-        oo, dd = o[:n].contiguous(), d[:n].contiguous()
-        c = torch.empty(n, 3, device=dev)
-        g = torch.full((n, 3), 1e-3, device=dev)
-        f = timed(lambda: B.plx_bg_render_fwd(bg.desc(), oo, dd, c, None, (0.0, 0.0, 0.0)))
-        bw = timed(lambda: B.plx_bg_render_bwd(bg.desc(), oo, dd, g, grad, touched, (0.0, 0.0, 0.0)))
-        log(f"bg kernels n={n}: fwd {f:.3f} ms, bwd {bw:.3f} ms")
-        out["runs"].append({"rays": n, "fwd_ms": round(f, 4), "bwd_ms": round(bw, 4)})
-    return out
-
-
 def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512),
                     occupancy: float = 0.05, n_blobs: int = 32, n_cams: int = 100,
-                    width: int = 800, height: int = 800, seed: int = 2, log=print) -> dict:
+                    width: int = 800, height: int = 800, seed: int = 2, log=print,
+                    on_final=None) -> dict:
+    """on_final(name, grid, heldout_rays): called with each trained grid
+    before it is released (the held-out rays are (o, d) of 10 poses at
+    200x200)."""
     dev = torch.device("cuda")
     gt = synth.blob_scene(reso, n_blobs, occupancy, seed, device=dev)
     gt_grid = Grid.from_mask(gt.mask, reso, gt.density, gt.sh)
@@ -437,10 +397,8 @@ def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512
     htgt = render_rays(gt_grid, ho, hd)
     del gt_grid
     # the trained grids start from the ground-truth occupancy with perturbed values
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(seed + 1000)
-    dens = gt.density * (0.5 + torch.rand(gt.n_vox, device=dev, generator=gen))
-    sh = gt.sh + 0.05 * torch.randn(gt.n_vox, 27, device=dev, generator=gen)
+    init = synth.perturbed(gt, seed=seed + 1000, device=dev)
+    dens, sh = init.density, init.sh
     out = {"scene": f"{reso[0]}^3 blobs at {occupancy:.0%} occupancy", "steps": steps,
            "batch_rays": batch, "heldout": "10 poses at 200x200", "runs": {}}
     renders = {}
@@ -460,6 +418,8 @@ def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512
                              "wall_s": round(wall, 1)}
         log(f"drift {name}: PSNR {p0:.2f} -> {out['runs'][name]['psnr_heldout']:.2f}, "
             f"{ms:.3f} ms/step")
+        if on_final is not None:
+            on_final(name, grid, (ho, hd))
         del grid, trainer, sampler
         torch.cuda.empty_cache()
     for name in ("bf16", "f16"):
@@ -470,42 +430,9 @@ def precision_drift(steps: int = 2000, batch: int = 1 << 20, reso=(512, 512, 512
     return out
 
 
-def serving_sweep(settings=((1, 32), (2, 32), (4, 32), (8, 32), (4, 8), (4, 64)), n_sat: int = 300,
-                  n_load: int = 600, log=print) -> dict:
-    """Saturation rate and 80%-load latency of the view server per (streams,
-    requests per launch) setting, on 8 resident scenes."""
-    from .serve import Server, random_requests, run_load
-    scenes = []
-    for i, seed in enumerate(range(3, 11)):
-        reso = (256,) * 3 if i < 4 else (512,) * 3
-        occ = 0.05 + 0.05 * (i % 4) / 3.0
-        sv = synth.blob_scene(reso, 32, occ, seed, device="cuda")
-        scenes.append(Grid.from_mask(sv.mask, reso, sv.density, sv.sh, sh_dtype=B.PLX_F16))
-        del sv
-    torch.cuda.synchronize()
-    out = {"scenes": "4x256^3 + 4x512^3, 5-10% occupancy, FP16 SH", "runs": []}
-    for ns, mb in settings:
-        srv = Server(scenes, hbm_budget=1 << 30, n_streams=ns, max_batch=mb, keep_outputs=False)
-        run_load(srv, random_requests(16, 8, seed=99), None)  # warm-up
-        reqs = random_requests(n_sat, 8, seed=100)
-        _, wall = run_load(srv, reqs, None)
-        pix = sum(r.n_pixels for r in reqs)
-        sat = n_sat / wall
-        lat, _ = run_load(srv, random_requests(n_load, 8, seed=180), sat * 0.8, seed=7)
-        r = {"streams": ns, "max_batch": mb, "saturation_requests_s": round(sat, 1),
-             "saturation_mrays_s": round(pix / wall / 1e6, 1),
-             "p50_ms_at_80": round(float(np.percentile(lat, 50)) * 1e3, 2),
-             "p99_ms_at_80": round(float(np.percentile(lat, 99)) * 1e3, 2)}
-        log(f"serving streams={ns} max_batch={mb}: {r}")
-        out["runs"].append(r)
-        del srv
-    return out
-
-
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360", "bg_kernels",
-                                    "serving_sweep"])
+    ap.add_argument("run", choices=["coarse_to_fine", "drift", "forward_facing", "unbounded_360"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--prune", choices=["density", "weight"], default="density")
     ap.add_argument("--prune-thresh", type=float, default=None)
@@ -517,10 +444,6 @@ def main(argv=None):
         s = args.steps or 300
         res = coarse_to_fine(steps_coarse=s, steps_fine=s, prune=args.prune,
                              prune_thresh=args.prune_thresh, log=log)
-    elif args.run == "bg_kernels":
-        res = bg_kernels(log=log)
-    elif args.run == "serving_sweep":
-        res = serving_sweep(log=log)
     elif args.run == "unbounded_360":
         s = args.steps or 300
         res = unbounded_360(steps_coarse=s, steps_fine=s, log=log,

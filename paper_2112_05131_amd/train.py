@@ -92,6 +92,32 @@ class RaySampler:
         return self.o[ids], self.d[ids], self.t[ids]
 
 
+class StepEvents:
+    """Device events around the calls of one training step (timing only):
+    the binning of its batch (on the stream that made the bins), the four
+    events the fused render call records between its kernels (before the
+    segment forward, after it, after the per-ray combine, after the segment
+    backward), and the ends of TV and of RMSProp."""
+
+    def __init__(self):
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        self.bins = [ev(), ev()]
+        self.render = [ev() for _ in range(4)]
+        self.tv = ev()
+        self.rmsprop = ev()
+        self.binned = False
+
+    def durations(self) -> dict:
+        """Milliseconds of each part (after a synchronisation)."""
+        r = self.render
+        out = {"seg_fwd": r[0].elapsed_time(r[1]), "seg_combine": r[1].elapsed_time(r[2]),
+               "seg_bwd": r[2].elapsed_time(r[3]), "render_train": r[0].elapsed_time(r[3]),
+               "tv": r[3].elapsed_time(self.tv), "rmsprop": self.tv.elapsed_time(self.rmsprop)}
+        if self.binned:
+            out["bins"] = self.bins[0].elapsed_time(self.bins[1])
+        return out
+
+
 class Trainer:
     """Holds the optimiser state of one grid (and of an optional MSI
     background grid) and runs training steps."""
@@ -155,17 +181,19 @@ class Trainer:
         start = int(self.rng.integers(0, n))
         return start, count
 
-    def step(self, rays_o, rays_d, target, tv: bool = True, rgb_out=None, bins=None):
+    def step(self, rays_o, rays_d, target, tv: bool = True, rgb_out=None, bins=None,
+             events: StepEvents | None = None):
         """One optimisation step on a ray batch (all device tensors).  bins:
         the batch's segment lists (binding.make_bins), made here when not
-        given."""
+        given; events: recorded around the step's calls when given."""
         c, g = self.cfg, self.grid
         lr_s, lr_h = self.learning_rates()
         n = rays_o.shape[0]
+        rev = events.render if events is not None else None
         if self.bg is None:
             B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
                                self.touched, self.loss_sum, rgb_out, c.background, self.priors(),
-                               bins=bins)
+                               bins=bins, events=rev)
         else:
             # background colours -> fused foreground step (which hands back
             # their gradient) -> background gradient
@@ -173,15 +201,19 @@ class Trainer:
             B.plx_bg_render_fwd(self.bg.desc(), rays_o, rays_d, cbg, None, c.bg_background)
             B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
                                self.touched, self.loss_sum, rgb_out, cbg, self.priors(), gbg,
-                               bins=bins)
+                               bins=bins, events=rev)
             B.plx_bg_render_bwd(self.bg.desc(), rays_o, rays_d, gbg, self.bg_grad, self.bg_touched,
                                 c.bg_background)
         if tv and (c.lambda_tv_sigma > 0 or c.lambda_tv_sh > 0):
             start, count = self.tv_segment()
             B.plx_tv_grad(g.desc(), start, count, c.lambda_tv_sigma, c.lambda_tv_sh, c.tv_eps,
                           self.grad, self.touched, self.tv_loss_sum)
+        if events is not None:
+            events.tv.record()
         B.plx_rmsprop_step(g.desc(), g.master, self.vstate, self.grad, self.touched, lr_s, lr_h,
                            c.beta, c.eps)
+        if events is not None:
+            events.rmsprop.record()
         if self.bg is not None:
             if tv and (c.lambda_tv_bg_sigma > 0 or c.lambda_tv_bg_color > 0):
                 nb = self.bg.n_cells
@@ -195,7 +227,8 @@ class Trainer:
                                c.beta, c.eps)
         self.step_id += 1
 
-    def run(self, sampler: RaySampler, n_steps: int, overlap: bool = True, tv: bool = True):
+    def run(self, sampler: RaySampler, n_steps: int, overlap: bool = True, tv: bool = True,
+            events: list | None = None):
         """n_steps optimisation steps on consecutive batches of the sampler.
 
         With overlap, batch t+1 is gathered and binned on a second stream
@@ -204,32 +237,40 @@ class Trainer:
         synchronising call (the segment count) then waits for that stream
         alone, so the device never idles on it.  The two sets of bin buffers
         alternate; a set is refilled only after the step that used it has
-        finished."""
+        finished.  events: a list that gets one StepEvents per step."""
         main = torch.cuda.current_stream()
         side = torch.cuda.Stream(device=self.grid.device) if overlap else main
         bufs = [[None, None], [None, None]]
         done = [None, None]
 
         def prepare(slot):
+            se = StepEvents() if events is not None else None
             with torch.cuda.stream(side):
                 if done[slot] is not None:
                     side.wait_event(done[slot])
+                if se is not None:
+                    se.bins[0].record(side)
                 o, d, t = sampler.next_batch()
                 b = B.make_bins(self.grid.desc(), o, d, bufs[slot][0], bufs[slot][1])
                 bufs[slot] = [b.ray_buf, b.seg_buf]
+                if se is not None:
+                    se.bins[1].record(side)
+                    se.binned = True
                 ev = torch.cuda.Event()
                 ev.record(side)
-            return o, d, t, b, ev
+            return o, d, t, b, ev, se
 
         nxt = prepare(0)
         for i in range(n_steps):
-            o, d, t, b, ev = nxt
+            o, d, t, b, ev, se = nxt
             if side is not main:
                 main.wait_event(ev)
                 for x in (o, d, t, b.ray_buf, b.seg_buf):
                     if x is not None:
                         x.record_stream(main)
-            self.step(o, d, t, tv=tv, bins=b)
+            self.step(o, d, t, tv=tv, bins=b, events=se)
+            if events is not None:
+                events.append(se)
             ev_done = torch.cuda.Event()
             ev_done.record(main)
             done[i % 2] = ev_done

@@ -320,6 +320,31 @@ def test_relu_kinks_have_zero_derivative():
     assert np.all(gs[:, 0:9] == 0.0) and np.any(gs[:, 9:18] != 0.0)
 
 
+def test_gradient_sums_do_not_depend_on_thread_count():
+    # the gradient and its mass are summed in a fixed order (block order of
+    # the rays), so one thread and all threads give the same bits, and a
+    # second run repeats them
+    sv = synth.dense_random((14, 12, 13), seed=26, occupancy=0.5)
+    g = oracle_grid(sv)
+    o, d = synth.random_rays(3000, seed=27)
+    G = np.random.default_rng(28).normal(size=(3000, 3))
+    n0 = O.max_threads()
+    try:
+        O.set_threads(1)
+        a = O.render_bwd(g, o.numpy(), d.numpy(), G)
+        ma = O.render_bwd_mass(g, o.numpy(), d.numpy(), np.abs(G))
+        O.set_threads(max(n0, 3))
+        b = O.render_bwd(g, o.numpy(), d.numpy(), G)
+        c = O.render_bwd(g, o.numpy(), d.numpy(), G)
+        mb = O.render_bwd_mass(g, o.numpy(), d.numpy(), np.abs(G))
+    finally:
+        O.set_threads(n0)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(y, z)
+    for x, y in zip(ma, mb):
+        assert np.array_equal(x, y)
+
+
 # ----------------------------------------------------------------------------
 # Total variation (Sec. 3.5 and supplement B.1)
 
