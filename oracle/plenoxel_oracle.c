@@ -692,21 +692,27 @@ int orc_ray_extent(const int32_t reso[3], const float scale[3],
 /* ------------------------------------------------------------------------ */
 /* Deterministic accumulation of per-voxel sums over rays.
  *
- * The rays are taken in fixed blocks of ORC_RAY_BLOCK consecutive rays.  A
- * block's terms are summed, ray after ray and sample after sample, into a
- * private sparse accumulator (a slot per voxel it touches, in first-touch
- * order); the blocks' partial sums are then added into the output arrays in
- * block order.  Every voxel's sum is therefore formed in one fixed order,
- * whatever the number of threads or their scheduling, and the results are
- * the same bits from run to run.  OpenMP only runs several blocks at once. */
-#define ORC_RAY_BLOCK 1024
+ * Each ray's terms are first summed per voxel, sample after sample, in a
+ * private sparse accumulator (a slot per voxel the ray touches); the rays'
+ * sums are then added into the output arrays in ray order.  Every voxel's
+ * sum is therefore formed in one fixed order -- per ray in sample order,
+ * then over the rays in batch order -- whatever the number of threads or
+ * their scheduling, and the results are the same bits from run to run.
+ * OpenMP runs the rays of a wave of ORC_RAY_WAVE rays in parallel (each
+ * thread appends its rays' sums to its own arena), then adds the wave into
+ * the outputs with the voxels split among the threads. */
+#define ORC_RAY_WAVE 8192
 #define ORC_ACC_W (ORC_NSH + 1) /* 27 SH values, then sigma */
 
 typedef struct {
-    int32_t *slot;   /* [M]: slot of a voxel in this block, -1 if none */
+    int32_t *slot;   /* [M]: row of a voxel for the current ray, -1 if none */
     int64_t *ids;    /* voxels in first-touch order */
     double *val;     /* [n][ORC_ACC_W] */
     int64_t n, cap;
+    /* arena of finished rays' rows for the current wave */
+    int64_t *a_ids;
+    double *a_val;
+    int64_t a_n, a_cap;
 } sparse_acc;
 
 static void acc_init(sparse_acc *a, int64_t n_vox)
@@ -717,6 +723,10 @@ static void acc_init(sparse_acc *a, int64_t n_vox)
     a->n = 0;
     a->ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)a->cap);
     a->val = (double *)malloc(sizeof(double) * ORC_ACC_W * (size_t)a->cap);
+    a->a_cap = 4096;
+    a->a_n = 0;
+    a->a_ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)a->a_cap);
+    a->a_val = (double *)malloc(sizeof(double) * ORC_ACC_W * (size_t)a->a_cap);
 }
 
 static void acc_free(sparse_acc *a)
@@ -724,9 +734,11 @@ static void acc_free(sparse_acc *a)
     free(a->slot);
     free(a->ids);
     free(a->val);
+    free(a->a_ids);
+    free(a->a_val);
 }
 
-/* Row of voxel id, created (zeroed) on first touch. */
+/* Row of voxel id for the current ray, created (zeroed) on first touch. */
 static double *acc_row(sparse_acc *a, int64_t id)
 {
     int32_t k = a->slot[id];
@@ -744,47 +756,75 @@ static double *acc_row(sparse_acc *a, int64_t id)
     return a->val + (size_t)k * ORC_ACC_W;
 }
 
-/* Adds a block's sums into out_density[M] / out_sh[M*27] (and marks
- * touched[M] when given), then empties the accumulator. */
-static void acc_flush(sparse_acc *a, double *out_density, double *out_sh, uint8_t *touched)
+/* Moves the current ray's rows to the arena; returns their first arena row. */
+static int64_t acc_finish_ray(sparse_acc *a)
 {
-    for (int64_t k = 0; k < a->n; ++k) {
-        const int64_t id = a->ids[k];
-        const double *v = a->val + (size_t)k * ORC_ACC_W;
-        for (int q = 0; q < ORC_NSH; ++q) out_sh[id * ORC_NSH + q] += v[q];
-        out_density[id] += v[ORC_NSH];
-        if (touched) touched[id] = 1;
-        a->slot[id] = -1;
+    const int64_t first = a->a_n;
+    if (a->a_n + a->n > a->a_cap) {
+        while (a->a_n + a->n > a->a_cap) a->a_cap *= 2;
+        a->a_ids = (int64_t *)realloc(a->a_ids, sizeof(int64_t) * (size_t)a->a_cap);
+        a->a_val = (double *)realloc(a->a_val, sizeof(double) * ORC_ACC_W * (size_t)a->a_cap);
     }
+    memcpy(a->a_ids + a->a_n, a->ids, sizeof(int64_t) * (size_t)a->n);
+    memcpy(a->a_val + (size_t)a->a_n * ORC_ACC_W, a->val, sizeof(double) * ORC_ACC_W * (size_t)a->n);
+    a->a_n += a->n;
+    for (int64_t k = 0; k < a->n; ++k) a->slot[a->ids[k]] = -1;
     a->n = 0;
+    return first;
 }
 
 typedef void (*ray_body_fn)(const void *ctx, int64_t r, sparse_acc *acc);
 
-/* Runs body over every ray, block by block, and adds the block sums into the
- * outputs in block order (see above). */
+/* Runs body over every ray and adds the rays' per-voxel sums into the
+ * outputs in ray order (see above). */
 static void accumulate_over_rays(int64_t n_rays, int64_t n_vox, ray_body_fn body, const void *ctx,
                                  double *out_density, double *out_sh, uint8_t *touched)
 {
-    const int64_t n_blocks = (n_rays + ORC_RAY_BLOCK - 1) / ORC_RAY_BLOCK;
     int n_thr = 1;
 #ifdef _OPENMP
     n_thr = omp_get_max_threads();
 #endif
     sparse_acc *acc = (sparse_acc *)malloc(sizeof(sparse_acc) * (size_t)n_thr);
     for (int t = 0; t < n_thr; ++t) acc_init(&acc[t], n_vox);
-    for (int64_t b0 = 0; b0 < n_blocks; b0 += n_thr) {
-        /* blocks b0 .. b0 + n_thr - 1, one per accumulator */
-#pragma omp parallel for schedule(static, 1)
-        for (int t = 0; t < n_thr; ++t) {
-            const int64_t b = b0 + t;
-            if (b >= n_blocks) continue;
-            const int64_t r1 = (b + 1) * ORC_RAY_BLOCK < n_rays ? (b + 1) * ORC_RAY_BLOCK : n_rays;
-            for (int64_t r = b * ORC_RAY_BLOCK; r < r1; ++r) body(ctx, r, &acc[t]);
+    /* per ray of a wave: arena (thread), first row, row count */
+    int32_t *r_thr = (int32_t *)malloc(sizeof(int32_t) * ORC_RAY_WAVE);
+    int64_t *r_first = (int64_t *)malloc(sizeof(int64_t) * ORC_RAY_WAVE);
+    int64_t *r_cnt = (int64_t *)malloc(sizeof(int64_t) * ORC_RAY_WAVE);
+    for (int64_t w0 = 0; w0 < n_rays; w0 += ORC_RAY_WAVE) {
+        const int64_t nw = n_rays - w0 < ORC_RAY_WAVE ? n_rays - w0 : ORC_RAY_WAVE;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nw; ++i) {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#endif
+            body(ctx, w0 + i, &acc[t]);
+            r_thr[i] = t;
+            const int64_t cnt = acc[t].n;
+            r_first[i] = acc_finish_ray(&acc[t]);
+            r_cnt[i] = cnt;
         }
-        for (int t = 0; t < n_thr && b0 + t < n_blocks; ++t)
-            acc_flush(&acc[t], out_density, out_sh, touched);
+        /* the wave's rays in ray order; each thread adds the rows of its
+         * own share of the voxels */
+#pragma omp parallel for schedule(static, 1)
+        for (int part = 0; part < n_thr; ++part) {
+            for (int64_t i = 0; i < nw; ++i) {
+                const sparse_acc *a = &acc[r_thr[i]];
+                for (int64_t k = r_first[i]; k < r_first[i] + r_cnt[i]; ++k) {
+                    const int64_t id = a->a_ids[k];
+                    if (id % n_thr != part) continue;
+                    const double *v = a->a_val + (size_t)k * ORC_ACC_W;
+                    for (int q = 0; q < ORC_NSH; ++q) out_sh[id * ORC_NSH + q] += v[q];
+                    out_density[id] += v[ORC_NSH];
+                    if (touched) touched[id] = 1;
+                }
+            }
+        }
+        for (int t = 0; t < n_thr; ++t) acc[t].a_n = 0;
     }
+    free(r_thr);
+    free(r_first);
+    free(r_cnt);
     for (int t = 0; t < n_thr; ++t) acc_free(&acc[t]);
     free(acc);
 }
