@@ -444,6 +444,25 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
                      const plx_bins *bins, float loss_scale, float *rgb_out, float *grad,
                      uint8_t *touched, double *loss_sum, plx_stream stream);
 
+/* plx_render_train for callers that cannot allocate device memory or
+ * synchronise (code under graph capture, tight serving or training loops):
+ * the same fused forward, MSE and backward, with the same arguments and
+ * results, but no plx_bins: the segment lists are built inside the call in a
+ * fixed scratch array of the library's own (64 MiB per device, kept until
+ * the process ends), sized for the worst case of n_rays * (Bx + By + Bz)
+ * segments (Ba = bricks per axis, plx_occ_words), and the segment kernels
+ * read the true count on the device.  A batch whose ray buffer
+ * (plx_bins_ray_bytes) plus segment buffer for that worst case
+ * (plx_bins_seg_bytes) exceeds 64 MiB is refused with PLX_ENOMEM before any
+ * launch: up to 12,532 rays on a 256^3 grid, 3,350 on 512^3.
+ * Never allocates or synchronises.  Every call on a device uses that
+ * device's one array, and the next call overwrites it: calls that overlap
+ * on one device (other streams, other threads) race; order them. */
+int plx_render_train_static(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                            const float *rays_d, const float *target, int64_t n_rays,
+                            float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
+                            double *loss_sum, plx_stream stream);
+
 /* Per-voxel maximum sample weight, the statistic of pruning by weight
  * (Sec. 3.4, the method of PlenOctrees).  Sample k of a ray has the weight
  * w_k = T_k (1 - exp(-sigma_k delta_k)) that Eq. (1) gives its colour, with

@@ -142,6 +142,7 @@ _SIGS = {
     "plx_render_bwd": ([_GP, _OP, _P, _P, _I64, _BP, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_train": ([_GP, _OP, _P, _P, _P, _I64, _BP, _F, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_max_weight": ([_GP, _P, _P, _I64, _BP, _P, _P], ctypes.c_int),
+    "plx_render_train_static": ([_GP, _OP, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_render_state_bytes": ([_I64, _I32], _I64),
     "plx_render_fwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P], ctypes.c_int),
     "plx_render_bwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P],
@@ -521,6 +522,24 @@ def plx_render_train(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touch
                                   _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
                                   _dptr(touched, "touched", torch.uint8),
                                   _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
+
+
+def plx_render_train_static(g: PlxGrid, rays_o, rays_d, target, loss_scale, grad, touched, loss_sum,
+                            rgb_out=None, bg=(1.0, 1.0, 1.0), priors: Priors | None = None,
+                            grad_bg=None, events=None):
+    """plx_render_train with the segment lists in the library's fixed
+    scratch: allocates nothing and never synchronises (PlxError with code
+    PLX_ENOMEM when the batch does not fit the scratch)."""
+    n = rays_o.shape[0]
+    o = _opts(bg, priors, n, grad_bg, events)
+    _check(lib().plx_render_train_static(ctypes.byref(g), ctypes.byref(o),
+                                         _dptr(rays_o, "rays_o", torch.float32, 3 * n),
+                                         _dptr(rays_d, "rays_d", torch.float32, 3 * n),
+                                         _dptr(target, "target", torch.float32, 3 * n), n,
+                                         float(loss_scale), _dptr(rgb_out, "rgb_out", torch.float32, 3 * n),
+                                         _dptr(grad, "grad", torch.float32, REC_SLOTS * g.n_vox),
+                                         _dptr(touched, "touched", torch.uint8),
+                                         _dptr(loss_sum, "loss_sum", torch.float64, 1), _stream()))
 
 
 def plx_render_state_bytes(n_rays: int, cap: int) -> int:

@@ -52,6 +52,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "plx_internal.hpp"
@@ -983,6 +984,7 @@ struct BinArgs {
     unsigned *status;    // set to 1 when the emitting walk disagrees with the counting walk
     const int64_t *n_seg_dev;  // when set, the segment count is read here instead of n_seg
     void **events;       // optional hipEvent_t[4] recorded between the render kernels
+    int64_t seg_cap;     // segment records the segment buffer holds
     Priors pri;
     float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
@@ -990,7 +992,7 @@ struct BinArgs {
 // Number of segments of the call: the host's count, or the device copy when
 // the launch was sized by a bound instead.
 __device__ __forceinline__ int64_t seg_count_of(const BinArgs &a) {
-    return a.n_seg_dev ? *a.n_seg_dev : a.n_seg;
+    return a.n_seg_dev ? min(*a.n_seg_dev, a.n_seg) : a.n_seg;
 }
 
 // A segment record with its ray and slot inside the call's arrays.  The emit
@@ -1072,7 +1074,9 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
         const int64_t bin = seg_bin(bid, k0, k1);
         const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
         // positions and slots stay inside the ranges the count reserved
-        if (pos < a.boff[bin + 1] && slot < slot_end) a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
+        // and inside the segment buffer
+        if (pos < a.boff[bin + 1] && slot < slot_end && pos < a.seg_cap && slot < a.seg_cap)
+            a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
         else bad = true;
         ++slot;
     });
@@ -1172,7 +1176,7 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
     double l2 = 0.0, lb = 0.0;
     if constexpr (MODE == MODE_MAXW) {
         if (ray < a.n_rays) {
-            const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
+            const int64_t s0 = a.seg_off[ray], s1 = min(a.seg_off[ray + 1], a.seg_cap);
             double tau = 0.0;
             for (int64_t s = s0; s < s1; s += kSegU) {
                 double ts[kSegU];
@@ -1190,7 +1194,7 @@ __global__ __launch_bounds__(kThreads) void seg_combine_kernel(BinArgs a) {
         return;
     }
     if (ray < a.n_rays) {
-        const int64_t s0 = a.seg_off[ray], s1 = a.seg_off[ray + 1];
+        const int64_t s0 = a.seg_off[ray], s1 = min(a.seg_off[ray + 1], a.seg_cap);
         double tau = 0.0;
         float C[3] = {0.0f, 0.0f, 0.0f};
         for (int64_t s = s0; s < s1; s += kSegU) {
@@ -1794,6 +1798,7 @@ int attach_bins(const plx_grid *grid, const plx_bins *bins, int64_t n_rays, BinA
     if (rc) return rc;
     attach_ray_buf(a, bins->ray_buf, rl);
     a.n_seg = bins->n_seg;
+    a.seg_cap = bins->n_seg;
     if (bins->n_seg > 0) {
         const SegBufLayout sl = seg_buf_layout(bins->n_seg);
         if ((rc = check_buf(bins->seg_buf, bins->seg_buf_bytes, sl.bytes, "bins->seg_buf", fn))) return rc;
@@ -1891,6 +1896,44 @@ RenderArgs base_args(const plx_render_opts *opts, const float *o, const float *d
     a.bg_rgb = opts->background_rgb;
     a.grad_bg = opts->grad_background;
     return a;
+}
+
+// ------------------------------------------------------------ fixed scratch
+//
+// plx_render_train_static serves callers that cannot allocate (code under
+// graph capture, serving loops): its segment lists live in a fixed device
+// array instead of caller buffers, sized for the worst case of the batch
+// (every ray crossing the most bricks a line can cross), and the segment
+// kernels read the true segment count on the device, so the call neither
+// allocates nor synchronises.  The array is per device and kept until the
+// process ends; calls that overlap on one device share it and race.
+constexpr int64_t kStaticScratchBytes = (int64_t)64 << 20;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Device address of this device's fixed scratch, looked up once per device
+// (the array's name is a host-side stand-in, never passed to a kernel).
+int static_scratch(void **out, const char *fn) {
+    int dev = 0;
+    PLX_CHECK_HIP(hipGetDevice(&dev), fn);
+    if (dev < 0 || dev >= kMaxDevices) return fail(PLX_EDEVICE, "%s: device %d out of range", fn, dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        PLX_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), fn);
+        if (!p) return fail(PLX_EDEVICE, "%s: no address for the fixed scratch", fn);
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return PLX_OK;
 }
 
 }  // namespace
@@ -2072,6 +2115,63 @@ int plx_render_train(const plx_grid *grid, const plx_render_opts *opts, const fl
     a.grad_bg = opts->grad_background;
     a.loss_scale = loss_scale;
     return render_binned<MODE_TRAIN>(grid, a, as_stream(stream), fn);
+}
+
+int plx_render_train_static(const plx_grid *grid, const plx_render_opts *opts, const float *rays_o,
+                            const float *rays_d, const float *target, int64_t n_rays,
+                            float loss_scale, float *rgb_out, float *grad, uint8_t *touched,
+                            double *loss_sum, plx_stream stream) {
+    const char *fn = "plx_render_train_static";
+    int rc = validate_grid(grid, true, fn);
+    if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
+    if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
+    if (n_rays == 0) return PLX_OK;
+    if (!target || !loss_sum || (grid->n_vox > 0 && (!grad || !touched)))
+        return fail(PLX_EINVAL, "%s: NULL target/grad/touched/loss_sum", fn);
+    const GridDev g = to_dev(grid);
+    const int64_t nbk = n_bins(g);
+    // a ray enters each brick at most once and a line crosses at most
+    // bx + by + bz - 2 bricks of the lattice
+    const int64_t per_ray = (int64_t)g.bx + g.by + g.bz;
+    const int64_t cap = n_rays * per_ray;
+    const RayBufLayout rl = ray_buf_layout(n_rays, nbk);
+    const SegBufLayout sl = seg_buf_layout(cap);
+    if (n_rays > kMaxRaysBinned || cap > kMaxRaysBinned || rl.bytes + sl.bytes > kStaticScratchBytes)
+        return fail(PLX_ENOMEM,
+                    "%s: %lld rays on a %dx%dx%d grid need %lld bytes of scratch, more than the fixed %lld "
+                    "(the bound is ray buffer + %lld segments per ray)",
+                    fn, (long long)n_rays, grid->reso[0], grid->reso[1], grid->reso[2],
+                    (long long)(rl.bytes + sl.bytes), (long long)kStaticScratchBytes, (long long)per_ray);
+    BinArgs a = {};
+    if ((rc = priors_from(opts, a.pri, fn))) return rc;
+    void *base = nullptr;
+    if ((rc = static_scratch(&base, fn))) return rc;
+    hipStream_t s = as_stream(stream);
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.n_rays = n_rays;
+    attach_ray_buf(a, base, rl);
+    attach_seg_buf(a, static_cast<char *>(base) + rl.bytes, sl);
+    int64_t *scan_tmp = reinterpret_cast<int64_t *>(static_cast<char *>(base) + rl.scan);
+    // counts, scans and records: the previous call's contents are cleared
+    // by the counting phase (bin counters, cursors, status)
+    if ((rc = bin_count_launch(g, a, nbk, scan_tmp, s, fn))) return rc;
+    a.n_seg = cap;  // launch bound; the kernels read the count itself
+    a.seg_cap = cap;
+    a.n_seg_dev = a.seg_off + n_rays;
+    seg_emit_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
+    if ((rc = check_launch(fn))) return rc;
+    a.events = opts->kernel_events;
+    a.target = target;
+    a.rgb_out = rgb_out;
+    a.loss_sum = loss_sum;
+    a.grad = grad;
+    a.touched = touched;
+    for (int i = 0; i < 3; ++i) a.bg[i] = opts->background[i];
+    a.bg_rgb = opts->background_rgb;
+    a.grad_bg = opts->grad_background;
+    a.loss_scale = loss_scale;
+    return render_binned<MODE_TRAIN>(grid, a, s, fn);
 }
 
 int64_t plx_render_state_bytes(int64_t n_rays, int32_t cap) {

@@ -315,3 +315,28 @@ def test_grid_workspace_validation():
                                   ctypes.byref(kept), ctypes.byref(pruned), None) == B.PLX_EINVAL
     assert L.plx_mask_count(p(0x1000), 5, p(0x100000), 255, ctypes.byref(kept), None) == B.PLX_EINVAL
     assert L.plx_touched_count(p(0x1000), 5, None, 256, ctypes.byref(kept), None) == B.PLX_EINVAL
+
+
+def test_static_training_call_refuses_batches_beyond_its_scratch():
+    """plx_render_train_static checks its fixed scratch before any launch:
+    1M rays (or 3351) on 512^3 exceed the 64 MiB worst case and
+    come back PLX_ENOMEM; bad arguments are PLX_EINVAL; zero rays are a
+    no-op."""
+    L = B.lib()
+    p = ctypes.c_void_p
+    g = _grid_desc(reso=(512, 512, 512), n_vox=100)
+    g.scale[:] = (512.0,) * 3
+    g.offset[:] = (255.5,) * 3
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+    for n in (1 << 20, 3351):
+        rc = L.plx_render_train_static(ctypes.byref(g), ctypes.byref(opts), p(0x40000), p(0x50000),
+                                       p(0x60000), n, 1.0, None, p(0x70000), p(0x80000), p(0x90000), None)
+        assert rc == B.PLX_ENOMEM, n
+        assert "scratch" in L.plx_last_error().decode()
+    # a bound that fits needs no device until the launch: the size check is
+    # the only thing that depends on n (NULL target is refused first)
+    assert L.plx_render_train_static(ctypes.byref(g), ctypes.byref(opts), p(0x40000), p(0x50000), None,
+                                     100, 1.0, None, p(0x70000), p(0x80000), p(0x90000),
+                                     None) == B.PLX_EINVAL
+    assert L.plx_render_train_static(ctypes.byref(g), ctypes.byref(opts), None, None, None, 0, 1.0, None,
+                                     None, None, None, None) == B.PLX_OK
