@@ -361,43 +361,64 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
  * voxel values), so one set serves every render call on those rays until the
  * occupancy is rebuilt.
  *
- * Two phases, both on caller-owned device buffers (256-byte aligned):
+ * Two phases, on caller-owned device buffers (each 256-byte aligned):
  *  1. plx_bins_count fills the ray buffer (plx_bins_ray_bytes(reso, n_rays)
- *     bytes: per-ray and per-bin counts and offsets, scan temporaries, a
- *     status word) and returns the number of segments.  Synchronising.
- *  2. plx_bins_apply writes the bin-major segment records into the segment
- *     buffer (plx_bins_seg_bytes(n_seg) bytes).  Asynchronous.
- * The render calls then use both buffers as their scratch (per-ray and
+ *     bytes: per-ray and per-bin counts and offsets, per-bin sample counts,
+ *     the list of bricks with segments, scan temporaries, a status word) and
+ *     the descriptor's counts: n_seg segments, n_samp sample slots (the
+ *     samples of all segments, occupied or not) and n_brick bricks with
+ *     segments.  Synchronising.
+ *  2. The caller attaches a segment buffer of plx_bins_seg_bytes(n_seg)
+ *     bytes and, optionally, a sample buffer of
+ *     plx_bins_samp_bytes(n_seg, n_samp) bytes; plx_bins_apply writes the
+ *     bin-major segment records (and the segments' sample slots).
+ *     Asynchronous.
+ * With a sample buffer the backward pass of plx_render_bwd/plx_render_train
+ * is the recorded one: the replay stores each occupied sample's position
+ * and gradients (32 B) in the sample buffer and a second kernel sums them
+ * per voxel, one brick per workgroup, so each voxel receives one line of
+ * FP32 atomics per brick instead of one per segment (same terms, other
+ * order of the additions).  Without one (samp_buf NULL) the replay
+ * scatters its gradients itself.
+ * The render calls use the buffers as their scratch (per-ray and
  * per-segment values passed between their kernels), so render calls that
  * share one plx_bins must be ordered on a stream; counting the next batch
  * into other buffers may overlap them.  plx_bins_verify (synchronising)
  * reports whether the emitting walk of plx_bins_apply met a segment the
  * count did not reserve (never expected: both walks run the same FP32
  * recipe; such a segment is dropped rather than written out of range).
- * Limits: n_rays and n_seg below 2^31 - 256. */
+ * Limits: n_rays and n_seg below 2^31 - 256, n_samp at most 2^40. */
 typedef struct plx_bins {
     int64_t n_rays;        /* rays the lists were made for */
-    int64_t n_seg;         /* segments (plx_bins_count's result) */
+    int64_t n_seg;         /* segments */
+    int64_t n_samp;        /* sample slots of the segments */
+    int64_t n_brick;       /* bricks with segments */
     void *ray_buf;         /* device, ray_buf_bytes */
     int64_t ray_buf_bytes;
     void *seg_buf;         /* device, seg_buf_bytes (may be NULL when n_seg == 0) */
     int64_t seg_buf_bytes;
+    void *samp_buf;        /* device, samp_buf_bytes, or NULL (optional) */
+    int64_t samp_buf_bytes;
 } plx_bins;
 
-/* Bytes of the ray buffer for n_rays rays on a grid of resolution reso, and
- * of the segment buffer for n_seg segments (0 for bad arguments). */
+/* Bytes of the ray buffer for n_rays rays on a grid of resolution reso, of
+ * the segment buffer for n_seg segments, and of the sample buffer for n_seg
+ * segments with n_samp sample slots (0 for bad arguments). */
 int64_t plx_bins_ray_bytes(const int32_t reso[3], int64_t n_rays);
 int64_t plx_bins_seg_bytes(int64_t n_seg);
+int64_t plx_bins_samp_bytes(int64_t n_seg, int64_t n_samp);
 
 /* Phase 1: counts the segments of the rays (rays_o/rays_d: device float32
- * [n_rays][3]) into ray_buf and returns their number in *n_seg (host).
- * Synchronising (waits for `stream`). */
+ * [n_rays][3]) into ray_buf and sets *bins to the rays, the ray buffer and
+ * the three counts (segment and sample buffers NULL).  Synchronising (waits
+ * for `stream`). */
 int plx_bins_count(const plx_grid *grid, const float *rays_o, const float *rays_d, int64_t n_rays,
-                   void *ray_buf, int64_t ray_buf_bytes, int64_t *n_seg, plx_stream stream);
+                   void *ray_buf, int64_t ray_buf_bytes, plx_bins *bins, plx_stream stream);
 
 /* Phase 2: writes the segment records of bins->n_rays rays (the same rays and
- * grid as phase 1; bins->ray_buf as filled by it, bins->n_seg its result)
- * into bins->seg_buf.  Asynchronous. */
+ * grid as phase 1; bins as filled by it, with seg_buf and optionally
+ * samp_buf attached) into bins->seg_buf, and their sample slots into
+ * bins->samp_buf.  Asynchronous. */
 int plx_bins_apply(const plx_grid *grid, const float *rays_o, const float *rays_d,
                    const plx_bins *bins, plx_stream stream);
 

@@ -79,10 +79,14 @@ class PlxBins(ctypes.Structure):
     _fields_ = [
         ("n_rays", ctypes.c_int64),
         ("n_seg", ctypes.c_int64),
+        ("n_samp", ctypes.c_int64),
+        ("n_brick", ctypes.c_int64),
         ("ray_buf", ctypes.c_void_p),
         ("ray_buf_bytes", ctypes.c_int64),
         ("seg_buf", ctypes.c_void_p),
         ("seg_buf_bytes", ctypes.c_int64),
+        ("samp_buf", ctypes.c_void_p),
+        ("samp_buf_bytes", ctypes.c_int64),
     ]
 
 
@@ -135,6 +139,7 @@ _SIGS = {
     "plx_bg_render_bwd": ([_GP, _P, _P, _I64, _P, _P, _P, _P, _P], ctypes.c_int),
     "plx_bins_ray_bytes": ([_P, _I64], _I64),
     "plx_bins_seg_bytes": ([_I64], _I64),
+    "plx_bins_samp_bytes": ([_I64, _I64], _I64),
     "plx_bins_count": ([_GP, _P, _P, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "plx_bins_apply": ([_GP, _P, _P, _BP, _P], ctypes.c_int),
     "plx_bins_verify": ([_GP, _BP, _P], ctypes.c_int),
@@ -408,16 +413,22 @@ def plx_bg_render_bwd(g: PlxGrid, rays_o, rays_d, grad_rgb, grad, touched, bg=(1
 
 
 class Bins:
-    """Caller-owned segment lists of one ray batch (plx_bins): the two device
+    """Caller-owned segment lists of one ray batch (plx_bins): the device
     buffers and their descriptor.  Made by make_bins (count, then apply);
     serves every render call on the same rays until the grid's occupancy is
     rebuilt."""
 
-    def __init__(self, n_rays: int, n_seg: int, ray_buf: torch.Tensor, seg_buf: torch.Tensor | None):
-        self.ray_buf, self.seg_buf = ray_buf, seg_buf
-        self.desc = PlxBins(int(n_rays), int(n_seg), ray_buf.data_ptr(), ray_buf.numel(),
-                            seg_buf.data_ptr() if seg_buf is not None and seg_buf.numel() else None,
-                            seg_buf.numel() if seg_buf is not None else 0)
+    def __init__(self, desc: PlxBins, ray_buf: torch.Tensor, seg_buf: torch.Tensor | None,
+                 samp_buf: torch.Tensor | None = None):
+        self.ray_buf, self.seg_buf, self.samp_buf = ray_buf, seg_buf, samp_buf
+        self.desc = desc
+        desc.ray_buf, desc.ray_buf_bytes = ray_buf.data_ptr(), ray_buf.numel()
+        has_seg = seg_buf is not None and seg_buf.numel() > 0
+        desc.seg_buf = seg_buf.data_ptr() if has_seg else None
+        desc.seg_buf_bytes = seg_buf.numel() if has_seg else 0
+        has_samp = samp_buf is not None and samp_buf.numel() > 0
+        desc.samp_buf = samp_buf.data_ptr() if has_samp else None
+        desc.samp_buf_bytes = samp_buf.numel() if has_samp else 0
 
     @property
     def n_rays(self) -> int:
@@ -426,6 +437,17 @@ class Bins:
     @property
     def n_seg(self) -> int:
         return int(self.desc.n_seg)
+
+    @property
+    def n_samp(self) -> int:
+        return int(self.desc.n_samp)
+
+    @property
+    def n_brick(self) -> int:
+        return int(self.desc.n_brick)
+
+    def buffers(self):
+        return [self.ray_buf, self.seg_buf, self.samp_buf]
 
 
 def plx_bins_ray_bytes(reso, n_rays: int) -> int:
@@ -436,14 +458,19 @@ def plx_bins_seg_bytes(n_seg: int) -> int:
     return int(lib().plx_bins_seg_bytes(int(n_seg)))
 
 
-def plx_bins_count(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor) -> int:
+def plx_bins_samp_bytes(n_seg: int, n_samp: int) -> int:
+    return int(lib().plx_bins_samp_bytes(int(n_seg), int(n_samp)))
+
+
+def plx_bins_count(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor) -> PlxBins:
+    """Phase 1: the descriptor with the rays, the ray buffer and the counts."""
     n = rays_o.shape[0]
-    out = ctypes.c_int64()
+    out = PlxBins()
     _check(lib().plx_bins_count(ctypes.byref(g), _dptr(rays_o, "rays_o", torch.float32, 3 * n),
                                 _dptr(rays_d, "rays_d", torch.float32, 3 * n), n,
                                 _dptr(ray_buf, "ray_buf", torch.uint8), ray_buf.numel(),
                                 ctypes.byref(out), _stream()))
-    return int(out.value)
+    return out
 
 
 def plx_bins_apply(g: PlxGrid, rays_o, rays_d, bins: Bins):
@@ -458,19 +485,29 @@ def plx_bins_verify(g: PlxGrid, bins: Bins):
 
 
 def make_bins(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor | None = None,
-              seg_buf: torch.Tensor | None = None) -> Bins:
+              seg_buf: torch.Tensor | None = None, samp_buf: torch.Tensor | None = None,
+              samples: bool = True) -> Bins:
     """Segment lists of a ray batch: plx_bins_count then plx_bins_apply on
     the current stream, into the given buffers when they are large enough,
-    else into new ones."""
+    else into new ones.  samples: attach a sample buffer (the recorded
+    backward); without one the backward replay scatters its gradients
+    itself."""
     n = rays_o.shape[0]
     need = plx_bins_ray_bytes(tuple(g.reso), n)
     if ray_buf is None or ray_buf.numel() < need:
         ray_buf = workspace(need, rays_o.device)
-    n_seg = plx_bins_count(g, rays_o, rays_d, ray_buf)
-    sneed = plx_bins_seg_bytes(n_seg)
-    if n_seg > 0 and (seg_buf is None or seg_buf.numel() < sneed):
-        seg_buf = workspace(sneed, rays_o.device)
-    bins = Bins(n, n_seg, ray_buf, seg_buf if n_seg > 0 else None)
+    desc = plx_bins_count(g, rays_o, rays_d, ray_buf)
+    n_seg = int(desc.n_seg)
+    if n_seg > 0:
+        sneed = plx_bins_seg_bytes(n_seg)
+        if seg_buf is None or seg_buf.numel() < sneed:
+            seg_buf = workspace(sneed, rays_o.device)
+        if samples:
+            pneed = plx_bins_samp_bytes(n_seg, int(desc.n_samp))
+            if samp_buf is None or samp_buf.numel() < pneed:
+                samp_buf = workspace(pneed, rays_o.device)
+    bins = Bins(desc, ray_buf, seg_buf if n_seg > 0 else None,
+                samp_buf if n_seg > 0 and samples else None)
     plx_bins_apply(g, rays_o, rays_d, bins)
     return bins
 

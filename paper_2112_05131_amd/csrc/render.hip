@@ -952,6 +952,14 @@ __global__ void zero_u32_kernel(unsigned *p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// One sample of the sample buffer: position in its cell and the cell's
+// number inside the brick, then the sample's gradients with respect to the
+// interpolated density and the three projected colour channels.
+struct SampleRec {
+    float4 pos;   // f[0], f[1], f[2], cell (x*64 + y*8 + z) as integer bits
+    float4 grad;  // d/d(sigma), d/d(r), d/d(g), d/d(b)
+};
+
 struct BinArgs {
     const float *rays_o;
     const float *rays_d;
@@ -985,6 +993,18 @@ struct BinArgs {
     const int64_t *n_seg_dev;  // when set, the segment count is read here instead of n_seg
     void **events;       // optional hipEvent_t[4] recorded between the render kernels
     int64_t seg_cap;     // segment records the segment buffer holds
+    // per-bin sample counts and the recorded backward (NULL when the bins
+    // carry no sample buffer)
+    unsigned *bsamp;     // [n_bins] samples (k1 - k0 + 1 summed) of each bin's segments
+    unsigned *bscursor;  // [n_bins] sample placement cursors
+    int64_t *bsoff;      // [n_bins + 1] first sample slot of each bin
+    unsigned *blist;     // [n_brick] binning-order positions of the bricks with segments
+    unsigned *nbrick;    // device count of blist entries
+    int64_t n_brick;
+    int64_t *soff;       // [n_seg] bin-major: first sample slot of each segment
+    int *nocc;           // [n_seg] bin-major: occupied samples the replay recorded
+    SampleRec *srec;     // [samp_cap] sample records
+    int64_t samp_cap;
     Priors pri;
     float *wmax;         // MAXW: [M] per-voxel maximum sample weight
 };
@@ -1053,7 +1073,9 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(GridDev g, BinArgs 
     unsigned cnt = 0;
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         ++cnt;
-        atomicAdd(a.bcount + seg_bin(bid, k0, k1), 1u);
+        const int64_t bin = seg_bin(bid, k0, k1);
+        atomicAdd(a.bcount + bin, 1u);
+        if (a.bsamp) atomicAdd(a.bsamp + bin, (unsigned)(k1 - k0 + 1));
     });
     a.nseg[ray] = cnt;
 }
@@ -1075,12 +1097,35 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
         const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
         // positions and slots stay inside the ranges the count reserved
         // and inside the segment buffer
-        if (pos < a.boff[bin + 1] && slot < slot_end && pos < a.seg_cap && slot < a.seg_cap)
+        if (pos < a.boff[bin + 1] && slot < slot_end && pos < a.seg_cap && slot < a.seg_cap) {
             a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
-        else bad = true;
+            if (a.soff) {
+                // the segment's sample slots, inside its bin's and the buffer's
+                const unsigned len = (unsigned)(k1 - k0 + 1);
+                const int64_t sp = a.bsoff[bin] + atomicAdd(a.bscursor + bin, len);
+                const bool fits = sp + len <= a.bsoff[bin + 1] && sp + len <= a.samp_cap;
+                a.soff[pos] = fits ? sp : -1;
+                bad |= !fits;
+            }
+        } else {
+            bad = true;
+        }
         ++slot;
     });
     if (bad || slot != slot_end) *a.status = 1u;
+}
+
+// Appends the binning-order position of every brick with segments to
+// a.blist (one counter update per wave; the order across waves is free).
+__global__ __launch_bounds__(kThreads) void brick_list_kernel(BinArgs a, int64_t n_bricks) {
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool has = j < n_bricks && a.boff[(j + 1) * kLenClasses] > a.boff[j * kLenClasses];
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    unsigned base = 0;
+    if (lane_id() == 0) base = atomicAdd(a.nbrick, (unsigned)__popcll(m));
+    base = __shfl(base, 0);
+    if (has) a.blist[base + lanes_below(m)] = (unsigned)j;
 }
 
 // Occupied samples of [k_lo, k_hi] in increasing / decreasing order.
@@ -1373,6 +1418,311 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
         drain(qu, a.grad, a.touched);
     }
     if (CAUCHY) add_prior_loss(a.pri, ls, 0.0);
+}
+
+// ------------------------------------------------------------ recorded backward
+//
+// The scatter of seg_bwd sends about nine partial gradients to every voxel a
+// batch reaches (one per segment that has it as a corner), each a 128-B line
+// of FP32 atomics, and global atomics are the slowest path on the chip (about
+// 20G 64-byte requests per second, whatever the lanes' pattern).  The
+// recorded backward splits the work in two launches instead:
+//  1. seg_bwd_rec (lane per segment, bin order) replays the segment exactly
+//     like seg_bwd but stores, per occupied sample, its position in the cell
+//     and its four scalar gradients (32 B) in the segment's slot range of the
+//     sample buffer, with no accumulation and no atomics;
+//  2. seg_scatter (one workgroup per brick with segments) sorts the brick's
+//     samples by cell in LDS, and each lane then owns one of the brick's 9^3
+//     corner voxels and sums the contributions of the samples of the (up to)
+//     8 cells around it, so every voxel gets one 128-B line of atomics per
+//     brick instead of one per segment.
+// Both sum the same terms as seg_bwd (Sec. 3.3, the chain rule through the
+// trilinear weights and the SH basis); only the order of the additions
+// differs.
+
+template <int DT, bool CAUCHY>
+__global__ __launch_bounds__(kThreads) void seg_bwd_rec_kernel(GridDev g, BinArgs a) {
+    __shared__ float q_y[kThreads * 9];
+    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
+    if (blk >= a.n_blocks) return;
+    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    const int64_t n_seg = seg_count_of(a);
+    int4 sg = make_int4(0, 0, -1, 0);
+    if (i < n_seg) sg = a.bseg[i];
+    const bool live = i < n_seg && seg_valid(a, sg, n_seg);
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+    if (live) load_ray_lane(a, sg.x, o, d);
+    RayGeom r;
+    const int n = live ? ray_setup(g, o, d, r) : 0;
+    float *y = q_y + threadIdx.x * 9;
+    sh_basis_all(d, y);
+
+    CornerCache cc;
+    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+    Q4 unused[8];
+    const Queue no_queue{};
+    float gr[3] = {0.f, 0.f, 0.f};
+    double tau_after = 0.0;
+    float gR = 0.0f, ls = 0.0f;
+    int64_t base = 0, room = 0;
+    if (live) {
+        const float4 gg = a.g_ray[sg.x];
+        gr[0] = gg.x;
+        gr[1] = gg.y;
+        gr[2] = gg.z;
+        tau_after = a.tau_in[sg.w] + a.tau_seg[sg.w];
+        gR = a.gr_after[sg.w] - gg.w;  // the beta factor joins the running sum
+        base = a.soff[i];
+        room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
+        if (base < 0 || base + room > a.samp_cap) room = 0;
+    }
+    float T_after = expf(-(float)tau_after);
+    SpanCursor cur{sg.z, 0, 0u};
+    int j = 0;
+    bool active = live && n > 0;
+    while (active) {
+        const int k = span_next_down(g, r, n, sg.y, cur);
+        if (k < 0 || j >= room) break;
+        const Sample s = sample_at(g, r, k);
+        move_to<DT, false>(g, cc, s.cell, unused, no_queue, y);
+        float w[8];
+        corner_weights(s.f, w);
+        const Q4 v = interpolate(cc, w);
+        const float sd = fmaxf(v.s, 0.0f) * s.delta;
+        const double tau_before = fmax(tau_after - (double)sd, 0.0);
+        const float T_before = expf(-(float)tau_before);
+        const float wk = T_before * (-expm1f(-sd));
+        const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) + gr[2] * fmaxf(v.b, 0.0f);
+        const float cs = CAUCHY ? cauchy_grad(a.pri, v.s, &ls) : 0.0f;
+        const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) + cs : 0.0f;
+        const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
+        const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
+        const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
+        const int cell = ((s.cell[0] & (PLX_BRICK - 1)) << 6) | ((s.cell[1] & (PLX_BRICK - 1)) << 3) |
+                         (s.cell[2] & (PLX_BRICK - 1));
+        SampleRec *rec = a.srec + base + j;
+        rec->pos = make_float4(s.f[0], s.f[1], s.f[2], __int_as_float(cell));
+        rec->grad = make_float4(dsig, g_r, g_g, g_b);
+        ++j;
+        gR += wk * gc;
+        tau_after = tau_before;
+        T_after = T_before;
+    }
+    if (live) a.nocc[i] = j;
+    if (CAUCHY) add_prior_loss(a.pri, ls, 0.0);
+}
+
+constexpr int kBrickCells = PLX_BRICK * PLX_BRICK * PLX_BRICK;           // 512
+constexpr int kBrickVox = (PLX_BRICK + 1) * (PLX_BRICK + 1) * (PLX_BRICK + 1);  // 729 corner voxels
+constexpr int kVoxRounds = (kBrickVox + kThreads - 1) / kThreads;
+constexpr int kScatterCap = 1536;          // samples sorted into LDS per pass
+constexpr int kScatterPer = kScatterCap / kThreads;
+constexpr int kStageRows = 16;             // rows a wave stages per flush round
+constexpr int kStageStride = 29;           // 28 values and the voxel id per staged row
+
+// A sample as the scatter keeps it in LDS: the SampleRec fields it uses
+// and the pass-local number of its segment (for the SH basis).
+struct LdsSample {
+    float f[3];
+    float g[4];
+    int seg;
+};
+
+// Sends the 28 gradient values of every lane's voxel (id < 0: none) to the
+// FP32 records, kStageRows rows at a time through the wave's staging rows:
+// lanes 0..31 then take one row and lanes 32..63 the next, lane s of a half
+// the record slot s (0..26 SH, 28 density, 29 the touched byte), so every
+// instruction covers two 128-B gradient lines.  Called by the whole wave.
+__device__ __forceinline__ void flush_voxel_rows(float *stage, const float acc[28], int id, float *grad,
+                                                 uint8_t *touched) {
+    const int L = lane_id();
+    const int s = L & 31;
+    const int half = L >> 5;
+    const int col = s < PLX_NSH ? s : PLX_NSH;  // staged column of the lane's slot
+#pragma unroll
+    for (int h = 0; h < kWave / kStageRows; ++h) {
+        const bool mine = L / kStageRows == h;
+        if (__ballot(id >= 0 && mine) == 0) continue;
+        if (mine) {
+            float *row = stage + (L % kStageRows) * kStageStride;
+#pragma unroll
+            for (int v = 0; v < 28; ++v) row[v] = acc[v];
+            row[28] = __int_as_float(id);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < kStageRows / 2; ++u) {
+            const float *row = stage + (2 * u + half) * kStageStride;
+            const int rid = __float_as_int(row[28]);
+            const float val = row[col];
+            if (rid >= 0) {
+                if ((s < PLX_NSH || s == PLX_SLOT_SIGMA) && val != 0.0f)
+                    unsafeAtomicAdd(grad + (int64_t)rid * PLX_REC_SLOTS + s, val);
+                if (s == PLX_SLOT_SIGMA + 1) touched[rid] = 1;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArgs a) {
+    __shared__ int64_t s_soff[kThreads];       // sample slot of each segment of the pass
+    __shared__ int s_pre[kThreads + 1];        // its first sample in the pass's numbering
+    __shared__ float s_y[kThreads * 9];        // SH basis of its ray
+    __shared__ int s_cnt[kBrickCells];         // samples per cell
+    __shared__ int s_coff[kBrickCells + 1];    // first sorted position of each cell
+    __shared__ LdsSample s_rec[kScatterCap];   // the pass's samples, sorted by cell
+    __shared__ float s_stage[kWavesPerBlock * kStageRows * kStageStride];
+
+    if (blockIdx.x >= (unsigned)a.n_brick) return;
+    const int t = threadIdx.x;
+    float *stage = s_stage + (t / kWave) * kStageRows * kStageStride;
+    // brick coordinates from its position in the binning order
+    const int64_t jo = a.blist[blockIdx.x];
+    const int nty = (g.by + kTile - 1) / kTile, ntz = (g.bz + kTile - 1) / kTile;
+    const int64_t tile = jo / (kTile * kTile * kTile);
+    const int in = (int)(jo % (kTile * kTile * kTile));
+    const int bxyz[3] = {(int)(tile / ((int64_t)nty * ntz)) * kTile + in / (kTile * kTile),
+                         (int)((tile / ntz) % nty) * kTile + (in / kTile) % kTile,
+                         (int)(tile % ntz) * kTile + in % kTile};
+    const int64_t seg0 = a.boff[jo * kLenClasses], seg1 = a.boff[(jo + 1) * kLenClasses];
+
+    // the lane's corner voxels (position p = x*81 + y*9 + z of the 9^3 lattice)
+    int vid[kVoxRounds];
+#pragma unroll
+    for (int rr = 0; rr < kVoxRounds; ++rr) {
+        const int p = t + rr * kThreads;
+        vid[rr] = -1;
+        if (p < kBrickVox) {
+            const int X = bxyz[0] * PLX_BRICK + p / 81, Y = bxyz[1] * PLX_BRICK + (p / 9) % 9,
+                      Z = bxyz[2] * PLX_BRICK + p % 9;
+            if (X < g.nx && Y < g.ny && Z < g.nz) vid[rr] = g.index[((int64_t)X * g.ny + Y) * g.nz + Z];
+        }
+    }
+
+    for (int64_t c0 = seg0; c0 < seg1; c0 += kThreads) {
+        const int ns = (int)min((int64_t)kThreads, seg1 - c0);
+        int occ = 0;
+        if (t < ns) {
+            const int64_t i = c0 + t;
+            const int4 sg = a.bseg[i];
+            float d[3] = {0.f, 0.f, 1.f};
+            if (seg_valid(a, sg, a.n_seg)) {
+                occ = a.nocc[i];
+                d[0] = a.rays_d[3 * (int64_t)sg.x];
+                d[1] = a.rays_d[3 * (int64_t)sg.x + 1];
+                d[2] = a.rays_d[3 * (int64_t)sg.x + 2];
+            }
+            s_soff[t] = a.soff[i];
+            sh_basis_all(d, s_y + t * 9);
+        }
+        int64_t tot64;
+        const int pre = (int)block_scan_excl(occ, &tot64);
+        const int tot = (int)tot64;
+        s_pre[t] = pre;  // segments past ns hold the total
+        if (t == 0) s_pre[kThreads] = tot;
+        __syncthreads();
+
+        for (int q0 = 0; q0 < tot; q0 += kScatterCap) {
+            const int nq = min(kScatterCap, tot - q0);
+            for (int c = t; c < kBrickCells; c += kThreads) s_cnt[c] = 0;
+            __syncthreads();
+            // count the pass's samples per cell; keep each one's cell, rank and slot
+            int cell_u[kScatterPer], rank_u[kScatterPer], seg_u[kScatterPer];
+            int64_t slot_u[kScatterPer];
+#pragma unroll
+            for (int u = 0; u < kScatterPer; ++u) {
+                const int q = u * kThreads + t;
+                cell_u[u] = -1;
+                if (q < nq) {
+                    const int qq = q0 + q;
+                    int lo = 0, hi = ns - 1;  // last segment whose first sample is <= qq
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= qq) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    slot_u[u] = s_soff[lo] + (qq - s_pre[lo]);
+                    seg_u[u] = lo;
+                    const int cell = __float_as_int(a.srec[slot_u[u]].pos.w) & (kBrickCells - 1);
+                    cell_u[u] = cell;
+                    rank_u[u] = atomicAdd(&s_cnt[cell], 1);
+                }
+            }
+            __syncthreads();
+            {
+                const int a0 = s_cnt[2 * t], a1 = s_cnt[2 * t + 1];
+                int64_t all;
+                const int ex = (int)block_scan_excl(a0 + a1, &all);
+                s_coff[2 * t] = ex;
+                s_coff[2 * t + 1] = ex + a0;
+                if (t == 0) s_coff[kBrickCells] = (int)all;
+            }
+            __syncthreads();
+            // place the samples in cell order
+#pragma unroll
+            for (int u = 0; u < kScatterPer; ++u) {
+                if (cell_u[u] >= 0) {
+                    const SampleRec sr = a.srec[slot_u[u]];
+                    LdsSample &ls = s_rec[s_coff[cell_u[u]] + rank_u[u]];
+                    ls.f[0] = sr.pos.x;
+                    ls.f[1] = sr.pos.y;
+                    ls.f[2] = sr.pos.z;
+                    ls.g[0] = sr.grad.x;
+                    ls.g[1] = sr.grad.y;
+                    ls.g[2] = sr.grad.z;
+                    ls.g[3] = sr.grad.w;
+                    ls.seg = seg_u[u];
+                }
+            }
+            __syncthreads();
+
+            // each lane sums its voxels' contributions and flushes them
+#pragma unroll 1
+            for (int rr = 0; rr < kVoxRounds; ++rr) {
+                const int p = t + rr * kThreads;
+                float acc[28];
+#pragma unroll
+                for (int v = 0; v < 28; ++v) acc[v] = 0.0f;
+                bool any = false;
+                if (vid[rr] >= 0) {
+                    const int px = p / 81, py = (p / 9) % 9, pz = p % 9;
+#pragma unroll 1
+                    for (int o = 0; o < 8; ++o) {
+                        // the voxel is corner o (x: bit 2) of the cell p - o
+                        const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+                        const int cx = px - ox, cy = py - oy, cz = pz - oz;
+                        if (cx < 0 || cy < 0 || cz < 0 || cx >= PLX_BRICK || cy >= PLX_BRICK || cz >= PLX_BRICK)
+                            continue;
+                        const int cell = (cx << 6) | (cy << 3) | cz;
+                        const int e1 = s_coff[cell + 1];
+                        for (int e = s_coff[cell]; e < e1; ++e) {
+                            const LdsSample &sr = s_rec[e];
+                            const float wx = ox ? sr.f[0] : 1.0f - sr.f[0];
+                            const float wy = oy ? sr.f[1] : 1.0f - sr.f[1];
+                            const float wz = oz ? sr.f[2] : 1.0f - sr.f[2];
+                            const float w = wx * wy * wz;
+                            const float *yy = s_y + sr.seg * 9;
+                            const float a_r = w * sr.g[1], a_g = w * sr.g[2], a_b = w * sr.g[3];
+#pragma unroll
+                            for (int l = 0; l < 9; ++l) {
+                                const float yl = yy[l];
+                                acc[l] += a_r * yl;
+                                acc[9 + l] += a_g * yl;
+                                acc[18 + l] += a_b * yl;
+                            }
+                            acc[27] += w * sr.g[0];
+                            any = true;
+                        }
+                    }
+                }
+                flush_voxel_rows(stage, acc, any ? vid[rr] : -1, a.grad, a.touched);
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------ maximum sample weight
@@ -1717,11 +2067,19 @@ inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 // values the render passes hand from one kernel to the next.
 
 struct RayBufLayout {
-    int64_t nseg, segoff, gray, bcount, bcursor, status, boff, scan, bytes;
+    int64_t nseg, segoff, gray, bcount, bcursor, status, boff, scan;
+    // per-bin sample counts (samples == true only)
+    int64_t bsamp, bscursor, nbrick, bsoff, blist;
+    int64_t bytes;
+    bool samples;
 };
 
-RayBufLayout ray_buf_layout(int64_t n_rays, int64_t nbk) {
-    RayBufLayout l;
+// samples: with the per-bin sample counts and the brick list that the
+// recorded backward needs (every caller-owned ray buffer has them; the
+// fixed scratch of plx_render_train_static does not).
+RayBufLayout ray_buf_layout(int64_t n_rays, int64_t nbk, bool samples = true) {
+    RayBufLayout l = {};
+    l.samples = samples;
     int64_t off = 0;
     l.nseg = off; off += align256(n_rays * 4);
     l.segoff = off; off += align256((n_rays + 1) * 8);
@@ -1731,10 +2089,36 @@ RayBufLayout ray_buf_layout(int64_t n_rays, int64_t nbk) {
     l.bcursor = off; off += nbk * 4;
     l.status = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
     l.boff = off; off += align256((nbk + 1) * 8);
+    if (samples) {
+        // sample counts, cursors and the brick counter: a second clear
+        l.bsamp = off; off += nbk * 4;
+        l.bscursor = off; off += nbk * 4;
+        l.nbrick = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
+        l.bsoff = off; off += align256((nbk + 1) * 8);
+        l.blist = off; off += align256(nbk / kLenClasses * 4);
+    }
     l.scan = off; off += align256((scan_tmp_words(n_rays) + scan_tmp_words(nbk)) * 8);
     l.bytes = off;
     return l;
 }
+
+struct SampBufLayout {
+    int64_t soff, nocc, srec, bytes;
+};
+
+SampBufLayout samp_buf_layout(int64_t n_seg, int64_t n_samp) {
+    SampBufLayout l;
+    int64_t off = 0;
+    l.soff = off; off += align256(n_seg * 8);
+    l.nocc = off; off += align256(n_seg * 4);
+    l.srec = off; off += align256(n_samp * (int64_t)sizeof(SampleRec));
+    l.bytes = off;
+    return l;
+}
+
+// Sample slots one call handles (the scatter numbers a pass's samples with
+// 32-bit integers; the records are addressed with 64-bit offsets).
+constexpr int64_t kMaxSampBinned = (int64_t)1 << 40;
 
 struct SegBufLayout {
     int64_t bseg, tseg, cseg, tin, gra, bytes;
@@ -1764,6 +2148,21 @@ void attach_ray_buf(BinArgs &a, void *ray_buf, const RayBufLayout &l) {
     a.bcursor = reinterpret_cast<unsigned *>(base + l.bcursor);
     a.status = reinterpret_cast<unsigned *>(base + l.status);
     a.boff = reinterpret_cast<int64_t *>(base + l.boff);
+    if (l.samples) {
+        a.bsamp = reinterpret_cast<unsigned *>(base + l.bsamp);
+        a.bscursor = reinterpret_cast<unsigned *>(base + l.bscursor);
+        a.nbrick = reinterpret_cast<unsigned *>(base + l.nbrick);
+        a.bsoff = reinterpret_cast<int64_t *>(base + l.bsoff);
+        a.blist = reinterpret_cast<unsigned *>(base + l.blist);
+    }
+}
+
+// Points a's recorded-backward arrays into a sample buffer.
+void attach_samp_buf(BinArgs &a, void *samp_buf, const SampBufLayout &l) {
+    char *b = static_cast<char *>(samp_buf);
+    a.soff = reinterpret_cast<int64_t *>(b + l.soff);
+    a.nocc = reinterpret_cast<int *>(b + l.nocc);
+    a.srec = reinterpret_cast<SampleRec *>(b + l.srec);
 }
 
 // Points a's per-segment arrays into a segment buffer.
@@ -1804,6 +2203,18 @@ int attach_bins(const plx_grid *grid, const plx_bins *bins, int64_t n_rays, BinA
         if ((rc = check_buf(bins->seg_buf, bins->seg_buf_bytes, sl.bytes, "bins->seg_buf", fn))) return rc;
         attach_seg_buf(a, bins->seg_buf, sl);
     }
+    const int64_t n_bricks = n_bins(to_dev(grid)) / kLenClasses;
+    if (bins->n_brick < 0 || bins->n_brick > n_bricks || (bins->n_seg > 0) != (bins->n_brick > 0))
+        return fail(PLX_EINVAL, "%s: bins->n_brick = %lld out of range", fn, (long long)bins->n_brick);
+    if (bins->n_samp < 0 || bins->n_samp > kMaxSampBinned || (bins->n_seg > 0 && bins->n_samp < bins->n_seg))
+        return fail(PLX_EINVAL, "%s: bins->n_samp = %lld out of range", fn, (long long)bins->n_samp);
+    a.n_brick = bins->n_brick;
+    if (bins->samp_buf && bins->n_seg > 0) {
+        const SampBufLayout pl = samp_buf_layout(bins->n_seg, bins->n_samp);
+        if ((rc = check_buf(bins->samp_buf, bins->samp_buf_bytes, pl.bytes, "bins->samp_buf", fn))) return rc;
+        attach_samp_buf(a, bins->samp_buf, pl);
+        a.samp_cap = bins->n_samp;
+    }
     return PLX_OK;
 }
 
@@ -1816,13 +2227,23 @@ int bin_count_launch(const GridDev &g, BinArgs &a, int64_t nbk, int64_t *scan_tm
     zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(a.bcount, nz);
     int rc = check_launch(fn);
     if (rc) return rc;
+    if (a.bsamp) {  // bsamp, bscursor, nbrick
+        zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(a.bsamp, nz);
+        if ((rc = check_launch(fn))) return rc;
+    }
     const int64_t nbr = (n_rays + kThreads - 1) / kThreads;
     a.n_blocks = (int)nbr;
     a.nb8 = round_up8(nbr);
     seg_count_kernel<<<a.nb8, kThreads, 0, s>>>(g, a);
     if ((rc = check_launch(fn))) return rc;
     if ((rc = scan_counts(a.nseg, n_rays, a.seg_off, scan_tmp, s, fn))) return rc;
-    return scan_counts(a.bcount, nbk, a.boff, scan_tmp + scan_tmp_words(n_rays), s, fn);
+    int64_t *bin_tmp = scan_tmp + scan_tmp_words(n_rays);
+    if ((rc = scan_counts(a.bcount, nbk, a.boff, bin_tmp, s, fn))) return rc;
+    if (!a.bsamp) return PLX_OK;
+    if ((rc = scan_counts(a.bsamp, nbk, a.bsoff, bin_tmp, s, fn))) return rc;
+    const int64_t n_bricks = nbk / kLenClasses;
+    brick_list_kernel<<<(unsigned)((n_bricks + kThreads - 1) / kThreads), kThreads, 0, s>>>(a, n_bricks);
+    return check_launch(fn);
 }
 
 // Render passes over binned segments: MODE_FWD renders, MODE_BWD and
@@ -1862,7 +2283,21 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     seg_combine_kernel<MODE><<<(unsigned)nbr, kThreads, 0, s>>>(a);
     if ((rc = check_launch(fn))) return rc;
     if ((rc = mark_event(a.events, 2, s, fn))) return rc;
-    if (MODE != MODE_FWD && a.n_seg > 0) {
+    if (MODE != MODE_FWD && a.n_seg > 0 && a.srec) {
+        // recorded backward: replay into the sample buffer, then one scatter
+        // workgroup per brick (the Cauchy prior's per-sample terms only in an
+        // instance of their own)
+        if (as.pri.lambda_s != 0.0f) {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_rec_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
+        } else {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_rec_kernel<DT, false><<<as.nb8, kThreads, 0, s>>>(g, as));
+        }
+        if ((rc = check_launch(fn))) return rc;
+        if (a.n_brick > 0) {
+            seg_scatter_kernel<<<(unsigned)a.n_brick, kThreads, 0, s>>>(g, as);
+            if ((rc = check_launch(fn))) return rc;
+        }
+    } else if (MODE != MODE_FWD && a.n_seg > 0) {
         // the Cauchy prior's per-sample terms only in an instance of their own
         if (as.pri.lambda_s != 0.0f) {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
@@ -1956,18 +2391,26 @@ int64_t plx_bins_seg_bytes(int64_t n_seg) {
     return seg_buf_layout(n_seg).bytes;
 }
 
+int64_t plx_bins_samp_bytes(int64_t n_seg, int64_t n_samp) {
+    if (n_seg < 0 || n_seg > kMaxRaysBinned || n_samp < 0 || n_samp > kMaxSampBinned) return 0;
+    return samp_buf_layout(n_seg, n_samp).bytes;
+}
+
 int plx_bins_count(const plx_grid *grid, const float *rays_o, const float *rays_d, int64_t n_rays,
-                   void *ray_buf, int64_t ray_buf_bytes, int64_t *n_seg, plx_stream stream) {
+                   void *ray_buf, int64_t ray_buf_bytes, plx_bins *bins, plx_stream stream) {
     const char *fn = "plx_bins_count";
     int rc = validate_grid(grid, true, fn);
     if (rc || (rc = validate_rays(rays_o, rays_d, n_rays, fn))) return rc;
-    if (!n_seg) return fail(PLX_EINVAL, "%s: n_seg is NULL", fn);
+    if (!bins) return fail(PLX_EINVAL, "%s: bins is NULL", fn);
     if (n_rays > kMaxRaysBinned) return fail(PLX_EINVAL, "%s: too many rays", fn);
     const GridDev g = to_dev(grid);
     const int64_t nbk = n_bins(g);
     const RayBufLayout l = ray_buf_layout(n_rays, nbk);
     if ((rc = check_buf(ray_buf, ray_buf_bytes, l.bytes, "ray_buf", fn))) return rc;
-    *n_seg = 0;
+    *bins = plx_bins{};
+    bins->n_rays = n_rays;
+    bins->ray_buf = ray_buf;
+    bins->ray_buf_bytes = ray_buf_bytes;
     if (n_rays == 0) return PLX_OK;
     hipStream_t s = as_stream(stream);
     BinArgs a = {};
@@ -1977,12 +2420,19 @@ int plx_bins_count(const plx_grid *grid, const float *rays_o, const float *rays_
     attach_ray_buf(a, ray_buf, l);
     int64_t *scan_tmp = reinterpret_cast<int64_t *>(static_cast<char *>(ray_buf) + l.scan);
     if ((rc = bin_count_launch(g, a, nbk, scan_tmp, s, fn))) return rc;
-    int64_t total = 0;
+    int64_t total = 0, samples = 0;
+    unsigned bricks = 0;
     PLX_CHECK_HIP(hipMemcpyAsync(&total, a.seg_off + n_rays, sizeof(total), hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipMemcpyAsync(&samples, a.bsoff + nbk, sizeof(samples), hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipMemcpyAsync(&bricks, a.nbrick, sizeof(bricks), hipMemcpyDeviceToHost, s), fn);
     PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
     if (total < 0 || total > kMaxRaysBinned)
         return fail(PLX_EINVAL, "%s: %lld ray segments, more than one call handles", fn, (long long)total);
-    *n_seg = total;
+    if (samples < 0 || samples > kMaxSampBinned)
+        return fail(PLX_EINVAL, "%s: %lld sample slots, more than one call handles", fn, (long long)samples);
+    bins->n_seg = total;
+    bins->n_samp = samples;
+    bins->n_brick = bricks;
     return PLX_OK;
 }
 
@@ -2134,7 +2584,7 @@ int plx_render_train_static(const plx_grid *grid, const plx_render_opts *opts, c
     // bx + by + bz - 2 bricks of the lattice
     const int64_t per_ray = (int64_t)g.bx + g.by + g.bz;
     const int64_t cap = n_rays * per_ray;
-    const RayBufLayout rl = ray_buf_layout(n_rays, nbk);
+    const RayBufLayout rl = ray_buf_layout(n_rays, nbk, false);
     const SegBufLayout sl = seg_buf_layout(cap);
     if (n_rays > kMaxRaysBinned || cap > kMaxRaysBinned || rl.bytes + sl.bytes > kStaticScratchBytes)
         return fail(PLX_ENOMEM,

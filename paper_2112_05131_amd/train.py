@@ -240,7 +240,7 @@ class Trainer:
         finished.  events: a list that gets one StepEvents per step."""
         main = torch.cuda.current_stream()
         side = torch.cuda.Stream(device=self.grid.device) if overlap else main
-        bufs = [[None, None], [None, None]]
+        bufs = [[None, None, None], [None, None, None]]
         done = [None, None]
 
         def prepare(slot):
@@ -251,8 +251,8 @@ class Trainer:
                 if se is not None:
                     se.bins[0].record(side)
                 o, d, t = sampler.next_batch()
-                b = B.make_bins(self.grid.desc(), o, d, bufs[slot][0], bufs[slot][1])
-                bufs[slot] = [b.ray_buf, b.seg_buf]
+                b = B.make_bins(self.grid.desc(), o, d, *bufs[slot])
+                bufs[slot] = b.buffers()
                 if se is not None:
                     se.bins[1].record(side)
                     se.binned = True
@@ -265,7 +265,7 @@ class Trainer:
             o, d, t, b, ev, se = nxt
             if side is not main:
                 main.wait_event(ev)
-                for x in (o, d, t, b.ray_buf, b.seg_buf):
+                for x in (o, d, t, *b.buffers()):
                     if x is not None:
                         x.record_stream(main)
             self.step(o, d, t, tv=tv, bins=b, events=se)

@@ -44,9 +44,10 @@ def check_losses(loss, ls_ref, lb_ref):
     assert abs(got[1] - lb_ref) <= 1e-6 * abs(lb_ref) + 1e-9
 
 
+@pytest.mark.parametrize("samples", [True, False])
 @pytest.mark.parametrize("sh_dtype", [B.PLX_F32, B.PLX_F16])
-def test_train_with_priors_matches_oracle(sh_dtype):
-    say("train + priors", sh_dtype)
+def test_train_with_priors_matches_oracle(sh_dtype, samples):
+    say("train + priors", sh_dtype, "samples", samples)
     og, gg = make_pair(synth.dense_random((27, 22, 30), seed=81, occupancy=0.45, sigma_lo=-5.0, sigma_hi=40.0,
                                           ho_scale=0.3), sh_dtype)
     o, d = synth.random_rays(3001, seed=82)
@@ -57,8 +58,9 @@ def test_train_with_priors_matches_oracle(sh_dtype):
     touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     pl = torch.zeros(2, dtype=torch.float64, device="cuda")
+    bins = B.make_bins(gg.desc(), o.cuda(), d.cuda(), samples=samples)
     B.plx_render_train(gg.desc(), o.cuda(), d.cuda(), torch.from_numpy(target).cuda(), 1.0 / n, grad, touched,
-                       loss, priors=B.Priors(LS, LB, EPS, pl))
+                       loss, priors=B.Priors(LS, LB, EPS, pl), bins=bins)
     torch.cuda.synchronize()
     rgb_ref = O.render_fwd(og, on, dn)[0]
     g_rgb, loss_ref = O.mse_grad(rgb_ref, target)

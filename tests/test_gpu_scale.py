@@ -215,12 +215,14 @@ def test_16bit_storage_at_c4_size(c3_scene, sh_dtype):
     assert torch.all(grad[~on_] == 0)
 
 
-def test_bins_serve_every_call_and_verify():
+@pytest.mark.parametrize("samples", [True, False])
+def test_bins_serve_every_call_and_verify(samples):
     """One set of segment lists serves forward, backward and the fused call
     (the same results as lists made afresh), plx_bins_verify finds every
     segment where the count reserved it, and buffers larger than needed are
-    accepted."""
-    say("bins reuse")
+    accepted; with and without a sample buffer (recorded backward or the
+    replay's own scatter)."""
+    say("bins reuse, samples", samples)
     sv = synth.dense_random((37, 29, 41), seed=301, occupancy=0.3, ho_scale=0.2)
     og, gg = make_pair(sv)
     o, d = synth.random_rays(3001, seed=302)
@@ -228,8 +230,9 @@ def test_bins_serve_every_call_and_verify():
     n, m = o.shape[0], gg.n_vox
     desc = gg.desc()
     big_r = B.workspace(B.plx_bins_ray_bytes(gg.reso, n) + 4096)
-    bins = B.make_bins(desc, o, d, ray_buf=big_r)
+    bins = B.make_bins(desc, o, d, ray_buf=big_r, samples=samples)
     assert bins.ray_buf.data_ptr() == big_r.data_ptr()
+    assert (bins.samp_buf is not None) == samples and bins.n_brick > 0 and bins.n_samp >= bins.n_seg
     B.plx_bins_verify(desc, bins)
     rgb1, tau1 = torch.empty(n, 3, device="cuda"), torch.empty(n, device="cuda")
     rgb2, tau2 = torch.empty(n, 3, device="cuda"), torch.empty(n, device="cuda")

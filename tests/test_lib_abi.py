@@ -253,44 +253,62 @@ def test_bins_layout_and_validation():
     r1, r2 = B.plx_bins_ray_bytes(reso, 1000), B.plx_bins_ray_bytes(reso, 2000)
     assert r2 - r1 >= 1000 * (4 + 8 + 16) - 3 * 256
     assert B.plx_bins_ray_bytes((64, 64, 64), 1000) > r1
+    # the sample buffer: slot offset and recorded count per segment, 32 B per sample slot
+    for n_seg, n_samp in ((0, 0), (1, 5), (1000, 11000), (123457, 1234567)):
+        assert B.plx_bins_samp_bytes(n_seg, n_samp) == up(8 * n_seg) + up(4 * n_seg) + up(32 * n_samp)
+    assert B.plx_bins_samp_bytes(-1, 0) == 0 and B.plx_bins_samp_bytes(1, -1) == 0
+    assert B.plx_bins_samp_bytes(1, (1 << 40) + 1) == 0
     opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
     o, d, rgb = p(0x40000), p(0x50000), p(0x60000)
     need_r = B.plx_bins_ray_bytes(reso, 4)
     need_s = B.plx_bins_seg_bytes(7)
-    good = B.PlxBins(4, 7, 0x1000000, need_r, 0x2000000, need_s)
-    cases = [(B.PlxBins(5, 7, 0x1000000, need_r, 0x2000000, need_s), "made for 5 rays"),
-             (B.PlxBins(4, 7, 0x1000000, need_r - 1, 0x2000000, need_s), "need"),
-             (B.PlxBins(4, 7, 0x1000010, need_r, 0x2000000, need_s), "aligned"),
-             (B.PlxBins(4, 7, None, need_r, 0x2000000, need_s), "NULL"),
-             (B.PlxBins(4, 7, 0x1000000, need_r, 0x2000000, need_s - 1), "need"),
-             (B.PlxBins(4, 7, 0x1000000, need_r, None, need_s), "NULL"),
-             (B.PlxBins(4, -3, 0x1000000, need_r, 0x2000000, need_s), "n_seg")]
-    for bins, needle in cases:
-        rc = L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), o, d, 4, ctypes.byref(bins), rgb,
+    need_p = B.plx_bins_samp_bytes(7, 30)
+
+    def bins(n_rays=4, n_seg=7, n_samp=30, n_brick=2, rb=0x1000000, rn=need_r, sb=0x2000000, sn=need_s,
+             pb=None, pn=0):
+        return B.PlxBins(n_rays, n_seg, n_samp, n_brick, rb, rn, sb, sn, pb, pn)
+
+    cases = [(bins(n_rays=5), "made for 5 rays"),
+             (bins(rn=need_r - 1), "need"),
+             (bins(rb=0x1000010), "aligned"),
+             (bins(rb=None), "NULL"),
+             (bins(sn=need_s - 1), "need"),
+             (bins(sb=None), "NULL"),
+             (bins(n_seg=-3), "n_seg"),
+             (bins(n_brick=0), "n_brick"),
+             (bins(n_brick=1 << 40), "n_brick"),
+             (bins(n_samp=6), "n_samp"),
+             (bins(n_samp=-1), "n_samp"),
+             (bins(pb=0x3000000, pn=need_p - 1), "samp_buf"),
+             (bins(pb=0x3000040, pn=need_p), "aligned")]
+    for b, needle in cases:
+        rc = L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), o, d, 4, ctypes.byref(b), rgb,
                               None, None)
         assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
         rc = L.plx_render_train(ctypes.byref(g), ctypes.byref(opts), o, d, p(0x70000), 4,
-                                ctypes.byref(bins), 0.25, None, p(0x80000), p(0x90000), p(0xa0000),
+                                ctypes.byref(b), 0.25, None, p(0x80000), p(0x90000), p(0xa0000),
                                 None)
         assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
-        rc = L.plx_bins_apply(ctypes.byref(g), o, d, ctypes.byref(bins), None)
-        if bins.n_rays == 4:
+        rc = L.plx_bins_apply(ctypes.byref(g), o, d, ctypes.byref(b), None)
+        if b.n_rays == 4:
             assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
     # NULL bins
     assert L.plx_render_fwd(ctypes.byref(g), ctypes.byref(opts), o, d, 4, None, rgb, None,
                             None) == B.PLX_EINVAL
     assert "bins" in L.plx_last_error().decode()
-    del good
-    # counting: NULL count, short or misaligned ray buffer; zero rays
-    n_seg = ctypes.c_int64(-1)
+    # counting: NULL descriptor, short or misaligned ray buffer; zero rays
+    out = B.PlxBins()
     assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000000), need_r, None, None) == B.PLX_EINVAL
-    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000000), need_r - 8, ctypes.byref(n_seg),
+    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000000), need_r - 8, ctypes.byref(out),
                             None) == B.PLX_EINVAL
-    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000080), need_r, ctypes.byref(n_seg),
+    assert L.plx_bins_count(ctypes.byref(g), o, d, 4, p(0x1000080), need_r, ctypes.byref(out),
                             None) == B.PLX_EINVAL
     z = B.plx_bins_ray_bytes(reso, 0)
-    assert L.plx_bins_count(ctypes.byref(g), None, None, 0, p(0x1000000), z, ctypes.byref(n_seg),
-                            None) == B.PLX_OK and n_seg.value == 0
+    out.n_seg = out.n_samp = out.n_brick = -1
+    assert L.plx_bins_count(ctypes.byref(g), None, None, 0, p(0x1000000), z, ctypes.byref(out),
+                            None) == B.PLX_OK
+    assert (out.n_rays, out.n_seg, out.n_samp, out.n_brick) == (0, 0, 0, 0)
+    assert out.ray_buf == 0x1000000 and out.ray_buf_bytes == z and not out.seg_buf and not out.samp_buf
 
 
 def test_grid_workspace_validation():
