@@ -879,8 +879,9 @@ __device__ __forceinline__ int64_t seg_bin(int64_t order, int k0, int k1) {
 constexpr int kScanT = 256, kScanI = 16, kScanTile = kScanT * kScanI;
 
 // Exclusive block-wide scan of one int64 per thread; *total gets the sum.
+template <int NT = kScanT>
 __device__ int64_t block_scan_excl(int64_t v, int64_t *total) {
-    __shared__ int64_t wsum[kScanT / kWave];
+    __shared__ int64_t wsum[NT / kWave];
     const int L = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     int64_t x = v;
 #pragma unroll
@@ -892,7 +893,7 @@ __device__ int64_t block_scan_excl(int64_t v, int64_t *total) {
     __syncthreads();
     int64_t before = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kScanT / kWave; ++i) {
+    for (int i = 0; i < NT / kWave; ++i) {
         if (i < w) before += wsum[i];
         tot += wsum[i];
     }
@@ -952,12 +953,12 @@ __global__ void zero_u32_kernel(unsigned *p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
-// One sample of the sample buffer: position in its cell and the cell's
-// number inside the brick, then the sample's gradients with respect to the
-// interpolated density and the three projected colour channels.
+// One occupied sample of the sample buffer, as the forward pass leaves it:
+// its position in its cell, its sample index and cell, and the interpolated
+// (pre-activation) density and projected colour.
 struct SampleRec {
-    float4 pos;   // f[0], f[1], f[2], cell (x*64 + y*8 + z) as integer bits
-    float4 grad;  // d/d(sigma), d/d(r), d/d(g), d/d(b)
+    float4 pos;   // f[0], f[1], f[2], (k << 9 | cell x*64 + y*8 + z) as integer bits
+    float4 val;   // sigma, r, g, b
 };
 
 struct BinArgs {
@@ -1163,9 +1164,13 @@ __device__ __forceinline__ int span_next_down(const GridDev &g, const RayGeom &r
     return c.k0 + b;
 }
 
-// Forward over one segment (transmittance relative to its start).
-template <int DT>
-__global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a) {
+// Forward over one segment (transmittance relative to its start).  REC
+// (the training and backward calls with a sample buffer) also stores every
+// occupied sample's position in its cell, cell, sample index and
+// interpolated values, in the segment's slots of the sample buffer.
+template <int DT, bool REC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void seg_fwd_kernel(GridDev g, BinArgs a) {
     const int blk = xcd_logical_block(blockIdx.x, a.nb8);
     if (blk >= a.n_blocks) return;
     const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
@@ -1186,6 +1191,13 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
     SpanCursor cur{sg.y, 0, 0u};
     double tau = 0.0;
     float C[3] = {0.0f, 0.0f, 0.0f};
+    int64_t base = 0, room = 0;
+    if (REC) {
+        base = a.soff[i];
+        room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
+        if (base < 0 || base + room > a.samp_cap) room = 0;
+    }
+    int j = 0;
     while (true) {
         const int k = span_next_up(g, r, n, sg.z, cur);
         if (k < 0) break;
@@ -1194,6 +1206,14 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
         float w[8];
         corner_weights(s.f, w);
         const Q4 v = interpolate(cc, w);
+        if (REC && j < room) {
+            const int code = (k << 9) | ((s.cell[0] & (PLX_BRICK - 1)) << 6) |
+                             ((s.cell[1] & (PLX_BRICK - 1)) << 3) | (s.cell[2] & (PLX_BRICK - 1));
+            SampleRec *rec = a.srec + base + j;
+            rec->pos = make_float4(s.f[0], s.f[1], s.f[2], __int_as_float(code));
+            rec->val = make_float4(v.s, v.r, v.g, v.b);
+        }
+        ++j;
         const float sd = fmaxf(v.s, 0.0f) * s.delta;
         const float wk = expf(-(float)tau) * (-expm1f(-sd));
         C[0] += wk * fmaxf(v.r, 0.0f);
@@ -1203,6 +1223,7 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_kernel(GridDev g, BinArgs a)
     }
     a.tau_seg[sg.w] = tau;
     a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
+    if (REC) a.nocc[i] = (int)min((int64_t)j, room);
 }
 
 // Segments of a ray are walked kSegU at a time: the loads of a group are
@@ -1425,106 +1446,42 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
 // The scatter of seg_bwd sends about nine partial gradients to every voxel a
 // batch reaches (one per segment that has it as a corner), each a 128-B line
 // of FP32 atomics, and global atomics are the slowest path on the chip (about
-// 20G 64-byte requests per second, whatever the lanes' pattern).  The
-// recorded backward splits the work in two launches instead:
-//  1. seg_bwd_rec (lane per segment, bin order) replays the segment exactly
-//     like seg_bwd but stores, per occupied sample, its position in the cell
-//     and its four scalar gradients (32 B) in the segment's slot range of the
-//     sample buffer, with no accumulation and no atomics;
-//  2. seg_scatter (one workgroup per brick with segments) sorts the brick's
-//     samples by cell in LDS, and each lane then owns one of the brick's 9^3
-//     corner voxels and sums the contributions of the samples of the (up to)
-//     8 cells around it, so every voxel gets one 128-B line of atomics per
-//     brick instead of one per segment.
-// Both sum the same terms as seg_bwd (Sec. 3.3, the chain rule through the
-// trilinear weights and the SH basis); only the order of the additions
-// differs.
-
-template <int DT, bool CAUCHY>
-__global__ __launch_bounds__(kThreads) void seg_bwd_rec_kernel(GridDev g, BinArgs a) {
-    __shared__ float q_y[kThreads * 9];
-    const int blk = xcd_logical_block(blockIdx.x, a.nb8);
-    if (blk >= a.n_blocks) return;
-    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-    const int64_t n_seg = seg_count_of(a);
-    int4 sg = make_int4(0, 0, -1, 0);
-    if (i < n_seg) sg = a.bseg[i];
-    const bool live = i < n_seg && seg_valid(a, sg, n_seg);
-    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
-    if (live) load_ray_lane(a, sg.x, o, d);
-    RayGeom r;
-    const int n = live ? ray_setup(g, o, d, r) : 0;
-    float *y = q_y + threadIdx.x * 9;
-    sh_basis_all(d, y);
-
-    CornerCache cc;
-    cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
-    Q4 unused[8];
-    const Queue no_queue{};
-    float gr[3] = {0.f, 0.f, 0.f};
-    double tau_after = 0.0;
-    float gR = 0.0f, ls = 0.0f;
-    int64_t base = 0, room = 0;
-    if (live) {
-        const float4 gg = a.g_ray[sg.x];
-        gr[0] = gg.x;
-        gr[1] = gg.y;
-        gr[2] = gg.z;
-        tau_after = a.tau_in[sg.w] + a.tau_seg[sg.w];
-        gR = a.gr_after[sg.w] - gg.w;  // the beta factor joins the running sum
-        base = a.soff[i];
-        room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
-        if (base < 0 || base + room > a.samp_cap) room = 0;
-    }
-    float T_after = expf(-(float)tau_after);
-    SpanCursor cur{sg.z, 0, 0u};
-    int j = 0;
-    bool active = live && n > 0;
-    while (active) {
-        const int k = span_next_down(g, r, n, sg.y, cur);
-        if (k < 0 || j >= room) break;
-        const Sample s = sample_at(g, r, k);
-        move_to<DT, false>(g, cc, s.cell, unused, no_queue, y);
-        float w[8];
-        corner_weights(s.f, w);
-        const Q4 v = interpolate(cc, w);
-        const float sd = fmaxf(v.s, 0.0f) * s.delta;
-        const double tau_before = fmax(tau_after - (double)sd, 0.0);
-        const float T_before = expf(-(float)tau_before);
-        const float wk = T_before * (-expm1f(-sd));
-        const float gc = gr[0] * fmaxf(v.r, 0.0f) + gr[1] * fmaxf(v.g, 0.0f) + gr[2] * fmaxf(v.b, 0.0f);
-        const float cs = CAUCHY ? cauchy_grad(a.pri, v.s, &ls) : 0.0f;
-        const float dsig = v.s > 0.0f ? s.delta * (T_after * gc - gR) + cs : 0.0f;
-        const float g_r = v.r > 0.0f ? wk * gr[0] : 0.0f;
-        const float g_g = v.g > 0.0f ? wk * gr[1] : 0.0f;
-        const float g_b = v.b > 0.0f ? wk * gr[2] : 0.0f;
-        const int cell = ((s.cell[0] & (PLX_BRICK - 1)) << 6) | ((s.cell[1] & (PLX_BRICK - 1)) << 3) |
-                         (s.cell[2] & (PLX_BRICK - 1));
-        SampleRec *rec = a.srec + base + j;
-        rec->pos = make_float4(s.f[0], s.f[1], s.f[2], __int_as_float(cell));
-        rec->grad = make_float4(dsig, g_r, g_g, g_b);
-        ++j;
-        gR += wk * gc;
-        tau_after = tau_before;
-        T_after = T_before;
-    }
-    if (live) a.nocc[i] = j;
-    if (CAUCHY) add_prior_loss(a.pri, ls, 0.0);
-}
+// 20G 64-byte requests per second, whatever the lanes' pattern); its replay
+// also repeats the forward's corner gathers.  The recorded backward instead:
+//  1. seg_fwd (REC) stores, per occupied sample, its position in the cell,
+//     sample index, cell and interpolated values (32 B) in the segment's
+//     slots of the sample buffer;
+//  2. seg_combine forms the per-ray and per-segment quantities as before;
+//  3. seg_scatter (one workgroup per brick with segments) loads the brick's
+//     samples into LDS, runs each segment's reverse recurrence over them
+//     (one lane per segment: transmittance from the FP64 optical depth after
+//     the segment, the radiance collected after it, the sample's gradients
+//     with respect to its density and projected colour), sorts the samples
+//     by cell, and then each lane owns one of the brick's 9^3 corner voxels
+//     and sums the contributions of the samples of the (up to) 8 cells around
+//     it, so every voxel gets one 128-B line of atomics per brick instead of
+//     one per segment, and no corner record is read a second time.
+// The terms are those of seg_bwd (Sec. 3.3, Eq. (1) and the chain rule
+// through the trilinear weights and the SH basis); only the order of the
+// additions differs.
 
 constexpr int kBrickCells = PLX_BRICK * PLX_BRICK * PLX_BRICK;           // 512
 constexpr int kBrickVox = (PLX_BRICK + 1) * (PLX_BRICK + 1) * (PLX_BRICK + 1);  // 729 corner voxels
-constexpr int kVoxRounds = (kBrickVox + kThreads - 1) / kThreads;
-constexpr int kScatterCap = 1536;          // samples sorted into LDS per pass
-constexpr int kScatterPer = kScatterCap / kThreads;
-constexpr int kStageRows = 16;             // rows a wave stages per flush round
+constexpr int kScatterThreads = 512;       // threads of a scatter workgroup
+constexpr int kScatterSegs = 256;          // segments per pass
+constexpr int kVoxRounds = (kBrickVox + kScatterThreads - 1) / kScatterThreads;
+constexpr int kScatterCap = 1536;          // samples in LDS per pass
+constexpr int kScatterPer = kScatterCap / kScatterThreads;
+constexpr int kStageRows = 8;              // rows a wave stages per flush round
 constexpr int kStageStride = 29;           // 28 values and the voxel id per staged row
 
-// A sample as the scatter keeps it in LDS: the SampleRec fields it uses
-// and the pass-local number of its segment (for the SH basis).
+// A sample in the scatter's LDS.  Before the sort: v = the interpolated
+// values, then (after the recurrence) the gradients; code = sample index and
+// cell.  After the sort: f, the gradients in v, and seg = the pass-local
+// number of its segment.
 struct LdsSample {
     float f[3];
-    float g[4];
+    float v[4];
     int seg;
 };
 
@@ -1567,17 +1524,29 @@ __device__ __forceinline__ void flush_voxel_rows(float *stage, const float acc[2
     }
 }
 
-__global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArgs a) {
-    __shared__ int64_t s_soff[kThreads];       // sample slot of each segment of the pass
-    __shared__ int s_pre[kThreads + 1];        // its first sample in the pass's numbering
-    __shared__ float s_y[kThreads * 9];        // SH basis of its ray
+// Reverse recurrence of one segment (the state a lane carries along it).
+struct SegState {
+    double tau_after;  // optical depth after the current sample
+    float T_after;
+    float gR;          // g . (radiance collected after the current sample)
+    float gr[3];       // dL/dC of the ray
+    float ls;          // Cauchy prior loss of the lane
+};
+
+template <bool CAUCHY>
+__global__ __launch_bounds__(kScatterThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void seg_scatter_kernel(GridDev g, BinArgs a) {
+    __shared__ int64_t s_soff[kScatterSegs];   // sample slot of each segment of the group
+    __shared__ int s_pre[kScatterSegs + 1];    // its first sample in the group's numbering
+    __shared__ float4 s_y4[kScatterSegs * 3];  // SH basis of its ray (9 of 12 floats)
     __shared__ int s_cnt[kBrickCells];         // samples per cell
     __shared__ int s_coff[kBrickCells + 1];    // first sorted position of each cell
-    __shared__ LdsSample s_rec[kScatterCap];   // the pass's samples, sorted by cell
-    __shared__ float s_stage[kWavesPerBlock * kStageRows * kStageStride];
+    __shared__ LdsSample s_rec[kScatterCap];   // the pass's samples
+    __shared__ float s_stage[kScatterThreads / kWave * kStageRows * kStageStride];
 
     if (blockIdx.x >= (unsigned)a.n_brick) return;
     const int t = threadIdx.x;
+    float *s_y = reinterpret_cast<float *>(s_y4);
     float *stage = s_stage + (t / kWave) * kStageRows * kStageStride;
     // brick coordinates from its position in the binning order
     const int64_t jo = a.blist[blockIdx.x];
@@ -1593,7 +1562,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
     int vid[kVoxRounds];
 #pragma unroll
     for (int rr = 0; rr < kVoxRounds; ++rr) {
-        const int p = t + rr * kThreads;
+        const int p = t + rr * kScatterThreads;
         vid[rr] = -1;
         if (p < kBrickVox) {
             const int X = bxyz[0] * PLX_BRICK + p / 81, Y = bxyz[1] * PLX_BRICK + (p / 9) % 9,
@@ -1601,41 +1570,55 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
             if (X < g.nx && Y < g.ny && Z < g.nz) vid[rr] = g.index[((int64_t)X * g.ny + Y) * g.nz + Z];
         }
     }
+    float ls = 0.0f;
 
-    for (int64_t c0 = seg0; c0 < seg1; c0 += kThreads) {
-        const int ns = (int)min((int64_t)kThreads, seg1 - c0);
+    for (int64_t c0 = seg0; c0 < seg1; c0 += kScatterSegs) {
+        // a group of up to kScatterSegs segments; lane t < ns walks segment t
+        const int ns = (int)min((int64_t)kScatterSegs, seg1 - c0);
         int occ = 0;
+        int4 sg = make_int4(0, 0, -1, 0);
+        SegState st = {};
         if (t < ns) {
             const int64_t i = c0 + t;
-            const int4 sg = a.bseg[i];
+            sg = a.bseg[i];
             float d[3] = {0.f, 0.f, 1.f};
             if (seg_valid(a, sg, a.n_seg)) {
                 occ = a.nocc[i];
                 d[0] = a.rays_d[3 * (int64_t)sg.x];
                 d[1] = a.rays_d[3 * (int64_t)sg.x + 1];
                 d[2] = a.rays_d[3 * (int64_t)sg.x + 2];
+                const float4 gg = a.g_ray[sg.x];
+                st.gr[0] = gg.x;
+                st.gr[1] = gg.y;
+                st.gr[2] = gg.z;
+                st.tau_after = a.tau_in[sg.w] + a.tau_seg[sg.w];
+                st.gR = a.gr_after[sg.w] - gg.w;  // the beta factor joins the running sum
+                st.T_after = expf(-(float)st.tau_after);
             }
             s_soff[t] = a.soff[i];
-            sh_basis_all(d, s_y + t * 9);
+            sh_basis_all(d, s_y + t * 12);
         }
         int64_t tot64;
-        const int pre = (int)block_scan_excl(occ, &tot64);
+        const int pre = (int)block_scan_excl<kScatterThreads>(occ, &tot64);
         const int tot = (int)tot64;
-        s_pre[t] = pre;  // segments past ns hold the total
-        if (t == 0) s_pre[kThreads] = tot;
+        if (t < kScatterSegs) s_pre[t] = pre;  // segments past ns hold the total
+        if (t == 0) s_pre[kScatterSegs] = tot;
         __syncthreads();
 
-        for (int q0 = 0; q0 < tot; q0 += kScatterCap) {
+        // passes over the group's samples from the last one back, so that a
+        // segment longer than a pass meets its samples in reverse order
+        for (int q0 = ((tot - 1) / kScatterCap) * kScatterCap; tot > 0 && q0 >= 0; q0 -= kScatterCap) {
             const int nq = min(kScatterCap, tot - q0);
-            for (int c = t; c < kBrickCells; c += kThreads) s_cnt[c] = 0;
-            __syncthreads();
-            // count the pass's samples per cell; keep each one's cell, rank and slot
-            int cell_u[kScatterPer], rank_u[kScatterPer], seg_u[kScatterPer];
+            for (int c = t; c < kBrickCells; c += kScatterThreads) s_cnt[c] = 0;
+            // load the pass's samples (slots first, then all loads), count them
+            // per cell and leave them unsorted in LDS for the recurrence
+            int seg_u[kScatterPer];
             int64_t slot_u[kScatterPer];
 #pragma unroll
             for (int u = 0; u < kScatterPer; ++u) {
-                const int q = u * kThreads + t;
-                cell_u[u] = -1;
+                const int q = u * kScatterThreads + t;
+                seg_u[u] = -1;
+                slot_u[u] = 0;
                 if (q < nq) {
                     const int qq = q0 + q;
                     int lo = 0, hi = ns - 1;  // last segment whose first sample is <= qq
@@ -1644,37 +1627,84 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
                         if (s_pre[mid] <= qq) lo = mid;
                         else hi = mid - 1;
                     }
-                    slot_u[u] = s_soff[lo] + (qq - s_pre[lo]);
                     seg_u[u] = lo;
-                    const int cell = __float_as_int(a.srec[slot_u[u]].pos.w) & (kBrickCells - 1);
-                    cell_u[u] = cell;
-                    rank_u[u] = atomicAdd(&s_cnt[cell], 1);
+                    slot_u[u] = s_soff[lo] + (qq - s_pre[lo]);
+                }
+            }
+            SampleRec rec_u[kScatterPer];
+#pragma unroll
+            for (int u = 0; u < kScatterPer; ++u)
+                if (seg_u[u] >= 0) rec_u[u] = a.srec[slot_u[u]];
+            __syncthreads();  // s_cnt cleared; the previous pass's LDS reads done
+            int cell_u[kScatterPer], rank_u[kScatterPer];
+#pragma unroll
+            for (int u = 0; u < kScatterPer; ++u) {
+                if (seg_u[u] >= 0) {
+                    const int code = __float_as_int(rec_u[u].pos.w);
+                    cell_u[u] = code & (kBrickCells - 1);
+                    rank_u[u] = atomicAdd(&s_cnt[cell_u[u]], 1);
+                    LdsSample &ls_q = s_rec[u * kScatterThreads + t];
+                    ls_q.f[0] = rec_u[u].pos.x;
+                    ls_q.f[1] = rec_u[u].pos.y;
+                    ls_q.f[2] = rec_u[u].pos.z;
+                    ls_q.v[0] = rec_u[u].val.x;
+                    ls_q.v[1] = rec_u[u].val.y;
+                    ls_q.v[2] = rec_u[u].val.z;
+                    ls_q.v[3] = rec_u[u].val.w;
+                    ls_q.seg = code;
                 }
             }
             __syncthreads();
             {
-                const int a0 = s_cnt[2 * t], a1 = s_cnt[2 * t + 1];
+                static_assert(kScatterThreads == kBrickCells, "one cell per thread");
                 int64_t all;
-                const int ex = (int)block_scan_excl(a0 + a1, &all);
-                s_coff[2 * t] = ex;
-                s_coff[2 * t + 1] = ex + a0;
+                s_coff[t] = (int)block_scan_excl<kScatterThreads>(s_cnt[t], &all);
                 if (t == 0) s_coff[kBrickCells] = (int)all;
             }
+            // the reverse recurrence of each segment over its samples of the pass
+            if (t < ns && occ > 0) {
+                const int e_lo = max(s_pre[t], q0) - q0, e_hi = min(s_pre[t] + occ, q0 + nq) - q0;
+                if (e_lo < e_hi) {
+                    float o[3], d[3];
+                    load_ray_lane(a, sg.x, o, d);
+                    RayGeom r;
+                    const int n = ray_setup(g, o, d, r);
+                    (void)n;
+                    for (int e = e_hi - 1; e >= e_lo; --e) {
+                        LdsSample &sm = s_rec[e];
+                        const int k = (unsigned)sm.seg >> 9;
+                        const float delta = sample_at(g, r, k).delta;
+                        const Q4 v = {sm.v[0], sm.v[1], sm.v[2], sm.v[3]};
+                        const float sd = fmaxf(v.s, 0.0f) * delta;
+                        const double tau_before = fmax(st.tau_after - (double)sd, 0.0);
+                        const float T_before = expf(-(float)tau_before);
+                        const float wk = T_before * (-expm1f(-sd));
+                        const float gc = st.gr[0] * fmaxf(v.r, 0.0f) + st.gr[1] * fmaxf(v.g, 0.0f) +
+                                         st.gr[2] * fmaxf(v.b, 0.0f);
+                        const float cs = CAUCHY ? cauchy_grad(a.pri, v.s, &ls) : 0.0f;
+                        sm.v[0] = v.s > 0.0f ? delta * (st.T_after * gc - st.gR) + cs : 0.0f;
+                        sm.v[1] = v.r > 0.0f ? wk * st.gr[0] : 0.0f;
+                        sm.v[2] = v.g > 0.0f ? wk * st.gr[1] : 0.0f;
+                        sm.v[3] = v.b > 0.0f ? wk * st.gr[2] : 0.0f;
+                        st.gR += wk * gc;
+                        st.tau_after = tau_before;
+                        st.T_after = T_before;
+                    }
+                }
+            }
             __syncthreads();
-            // place the samples in cell order
+            // sort by cell: each thread takes its samples (now with their
+            // gradients) back, then puts every one in its cell's range
+            LdsSample mine[kScatterPer];
+#pragma unroll
+            for (int u = 0; u < kScatterPer; ++u)
+                if (seg_u[u] >= 0) mine[u] = s_rec[u * kScatterThreads + t];
+            __syncthreads();
 #pragma unroll
             for (int u = 0; u < kScatterPer; ++u) {
-                if (cell_u[u] >= 0) {
-                    const SampleRec sr = a.srec[slot_u[u]];
-                    LdsSample &ls = s_rec[s_coff[cell_u[u]] + rank_u[u]];
-                    ls.f[0] = sr.pos.x;
-                    ls.f[1] = sr.pos.y;
-                    ls.f[2] = sr.pos.z;
-                    ls.g[0] = sr.grad.x;
-                    ls.g[1] = sr.grad.y;
-                    ls.g[2] = sr.grad.z;
-                    ls.g[3] = sr.grad.w;
-                    ls.seg = seg_u[u];
+                if (seg_u[u] >= 0) {
+                    mine[u].seg = seg_u[u];
+                    s_rec[s_coff[cell_u[u]] + rank_u[u]] = mine[u];
                 }
             }
             __syncthreads();
@@ -1682,7 +1712,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
             // each lane sums its voxels' contributions and flushes them
 #pragma unroll 1
             for (int rr = 0; rr < kVoxRounds; ++rr) {
-                const int p = t + rr * kThreads;
+                const int p = t + rr * kScatterThreads;
                 float acc[28];
 #pragma unroll
                 for (int v = 0; v < 28; ++v) acc[v] = 0.0f;
@@ -1704,16 +1734,17 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
                             const float wy = oy ? sr.f[1] : 1.0f - sr.f[1];
                             const float wz = oz ? sr.f[2] : 1.0f - sr.f[2];
                             const float w = wx * wy * wz;
-                            const float *yy = s_y + sr.seg * 9;
-                            const float a_r = w * sr.g[1], a_g = w * sr.g[2], a_b = w * sr.g[3];
+                            const float4 y0 = s_y4[sr.seg * 3], y1 = s_y4[sr.seg * 3 + 1],
+                                         y2 = s_y4[sr.seg * 3 + 2];
+                            const float yy[9] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w, y2.x};
+                            const float a_r = w * sr.v[1], a_g = w * sr.v[2], a_b = w * sr.v[3];
 #pragma unroll
                             for (int l = 0; l < 9; ++l) {
-                                const float yl = yy[l];
-                                acc[l] += a_r * yl;
-                                acc[9 + l] += a_g * yl;
-                                acc[18 + l] += a_b * yl;
+                                acc[l] += a_r * yy[l];
+                                acc[9 + l] += a_g * yy[l];
+                                acc[18 + l] += a_b * yy[l];
                             }
-                            acc[27] += w * sr.g[0];
+                            acc[27] += w * sr.v[0];
                             any = true;
                         }
                     }
@@ -1723,6 +1754,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter_kernel(GridDev g, BinArg
             __syncthreads();
         }
     }
+    if (CAUCHY) add_prior_loss(a.pri, ls, 0.0);
 }
 
 // ------------------------------------------------------------ maximum sample weight
@@ -2276,7 +2308,11 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
         return check_launch(fn);
     }
     if (a.n_seg > 0) {
-        PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT><<<as.nb8, kThreads, 0, s>>>(g, as));
+        if (MODE != MODE_FWD && a.srec) {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
+        } else {
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, false><<<as.nb8, kThreads, 0, s>>>(g, as));
+        }
         if ((rc = check_launch(fn))) return rc;
     }
     if ((rc = mark_event(a.events, 1, s, fn))) return rc;
@@ -2284,17 +2320,13 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     if ((rc = check_launch(fn))) return rc;
     if ((rc = mark_event(a.events, 2, s, fn))) return rc;
     if (MODE != MODE_FWD && a.n_seg > 0 && a.srec) {
-        // recorded backward: replay into the sample buffer, then one scatter
-        // workgroup per brick (the Cauchy prior's per-sample terms only in an
-        // instance of their own)
-        if (as.pri.lambda_s != 0.0f) {
-            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_rec_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
-        } else {
-            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_bwd_rec_kernel<DT, false><<<as.nb8, kThreads, 0, s>>>(g, as));
-        }
-        if ((rc = check_launch(fn))) return rc;
+        // recorded backward: one scatter workgroup per brick (the Cauchy
+        // prior's per-sample terms only in an instance of their own)
         if (a.n_brick > 0) {
-            seg_scatter_kernel<<<(unsigned)a.n_brick, kThreads, 0, s>>>(g, as);
+            if (as.pri.lambda_s != 0.0f)
+                seg_scatter_kernel<true><<<(unsigned)a.n_brick, kScatterThreads, 0, s>>>(g, as);
+            else
+                seg_scatter_kernel<false><<<(unsigned)a.n_brick, kScatterThreads, 0, s>>>(g, as);
             if ((rc = check_launch(fn))) return rc;
         }
     } else if (MODE != MODE_FWD && a.n_seg > 0) {
