@@ -13,9 +13,11 @@ the gather and segment lists of batch t+1 run on a second stream during step
 t (Trainer.run), and the timed region holds every part of every step.
 
 Prints one JSON line: whole-step Mrays/s; the roofline of the dominant kernel
-(seg_bwd, the segment backward: the algorithmic bytes of the backward pass
-from the library's work counters over its duration measured with HIP events
-recorded on its stream), with the per-kernel times and fractions beside it;
+of the fused render call (the longer of seg_fwd, the segment forward, and
+seg_scatter, the recorded backward: the algorithmic bytes of the forward or
+backward pass from the library's work counters over the kernel's duration
+measured with HIP events recorded on its stream), with the per-kernel times
+and fractions beside it;
 the same step with BF16/FP16 SH storage, with shuffled rays, without the
 second stream and with the sparsity and beta priors on; separate
 forward/backward with and without stored per-sample state; the
@@ -50,11 +52,14 @@ N_BLOBS = 32
 SEED = 2
 BATCH = 1 << 20
 N_CAMS, W, H = 100, 800, 800
-# HBM bytes per seg_bwd launch measured by rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (scaled by a plain copy's readings), with the hash of the kernel
-# source they were taken on; a changed source makes them stale (null).
-COUNTERS = os.path.join(ROOT, "profiles", "seg_bwd_512cubed_1Mrays_counters.json")
+# HBM bytes per launch of the render kernels measured by rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes (scaled by a plain copy's readings), with the hash of the
+# kernel source they were taken on; a changed source makes them stale (null).
+COUNTERS = os.path.join(ROOT, "profiles", "render_train_512cubed_1Mrays_counters.json")
 RENDER_SRC = os.path.join(ROOT, "paper_2112_05131_amd", "csrc", "render.hip")
+# kernels of one plx_render_train call, as rocprofv3 names them
+COUNTED_KERNELS = {"seg_fwd": "seg_fwd_kernel", "seg_combine": "seg_combine_kernel",
+                   "seg_scatter": "seg_scatter_kernel"}
 
 
 def log(*a):
@@ -65,21 +70,65 @@ def source_hash(path=RENDER_SRC) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(sh_dtype):
-    """(bytes per seg_bwd launch, source of the figure) from the committed
-    counter summary when it was taken on this kernel source, else (None,
-    reason)."""
+def measured_traffic(sh_dtype, kernel):
+    """(bytes per launch of `kernel`, source of the figure) from the
+    committed counter summary when it was taken on this kernel source, else
+    (None, reason)."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None, "no counter summary"
     key = {B.PLX_F32: "f32", B.PLX_BF16: "bf16", B.PLX_F16: "f16"}[sh_dtype]
-    e = c.get(key)
+    e = c.get(key, {}).get(kernel)
     if not e:
-        return None, f"no {key} counters"
-    if e.get("render_hip_sha16") != source_hash():
+        return None, f"no {key} {kernel} counters"
+    if c[key].get("render_hip_sha16") != source_hash():
         return None, "stale: render.hip changed since the counters were taken"
-    return e["fetch_bytes"] + e["write_bytes"], e.get("command", "")
+    return e["fetch_bytes"] + e["write_bytes"], c[key].get("command", "")
+
+
+def counters_summary(dtype, fetch_csv, write_csv):
+    """Per-launch HBM bytes of the render kernels from the counter_collection
+    CSVs of two rocprofv3 --pmc passes over `bench.py --counters` (FETCH_SIZE,
+    then WRITE_SIZE; KiB per dispatch summed over the L2 channels).  The last
+    dispatch of each kernel is the measured step's; the run's last dispatch is
+    the 1 GiB copy, whose readings scale the counters to bytes."""
+    import csv
+
+    def per_dispatch(path, counter):
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, val = rows.get(d, (r["Kernel_Name"], 0.0))
+            rows[d] = (name, val + float(r["Counter_Value"]))
+        return [rows[d] for d in sorted(rows)]
+
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    copy_kib = 1 << 20  # 1 GiB read and written by the copy
+    f_scale, w_scale = copy_kib / fetch[-1][1], copy_kib / write[-1][1]
+    out = {"render_hip_sha16": source_hash(),
+           "copy": {"kernel": fetch[-1][0][:80], "fetch_kib": fetch[-1][1], "write_kib": write[-1][1],
+                    "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
+           "command": (f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
+                       f"--counters --dtype {dtype}; python bench.py --counters-summary {dtype} "
+                       "<fetch counter_collection.csv> <write counter_collection.csv>")}
+    for key, name in COUNTED_KERNELS.items():
+        fk = [v for n, v in fetch if name in n]
+        wk = [v for n, v in write if name in n]
+        if fk and wk:
+            out[key] = {"fetch_kib": fk[-1], "write_kib": wk[-1],
+                        "fetch_bytes": int(fk[-1] * 1024 * f_scale), "write_bytes": int(wk[-1] * 1024 * w_scale)}
+    try:
+        allc = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        allc = {}
+    allc[dtype] = out
+    with open(COUNTERS, "w") as f:
+        json.dump(allc, f, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 class Workload:
@@ -316,6 +365,7 @@ def serving_leg(n_sat=400, n_load=2000):
     resident = sum(s.index.numel() * 4 + s.data.numel() * s.data.element_size() +
                    s.occ.numel() * 4 for s in scenes)
     log(f"serving scenes built in {time.time() - t0:.1f}s, resident {resident / 1e9:.2f} GB")
+    roof = views_roofline(scenes)
     srv = Server(scenes, hbm_budget=1 << 30, n_streams=4, max_batch=32, keep_outputs=False)
     run_load(srv, random_requests(16, 8, seed=99), None)  # warm-up
     reqs = random_requests(n_sat, 8, seed=100)
@@ -325,7 +375,7 @@ def serving_leg(n_sat=400, n_load=2000):
     out = {"scenes": "4x256^3 + 4x512^3, 5-10% occupancy, FP16 SH",
            "resident_gb": round(resident / 1e9, 3),
            "saturation_mrays_s": round(pix / wall / 1e6, 2),
-           "saturation_requests_s": round(sat_rps, 1), "loads": []}
+           "saturation_requests_s": round(sat_rps, 1), "views_kernel_roofline": roof, "loads": []}
     for frac in (0.5, 0.8, 0.95):
         reqs = random_requests(n_load, 8, seed=101 + int(frac * 100))
         lat, wall = run_load(srv, reqs, sat_rps * frac, seed=7)
@@ -340,9 +390,68 @@ def serving_leg(n_sat=400, n_load=2000):
     return out
 
 
+def view_rays(req):
+    """Rays of one view by the pinhole definition plx_render_views uses
+    (FP64, rounded to FP32), on the device: for the work counters only."""
+    dev = torch.device("cuda")
+    c2w = torch.tensor(np.asarray(req.c2w, np.float64).reshape(3, 4), dtype=torch.float64, device=dev)
+    py, px = torch.meshgrid(torch.arange(req.height, dtype=torch.float64, device=dev),
+                            torch.arange(req.width, dtype=torch.float64, device=dev), indexing="ij")
+    dc = torch.stack([(px + 0.5 - req.width / 2) / req.focal, -((py + 0.5 - req.height / 2) / req.focal),
+                      -torch.ones_like(px)], -1).reshape(-1, 3)
+    d = dc @ c2w[:, :3].T
+    d = (d / d.norm(dim=1, keepdim=True)).float().contiguous()
+    o = c2w[:, 3].float().expand_as(d).contiguous()
+    return o, d
+
+
+def views_roofline(scenes, reps=5):
+    """One launch of 8 views at 1920x1080 (one per scene): its duration (HIP
+    events on its stream, best of `reps`) against the algorithmic bytes of
+    its rays (per view 4 U_idx + P U_occ from the work counters, 12 B of
+    colour per pixel)."""
+    from paper_2112_05131_amd.serve import random_requests
+    reqs = random_requests(len(scenes), len(scenes), seed=77, resolutions=((1920, 1080),))
+    views, nbytes, off = [], 0, 0
+    P = 112 if scenes[0].sh_dtype == B.PLX_F32 else 58
+    for i, r in enumerate(reqs):
+        r.scene = i
+        v = B.PlxView()
+        v.c2w[:] = [float(x) for x in np.asarray(r.c2w, np.float64).reshape(12)]
+        v.focal, v.width, v.height, v.scene, v.reserved, v.out_offset = r.focal, r.width, r.height, i, 0, off
+        views.append(v)
+        off += r.n_pixels
+        o, d = view_rays(r)
+        g = scenes[i]
+        cm = torch.zeros((g.n_cells + 31) // 32, dtype=torch.int32, device="cuda")
+        vm = torch.zeros((g.n_vox + 31) // 32, dtype=torch.int32, device="cuda")
+        c = B.plx_render_stats(g.desc(), o, d, cm, vm)
+        nbytes += 4 * c[2] + P * c[3] + 12 * r.n_pixels
+        del o, d, cm, vm
+    table = B.SceneTable(scenes)
+    out = torch.empty(3 * off, device="cuda")
+    ws = B.workspace(B.plx_render_views_workspace(len(views)))
+    B.plx_render_views(table, views, out, ws)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        B.plx_render_views(table, views, out, ws)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    B.plx_render_views_status(ws, len(views))
+    gbs = nbytes / (best * 1e-3) / 1e9
+    log(f"views kernel: 8 x 1920x1080 in {best:.3f} ms, {gbs:.1f} GB/s algorithmic")
+    return {"launch": "8 views at 1920x1080, one per scene", "ms": round(best, 4),
+            "mrays_s": round(off / best / 1e3, 2), "algorithmic_gb": round(nbytes / 1e9, 4),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_model": "per view 4 U_idx + P U_occ (P = 58 B for FP16 SH) + 12 B per pixel"}
+
+
 def counter_run(sh_dtype, coherent):
     """Dispatch sequence for rocprofv3 --pmc passes: two warm-up steps, one
-    training step (its gather, segment lists, seg_fwd, seg_combine, seg_bwd,
+    training step (its gather, segment lists, seg_fwd, seg_combine, seg_scatter,
     tv and rmsprop kernels), then a 1 GiB device-to-device copy (1 GiB read
     + 1 GiB written) whose counter readings give the scale of FETCH_SIZE /
     WRITE_SIZE."""
@@ -422,10 +531,16 @@ def main():
                     help="for counter runs under rocprofv3: warm-up steps and one training "
                          "step, then a 1 GiB device copy that calibrates the byte counters; "
                          "prints no JSON line")
+    ap.add_argument("--counters-summary", nargs=3, metavar=("DTYPE", "FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-kernel HBM bytes of two --counters passes (rocprofv3 "
+                         "counter_collection.csv files) into the committed counter summary")
     ap.add_argument("--serving-only", action="store_true",
                     help="for trace runs under rocprofv3: only the serving leg, printed as its "
                          "own JSON object")
     args = ap.parse_args()
+    if args.counters_summary:
+        counters_summary(*args.counters_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the library has no multi-GPU path).", file=sys.stderr)
@@ -455,9 +570,19 @@ def main():
         + ", ".join(f"{k} {v:.3f}" for k, v in k_ms.items()))
 
     fwd_b, bwd_b, fused_b = byte_model(counts, BATCH, sh_dtype)
+    rec_b = 32 * counts[1]  # sample records: written by seg_fwd, read by seg_scatter
     gbs = lambda b, t_ms: b / (t_ms * 1e-3) / 1e9  # noqa: E731
-    achieved = gbs(bwd_b, k_ms["seg_bwd"])
-    traffic, traffic_src = measured_traffic(sh_dtype)
+    # the dominant kernel of the fused call and its algorithmic bytes
+    if k_ms["seg_fwd"] >= k_ms["seg_bwd"]:
+        dom, dom_ms, dom_b = "seg_fwd", k_ms["seg_fwd"], fwd_b
+        dom_desc = "seg_fwd (segment forward of plx_render_train, recording the occupied samples)"
+        dom_model = "forward: 4 U_idx + P U_occ + 40 R"
+    else:
+        dom, dom_ms, dom_b = "seg_scatter", k_ms["seg_bwd"], bwd_b
+        dom_desc = "seg_scatter (recorded backward of plx_render_train: recurrence + per-voxel sums)"
+        dom_model = "backward with recomputation: 4 U_idx + P U_occ + 224 U_occ + 28 R"
+    achieved = gbs(dom_b, dom_ms)
+    traffic, traffic_src = measured_traffic(sh_dtype, dom)
     alg_rms = n_act * (672 if sh_dtype == B.PLX_F32 else 726)
     alg_tv = 16 * tv_cells
     step_gbs = gbs(fwd_b + bwd_b + alg_rms + alg_tv, ms)
@@ -492,7 +617,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "seg_bwd (segment backward replay of plx_render_train)",
+            "kernel": dom_desc,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -500,12 +625,15 @@ def main():
             "traffic": round(traffic / 1e9, 3) if traffic else None,
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_source": traffic_src,
-            "algorithmic_gb": round(bwd_b / 1e9, 4),
-            "bytes_model": "backward with recomputation: 4 U_idx + P U_occ + 224 U_occ + 28 R",
+            "algorithmic_gb": round(dom_b / 1e9, 4),
+            "bytes_model": dom_model,
         },
         "kernels": {
-            "seg_fwd": frac(fwd_b, k_ms["seg_fwd"]),
-            "seg_bwd": frac(bwd_b, k_ms["seg_bwd"]),
+            "seg_fwd": dict(frac(fwd_b, k_ms["seg_fwd"]), bytes_model="forward: 4 U_idx + P U_occ + 40 R",
+                            sample_records_written_gb=round(rec_b / 1e9, 4)),
+            "seg_scatter": dict(frac(bwd_b, k_ms["seg_bwd"]),
+                                bytes_model="backward with recomputation: 4 U_idx + P U_occ + 224 U_occ + 28 R",
+                                sample_records_read_gb=round(rec_b / 1e9, 4)),
             "seg_combine_ms": round(k_ms["seg_combine"], 4),
             "render_train_call": dict(frac(fwd_b + bwd_b, k_ms["render_train"]),
                                       bytes_model="forward + backward with recomputation"),
@@ -525,7 +653,7 @@ def main():
         # state and accumulation in all three), the same batches
         prec = {args.dtype: {"ms_per_step": round(ms, 4), "mrays_s": round(mrays, 3),
                              "render_train_ms": round(k_ms["render_train"], 4),
-                             "seg_fwd_ms": round(k_ms["seg_fwd"], 4), "seg_bwd_ms": round(k_ms["seg_bwd"], 4)}}
+                             "seg_fwd_ms": round(k_ms["seg_fwd"], 4), "seg_scatter_ms": round(k_ms["seg_bwd"], 4)}}
         for name in ("f32", "bf16", "f16"):
             if name in prec:
                 continue
@@ -533,7 +661,7 @@ def main():
             ms2, _, k2 = time_steps(tr2, wl.sampler(coherent), 2, max(5, args.steps // 2))
             prec[name] = {"ms_per_step": round(ms2, 4), "mrays_s": round(BATCH / ms2 / 1e3, 3),
                           "render_train_ms": round(k2["render_train"], 4),
-                          "seg_fwd_ms": round(k2["seg_fwd"], 4), "seg_bwd_ms": round(k2["seg_bwd"], 4)}
+                          "seg_fwd_ms": round(k2["seg_fwd"], 4), "seg_scatter_ms": round(k2["seg_bwd"], 4)}
             log(f"{name}: step {ms2:.3f} ms, render_train {k2['render_train']:.3f} ms")
             del tr2
         for name in prec:

@@ -540,23 +540,44 @@ typedef struct plx_view {
     int64_t out_offset; /* index (in pixels) of this view's first pixel in rgb_out */
 } plx_view;
 
-/* Bytes of device workspace plx_render_views needs for these table sizes. */
-int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views);
+/* Scene table: the device copy of the descriptors of n_scenes resident scenes
+ * (one sh_dtype, occupancy built) that plx_render_views renders from.  Its
+ * size; and the call that writes it into `table` (device, 256-byte aligned,
+ * plx_scene_table_bytes bytes), asynchronously on `stream` (the descriptors
+ * travel as kernel arguments: no copy engine, and the host array may be
+ * released on return).  Write it again after a scene's grid changes. */
+int64_t plx_scene_table_bytes(int32_t n_scenes);
+int plx_scene_table_set(const plx_grid *scenes, int32_t n_scenes, void *table, int64_t table_bytes,
+                        plx_stream stream);
+
+/* Bytes of device workspace plx_render_views needs for n_views views (the
+ * tile queue counter, a status word, tile offsets and the view table). */
+int64_t plx_render_views_workspace(int32_t n_views);
 
 /* Renders a batch of novel views of resident scenes in one launch (the
  * forward model of plx_render_fwd, Sec. 3.1-3.3, with rays generated on the
  * device; interactive rendering is claimed in Sec. 1).  The views may mix
- * scenes and resolutions.  All pixels of all views form one queue of 16x16-pixel
- * tiles drained by a persistent grid, so the colour of a pixel depends only on
- * its ray and scene, never on the rest of the batch.  scenes (host array of
- * n_scenes descriptors, one sh_dtype, occupancy built) and views (host array)
- * are copied into `workspace` (device, plx_render_views_workspace bytes); the
- * call waits for that copy on `stream` (work queued before it on `stream`
- * completes first) and then enqueues the render.  rgb_out: device float32,
- * 3 floats per pixel at 3*(out_offset + py*width + px). */
-int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *views,
+ * scenes and resolutions.  All pixels of all views form one queue of
+ * 16x16-pixel tiles drained by a persistent grid, so the colour of a pixel
+ * depends only on its ray and scene, never on the rest of the batch.
+ * scene_table: written by plx_scene_table_set for n_scenes scenes of storage
+ * type sh_dtype.  views: host array, validated here (scene index, size,
+ * focal, offset) and passed to the device as kernel arguments into
+ * `workspace` (device, 256-byte aligned, plx_render_views_workspace bytes),
+ * which also holds the tile queue, reset by a kernel (no memset).  Never
+ * allocates, copies through a copy engine or synchronises: the views array
+ * may be released on return.  A table that is not of sh_dtype (or holds
+ * fewer scenes than a view names) renders nothing for those views and sets
+ * the status word that plx_render_views_status reads.  rgb_out: device
+ * float32, 3 floats per pixel at 3*(out_offset + py*width + px).  Calls that
+ * share a workspace must be ordered on one stream. */
+int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype, const plx_view *views,
                      int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
                      int64_t workspace_bytes, plx_stream stream);
+
+/* PLX_OK when the last plx_render_views call on `workspace` (n_views views)
+ * rendered every view, PLX_EINVAL otherwise.  Synchronising. */
+int plx_render_views_status(const void *workspace, int32_t n_views, plx_stream stream);
 
 /* Work counters of a ray batch, for bandwidth accounting (not timed work):
  * counts[0] = samples (all), counts[1] = samples in occupied cells,

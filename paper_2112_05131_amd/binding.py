@@ -153,8 +153,11 @@ _SIGS = {
     "plx_render_bwd_state": ([_GP, _OP, _P, _P, _I64, _P, _P, _P, _I64, _I32, _P, _P, _P],
                              ctypes.c_int),
     "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
-    "plx_render_views_workspace": ([_I32, _I32], _I64),
-    "plx_render_views": ([_GP, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
+    "plx_scene_table_bytes": ([_I32], _I64),
+    "plx_scene_table_set": ([_GP, _I32, _P, _I64, _P], ctypes.c_int),
+    "plx_render_views_workspace": ([_I32], _I64),
+    "plx_render_views": ([_P, _I32, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
+    "plx_render_views_status": ([_P, _I32, _P], ctypes.c_int),
     "plx_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_touched_count": ([_P, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "plx_rmsprop_step": ([_GP, _P, _P, _P, _P, _F, _F, _F, _F, _P], ctypes.c_int),
@@ -628,23 +631,50 @@ def plx_render_bwd_state(g: PlxGrid, rays_o, rays_d, grad_rgb, tau_fwd, state, c
                                       _dptr(touched, "touched", torch.uint8), _stream()))
 
 
-def plx_render_views_workspace(n_scenes: int, n_views: int) -> int:
-    return int(lib().plx_render_views_workspace(int(n_scenes), int(n_views)))
+class SceneTable:
+    """Device copy of the descriptors of resident scenes (plx_scene_table_set),
+    the scene argument of plx_render_views.  Keeps the grids referenced."""
+
+    def __init__(self, scenes, stream=None):
+        self.grids = list(scenes)
+        descs = [g.desc() for g in self.grids]
+        if not descs:
+            raise ValueError("need at least one scene")
+        self.n_scenes = len(descs)
+        self.sh_dtype = int(descs[0].sh_dtype)
+        self.buf = workspace(plx_scene_table_bytes(self.n_scenes), self.grids[0].device)
+        sc = (PlxGrid * self.n_scenes)(*descs)
+        s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        _check(lib().plx_scene_table_set(ctypes.cast(sc, _GP), self.n_scenes, _dptr(self.buf, "table", torch.uint8),
+                                         self.buf.numel(), s))
 
 
-def plx_render_views(scenes, views, rgb_out, workspace, bg=(1.0, 1.0, 1.0), stream=None):
-    """scenes: list of PlxGrid; views: list of PlxView; rgb_out: device
-    float32 tensor; workspace: device uint8 tensor of at least
+def plx_scene_table_bytes(n_scenes: int) -> int:
+    return int(lib().plx_scene_table_bytes(int(n_scenes)))
+
+
+def plx_render_views_workspace(n_views: int) -> int:
+    return int(lib().plx_render_views_workspace(int(n_views)))
+
+
+def plx_render_views(table: SceneTable, views, rgb_out, workspace, bg=(1.0, 1.0, 1.0), stream=None):
+    """table: SceneTable; views: list of PlxView; rgb_out: device float32
+    tensor; workspace: device uint8 tensor of at least
     plx_render_views_workspace bytes.  stream: a torch.cuda.Stream (default:
-    the current stream)."""
-    sc = (PlxGrid * len(scenes))(*scenes)
+    the current stream).  Asynchronous."""
     vw = (PlxView * max(len(views), 1))(*views)
     o = _opts(bg)
     s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-    _check(lib().plx_render_views(ctypes.cast(sc, _GP), len(scenes), ctypes.cast(vw, _P), len(views),
-                                  ctypes.byref(o), _dptr(rgb_out, "rgb_out", torch.float32),
+    _check(lib().plx_render_views(_dptr(table.buf, "table", torch.uint8), table.n_scenes, table.sh_dtype,
+                                  ctypes.cast(vw, _P), len(views), ctypes.byref(o),
+                                  _dptr(rgb_out, "rgb_out", torch.float32),
                                   _dptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
                                   s))
+
+
+def plx_render_views_status(workspace, n_views: int, stream=None):
+    s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    _check(lib().plx_render_views_status(_dptr(workspace, "workspace"), int(n_views), s))
 
 
 def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark, ws=None):

@@ -51,6 +51,7 @@
 // density slot of the same corner accumulators.
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -1901,16 +1902,74 @@ __device__ inline void camera_ray(const plx_view &v, int px, int py, float o[3],
 
 constexpr int kTileW = 16, kTileH = 16;  // pixels per tile = rays per block
 
+// Scene table (device, written by plx_scene_table_set): a 256-byte header,
+// then one GridDev per scene.
+constexpr unsigned kSceneMagic = 0x504c5853u;
+struct SceneTableHeader {
+    unsigned magic;
+    int n_scenes;
+    int sh_dtype;
+};
+constexpr int64_t kSceneTableHead = 256;
+
 struct ViewsArgs {
+    const SceneTableHeader *table;
     const GridDev *scenes;
     const plx_view *views;
     const int64_t *tile_start;  // [n_views + 1]
     unsigned long long *counter;
+    unsigned *status;
     int n_views;
     int64_t n_tiles;
     float bg[3];
     float *rgb_out;
 };
+
+// Views and scene descriptors reach the device as kernel arguments (no copy
+// engine, no host buffer that must outlive the call): each setup launch
+// writes up to kSetupItems entries into the workspace or the scene table.
+constexpr int kSetupItems = 24;
+
+struct ViewsSetupArgs {
+    plx_view v[kSetupItems];
+    int64_t tile_start[kSetupItems];
+    int first, count, n_views;
+    int64_t n_tiles;
+    plx_view *views;
+    int64_t *ws_tile_start;
+    unsigned long long *counter;
+    unsigned *status;
+};
+
+__global__ void views_setup_kernel(ViewsSetupArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.count) {
+        a.views[a.first + i] = a.v[i];
+        a.ws_tile_start[a.first + i] = a.tile_start[i];
+    }
+    if (a.first == 0 && i == 0) {
+        a.ws_tile_start[a.n_views] = a.n_tiles;
+        *a.counter = 0ull;
+        *a.status = 0u;
+    }
+}
+
+struct SceneSetupArgs {
+    GridDev g[kSetupItems];
+    int first, count, n_scenes, sh_dtype;
+    SceneTableHeader *table;
+    GridDev *scenes;
+};
+
+__global__ void scene_setup_kernel(SceneSetupArgs a) {
+    const int i = threadIdx.x;
+    if (i < a.count) a.scenes[a.first + i] = a.g[i];
+    if (a.first == 0 && i == 0) {
+        a.table->magic = kSceneMagic;
+        a.table->n_scenes = a.n_scenes;
+        a.table->sh_dtype = a.sh_dtype;
+    }
+}
 
 // Persistent tile queue over all pixels of all views of the launch: each block
 // takes the next 16x16-pixel tile, finds its view, generates the rays of its
@@ -1921,6 +1980,14 @@ template <int DT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void views_kernel(ViewsArgs a) {
     __shared__ long long tile_sh;
+    // a table of other scenes' storage type (or not a scene table): nothing
+    // is rendered and the status word says so
+    const unsigned magic = a.table->magic;
+    const int n_scenes = a.table->n_scenes, table_dt = a.table->sh_dtype;
+    if (magic != kSceneMagic || table_dt != DT) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.status = 1u;
+        return;
+    }
     while (true) {
         if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(a.counter, 1ull);
         __syncthreads();
@@ -1939,8 +2006,13 @@ void views_kernel(ViewsArgs a) {
         const int tpr = (width + kTileW - 1) / kTileW;
         const int px = (int)(tl % tpr) * kTileW + (int)(threadIdx.x % kTileW);
         const int py = (int)(tl / tpr) * kTileH + (int)(threadIdx.x / kTileW);
+        const int scene = uni(v.scene);
+        if (scene >= n_scenes) {
+            if (threadIdx.x == 0) *a.status = 1u;
+            continue;
+        }
         if (px < width && py < height) {
-            const GridDev g = uniform_grid(a.scenes[uni(v.scene)]);
+            const GridDev g = uniform_grid(a.scenes[scene]);
             float o[3], d[3];
             camera_ray(v, px, py, o, d);
             RayGeom r;
@@ -1961,16 +2033,16 @@ void views_kernel(ViewsArgs a) {
 }
 
 struct ViewsLayout {
-    int64_t counter, tile_start, scenes, views, bytes;
+    int64_t counter, status, tile_start, views, bytes;
 };
 
-ViewsLayout views_layout(int32_t n_scenes, int32_t n_views) {
+ViewsLayout views_layout(int32_t n_views) {
     auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
     ViewsLayout l;
     l.counter = 0;
+    l.status = 8;
     l.tile_start = 256;
-    l.scenes = l.tile_start + up((int64_t)(n_views + 1) * (int64_t)sizeof(int64_t));
-    l.views = l.scenes + up((int64_t)n_scenes * (int64_t)sizeof(GridDev));
+    l.views = l.tile_start + up((int64_t)(n_views + 1) * (int64_t)sizeof(int64_t));
     l.bytes = l.views + up((int64_t)n_views * (int64_t)sizeof(plx_view));
     return l;
 }
@@ -2698,65 +2770,127 @@ int plx_render_bwd_state(const plx_grid *grid, const plx_render_opts *opts, cons
     return launch_render<MODE_BWD, true>(grid, a, as_stream(stream), fn);
 }
 
-int64_t plx_render_views_workspace(int32_t n_scenes, int32_t n_views) {
-    if (n_scenes < 1 || n_views < 0) return 0;
-    return views_layout(n_scenes, n_views).bytes;
+int64_t plx_scene_table_bytes(int32_t n_scenes) {
+    if (n_scenes < 1) return 0;
+    return kSceneTableHead + (int64_t)n_scenes * (int64_t)sizeof(GridDev);
 }
 
-int plx_render_views(const plx_grid *scenes, int32_t n_scenes, const plx_view *views,
+int plx_scene_table_set(const plx_grid *scenes, int32_t n_scenes, void *table, int64_t table_bytes,
+                        plx_stream stream) {
+    const char *fn = "plx_scene_table_set";
+    if (!scenes || n_scenes < 1) return fail(PLX_EINVAL, "%s: need at least one scene", fn);
+    if (!table || reinterpret_cast<uintptr_t>(table) % 256)
+        return fail(PLX_EINVAL, "%s: table must be a 256-byte aligned device pointer", fn);
+    if (table_bytes < plx_scene_table_bytes(n_scenes))
+        return fail(PLX_EINVAL, "%s: table of %lld bytes, need %lld", fn, (long long)table_bytes,
+                    (long long)plx_scene_table_bytes(n_scenes));
+    const int32_t dt = scenes[0].sh_dtype;
+    for (int32_t i = 0; i < n_scenes; ++i) {
+        int rc = validate_grid(&scenes[i], true, fn);
+        if (rc) return rc;
+        if (scenes[i].sh_dtype != dt) return fail(PLX_EINVAL, "%s: scenes must share one sh_dtype", fn);
+    }
+    hipStream_t s = as_stream(stream);
+    SceneSetupArgs a = {};
+    a.n_scenes = n_scenes;
+    a.sh_dtype = dt;
+    a.table = static_cast<SceneTableHeader *>(table);
+    a.scenes = reinterpret_cast<GridDev *>(static_cast<char *>(table) + kSceneTableHead);
+    for (int32_t first = 0; first < n_scenes; first += kSetupItems) {
+        a.first = first;
+        a.count = std::min(kSetupItems, n_scenes - first);
+        for (int i = 0; i < a.count; ++i) a.g[i] = to_dev(&scenes[first + i]);
+        scene_setup_kernel<<<1, 32, 0, s>>>(a);
+        int rc = check_launch(fn);
+        if (rc) return rc;
+    }
+    return PLX_OK;
+}
+
+int64_t plx_render_views_workspace(int32_t n_views) {
+    if (n_views < 0) return 0;
+    return views_layout(n_views).bytes;
+}
+
+int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype, const plx_view *views,
                      int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
                      int64_t workspace_bytes, plx_stream stream) {
     const char *fn = "plx_render_views";
-    if (!scenes || n_scenes < 1) return fail(PLX_EINVAL, "%s: need at least one scene", fn);
+    if (!scene_table || n_scenes < 1) return fail(PLX_EINVAL, "%s: need a scene table of at least one scene", fn);
+    if (sh_dtype != PLX_F32 && sh_dtype != PLX_BF16 && sh_dtype != PLX_F16)
+        return fail(PLX_EINVAL, "%s: bad sh_dtype %d", fn, sh_dtype);
     if (n_views < 0) return fail(PLX_EINVAL, "%s: n_views < 0", fn);
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_views == 0) return PLX_OK;
     if (!views || !rgb_out || !workspace) return fail(PLX_EINVAL, "%s: NULL views/rgb_out/workspace", fn);
-    const ViewsLayout lay = views_layout(n_scenes, n_views);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(PLX_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+    const ViewsLayout lay = views_layout(n_views);
     if (workspace_bytes < lay.bytes)
         return fail(PLX_EINVAL, "%s: workspace of %lld bytes, need %lld", fn, (long long)workspace_bytes,
                     (long long)lay.bytes);
-    const int32_t dt = scenes[0].sh_dtype;
-    for (int32_t s = 0; s < n_scenes; ++s) {
-        int rc = validate_grid(&scenes[s], true, fn);
-        if (rc) return rc;
-        if (scenes[s].sh_dtype != dt) return fail(PLX_EINVAL, "%s: scenes must share one sh_dtype", fn);
-    }
-    // host image of the workspace: counter, tile offsets, scene and view tables
-    std::vector<unsigned char> img((size_t)lay.bytes, 0);
-    int64_t *tile_start = reinterpret_cast<int64_t *>(img.data() + lay.tile_start);
+    std::vector<int64_t> tile_start((size_t)n_views + 1);
     int64_t tiles = 0;
     for (int32_t i = 0; i < n_views; ++i) {
         const plx_view &v = views[i];
         if (v.scene < 0 || v.scene >= n_scenes) return fail(PLX_EINVAL, "%s: view %d: bad scene", fn, i);
         if (v.width < 1 || v.height < 1 || v.width > 65536 || v.height > 65536)
             return fail(PLX_EINVAL, "%s: view %d: bad size %dx%d", fn, i, v.width, v.height);
-        if (!(v.focal > 0.0) || v.out_offset < 0)
+        if (!(v.focal > 0.0) || !std::isfinite(v.focal) || v.out_offset < 0)
             return fail(PLX_EINVAL, "%s: view %d: bad focal or out_offset", fn, i);
         tile_start[i] = tiles;
         tiles += (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + kTileH - 1) / kTileH);
     }
     tile_start[n_views] = tiles;
-    GridDev *sc = reinterpret_cast<GridDev *>(img.data() + lay.scenes);
-    for (int32_t s = 0; s < n_scenes; ++s) sc[s] = to_dev(&scenes[s]);
-    memcpy(img.data() + lay.views, views, sizeof(plx_view) * (size_t)n_views);
     hipStream_t s = as_stream(stream);
-    PLX_CHECK_HIP(hipMemcpyAsync(workspace, img.data(), (size_t)lay.bytes, hipMemcpyHostToDevice, s), fn);
-    // the host image is released on return: wait for the copy
-    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
     char *ws = static_cast<char *>(workspace);
+    ViewsSetupArgs sa;
+    sa.n_views = n_views;
+    sa.n_tiles = tiles;
+    sa.views = reinterpret_cast<plx_view *>(ws + lay.views);
+    sa.ws_tile_start = reinterpret_cast<int64_t *>(ws + lay.tile_start);
+    sa.counter = reinterpret_cast<unsigned long long *>(ws + lay.counter);
+    sa.status = reinterpret_cast<unsigned *>(ws + lay.status);
+    for (int32_t first = 0; first < n_views; first += kSetupItems) {
+        sa.first = first;
+        sa.count = std::min(kSetupItems, n_views - first);
+        for (int i = 0; i < sa.count; ++i) {
+            sa.v[i] = views[first + i];
+            sa.tile_start[i] = tile_start[first + i];
+        }
+        views_setup_kernel<<<1, 32, 0, s>>>(sa);
+        int rc = check_launch(fn);
+        if (rc) return rc;
+    }
     ViewsArgs va;
-    va.counter = reinterpret_cast<unsigned long long *>(ws + lay.counter);
-    va.tile_start = reinterpret_cast<const int64_t *>(ws + lay.tile_start);
-    va.scenes = reinterpret_cast<const GridDev *>(ws + lay.scenes);
-    va.views = reinterpret_cast<const plx_view *>(ws + lay.views);
+    va.table = static_cast<const SceneTableHeader *>(scene_table);
+    va.scenes = reinterpret_cast<const GridDev *>(static_cast<const char *>(scene_table) + kSceneTableHead);
+    va.counter = sa.counter;
+    va.status = sa.status;
+    va.tile_start = sa.ws_tile_start;
+    va.views = sa.views;
     va.n_views = n_views;
     va.n_tiles = tiles;
     va.rgb_out = rgb_out;
     for (int i = 0; i < 3; ++i) va.bg[i] = opts->background[i];
     const int64_t nblk = tiles < 2048 ? tiles : 2048;  // persistent: 8 blocks per CU
-    PLX_DISPATCH_DT(dt, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
+    PLX_DISPATCH_DT(sh_dtype, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
     return check_launch(fn);
+}
+
+int plx_render_views_status(const void *workspace, int32_t n_views, plx_stream stream) {
+    const char *fn = "plx_render_views_status";
+    if (!workspace || n_views < 1) return fail(PLX_EINVAL, "%s: NULL workspace or no views", fn);
+    const ViewsLayout lay = views_layout(n_views);
+    hipStream_t s = as_stream(stream);
+    unsigned st = 0;
+    PLX_CHECK_HIP(hipMemcpyAsync(&st, static_cast<const char *>(workspace) + lay.status, sizeof(st),
+                                 hipMemcpyDeviceToHost, s), fn);
+    PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
+    if (st != 0)
+        return fail(PLX_EINVAL, "%s: the scene table is not one of this storage type, or a view named a "
+                                "scene beyond it; those views were not rendered", fn);
+    return PLX_OK;
 }
 
 int plx_render_stats(const plx_grid *grid, const float *rays_o, const float *rays_d,

@@ -75,12 +75,14 @@ class Server:
         if any(s.sh_dtype != dt for s in scenes):
             raise ValueError("scenes must share one SH storage type")
         self.scenes = scenes
-        self.descs = [s.desc() for s in scenes]
+        self.table = B.SceneTable(scenes)  # resident descriptors, written once
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
         self.bg = tuple(background)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        ws = B.plx_render_views_workspace(len(scenes), self.max_batch)
+        for st in self.streams:
+            st.wait_stream(torch.cuda.current_stream())  # the table is written
+        ws = B.plx_render_views_workspace(self.max_batch)
         self.workspaces = [torch.empty(ws, dtype=torch.uint8, device=scenes[0].device)
                            for _ in range(n_streams)]
         self.queue: deque[Request] = deque()
@@ -133,7 +135,7 @@ class Server:
                 off += r.n_pixels
                 views.append(v)
             t = time.perf_counter()
-            B.plx_render_views(self.descs, views, out, self.workspaces[si], self.bg, stream)
+            B.plx_render_views(self.table, views, out, self.workspaces[si], self.bg, stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         for r in batch:

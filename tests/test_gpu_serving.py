@@ -1,9 +1,12 @@
 """GPU tests of novel-view serving: plx_render_views against the FP64 oracle
-(camera rays from the same pinhole definition, rendered by the oracle), a
-view rendered alone versus inside mixed batches (bitwise equal: a pixel's
-colour depends only on its own ray and scene), and the continuous-batching
-server (every result equal to its stand-alone render, admission within the
-HBM budget)."""
+(camera rays from the same pinhole definition, rendered by the oracle) on
+small scenes and, on sampled pixels, at 1920x1080 on 512^3 and 256^3 FP16
+scenes; a view rendered alone versus inside mixed batches (bitwise equal: a
+pixel's colour depends only on its own ray and scene); a scene table of
+another storage type (nothing rendered, status raised); launches on two
+streams overlapping on the device; and the continuous-batching server
+(every result equal to its stand-alone render, admission within the HBM
+budget)."""
 import math
 
 import numpy as np
@@ -42,10 +45,9 @@ def _render(grids, reqs):
         views.append(_view(r, off))
         off += r.n_pixels
     out = torch.full((off * 3,), -1.0, device="cuda")
-    ws = torch.empty(B.plx_render_views_workspace(len(grids), len(views)), dtype=torch.uint8,
-                     device="cuda")
-    B.plx_render_views([g.desc() for g in grids], views, out, ws)
-    torch.cuda.synchronize()
+    ws = B.workspace(B.plx_render_views_workspace(len(views)))
+    B.plx_render_views(B.SceneTable(grids), views, out, ws)
+    B.plx_render_views_status(ws, len(views))
     res, off = [], 0
     for r in reqs:
         res.append(out[3 * off:3 * (off + r.n_pixels)].view(r.height, r.width, 3).clone())
@@ -97,3 +99,91 @@ def test_server_continuous_batching_results_and_budget():
     assert srv.in_use == 0 and not srv.inflight and not srv.queue
     with pytest.raises(ValueError):
         srv.submit(Request(0, reqs[0].c2w, 100.0, 1000, 1000))  # beyond the budget
+
+
+def test_views_c5_size_sampled_against_oracle():
+    """One launch with a 1920x1080 view of a 512^3 (5%) and of a 256^3 (10%)
+    FP16 scene (the serving configuration's largest requests); 1500 sampled
+    pixels of each against the oracle fed the stored FP16 coefficients."""
+    say("views at 1920x1080, sampled")
+    svs = [synth.blob_scene((512,) * 3, 32, 0.05, 3), synth.blob_scene((256,) * 3, 32, 0.10, 4)]
+    pairs = [make_pair(sv, sh_dtype=B.PLX_F16) for sv in svs]
+    ogs, grids = [p[0] for p in pairs], [p[1] for p in pairs]
+    reqs = random_requests(2, 2, seed=31, resolutions=((1920, 1080),))
+    reqs[0].scene, reqs[1].scene = 0, 1
+    outs = _render(grids, reqs)
+    rng = np.random.default_rng(32)
+    for r, img in zip(reqs, outs):
+        o, d = O.camera_rays(r.c2w, r.focal, r.width, r.height)
+        sel = np.sort(rng.choice(r.n_pixels, 1500, replace=False))
+        ref = O.render_fwd(ogs[r.scene], o[sel], d[sel])[0]
+        got = img.reshape(-1, 3)[torch.from_numpy(sel).cuda()].cpu().double().numpy()
+        err = np.abs(got - ref).max()
+        say(f"  scene {r.scene}: max |gpu - oracle| over 1500 pixels = {err:.2e}")
+        assert err <= RGB_ATOL, err
+        assert torch.all(img >= 0)  # every pixel written
+
+
+def test_scene_table_of_another_storage_type_renders_nothing():
+    say("views: table / dtype mismatch")
+    _, grids = _scenes(B.PLX_F32)
+    table = B.SceneTable(grids)
+    reqs = random_requests(2, 2, seed=9, resolutions=((40, 30),))
+    views = [_view(reqs[0], 0), _view(reqs[1], reqs[0].n_pixels)]
+    out = torch.full((3 * sum(r.n_pixels for r in reqs),), -1.0, device="cuda")
+    ws = B.workspace(B.plx_render_views_workspace(len(views)))
+    table.sh_dtype = B.PLX_F16  # claims FP16 over an FP32 table
+    B.plx_render_views(table, views, out, ws)
+    with pytest.raises(B.PlxError, match="not rendered"):
+        B.plx_render_views_status(ws, len(views))
+    assert torch.all(out == -1.0)
+    table.sh_dtype = B.PLX_F32
+    B.plx_render_views(table, views, out, ws)
+    B.plx_render_views_status(ws, len(views))
+    assert torch.all(out >= 0.0)
+
+
+def test_launches_on_two_streams_overlap():
+    """Two launches issued on two streams run at the same time: their
+    common span is well below the sum of their stand-alone durations (each
+    launch holds fewer tiles than the device has workgroup slots)."""
+    say("views: two streams overlap")
+    grids = [make_pair(synth.blob_scene((192,) * 3, 16, 0.2, s))[1] for s in (41, 42)]
+    table = B.SceneTable(grids)
+    reqs = random_requests(2, 2, seed=43, resolutions=((288, 288),))
+    reqs[0].scene, reqs[1].scene = 0, 1
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(3 * r.n_pixels, device="cuda") for r in reqs]
+    wss = [B.workspace(B.plx_render_views_workspace(1)) for _ in reqs]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def alone(i):
+        best = float("inf")
+        for _ in range(5):
+            a, b = ev(), ev()
+            a.record(streams[i])
+            B.plx_render_views(table, [_view(reqs[i])], outs[i], wss[i], stream=streams[i])
+            b.record(streams[i])
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return best
+
+    d0, d1 = alone(0), alone(1)
+    spans = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        start, e0, e1 = ev(), ev(), ev()
+        main = torch.cuda.current_stream()
+        start.record(main)
+        for i, st in enumerate(streams):
+            st.wait_event(start)
+            B.plx_render_views(table, [_view(reqs[i])], outs[i], wss[i], stream=st)
+        e0.record(streams[0])
+        e1.record(streams[1])
+        torch.cuda.synchronize()
+        spans.append(max(start.elapsed_time(e0), start.elapsed_time(e1)))
+    span = min(spans)
+    say(f"  alone {d0:.3f} + {d1:.3f} ms, together {span:.3f} ms")
+    assert span < 0.8 * (d0 + d1), (span, d0, d1)

@@ -358,3 +358,49 @@ def test_static_training_call_refuses_batches_beyond_its_scratch():
                                      None) == B.PLX_EINVAL
     assert L.plx_render_train_static(ctypes.byref(g), ctypes.byref(opts), None, None, None, 0, 1.0, None,
                                      None, None, None, None) == B.PLX_OK
+
+
+def test_views_and_scene_table_validation():
+    """plx_scene_table_set / plx_render_views reject bad tables, views and
+    workspaces before any launch; the workspace size is the counter block,
+    the tile offsets and the view table."""
+    L = B.lib()
+    p = ctypes.c_void_p
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert B.plx_render_views_workspace(0) == 256 + 256
+    assert B.plx_render_views_workspace(3) == 256 + up(4 * 8) + up(3 * ctypes.sizeof(B.PlxView))
+    assert B.plx_render_views_workspace(-1) == 0
+    assert B.plx_scene_table_bytes(0) == 0 and B.plx_scene_table_bytes(2) > B.plx_scene_table_bytes(1) > 256
+    g = _grid_desc()
+    gs = (B.PlxGrid * 1)(g)
+    need_t = B.plx_scene_table_bytes(1)
+    for table, nbytes, needle in [(None, need_t, "table"), (0x100040, need_t, "aligned"),
+                                  (0x100000, need_t - 1, "need")]:
+        rc = L.plx_scene_table_set(ctypes.cast(gs, ctypes.POINTER(B.PlxGrid)), 1, p(table) if table else None,
+                                   nbytes, None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
+    opts = B.PlxRenderOpts((ctypes.c_float * 3)(1, 1, 1))
+
+    def view(**kw):
+        v = B.PlxView()
+        v.c2w[:] = [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 2]
+        v.focal, v.width, v.height, v.scene, v.out_offset = 50.0, 32, 16, 0, 0
+        for k, x in kw.items():
+            setattr(v, k, x)
+        return v
+
+    need_w = B.plx_render_views_workspace(1)
+    cases = [(dict(scene=1), dict(), "bad scene"), (dict(scene=-1), dict(), "bad scene"),
+             (dict(width=0), dict(), "bad size"), (dict(height=70000), dict(), "bad size"),
+             (dict(focal=0.0), dict(), "focal"), (dict(focal=float("nan")), dict(), "focal"),
+             (dict(out_offset=-1), dict(), "out_offset"),
+             (dict(), dict(ws=0x200040), "aligned"), (dict(), dict(wsb=need_w - 1), "need"),
+             (dict(), dict(dt=7), "sh_dtype"), (dict(), dict(table=None), "scene table"),
+             (dict(), dict(n_scenes=0), "scene table")]
+    for vkw, kw, needle in cases:
+        vs = (B.PlxView * 1)(view(**vkw))
+        rc = L.plx_render_views(p(kw.get("table", 0x100000)) if kw.get("table", 1) else None,
+                                kw.get("n_scenes", 1), kw.get("dt", B.PLX_F32), ctypes.cast(vs, p), 1,
+                                ctypes.byref(opts), p(0x300000), p(kw.get("ws", 0x200000)),
+                                kw.get("wsb", need_w), None)
+        assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
