@@ -857,6 +857,8 @@ void render_bwd_kernel(GridDev g, RenderArgs a) {
 constexpr int kLenClasses = 8;
 constexpr int kLenStep = 4;
 constexpr int kTile = 4;
+constexpr int kBrickCells = PLX_BRICK * PLX_BRICK * PLX_BRICK;           // 512
+constexpr int kBrickVox = (PLX_BRICK + 1) * (PLX_BRICK + 1) * (PLX_BRICK + 1);  // 729 corner voxels
 
 inline int tiles_along(int bricks) { return (bricks + kTile - 1) / kTile; }
 // Number of (brick, class) bins: brick order positions times classes.
@@ -1227,6 +1229,202 @@ void seg_fwd_kernel(GridDev g, BinArgs a) {
     if (REC) a.nocc[i] = (int)min((int64_t)j, room);
 }
 
+// ------------------------------------------------------------ brick-staged forward
+//
+// The segments of one brick read the same (at most 9^3) corner records, and
+// at the training workload about 240 bricks are in flight per XCD at once,
+// several times what its 4 MB L2 holds, so the lane-per-segment forward
+// fetches each record from HBM several times.  The staged forward gives each
+// brick with segments one workgroup: the brick's corner records are loaded
+// once, coalesced, into LDS, and the workgroup's lanes march the brick's
+// segments (one lane each) with the corner fetches served from LDS.  The
+// arithmetic is that of seg_fwd.  It serves the 16-bit storage types; FP32
+// records need 82 KB of LDS per brick, which leaves one workgroup (about two
+// busy waves) per CU, and there the lane-per-segment kernel wins.
+
+// 16-byte words of a staged record: FP32 slots 0..26 and the density in
+// word 6's last float (28 floats); the 64-byte 16-bit record as stored.
+template <int DT> struct StagedRec {
+    static constexpr int kWords = DT == PLX_F32 ? 7 : 4;
+};
+
+template <int DT>
+__device__ __forceinline__ Q4 project_staged(const uint4 *w4, const float y[9]) {
+    if constexpr (DT == PLX_F32) {
+        float v[28];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            const uint4 t = w4[i];
+            v[4 * i] = __uint_as_float(t.x);
+            v[4 * i + 1] = __uint_as_float(t.y);
+            v[4 * i + 2] = __uint_as_float(t.z);
+            v[4 * i + 3] = __uint_as_float(t.w);
+        }
+        Q4 q;
+        q.s = v[27];
+        q.r = 0.0f;
+        q.g = 0.0f;
+        q.b = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            q.r += y[l] * v[l];
+            q.g += y[l] * v[9 + l];
+            q.b += y[l] * v[18 + l];
+        }
+        return q;
+    } else {
+        uint32_t w[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint4 t = w4[i];
+            w[4 * i] = t.x;
+            w[4 * i + 1] = t.y;
+            w[4 * i + 2] = t.z;
+            w[4 * i + 3] = t.w;
+        }
+        Q4 q;
+        q.s = __uint_as_float(w[14]);
+        q.r = 0.0f;
+        q.g = 0.0f;
+        q.b = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            q.r += y[l] * Project16<DT>::slot(w, l);
+            q.g += y[l] * Project16<DT>::slot(w, 9 + l);
+            q.b += y[l] * Project16<DT>::slot(w, 18 + l);
+        }
+        return q;
+    }
+}
+
+// move_to of the staged forward: cc.ids hold brick-local lattice positions
+// (x*81 + y*9 + z) of non-NULL corners, -1 for NULL ones.
+template <int DT>
+__device__ __forceinline__ void move_staged(CornerCache &cc, const int cell[3], const int b0[3],
+                                            const uint4 *s_rec, const int *s_id, const float y[9]) {
+    const int dx = cell[0] - cc.cell[0], dy = cell[1] - cc.cell[1], dz = cell[2] - cc.cell[2];
+    if (dx == 0 && dy == 0 && dz == 0) return;
+    const bool had = cc.cell[0] >= 0;
+    const bool adj = had && abs(dx) + abs(dy) + abs(dz) == 1;
+    const int bit = dx != 0 ? 4 : (dy != 0 ? 2 : 1);
+    const bool plus = dx + dy + dz > 0;
+    unsigned keep = 0;
+    if (adj) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (((c & bit) != 0) != plus) keep |= 1u << c;
+        Q4 unused[8];
+        if (bit == 4) swap_faces<4, false>(cc, unused);
+        else if (bit == 2) swap_faces<2, false>(cc, unused);
+        else swap_faces<1, false>(cc, unused);
+    }
+    cc.cell[0] = cell[0];
+    cc.cell[1] = cell[1];
+    cc.cell[2] = cell[2];
+    const int lx = cell[0] - b0[0], ly = cell[1] - b0[1], lz = cell[2] - b0[2];
+    const bool inside = (unsigned)lx < PLX_BRICK && (unsigned)ly < PLX_BRICK && (unsigned)lz < PLX_BRICK;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (!((keep >> c) & 1u)) {
+            const int p = (lx + ((c >> 2) & 1)) * 81 + (ly + ((c >> 1) & 1)) * 9 + (lz + (c & 1));
+            const bool has = inside && s_id[p] >= 0;
+            cc.ids[c] = has ? p : -1;
+            cc.q[c] = has ? project_staged<DT>(s_rec + p * StagedRec<DT>::kWords, y) : q4_zero();
+        }
+    }
+}
+
+template <int DT, bool REC>
+__global__ __launch_bounds__(kThreads) void seg_fwd_brick_kernel(GridDev g, BinArgs a) {
+    constexpr int W = StagedRec<DT>::kWords;
+    __shared__ uint4 s_rec[kBrickVox * W];
+    __shared__ int s_id[kBrickVox];
+    if (blockIdx.x >= (unsigned)a.n_brick) return;
+    const int t = threadIdx.x;
+    const int64_t jo = a.blist[blockIdx.x];
+    const int nty = (g.by + kTile - 1) / kTile, ntz = (g.bz + kTile - 1) / kTile;
+    const int64_t tile = jo / (kTile * kTile * kTile);
+    const int in = (int)(jo % (kTile * kTile * kTile));
+    const int b0[3] = {((int)(tile / ((int64_t)nty * ntz)) * kTile + in / (kTile * kTile)) * PLX_BRICK,
+                       ((int)((tile / ntz) % nty) * kTile + (in / kTile) % kTile) * PLX_BRICK,
+                       ((int)(tile % ntz) * kTile + in % kTile) * PLX_BRICK};
+    const int64_t seg0 = a.boff[jo * kLenClasses], seg1 = a.boff[(jo + 1) * kLenClasses];
+
+    // stage the brick's corner records
+    for (int p = t; p < kBrickVox; p += kThreads) {
+        const int X = b0[0] + p / 81, Y = b0[1] + (p / 9) % 9, Z = b0[2] + p % 9;
+        s_id[p] = (X < g.nx && Y < g.ny && Z < g.nz) ? g.index[((int64_t)X * g.ny + Y) * g.nz + Z] : -1;
+    }
+    __syncthreads();
+    for (int k = t; k < kBrickVox * W; k += kThreads) {
+        const int p = k / W, w = k - p * W;
+        const int id = s_id[p];
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (id >= 0) {
+            if constexpr (DT == PLX_F32) {
+                const float *rec = static_cast<const float *>(g.data) + (int64_t)id * PLX_REC_SLOTS;
+                v = reinterpret_cast<const uint4 *>(rec)[w];
+                if (w == 6) v.w = __float_as_uint(rec[PLX_SLOT_SIGMA]);  // slot 27 is padding
+            } else {
+                v = reinterpret_cast<const uint4 *>(static_cast<const char *>(g.data) +
+                                                    (int64_t)id * kRec16Bytes)[w];
+            }
+        }
+        s_rec[k] = v;
+    }
+    __syncthreads();
+
+    // march the brick's segments, one lane each
+    for (int64_t i = seg0 + t; i < seg1; i += kThreads) {
+        const int4 sg = a.bseg[i];
+        if (!seg_valid(a, sg, a.n_seg)) continue;
+        float o[3], d[3];
+        load_ray_lane(a, sg.x, o, d);
+        RayGeom r;
+        const int n = ray_setup(g, o, d, r);
+        float y[9];
+        sh_basis_all(d, y);
+        CornerCache cc;
+        cc.cell[0] = cc.cell[1] = cc.cell[2] = -1;
+        SpanCursor cur{sg.y, 0, 0u};
+        double tau = 0.0;
+        float C[3] = {0.0f, 0.0f, 0.0f};
+        int64_t base = 0, room = 0;
+        if (REC) {
+            base = a.soff[i];
+            room = (int64_t)sg.z - sg.y + 1;
+            if (base < 0 || base + room > a.samp_cap) room = 0;
+        }
+        int j = 0;
+        while (true) {
+            const int k = span_next_up(g, r, n, sg.z, cur);
+            if (k < 0) break;
+            const Sample s = sample_at(g, r, k);
+            move_staged<DT>(cc, s.cell, b0, s_rec, s_id, y);
+            float w[8];
+            corner_weights(s.f, w);
+            const Q4 v = interpolate(cc, w);
+            if (REC && j < room) {
+                const int code = (k << 9) | ((s.cell[0] & (PLX_BRICK - 1)) << 6) |
+                                 ((s.cell[1] & (PLX_BRICK - 1)) << 3) | (s.cell[2] & (PLX_BRICK - 1));
+                SampleRec *rec = a.srec + base + j;
+                rec->pos = make_float4(s.f[0], s.f[1], s.f[2], __int_as_float(code));
+                rec->val = make_float4(v.s, v.r, v.g, v.b);
+            }
+            ++j;
+            const float sd = fmaxf(v.s, 0.0f) * s.delta;
+            const float wk = expf(-(float)tau) * (-expm1f(-sd));
+            C[0] += wk * fmaxf(v.r, 0.0f);
+            C[1] += wk * fmaxf(v.g, 0.0f);
+            C[2] += wk * fmaxf(v.b, 0.0f);
+            tau += (double)sd;
+        }
+        a.tau_seg[sg.w] = tau;
+        a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
+        if (REC) a.nocc[i] = (int)min((int64_t)j, room);
+    }
+}
+
 // Segments of a ray are walked kSegU at a time: the loads of a group are
 // issued together (positions past the last segment are clamped to it and
 // their values unused), then the group is composed in order.
@@ -1466,8 +1664,6 @@ void seg_bwd_kernel(GridDev g, BinArgs a) {
 // through the trilinear weights and the SH basis); only the order of the
 // additions differs.
 
-constexpr int kBrickCells = PLX_BRICK * PLX_BRICK * PLX_BRICK;           // 512
-constexpr int kBrickVox = (PLX_BRICK + 1) * (PLX_BRICK + 1) * (PLX_BRICK + 1);  // 729 corner voxels
 constexpr int kScatterThreads = 512;       // threads of a scatter workgroup
 constexpr int kScatterSegs = 256;          // segments per pass
 constexpr int kVoxRounds = (kBrickVox + kScatterThreads - 1) / kScatterThreads;
@@ -2380,7 +2576,18 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
         return check_launch(fn);
     }
     if (a.n_seg > 0) {
-        if (MODE != MODE_FWD && a.srec) {
+        const bool rec = MODE != MODE_FWD && a.srec;
+        if (a.blist && a.n_brick > 0 && grid->sh_dtype != PLX_F32) {
+            // brick-staged (16-bit records: 47 KB of LDS per brick, three
+            // workgroups per CU; FP32's 82 KB leave one, and the lane-per-
+            // segment kernel with its L2 traffic is then twice as fast)
+            const unsigned nb = (unsigned)a.n_brick;
+            if (rec) {
+                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, true><<<nb, kThreads, 0, s>>>(g, as));
+            } else {
+                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, false><<<nb, kThreads, 0, s>>>(g, as));
+            }
+        } else if (rec) {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
         } else {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, false><<<as.nb8, kThreads, 0, s>>>(g, as));

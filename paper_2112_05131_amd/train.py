@@ -92,6 +92,18 @@ class RaySampler:
         return self.o[ids], self.d[ids], self.t[ids]
 
 
+# Batches from this size on use the recorded backward (sample buffer and one
+# scatter workgroup per brick).  Smaller batches put few segments in each
+# brick, so the per-brick set-up of the scatter outweighs what it saves on
+# atomics, and the replay's own scatter is faster: at 5000-ray batches on a
+# 256^3 grid a step takes 0.62 ms with it and 0.79 ms with the recorded one.
+RECORDED_MIN_RAYS = 1 << 16
+
+
+def recorded_backward(n_rays: int) -> bool:
+    return n_rays >= RECORDED_MIN_RAYS
+
+
 class StepEvents:
     """Device events around the calls of one training step (timing only):
     the binning of its batch (on the stream that made the bins), the four
@@ -190,6 +202,8 @@ class Trainer:
         lr_s, lr_h = self.learning_rates()
         n = rays_o.shape[0]
         rev = events.render if events is not None else None
+        if bins is None:
+            bins = B.make_bins(g.desc(), rays_o, rays_d, samples=recorded_backward(n))
         if self.bg is None:
             B.plx_render_train(g.desc(), rays_o, rays_d, target, 1.0 / max(n, 1), self.grad,
                                self.touched, self.loss_sum, rgb_out, c.background, self.priors(),
@@ -251,7 +265,7 @@ class Trainer:
                 if se is not None:
                     se.bins[0].record(side)
                 o, d, t = sampler.next_batch()
-                b = B.make_bins(self.grid.desc(), o, d, *bufs[slot])
+                b = B.make_bins(self.grid.desc(), o, d, *bufs[slot], samples=recorded_backward(o.shape[0]))
                 bufs[slot] = b.buffers()
                 if se is not None:
                     se.bins[1].record(side)
