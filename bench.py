@@ -58,8 +58,8 @@ N_CAMS, W, H = 100, 800, 800
 COUNTERS = os.path.join(ROOT, "profiles", "render_train_512cubed_1Mrays_counters.json")
 RENDER_SRC = os.path.join(ROOT, "paper_2112_05131_amd", "csrc", "render.hip")
 # kernels of one plx_render_train call, as rocprofv3 names them
-COUNTED_KERNELS = {"seg_fwd": "seg_fwd_kernel", "seg_combine": "seg_combine_kernel",
-                   "seg_scatter": "seg_scatter_kernel"}
+COUNTED_KERNELS = {"seg_fwd": ("seg_fwd_kernel", "seg_fwd_brick_kernel"), "seg_combine": ("seg_combine_kernel",),
+                   "seg_scatter": ("seg_scatter_kernel",)}
 
 
 def log(*a):
@@ -115,12 +115,12 @@ def counters_summary(dtype, fetch_csv, write_csv):
            "command": (f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
                        f"--counters --dtype {dtype}; python bench.py --counters-summary {dtype} "
                        "<fetch counter_collection.csv> <write counter_collection.csv>")}
-    for key, name in COUNTED_KERNELS.items():
-        fk = [v for n, v in fetch if name in n]
-        wk = [v for n, v in write if name in n]
+    for key, names in COUNTED_KERNELS.items():
+        fk = [(n, v) for n, v in fetch if any(x + "<" in n or x + "(" in n for x in names)]
+        wk = [(n, v) for n, v in write if any(x + "<" in n or x + "(" in n for x in names)]
         if fk and wk:
-            out[key] = {"fetch_kib": fk[-1], "write_kib": wk[-1],
-                        "fetch_bytes": int(fk[-1] * 1024 * f_scale), "write_bytes": int(wk[-1] * 1024 * w_scale)}
+            out[key] = {"kernel": fk[-1][0][:90], "fetch_kib": fk[-1][1], "write_kib": wk[-1][1],
+                        "fetch_bytes": int(fk[-1][1] * 1024 * f_scale), "write_bytes": int(wk[-1][1] * 1024 * w_scale)}
     try:
         allc = json.load(open(COUNTERS))
     except (OSError, ValueError):
@@ -366,7 +366,8 @@ def serving_leg(n_sat=400, n_load=2000):
                    s.occ.numel() * 4 for s in scenes)
     log(f"serving scenes built in {time.time() - t0:.1f}s, resident {resident / 1e9:.2f} GB")
     roof = views_roofline(scenes)
-    srv = Server(scenes, hbm_budget=1 << 30, n_streams=4, max_batch=32, keep_outputs=False)
+    srv = Server(scenes, hbm_budget=1 << 30, n_streams=4, max_batch=32, keep_outputs=False,
+                 max_batch_pixels=1 << 21)
     run_load(srv, random_requests(16, 8, seed=99), None)  # warm-up
     reqs = random_requests(n_sat, 8, seed=100)
     lat, wall = run_load(srv, reqs, None)
@@ -430,17 +431,17 @@ def views_roofline(scenes, reps=5):
         del o, d, cm, vm
     table = B.SceneTable(scenes)
     out = torch.empty(3 * off, device="cuda")
-    ws = B.workspace(B.plx_render_views_workspace(len(views)))
-    B.plx_render_views(table, views, out, ws)
+    q = B.views_queue()
+    B.plx_render_views(table, views, out, q)
     best = float("inf")
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        B.plx_render_views(table, views, out, ws)
+        B.plx_render_views(table, views, out, q)
         b.record()
         b.synchronize()
         best = min(best, a.elapsed_time(b))
-    B.plx_render_views_status(ws, len(views))
+    B.plx_render_views_status(q)
     gbs = nbytes / (best * 1e-3) / 1e9
     log(f"views kernel: 8 x 1920x1080 in {best:.3f} ms, {gbs:.1f} GB/s algorithmic")
     return {"launch": "8 views at 1920x1080, one per scene", "ms": round(best, 4),

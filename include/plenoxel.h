@@ -550,34 +550,35 @@ int64_t plx_scene_table_bytes(int32_t n_scenes);
 int plx_scene_table_set(const plx_grid *scenes, int32_t n_scenes, void *table, int64_t table_bytes,
                         plx_stream stream);
 
-/* Bytes of device workspace plx_render_views needs for n_views views (the
- * tile queue counter, a status word, tile offsets and the view table). */
-int64_t plx_render_views_workspace(int32_t n_views);
+/* Bytes of the tile queue of plx_render_views: device memory, 256-byte
+ * aligned, zero-filled once before its first use (every launch leaves it at
+ * zero again, apart from the sticky status word). */
+#define PLX_VIEWS_QUEUE_BYTES 256
 
-/* Renders a batch of novel views of resident scenes in one launch (the
- * forward model of plx_render_fwd, Sec. 3.1-3.3, with rays generated on the
- * device; interactive rendering is claimed in Sec. 1).  The views may mix
- * scenes and resolutions.  All pixels of all views form one queue of
- * 16x16-pixel tiles drained by a persistent grid, so the colour of a pixel
- * depends only on its ray and scene, never on the rest of the batch.
- * scene_table: written by plx_scene_table_set for n_scenes scenes of storage
- * type sh_dtype.  views: host array, validated here (scene index, size,
- * focal, offset) and passed to the device as kernel arguments into
- * `workspace` (device, 256-byte aligned, plx_render_views_workspace bytes),
- * which also holds the tile queue, reset by a kernel (no memset).  Never
- * allocates, copies through a copy engine or synchronises: the views array
- * may be released on return.  A table that is not of sh_dtype (or holds
- * fewer scenes than a view names) renders nothing for those views and sets
- * the status word that plx_render_views_status reads.  rgb_out: device
- * float32, 3 floats per pixel at 3*(out_offset + py*width + px).  Calls that
- * share a workspace must be ordered on one stream. */
+/* Renders a batch of novel views of resident scenes (the forward model of
+ * plx_render_fwd, Sec. 3.1-3.3, with rays generated on the device;
+ * interactive rendering is claimed in Sec. 1).  The views may mix scenes and
+ * resolutions.  All pixels of all views form one queue of 16x16-pixel tiles
+ * drained by a persistent grid, so the colour of a pixel depends only on its
+ * ray and scene, never on the rest of the batch.  scene_table: written by
+ * plx_scene_table_set for n_scenes scenes of storage type sh_dtype.  views:
+ * host array, validated here (scene index, size, focal, offset) and passed
+ * to the device as kernel arguments, 24 views per launch: the call
+ * allocates nothing, copies nothing through a copy engine, never
+ * synchronises, and the array may be released on return.  queue: the tile
+ * queue (PLX_VIEWS_QUEUE_BYTES); launches that share one must be ordered on
+ * a stream, launches on separate queues may overlap.  A table that is not of
+ * sh_dtype (or holds fewer scenes than a view names) renders nothing for
+ * those views and sets the queue's status word, which
+ * plx_render_views_status reads.  rgb_out: device float32, 3 floats per
+ * pixel at 3*(out_offset + py*width + px). */
 int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype, const plx_view *views,
-                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
-                     int64_t workspace_bytes, plx_stream stream);
+                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *queue,
+                     plx_stream stream);
 
-/* PLX_OK when the last plx_render_views call on `workspace` (n_views views)
- * rendered every view, PLX_EINVAL otherwise.  Synchronising. */
-int plx_render_views_status(const void *workspace, int32_t n_views, plx_stream stream);
+/* PLX_OK unless a launch on `queue` met a mismatched table or scene (then
+ * PLX_EINVAL; the status stays set).  Synchronising. */
+int plx_render_views_status(const void *queue, plx_stream stream);
 
 /* Work counters of a ray batch, for bandwidth accounting (not timed work):
  * counts[0] = samples (all), counts[1] = samples in occupied cells,

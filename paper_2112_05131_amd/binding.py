@@ -155,9 +155,8 @@ _SIGS = {
     "plx_render_stats": ([_GP, _P, _P, _I64, _P, _P, _P, _I64, _P, _P], ctypes.c_int),
     "plx_scene_table_bytes": ([_I32], _I64),
     "plx_scene_table_set": ([_GP, _I32, _P, _I64, _P], ctypes.c_int),
-    "plx_render_views_workspace": ([_I32], _I64),
-    "plx_render_views": ([_P, _I32, _I32, _P, _I32, _OP, _P, _P, _I64, _P], ctypes.c_int),
-    "plx_render_views_status": ([_P, _I32, _P], ctypes.c_int),
+    "plx_render_views": ([_P, _I32, _I32, _P, _I32, _OP, _P, _P, _P], ctypes.c_int),
+    "plx_render_views_status": ([_P, _P], ctypes.c_int),
     "plx_tv_grad": ([_GP, _I64, _I64, _F, _F, _F, _P, _P, _P, _P], ctypes.c_int),
     "plx_touched_count": ([_P, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "plx_rmsprop_step": ([_GP, _P, _P, _P, _P, _F, _F, _F, _F, _P], ctypes.c_int),
@@ -653,28 +652,30 @@ def plx_scene_table_bytes(n_scenes: int) -> int:
     return int(lib().plx_scene_table_bytes(int(n_scenes)))
 
 
-def plx_render_views_workspace(n_views: int) -> int:
-    return int(lib().plx_render_views_workspace(int(n_views)))
+VIEWS_QUEUE_BYTES = 256
 
 
-def plx_render_views(table: SceneTable, views, rgb_out, workspace, bg=(1.0, 1.0, 1.0), stream=None):
+def views_queue(device=None) -> torch.Tensor:
+    """A tile queue for plx_render_views (zero-filled, as the call needs)."""
+    return torch.zeros(VIEWS_QUEUE_BYTES, dtype=torch.uint8, device=device if device is not None else "cuda")
+
+
+def plx_render_views(table: SceneTable, views, rgb_out, queue, bg=(1.0, 1.0, 1.0), stream=None):
     """table: SceneTable; views: list of PlxView; rgb_out: device float32
-    tensor; workspace: device uint8 tensor of at least
-    plx_render_views_workspace bytes.  stream: a torch.cuda.Stream (default:
-    the current stream).  Asynchronous."""
+    tensor; queue: views_queue().  stream: a torch.cuda.Stream (default: the
+    current stream).  Asynchronous."""
     vw = (PlxView * max(len(views), 1))(*views)
     o = _opts(bg)
     s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
     _check(lib().plx_render_views(_dptr(table.buf, "table", torch.uint8), table.n_scenes, table.sh_dtype,
                                   ctypes.cast(vw, _P), len(views), ctypes.byref(o),
                                   _dptr(rgb_out, "rgb_out", torch.float32),
-                                  _dptr(workspace, "workspace"), workspace.numel() * workspace.element_size(),
-                                  s))
+                                  _dptr(queue, "queue", torch.uint8, VIEWS_QUEUE_BYTES), s))
 
 
-def plx_render_views_status(workspace, n_views: int, stream=None):
+def plx_render_views_status(queue, stream=None):
     s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-    _check(lib().plx_render_views_status(_dptr(workspace, "workspace"), int(n_views), s))
+    _check(lib().plx_render_views_status(_dptr(queue, "queue", torch.uint8), s))
 
 
 def plx_render_stats(g: PlxGrid, rays_o, rays_d, cell_mark, vox_mark, ws=None):

@@ -2108,47 +2108,34 @@ struct SceneTableHeader {
 };
 constexpr int64_t kSceneTableHead = 256;
 
+// Views reach the device as kernel arguments (no copy engine, no setup
+// launch, no host buffer that must outlive the call): one launch renders up
+// to kViewsPerLaunch views, and a longer list is split into several.
+constexpr int kViewsPerLaunch = 24;
+
+// The caller's tile queue (PLX_VIEWS_QUEUE_BYTES, zero before first use):
+// the next tile, the blocks that have left, and a sticky status word.  The
+// last block of a launch to leave resets the first two, so every launch
+// finds the queue at zero without a memset.
+struct ViewsQueue {
+    unsigned long long next;
+    unsigned done;
+    unsigned status;
+};
+
 struct ViewsArgs {
     const SceneTableHeader *table;
     const GridDev *scenes;
-    const plx_view *views;
-    const int64_t *tile_start;  // [n_views + 1]
-    unsigned long long *counter;
-    unsigned *status;
+    plx_view v[kViewsPerLaunch];
+    int64_t tile_start[kViewsPerLaunch + 1];
     int n_views;
-    int64_t n_tiles;
+    ViewsQueue *queue;
     float bg[3];
     float *rgb_out;
 };
 
-// Views and scene descriptors reach the device as kernel arguments (no copy
-// engine, no host buffer that must outlive the call): each setup launch
-// writes up to kSetupItems entries into the workspace or the scene table.
+// Descriptors of the scene table reach the device the same way.
 constexpr int kSetupItems = 24;
-
-struct ViewsSetupArgs {
-    plx_view v[kSetupItems];
-    int64_t tile_start[kSetupItems];
-    int first, count, n_views;
-    int64_t n_tiles;
-    plx_view *views;
-    int64_t *ws_tile_start;
-    unsigned long long *counter;
-    unsigned *status;
-};
-
-__global__ void views_setup_kernel(ViewsSetupArgs a) {
-    const int i = threadIdx.x;
-    if (i < a.count) {
-        a.views[a.first + i] = a.v[i];
-        a.ws_tile_start[a.first + i] = a.tile_start[i];
-    }
-    if (a.first == 0 && i == 0) {
-        a.ws_tile_start[a.n_views] = a.n_tiles;
-        *a.counter = 0ull;
-        *a.status = 0u;
-    }
-}
 
 struct SceneSetupArgs {
     GridDev g[kSetupItems];
@@ -2167,11 +2154,11 @@ __global__ void scene_setup_kernel(SceneSetupArgs a) {
     }
 }
 
-// Persistent tile queue over all pixels of all views of the launch: each block
-// takes the next 16x16-pixel tile, finds its view, generates the rays of its
-// pixels (one per lane) and runs the same forward march as plx_render_fwd.  A
-// pixel's colour depends only on its own ray and scene, never on the rest of
-// the batch.
+// Persistent tile queue over all pixels of all views of the launch: each
+// block takes the next 16x16-pixel tile, finds its view, generates the rays
+// of its pixels (one per lane) and runs the same forward march as
+// plx_render_fwd.  A pixel's colour depends only on its own ray and scene,
+// never on the rest of the batch.
 template <int DT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void views_kernel(ViewsArgs a) {
@@ -2180,31 +2167,27 @@ void views_kernel(ViewsArgs a) {
     // is rendered and the status word says so
     const unsigned magic = a.table->magic;
     const int n_scenes = a.table->n_scenes, table_dt = a.table->sh_dtype;
-    if (magic != kSceneMagic || table_dt != DT) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.status = 1u;
-        return;
-    }
-    while (true) {
-        if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(a.counter, 1ull);
+    const bool ok = magic == kSceneMagic && table_dt == DT;
+    if (!ok && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.queue->status, 1u);
+    const int64_t n_tiles = ok ? a.tile_start[a.n_views] : 0;
+    while (n_tiles > 0) {
+        if (threadIdx.x == 0) tile_sh = (long long)atomicAdd(&a.queue->next, 1ull);
         __syncthreads();
         const int64_t tile = uni64(tile_sh);
         __syncthreads();
-        if (tile >= a.n_tiles) break;
-        int lo = 0, hi = a.n_views - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.tile_start[mid] <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        const plx_view &v = a.views[lo];
+        if (tile >= n_tiles) break;
+        int lo = 0;  // the view of the tile
+        for (int i = 1; i < a.n_views; ++i)
+            if (a.tile_start[i] <= tile) lo = i;
+        const plx_view &v = a.v[lo];
         const int width = uni(v.width), height = uni(v.height);
-        const int64_t tl = tile - uni64(a.tile_start[lo]);
+        const int64_t tl = tile - a.tile_start[lo];
         const int tpr = (width + kTileW - 1) / kTileW;
         const int px = (int)(tl % tpr) * kTileW + (int)(threadIdx.x % kTileW);
         const int py = (int)(tl / tpr) * kTileH + (int)(threadIdx.x / kTileW);
         const int scene = uni(v.scene);
         if (scene >= n_scenes) {
-            if (threadIdx.x == 0) *a.status = 1u;
+            if (threadIdx.x == 0) atomicOr(&a.queue->status, 1u);
             continue;
         }
         if (px < width && py < height) {
@@ -2226,21 +2209,15 @@ void views_kernel(ViewsArgs a) {
             for (int c3 = 0; c3 < 3; ++c3) out[c3] = C[c3] + T_final * a.bg[c3];
         }
     }
-}
-
-struct ViewsLayout {
-    int64_t counter, status, tile_start, views, bytes;
-};
-
-ViewsLayout views_layout(int32_t n_views) {
-    auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
-    ViewsLayout l;
-    l.counter = 0;
-    l.status = 8;
-    l.tile_start = 256;
-    l.views = l.tile_start + up((int64_t)(n_views + 1) * (int64_t)sizeof(int64_t));
-    l.bytes = l.views + up((int64_t)n_views * (int64_t)sizeof(plx_view));
-    return l;
+    // leave; the last block resets the queue for the next launch (every
+    // block's last take from it precedes its leaving)
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.queue->done, 1u) == gridDim.x - 1) {
+            atomicExch(&a.queue->next, 0ull);
+            atomicExch(&a.queue->done, 0u);
+        }
+    }
 }
 
 // Work counters (one thread per ray; diagnostic, not a hot path).
@@ -3014,14 +2991,9 @@ int plx_scene_table_set(const plx_grid *scenes, int32_t n_scenes, void *table, i
     return PLX_OK;
 }
 
-int64_t plx_render_views_workspace(int32_t n_views) {
-    if (n_views < 0) return 0;
-    return views_layout(n_views).bytes;
-}
-
 int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype, const plx_view *views,
-                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *workspace,
-                     int64_t workspace_bytes, plx_stream stream) {
+                     int32_t n_views, const plx_render_opts *opts, float *rgb_out, void *queue,
+                     plx_stream stream) {
     const char *fn = "plx_render_views";
     if (!scene_table || n_scenes < 1) return fail(PLX_EINVAL, "%s: need a scene table of at least one scene", fn);
     if (sh_dtype != PLX_F32 && sh_dtype != PLX_BF16 && sh_dtype != PLX_F16)
@@ -3029,15 +3001,9 @@ int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype
     if (n_views < 0) return fail(PLX_EINVAL, "%s: n_views < 0", fn);
     if (!opts) return fail(PLX_EINVAL, "%s: opts is NULL", fn);
     if (n_views == 0) return PLX_OK;
-    if (!views || !rgb_out || !workspace) return fail(PLX_EINVAL, "%s: NULL views/rgb_out/workspace", fn);
-    if (reinterpret_cast<uintptr_t>(workspace) % 256)
-        return fail(PLX_EINVAL, "%s: workspace must be 256-byte aligned", fn);
-    const ViewsLayout lay = views_layout(n_views);
-    if (workspace_bytes < lay.bytes)
-        return fail(PLX_EINVAL, "%s: workspace of %lld bytes, need %lld", fn, (long long)workspace_bytes,
-                    (long long)lay.bytes);
-    std::vector<int64_t> tile_start((size_t)n_views + 1);
-    int64_t tiles = 0;
+    if (!views || !rgb_out || !queue) return fail(PLX_EINVAL, "%s: NULL views/rgb_out/queue", fn);
+    if (reinterpret_cast<uintptr_t>(queue) % 256)
+        return fail(PLX_EINVAL, "%s: queue must be 256-byte aligned", fn);
     for (int32_t i = 0; i < n_views; ++i) {
         const plx_view &v = views[i];
         if (v.scene < 0 || v.scene >= n_scenes) return fail(PLX_EINVAL, "%s: view %d: bad scene", fn, i);
@@ -3045,58 +3011,43 @@ int plx_render_views(const void *scene_table, int32_t n_scenes, int32_t sh_dtype
             return fail(PLX_EINVAL, "%s: view %d: bad size %dx%d", fn, i, v.width, v.height);
         if (!(v.focal > 0.0) || !std::isfinite(v.focal) || v.out_offset < 0)
             return fail(PLX_EINVAL, "%s: view %d: bad focal or out_offset", fn, i);
-        tile_start[i] = tiles;
-        tiles += (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + kTileH - 1) / kTileH);
     }
-    tile_start[n_views] = tiles;
     hipStream_t s = as_stream(stream);
-    char *ws = static_cast<char *>(workspace);
-    ViewsSetupArgs sa;
-    sa.n_views = n_views;
-    sa.n_tiles = tiles;
-    sa.views = reinterpret_cast<plx_view *>(ws + lay.views);
-    sa.ws_tile_start = reinterpret_cast<int64_t *>(ws + lay.tile_start);
-    sa.counter = reinterpret_cast<unsigned long long *>(ws + lay.counter);
-    sa.status = reinterpret_cast<unsigned *>(ws + lay.status);
-    for (int32_t first = 0; first < n_views; first += kSetupItems) {
-        sa.first = first;
-        sa.count = std::min(kSetupItems, n_views - first);
-        for (int i = 0; i < sa.count; ++i) {
-            sa.v[i] = views[first + i];
-            sa.tile_start[i] = tile_start[first + i];
-        }
-        views_setup_kernel<<<1, 32, 0, s>>>(sa);
-        int rc = check_launch(fn);
-        if (rc) return rc;
-    }
     ViewsArgs va;
     va.table = static_cast<const SceneTableHeader *>(scene_table);
     va.scenes = reinterpret_cast<const GridDev *>(static_cast<const char *>(scene_table) + kSceneTableHead);
-    va.counter = sa.counter;
-    va.status = sa.status;
-    va.tile_start = sa.ws_tile_start;
-    va.views = sa.views;
-    va.n_views = n_views;
-    va.n_tiles = tiles;
+    va.queue = static_cast<ViewsQueue *>(queue);
     va.rgb_out = rgb_out;
     for (int i = 0; i < 3; ++i) va.bg[i] = opts->background[i];
-    const int64_t nblk = tiles < 2048 ? tiles : 2048;  // persistent: 8 blocks per CU
-    PLX_DISPATCH_DT(sh_dtype, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
-    return check_launch(fn);
+    for (int32_t first = 0; first < n_views; first += kViewsPerLaunch) {
+        va.n_views = std::min(kViewsPerLaunch, n_views - first);
+        int64_t tiles = 0;
+        for (int i = 0; i < va.n_views; ++i) {
+            const plx_view &v = views[first + i];
+            va.v[i] = v;
+            va.tile_start[i] = tiles;
+            tiles += (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + kTileH - 1) / kTileH);
+        }
+        va.tile_start[va.n_views] = tiles;
+        const int64_t nblk = tiles < 2048 ? tiles : 2048;  // persistent: 8 blocks per CU
+        PLX_DISPATCH_DT(sh_dtype, DT, views_kernel<DT><<<(unsigned)nblk, kThreads, 0, s>>>(va));
+        int rc = check_launch(fn);
+        if (rc) return rc;
+    }
+    return PLX_OK;
 }
 
-int plx_render_views_status(const void *workspace, int32_t n_views, plx_stream stream) {
+int plx_render_views_status(const void *queue, plx_stream stream) {
     const char *fn = "plx_render_views_status";
-    if (!workspace || n_views < 1) return fail(PLX_EINVAL, "%s: NULL workspace or no views", fn);
-    const ViewsLayout lay = views_layout(n_views);
+    if (!queue) return fail(PLX_EINVAL, "%s: queue is NULL", fn);
     hipStream_t s = as_stream(stream);
     unsigned st = 0;
-    PLX_CHECK_HIP(hipMemcpyAsync(&st, static_cast<const char *>(workspace) + lay.status, sizeof(st),
+    PLX_CHECK_HIP(hipMemcpyAsync(&st, &static_cast<const ViewsQueue *>(queue)->status, sizeof(st),
                                  hipMemcpyDeviceToHost, s), fn);
     PLX_CHECK_HIP(hipStreamSynchronize(s), fn);
     if (st != 0)
-        return fail(PLX_EINVAL, "%s: the scene table is not one of this storage type, or a view named a "
-                                "scene beyond it; those views were not rendered", fn);
+        return fail(PLX_EINVAL, "%s: a launch on this queue met a scene table of another storage type, or "
+                                "a view naming a scene beyond it; those views were not rendered", fn);
     return PLX_OK;
 }
 

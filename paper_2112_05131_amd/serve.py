@@ -63,11 +63,14 @@ class Server:
     """Continuous-batching render server.
 
     hbm_budget: bytes of output buffers admitted at once (queued requests wait
-    beyond it); n_streams: launches in flight at once; max_batch: requests per
+    beyond it); max_batch_pixels: pixels per launch (a request larger than it
+    runs alone), so that no launch, whose requests all complete together,
+    grows long; n_streams: launches in flight at once; max_batch: requests per
     launch."""
 
     def __init__(self, scenes: list[Grid], hbm_budget: int = 512 << 20, n_streams: int = 4,
-                 max_batch: int = 64, background=(1.0, 1.0, 1.0), keep_outputs: bool = True):
+                 max_batch: int = 64, background=(1.0, 1.0, 1.0), keep_outputs: bool = True,
+                 max_batch_pixels: int | None = 1 << 21):
         self.keep_outputs = keep_outputs
         if not scenes:
             raise ValueError("need at least one scene")
@@ -78,13 +81,12 @@ class Server:
         self.table = B.SceneTable(scenes)  # resident descriptors, written once
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
+        self.max_batch_pixels = max_batch_pixels
         self.bg = tuple(background)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.queues = [B.views_queue(scenes[0].device) for _ in range(n_streams)]
         for st in self.streams:
-            st.wait_stream(torch.cuda.current_stream())  # the table is written
-        ws = B.plx_render_views_workspace(self.max_batch)
-        self.workspaces = [torch.empty(ws, dtype=torch.uint8, device=scenes[0].device)
-                           for _ in range(n_streams)]
+            st.wait_stream(torch.cuda.current_stream())  # the table and queues are written
         self.queue: deque[Request] = deque()
         self.inflight: list[_Batch] = []
         self.in_use = 0
@@ -109,12 +111,15 @@ class Server:
         for si in self._idle_streams():
             if not self.queue:
                 return
-            batch, nbytes = [], 0
+            batch, nbytes, npix = [], 0, 0
             while (self.queue and len(batch) < self.max_batch
-                   and self.in_use + nbytes + self.queue[0].out_bytes <= self.budget):
+                   and self.in_use + nbytes + self.queue[0].out_bytes <= self.budget
+                   and (not batch or self.max_batch_pixels is None
+                        or npix + self.queue[0].n_pixels <= self.max_batch_pixels)):
                 r = self.queue.popleft()
                 batch.append(r)
                 nbytes += r.out_bytes
+                npix += r.n_pixels
             if not batch:
                 return  # head of the queue waits for budget
             self._launch(batch, nbytes, si)
@@ -135,7 +140,7 @@ class Server:
                 off += r.n_pixels
                 views.append(v)
             t = time.perf_counter()
-            B.plx_render_views(self.table, views, out, self.workspaces[si], self.bg, stream)
+            B.plx_render_views(self.table, views, out, self.queues[si], self.bg, stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         for r in batch:

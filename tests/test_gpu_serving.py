@@ -45,9 +45,10 @@ def _render(grids, reqs):
         views.append(_view(r, off))
         off += r.n_pixels
     out = torch.full((off * 3,), -1.0, device="cuda")
-    ws = B.workspace(B.plx_render_views_workspace(len(views)))
-    B.plx_render_views(B.SceneTable(grids), views, out, ws)
-    B.plx_render_views_status(ws, len(views))
+    q = B.views_queue()
+    B.plx_render_views(B.SceneTable(grids), views, out, q)
+    B.plx_render_views_status(q)
+    assert torch.count_nonzero(q[:12]).item() == 0  # left at zero for the next launch
     res, off = [], 0
     for r in reqs:
         res.append(out[3 * off:3 * (off + r.n_pixels)].view(r.height, r.width, 3).clone())
@@ -131,15 +132,16 @@ def test_scene_table_of_another_storage_type_renders_nothing():
     reqs = random_requests(2, 2, seed=9, resolutions=((40, 30),))
     views = [_view(reqs[0], 0), _view(reqs[1], reqs[0].n_pixels)]
     out = torch.full((3 * sum(r.n_pixels for r in reqs),), -1.0, device="cuda")
-    ws = B.workspace(B.plx_render_views_workspace(len(views)))
+    q = B.views_queue()
     table.sh_dtype = B.PLX_F16  # claims FP16 over an FP32 table
-    B.plx_render_views(table, views, out, ws)
+    B.plx_render_views(table, views, out, q)
     with pytest.raises(B.PlxError, match="not rendered"):
-        B.plx_render_views_status(ws, len(views))
+        B.plx_render_views_status(q)
     assert torch.all(out == -1.0)
     table.sh_dtype = B.PLX_F32
-    B.plx_render_views(table, views, out, ws)
-    B.plx_render_views_status(ws, len(views))
+    q = B.views_queue()
+    B.plx_render_views(table, views, out, q)
+    B.plx_render_views_status(q)
     assert torch.all(out >= 0.0)
 
 
@@ -154,7 +156,7 @@ def test_launches_on_two_streams_overlap():
     reqs[0].scene, reqs[1].scene = 0, 1
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     outs = [torch.empty(3 * r.n_pixels, device="cuda") for r in reqs]
-    wss = [B.workspace(B.plx_render_views_workspace(1)) for _ in reqs]
+    qs = [B.views_queue() for _ in reqs]
     for st in streams:
         st.wait_stream(torch.cuda.current_stream())
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -164,7 +166,7 @@ def test_launches_on_two_streams_overlap():
         for _ in range(5):
             a, b = ev(), ev()
             a.record(streams[i])
-            B.plx_render_views(table, [_view(reqs[i])], outs[i], wss[i], stream=streams[i])
+            B.plx_render_views(table, [_view(reqs[i])], outs[i], qs[i], stream=streams[i])
             b.record(streams[i])
             b.synchronize()
             best = min(best, a.elapsed_time(b))
@@ -179,7 +181,7 @@ def test_launches_on_two_streams_overlap():
         start.record(main)
         for i, st in enumerate(streams):
             st.wait_event(start)
-            B.plx_render_views(table, [_view(reqs[i])], outs[i], wss[i], stream=st)
+            B.plx_render_views(table, [_view(reqs[i])], outs[i], qs[i], stream=st)
         e0.record(streams[0])
         e1.record(streams[1])
         torch.cuda.synchronize()
@@ -187,3 +189,15 @@ def test_launches_on_two_streams_overlap():
     span = min(spans)
     say(f"  alone {d0:.3f} + {d1:.3f} ms, together {span:.3f} ms")
     assert span < 0.8 * (d0 + d1), (span, d0, d1)
+
+
+def test_long_view_lists_span_launches():
+    """More views than one launch takes (24 as kernel arguments): the list is
+    split over launches, and every view equals its stand-alone render."""
+    say("views: 30 views in one call")
+    _, grids = _scenes()
+    reqs = random_requests(30, 2, seed=51, resolutions=((24, 20), (40, 32), (17, 9)))
+    alone = [_render(grids, [r])[0] for r in reqs]
+    together = _render(grids, reqs)
+    for a, t in zip(alone, together):
+        assert torch.equal(a, t)

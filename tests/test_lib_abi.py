@@ -361,15 +361,10 @@ def test_static_training_call_refuses_batches_beyond_its_scratch():
 
 
 def test_views_and_scene_table_validation():
-    """plx_scene_table_set / plx_render_views reject bad tables, views and
-    workspaces before any launch; the workspace size is the counter block,
-    the tile offsets and the view table."""
+    """plx_scene_table_set / plx_render_views reject bad tables and views
+    before any launch."""
     L = B.lib()
     p = ctypes.c_void_p
-    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    assert B.plx_render_views_workspace(0) == 256 + 256
-    assert B.plx_render_views_workspace(3) == 256 + up(4 * 8) + up(3 * ctypes.sizeof(B.PlxView))
-    assert B.plx_render_views_workspace(-1) == 0
     assert B.plx_scene_table_bytes(0) == 0 and B.plx_scene_table_bytes(2) > B.plx_scene_table_bytes(1) > 256
     g = _grid_desc()
     gs = (B.PlxGrid * 1)(g)
@@ -389,18 +384,17 @@ def test_views_and_scene_table_validation():
             setattr(v, k, x)
         return v
 
-    need_w = B.plx_render_views_workspace(1)
     cases = [(dict(scene=1), dict(), "bad scene"), (dict(scene=-1), dict(), "bad scene"),
              (dict(width=0), dict(), "bad size"), (dict(height=70000), dict(), "bad size"),
              (dict(focal=0.0), dict(), "focal"), (dict(focal=float("nan")), dict(), "focal"),
              (dict(out_offset=-1), dict(), "out_offset"),
-             (dict(), dict(ws=0x200040), "aligned"), (dict(), dict(wsb=need_w - 1), "need"),
              (dict(), dict(dt=7), "sh_dtype"), (dict(), dict(table=None), "scene table"),
-             (dict(), dict(n_scenes=0), "scene table")]
+             (dict(), dict(n_scenes=0), "scene table"), (dict(), dict(out=None), "rgb_out"),
+             (dict(), dict(q=None), "queue"), (dict(), dict(q=0x200040), "aligned")]
     for vkw, kw, needle in cases:
-        vs = (B.PlxView * 1)(view(**vkw))
+        vs = (B.PlxView * 2)(view(), view(**vkw))
         rc = L.plx_render_views(p(kw.get("table", 0x100000)) if kw.get("table", 1) else None,
-                                kw.get("n_scenes", 1), kw.get("dt", B.PLX_F32), ctypes.cast(vs, p), 1,
-                                ctypes.byref(opts), p(0x300000), p(kw.get("ws", 0x200000)),
-                                kw.get("wsb", need_w), None)
+                                kw.get("n_scenes", 1), kw.get("dt", B.PLX_F32), ctypes.cast(vs, p), 2,
+                                ctypes.byref(opts), p(0x300000) if kw.get("out", 1) else None,
+                                p(kw.get("q", 0x200000)) if kw.get("q", 1) else None, None)
         assert rc == B.PLX_EINVAL and needle in L.plx_last_error().decode(), needle
