@@ -470,7 +470,7 @@ def counter_run(sh_dtype, coherent):
     log("counter run done")
 
 
-def c2_leg(steps=200, warmup=20):
+def c2_leg(steps=200, warmup=200):
     """The coarse-to-fine configuration's step: 5000-ray batches on the 256^3
     grid at 10% occupancy (32 blobs, seed 1; 100 cameras at 800x800 as the
     ray pool, ground-truth renders as targets), with the next batch binned on
