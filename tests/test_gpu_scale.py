@@ -292,3 +292,39 @@ def test_trainer_overlapped_binning_matches_sequential():
     say(f"  losses {losses[True]}")
     np.testing.assert_allclose(losses[True], losses[False], rtol=1e-4)
     assert all(x > 0 for x in losses[True])
+
+
+@pytest.mark.parametrize("sh_dtype", [B.PLX_F32, B.PLX_BF16])
+def test_crowded_bricks_recorded_backward(sh_dtype):
+    """The recorded backward where one brick holds many segments and long
+    ones: 30000 rays through a 13^3 grid (8 bricks) with a step of 0.1 voxel,
+    so a brick holds thousands of segments (several groups of 256) and tens
+    of thousands of samples (many LDS passes, segments across pass
+    boundaries, walked last pass first).  plx_render_bwd with and without a
+    sample buffer against the oracle, and the touched set bit-exact."""
+    say("crowded bricks", sh_dtype)
+    sv = synth.dense_random((13, 13, 13), seed=331, occupancy=0.6, sigma_lo=0.5, sigma_hi=6.0, ho_scale=0.2)
+    og, gg = make_pair(sv, sh_dtype=sh_dtype, step_voxels=0.1)
+    o, d = synth.random_rays(30000, seed=332)
+    n = o.shape[0]
+    oc, dc = o.cuda(), d.cuda()
+    G = np.random.default_rng(333).normal(size=(n, 3))
+    Gc = torch.from_numpy(G).float().cuda()
+    rgb, tau = torch.empty(n, 3, device="cuda"), torch.empty(n, device="cuda")
+    desc = gg.desc()
+    B.plx_render_fwd(desc, oc, dc, rgb, tau)
+    rgb_ref = O.render_fwd(og, o.numpy(), d.numpy())[0]
+    assert np.abs(rgb.cpu().double().numpy() - rgb_ref).max() <= RGB_ATOL
+    gd, gs, t_ref = O.render_bwd(og, o.numpy(), d.numpy(), G)
+    mass = grad_mass(og, o.numpy(), d.numpy(), G)
+    for samples in (True, False):
+        bins = B.make_bins(desc, oc, dc, samples=samples)
+        if samples:
+            say(f"  {bins.n_seg} segments in {bins.n_brick} bricks, {bins.n_samp} sample slots")
+            assert bins.n_seg > 8 * 256 and bins.n_samp > 8 * 1536
+        grad = torch.zeros(gg.n_vox, 32, device="cuda")
+        touched = torch.zeros(gg.n_vox, dtype=torch.uint8, device="cuda")
+        B.plx_render_bwd(desc, oc, dc, Gc, tau, grad, touched, bins=bins)
+        torch.cuda.synchronize()
+        assert_touched_equal(touched, t_ref, f"crowded, samples={samples}")
+        assert_grads_close(grad, gd, gs, f"crowded, samples={samples}", mass)
