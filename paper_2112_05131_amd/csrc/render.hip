@@ -905,13 +905,15 @@ __device__ int64_t block_scan_excl(int64_t v, int64_t *total) {
     return before + x - v;
 }
 
-__global__ __launch_bounds__(kScanT) void count_sum_kernel(const unsigned *c, int64_t n,
+// The counts are c[0], c[stride], c[2*stride], ... (stride 2 reads one half
+// of an array of 64-bit counter pairs).
+__global__ __launch_bounds__(kScanT) void count_sum_kernel(const unsigned *c, int64_t n, int stride,
                                                            int64_t *bsum) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < kScanI; ++i)
-        if (base + i < n) s += c[base + i];
+        if (base + i < n) s += c[(base + i) * stride];
     int64_t tot;
     block_scan_excl(s, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -931,14 +933,14 @@ __global__ __launch_bounds__(kScanT) void block_offsets_kernel(const int64_t *bs
 }
 
 // out[i] = sum of c[0..i), out[n] = total.
-__global__ __launch_bounds__(kScanT) void count_scan_kernel(const unsigned *c, int64_t n,
+__global__ __launch_bounds__(kScanT) void count_scan_kernel(const unsigned *c, int64_t n, int stride,
                                                             const int64_t *boff, int64_t *out) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
     unsigned v[kScanI];
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < kScanI; ++i) {
-        v[i] = base + i < n ? c[base + i] : 0u;
+        v[i] = base + i < n ? c[(base + i) * stride] : 0u;
         s += v[i];
     }
     int64_t tot;
@@ -999,8 +1001,8 @@ struct BinArgs {
     int64_t seg_cap;     // segment records the segment buffer holds
     // per-bin sample counts and the recorded backward (NULL when the bins
     // carry no sample buffer)
-    unsigned *bsamp;     // [n_bins] samples (k1 - k0 + 1 summed) of each bin's segments
-    unsigned *bscursor;  // [n_bins] sample placement cursors
+    unsigned long long *bcnt64;  // [n_bins] segments (low half) and sample slots (high half) per bin
+    unsigned long long *bcur64;  // [n_bins] segment and sample placement cursors, packed the same way
     int64_t *bsoff;      // [n_bins + 1] first sample slot of each bin
     unsigned *blist;     // [n_brick] binning-order positions of the bricks with segments
     unsigned *nbrick;    // device count of blist entries
@@ -1078,8 +1080,8 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(GridDev g, BinArgs 
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         ++cnt;
         const int64_t bin = seg_bin(bid, k0, k1);
-        atomicAdd(a.bcount + bin, 1u);
-        if (a.bsamp) atomicAdd(a.bsamp + bin, (unsigned)(k1 - k0 + 1));
+        if (a.bcnt64) atomicAdd(a.bcnt64 + bin, 1ull | ((unsigned long long)(k1 - k0 + 1) << 32));
+        else atomicAdd(a.bcount + bin, 1u);
     });
     a.nseg[ray] = cnt;
 }
@@ -1098,15 +1100,19 @@ __global__ __launch_bounds__(kThreads) void seg_emit_kernel(GridDev g, BinArgs a
     bool bad = false;
     walk_bricks(g, r, n, [&](int64_t bid, int k0, int k1) {
         const int64_t bin = seg_bin(bid, k0, k1);
-        const int64_t pos = a.boff[bin] + atomicAdd(a.bcursor + bin, 1u);
+        const unsigned len = (unsigned)(k1 - k0 + 1);
+        // one cursor update gives the segment's position and (with a sample
+        // buffer) its first sample slot
+        unsigned long long cur = 0;
+        if (a.bcur64) cur = atomicAdd(a.bcur64 + bin, 1ull | ((unsigned long long)len << 32));
+        const int64_t pos = a.boff[bin] + (a.bcur64 ? (int64_t)(unsigned)cur : (int64_t)atomicAdd(a.bcursor + bin, 1u));
         // positions and slots stay inside the ranges the count reserved
         // and inside the segment buffer
         if (pos < a.boff[bin + 1] && slot < slot_end && pos < a.seg_cap && slot < a.seg_cap) {
             a.bseg[pos] = make_int4((int)ray, k0, k1, (int)slot);
             if (a.soff) {
                 // the segment's sample slots, inside its bin's and the buffer's
-                const unsigned len = (unsigned)(k1 - k0 + 1);
-                const int64_t sp = a.bsoff[bin] + atomicAdd(a.bscursor + bin, len);
+                const int64_t sp = a.bsoff[bin] + (int64_t)(cur >> 32);
                 const bool fits = sp + len <= a.bsoff[bin + 1] && sp + len <= a.samp_cap;
                 a.soff[pos] = fits ? sp : -1;
                 bad |= !fits;
@@ -2319,16 +2325,16 @@ int attach_state(RenderArgs &a, void *state, int64_t state_bytes, int32_t cap, c
 // Exclusive scan of n counts into out[0..n] (out[n] = total).  tmp: 2*nb+1
 // int64 where nb = ceil(n / kScanTile).
 int scan_counts(const unsigned *c, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s,
-                const char *fn) {
+                const char *fn, int stride = 1) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb < 1 || nb > 0x7fffffff) return fail(PLX_EINVAL, "%s: bad scan size", fn);
     int64_t *bsum = tmp, *boff = tmp + nb;
-    count_sum_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, bsum);
+    count_sum_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, stride, bsum);
     int rc = check_launch(fn);
     if (rc) return rc;
     block_offsets_kernel<<<1, kScanT, 0, s>>>(bsum, nb, boff);
     if ((rc = check_launch(fn))) return rc;
-    count_scan_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, boff, out);
+    count_scan_kernel<<<(unsigned)nb, kScanT, 0, s>>>(c, n, stride, boff, out);
     return check_launch(fn);
 }
 
@@ -2346,7 +2352,7 @@ inline int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 struct RayBufLayout {
     int64_t nseg, segoff, gray, bcount, bcursor, status, boff, scan;
     // per-bin sample counts (samples == true only)
-    int64_t bsamp, bscursor, nbrick, bsoff, blist;
+    int64_t nbrick, bsoff, blist;
     int64_t bytes;
     bool samples;
 };
@@ -2362,15 +2368,20 @@ RayBufLayout ray_buf_layout(int64_t n_rays, int64_t nbk, bool samples = true) {
     l.segoff = off; off += align256((n_rays + 1) * 8);
     l.gray = off; off += align256(n_rays * 16);
     // bin counts, cursors and the status word are cleared by one launch
-    l.bcount = off; off += nbk * 4;
-    l.bcursor = off; off += nbk * 4;
-    l.status = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
+    if (samples) {
+        // 64-bit (segments, sample slots) counters and cursors, the status
+        // word and the brick counter, cleared by one launch
+        l.bcount = off; off += nbk * 8;
+        l.bcursor = off; off += nbk * 8;
+        l.status = off; off += 4;
+        l.nbrick = off; off = align256(off + 4);
+    } else {
+        l.bcount = off; off += nbk * 4;
+        l.bcursor = off; off += nbk * 4;
+        l.status = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
+    }
     l.boff = off; off += align256((nbk + 1) * 8);
     if (samples) {
-        // sample counts, cursors and the brick counter: a second clear
-        l.bsamp = off; off += nbk * 4;
-        l.bscursor = off; off += nbk * 4;
-        l.nbrick = off; off += align256(2 * nbk * 4 + 4) - 2 * nbk * 4;
         l.bsoff = off; off += align256((nbk + 1) * 8);
         l.blist = off; off += align256(nbk / kLenClasses * 4);
     }
@@ -2421,16 +2432,18 @@ void attach_ray_buf(BinArgs &a, void *ray_buf, const RayBufLayout &l) {
     a.nseg = reinterpret_cast<unsigned *>(base + l.nseg);
     a.seg_off = reinterpret_cast<int64_t *>(base + l.segoff);
     a.g_ray = reinterpret_cast<float4 *>(base + l.gray);
-    a.bcount = reinterpret_cast<unsigned *>(base + l.bcount);
-    a.bcursor = reinterpret_cast<unsigned *>(base + l.bcursor);
     a.status = reinterpret_cast<unsigned *>(base + l.status);
     a.boff = reinterpret_cast<int64_t *>(base + l.boff);
     if (l.samples) {
-        a.bsamp = reinterpret_cast<unsigned *>(base + l.bsamp);
-        a.bscursor = reinterpret_cast<unsigned *>(base + l.bscursor);
+        a.bcnt64 = reinterpret_cast<unsigned long long *>(base + l.bcount);
+        a.bcur64 = reinterpret_cast<unsigned long long *>(base + l.bcursor);
+        a.bcount = reinterpret_cast<unsigned *>(base + l.bcount);  // the low halves, read at stride 2
         a.nbrick = reinterpret_cast<unsigned *>(base + l.nbrick);
         a.bsoff = reinterpret_cast<int64_t *>(base + l.bsoff);
         a.blist = reinterpret_cast<unsigned *>(base + l.blist);
+    } else {
+        a.bcount = reinterpret_cast<unsigned *>(base + l.bcount);
+        a.bcursor = reinterpret_cast<unsigned *>(base + l.bcursor);
     }
 }
 
@@ -2500,14 +2513,12 @@ int attach_bins(const plx_grid *grid, const plx_bins *bins, int64_t n_rays, BinA
 int bin_count_launch(const GridDev &g, BinArgs &a, int64_t nbk, int64_t *scan_tmp, hipStream_t s,
                      const char *fn) {
     const int64_t n_rays = a.n_rays;
-    const int64_t nz = 2 * nbk + 1;  // bcount, bcursor, status
-    zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(a.bcount, nz);
+    // counters, cursors, the status word (and the brick counter)
+    const int64_t nz = a.bcnt64 ? 4 * nbk + 2 : 2 * nbk + 1;
+    zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(
+        a.bcnt64 ? reinterpret_cast<unsigned *>(a.bcnt64) : a.bcount, nz);
     int rc = check_launch(fn);
     if (rc) return rc;
-    if (a.bsamp) {  // bsamp, bscursor, nbrick
-        zero_u32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(a.bsamp, nz);
-        if ((rc = check_launch(fn))) return rc;
-    }
     const int64_t nbr = (n_rays + kThreads - 1) / kThreads;
     a.n_blocks = (int)nbr;
     a.nb8 = round_up8(nbr);
@@ -2515,9 +2526,10 @@ int bin_count_launch(const GridDev &g, BinArgs &a, int64_t nbk, int64_t *scan_tm
     if ((rc = check_launch(fn))) return rc;
     if ((rc = scan_counts(a.nseg, n_rays, a.seg_off, scan_tmp, s, fn))) return rc;
     int64_t *bin_tmp = scan_tmp + scan_tmp_words(n_rays);
-    if ((rc = scan_counts(a.bcount, nbk, a.boff, bin_tmp, s, fn))) return rc;
-    if (!a.bsamp) return PLX_OK;
-    if ((rc = scan_counts(a.bsamp, nbk, a.bsoff, bin_tmp, s, fn))) return rc;
+    if (!a.bcnt64) return scan_counts(a.bcount, nbk, a.boff, bin_tmp, s, fn);
+    const unsigned *halves = reinterpret_cast<const unsigned *>(a.bcnt64);
+    if ((rc = scan_counts(halves, nbk, a.boff, bin_tmp, s, fn, 2))) return rc;
+    if ((rc = scan_counts(halves + 1, nbk, a.bsoff, bin_tmp, s, fn, 2))) return rc;
     const int64_t n_bricks = nbk / kLenClasses;
     brick_list_kernel<<<(unsigned)((n_bricks + kThreads - 1) / kThreads), kThreads, 0, s>>>(a, n_bricks);
     return check_launch(fn);
