@@ -192,6 +192,10 @@ def test_training_step_foreground_and_background_matches_oracle():
     cbg_ref, _ = O.bg_render_fwd(obg, on, dn, bgc)
     assert np.abs(cbg.cpu().double().numpy() - cbg_ref).max() <= RGB_ATOL
     rgb_ref, _, tf, _ = O.render_fwd(og, on, dn, cbg_ref)
+    # the foreground kernel against the oracle fed the device's background
+    # colours: within the RGB tolerance; end to end, the two stages' bounds add
+    rgb_dev_bg = O.render_fwd(og, on, dn, cbg.cpu().double().numpy())[0]
+    assert np.abs(rgb.cpu().double().numpy() - rgb_dev_bg).max() <= RGB_ATOL
     assert np.abs(rgb.cpu().double().numpy() - rgb_ref).max() <= 2 * RGB_ATOL
     g_rgb, loss_ref = O.mse_grad(rgb_ref, target)
     assert abs(loss.item() - loss_ref) <= 1e-5 * loss_ref

@@ -201,3 +201,19 @@ def test_long_view_lists_span_launches():
     together = _render(grids, reqs)
     for a, t in zip(alone, together):
         assert torch.equal(a, t)
+
+
+def test_scene_table_of_many_scenes():
+    """A table of more scenes than one set-up launch writes (24): views of the
+    last scenes equal their renders from a table of that scene alone."""
+    say("views: 30-scene table")
+    grids = [make_pair(synth.blob_scene((20, 18, 22), n_blobs=2, occupancy=0.2, seed=60 + i))[1]
+             for i in range(30)]
+    table = B.SceneTable(grids)
+    reqs = random_requests(6, 30, seed=61, resolutions=((24, 16),))
+    for k, r in enumerate(reqs):
+        r.scene = 24 + k  # scenes written by the second set-up launch
+    together = _render(grids, reqs)
+    for r, img in zip(reqs, together):
+        alone = _render([grids[r.scene]], [Request(0, r.c2w, r.focal, r.width, r.height)])[0]
+        assert torch.equal(img, alone)
