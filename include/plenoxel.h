@@ -423,7 +423,9 @@ int plx_bins_apply(const plx_grid *grid, const float *rays_o, const float *rays_
                    const plx_bins *bins, plx_stream stream);
 
 /* PLX_OK when every segment of plx_bins_apply went where plx_bins_count
- * reserved it, PLX_EDEVICE otherwise.  Synchronising. */
+ * reserved it, PLX_EDEVICE otherwise.  Synchronising.  After a PLX_EDEVICE
+ * the render calls' results on those bins are not defined (a segment
+ * without sample slots contributes nothing to a training call). */
 int plx_bins_verify(const plx_grid *grid, const plx_bins *bins, plx_stream stream);
 
 /* Forward rendering (Sec. 3.1-3.3).  Each ray (unit direction) is marched

@@ -1244,9 +1244,11 @@ void seg_fwd_kernel(GridDev g, BinArgs a) {
 // brick with segments one workgroup: the brick's corner records are loaded
 // once, coalesced, into LDS, and the workgroup's lanes march the brick's
 // segments (one lane each) with the corner fetches served from LDS.  The
-// arithmetic is that of seg_fwd.  It serves the 16-bit storage types; FP32
-// records need 82 KB of LDS per brick, which leaves one workgroup (about two
-// busy waves) per CU, and there the lane-per-segment kernel wins.
+// arithmetic is that of seg_fwd.  It serves the forward renders of the
+// 16-bit storage types (the recording forward of the training call is the
+// sample-parallel one below); FP32 records need 82 KB of LDS per brick,
+// which leaves one workgroup (about two busy waves) per CU, and there the
+// lane-per-segment kernel wins.
 
 // 16-byte words of a staged record: FP32 slots 0..26 and the density in
 // word 6's last float (28 floats); the 64-byte 16-bit record as stored.
@@ -1428,6 +1430,211 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_brick_kernel(GridDev g, BinA
         a.tau_seg[sg.w] = tau;
         a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
         if (REC) a.nocc[i] = (int)min((int64_t)j, room);
+    }
+}
+
+// ------------------------------------------------------------ sample-parallel forward
+//
+// The recording forward of the training call, one workgroup per brick with
+// segments, in three phases per group of up to kFwdSegs of its segments:
+//  1. one lane per segment walks its occupied samples and stores each one's
+//     position record (position in its cell, sample index, cell) in the
+//     segment's slots of the sample buffer;
+//  2. every lane takes samples of the group (all lanes busy, whatever the
+//     segments' lengths) and interpolates them from the brick's corner
+//     records, staged in LDS (FP32 in two halves along x of 5 x 9 x 9
+//     corners, 45 KB, so that two workgroups fit on a CU; 16-bit records
+//     whole), storing the values in the sample's record;
+//  3. one lane per segment composes its samples' records in order.
+// The values and the composition are those of seg_fwd (project each corner
+// on the ray's SH basis, trilinear weights, Eq. (1) with the FP64 optical
+// depth); only the assignment of work to lanes differs.
+
+constexpr int kFwdThreads = 512;  // threads of a forward workgroup
+constexpr int kFwdSegs = 512;     // segments per group
+constexpr int kFwdPer = 4;        // samples a thread keeps across the halves
+constexpr int kFwdChunk = kFwdPer * kFwdThreads;
+
+template <int DT> struct FwdStage {
+    static constexpr int kHalves = DT == PLX_F32 ? 2 : 1;
+    static constexpr int kPlanes = PLX_BRICK / kHalves + 1;  // corner planes along x per half
+    static constexpr int kWords = StagedRec<DT>::kWords;
+    static constexpr int kVox = kPlanes * 81;
+};
+
+// Stages the corner records of planes x = x0 .. x0 + kPlanes - 1 of the
+// brick's 9^3 lattice (NULL corners as zeros).
+template <int DT>
+__device__ __forceinline__ void stage_planes(const GridDev &g, uint4 *s_rec, const int *s_id, int x0) {
+    constexpr int W = FwdStage<DT>::kWords;
+    for (int k = threadIdx.x; k < FwdStage<DT>::kVox * W; k += kFwdThreads) {
+        const int p = k / W, w = k - p * W;
+        const int id = s_id[x0 * 81 + p];
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (id >= 0) {
+            if constexpr (DT == PLX_F32) {
+                const float *rec = static_cast<const float *>(g.data) + (int64_t)id * PLX_REC_SLOTS;
+                v = reinterpret_cast<const uint4 *>(rec)[w];
+                if (w == 6) v.w = __float_as_uint(rec[PLX_SLOT_SIGMA]);  // slot 27 is padding
+            } else {
+                v = reinterpret_cast<const uint4 *>(static_cast<const char *>(g.data) +
+                                                    (int64_t)id * kRec16Bytes)[w];
+            }
+        }
+        s_rec[k] = v;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
+    using FS = FwdStage<DT>;
+    __shared__ uint4 s_rec[FS::kVox * FS::kWords];
+    __shared__ int s_id[kBrickVox];
+    __shared__ float4 s_y4[kFwdSegs * 3];      // SH basis of each segment's ray (9 of 12 floats)
+    __shared__ int s_pre[kFwdSegs + 1];        // first sample of each segment in the group's numbering
+    __shared__ int64_t s_soff[kFwdSegs];       // its first sample slot
+    if (blockIdx.x >= (unsigned)a.n_brick) return;
+    const int t = threadIdx.x;
+    float *s_y = reinterpret_cast<float *>(s_y4);
+    const int64_t jo = a.blist[blockIdx.x];
+    const int nty = (g.by + kTile - 1) / kTile, ntz = (g.bz + kTile - 1) / kTile;
+    const int64_t tile = jo / (kTile * kTile * kTile);
+    const int in = (int)(jo % (kTile * kTile * kTile));
+    const int b0[3] = {((int)(tile / ((int64_t)nty * ntz)) * kTile + in / (kTile * kTile)) * PLX_BRICK,
+                       ((int)((tile / ntz) % nty) * kTile + (in / kTile) % kTile) * PLX_BRICK,
+                       ((int)(tile % ntz) * kTile + in % kTile) * PLX_BRICK};
+    const int64_t seg0 = a.boff[jo * kLenClasses], seg1 = a.boff[(jo + 1) * kLenClasses];
+    for (int p = t; p < kBrickVox; p += kFwdThreads) {
+        const int X = b0[0] + p / 81, Y = b0[1] + (p / 9) % 9, Z = b0[2] + p % 9;
+        s_id[p] = (X < g.nx && Y < g.ny && Z < g.nz) ? g.index[((int64_t)X * g.ny + Y) * g.nz + Z] : -1;
+    }
+    bool staged = false;  // whole-brick staging (16-bit) is loaded once
+
+    for (int64_t c0 = seg0; c0 < seg1; c0 += kFwdSegs) {
+        const int ns = (int)min((int64_t)kFwdSegs, seg1 - c0);
+        // 1. walk: lane t < ns stores its segment's sample positions
+        const int64_t i = c0 + t;
+        int4 sg = make_int4(0, 0, -1, 0);
+        bool live = false;
+        RayGeom r = {};
+        int occ = 0;
+        int64_t base = 0;
+        if (t < ns) {
+            sg = a.bseg[i];
+            float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+            live = seg_valid(a, sg, a.n_seg);
+            if (live) {
+                load_ray_lane(a, sg.x, o, d);
+                const int n = ray_setup(g, o, d, r);
+                base = a.soff[i];
+                const int64_t room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
+                if (base >= 0 && base + room <= a.samp_cap) {
+                    SpanCursor cur{sg.y, 0, 0u};
+                    while (true) {
+                        const int k = span_next_up(g, r, n, sg.z, cur);
+                        if (k < 0) break;
+                        const Sample sm = sample_at(g, r, k);
+                        const int code = (k << 9) | ((sm.cell[0] & (PLX_BRICK - 1)) << 6) |
+                                         ((sm.cell[1] & (PLX_BRICK - 1)) << 3) | (sm.cell[2] & (PLX_BRICK - 1));
+                        a.srec[base + occ].pos = make_float4(sm.f[0], sm.f[1], sm.f[2], __int_as_float(code));
+                        ++occ;
+                    }
+                }
+            }
+            sh_basis_all(d, s_y + t * 12);
+            s_soff[t] = base;
+        }
+        int64_t tot64;
+        const int pre = (int)block_scan_excl<kFwdThreads>(occ, &tot64);
+        const int tot = (int)tot64;
+        if (t < kFwdSegs) s_pre[t] = pre;  // segments past ns hold the total
+        if (t == 0) s_pre[kFwdSegs] = tot;
+        __syncthreads();  // positions stored, s_pre / s_soff / s_y written
+
+        // 2. values: kFwdPer samples per thread per chunk, each half staged once per chunk
+        for (int q0 = 0; q0 < tot; q0 += kFwdChunk) {
+            int seg_u[kFwdPer];
+            int64_t slot_u[kFwdPer];
+            float4 pos_u[kFwdPer];
+#pragma unroll
+            for (int u = 0; u < kFwdPer; ++u) {
+                const int q = q0 + u * kFwdThreads + t;
+                seg_u[u] = -1;
+                slot_u[u] = 0;
+                if (q < tot) {
+                    int lo = 0, hi = ns - 1;  // last segment whose first sample is <= q
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= q) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    seg_u[u] = lo;
+                    slot_u[u] = s_soff[lo] + (q - s_pre[lo]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kFwdPer; ++u)
+                if (seg_u[u] >= 0) pos_u[u] = a.srec[slot_u[u]].pos;
+            for (int h = 0; h < FS::kHalves; ++h) {
+                if (FS::kHalves > 1 || !staged) {
+                    __syncthreads();  // the previous half's reads are done
+                    stage_planes<DT>(g, s_rec, s_id, h * (FS::kPlanes - 1));
+                    __syncthreads();
+                    staged = true;
+                }
+#pragma unroll
+                for (int u = 0; u < kFwdPer; ++u) {
+                    if (seg_u[u] < 0) continue;
+                    const int code = __float_as_int(pos_u[u].w);
+                    const int cx = (code >> 6) & (PLX_BRICK - 1), cy = (code >> 3) & (PLX_BRICK - 1),
+                              cz = code & (PLX_BRICK - 1);
+                    const int lx = cx - h * (FS::kPlanes - 1);
+                    if (lx < 0 || lx >= FS::kPlanes - 1) continue;  // the sample's cell is in the other half
+                    float y[9];
+#pragma unroll
+                    for (int l = 0; l < 9; ++l) y[l] = s_y[seg_u[u] * 12 + l];
+                    const float f[3] = {pos_u[u].x, pos_u[u].y, pos_u[u].z};
+                    float w[8];
+                    corner_weights(f, w);
+                    Q4 v = q4_zero();
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int p = (lx + ((c >> 2) & 1)) * 81 + (cy + ((c >> 1) & 1)) * 9 + (cz + (c & 1));
+                        const Q4 qc = project_staged<DT>(s_rec + p * FS::kWords, y);
+                        v.s += w[c] * qc.s;
+                        v.r += w[c] * qc.r;
+                        v.g += w[c] * qc.g;
+                        v.b += w[c] * qc.b;
+                    }
+                    a.srec[slot_u[u]].val = make_float4(v.s, v.r, v.g, v.b);
+                }
+            }
+        }
+        __syncthreads();  // every value stored before the segments compose
+
+        // 3. composition, one lane per segment, in sample order
+        if (live) {
+            double tau = 0.0;
+            float C[3] = {0.0f, 0.0f, 0.0f};
+            // (a segment without slots, which the emit walk reports in the
+            // status word, contributes nothing)
+            for (int j = 0; j < occ; ++j) {
+                const SampleRec rc = a.srec[base + j];
+                const int k = (int)((unsigned)__float_as_int(rc.pos.w) >> 9);
+                const float delta = sample_at(g, r, k).delta;
+                const float sd = fmaxf(rc.val.x, 0.0f) * delta;
+                const float wk = expf(-(float)tau) * (-expm1f(-sd));
+                C[0] += wk * fmaxf(rc.val.y, 0.0f);
+                C[1] += wk * fmaxf(rc.val.z, 0.0f);
+                C[2] += wk * fmaxf(rc.val.w, 0.0f);
+                tau += (double)sd;
+            }
+            a.tau_seg[sg.w] = tau;
+            a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
+            a.nocc[i] = occ;
+        }
+        __syncthreads();  // s_y / s_pre / s_soff are rewritten by the next group
     }
 }
 
@@ -2566,16 +2773,15 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     }
     if (a.n_seg > 0) {
         const bool rec = MODE != MODE_FWD && a.srec;
-        if (a.blist && a.n_brick > 0 && grid->sh_dtype != PLX_F32) {
+        if (rec && a.blist && a.n_brick > 0) {
+            // recording forward: sample-parallel, one workgroup per brick
+            PLX_DISPATCH_DT(grid->sh_dtype, DT,
+                            seg_fwd_samples_kernel<DT><<<(unsigned)a.n_brick, kFwdThreads, 0, s>>>(g, as));
+        } else if (a.blist && a.n_brick > 0 && grid->sh_dtype != PLX_F32) {
             // brick-staged (16-bit records: 47 KB of LDS per brick, three
             // workgroups per CU; FP32's 82 KB leave one, and the lane-per-
             // segment kernel with its L2 traffic is then twice as fast)
-            const unsigned nb = (unsigned)a.n_brick;
-            if (rec) {
-                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, true><<<nb, kThreads, 0, s>>>(g, as));
-            } else {
-                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, false><<<nb, kThreads, 0, s>>>(g, as));
-            }
+            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, false><<<(unsigned)a.n_brick, kThreads, 0, s>>>(g, as));
         } else if (rec) {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
         } else {
