@@ -1452,14 +1452,15 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_brick_kernel(GridDev g, BinA
 
 constexpr int kFwdThreads = 512;  // threads of a forward workgroup
 constexpr int kFwdSegs = 512;     // segments per group
-constexpr int kFwdPer = 4;        // samples a thread keeps across the halves
-constexpr int kFwdChunk = kFwdPer * kFwdThreads;
 
 template <int DT> struct FwdStage {
     static constexpr int kHalves = DT == PLX_F32 ? 2 : 1;
     static constexpr int kPlanes = PLX_BRICK / kHalves + 1;  // corner planes along x per half
     static constexpr int kWords = StagedRec<DT>::kWords;
     static constexpr int kVox = kPlanes * 81;
+    // samples a thread keeps across the halves (FP32: two, within 128 registers)
+    static constexpr int kPer = DT == PLX_F32 ? 2 : 4;
+    static constexpr int kChunk = kPer * kFwdThreads;
 };
 
 // Stages the corner records of planes x = x0 .. x0 + kPlanes - 1 of the
@@ -1485,11 +1486,53 @@ __device__ __forceinline__ void stage_planes(const GridDev &g, uint4 *s_rec, con
     }
 }
 
+// Loads the words of corner p (brick lattice position) of the brick at b0
+// from its id (NULL: zeros).
+template <int DT>
+__device__ __forceinline__ void load_corner_words(const GridDev &g, int id, uint4 wv[]) {
+    constexpr int W = StagedRec<DT>::kWords;
+#pragma unroll
+    for (int w = 0; w < W; ++w) wv[w] = make_uint4(0u, 0u, 0u, 0u);
+    if (id < 0) return;
+    if constexpr (DT == PLX_F32) {
+        const float *rec = static_cast<const float *>(g.data) + (int64_t)id * PLX_REC_SLOTS;
+#pragma unroll
+        for (int w = 0; w < W; ++w) wv[w] = reinterpret_cast<const uint4 *>(rec)[w];
+        wv[W - 1].w = __float_as_uint(rec[PLX_SLOT_SIGMA]);  // slot 27 is padding
+    } else {
+        const uint4 *rec = reinterpret_cast<const uint4 *>(static_cast<const char *>(g.data) +
+                                                           (int64_t)id * kRec16Bytes);
+#pragma unroll
+        for (int w = 0; w < W; ++w) wv[w] = rec[w];
+    }
+}
+
+// Loads the ids of the brick's 9^3 corners into s_id and the records of the
+// first staging (planes 0 .. kPlanes-1) into s_rec; thread `start` of
+// `stride` threads takes corners start, start + stride, ...
+template <int DT>
+__device__ __forceinline__ void stage_ids_first(const GridDev &g, const int b0[3], int *s_id, uint4 *s_rec,
+                                                int start, int stride) {
+    constexpr int W = StagedRec<DT>::kWords;
+    for (int p = start; p < kBrickVox; p += stride) {
+        const int X = b0[0] + p / 81, Y = b0[1] + (p / 9) % 9, Z = b0[2] + p % 9;
+        const int id = (X < g.nx && Y < g.ny && Z < g.nz) ? g.index[((int64_t)X * g.ny + Y) * g.nz + Z] : -1;
+        s_id[p] = id;
+        if (p < FwdStage<DT>::kVox) {
+            uint4 wv[W];
+            load_corner_words<DT>(g, id, wv);
+#pragma unroll
+            for (int w = 0; w < W; ++w) s_rec[p * W + w] = wv[w];
+        }
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
     using FS = FwdStage<DT>;
-    __shared__ uint4 s_rec[FS::kVox * FS::kWords];
+    constexpr int W = FS::kWords;
+    __shared__ uint4 s_rec[FS::kVox * W];
     __shared__ int s_id[kBrickVox];
     __shared__ float4 s_y4[kFwdSegs * 3];      // SH basis of each segment's ray (9 of 12 floats)
     __shared__ int s_pre[kFwdSegs + 1];        // first sample of each segment in the group's numbering
@@ -1505,11 +1548,7 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
                        ((int)((tile / ntz) % nty) * kTile + (in / kTile) % kTile) * PLX_BRICK,
                        ((int)(tile % ntz) * kTile + in % kTile) * PLX_BRICK};
     const int64_t seg0 = a.boff[jo * kLenClasses], seg1 = a.boff[(jo + 1) * kLenClasses];
-    for (int p = t; p < kBrickVox; p += kFwdThreads) {
-        const int X = b0[0] + p / 81, Y = b0[1] + (p / 9) % 9, Z = b0[2] + p % 9;
-        s_id[p] = (X < g.nx && Y < g.ny && Z < g.nz) ? g.index[((int64_t)X * g.ny + Y) * g.nz + Z] : -1;
-    }
-    bool staged = false;  // whole-brick staging (16-bit) is loaded once
+    int cur_half = -1;  // half whose corners are in LDS
 
     for (int64_t c0 = seg0; c0 < seg1; c0 += kFwdSegs) {
         const int ns = (int)min((int64_t)kFwdSegs, seg1 - c0);
@@ -1520,14 +1559,19 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
         RayGeom r = {};
         int occ = 0;
         int64_t base = 0;
+        // the waves with no segment of the first group load the corner ids
+        // and the first staging meanwhile
+        const int st0 = (ns + kWave - 1) / kWave * kWave;
+        const bool pre_stage = cur_half < 0 && st0 < kFwdThreads;
+        if (pre_stage && t >= st0) stage_ids_first<DT>(g, b0, s_id, s_rec, t - st0, kFwdThreads - st0);
         if (t < ns) {
             sg = a.bseg[i];
+            base = a.soff[i];
             float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
             live = seg_valid(a, sg, a.n_seg);
             if (live) {
                 load_ray_lane(a, sg.x, o, d);
                 const int n = ray_setup(g, o, d, r);
-                base = a.soff[i];
                 const int64_t room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
                 if (base >= 0 && base + room <= a.samp_cap) {
                     SpanCursor cur{sg.y, 0, 0u};
@@ -1545,20 +1589,28 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
             sh_basis_all(d, s_y + t * 12);
             s_soff[t] = base;
         }
+        if (cur_half < 0) {
+            if (!pre_stage) {
+                // no wave was free during the walk: all threads stage
+                stage_ids_first<DT>(g, b0, s_id, s_rec, t, kFwdThreads);
+            }
+            cur_half = 0;
+        }
         int64_t tot64;
         const int pre = (int)block_scan_excl<kFwdThreads>(occ, &tot64);
         const int tot = (int)tot64;
         if (t < kFwdSegs) s_pre[t] = pre;  // segments past ns hold the total
         if (t == 0) s_pre[kFwdSegs] = tot;
-        __syncthreads();  // positions stored, s_pre / s_soff / s_y written
+        __syncthreads();  // positions stored, s_pre / s_soff / s_y / the staging written
 
-        // 2. values: kFwdPer samples per thread per chunk, each half staged once per chunk
-        for (int q0 = 0; q0 < tot; q0 += kFwdChunk) {
-            int seg_u[kFwdPer];
-            int64_t slot_u[kFwdPer];
-            float4 pos_u[kFwdPer];
+        // 2. values: FS::kPer samples per thread per chunk; the chunk takes the
+        // halves starting with the one in LDS
+        for (int q0 = 0; q0 < tot; q0 += FS::kChunk) {
+            int seg_u[FS::kPer];
+            int64_t slot_u[FS::kPer];
+            float4 pos_u[FS::kPer];
 #pragma unroll
-            for (int u = 0; u < kFwdPer; ++u) {
+            for (int u = 0; u < FS::kPer; ++u) {
                 const int q = q0 + u * kFwdThreads + t;
                 seg_u[u] = -1;
                 slot_u[u] = 0;
@@ -1574,17 +1626,18 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kFwdPer; ++u)
+            for (int u = 0; u < FS::kPer; ++u)
                 if (seg_u[u] >= 0) pos_u[u] = a.srec[slot_u[u]].pos;
-            for (int h = 0; h < FS::kHalves; ++h) {
-                if (FS::kHalves > 1 || !staged) {
-                    __syncthreads();  // the previous half's reads are done
+            for (int hh = 0; hh < FS::kHalves; ++hh) {
+                const int h = (cur_half + hh) % FS::kHalves;
+                if (h != cur_half) {
+                    __syncthreads();  // the other half's reads are done
                     stage_planes<DT>(g, s_rec, s_id, h * (FS::kPlanes - 1));
                     __syncthreads();
-                    staged = true;
+                    cur_half = h;
                 }
 #pragma unroll
-                for (int u = 0; u < kFwdPer; ++u) {
+                for (int u = 0; u < FS::kPer; ++u) {
                     if (seg_u[u] < 0) continue;
                     const int code = __float_as_int(pos_u[u].w);
                     const int cx = (code >> 6) & (PLX_BRICK - 1), cy = (code >> 3) & (PLX_BRICK - 1),
@@ -1601,7 +1654,7 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         const int p = (lx + ((c >> 2) & 1)) * 81 + (cy + ((c >> 1) & 1)) * 9 + (cz + (c & 1));
-                        const Q4 qc = project_staged<DT>(s_rec + p * FS::kWords, y);
+                        const Q4 qc = project_staged<DT>(s_rec + p * W, y);
                         v.s += w[c] * qc.s;
                         v.r += w[c] * qc.r;
                         v.g += w[c] * qc.g;
@@ -1613,22 +1666,30 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
         }
         __syncthreads();  // every value stored before the segments compose
 
-        // 3. composition, one lane per segment, in sample order
+        // 3. composition, one lane per segment, in sample order, the record
+        // loads kCompU at a time (a segment without slots, which the emit walk
+        // reports in the status word, contributes nothing)
         if (live) {
+            constexpr int kCompU = 4;
             double tau = 0.0;
             float C[3] = {0.0f, 0.0f, 0.0f};
-            // (a segment without slots, which the emit walk reports in the
-            // status word, contributes nothing)
-            for (int j = 0; j < occ; ++j) {
-                const SampleRec rc = a.srec[base + j];
-                const int k = (int)((unsigned)__float_as_int(rc.pos.w) >> 9);
-                const float delta = sample_at(g, r, k).delta;
-                const float sd = fmaxf(rc.val.x, 0.0f) * delta;
-                const float wk = expf(-(float)tau) * (-expm1f(-sd));
-                C[0] += wk * fmaxf(rc.val.y, 0.0f);
-                C[1] += wk * fmaxf(rc.val.z, 0.0f);
-                C[2] += wk * fmaxf(rc.val.w, 0.0f);
-                tau += (double)sd;
+            for (int j0 = 0; j0 < occ; j0 += kCompU) {
+                SampleRec rb[kCompU];
+#pragma unroll
+                for (int u = 0; u < kCompU; ++u)
+                    if (j0 + u < occ) rb[u] = a.srec[base + j0 + u];
+#pragma unroll
+                for (int u = 0; u < kCompU; ++u) {
+                    if (j0 + u >= occ) break;
+                    const int k = (int)((unsigned)__float_as_int(rb[u].pos.w) >> 9);
+                    const float delta = sample_at(g, r, k).delta;
+                    const float sd = fmaxf(rb[u].val.x, 0.0f) * delta;
+                    const float wk = expf(-(float)tau) * (-expm1f(-sd));
+                    C[0] += wk * fmaxf(rb[u].val.y, 0.0f);
+                    C[1] += wk * fmaxf(rb[u].val.z, 0.0f);
+                    C[2] += wk * fmaxf(rb[u].val.w, 0.0f);
+                    tau += (double)sd;
+                }
             }
             a.tau_seg[sg.w] = tau;
             a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
