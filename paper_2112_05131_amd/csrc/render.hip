@@ -1955,6 +1955,7 @@ struct LdsSample {
     float v[4];
     int seg;
 };
+static_assert(sizeof(LdsSample) == 32, "two 16-byte words per sample");
 
 // Sends the 28 gradient values of every lane's voxel (id < 0: none) to the
 // FP32 records, kStageRows rows at a time through the wave's staging rows:
@@ -2012,7 +2013,7 @@ void seg_scatter_kernel(GridDev g, BinArgs a) {
     __shared__ float4 s_y4[kScatterSegs * 3];  // SH basis of its ray (9 of 12 floats)
     __shared__ int s_cnt[kBrickCells];         // samples per cell
     __shared__ int s_coff[kBrickCells + 1];    // first sorted position of each cell
-    __shared__ LdsSample s_rec[kScatterCap];   // the pass's samples
+    __shared__ __align__(16) LdsSample s_rec[kScatterCap];   // the pass's samples
     __shared__ float s_stage[kScatterThreads / kWave * kStageRows * kStageStride];
 
     if (blockIdx.x >= (unsigned)a.n_brick) return;
@@ -2187,37 +2188,75 @@ void seg_scatter_kernel(GridDev g, BinArgs a) {
                 float acc[28];
 #pragma unroll
                 for (int v = 0; v < 28; ++v) acc[v] = 0.0f;
-                bool any = false;
-                if (vid[rr] >= 0) {
+                // the sample ranges of the voxel's (up to) 8 cells, the
+                // non-empty ones first in corner order (start | count << 11 |
+                // corner << 22), walked as one list: a wave then runs as long
+                // as its busiest lane's total, not the sum over the corners of
+                // each corner's busiest lane
+                unsigned qr[8];
+                int nne = 0;
+                {
                     const int px = p / 81, py = (p / 9) % 9, pz = p % 9;
-#pragma unroll 1
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) qr[j] = 0u;
+#pragma unroll
                     for (int o = 0; o < 8; ++o) {
                         // the voxel is corner o (x: bit 2) of the cell p - o
-                        const int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
-                        const int cx = px - ox, cy = py - oy, cz = pz - oz;
-                        if (cx < 0 || cy < 0 || cz < 0 || cx >= PLX_BRICK || cy >= PLX_BRICK || cz >= PLX_BRICK)
-                            continue;
-                        const int cell = (cx << 6) | (cy << 3) | cz;
-                        const int e1 = s_coff[cell + 1];
-                        for (int e = s_coff[cell]; e < e1; ++e) {
-                            const LdsSample &sr = s_rec[e];
-                            const float wx = ox ? sr.f[0] : 1.0f - sr.f[0];
-                            const float wy = oy ? sr.f[1] : 1.0f - sr.f[1];
-                            const float wz = oz ? sr.f[2] : 1.0f - sr.f[2];
-                            const float w = wx * wy * wz;
-                            const float4 y0 = s_y4[sr.seg * 3], y1 = s_y4[sr.seg * 3 + 1],
-                                         y2 = s_y4[sr.seg * 3 + 2];
-                            const float yy[9] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w, y2.x};
-                            const float a_r = w * sr.v[1], a_g = w * sr.v[2], a_b = w * sr.v[3];
-#pragma unroll
-                            for (int l = 0; l < 9; ++l) {
-                                acc[l] += a_r * yy[l];
-                                acc[9 + l] += a_g * yy[l];
-                                acc[18 + l] += a_b * yy[l];
-                            }
-                            acc[27] += w * sr.v[0];
-                            any = true;
+                        const int cx = px - ((o >> 2) & 1), cy = py - ((o >> 1) & 1), cz = pz - (o & 1);
+                        unsigned ent = 0u;
+                        if (vid[rr] >= 0 && cx >= 0 && cy >= 0 && cz >= 0 && cx < PLX_BRICK && cy < PLX_BRICK &&
+                            cz < PLX_BRICK) {
+                            const int cell = (cx << 6) | (cy << 3) | cz;
+                            const int c0 = s_coff[cell], n = s_coff[cell + 1] - c0;
+                            if (n > 0) ent = (unsigned)c0 | ((unsigned)n << 11) | ((unsigned)o << 22);
                         }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (ent != 0u && j == nne) qr[j] = ent;
+                        nne += ent != 0u ? 1 : 0;
+                    }
+                }
+                const bool any = nne > 0;
+                int e = (int)(qr[0] & 0x7ffu), cnt = (int)((qr[0] >> 11) & 0x7ffu), oc = (int)(qr[0] >> 22);
+#pragma unroll
+                for (int j = 0; j < 7; ++j) qr[j] = qr[j + 1];
+                qr[7] = 0u;
+#pragma unroll 1
+                for (;;) {
+                    // the wave leaves together; a lane that is done adds nothing
+                    const bool live = cnt > 0;
+                    if (__ballot(live) == 0) break;
+                    // the whole sample in two 16-byte reads, f0 f1 f2 v0 | v1 v2 v3 seg
+                    // (a done lane reads sorted sample 0, a valid one)
+                    const float4 *sp = reinterpret_cast<const float4 *>(s_rec + (live ? e : 0));
+                    const float4 sa = sp[0], sb = sp[1];
+                    const float wx = (oc & 4) ? sa.x : 1.0f - sa.x;
+                    const float wy = (oc & 2) ? sa.y : 1.0f - sa.y;
+                    const float wz = (oc & 1) ? sa.z : 1.0f - sa.z;
+                    const float w = wx * wy * wz;
+                    const int sy = __float_as_int(sb.w) * 3;
+                    const float4 y0 = s_y4[sy], y1 = s_y4[sy + 1], y2 = s_y4[sy + 2];
+                    const float yy[9] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w, y2.x};
+                    const float a_r = live ? w * sb.x : 0.0f, a_g = live ? w * sb.y : 0.0f,
+                                a_b = live ? w * sb.z : 0.0f;
+#pragma unroll
+                    for (int l = 0; l < 9; ++l) {
+                        acc[l] += a_r * yy[l];
+                        acc[9 + l] += a_g * yy[l];
+                        acc[18 + l] += a_b * yy[l];
+                    }
+                    const float s27 = acc[27] + w * sa.w;
+                    acc[27] = live ? s27 : acc[27];
+                    ++e;
+                    cnt -= live ? 1 : 0;
+                    if (live && cnt == 0) {
+                        // next range (an empty entry leaves the lane done)
+                        e = (int)(qr[0] & 0x7ffu);
+                        cnt = (int)((qr[0] >> 11) & 0x7ffu);
+                        oc = (int)(qr[0] >> 22);
+#pragma unroll
+                        for (int j = 0; j < 7; ++j) qr[j] = qr[j + 1];
+                        qr[7] = 0u;
                     }
                 }
                 flush_voxel_rows(stage, acc, any ? vid[rr] : -1, a.grad, a.touched);
