@@ -470,17 +470,20 @@ __device__ __forceinline__ Q4 interpolate(const CornerCache &cc, const float w[8
 
 // ------------------------------------------------------------ sample cursor
 
-// Occupancy of samples k0 .. k0+15 (bit i: sample k0+i exists and its cell
-// is occupied); the 16 bitmap loads are independent.
+// Occupancy of samples k0 .. k0+M-1 (bit i: sample k0+i exists and its cell
+// is occupied); the M bitmap loads are independent.
 // The loads are unconditional (indices outside [0, n) are clamped and their
 // bits masked off afterwards): a load under a per-sample branch would be
 // waited for inside that branch, serialising the 16 round trips.
+template <int M = kChunk>
 __device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &r, int n, int k0) {
+    static_assert(M >= 1 && M < 32, "chunk size");
+    constexpr uint32_t kFull = (1u << M) - 1u;
     const int k_max = n > 0 ? n - 1 : 0;
-    uint32_t word[kChunk];
-    int bit[kChunk];
+    uint32_t word[M];
+    int bit[M];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) {
+    for (int i = 0; i < M; ++i) {
         int k = k0 + i;
         k = k < 0 ? 0 : (k > k_max ? k_max : k);
         const Sample s = sample_at(g, r, k);
@@ -491,12 +494,12 @@ __device__ __forceinline__ uint32_t chunk_bits(const GridDev &g, const RayGeom &
     }
     uint32_t m = 0;
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) m |= ((word[i] >> bit[i]) & 1u) << i;
+    for (int i = 0; i < M; ++i) m |= ((word[i] >> bit[i]) & 1u) << i;
     // samples k0 + i inside [0, n)
     const int lo = k0 < 0 ? -k0 : 0;
     const int hi = n - k0;  // first i past the end
-    uint32_t valid = hi <= 0 ? 0u : (hi >= kChunk ? 0xffffu : ((1u << hi) - 1u));
-    valid &= lo >= kChunk ? 0u : (0xffffu << lo);
+    uint32_t valid = hi <= 0 ? 0u : (hi >= M ? kFull : ((1u << hi) - 1u));
+    valid &= lo >= M ? 0u : ((kFull << lo) & kFull);
     return m & valid;
 }
 
@@ -1452,6 +1455,7 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_brick_kernel(GridDev g, BinA
 
 constexpr int kFwdThreads = 512;  // threads of a forward workgroup
 constexpr int kFwdSegs = 512;     // segments per group
+constexpr int kWalkRun = 8;       // consecutive samples a walking lane tests at once
 
 template <int DT> struct FwdStage {
     static constexpr int kHalves = DT == PLX_F32 ? 2 : 1;
@@ -1552,8 +1556,13 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
 
     for (int64_t c0 = seg0; c0 < seg1; c0 += kFwdSegs) {
         const int ns = (int)min((int64_t)kFwdSegs, seg1 - c0);
-        // 1. walk: lane t < ns stores its segment's sample positions
-        const int64_t i = c0 + t;
+        // 1. walk: kL lanes per segment (lane t: segment t / kL, part t % kL),
+        // each taking runs of kWalkRun consecutive samples, store the
+        // segment's occupied sample positions in order
+        const int kL = ns * 4 <= kFwdThreads - 2 * kWave ? 4 : (ns * 2 <= kFwdThreads - 2 * kWave ? 2 : 1);
+        const int sx = t / kL, part = t % kL;
+        const bool mine = sx < ns;
+        const int64_t i = c0 + sx;
         int4 sg = make_int4(0, 0, -1, 0);
         bool live = false;
         RayGeom r = {};
@@ -1561,10 +1570,10 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
         int64_t base = 0;
         // the waves with no segment of the first group load the corner ids
         // and the first staging meanwhile
-        const int st0 = (ns + kWave - 1) / kWave * kWave;
+        const int st0 = (ns * kL + kWave - 1) / kWave * kWave;
         const bool pre_stage = cur_half < 0 && st0 < kFwdThreads;
         if (pre_stage && t >= st0) stage_ids_first<DT>(g, b0, s_id, s_rec, t - st0, kFwdThreads - st0);
-        if (t < ns) {
+        if (mine) {
             sg = a.bseg[i];
             base = a.soff[i];
             float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
@@ -1574,20 +1583,39 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
                 const int n = ray_setup(g, o, d, r);
                 const int64_t room = (int64_t)sg.z - sg.y + 1;  // the slots the count reserved
                 if (base >= 0 && base + room <= a.samp_cap) {
-                    SpanCursor cur{sg.y, 0, 0u};
-                    while (true) {
-                        const int k = span_next_up(g, r, n, sg.z, cur);
-                        if (k < 0) break;
-                        const Sample sm = sample_at(g, r, k);
-                        const int code = (k << 9) | ((sm.cell[0] & (PLX_BRICK - 1)) << 6) |
-                                         ((sm.cell[1] & (PLX_BRICK - 1)) << 3) | (sm.cell[2] & (PLX_BRICK - 1));
-                        a.srec[base + occ].pos = make_float4(sm.f[0], sm.f[1], sm.f[2], __int_as_float(code));
-                        ++occ;
+                    // the kL lanes of a segment are adjacent and loop together
+                    for (int kr = sg.y; kr <= sg.z; kr += kL * kWalkRun) {
+                        const int ks = kr + part * kWalkRun;
+                        uint32_t bits = 0u;
+                        if (ks <= sg.z) {
+                            bits = chunk_bits<kWalkRun>(g, r, n, ks);
+                            if (sg.z - ks < kWalkRun - 1) bits &= (2u << (sg.z - ks)) - 1u;
+                        }
+                        const int c = __popc(bits);
+                        int incl = c;  // inclusive prefix over the segment's parts
+                        for (int dd = 1; dd < kL; dd <<= 1) {
+                            const int y = __shfl_up(incl, dd, kL);
+                            if (part >= dd) incl += y;
+                        }
+                        const int all = __shfl(incl, kL - 1, kL);
+                        int at = occ + incl - c;
+                        while (bits != 0u) {
+                            const int k = ks + __builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            const Sample sm = sample_at(g, r, k);
+                            const int code = (k << 9) | ((sm.cell[0] & (PLX_BRICK - 1)) << 6) |
+                                             ((sm.cell[1] & (PLX_BRICK - 1)) << 3) | (sm.cell[2] & (PLX_BRICK - 1));
+                            a.srec[base + at].pos = make_float4(sm.f[0], sm.f[1], sm.f[2], __int_as_float(code));
+                            ++at;
+                        }
+                        occ += all;
                     }
                 }
             }
-            sh_basis_all(d, s_y + t * 12);
-            s_soff[t] = base;
+            if (part == 0) {
+                sh_basis_all(d, s_y + sx * 12);
+                s_soff[sx] = base;
+            }
         }
         if (cur_half < 0) {
             if (!pre_stage) {
@@ -1597,9 +1625,9 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
             cur_half = 0;
         }
         int64_t tot64;
-        const int pre = (int)block_scan_excl<kFwdThreads>(occ, &tot64);
+        const int pre = (int)block_scan_excl<kFwdThreads>(mine && part == 0 ? occ : 0, &tot64);
         const int tot = (int)tot64;
-        if (t < kFwdSegs) s_pre[t] = pre;  // segments past ns hold the total
+        if (mine && part == 0) s_pre[sx] = pre;
         if (t == 0) s_pre[kFwdSegs] = tot;
         __syncthreads();  // positions stored, s_pre / s_soff / s_y / the staging written
 
@@ -1666,21 +1694,25 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
         }
         __syncthreads();  // every value stored before the segments compose
 
-        // 3. composition, one lane per segment, in sample order, the record
-        // loads kCompU at a time (a segment without slots, which the emit walk
-        // reports in the status word, contributes nothing)
-        if (live) {
+        // 3. composition: the kL lanes of a segment each compose a run of its
+        // samples (transmittance from the run's start, record loads kCompU at
+        // a time), then the runs are chained: run q's colour is scaled by the
+        // transmittance of the runs before it (a segment without slots, which
+        // the emit walk reports in the status word, contributes nothing)
+        if (mine && live) {
             constexpr int kCompU = 4;
+            const int per = (occ + kL - 1) / kL;
+            const int j_lo = min(occ, part * per), j_hi = min(occ, j_lo + per);
             double tau = 0.0;
             float C[3] = {0.0f, 0.0f, 0.0f};
-            for (int j0 = 0; j0 < occ; j0 += kCompU) {
+            for (int j0 = j_lo; j0 < j_hi; j0 += kCompU) {
                 SampleRec rb[kCompU];
 #pragma unroll
                 for (int u = 0; u < kCompU; ++u)
-                    if (j0 + u < occ) rb[u] = a.srec[base + j0 + u];
+                    if (j0 + u < j_hi) rb[u] = a.srec[base + j0 + u];
 #pragma unroll
                 for (int u = 0; u < kCompU; ++u) {
-                    if (j0 + u >= occ) break;
+                    if (j0 + u >= j_hi) break;
                     const int k = (int)((unsigned)__float_as_int(rb[u].pos.w) >> 9);
                     const float delta = sample_at(g, r, k).delta;
                     const float sd = fmaxf(rb[u].val.x, 0.0f) * delta;
@@ -1691,9 +1723,25 @@ void seg_fwd_samples_kernel(GridDev g, BinArgs a) {
                     tau += (double)sd;
                 }
             }
-            a.tau_seg[sg.w] = tau;
-            a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
-            a.nocc[i] = occ;
+            if (kL > 1) {
+                double incl = tau;  // optical depth up to the end of this run
+                for (int dd = 1; dd < kL; dd <<= 1) {
+                    const double y = __shfl_up(incl, dd, kL);
+                    if (part >= dd) incl += y;
+                }
+                const float T0 = expf(-(float)(incl - tau));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    C[c] *= T0;
+                    for (int dd = 1; dd < kL; dd <<= 1) C[c] += __shfl_xor(C[c], dd, kL);
+                }
+                tau = __shfl(incl, kL - 1, kL);
+            }
+            if (part == 0) {
+                a.tau_seg[sg.w] = tau;
+                a.c_seg[sg.w] = make_float4(C[0], C[1], C[2], 0.0f);
+                a.nocc[i] = occ;
+            }
         }
         __syncthreads();  // s_y / s_pre / s_soff are rewritten by the next group
     }
