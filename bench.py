@@ -58,7 +58,8 @@ N_CAMS, W, H = 100, 800, 800
 COUNTERS = os.path.join(ROOT, "profiles", "render_train_512cubed_1Mrays_counters.json")
 RENDER_SRC = os.path.join(ROOT, "paper_2112_05131_amd", "csrc", "render.hip")
 # kernels of one plx_render_train call, as rocprofv3 names them
-COUNTED_KERNELS = {"seg_fwd": ("seg_fwd_kernel", "seg_fwd_brick_kernel"), "seg_combine": ("seg_combine_kernel",),
+COUNTED_KERNELS = {"seg_fwd": ("seg_fwd_samples_kernel", "seg_fwd_kernel", "seg_fwd_brick_kernel"),
+                   "seg_combine": ("seg_combine_kernel",),
                    "seg_scatter": ("seg_scatter_kernel",)}
 
 
