@@ -374,12 +374,14 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
  *     bin-major segment records (and the segments' sample slots).
  *     Asynchronous.
  * With a sample buffer the backward pass of plx_render_bwd/plx_render_train
- * is the recorded one: the replay stores each occupied sample's position
- * and gradients (32 B) in the sample buffer and a second kernel sums them
- * per voxel, one brick per workgroup, so each voxel receives one line of
- * FP32 atomics per brick instead of one per segment (same terms, other
- * order of the additions).  Without one (samp_buf NULL) the replay
- * scatters its gradients itself.
+ * is the recorded one: the forward stores each occupied sample's position
+ * and interpolated values (32 B) in the sample buffer (one workgroup per
+ * brick, the samples interpolated by all its lanes from the brick's corner
+ * records in LDS), and the backward runs the reverse recurrence over them
+ * and sums the gradients per voxel, one brick per workgroup, so each voxel
+ * receives one line of FP32 atomics per brick instead of one per segment
+ * (same terms, other order of the additions).  Without one (samp_buf
+ * NULL) a replay of each segment scatters its gradients itself.
  * The render calls use the buffers as their scratch (per-ray and
  * per-segment values passed between their kernels), so render calls that
  * share one plx_bins must be ordered on a stream; counting the next batch
