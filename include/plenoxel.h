@@ -375,9 +375,10 @@ int plx_bg_render_bwd(const plx_grid *bg_grid, const float *rays_o, const float 
  *     Asynchronous.
  * With a sample buffer the backward pass of plx_render_bwd/plx_render_train
  * is the recorded one: the forward stores each occupied sample's position
- * and interpolated values (32 B) in the sample buffer (one workgroup per
- * brick, the samples interpolated by all its lanes from the brick's corner
- * records in LDS), and the backward runs the reverse recurrence over them
+ * and interpolated values (32 B) in the sample buffer (where the bricks
+ * hold at least 40 segments on average, one workgroup per brick with the
+ * samples interpolated by all its lanes from the brick's corner records in
+ * LDS), and the backward runs the reverse recurrence over them
  * and sums the gradients per voxel, one brick per workgroup, so each voxel
  * receives one line of FP32 atomics per brick instead of one per segment
  * (same terms, other order of the additions).  Without one (samp_buf

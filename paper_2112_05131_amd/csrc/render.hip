@@ -1248,10 +1248,10 @@ void seg_fwd_kernel(GridDev g, BinArgs a) {
 // once, coalesced, into LDS, and the workgroup's lanes march the brick's
 // segments (one lane each) with the corner fetches served from LDS.  The
 // arithmetic is that of seg_fwd.  It serves the forward renders of the
-// 16-bit storage types (the recording forward of the training call is the
-// sample-parallel one below); FP32 records need 82 KB of LDS per brick,
-// which leaves one workgroup (about two busy waves) per CU, and there the
-// lane-per-segment kernel wins.
+// 16-bit storage types, and their recording forward where bricks hold few
+// segments (with many, the sample-parallel one below); FP32 records need
+// 82 KB of LDS per brick, which leaves one workgroup (about two busy waves)
+// per CU, and there the lane-per-segment kernel wins.
 
 // 16-byte words of a staged record: FP32 slots 0..26 and the density in
 // word 6's last float (28 floats); the 64-byte 16-bit record as stored.
@@ -1440,22 +1440,34 @@ __global__ __launch_bounds__(kThreads) void seg_fwd_brick_kernel(GridDev g, BinA
 //
 // The recording forward of the training call, one workgroup per brick with
 // segments, in three phases per group of up to kFwdSegs of its segments:
-//  1. one lane per segment walks its occupied samples and stores each one's
-//     position record (position in its cell, sample index, cell) in the
-//     segment's slots of the sample buffer;
+//  1. two or four lanes per segment (one for a large group) walk its
+//     samples in runs of kWalkRun and store each occupied one's position
+//     record (position in its cell, sample index, cell) in the segment's
+//     slots of the sample buffer, in sample order; the waves with no
+//     segment meanwhile load the brick's corner ids and first staging;
 //  2. every lane takes samples of the group (all lanes busy, whatever the
 //     segments' lengths) and interpolates them from the brick's corner
 //     records, staged in LDS (FP32 in two halves along x of 5 x 9 x 9
 //     corners, 45 KB, so that two workgroups fit on a CU; 16-bit records
 //     whole), storing the values in the sample's record;
-//  3. one lane per segment composes its samples' records in order.
+//  3. the lanes of a segment compose runs of its records, each with the
+//     transmittance from the run's start, and chain the runs (a run's colour
+//     times the transmittance of the runs before it).
 // The values and the composition are those of seg_fwd (project each corner
 // on the ray's SH basis, trilinear weights, Eq. (1) with the FP64 optical
-// depth); only the assignment of work to lanes differs.
+// depth); the assignment of work to lanes and the grouping of the
+// composition's products differ.
 
 constexpr int kFwdThreads = 512;  // threads of a forward workgroup
 constexpr int kFwdSegs = 512;     // segments per group
 constexpr int kWalkRun = 8;       // consecutive samples a walking lane tests at once
+// Segments per brick (on average over the call) from which the training call
+// takes this forward: with fewer, most of a 512-thread workgroup idles in the
+// walk and the composition, and the lane-per-segment forward is faster (on
+// the 512^3 / 5% grid: 0.35 against 0.72 ms at 65,536 rays, about 9
+// segments per brick; even at 262,144 rays, about 36; 2.66 against 1.81 ms
+// at 1M rays, 138)
+constexpr int64_t kFwdParMinSegs = 40;
 
 template <int DT> struct FwdStage {
     static constexpr int kHalves = DT == PLX_F32 ? 2 : 1;
@@ -1490,8 +1502,7 @@ __device__ __forceinline__ void stage_planes(const GridDev &g, uint4 *s_rec, con
     }
 }
 
-// Loads the words of corner p (brick lattice position) of the brick at b0
-// from its id (NULL: zeros).
+// The staged words of the corner record with id `id` (NULL: zeros).
 template <int DT>
 __device__ __forceinline__ void load_corner_words(const GridDev &g, int id, uint4 wv[]) {
     constexpr int W = StagedRec<DT>::kWords;
@@ -2921,15 +2932,21 @@ int render_binned(const plx_grid *grid, BinArgs a, hipStream_t s, const char *fn
     }
     if (a.n_seg > 0) {
         const bool rec = MODE != MODE_FWD && a.srec;
-        if (rec && a.blist && a.n_brick > 0) {
+        const bool lists = a.blist && a.n_brick > 0;
+        if (rec && lists && a.n_seg >= kFwdParMinSegs * a.n_brick) {
             // recording forward: sample-parallel, one workgroup per brick
             PLX_DISPATCH_DT(grid->sh_dtype, DT,
                             seg_fwd_samples_kernel<DT><<<(unsigned)a.n_brick, kFwdThreads, 0, s>>>(g, as));
-        } else if (a.blist && a.n_brick > 0 && grid->sh_dtype != PLX_F32) {
+        } else if (lists && grid->sh_dtype != PLX_F32) {
             // brick-staged (16-bit records: 47 KB of LDS per brick, three
             // workgroups per CU; FP32's 82 KB leave one, and the lane-per-
             // segment kernel with its L2 traffic is then twice as fast)
-            PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, false><<<(unsigned)a.n_brick, kThreads, 0, s>>>(g, as));
+            const unsigned nb = (unsigned)a.n_brick;
+            if (rec) {
+                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, true><<<nb, kThreads, 0, s>>>(g, as));
+            } else {
+                PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_brick_kernel<DT, false><<<nb, kThreads, 0, s>>>(g, as));
+            }
         } else if (rec) {
             PLX_DISPATCH_DT(grid->sh_dtype, DT, seg_fwd_kernel<DT, true><<<as.nb8, kThreads, 0, s>>>(g, as));
         } else {

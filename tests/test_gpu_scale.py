@@ -294,14 +294,17 @@ def test_trainer_overlapped_binning_matches_sequential():
     assert all(x > 0 for x in losses[True])
 
 
-@pytest.mark.parametrize("sh_dtype", [B.PLX_F32, B.PLX_BF16])
+@pytest.mark.parametrize("sh_dtype", [B.PLX_F32, B.PLX_BF16, B.PLX_F16])
 def test_crowded_bricks_recorded_backward(sh_dtype):
     """The recorded backward where one brick holds many segments and long
     ones: 30000 rays through a 13^3 grid (8 bricks) with a step of 0.1 voxel,
     so a brick holds thousands of segments (several groups of 256) and tens
     of thousands of samples (many LDS passes, segments across pass
-    boundaries, walked last pass first).  plx_render_bwd with and without a
-    sample buffer against the oracle, and the touched set bit-exact."""
+    boundaries, walked last pass first); with that many segments per brick
+    the forward is the sample-parallel one (groups of 512 segments walked
+    by one, two or four lanes each, FP32 corners staged in two halves, more
+    samples than one chunk).  plx_render_bwd with and without a sample
+    buffer against the oracle, and the touched set bit-exact."""
     say("crowded bricks", sh_dtype)
     sv = synth.dense_random((13, 13, 13), seed=331, occupancy=0.6, sigma_lo=0.5, sigma_hi=6.0, ho_scale=0.2)
     og, gg = make_pair(sv, sh_dtype=sh_dtype, step_voxels=0.1)
