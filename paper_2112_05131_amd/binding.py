@@ -493,7 +493,9 @@ def make_bins(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor | None = None,
     the current stream, into the given buffers when they are large enough,
     else into new ones.  samples: attach a sample buffer (the recorded
     backward); without one the backward replay scatters its gradients
-    itself."""
+    itself.  New segment and sample buffers get 1/8 more than this batch
+    needs, so that a training loop passing them back in does not allocate
+    again for every batch that holds a few more segments than the last."""
     n = rays_o.shape[0]
     need = plx_bins_ray_bytes(tuple(g.reso), n)
     if ray_buf is None or ray_buf.numel() < need:
@@ -503,11 +505,11 @@ def make_bins(g: PlxGrid, rays_o, rays_d, ray_buf: torch.Tensor | None = None,
     if n_seg > 0:
         sneed = plx_bins_seg_bytes(n_seg)
         if seg_buf is None or seg_buf.numel() < sneed:
-            seg_buf = workspace(sneed, rays_o.device)
+            seg_buf = workspace(sneed + sneed // 8, rays_o.device)
         if samples:
             pneed = plx_bins_samp_bytes(n_seg, int(desc.n_samp))
             if samp_buf is None or samp_buf.numel() < pneed:
-                samp_buf = workspace(pneed, rays_o.device)
+                samp_buf = workspace(pneed + pneed // 8, rays_o.device)
     bins = Bins(desc, ray_buf, seg_buf if n_seg > 0 else None,
                 samp_buf if n_seg > 0 and samples else None)
     plx_bins_apply(g, rays_o, rays_d, bins)

@@ -139,6 +139,12 @@ class Trainer:
         self.cfg = cfg or TrainConfig()
         self.rng = np.random.default_rng(seed)
         self.step_id = 0
+        # the two alternating sets of segment-list buffers of run() and the
+        # completion events of the steps that last used them, kept across
+        # calls so that a new call neither allocates them again nor refills
+        # a set that a step of the previous call may still be reading
+        self._run_bufs = [[None, None, None], [None, None, None]]
+        self._run_done = [None, None]
         self.set_grid(grid)
         self.set_background(background)
 
@@ -254,8 +260,8 @@ class Trainer:
         finished.  events: a list that gets one StepEvents per step."""
         main = torch.cuda.current_stream()
         side = torch.cuda.Stream(device=self.grid.device) if overlap else main
-        bufs = [[None, None, None], [None, None, None]]
-        done = [None, None]
+        bufs = self._run_bufs
+        done = self._run_done
 
         def prepare(slot):
             se = StepEvents() if events is not None else None
