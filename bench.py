@@ -25,6 +25,7 @@ pruning-by-weight pass; the serving latency leg; and the FP64 oracle timed
 on a bounded sample of the same workload on all host cores and on one.
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -56,6 +57,9 @@ N_CAMS, W, H = 100, 800, 800
 # WRITE_SIZE passes (scaled by a plain copy's readings), with the hash of the
 # kernel source they were taken on; a changed source makes them stale (null).
 COUNTERS = os.path.join(ROOT, "profiles", "render_train_512cubed_1Mrays_counters.json")
+# warm-up steps of the comparison legs (each a new trainer: its first steps
+# allocate its optimiser state and segment-list buffers)
+CMP_WARMUP = 5
 RENDER_SRC = os.path.join(ROOT, "paper_2112_05131_amd", "csrc", "render.hip")
 # kernels of one plx_render_train call, as rocprofv3 names them
 COUNTED_KERNELS = {"seg_fwd": ("seg_fwd_samples_kernel", "seg_fwd_kernel", "seg_fwd_brick_kernel"),
@@ -158,6 +162,9 @@ def time_steps(trainer, sampler, warmup, steps, overlap=True):
     """W untimed steps, then exactly K steps between two synchronisations;
     returns (ms per step, wall s, mean per-part ms)."""
     trainer.run(sampler, warmup, overlap=overlap)
+    # collect the previous legs' garbage (trainers, events) before, not
+    # inside, the timed region
+    gc.collect()
     torch.cuda.synchronize()
     evs = []
     start = torch.cuda.Event(enable_timing=True)
@@ -660,7 +667,7 @@ def main():
             if name in prec:
                 continue
             tr2 = Trainer(wl.grid(B.DTYPES[name]), TrainConfig(), seed=SEED)
-            ms2, _, k2 = time_steps(tr2, wl.sampler(coherent), 2, max(5, args.steps // 2))
+            ms2, _, k2 = time_steps(tr2, wl.sampler(coherent), CMP_WARMUP, max(5, args.steps))
             prec[name] = {"ms_per_step": round(ms2, 4), "mrays_s": round(BATCH / ms2 / 1e3, 3),
                           "render_train_ms": round(k2["render_train"], 4),
                           "seg_fwd_ms": round(k2["seg_fwd"], 4), "seg_scatter_ms": round(k2["seg_bwd"], 4)}
@@ -672,7 +679,7 @@ def main():
         if coherent:
             # the same pixels, each batch in the permutation's order
             tr3 = Trainer(wl.grid(sh_dtype), TrainConfig(), seed=SEED)
-            ms3, _, k3 = time_steps(tr3, wl.sampler(False), 2, max(5, args.steps // 2))
+            ms3, _, k3 = time_steps(tr3, wl.sampler(False), CMP_WARMUP, max(5, args.steps))
             out["random_order"] = {"ms_per_step": round(ms3, 4), "mrays_s": round(BATCH / ms3 / 1e3, 3),
                                    "render_train_ms": round(k3["render_train"], 4)}
             log(f"random ray order: step {ms3:.3f} ms, render_train {k3['render_train']:.3f} ms")
@@ -680,14 +687,14 @@ def main():
         # the segment lists made on the training stream itself (their count's
         # synchronisation then stalls the device once per step)
         tr5 = Trainer(wl.grid(sh_dtype), TrainConfig(), seed=SEED)
-        ms5, _, k5 = time_steps(tr5, wl.sampler(coherent), 2, max(5, args.steps // 2), overlap=False)
+        ms5, _, k5 = time_steps(tr5, wl.sampler(coherent), CMP_WARMUP, max(5, args.steps), overlap=False)
         out["sequential_binning"] = {"ms_per_step": round(ms5, 4), "mrays_s": round(BATCH / ms5 / 1e3, 3)}
         log(f"sequential binning: step {ms5:.3f} ms")
         del tr5
         # the same step with the sparsity and beta priors of Sec. 3.7 on (the
         # paper's 360-degree weights)
         tr4 = Trainer(wl.grid(sh_dtype), TrainConfig(lambda_sparsity=1e-11, lambda_beta=1e-5), seed=SEED)
-        ms4, _, k4 = time_steps(tr4, wl.sampler(coherent), 2, max(5, args.steps // 2))
+        ms4, _, k4 = time_steps(tr4, wl.sampler(coherent), CMP_WARMUP, max(5, args.steps))
         out["with_priors"] = {"lambda_sparsity": 1e-11, "lambda_beta": 1e-5, "ms_per_step": round(ms4, 4),
                               "mrays_s": round(BATCH / ms4 / 1e3, 3),
                               "render_train_ms": round(k4["render_train"], 4)}
