@@ -263,7 +263,8 @@ def test_bins_serve_every_call_and_verify(samples):
 def test_trainer_overlapped_binning_matches_sequential():
     """Trainer.run bins batch t+1 on a second stream while step t runs; the
     losses of every step equal those of the plain loop over the same
-    batches (up to the order of FP32 atomics)."""
+    batches (up to the order of FP32 atomics).  Repeated run() calls reuse
+    the trainer's two sets of segment-list buffers."""
     say("overlapped trainer")
     gt = synth.blob_scene((48, 48, 48), n_blobs=6, occupancy=0.2, seed=311)
     poses = synth.sphere_poses(8, seed=311)
@@ -284,11 +285,17 @@ def test_trainer_overlapped_binning_matches_sequential():
             tr.run(sampler, 1, overlap=overlap)
             torch.cuda.synchronize()
             per_step.append(tr.loss_sum.item())
+        # the single-step runs all used the first set (ray and segment buffers)
+        ptr0 = [x.data_ptr() if x is not None else None for x in tr._run_bufs[0]]
+        assert ptr0[0] is not None and ptr0[1] is not None
         tr.loss_sum.zero_()
         tr.run(sampler, 5, overlap=overlap)
         torch.cuda.synchronize()
         per_step.append(tr.loss_sum.item())
         losses[overlap] = per_step
+        # batches of one scene differ by a few segments; the buffers' slack holds them
+        assert ptr0 == [x.data_ptr() if x is not None else None for x in tr._run_bufs[0]]
+        assert tr._run_bufs[1][1] is not None
     say(f"  losses {losses[True]}")
     np.testing.assert_allclose(losses[True], losses[False], rtol=1e-4)
     assert all(x > 0 for x in losses[True])
