@@ -79,7 +79,17 @@ class RaySampler:
         self._perm = None
         self._pos = self.n
 
-    def next_batch(self):
+    def batch_buffers(self):
+        """Device buffers that next_batch(out=...) fills: the batch's rays and
+        targets, and the sorted ray ids (values, positions)."""
+        dev, b = self.o.device, self.batch
+        return (torch.empty(b, 3, dtype=self.o.dtype, device=dev), torch.empty(b, 3, dtype=self.d.dtype, device=dev),
+                torch.empty(b, 3, dtype=self.t.dtype, device=dev), torch.empty(b, dtype=torch.int64, device=dev),
+                torch.empty(b, dtype=torch.int64, device=dev))
+
+    def next_batch(self, out=None):
+        """(rays_o, rays_d, target) of the next batch: new tensors, or the
+        first three of `out` (batch_buffers()) filled in place."""
         if self._pos + self.batch > self.n:
             # a new epoch; a short tail of the previous permutation is dropped
             self._perm = torch.randperm(self.n, device=self.o.device, generator=self.gen)
@@ -87,9 +97,18 @@ class RaySampler:
             self.epoch += 1
         ids = self._perm[self._pos:self._pos + self.batch]
         self._pos += self.batch
+        if out is None:
+            if self.coherent:
+                ids = torch.sort(ids).values
+            return self.o[ids], self.d[ids], self.t[ids]
+        o, d, t, sv, si = out
         if self.coherent:
-            ids = torch.sort(ids).values
-        return self.o[ids], self.d[ids], self.t[ids]
+            torch.sort(ids, out=(sv, si))
+            ids = sv
+        torch.index_select(self.o, 0, ids, out=o)
+        torch.index_select(self.d, 0, ids, out=d)
+        torch.index_select(self.t, 0, ids, out=t)
+        return o, d, t
 
 
 # Batches from this size on use the recorded backward (sample buffer and one
@@ -144,6 +163,7 @@ class Trainer:
         # calls so that a new call neither allocates them again nor refills
         # a set that a step of the previous call may still be reading
         self._run_bufs = [[None, None, None], [None, None, None]]
+        self._run_batch = [None, None]  # batch buffers of each set (RaySampler.batch_buffers)
         self._run_done = [None, None]
         self.set_grid(grid)
         self.set_background(background)
@@ -255,9 +275,11 @@ class Trainer:
         while step t runs on the current one: the binning reads only the rays
         and the grid's occupancy, which a step does not change, and its one
         synchronising call (the segment count) then waits for that stream
-        alone, so the device never idles on it.  The two sets of bin buffers
-        alternate; a set is refilled only after the step that used it has
-        finished.  events: a list that gets one StepEvents per step."""
+        alone, so the device never idles on it.  The two sets of batch and
+        segment-list buffers alternate (kept by the trainer, so that a step
+        allocates nothing once both exist); a set is refilled only after the
+        step that used it has finished.  events: a list that gets one
+        StepEvents per step."""
         main = torch.cuda.current_stream()
         side = torch.cuda.Stream(device=self.grid.device) if overlap else main
         bufs = self._run_bufs
@@ -270,7 +292,10 @@ class Trainer:
                     side.wait_event(done[slot])
                 if se is not None:
                     se.bins[0].record(side)
-                o, d, t = sampler.next_batch()
+                bb = self._run_batch[slot]
+                if bb is None or bb[0].shape[0] != sampler.batch or bb[0].device != sampler.o.device:
+                    bb = self._run_batch[slot] = sampler.batch_buffers()
+                o, d, t = sampler.next_batch(out=bb)
                 b = B.make_bins(self.grid.desc(), o, d, *bufs[slot], samples=recorded_backward(o.shape[0]))
                 bufs[slot] = b.buffers()
                 if se is not None:
