@@ -161,7 +161,9 @@ class Workload:
 def time_steps(trainer, sampler, warmup, steps, overlap=True):
     """W untimed steps, then exactly K steps between two synchronisations;
     returns (ms per step, wall s, mean per-part ms)."""
-    trainer.run(sampler, warmup, overlap=overlap)
+    # the warm-up takes the timed steps' path, per-part events included (the
+    # first timing events of a process are slow to create)
+    trainer.run(sampler, warmup, overlap=overlap, events=[])
     # collect the previous legs' garbage (trainers, events) before, not
     # inside, the timed region
     gc.collect()

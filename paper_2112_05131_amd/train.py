@@ -165,6 +165,7 @@ class Trainer:
         self._run_bufs = [[None, None, None], [None, None, None]]
         self._run_batch = [None, None]  # batch buffers of each set (RaySampler.batch_buffers)
         self._run_done = [None, None]
+        self._side = None  # run()'s second stream
         self.set_grid(grid)
         self.set_background(background)
 
@@ -281,7 +282,11 @@ class Trainer:
         step that used it has finished.  events: a list that gets one
         StepEvents per step."""
         main = torch.cuda.current_stream()
-        side = torch.cuda.Stream(device=self.grid.device) if overlap else main
+        if overlap and (self._side is None or self._side.device != self.grid.device):
+            # one second stream per trainer: a new stream per call costs the
+            # runtime a queue set-up at the start of the first calls
+            self._side = torch.cuda.Stream(device=self.grid.device)
+        side = self._side if overlap else main
         bufs = self._run_bufs
         done = self._run_done
 
