@@ -281,6 +281,8 @@ class Trainer:
         allocates nothing once both exist); a set is refilled only after the
         step that used it has finished.  events: a list that gets one
         StepEvents per step."""
+        if n_steps <= 0:
+            return
         main = torch.cuda.current_stream()
         if overlap and (self._side is None or self._side.device != self.grid.device):
             # one second stream per trainer: a new stream per call costs the
